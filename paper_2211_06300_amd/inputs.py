@@ -1,0 +1,153 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module only draws and shapes inputs: velocity models, acquisition
+geometry, source wavelets and random test vectors.  It holds none of the
+method's arithmetic (no propagation, no operator, no solver) and imports
+nothing else from the package, so the FP64 oracle and the GPU path can both
+consume its output.  Every generator works in float64 from
+``numpy.random.default_rng(seed)`` and rounds once to float32; both sides use
+those float32 values.
+
+The paper's own workloads (Sec. 4: a two-layer reflection model, a 1D layered
+landscape model and Marmousi-II with 28 surface shots, 641 receivers and a
+5 Hz Ricker) are not available; the configurations below stand in for them
+with the same acquisition style: surface sources and receivers, a 1500 m/s
+top layer and Ricker sources.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+def ricker_samples(nt: int, dt: float, f: float, t0: float | None = None) -> np.ndarray:
+    """Ricker wavelet of peak frequency f sampled at t_n = n dt, delay t0 = 1/f.
+
+    w(t) = (1 - 2 pi^2 f^2 (t - t0)^2) exp(-pi^2 f^2 (t - t0)^2); float32 [nt].
+    """
+    if t0 is None:
+        t0 = 1.0 / f
+    t = np.arange(nt, dtype=np.float64) * dt
+    a = (np.pi * f * (t - t0)) ** 2
+    return ((1.0 - 2.0 * a) * np.exp(-a)).astype(np.float32)
+
+
+@dataclass
+class Config:
+    """One workload: grid, time axis, geometry, models and solver settings."""
+    name: str
+    ndim: int
+    nz: int
+    nx: int
+    ny: int
+    dx: float
+    dt: float
+    nt: int
+    nb: int
+    freq: float
+    beta: float
+    cg_iters: int
+    v_true: np.ndarray                 # float32 [nz][(ny)][nx]
+    v_start: np.ndarray                # float32, model the solve runs in
+    src: np.ndarray                    # int32 [nshots][ndim] (ix, iz[, iy])
+    rec_ptr: np.ndarray                # int64 [nshots+1]
+    rec: np.ndarray                    # int32 [nrec_total][ndim]
+    wavelet: np.ndarray                # float32 [nt]
+    b_eps: float = 1.0
+    notes: dict = field(default_factory=dict)
+
+    @property
+    def nshots(self) -> int:
+        return int(self.src.shape[0])
+
+    @property
+    def phys_shape(self):
+        return (self.nz, self.nx) if self.ndim == 2 else (self.nz, self.ny, self.nx)
+
+    def shot_rec(self, s: int) -> np.ndarray:
+        return self.rec[self.rec_ptr[s]:self.rec_ptr[s + 1]]
+
+
+def _csr(recs):
+    ptr = np.zeros(len(recs) + 1, dtype=np.int64)
+    ptr[1:] = np.cumsum([len(r) for r in recs])
+    return ptr, np.concatenate(recs).astype(np.int32)
+
+
+def cfg_small() -> Config:
+    """201 x 201 grid, dx 10 m, v = 2000 m/s, one 10 Hz Ricker at (100, 5),
+    201 receivers along row 5, 500 steps of 1 ms, 20-cell sponge, beta 1e-2,
+    5 CG iterations (the small parity workload)."""
+    nz = nx = 201
+    v = np.full((nz, nx), 2000.0, dtype=np.float32)
+    src = np.array([[100, 5]], dtype=np.int32)
+    rec = np.stack([np.arange(nx), np.full(nx, 5)], axis=1).astype(np.int32)
+    ptr, rr = _csr([rec])
+    return Config("small-201x201", 2, nz, nx, 1, 10.0, 1e-3, 500, 20, 10.0, 1e-2, 5,
+                  v, v.copy(), src, ptr, rr, ricker_samples(500, 1e-3, 10.0))
+
+
+def layered_model(nz: int, nx: int, seed: int, water_cells: int = 40) -> np.ndarray:
+    """1500 m/s water over 5 layers (sorted U[1700, 4500] m/s, tops at cell 40
+    and at 4 sorted U[60, 380] depths) with 3 Gaussian anomalies of +-10 %
+    (centres uniform below the water, sigma U[15, 40] cells); float64."""
+    rng = np.random.default_rng(seed)
+    vel = np.sort(rng.uniform(1700.0, 4500.0, 5))
+    tops = np.concatenate([[water_cells], np.sort(rng.uniform(60.0, 0.95 * nz, 4))])
+    z = np.arange(nz, dtype=np.float64)[:, None]
+    v = np.full((nz, nx), 1500.0)
+    for vk, tk in zip(vel, tops):
+        v = np.where(z >= tk, vk, v)
+    zz, xx = np.meshgrid(np.arange(nz, dtype=np.float64), np.arange(nx, dtype=np.float64),
+                         indexing="ij")
+    for _ in range(3):
+        cz = rng.uniform(water_cells + 20, nz)
+        cx = rng.uniform(0, nx)
+        sig = rng.uniform(15.0, 40.0)
+        amp = 0.1 * rng.choice([-1.0, 1.0])
+        v = v * (1.0 + amp * np.exp(-((zz - cz) ** 2 + (xx - cx) ** 2) / (2 * sig * sig)))
+    return v
+
+
+def smooth_model(v: np.ndarray, sigma: float) -> np.ndarray:
+    """Gaussian-smoothed start model (sigma in cells, nearest-edge boundary)."""
+    from scipy.ndimage import gaussian_filter
+    return gaussian_filter(np.asarray(v, dtype=np.float64), sigma=sigma, mode="nearest")
+
+
+def cfg_single_solve(nshots: int = 32, nx: int = 801, nz: int = 401, nt: int = 2000,
+                     seed: int = 1) -> Config:
+    """801 x 401 grid, dx 12.5 m, layered 1500-4500 m/s with 3 anomalies (seed 1),
+    32 shots of an 8 Hz Ricker at depth cell 2 (x evenly 12..788), 401 receivers
+    at depth cell 2 every 2nd cell, 2000 steps of 1 ms, start model smoothed
+    with sigma 10 cells, 20 CG iterations, beta 1e-2 (the single-solve workload)."""
+    v_true = layered_model(nz, nx, seed)
+    v_start = smooth_model(v_true, 10.0)
+    xs = np.round(np.linspace(12, nx - 13, nshots)).astype(np.int32)
+    src = np.stack([xs, np.full(nshots, 2)], axis=1).astype(np.int32)
+    rx = np.arange(0, nx, 2)
+    rec1 = np.stack([rx, np.full(rx.size, 2)], axis=1).astype(np.int32)
+    ptr, rr = _csr([rec1] * nshots)
+    return Config("single-solve-801x401", 2, nz, nx, 1, 12.5, 1e-3, nt, 20, 8.0, 1e-2, 20,
+                  v_true.astype(np.float32), v_start.astype(np.float32), src, ptr, rr,
+                  ricker_samples(nt, 1e-3, 8.0))
+
+
+def cfg_tiny(nz: int = 8, nx: int = 8, nt: int = 24, nb: int = 4, seed: int = 7,
+             nrec: int = 4, dx: float = 10.0, dt: float = 1e-3) -> Config:
+    """Tiny heterogeneous 2D grid on which dense operators can be formed."""
+    rng = np.random.default_rng(seed)
+    v = rng.uniform(1800.0, 2600.0, (nz, nx))
+    src = np.array([[nx // 2, 1]], dtype=np.int32)
+    rx = np.linspace(0, nx - 1, nrec).round().astype(np.int32)
+    rec = np.stack([rx, np.full(nrec, 1)], axis=1).astype(np.int32)
+    ptr, rr = _csr([rec])
+    return Config("tiny", 2, nz, nx, 1, dx, dt, nt, nb, 25.0, 1e-2, 10,
+                  v.astype(np.float32), v.astype(np.float32), src, ptr, rr,
+                  ricker_samples(nt, dt, 25.0))
+
+
+def random_field(shape, seed: int) -> np.ndarray:
+    """Seeded N(0, 1) float32 array (dot-test and parity vectors)."""
+    return np.random.default_rng(seed).standard_normal(shape).astype(np.float32)
