@@ -1,0 +1,194 @@
+"""Benchmark of the ESI hot path on one MI355X.
+
+One step = the whole hot path over one batch of synthetic input: for every
+shot group, the right-hand side S^T d by adjoint modelling, K iterations of
+CG on (S^T S + beta B^T B) q = S^T d (two propagations each) and the PENALTY
+gradient (one propagation).  Default workload: 801 x 401 grid, dx 12.5 m,
+layered model with 3 anomalies, 32 shots of an 8 Hz Ricker, 401 receivers,
+2000 steps of 1 ms, 20 CG iterations in the smoothed start model, full
+wavefield storage of the CG vectors, shots in groups of 16.
+
+Prints one JSON line.  value = padded grid-point updates per second over the
+whole timed region (GPts/s).  The roofline object covers the dominant time-step
+kernel, timed live with hipEvents around its time loops inside the timed
+region; cpu_baseline is the FP64 oracle on a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "stencil GPts/s + %HBM peak; ESI CG solve time to 1e-3 residual, plain vs learned PCG"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+# algorithmic bytes of one time-step launch, per shot: 16 B per padded point
+# (read u^n, u^{n-1}, c; write u^{n+1}) plus the dense streams of its variant
+DENSE_BYTES = {2: 4, 4: 20, 32: 4, 64: 8, 128: 8, 256: 4, 512: 12}
+
+
+def bytes_per_shot_launch(flags: int, npad: int, nphys: int) -> int:
+    b = 16 * npad
+    for bit, per in DENSE_BYTES.items():
+        if flags & bit:
+            b += per * nphys
+    return b
+
+
+def cpu_baseline(cfg, nt_sample: int):
+    """FP64 oracle (plain C loops, OpenMP over rows) on one shot of the same grid:
+    one normal-operator application (forward + adjoint) over nt_sample steps."""
+    from oracle import core
+    g = core.Grid(2, cfg.nz, cfg.nx, nb=cfg.nb, nt=nt_sample, dx=cfg.dx, dt=cfg.dt)
+    m = core.make_model(g, cfg.v_start)
+    rng = np.random.default_rng(0)
+    p = rng.standard_normal((nt_sample, cfg.nz, cfg.nx))
+    w2 = core.annihilator_sq(g, cfg.src[0])
+    core.build_oracle()
+    t0 = time.perf_counter()
+    core.normal_apply(m, cfg.shot_rec(0), w2, cfg.beta, p)
+    t = time.perf_counter() - t0
+    npad = (cfg.nz + 2 * cfg.nb) * (cfg.nx + 2 * cfg.nb)
+    pts = 2 * npad * nt_sample
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": pts / t / 1e9, "unit": "GPts/s", "cores": threads, "kind": "oracle",
+            "sample": f"1 shot, 1 normal-operator application (forward+adjoint), "
+                      f"{nt_sample} of {cfg.nt} steps on the {cfg.nx}x{cfg.nz} grid; {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--shots", type=int, default=32)
+    ap.add_argument("--group", type=int, default=16)
+    ap.add_argument("--cg-iters", type=int, default=20)
+    ap.add_argument("--nt", type=int, default=2000)
+    ap.add_argument("--cpu-nt", type=int, default=1000, help="steps in the oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(shots shard across GPUs by design, see DESIGN.md)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2211_06300_amd import esi, inputs
+
+    dev = torch.device("cuda:0")
+    cfg = inputs.cfg_single_solve(nshots=args.shots, nt=args.nt)
+    npad = (cfg.nz + 2 * cfg.nb) * (cfg.nx + 2 * cfg.nb)
+    nphys = cfg.nz * cfg.nx
+    G = min(args.group, cfg.nshots)
+    groups = [(s, min(G, cfg.nshots - s)) for s in range(0, cfg.nshots, G)]
+    log(f"workload {cfg.name}: {cfg.nshots} shots, groups of {G}, nt {cfg.nt}, "
+        f"{args.cg_iters} CG iterations")
+
+    # observed data from the true model (setup, untimed)
+    plan_true = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_true).to(dev))
+    wav = torch.from_numpy(np.tile(cfg.wavelet, (cfg.nshots, 1))).to(dev)
+    d_obs = plan_true.forward(wav, esi.SRC_POINT)
+    torch.cuda.synchronize()
+    plan_true.close()
+    del plan_true, wav
+    plan = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_start).to(dev))
+    x = plan.new_vec(G)
+    work = torch.empty((3, *plan.vec_shape(G)), dtype=torch.float32, device=dev)
+    grad = torch.zeros(plan.phys_shape, dtype=torch.float32, device=dev)
+    offs = [int(cfg.nt * cfg.rec_ptr[s]) for s in range(cfg.nshots + 1)]
+    log("setup done")
+
+    last_hist = {}
+
+    def step():
+        grad.zero_()
+        for s0, ns in groups:
+            d = d_obs[offs[s0]:offs[s0 + ns]]
+            xs = x[:ns]
+            ws = work[:, :ns] if ns == G else torch.empty((3, *plan.vec_shape(ns)),
+                                                          dtype=torch.float32, device=dev)
+            _, rep = plan.cg_solve(d, args.cg_iters, 0.0, shot0=s0, nshots=ns, x=xs, work=ws)
+            plan.gradient(esi.GRAD_PENALTY, xs, shot0=s0, nshots=ns, grad_m=grad)
+            last_hist[s0] = rep["res_hist"]
+
+    for i in range(args.warmup):
+        t0 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {i}: {time.perf_counter() - t0:.2f} s")
+
+    stream = torch.cuda.current_stream(dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    plan.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for i in range(args.steps):
+        step()
+        log(f"step {i} queued/done")
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    prof = plan.profile_read()
+    plan.profile(False)
+
+    props_per_shot = 1 + 2 * args.cg_iters + 1
+    pts = args.steps * cfg.nshots * props_per_shot * npad * cfg.nt
+    value = pts / wall / 1e9
+
+    # dominant time-step kernel variant: largest share of the timed loops
+    name, rec = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    per_launch_ms = rec["ms"] / rec["launches"]
+    shots_per_launch = rec["shot_launches"] / rec["launches"]
+    alg_bytes = bytes_per_shot_launch(rec["flags"], npad, nphys) * shots_per_launch
+    achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9
+    hist = np.concatenate([h for h in last_hist.values()])
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "GPts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "grid": f"{cfg.nx}x{cfg.nz}", "nb": cfg.nb,
+                   "nt": cfg.nt, "shots": cfg.nshots, "shot_group": G,
+                   "cg_iters": args.cg_iters, "beta": cfg.beta,
+                   "propagations_per_shot": props_per_shot},
+        "roofline": {"bound": "hbm", "kernel": f"k_step2d<{name}>",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "alg_bytes_per_launch": int(alg_bytes),
+                     "avg_launch_us": round(per_launch_ms * 1e3, 2)},
+        "gpu_event_ms": round(gpu_ms, 1),
+        "cg_final_rel_residual_max": float(np.max(hist[:, -1])),
+        "kernel_loops": {k: {"launches": v["launches"], "ms": round(v["ms"], 1)} for k, v in prof.items()},
+    }
+    if not args.no_cpu:
+        log("timing the oracle on the host cores")
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_nt)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

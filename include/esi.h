@@ -1,0 +1,216 @@
+/*
+ * esi.h -- C ABI of the MI355X (gfx950) hot path of time-domain extended
+ * source waveform inversion (ESI), after Yang & Zhou, "Algorithmic analysis
+ * towards time-domain extended source waveform inversion" (arXiv 2211.06300).
+ *
+ * The library solves, shot by shot, the ESI normal equation
+ *     (S^T S + beta B^T B) q = S^T d                       (eq. normalewi, Sec. 2.3)
+ * with S = R A^{-1} the modelling operator of the constant-density acoustic
+ * equation A(m) u = (1/v^2) d_t^2 u - Laplacian u (eq. wave, Sec. 2.1), and it
+ * forms the adjoint-state gradient <lambda, (dA/dm) u> (eq. gradewi, Sec. 2.3).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  * Grid: a physical grid nz x nx (2D) or nz x ny x nx (3D), spacing dx, with
+ *    an absorbing layer of nb cells added OUTSIDE it on every side (Sec. 4.1
+ *    asks for an absorbing boundary that also removes the free surface).  The
+ *    layer is a damping term eta(x) u_t, eta = eta_max sum_d (delta_d/nb)^2.
+ *    Beyond the padded grid the field is zero.
+ *  * Scheme: O(dt^2, dx^8) (Sec. 4.1).  With c = v^2 dt^2, k = eta dt / 2,
+ *        (1+k) u^{n+1} = 2 u^n - (1-k) u^{n-1} + c (L u^n + P q^n),
+ *        d^n = R u^{n+1},      n = 0 .. nt-1,   u^{-1} = u^0 = 0,
+ *    so q^n enters at step n and d^n is the sample at time (n+1) dt.  The
+ *    adjoint runs the same recurrence backward in time with R^T d^j injected.
+ *  * Positions are 0-based physical cell indices, (ix, iz) in 2D and
+ *    (ix, iz, iy) in 3D.
+ *  * Dense wavefield-sized vectors (extended sources q, CG vectors, adjoint
+ *    outputs) are float32 [nshots][nt][nz][(ny)][nx], x fastest, physical
+ *    grid only.  Data are float32; the traces of one shot are [nt][nrec_s]
+ *    and shots follow each other in the order of geom.rec_ptr (CSR): within
+ *    a call on shots [shot0, shot0+nshots) the data of shot s start at
+ *    element nt * (rec_ptr[s] - rec_ptr[shot0]).
+ *  * Model: m = 1/v^2.  Gradients are with respect to m on the physical grid
+ *    (multiply by -2/v^3 for the gradient with respect to v).
+ *  * Annihilator: B(x) = |x - x_s| / dx + b_eps (distance in cells), the
+ *    choice of Sec. 4 with a small positive number added at the source.
+ *  * Inner products are plain sums over cells and steps.
+ *
+ * Memory and streams: every pointer named "device" is device memory on the
+ * plan's device, owned by the caller, float32 and contiguous unless stated.
+ * The plan owns only what it derives (coefficients, wavefield rings, data
+ * and reduction scratch, per-tile injection lists); it grows that scratch on
+ * demand with hipMalloc and frees it in esi_plan_destroy.  All work is
+ * queued on the stream given at plan creation; calls return once the work is
+ * queued, except esi_cg_solve, which waits for each iteration's residual norms
+ * to decide convergence.
+ *
+ * Errors: every call returns an esi_status_t; nothing aborts and no C++
+ * exception crosses the boundary.  Arguments are validated before any work is
+ * queued.  esi_last_error() returns a text for the last failure on the
+ * calling thread.  A plan must not be used from two threads at once.
+ */
+#ifndef ESI_H
+#define ESI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct esi_plan_s* esi_plan_t;
+
+typedef enum {
+    ESI_OK = 0,
+    ESI_ERR_ARG = 1,        /* null pointer, bad enum, bad shot range */
+    ESI_ERR_SHAPE = 2,      /* inconsistent sizes or positions outside the grid */
+    ESI_ERR_CFL = 3,        /* v_max dt / dx beyond the stability limit */
+    ESI_ERR_OOM = 4,        /* device allocation failed */
+    ESI_ERR_HIP = 5,        /* a HIP runtime call or kernel launch failed */
+    ESI_ERR_BREAKDOWN = 6,  /* CG: p^T N p <= 0 */
+    ESI_ERR_NONFINITE = 7   /* CG: non-finite scalar */
+} esi_status_t;
+
+enum { ESI_SRC_POINT = 0, ESI_SRC_DENSE = 1 };
+enum { ESI_GRAD_PENALTY = 0, ESI_GRAD_ADJOINT = 1, ESI_GRAD_SEED = 2 };
+
+typedef struct {
+    int32_t ndim;       /* 2 or 3 */
+    int32_t nz, nx, ny; /* physical grid; ny must be 1 when ndim == 2 */
+    int32_t nb;         /* absorbing-layer width in cells, >= 4 */
+    int32_t nt;         /* number of time steps, >= 1 */
+    double dx, dt;      /* metres, seconds */
+    double eta_max;     /* peak damping (1/s); < 0: 3 v_max ln(1000) / (2 nb dx); 0: off */
+    double beta;        /* penalty weight of eq. (esi), >= 0 */
+    double b_eps;       /* annihilator offset in cells, > 0 when beta > 0 */
+} esi_grid_t;
+
+typedef struct {
+    int32_t nshots;
+    const int32_t* src;     /* host [nshots][ndim] source cells */
+    const int64_t* rec_ptr; /* host [nshots+1], rec_ptr[0] = 0, non-decreasing */
+    const int32_t* rec;     /* host [rec_ptr[nshots]][ndim] receiver cells */
+} esi_geom_t;
+
+/*
+ * Create a plan for one grid, acquisition and velocity model.
+ *   vel:    device [nz][(ny)][nx] velocity in m/s (copied; the caller keeps it).
+ *   stream: hipStream_t to queue work on (NULL = default stream).
+ * Checks the CFL limit of the 8th-order scheme (v_max dt/dx <= 0.5547 in 2D,
+ * 0.4529 in 3D) -> ESI_ERR_CFL.  Geometry arrays are copied.
+ */
+esi_status_t esi_plan_create(esi_plan_t* plan, const esi_grid_t* grid, const esi_geom_t* geom,
+                             const float* vel, void* stream);
+
+/* Replace the velocity model (device [nz][(ny)][nx]); same checks as creation.
+ * eta_max keeps the value fixed at plan creation. */
+esi_status_t esi_plan_set_model(esi_plan_t plan, const float* vel);
+
+/* Release the plan and every buffer it owns (waits for its stream). */
+esi_status_t esi_plan_destroy(esi_plan_t plan);
+
+/* Text of the last error on this thread ("" if none).  Valid until the next call. */
+const char* esi_last_error(void);
+
+/*
+ * Forward modelling d = S q (Sec. 2.1 eq. fwi / eq. wave; S = R A^{-1}, Sec. 2.2).
+ *   src_kind ESI_SRC_POINT: src = device [nshots][nt] wavelets, injected at each
+ *            shot's source cell (the physical source f).
+ *   src_kind ESI_SRC_DENSE: src = device [nshots][nt][phys] extended source q
+ *            (eq. newq2), injected on every physical cell.
+ *   data:    device output, [nshots] x [nt][nrec_s] (CSR layout above).
+ */
+esi_status_t esi_forward(esi_plan_t plan, int32_t shot0, int32_t nshots, int32_t src_kind,
+                         const float* src, float* data);
+
+/*
+ * Adjoint modelling S^T d = A^{-T} R^T d (eq. FWI_lambda; the CG right-hand side
+ * "by adjoint modelling", Sec. 3).
+ *   data: device input, CSR layout; receivers sharing a cell add up.
+ *   out:  device output [nshots][nt][phys].
+ */
+esi_status_t esi_adjoint(esi_plan_t plan, int32_t shot0, int32_t nshots, const float* data,
+                         float* out);
+
+/*
+ * Matrix-free normal operator N p = S^T S p + beta B^T B p (eq. axb, Sec. 3:
+ * forward modelling with p as the source, receiver extraction, adjoint
+ * modelling, plus the pointwise beta B^2 p).
+ *   p, Ap: device [nshots][nt][phys] (must not overlap).
+ *   pAp:   device double [nshots] output p . Np per shot, or NULL.
+ */
+esi_status_t esi_normal_apply(esi_plan_t plan, int32_t shot0, int32_t nshots, const float* p,
+                              float* Ap, double* pAp);
+
+typedef struct {
+    int32_t iters;       /* out: largest number of iterations done by a shot */
+    int32_t* shot_iters; /* host [nshots] out, or NULL */
+    double* res_hist;    /* host [nshots][max_iter+1] out, or NULL: ||r_k|| / ||r_0|| of
+                            the recursively updated residual; unused entries set to -1 */
+} esi_cg_report_t;
+
+/*
+ * Conjugate gradients (Algorithm 1, Sec. 3) on eq. (normalewi), one independent
+ * system per shot, x_0 = 0.  Each shot stops after the iteration in which
+ * ||r_{k+1}|| < rtol ||r_0||, or after max_iter iterations.  Vectors are
+ * float32; dot products and step lengths are float64.
+ *   d_obs: device data (CSR layout).
+ *   x:     device [nshots][nt][phys] output (the extended source).
+ *   work:  device float32 scratch of 3 * nshots * nt * phys elements (r, p, Np).
+ *   rep:   host report, may be NULL.
+ * Returns ESI_ERR_BREAKDOWN if p.Np <= 0 or ESI_ERR_NONFINITE on a non-finite
+ * scalar; x then holds the last finished iterate.
+ */
+esi_status_t esi_cg_solve(esi_plan_t plan, int32_t shot0, int32_t nshots, const float* d_obs,
+                          float* x, float* work, int32_t max_iter, double rtol,
+                          esi_cg_report_t* rep);
+
+/*
+ * Adjoint-state gradient with respect to m = 1/v^2, summed over the shots and
+ * ADDED to grad_m (device [phys]):
+ *   g(x) = sum_n lambda^n(x) v(x)^2 (L u^n + P q^n)(x),   u = A^{-1} q,
+ * where v^2 (L u^n + q^n) is the discrete (dA/dm) u (eq. gradewi, Sec. 2.3).
+ *   ESI_GRAD_PENALTY: lambda = beta B^T B q (Algorithm 2); src = q (dense).
+ *                     One forward pass; no wavefield storage.  data unused.
+ *   ESI_GRAD_ADJOINT: lambda = S^T (d_obs - S q) (eq. ewiadj); src = q (dense),
+ *                     data = d_obs.
+ *   ESI_GRAD_SEED:    gradients of a loss L(d), d = S q, given data = dL/dd:
+ *                     adds -sum_n (S^T G)^n (dA/dm) u^n to grad_m and, when
+ *                     grad_src is not NULL, writes dL/dq to grad_src
+ *                     ([nshots][nt] for a point source, [nshots][nt][phys] for a
+ *                     dense one).  src_kind as in esi_forward.
+ *   ckpt_every: 0 stores (dA/dm)u for every step (nshots*nt*phys floats of plan
+ *               scratch); K > 0 stores two time levels every K steps and
+ *               recomputes each K-step segment during the backward pass.
+ */
+esi_status_t esi_gradient(esi_plan_t plan, int32_t shot0, int32_t nshots, int32_t mode,
+                          int32_t src_kind, const float* src, const float* data,
+                          float* grad_m, float* grad_src, int32_t ckpt_every);
+
+/*
+ * Kernel timing (the tracing facility of the library).  With profiling on,
+ * every time loop of a call is bracketed by a pair of hipEvents on the plan's
+ * stream; esi_plan_profile_read waits for them and reports, per time-step
+ * kernel variant, the number of launches and the elapsed milliseconds of the
+ * loops that ran it (kernel time plus the gaps between its launches).  The
+ * variant is a bit set of fused work (source kind, recording, injection,
+ * outputs, CG fusion, correlation) whose meaning is given by the ESI_K_*
+ * values below.  Turning profiling on (enable != 0) clears the counters.
+ */
+enum {
+    ESI_K_SRC_POINT = 1, ESI_K_SRC_DENSE = 2, ESI_K_CG_FUSE = 4, ESI_K_INJ = 8,
+    ESI_K_GATHER = 16, ESI_K_OUT = 32, ESI_K_NORMAL = 64, ESI_K_PENALTY = 128,
+    ESI_K_STORE = 256, ESI_K_CORR = 512, ESI_K_SRC_REC = 1024
+};
+esi_status_t esi_plan_profile(esi_plan_t plan, int32_t enable);
+/* Fills up to `cap` entries; *count receives the number of variants seen.
+ * flags: host uint32 [cap]; launches: host int64 [cap]; ms: host double [cap];
+ * shot_launches: host int64 [cap], launches weighted by the shots each covered. */
+esi_status_t esi_plan_profile_read(esi_plan_t plan, int32_t cap, int32_t* count, uint32_t* flags,
+                                   int64_t* launches, int64_t* shot_launches, double* ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ESI_H */

@@ -1,0 +1,475 @@
+// C-ABI entry points: modelling, adjoint modelling, normal operator, CG and
+// gradient (the calls of the ESI hot path, Sec. 2-3 and Algorithms 1-2).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "esi_internal.h"
+
+namespace esi {
+
+esi_status_t launch_step2d(Plan* P, unsigned flags, const StepArgs& a);
+void step2d_tile_shape(int* tx, int* tz);
+esi_status_t launch_step3d(Plan* P, unsigned flags, const StepArgs& a);
+void step3d_tile_shape(int* tx, int* ty, int* tz);
+esi_status_t launch_dot(Plan* P, const float* x, const float* y, int nshots, int64_t len,
+                        double* out);
+esi_status_t launch_copy_shots(Plan* P, float* dst, int64_t dst_stride, const float* src,
+                               int64_t src_stride, int64_t n, int nshots);
+
+namespace {
+
+// per-shot ring: u slot 0, u slot 1 (u^n in slot n&1), increment d in slot 2
+constexpr int RING = 3;
+
+esi_status_t check_shots(Plan* P, int shot0, int nshots) {
+    if (nshots < 1 || shot0 < 0 || shot0 + nshots > P->nshots)
+        return fail(ESI_ERR_ARG, "shot range [" + std::to_string(shot0) + ", " +
+                                     std::to_string(shot0 + nshots) + ") outside [0, " +
+                                     std::to_string(P->nshots) + ")");
+    return ESI_OK;
+}
+
+esi_status_t lists_for(Plan* P, TileLists** L) {
+    int tx, ty = 1, tz;
+    if (P->ndim == 2) step2d_tile_shape(&tx, &tz);
+    else step3d_tile_shape(&tx, &ty, &tz);
+    return get_lists(P, tx, tz, ty, L);
+}
+
+esi_status_t launch_step(Plan* P, unsigned flags, const StepArgs& a) {
+    return P->ndim == 2 ? launch_step2d(P, flags, a) : launch_step3d(P, flags, a);
+}
+
+// Fill the fields every step of a call shares.
+StepArgs base_args(Plan* P, const TileLists* L, int shot0, int nshots) {
+    StepArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.fstride = RING * P->fsize;
+    a.c2 = P->c2; a.kx = P->kx; a.kz = P->kz; a.ky = P->ky;
+    a.nzp = P->nzp; a.nyp = P->nyp; a.nxp = P->nxp; a.XS = P->XS; a.YS = P->YS;
+    a.nb = P->nb; a.nz = P->nz; a.ny = P->ny; a.nx = P->nx; a.nphys = P->nphys;
+    a.w0 = P->lap_w[0]; a.w1 = P->lap_w[1]; a.w2 = P->lap_w[2]; a.w3 = P->lap_w[3]; a.w4 = P->lap_w[4];
+    a.dx2 = (float)(P->dx * P->dx);
+    a.inv_dt2 = (float)(1.0 / (P->dt * P->dt));
+    a.beta = (float)P->beta;
+    a.b_eps = (float)P->b_eps;
+    a.nt = P->nt;
+    a.tiles_x = L->tiles_x; a.tiles_y = L->tiles_y; a.tiles_z = L->tiles_z; a.tiles = L->tiles;
+    a.nshots = nshots; a.shot0 = shot0;
+    a.src_pos = P->d_src; a.rec_ptr = P->d_rec_ptr;
+    a.inj_ptr = L->inj_ptr; a.inj_cell = L->inj_cell; a.inj_rptr = L->inj_rptr; a.inj_rid = L->inj_rid;
+    a.gat_ptr = L->gat_ptr; a.gat_cell = L->gat_cell; a.gat_rid = L->gat_rid;
+    a.src_tile = L->src_tile; a.src_cell = L->src_cell;
+    return a;
+}
+
+esi_status_t ring_for(Plan* P, float** ring, int* cap, int nshots) {
+    if (nshots > *cap || !*ring) {
+        int64_t capb = (int64_t)(*ring ? *cap : 0) * RING * P->fsize * (int64_t)sizeof(float);
+        ESI_TRY(grow((void**)ring, &capb, (int64_t)nshots * RING * P->fsize * (int64_t)sizeof(float), P->stream));
+        *cap = nshots;
+    }
+    return launch_fill(P, *ring, (int64_t)nshots * RING * P->fsize, 0.f);
+}
+
+int64_t data_len(Plan* P, int shot0, int nshots) {
+    return (int64_t)P->nt * (P->h_rec_ptr[shot0 + nshots] - P->h_rec_ptr[shot0]);
+}
+
+// Profiling brackets around a time loop.
+struct ProfScope {
+    Plan* P; unsigned flags; int64_t launches, shots; hipEvent_t e0 = nullptr, e1 = nullptr;
+    ProfScope(Plan* p, unsigned f, int64_t n, int64_t ns) : P(p), flags(f), launches(n), shots(ns) {
+        if (!P->prof_on || n <= 0) return;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) { e0 = e1 = nullptr; return; }
+        hipEventRecord(e0, P->stream);
+    }
+    ~ProfScope() {
+        if (!e0) return;
+        hipEventRecord(e1, P->stream);
+        P->prof_pending.push_back({flags, launches, launches * shots, e0, e1});
+    }
+};
+
+// Forward time loop over [n0, n1) on `ring` (slot n&1 holds u^n).  Optional
+// checkpoint saves of (u^n, d^n) at n = k*K into ckpt[s][k][2][fsize].
+esi_status_t forward_loop(Plan* P, StepArgs a, unsigned flags, float* ring, int n0, int n1,
+                          float* ckpt = nullptr, int K = 0, int nseg = 0) {
+    ProfScope prof(P, flags, n1 - n0, a.nshots);
+    for (int n = n0; n < n1; ++n) {
+        if (ckpt && n % K == 0) {
+            const int k = n / K;
+            const int64_t cs = (int64_t)nseg * 2 * P->fsize;   // per-shot checkpoint stride
+            ESI_TRY(launch_copy_shots(P, ckpt + (int64_t)k * 2 * P->fsize, cs,
+                                      ring + (int64_t)(n & 1) * P->fsize, RING * P->fsize, P->fsize,
+                                      a.nshots));
+            ESI_TRY(launch_copy_shots(P, ckpt + (int64_t)k * 2 * P->fsize + P->fsize, cs,
+                                      ring + 2 * P->fsize, RING * P->fsize, P->fsize, a.nshots));
+        }
+        a.step = n;
+        a.cur = ring + (int64_t)(n & 1) * P->fsize;
+        a.nxt = ring + (int64_t)((n + 1) & 1) * P->fsize;
+        a.dvel = ring + 2 * P->fsize;
+        if (flags & F_STORE) a.store_slot = K > 0 ? n % K : n;
+        ESI_TRY(launch_step(P, flags, a));
+    }
+    return ESI_OK;
+}
+
+// Adjoint time loop over j = j1-1 .. j0 on `ring`; `k` counts steps since the
+// start of the whole backward sweep (slot k&1 holds mu^{j+1}).
+esi_status_t adjoint_loop(Plan* P, StepArgs a, unsigned flags, float* ring, int j0, int j1,
+                          int K = 0) {
+    ProfScope prof(P, flags, j1 - j0, a.nshots);
+    for (int j = j1 - 1; j >= j0; --j) {
+        const int k = P->nt - 1 - j;
+        a.step = j;
+        a.cur = ring + (int64_t)(k & 1) * P->fsize;
+        a.nxt = ring + (int64_t)((k + 1) & 1) * P->fsize;
+        a.dvel = ring + 2 * P->fsize;
+        if (flags & F_CORR) a.store_slot = K > 0 ? j % K : j;
+        ESI_TRY(launch_step(P, flags, a));
+    }
+    return ESI_OK;
+}
+
+esi_status_t do_forward(Plan* P, int shot0, int ns, int kind, const float* src, float* data,
+                        const TileLists* L) {
+    ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
+    StepArgs a = base_args(P, L, shot0, ns);
+    unsigned fl = F_GATHER;
+    if (kind == ESI_SRC_POINT) { fl |= F_SRC_POINT; a.wavelet = src; }
+    else { fl |= F_SRC_DENSE; a.dsrc = src; }
+    a.gat_data = data;
+    ESI_TRY(forward_loop(P, a, fl, P->ring, 0, P->nt));
+    return launch_final_gather(P, P->ring + (int64_t)(P->nt & 1) * P->fsize, RING * P->fsize, data,
+                               shot0, ns);
+}
+
+// N p into Ap (+ p.Np partials in P->part [ns][tiles]) for the active shots.
+esi_status_t do_normal(Plan* P, int shot0, int ns, const float* p, float* Ap, const TileLists* L,
+                       const int* active, bool cg_fuse, float* r, float* x, double* alpha,
+                       double* beta) {
+    const int64_t dl = data_len(P, shot0, ns);
+    ESI_TRY(grow_t(&P->dscr, &P->dscr_cap, std::max<int64_t>(dl, 1), P->stream));
+    ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
+    StepArgs a = base_args(P, L, shot0, ns);
+    a.active = active;
+    a.gat_data = P->dscr;
+    if (cg_fuse) {
+        a.cg_r = r; a.cg_p = (float*)p; a.cg_x = x; a.cg_alpha = alpha; a.cg_beta = beta;
+        ESI_TRY(forward_loop(P, a, F_CG_FUSE | F_GATHER, P->ring, 0, P->nt));
+    } else {
+        a.dsrc = p;
+        ESI_TRY(forward_loop(P, a, F_SRC_DENSE | F_GATHER, P->ring, 0, P->nt));
+    }
+    ESI_TRY(launch_final_gather(P, P->ring + (int64_t)(P->nt & 1) * P->fsize, RING * P->fsize, P->dscr,
+                                shot0, ns));
+    ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
+    ESI_TRY(grow_t(&P->part, &P->part_cap, (int64_t)ns * L->tiles, P->stream));
+    hipError_t e = hipMemsetAsync(P->part, 0, (size_t)ns * L->tiles * sizeof(double), P->stream);
+    if (e != hipSuccess) return fail(ESI_ERR_HIP, hipGetErrorString(e));
+    StepArgs b = base_args(P, L, shot0, ns);
+    b.active = active;
+    b.inj_data = P->dscr;
+    b.dp = p;
+    b.dout = Ap;
+    b.part = P->part;
+    return adjoint_loop(P, b, F_INJ | F_NORMAL, P->ring, 0, P->nt);
+}
+
+}  // namespace
+}  // namespace esi
+
+using namespace esi;
+
+extern "C" esi_status_t esi_forward(esi_plan_t plan, int32_t shot0, int32_t nshots,
+                                    int32_t src_kind, const float* src, float* data) {
+    set_error("");
+    if (!plan) return fail(ESI_ERR_ARG, "null plan");
+    Plan* P = (Plan*)plan;
+    ESI_TRY(check_shots(P, shot0, nshots));
+    if (src_kind != ESI_SRC_POINT && src_kind != ESI_SRC_DENSE) return fail(ESI_ERR_ARG, "bad src_kind");
+    if (!src) return fail(ESI_ERR_ARG, "null src");
+    if (!data && data_len(P, shot0, nshots) > 0) return fail(ESI_ERR_ARG, "null data");
+    TileLists* L;
+    ESI_TRY(lists_for(P, &L));
+    return do_forward(P, shot0, nshots, src_kind, src, data, L);
+}
+
+extern "C" esi_status_t esi_adjoint(esi_plan_t plan, int32_t shot0, int32_t nshots,
+                                    const float* data, float* out) {
+    set_error("");
+    if (!plan) return fail(ESI_ERR_ARG, "null plan");
+    Plan* P = (Plan*)plan;
+    ESI_TRY(check_shots(P, shot0, nshots));
+    if (!out || (!data && data_len(P, shot0, nshots) > 0)) return fail(ESI_ERR_ARG, "null pointer");
+    TileLists* L;
+    ESI_TRY(lists_for(P, &L));
+    ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, nshots));
+    StepArgs a = base_args(P, L, shot0, nshots);
+    a.inj_data = data;
+    a.dout = out;
+    return adjoint_loop(P, a, F_INJ | F_OUT, P->ring, 0, P->nt);
+}
+
+extern "C" esi_status_t esi_normal_apply(esi_plan_t plan, int32_t shot0, int32_t nshots,
+                                         const float* p, float* Ap, double* pAp) {
+    set_error("");
+    if (!plan) return fail(ESI_ERR_ARG, "null plan");
+    Plan* P = (Plan*)plan;
+    ESI_TRY(check_shots(P, shot0, nshots));
+    if (!p || !Ap) return fail(ESI_ERR_ARG, "null pointer");
+    const int64_t n = (int64_t)nshots * P->nt * P->nphys;
+    if ((Ap < p + n) && (p < Ap + n)) return fail(ESI_ERR_ARG, "p and Ap overlap");
+    TileLists* L;
+    ESI_TRY(lists_for(P, &L));
+    ESI_TRY(do_normal(P, shot0, nshots, p, Ap, L, nullptr, false, nullptr, nullptr, nullptr, nullptr));
+    if (pAp) ESI_TRY(launch_reduce_parts(P, P->part, L->tiles, nshots, pAp));
+    return ESI_OK;
+}
+
+extern "C" esi_status_t esi_cg_solve(esi_plan_t plan, int32_t shot0, int32_t ns,
+                                     const float* d_obs, float* x, float* work, int32_t max_iter,
+                                     double rtol, esi_cg_report_t* rep) {
+    set_error("");
+    if (!plan) return fail(ESI_ERR_ARG, "null plan");
+    Plan* P = (Plan*)plan;
+    ESI_TRY(check_shots(P, shot0, ns));
+    if (!x || !work || (!d_obs && data_len(P, shot0, ns) > 0)) return fail(ESI_ERR_ARG, "null pointer");
+    if (max_iter < 1) return fail(ESI_ERR_ARG, "max_iter must be >= 1");
+    if (!(rtol >= 0)) return fail(ESI_ERR_ARG, "rtol must be >= 0");
+    TileLists* L;
+    ESI_TRY(lists_for(P, &L));
+    const int64_t len = (int64_t)P->nt * P->nphys;
+    float* r = work;
+    float* p = work + (int64_t)ns * len;
+    float* Ap = work + 2 * (int64_t)ns * len;
+    if (P->nshots < ns) return fail(ESI_ERR_ARG, "internal: scalar space");
+    double* rr = P->scal;
+    double* pAp = P->scal + P->nshots;
+    double* alpha = P->scal + 2 * P->nshots;
+    double* beta = P->scal + 3 * P->nshots;
+    double* rr_new = P->scal + 4 * P->nshots;
+    int* active = P->flags;
+    int* finish = P->flags + P->nshots;
+
+    // b = S^T d (adjoint modelling, Sec. 3); r_0 = b, p_0 = r_0, x_0 = 0
+    ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
+    {
+        StepArgs a = base_args(P, L, shot0, ns);
+        a.inj_data = d_obs;
+        a.dout = r;
+        ESI_TRY(adjoint_loop(P, a, F_INJ | F_OUT, P->ring, 0, P->nt));
+    }
+    ESI_TRY(launch_copy(P, p, r, ns * len));
+    ESI_TRY(launch_fill(P, x, ns * len, 0.f));
+    ESI_TRY(launch_dot(P, r, r, ns, len, rr));
+
+    std::vector<double> h_rr0(ns), h_rr(ns), h_pAp(ns);
+    std::vector<int> h_active(ns, 1), h_finish(ns, 0), h_iters(ns, 0);
+    ESI_HIP_TRY(hipMemcpyAsync(h_rr0.data(), rr, ns * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+    ESI_HIP_TRY(hipStreamSynchronize(P->stream));
+    if (rep && rep->res_hist)
+        for (int s = 0; s < ns; ++s) {
+            for (int k = 0; k <= max_iter; ++k) rep->res_hist[(int64_t)s * (max_iter + 1) + k] = -1.0;
+            rep->res_hist[(int64_t)s * (max_iter + 1)] = 1.0;
+        }
+    int nact = 0;
+    for (int s = 0; s < ns; ++s) {
+        if (!std::isfinite(h_rr0[s])) return fail(ESI_ERR_NONFINITE, "non-finite right-hand side");
+        if (h_rr0[s] == 0.0) h_active[s] = 0;   // b = 0: x = 0 is exact
+        nact += h_active[s];
+    }
+    ESI_HIP_TRY(hipMemcpyAsync(active, h_active.data(), ns * sizeof(int), hipMemcpyHostToDevice, P->stream));
+    ESI_HIP_TRY(hipMemcpyAsync(finish, h_finish.data(), ns * sizeof(int), hipMemcpyHostToDevice, P->stream));
+
+    int done_iters = 0;
+    esi_status_t status = ESI_OK;
+    for (int k = 0; k < max_iter && nact > 0; ++k) {
+        // N p_k (the first direction is p_0 = r_0; later ones are formed in the
+        // forward pass: p_k = r_k + beta p_{k-1}, x_k = x_{k-1} + alpha p_{k-1})
+        ESI_TRY(do_normal(P, shot0, ns, p, Ap, L, active, k > 0, r, x, alpha, beta));
+        ESI_TRY(launch_reduce_parts(P, P->part, L->tiles, ns, pAp));
+        ESI_TRY(launch_cg_alpha(P, rr, pAp, alpha, ns));
+        ESI_TRY(launch_r_update(P, r, Ap, alpha, active, ns, len, rr_new));
+        ESI_HIP_TRY(hipMemcpyAsync(h_rr.data(), rr_new, ns * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+        ESI_HIP_TRY(hipMemcpyAsync(h_pAp.data(), pAp, ns * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+        ESI_HIP_TRY(hipStreamSynchronize(P->stream));
+        done_iters = k + 1;
+        int nfin = 0;
+        for (int s = 0; s < ns; ++s) {
+            h_finish[s] = 0;
+            if (!h_active[s]) continue;
+            h_iters[s] = k + 1;
+            if (!std::isfinite(h_pAp[s]) || !std::isfinite(h_rr[s])) status = ESI_ERR_NONFINITE;
+            else if (h_pAp[s] <= 0.0) status = ESI_ERR_BREAKDOWN;
+            const double rel = std::sqrt(h_rr[s] / h_rr0[s]);
+            if (rep && rep->res_hist) rep->res_hist[(int64_t)s * (max_iter + 1) + k + 1] = rel;
+            if (status != ESI_OK || rel < rtol || k == max_iter - 1) {
+                h_finish[s] = 1;
+                ++nfin;
+            }
+        }
+        if (status != ESI_OK) {
+            // keep x at the last finished iterate x_k: nothing more is applied
+            fail(status, status == ESI_ERR_BREAKDOWN ? "CG breakdown: p.Np <= 0"
+                                                     : "CG: non-finite scalar");
+            break;
+        }
+        ESI_TRY(launch_cg_beta(P, rr_new, rr, beta, ns));
+        if (nfin > 0) {
+            // shots leaving now take their last update x_{k+1} = x_k + alpha_k p_k here
+            ESI_HIP_TRY(hipMemcpyAsync(finish, h_finish.data(), ns * sizeof(int), hipMemcpyHostToDevice, P->stream));
+            ESI_TRY(launch_axpy_flag(P, x, p, alpha, finish, 1, ns, len));
+            for (int s = 0; s < ns; ++s)
+                if (h_finish[s]) { h_active[s] = 0; --nact; }
+            ESI_HIP_TRY(hipMemcpyAsync(active, h_active.data(), ns * sizeof(int), hipMemcpyHostToDevice, P->stream));
+            // the host vectors must outlive the queued copies
+            ESI_HIP_TRY(hipStreamSynchronize(P->stream));
+        }
+    }
+    if (rep) {
+        rep->iters = done_iters;
+        if (rep->shot_iters)
+            for (int s = 0; s < ns; ++s) rep->shot_iters[s] = h_iters[s];
+    }
+    return status;
+}
+
+extern "C" esi_status_t esi_gradient(esi_plan_t plan, int32_t shot0, int32_t ns, int32_t mode,
+                                     int32_t src_kind, const float* src, const float* data,
+                                     float* grad_m, float* grad_src, int32_t K) {
+    set_error("");
+    if (!plan) return fail(ESI_ERR_ARG, "null plan");
+    Plan* P = (Plan*)plan;
+    ESI_TRY(check_shots(P, shot0, ns));
+    if (mode != ESI_GRAD_PENALTY && mode != ESI_GRAD_ADJOINT && mode != ESI_GRAD_SEED)
+        return fail(ESI_ERR_ARG, "bad gradient mode");
+    if (src_kind != ESI_SRC_POINT && src_kind != ESI_SRC_DENSE) return fail(ESI_ERR_ARG, "bad src_kind");
+    if (mode != ESI_GRAD_SEED && src_kind != ESI_SRC_DENSE)
+        return fail(ESI_ERR_ARG, "PENALTY and ADJOINT modes take a dense extended source");
+    if (!src || !grad_m) return fail(ESI_ERR_ARG, "null pointer");
+    if (mode != ESI_GRAD_PENALTY && !data && data_len(P, shot0, ns) > 0) return fail(ESI_ERR_ARG, "null data");
+    if (K < 0) return fail(ESI_ERR_ARG, "ckpt_every must be >= 0");
+    TileLists* L;
+    ESI_TRY(lists_for(P, &L));
+    const int64_t nph = P->nphys;
+    ESI_TRY(grow_t(&P->gshot, &P->gshot_cap, (int64_t)ns * nph, P->stream));
+    ESI_TRY(launch_fill(P, P->gshot, (int64_t)ns * nph, 0.f));
+    const unsigned srcfl = src_kind == ESI_SRC_POINT ? F_SRC_POINT : F_SRC_DENSE;
+
+    if (mode == ESI_GRAD_PENALTY) {
+        // one forward pass of q correlating beta B^2 q with (dA/dm) u (Algorithm 2)
+        ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
+        StepArgs a = base_args(P, L, shot0, ns);
+        a.dsrc = src;
+        a.gacc = P->gshot;
+        ESI_TRY(forward_loop(P, a, F_SRC_DENSE | F_PENALTY, P->ring, 0, P->nt));
+        return launch_sum_shots(P, P->gshot, ns, nph, 1.f, grad_m);
+    }
+
+    // ADJOINT and SEED: adjoint field of G (G = S q - d_obs for ADJOINT, G = data for SEED),
+    // correlated with the stored or recomputed (dA/dm) u.
+    const int nt = P->nt;
+    const int64_t dl = data_len(P, shot0, ns);
+    const bool ckpt = K > 0 && K < nt;
+    const int Kc = ckpt ? K : 0;
+    const int nseg = ckpt ? (nt + K - 1) / K : 1;
+    const int slots = ckpt ? K : nt;
+    ESI_TRY(grow_t(&P->store, &P->store_cap, (int64_t)ns * slots * nph, P->stream));
+    if (ckpt) ESI_TRY(grow_t(&P->ckpt, &P->ckpt_cap, (int64_t)ns * nseg * 2 * P->fsize, P->stream));
+    ESI_TRY(grow_t(&P->dscr, &P->dscr_cap, std::max<int64_t>(dl, 1), P->stream));
+    ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
+    StepArgs a = base_args(P, L, shot0, ns);
+    if (src_kind == ESI_SRC_POINT) a.wavelet = src; else a.dsrc = src;
+    a.store = P->store;
+    a.store_stride = (int64_t)slots * nph;
+    const float* G = data;
+    if (mode == ESI_GRAD_ADJOINT) {
+        a.gat_data = P->dscr;
+        ESI_TRY(forward_loop(P, a, srcfl | F_GATHER | (ckpt ? 0u : F_STORE), P->ring, 0, nt,
+                             ckpt ? P->ckpt : nullptr, Kc, nseg));
+        ESI_TRY(launch_final_gather(P, P->ring + (int64_t)(nt & 1) * P->fsize, RING * P->fsize, P->dscr,
+                                    shot0, ns));
+        ESI_TRY(launch_sub(P, P->dscr, P->dscr, data, dl));   // G = S q - d_obs
+        G = P->dscr;
+    } else {
+        ESI_TRY(forward_loop(P, a, srcfl | (ckpt ? 0u : F_STORE), P->ring, 0, nt,
+                             ckpt ? P->ckpt : nullptr, Kc, nseg));
+    }
+    // backward sweep
+    ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
+    if (ckpt) ESI_TRY(ring_for(P, &P->ring2, &P->ring2_cap, ns));
+    float* adj_ring = P->ring;
+    StepArgs b = base_args(P, L, shot0, ns);
+    b.inj_data = G;
+    b.gacc = P->gshot;
+    b.store = P->store;
+    b.store_stride = (int64_t)slots * nph;
+    unsigned bfl = F_INJ | F_CORR;
+    if (mode == ESI_GRAD_SEED && grad_src) {
+        if (src_kind == ESI_SRC_DENSE) { bfl |= F_OUT; b.dout = grad_src; }
+        else { bfl |= F_SRC_REC; b.src_rec = grad_src; }
+    }
+    if (!ckpt) {
+        ESI_TRY(adjoint_loop(P, b, bfl, adj_ring, 0, nt));
+    } else {
+        for (int k = nseg - 1; k >= 0; --k) {
+            const int n0 = k * K, n1 = std::min(nt, n0 + K);
+            // restore (u^{n0}, d^{n0}) into the recompute ring: slot n0&1 holds u^{n0}
+            const int64_t cs = (int64_t)nseg * 2 * P->fsize;
+            ESI_TRY(launch_copy_shots(P, P->ring2 + (int64_t)(n0 & 1) * P->fsize, RING * P->fsize,
+                                      P->ckpt + (int64_t)k * 2 * P->fsize, cs, P->fsize, ns));
+            ESI_TRY(launch_copy_shots(P, P->ring2 + 2 * P->fsize, RING * P->fsize,
+                                      P->ckpt + (int64_t)k * 2 * P->fsize + P->fsize, cs, P->fsize, ns));
+            ESI_TRY(forward_loop(P, a, srcfl | F_STORE, P->ring2, n0, n1, nullptr, K, nseg));
+            ESI_TRY(adjoint_loop(P, b, bfl, adj_ring, n0, n1, K));
+        }
+    }
+    // ADJOINT: lambda = S^T (d_obs - S q) = -S^T G; SEED: grad_m = -sum S^T G (dA/dm) u
+    return launch_sum_shots(P, P->gshot, ns, nph, -1.f, grad_m);
+}
+
+extern "C" esi_status_t esi_plan_profile(esi_plan_t plan, int32_t enable) {
+    set_error("");
+    if (!plan) return fail(ESI_ERR_ARG, "null plan");
+    Plan* P = (Plan*)plan;
+    ESI_HIP_TRY(hipStreamSynchronize(P->stream));
+    for (auto& r : P->prof_pending) { hipEventDestroy(r.e0); hipEventDestroy(r.e1); }
+    P->prof_pending.clear();
+    if (enable) P->prof_tot.clear();
+    P->prof_on = enable != 0;
+    return ESI_OK;
+}
+
+extern "C" esi_status_t esi_plan_profile_read(esi_plan_t plan, int32_t cap, int32_t* count,
+                                              uint32_t* flags, int64_t* launches,
+                                              int64_t* shot_launches, double* ms) {
+    set_error("");
+    if (!plan || !count) return fail(ESI_ERR_ARG, "null argument");
+    if (cap > 0 && (!flags || !launches || !shot_launches || !ms)) return fail(ESI_ERR_ARG, "null output array");
+    Plan* P = (Plan*)plan;
+    for (auto& r : P->prof_pending) {
+        ESI_HIP_TRY(hipEventSynchronize(r.e1));
+        float t = 0.f;
+        ESI_HIP_TRY(hipEventElapsedTime(&t, r.e0, r.e1));
+        bool found = false;
+        for (auto& q : P->prof_tot)
+            if (q.flags == r.flags) { q.launches += r.launches; q.shot_launches += r.shot_launches; q.ms += t; found = true; }
+        if (!found) P->prof_tot.push_back({r.flags, r.launches, r.shot_launches, (double)t});
+        hipEventDestroy(r.e0);
+        hipEventDestroy(r.e1);
+    }
+    P->prof_pending.clear();
+    *count = (int32_t)P->prof_tot.size();
+    for (int i = 0; i < cap && i < (int)P->prof_tot.size(); ++i) {
+        flags[i] = P->prof_tot[i].flags;
+        launches[i] = P->prof_tot[i].launches;
+        shot_launches[i] = P->prof_tot[i].shot_launches;
+        ms[i] = P->prof_tot[i].ms;
+    }
+    return ESI_OK;
+}

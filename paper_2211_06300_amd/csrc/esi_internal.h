@@ -1,0 +1,228 @@
+// Internal declarations of the ESI library: plan layout, device helpers and
+// the launchers each translation unit provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "esi.h"
+
+namespace esi {
+
+constexpr int HALO = 4;          // 8th-order stencil half width
+constexpr int XCDS = 8;          // MI355X: 8 accelerator complex dies, 32 CUs each
+
+// Thread-local error text.
+void set_error(const std::string& s);
+
+// Throw-free status helper: record text, return code.
+esi_status_t fail(esi_status_t code, const std::string& s);
+
+#define ESI_HIP_TRY(expr)                                                            \
+    do {                                                                             \
+        hipError_t _e = (expr);                                                      \
+        if (_e != hipSuccess)                                                        \
+            return ::esi::fail(_e == hipErrorOutOfMemory ? ESI_ERR_OOM : ESI_ERR_HIP, \
+                               std::string(#expr) + ": " + hipGetErrorString(_e));   \
+    } while (0)
+
+#define ESI_TRY(expr)                        \
+    do {                                     \
+        esi_status_t _s = (expr);            \
+        if (_s != ESI_OK) return _s;         \
+    } while (0)
+
+// Per-tile sparse lists for one tile shape, all shots of the plan.
+//  inj: unique injection cells (receivers sharing a cell are summed in a fixed
+//       order); each cell has a CSR range into inj_rid (receiver ids).
+//  gat: one entry per receiver (tile-local cell, receiver id).
+//  src: one entry per shot (tile id, tile-local cell) for the point source.
+struct TileLists {
+    int tx = 0, tz = 0, ty = 0;          // tile shape the lists were built for
+    int tiles_x = 0, tiles_y = 0, tiles_z = 0, tiles = 0;
+    int32_t* inj_ptr = nullptr;          // [nshots][tiles+1] into inj_cell
+    int32_t* inj_cell = nullptr;         // tile-local cell index
+    int32_t* inj_rptr = nullptr;         // [ncell+1] into inj_rid
+    int32_t* inj_rid = nullptr;          // receiver index within its shot
+    int32_t* gat_ptr = nullptr;          // [nshots][tiles+1]
+    int32_t* gat_cell = nullptr;         // tile-local cell index
+    int32_t* gat_rid = nullptr;          // receiver index within its shot
+    int32_t* src_tile = nullptr;         // [nshots]
+    int32_t* src_cell = nullptr;         // [nshots]
+};
+
+struct Plan {
+    // grid
+    int ndim = 2, nz = 0, nx = 0, ny = 1, nb = 0, nt = 0;
+    double dx = 0, dt = 0, eta_max = 0, beta = 0, b_eps = 1;
+    int nzp = 0, nyp = 1, nxp = 0;       // padded grid
+    int ZS = 0, YS = 1, XS = 0;          // storage grid (padded + zero ghost halo)
+    int64_t fsize = 0;                   // floats per stored field (one shot)
+    int64_t nphys = 0;                   // physical cells
+    hipStream_t stream = nullptr;
+    int device = 0;
+
+    // geometry (host copies + device copies)
+    int nshots = 0;
+    std::vector<int32_t> h_src;          // [nshots][ndim]
+    std::vector<int64_t> h_rec_ptr;      // [nshots+1]
+    std::vector<int32_t> h_rec;          // [nrec][ndim]
+    int32_t* d_src = nullptr;            // [nshots][3] (ix, iz, iy), iy = 0 in 2D
+    int64_t* d_rec_ptr = nullptr;        // [nshots+1]
+    int32_t* d_rec = nullptr;            // [nrec][3] (ix, iz, iy)
+    int max_nrec = 0;
+
+    // model-derived coefficients
+    float* c2 = nullptr;                 // storage layout: v^2 dt^2 / dx^2
+    float* kx = nullptr;                 // [nxp] damping contribution per column
+    float* kz = nullptr;                 // [nzp]
+    float* ky = nullptr;                 // [nyp]
+    float vmax = 0.f;
+    float lap_w[5] = {0, 0, 0, 0, 0};    // a_0..a_4 rounded once to float32
+
+    // scratch, grown on demand
+    float* ring = nullptr;               // [cap][3][fsize]: u slots 0/1, increment d
+    int ring_cap = 0;
+    float* ring2 = nullptr;              // second ring (gradient recompute)
+    int ring2_cap = 0;
+    float* dscr = nullptr;               // data scratch (CSR layout)
+    int64_t dscr_cap = 0;
+    float* dscr2 = nullptr;
+    int64_t dscr2_cap = 0;
+    double* part = nullptr;              // reduction partials
+    int64_t part_cap = 0;
+    double* scal = nullptr;              // CG scalars [8][nshots]
+    float* gshot = nullptr;              // per-shot gradient accumulators
+    int64_t gshot_cap = 0;
+    float* store = nullptr;              // (dA/dm)u storage or segment buffer
+    int64_t store_cap = 0;
+    float* ckpt = nullptr;               // checkpoints
+    int64_t ckpt_cap = 0;
+    int* flags = nullptr;                // per-shot active flags [nshots]
+
+    std::vector<TileLists*> lists;       // one per tile shape used
+
+    // profiling: event pairs around time loops, folded into totals on read
+    struct ProfRec { unsigned flags; int64_t launches, shot_launches; hipEvent_t e0, e1; };
+    struct ProfTot { unsigned flags; int64_t launches, shot_launches; double ms; };
+    bool prof_on = false;
+    std::vector<ProfRec> prof_pending;
+    std::vector<ProfTot> prof_tot;
+};
+
+// ---- allocation helpers -------------------------------------------------
+esi_status_t grow(void** p, int64_t* cap, int64_t need_bytes, hipStream_t stream);
+template <class T>
+esi_status_t grow_t(T** p, int64_t* cap_elems, int64_t need_elems, hipStream_t stream) {
+    int64_t capb = *cap_elems * (int64_t)sizeof(T);
+    esi_status_t s = grow((void**)p, &capb, need_elems * (int64_t)sizeof(T), stream);
+    *cap_elems = capb / (int64_t)sizeof(T);
+    return s;
+}
+
+// Lists for a tile shape (built on first use).
+esi_status_t get_lists(Plan* P, int tx, int tz, int ty, TileLists** out);
+
+// ---- launch-side descriptions -----------------------------------------------
+// Everything a time step needs; passed by value to the kernels.
+struct StepArgs {
+    // fields
+    const float* cur;        // u^n (shot 0); shots are fstride apart
+    float* nxt;              // u^{n+1} out
+    float* dvel;             // d^n = u^n - u^{n-1} in, d^{n+1} out
+    int64_t fstride;
+    const float* c2;
+    const float* kx;
+    const float* kz;
+    const float* ky;
+    int nzp, nyp, nxp, XS, YS;
+    int nb, nz, ny, nx;
+    int64_t nphys;
+    float w0, w1, w2, w3, w4;
+    float dx2;               // dx^2 (source scale inside c2 (lap + dx^2 q))
+    float inv_dt2;           // 1 / dt^2
+    float beta;
+    float b_eps;
+    int step;                // n (forward) or j (adjoint)
+    int nt;
+    int tiles_x, tiles_y, tiles_z, tiles;   // per shot
+    int nshots;
+    int shot0;               // global index of the first shot
+    const int32_t* src_pos;  // [global shots][3]
+    const int64_t* rec_ptr;  // [global shots + 1]
+    const int* active;       // [nshots] or null (all active)
+    // tile lists
+    const int32_t* inj_ptr; const int32_t* inj_cell; const int32_t* inj_rptr; const int32_t* inj_rid;
+    const int32_t* gat_ptr; const int32_t* gat_cell; const int32_t* gat_rid;
+    const int32_t* src_tile; const int32_t* src_cell;
+    // sparse values
+    const float* wavelet;    // point source [nshots][nt]
+    const float* inj_data;   // data injected (adjoint), CSR layout
+    float* gat_data;         // data recorded (forward), CSR layout
+    // dense vectors, [nshots][nt][phys]
+    const float* dsrc;       // dense source q^n (forward)
+    float* dout;             // dense output (adjoint mu^j, or N p)
+    const float* dp;         // p for N p = mu + beta B^2 p
+    double* part;            // per-(shot, tile) float64 partial sums, accumulated
+    // CG fused direction update (forward): p = r + b p_old; x += a p_old
+    const float* cg_r;
+    float* cg_p;
+    float* cg_x;
+    const double* cg_alpha;  // [nshots]
+    const double* cg_beta;   // [nshots]
+    // gradient
+    float* gacc;             // [nshots][phys] per-shot accumulators
+    float* store;            // (dA/dm)u store [nshots][slots][phys]
+    int64_t store_stride;    // floats per shot in store
+    int store_slot;          // slot of this step
+    float* src_rec;          // [nshots][nt] adjoint field at the source cell
+};
+
+// kernel flag bits
+enum : unsigned {
+    F_SRC_POINT = 1u << 0,   // inject wavelet at the shot's source cell
+    F_SRC_DENSE = 1u << 1,   // inject dense q^n
+    F_CG_FUSE = 1u << 2,     // q^n = p_new = r + beta p_old, x += alpha p_old
+    F_INJ = 1u << 3,         // inject R^T data^j (adjoint)
+    F_GATHER = 1u << 4,      // record data^{n-1} = R u^n (forward)
+    F_OUT = 1u << 5,         // write mu^j to dout (adjoint)
+    F_NORMAL = 1u << 6,      // write mu^j + beta B^2 p^j to dout, accumulate p.Np
+    F_PENALTY = 1u << 7,     // gacc += beta B^2 q^n (dA/dm) u^n (forward)
+    F_STORE = 1u << 8,       // store (dA/dm) u^n into store slot (forward)
+    F_CORR = 1u << 9,        // gacc += mu^j * store slot (adjoint)
+    F_SRC_REC = 1u << 10,    // src_rec[s][j] = mu^j at the shot's source cell (adjoint)
+};
+
+// Gather of the last trace d^{nt-1} = R u^{nt} (after the time loop).
+esi_status_t launch_final_gather(Plan* P, const float* field, int64_t fstride, float* data,
+                                 int shot0, int nshots);
+
+// ---- vector kernels (vec.hip) ---------------------------------------------
+esi_status_t launch_fill(Plan* P, float* p, int64_t n, float v);
+esi_status_t launch_copy(Plan* P, float* dst, const float* src, int64_t n);
+// r -= alpha_s Np (float32), partial r.r (float64) per block into part;
+// then reduce into out[s].  Vectors are [nshots][len].
+esi_status_t launch_r_update(Plan* P, float* r, const float* Ap, const double* alpha,
+                             const int* active, int nshots, int64_t len, double* rr_out);
+// x += alpha_s p for the shots whose flag equals `which`.
+esi_status_t launch_axpy_flag(Plan* P, float* x, const float* p, const double* alpha,
+                              const int* flag, int which, int nshots, int64_t len);
+// out[s] = sum of part[s][0..n)
+esi_status_t launch_reduce_parts(Plan* P, const double* part, int64_t n, int nshots,
+                                 double* out);
+// per-shot scalar updates of CG
+esi_status_t launch_cg_alpha(Plan* P, const double* rr, const double* pAp, double* alpha,
+                             int nshots);
+esi_status_t launch_cg_beta(Plan* P, const double* rr_new, double* rr, double* beta, int nshots);
+// grad[phys] += sum_s gacc[s][phys] (fixed order over s)
+esi_status_t launch_sum_shots(Plan* P, const float* gacc, int nshots, int64_t len, float sign,
+                              float* grad);
+// out = a - b elementwise
+esi_status_t launch_sub(Plan* P, float* out, const float* a, const float* b, int64_t n);
+// grad_src point: out[s][n] = mu at the source cell, from a dense [nshots][nt][phys] field
+esi_status_t launch_trace_at_src(Plan* P, const float* dense, int shot0, int nshots, float* out);
+
+}  // namespace esi

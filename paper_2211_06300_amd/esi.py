@@ -1,0 +1,255 @@
+"""Python binding of the ESI C ABI (``include/esi.h``, ``libesi.so``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libesi.so``.  Device memory and streams come from PyTorch.  If the
+library is missing this module raises; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libesi.so")
+
+SRC_POINT, SRC_DENSE = 0, 1
+GRAD_PENALTY, GRAD_ADJOINT, GRAD_SEED = 0, 1, 2
+_STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_SHAPE", 3: "ERR_CFL", 4: "ERR_OOM", 5: "ERR_HIP",
+           6: "ERR_BREAKDOWN", 7: "ERR_NONFINITE"}
+
+
+class EsiError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("nz", ctypes.c_int32), ("nx", ctypes.c_int32),
+                ("ny", ctypes.c_int32), ("nb", ctypes.c_int32), ("nt", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dt", ctypes.c_double), ("eta_max", ctypes.c_double),
+                ("beta", ctypes.c_double), ("b_eps", ctypes.c_double)]
+
+
+class _Geom(ctypes.Structure):
+    _fields_ = [("nshots", ctypes.c_int32), ("src", ctypes.POINTER(ctypes.c_int32)),
+                ("rec_ptr", ctypes.POINTER(ctypes.c_int64)), ("rec", ctypes.POINTER(ctypes.c_int32))]
+
+
+class _CgReport(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("shot_iters", ctypes.POINTER(ctypes.c_int32)),
+                ("res_hist", ctypes.POINTER(ctypes.c_double))]
+
+
+_lib = None
+EXPORTS = ["esi_plan_create", "esi_plan_set_model", "esi_plan_destroy", "esi_last_error",
+           "esi_forward", "esi_adjoint", "esi_normal_apply", "esi_cg_solve", "esi_gradient",
+           "esi_plan_profile", "esi_plan_profile_read"]
+# time-step kernel variants (bit set of fused work), as in include/esi.h
+K_FLAGS = {1: "SRC_POINT", 2: "SRC_DENSE", 4: "CG_FUSE", 8: "INJ", 16: "GATHER", 32: "OUT",
+           64: "NORMAL", 128: "PENALTY", 256: "STORE", 512: "CORR", 1024: "SRC_REC"}
+
+
+def load_library(path: str = LIB_PATH):
+    """Load ``libesi.so`` and declare the signatures of ``include/esi.h``."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.esi_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_Grid), ctypes.POINTER(_Geom),
+                                  vp, vp]
+    L.esi_plan_set_model.argtypes = [vp, vp]
+    L.esi_plan_destroy.argtypes = [vp]
+    L.esi_last_error.argtypes = []
+    L.esi_last_error.restype = ctypes.c_char_p
+    L.esi_forward.argtypes = [vp, i32, i32, i32, vp, vp]
+    L.esi_adjoint.argtypes = [vp, i32, i32, vp, vp]
+    L.esi_normal_apply.argtypes = [vp, i32, i32, vp, vp, vp]
+    L.esi_cg_solve.argtypes = [vp, i32, i32, vp, vp, vp, i32, dbl, ctypes.POINTER(_CgReport)]
+    L.esi_gradient.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp, vp, i32]
+    L.esi_plan_profile.argtypes = [vp, i32]
+    L.esi_plan_profile_read.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+    for f in EXPORTS:
+        if f != "esi_last_error":
+            getattr(L, f).restype = ctypes.c_int
+    if path == LIB_PATH:
+        _lib = L
+    return L
+
+
+def _check(code: int):
+    if code != 0:
+        raise EsiError(code, load_library().esi_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("tensors must be contiguous and on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _f32(t, shape, name):
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return _ptr(t)
+
+
+class Plan:
+    """One grid, acquisition and velocity model (``esi_plan_create``).
+
+    ``src`` is int [nshots, ndim] and ``rec`` int [nrec_total, ndim] of physical
+    cells (ix, iz[, iy]); ``rec_ptr`` int [nshots+1] splits ``rec`` by shot.
+    ``vel`` is a CUDA float32 tensor of the physical grid shape.
+    """
+
+    def __init__(self, *, ndim, nz, nx, ny=1, nb, nt, dx, dt, beta, b_eps=1.0, eta_max=-1.0,
+                 src, rec_ptr, rec, vel: torch.Tensor, stream=None):
+        self._lib = load_library()
+        self.ndim, self.nz, self.nx, self.ny, self.nb, self.nt = ndim, nz, nx, ny, nb, nt
+        self.dx, self.dt, self.beta = dx, dt, beta
+        self.phys_shape = (nz, nx) if ndim == 2 else (nz, ny, nx)
+        self.nphys = int(np.prod(self.phys_shape))
+        self.src = np.ascontiguousarray(src, dtype=np.int32).reshape(-1, ndim)
+        self.rec_ptr = np.ascontiguousarray(rec_ptr, dtype=np.int64)
+        self.rec = np.ascontiguousarray(rec, dtype=np.int32).reshape(-1, ndim)
+        self.nshots = self.src.shape[0]
+        g = _Grid(ndim, nz, nx, ny, nb, nt, dx, dt, eta_max, beta, b_eps)
+        geo = _Geom(self.nshots, self.src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                    self.rec_ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                    self.rec.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        self.device = vel.device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(vel.device)
+        h = ctypes.c_void_p()
+        _check(self._lib.esi_plan_create(ctypes.byref(h), ctypes.byref(g), ctypes.byref(geo),
+                                         _f32(vel, self.phys_shape, "vel"),
+                                         ctypes.c_void_p(self.stream.cuda_stream)))
+        self._h = h
+
+    @classmethod
+    def from_config(cls, cfg, vel: torch.Tensor | None = None, device="cuda", **kw):
+        if vel is None:
+            vel = torch.from_numpy(np.ascontiguousarray(cfg.v_start)).to(device)
+        return cls(ndim=cfg.ndim, nz=cfg.nz, nx=cfg.nx, ny=cfg.ny, nb=cfg.nb, nt=cfg.nt,
+                   dx=cfg.dx, dt=cfg.dt, beta=cfg.beta, b_eps=cfg.b_eps, src=cfg.src,
+                   rec_ptr=cfg.rec_ptr, rec=cfg.rec, vel=vel, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(self._lib.esi_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- shapes ---------------------------------------------------------------
+    def _range(self, shot0, nshots):
+        if nshots is None:
+            nshots = self.nshots - shot0
+        return int(shot0), int(nshots)
+
+    def data_shape(self, shot0=0, nshots=None):
+        shot0, nshots = self._range(shot0, nshots)
+        return (self.nt * int(self.rec_ptr[shot0 + nshots] - self.rec_ptr[shot0]),)
+
+    def vec_shape(self, nshots):
+        return (nshots, self.nt, *self.phys_shape)
+
+    def new_data(self, shot0=0, nshots=None):
+        return torch.zeros(self.data_shape(shot0, nshots), dtype=torch.float32, device=self.device)
+
+    def new_vec(self, nshots):
+        return torch.zeros(self.vec_shape(nshots), dtype=torch.float32, device=self.device)
+
+    # -- calls ------------------------------------------------------------------
+    def set_model(self, vel: torch.Tensor):
+        _check(self._lib.esi_plan_set_model(self._h, _f32(vel, self.phys_shape, "vel")))
+
+    def forward(self, src, kind=SRC_POINT, shot0=0, nshots=None, out=None):
+        shot0, nshots = self._range(shot0, nshots)
+        shape = (nshots, self.nt) if kind == SRC_POINT else self.vec_shape(nshots)
+        out = self.new_data(shot0, nshots) if out is None else out
+        _check(self._lib.esi_forward(self._h, shot0, nshots, kind, _f32(src, shape, "src"),
+                                     _f32(out, self.data_shape(shot0, nshots), "data")))
+        return out
+
+    def adjoint(self, data, shot0=0, nshots=None, out=None):
+        shot0, nshots = self._range(shot0, nshots)
+        out = self.new_vec(nshots) if out is None else out
+        _check(self._lib.esi_adjoint(self._h, shot0, nshots,
+                                     _f32(data, self.data_shape(shot0, nshots), "data"),
+                                     _f32(out, self.vec_shape(nshots), "out")))
+        return out
+
+    def normal_apply(self, p, shot0=0, nshots=None, out=None, want_pAp=True):
+        shot0, nshots = self._range(shot0, nshots)
+        out = self.new_vec(nshots) if out is None else out
+        pAp = torch.zeros(nshots, dtype=torch.float64, device=self.device) if want_pAp else None
+        _check(self._lib.esi_normal_apply(self._h, shot0, nshots, _f32(p, self.vec_shape(nshots), "p"),
+                                          _f32(out, self.vec_shape(nshots), "Ap"), _ptr(pAp)))
+        return out, pAp
+
+    def cg_solve(self, d_obs, max_iter, rtol=0.0, shot0=0, nshots=None, x=None, work=None):
+        shot0, nshots = self._range(shot0, nshots)
+        x = self.new_vec(nshots) if x is None else x
+        if work is None:
+            work = torch.empty((3, *self.vec_shape(nshots)), dtype=torch.float32, device=self.device)
+        hist = np.zeros((nshots, max_iter + 1))
+        iters = np.zeros(nshots, dtype=np.int32)
+        rep = _CgReport(0, iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                        hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        _check(self._lib.esi_cg_solve(self._h, shot0, nshots,
+                                      _f32(d_obs, self.data_shape(shot0, nshots), "d_obs"),
+                                      _f32(x, self.vec_shape(nshots), "x"),
+                                      _f32(work, (3, *self.vec_shape(nshots)), "work"),
+                                      int(max_iter), float(rtol), ctypes.byref(rep)))
+        return x, {"iters": int(rep.iters), "shot_iters": iters, "res_hist": hist}
+
+    def gradient(self, mode, src, data=None, kind=SRC_DENSE, shot0=0, nshots=None, grad_m=None,
+                 grad_src=None, ckpt_every=0):
+        shot0, nshots = self._range(shot0, nshots)
+        grad_m = torch.zeros(self.phys_shape, dtype=torch.float32, device=self.device) \
+            if grad_m is None else grad_m
+        sshape = (nshots, self.nt) if kind == SRC_POINT else self.vec_shape(nshots)
+        dptr = None if data is None else _f32(data, self.data_shape(shot0, nshots), "data")
+        gsp = None if grad_src is None else _f32(grad_src, sshape, "grad_src")
+        _check(self._lib.esi_gradient(self._h, shot0, nshots, mode, kind, _f32(src, sshape, "src"),
+                                      dptr, _f32(grad_m, self.phys_shape, "grad_m"), gsp,
+                                      int(ckpt_every)))
+        return grad_m
+
+    # -- timing ------------------------------------------------------------------
+    def profile(self, enable=True):
+        _check(self._lib.esi_plan_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """Per time-step kernel variant: launches, shot-weighted launches and the
+        elapsed milliseconds of the time loops that ran it (hipEvents)."""
+        cap = 32
+        cnt = np.zeros(1, dtype=np.int32)
+        fl = np.zeros(cap, dtype=np.uint32)
+        la = np.zeros(cap, dtype=np.int64)
+        sl = np.zeros(cap, dtype=np.int64)
+        ms = np.zeros(cap, dtype=np.float64)
+        _check(self._lib.esi_plan_profile_read(self._h, cap, cnt.ctypes.data, fl.ctypes.data,
+                                               la.ctypes.data, sl.ctypes.data, ms.ctypes.data))
+        out = {}
+        for i in range(min(int(cnt[0]), cap)):
+            name = "|".join(v for k, v in K_FLAGS.items() if int(fl[i]) & k)
+            out[name] = {"flags": int(fl[i]), "launches": int(la[i]), "shot_launches": int(sl[i]),
+                         "ms": float(ms[i])}
+        return out
