@@ -48,25 +48,27 @@ def bytes_per_shot_launch(flags: int, npad: int, nphys: int) -> int:
     return b
 
 
-def cpu_baseline(cfg, nt_sample: int):
-    """FP64 oracle (plain C loops, OpenMP over rows) on one shot of the same grid:
-    one normal-operator application (forward + adjoint) over nt_sample steps."""
+def cpu_baseline(cfg, nt_sample: int, iters: int = 3):
+    """FP64 oracle (plain C loops, OpenMP over rows) on a bounded sample of the
+    same solve: one shot, the first nt_sample steps of the time axis, the
+    right-hand side S^T d plus `iters` CG iterations (1 + 2 iters propagations)."""
     from oracle import core
     g = core.Grid(2, cfg.nz, cfg.nx, nb=cfg.nb, nt=nt_sample, dx=cfg.dx, dt=cfg.dt)
-    m = core.make_model(g, cfg.v_start)
-    rng = np.random.default_rng(0)
-    p = rng.standard_normal((nt_sample, cfg.nz, cfg.nx))
-    w2 = core.annihilator_sq(g, cfg.src[0])
-    core.build_oracle()
+    m_true = core.make_model(g, cfg.v_true)
+    m0 = core.make_model(g, cfg.v_start)
+    rec = cfg.shot_rec(0)
+    d_obs = core.forward(m_true, cfg.wavelet[:nt_sample].astype(np.float64), rec,
+                         src_pos=cfg.src[0])
     t0 = time.perf_counter()
-    core.normal_apply(m, cfg.shot_rec(0), w2, cfg.beta, p)
+    core.esi_cg(m0, cfg.src[0], rec, d_obs, cfg.beta, iters)
     t = time.perf_counter() - t0
     npad = (cfg.nz + 2 * cfg.nb) * (cfg.nx + 2 * cfg.nb)
-    pts = 2 * npad * nt_sample
+    pts = (1 + 2 * iters) * npad * nt_sample
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": pts / t / 1e9, "unit": "GPts/s", "cores": threads, "kind": "oracle",
-            "sample": f"1 shot, 1 normal-operator application (forward+adjoint), "
-                      f"{nt_sample} of {cfg.nt} steps on the {cfg.nx}x{cfg.nz} grid; {t:.1f} s"}
+            "sample": f"1 shot of {cfg.nshots}, steps 0..{nt_sample - 1} of {cfg.nt}: right-hand "
+                      f"side + {iters} CG iterations ({1 + 2 * iters} propagations) on the "
+                      f"{cfg.nx}x{cfg.nz} grid in {t:.1f} s"}
 
 
 def main():
@@ -80,6 +82,8 @@ def main():
     ap.add_argument("--nt", type=int, default=2000)
     ap.add_argument("--cpu-nt", type=int, default=1000, help="steps in the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="also run one elementwise copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -90,6 +94,12 @@ def main():
     from paper_2211_06300_amd import esi, inputs
 
     dev = torch.device("cuda:0")
+    if args.copy_calib:
+        # reference kernel of known traffic: reads and writes copy_calib MiB each
+        a = torch.ones(args.copy_calib * 262144, dtype=torch.float32, device=dev)
+        b = torch.mul(a, 1.0)
+        torch.cuda.synchronize()
+        del a, b
     cfg = inputs.cfg_single_solve(nshots=args.shots, nt=args.nt)
     npad = (cfg.nz + 2 * cfg.nb) * (cfg.nx + 2 * cfg.nb)
     nphys = cfg.nz * cfg.nx

@@ -45,6 +45,9 @@ __global__ __launch_bounds__(256) void k_step2d(const StepArgs a) {
     __shared__ float sinj[(FL & F_INJ) ? TZ * TX : 1];
     __shared__ double sred[WZ];
 
+    // tile index fastest within a shot: each XCD streams a contiguous stretch
+    // of one shot's fields (tried shot-fastest to share c2 in L2: fewer bytes
+    // fetched but slower, the scattered streams cost more than they save)
     const int L = xcd_remap(blockIdx.x, gridDim.x);
     const int s = L / a.tiles;
     const int t = L - s * a.tiles;
@@ -53,14 +56,93 @@ __global__ __launch_bounds__(256) void k_step2d(const StepArgs a) {
     const int tzi = t / a.tiles_x, txi = t - tzi * a.tiles_x;
     const int x0 = txi * TX, z0 = tzi * TZ;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int XS = a.XS;
+    // every storage offset of a shot's field fits in 32 bits
     const float* __restrict__ cur = a.cur + s * a.fstride;
     float* __restrict__ nxt = a.nxt + s * a.fstride;
     float* __restrict__ dvel = a.dvel + s * a.fstride;
 
-    // LDS (r, c) <- storage (z0 + r, x0 + c), i.e. padded (z0 + r - 4, x0 + c - 4)
-    for (int i = tid; i < LH * LW; i += 256) {
-        const int r = i / LW, c = i - r * LW;
-        sh[i] = cur[(int64_t)(z0 + r) * a.XS + x0 + c];
+    // LDS (r, c) <- storage (z0 + r, x0 + c), i.e. padded (z0 + r - 4, x0 + c - 4).
+    // Wave w stages rows w, w + 4, ...: 64 lanes take the row body, 8 the halo
+    // (the other lanes repeat a halo load so every load is unconditional).
+    // All rows are loaded into registers before the first LDS write.
+    constexpr int RPW = LH / WZ;
+    static_assert(LH % WZ == 0, "tile rows must split evenly over the waves");
+    float tb[RPW], th[RPW];
+    {
+        const float* src = cur + (z0 + wv) * XS + x0;
+#pragma unroll
+        for (int k = 0; k < RPW; ++k) {
+            tb[k] = src[k * WZ * XS + lane];
+            th[k] = src[k * WZ * XS + TX + (lane & (2 * HALO - 1))];
+        }
+    }
+
+    // Per-lane column and rows of this lane: issue every global load first.
+    const int x = x0 + lane;
+    const bool xin = x < a.nxp;
+    const float kxv = a.kx[min(x, a.nxp - 1)];
+    const int ix = x - a.nb;
+    const bool xphys = ix >= 0 && ix < a.nx;
+    const int zb = z0 + wv * RZ;                         // first row of this lane
+    const int so0 = (zb + HALO) * XS + x + HALO;         // storage offset of that row
+    const int64_t vbase = ((int64_t)s * a.nt + a.step) * a.nphys;
+    float c2v[RZ], dv[RZ], kzv[RZ], qv[RZ];
+    int pi[RZ];
+    bool ph[RZ];
+#pragma unroll
+    for (int i = 0; i < RZ; ++i) {
+        const int z = zb + i;
+        c2v[i] = a.c2[so0 + i * XS];
+        dv[i] = dvel[so0 + i * XS];
+        kzv[i] = a.kz[min(z, a.nzp - 1)];
+        const int iz = z - a.nb;
+        ph[i] = xphys && iz >= 0 && iz < a.nz;
+        pi[i] = ph[i] ? iz * a.nx + ix : 0;             // clamped: loads stay unconditional
+        qv[i] = 0.f;
+    }
+    float po[RZ], pn[RZ], pv[RZ];
+    if constexpr ((FL & F_SRC_DENSE) != 0) {
+        const float* __restrict__ q = a.dsrc + vbase;
+#pragma unroll
+        for (int i = 0; i < RZ; ++i) qv[i] = ph[i] ? q[pi[i]] : 0.f;
+    }
+    if constexpr ((FL & F_CG_FUSE) != 0) {
+        const float alp = (float)a.cg_alpha[s];
+        const float bet = (float)a.cg_beta[s];
+        float* __restrict__ p = a.cg_p + vbase;
+        const float* __restrict__ r = a.cg_r + vbase;
+        float* __restrict__ xv = a.cg_x + vbase;
+        float rv[RZ], xo[RZ];
+#pragma unroll
+        for (int i = 0; i < RZ; ++i) { po[i] = p[pi[i]]; rv[i] = r[pi[i]]; xo[i] = xv[pi[i]]; }
+#pragma unroll
+        for (int i = 0; i < RZ; ++i) {
+            pn[i] = fmaf(bet, po[i], rv[i]);
+            if (ph[i]) {
+                p[pi[i]] = pn[i];
+                if (alp != 0.f) xv[pi[i]] = fmaf(alp, po[i], xo[i]);
+            }
+            qv[i] = ph[i] ? pn[i] : 0.f;
+        }
+    }
+    if constexpr ((FL & F_NORMAL) != 0) {
+        const float* __restrict__ p = a.dp + vbase;
+#pragma unroll
+        for (int i = 0; i < RZ; ++i) pv[i] = p[pi[i]];
+    }
+    float stv[RZ];
+    if constexpr ((FL & F_CORR) != 0) {
+        const float* __restrict__ st = a.store + s * a.store_stride + (int64_t)a.store_slot * a.nphys;
+#pragma unroll
+        for (int i = 0; i < RZ; ++i) stv[i] = st[pi[i]];
+    }
+
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) {
+        const int r = wv + k * WZ;
+        sh[r * LW + lane] = tb[k];
+        if (lane < 2 * HALO) sh[r * LW + TX + lane] = th[k];
     }
 
     const int64_t nrec_s = (FL & (F_INJ | F_GATHER)) ? a.rec_ptr[gs + 1] - a.rec_ptr[gs] : 0;
@@ -103,11 +185,6 @@ __global__ __launch_bounds__(256) void k_step2d(const StepArgs a) {
             if constexpr ((FL & F_SRC_POINT) != 0) src_val = a.wavelet[(int64_t)s * a.nt + a.step];
         }
     }
-    float alp = 0.f, bet = 0.f;
-    if constexpr ((FL & F_CG_FUSE) != 0) {
-        alp = (float)a.cg_alpha[s];
-        bet = (float)a.cg_beta[s];
-    }
     float sx = 0.f, sz = 0.f;
     if constexpr ((FL & (F_NORMAL | F_PENALTY)) != 0) {
         sx = (float)a.src_pos[gs * 3 + 0];
@@ -118,19 +195,12 @@ __global__ __launch_bounds__(256) void k_step2d(const StepArgs a) {
 #pragma unroll
     for (int k = 0; k < RZ + 2 * HALO; ++k) col[k] = sh[(wv * RZ + k) * LW + lane + HALO];
 
-    const int x = x0 + lane;
-    const bool xin = x < a.nxp;
-    const float kxv = xin ? a.kx[x] : 0.f;
-    const int ix = x - a.nb;
-    const bool xphys = ix >= 0 && ix < a.nx;
-    const int64_t vbase = ((int64_t)s * a.nt + a.step) * a.nphys;
     double acc = 0.0;
-
 #pragma unroll
     for (int i = 0; i < RZ; ++i) {
         const int zl = wv * RZ + i;
         const int z = z0 + zl;
-        if (!xin || z >= a.nzp) continue;
+        const bool valid = xin && z < a.nzp;
         const float* row = sh + (zl + HALO) * LW + lane + HALO;
         const float cv = col[i + HALO];
         // Laplacian from neighbour differences: the centre weight is -2 sum_k a_k,
@@ -146,75 +216,49 @@ __global__ __launch_bounds__(256) void k_step2d(const StepArgs a) {
         lz = fmaf(a.w4, (col[i + 0] - cv) + (col[i + 8] - cv), lz);
         const float lap = lx + lz;
 
-        const int64_t si = (int64_t)(z + HALO) * a.XS + x + HALO;
-        const float c2v = a.c2[si];
-        const float dv = dvel[si];
-        const int iz = z - a.nb;
-        const bool phys = xphys && iz >= 0 && iz < a.nz;
-        const int64_t pi = (int64_t)iz * a.nx + ix;
-
-        float q = 0.f;
-        if constexpr ((FL & F_SRC_DENSE) != 0) {
-            if (phys) q = a.dsrc[vbase + pi];
-        }
-        if constexpr ((FL & F_CG_FUSE) != 0) {
-            if (phys) {
-                const float po = a.cg_p[vbase + pi];
-                const float pn = fmaf(bet, po, a.cg_r[vbase + pi]);
-                a.cg_p[vbase + pi] = pn;
-                if (alp != 0.f) a.cg_x[vbase + pi] = fmaf(alp, po, a.cg_x[vbase + pi]);
-                q = pn;
-            }
-        }
+        float q = qv[i];
         if constexpr ((FL & F_SRC_POINT) != 0) {
             if (zl * TX + lane == src_cell) q += src_val;
         }
         if constexpr ((FL & F_INJ) != 0) {
             if (has_inj) q += sinj[zl * TX + lane];
         }
-        const float kap = kxv + a.kz[z];
+        const float kap = kxv + kzv[i];
         const float lq = fmaf(a.dx2, q, lap);
         // (1+k) u^{n+1} = 2u^n - (1-k) u^{n-1} + c lq advanced through the
         // increment d^n = u^n - u^{n-1}: (1+k) d^{n+1} = (1-k) d^n + c lq and
         // u^{n+1} = u^n + d^{n+1}.  Keeping d in its own array stops the rounding
         // of u from leaking into the velocity, where it would persist.
-        const float dn = fmaf(c2v, lq, (1.f - kap) * dv) / (1.f + kap);
+        const float dn = fmaf(c2v[i], lq, (1.f - kap) * dv[i]) / (1.f + kap);
         const float un = cv + dn;
-        dvel[si] = dn;
-        nxt[si] = un;
-
-        if constexpr ((FL & F_OUT) != 0) {
-            if (phys) a.dout[vbase + pi] = un;
+        if (valid) {
+            dvel[so0 + i * XS] = dn;
+            nxt[so0 + i * XS] = un;
         }
+        if (!ph[i]) continue;
+        if constexpr ((FL & F_OUT) != 0) a.dout[vbase + pi[i]] = un;
         if constexpr ((FL & F_SRC_REC) != 0) {
             if (zl * TX + lane == src_cell) a.src_rec[(int64_t)s * a.nt + a.step] = un;
         }
         if constexpr ((FL & (F_NORMAL | F_PENALTY)) != 0) {
-            if (phys) {
-                const float ddx = (float)ix - sx, ddz = (float)iz - sz;
-                const float bb = sqrtf(ddx * ddx + ddz * ddz) + a.b_eps;
-                const float wb = a.beta * (bb * bb);
-                if constexpr ((FL & F_NORMAL) != 0) {
-                    const float pv = a.dp[vbase + pi];
-                    const float np = fmaf(wb, pv, un);
-                    a.dout[vbase + pi] = np;
-                    acc += (double)pv * (double)np;
-                }
-                if constexpr ((FL & F_PENALTY) != 0) {
-                    float* g = a.gacc + (int64_t)s * a.nphys + pi;
-                    *g = fmaf(wb * q, c2v * a.inv_dt2 * lq, *g);
-                }
+            const float ddx = (float)ix - sx, ddz = (float)(z - a.nb) - sz;
+            const float bb = sqrtf(ddx * ddx + ddz * ddz) + a.b_eps;
+            const float wb = a.beta * (bb * bb);
+            if constexpr ((FL & F_NORMAL) != 0) {
+                const float np = fmaf(wb, pv[i], un);
+                a.dout[vbase + pi[i]] = np;
+                acc += (double)pv[i] * (double)np;
+            }
+            if constexpr ((FL & F_PENALTY) != 0) {
+                float* g = a.gacc + (int64_t)s * a.nphys + pi[i];
+                *g = fmaf(wb * q, c2v[i] * a.inv_dt2 * lq, *g);
             }
         }
-        if constexpr ((FL & F_STORE) != 0) {
-            if (phys) a.store[s * a.store_stride + (int64_t)a.store_slot * a.nphys + pi] =
-                c2v * a.inv_dt2 * lq;
-        }
+        if constexpr ((FL & F_STORE) != 0)
+            a.store[s * a.store_stride + (int64_t)a.store_slot * a.nphys + pi[i]] = c2v[i] * a.inv_dt2 * lq;
         if constexpr ((FL & F_CORR) != 0) {
-            if (phys) {
-                float* g = a.gacc + (int64_t)s * a.nphys + pi;
-                *g = fmaf(un, a.store[s * a.store_stride + (int64_t)a.store_slot * a.nphys + pi], *g);
-            }
+            float* g = a.gacc + (int64_t)s * a.nphys + pi[i];
+            *g = fmaf(un, stv[i], *g);
         }
     }
 

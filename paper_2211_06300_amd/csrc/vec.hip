@@ -44,6 +44,8 @@ __global__ void k_sub(float* __restrict__ d, const float* __restrict__ a, const 
 }
 
 // grid: (bps, nshots).  r -= alpha_s Ap; part[s][b] = sum r^2 over the block's chunk.
+// Chunks are multiples of 4 elements so the body runs on float4 when the
+// shot's slice is 16-byte aligned.
 __global__ __launch_bounds__(NT) void k_r_update(float* __restrict__ r, const float* __restrict__ Ap,
                                                  const double* __restrict__ alpha,
                                                  const int* __restrict__ active, int64_t len,
@@ -55,12 +57,28 @@ __global__ __launch_bounds__(NT) void k_r_update(float* __restrict__ r, const fl
         return;
     }
     const float al = (float)alpha[s];
-    const int64_t chunk = (len + bps - 1) / bps;
-    const int64_t beg = (int64_t)b * chunk, end = min(len, beg + chunk);
+    const int64_t chunk = ((len + bps - 1) / bps + 3) & ~(int64_t)3;
+    const int64_t beg = min(len, (int64_t)b * chunk), end = min(len, beg + chunk);
     float* rs = r + (int64_t)s * len;
     const float* as = Ap + (int64_t)s * len;
     double acc = 0.0;
-    for (int64_t i = beg + threadIdx.x; i < end; i += NT) {
+    const bool vec = ((reinterpret_cast<uintptr_t>(rs) | reinterpret_cast<uintptr_t>(as)) & 15) == 0;
+    int64_t i0 = beg;
+    if (vec) {
+        const int64_t nv = (end - beg) >> 2;
+        float4* r4 = reinterpret_cast<float4*>(rs + beg);
+        const float4* a4 = reinterpret_cast<const float4*>(as + beg);
+        for (int64_t k = threadIdx.x; k < nv; k += NT) {
+            float4 v = r4[k];
+            const float4 w = a4[k];
+            v.x = fmaf(-al, w.x, v.x); v.y = fmaf(-al, w.y, v.y);
+            v.z = fmaf(-al, w.z, v.z); v.w = fmaf(-al, w.w, v.w);
+            r4[k] = v;
+            acc += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
+        }
+        i0 = beg + 4 * nv;
+    }
+    for (int64_t i = i0 + threadIdx.x; i < end; i += NT) {
         const float v = fmaf(-al, as[i], rs[i]);
         rs[i] = v;
         acc += (double)v * (double)v;
