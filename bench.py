@@ -40,12 +40,17 @@ def log(*a):
 DENSE_BYTES = {2: 4, 4: 20, 32: 4, 64: 8, 128: 8, 256: 4, 512: 12}
 
 
+TWO_STEP = 1 << 15
+
+
 def bytes_per_shot_launch(flags: int, npad: int, nphys: int) -> int:
+    """Algorithmic bytes of one launch for one shot (a two-step launch counts
+    both steps)."""
     b = 16 * npad
     for bit, per in DENSE_BYTES.items():
         if flags & bit:
             b += per * nphys
-    return b
+    return b * (2 if flags & TWO_STEP else 1)
 
 
 def cpu_baseline(cfg, nt_sample: int, iters: int = 3):
@@ -185,7 +190,8 @@ def main():
                    "nt": cfg.nt, "shots": cfg.nshots, "shot_group": G,
                    "cg_iters": args.cg_iters, "beta": cfg.beta,
                    "propagations_per_shot": props_per_shot},
-        "roofline": {"bound": "hbm", "kernel": f"k_step2d<{name}>",
+        "roofline": {"bound": "hbm",
+                     "kernel": ("k_step2d_t2" if rec["flags"] & TWO_STEP else "k_step2d") + f"<{name}>",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "alg_bytes_per_launch": int(alg_bytes),

@@ -188,6 +188,14 @@ esi_status_t esi_gradient(esi_plan_t plan, int32_t shot0, int32_t nshots, int32_
                           float* grad_m, float* grad_src, int32_t ckpt_every);
 
 /*
+ * Time blocking of the 2D kernels: 2 (default) advances two time steps per
+ * launch wherever a call allows it (the wavefield state then crosses HBM once
+ * per two steps), 1 advances one step per launch.  Results are identical bit
+ * for bit either way.  Returns ESI_ERR_ARG for other values.
+ */
+esi_status_t esi_plan_set_time_block(esi_plan_t plan, int32_t steps);
+
+/*
  * Kernel timing (the tracing facility of the library).  With profiling on,
  * every time loop of a call is bracketed by a pair of hipEvents on the plan's
  * stream; esi_plan_profile_read waits for them and reports, per time-step
@@ -195,12 +203,13 @@ esi_status_t esi_gradient(esi_plan_t plan, int32_t shot0, int32_t nshots, int32_
  * loops that ran it (kernel time plus the gaps between its launches).  The
  * variant is a bit set of fused work (source kind, recording, injection,
  * outputs, CG fusion, correlation) whose meaning is given by the ESI_K_*
- * values below.  Turning profiling on (enable != 0) clears the counters.
+ * values below; ESI_K_TWO_STEP marks launches that advance two steps.
+ * Turning profiling on (enable != 0) clears the counters.
  */
 enum {
     ESI_K_SRC_POINT = 1, ESI_K_SRC_DENSE = 2, ESI_K_CG_FUSE = 4, ESI_K_INJ = 8,
     ESI_K_GATHER = 16, ESI_K_OUT = 32, ESI_K_NORMAL = 64, ESI_K_PENALTY = 128,
-    ESI_K_STORE = 256, ESI_K_CORR = 512, ESI_K_SRC_REC = 1024
+    ESI_K_STORE = 256, ESI_K_CORR = 512, ESI_K_SRC_REC = 1024, ESI_K_TWO_STEP = 32768
 };
 esi_status_t esi_plan_profile(esi_plan_t plan, int32_t enable);
 /* Fills up to `cap` entries; *count receives the number of variants seen.

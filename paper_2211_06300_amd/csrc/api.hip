@@ -9,19 +9,22 @@
 
 namespace esi {
 
-esi_status_t launch_step2d(Plan* P, unsigned flags, const StepArgs& a);
+esi_status_t launch_step2d(Plan* P, unsigned flags, const StepArgs& a, bool two_steps);
 void step2d_tile_shape(int* tx, int* tz);
+void step2d_t2_tile_shape(int* tx, int* tz);
 esi_status_t launch_step3d(Plan* P, unsigned flags, const StepArgs& a);
 void step3d_tile_shape(int* tx, int* ty, int* tz);
 esi_status_t launch_dot(Plan* P, const float* x, const float* y, int nshots, int64_t len,
                         double* out);
 esi_status_t launch_copy_shots(Plan* P, float* dst, int64_t dst_stride, const float* src,
                                int64_t src_stride, int64_t n, int nshots);
+esi_status_t launch_fill_d(Plan* P, double* p, int64_t n);
 
 namespace {
 
-// per-shot ring: u slot 0, u slot 1 (u^n in slot n&1), increment d in slot 2
-constexpr int RING = 3;
+// per-shot ring: u slot 0, u slot 1, d slot 0, d slot 1.  The current state is
+// (u[cs], d[cs]); every launch writes (u[1-cs], d[1-cs]) and flips cs.
+constexpr int RING = 4;
 
 esi_status_t check_shots(Plan* P, int shot0, int nshots) {
     if (nshots < 1 || shot0 < 0 || shot0 + nshots > P->nshots)
@@ -38,8 +41,28 @@ esi_status_t lists_for(Plan* P, TileLists** L) {
     return get_lists(P, tx, tz, ty, L);
 }
 
-esi_status_t launch_step(Plan* P, unsigned flags, const StepArgs& a) {
-    return P->ndim == 2 ? launch_step2d(P, flags, a) : launch_step3d(P, flags, a);
+esi_status_t launch_step(Plan* P, unsigned flags, const StepArgs& a, bool two) {
+    return P->ndim == 2 ? launch_step2d(P, flags, a, two) : launch_step3d(P, flags, a);
+}
+
+bool two_step_ok(Plan* P) { return P->ndim == 2 && P->time_block == 2; }
+
+// Point the tile fields and sparse lists of `a` at the tiling `L`.
+void apply_lists(StepArgs& a, const TileLists* L) {
+    a.tiles_x = L->tiles_x; a.tiles_y = L->tiles_y; a.tiles_z = L->tiles_z; a.tiles = L->tiles;
+    a.inj_ptr = L->inj_ptr; a.inj_cell = L->inj_cell; a.inj_rptr = L->inj_rptr; a.inj_rid = L->inj_rid;
+    a.gat_ptr = L->gat_ptr; a.gat_cell = L->gat_cell; a.gat_rid = L->gat_rid;
+    a.src_tile = L->src_tile; a.src_cell = L->src_cell;
+    a.inj2_ptr = L->inj2_ptr; a.inj2_cell = L->inj2_cell; a.inj2_rptr = L->inj2_rptr; a.inj2_rid = L->inj2_rid;
+}
+
+// Tiling of two-step launches (nullptr when they are not used).
+esi_status_t t2_lists(Plan* P, TileLists** L2) {
+    *L2 = nullptr;
+    if (!two_step_ok(P)) return ESI_OK;
+    int tx, tz;
+    step2d_t2_tile_shape(&tx, &tz);
+    return get_lists(P, tx, tz, 1, L2);
 }
 
 // Fill the fields every step of a call shares.
@@ -56,15 +79,14 @@ StepArgs base_args(Plan* P, const TileLists* L, int shot0, int nshots) {
     a.beta = (float)P->beta;
     a.b_eps = (float)P->b_eps;
     a.nt = P->nt;
-    a.tiles_x = L->tiles_x; a.tiles_y = L->tiles_y; a.tiles_z = L->tiles_z; a.tiles = L->tiles;
+    a.dir = 1;
     a.nshots = nshots; a.shot0 = shot0;
     a.src_pos = P->d_src; a.rec_ptr = P->d_rec_ptr;
-    a.inj_ptr = L->inj_ptr; a.inj_cell = L->inj_cell; a.inj_rptr = L->inj_rptr; a.inj_rid = L->inj_rid;
-    a.gat_ptr = L->gat_ptr; a.gat_cell = L->gat_cell; a.gat_rid = L->gat_rid;
-    a.src_tile = L->src_tile; a.src_cell = L->src_cell;
+    apply_lists(a, L);
     return a;
 }
 
+// A zeroed ring for `nshots` shots; the state starts in slot 0.
 esi_status_t ring_for(Plan* P, float** ring, int* cap, int nshots) {
     if (nshots > *cap || !*ring) {
         int64_t capb = (int64_t)(*ring ? *cap : 0) * RING * P->fsize * (int64_t)sizeof(float);
@@ -74,6 +96,13 @@ esi_status_t ring_for(Plan* P, float** ring, int* cap, int nshots) {
     return launch_fill(P, *ring, (int64_t)nshots * RING * P->fsize, 0.f);
 }
 
+void set_fields(Plan* P, StepArgs& a, float* ring, int cs) {
+    a.cur = ring + (int64_t)cs * P->fsize;
+    a.nxt = ring + (int64_t)(1 - cs) * P->fsize;
+    a.din = ring + (int64_t)(2 + cs) * P->fsize;
+    a.dnx = ring + (int64_t)(3 - cs) * P->fsize;
+}
+
 int64_t data_len(Plan* P, int shot0, int nshots) {
     return (int64_t)P->nt * (P->h_rec_ptr[shot0 + nshots] - P->h_rec_ptr[shot0]);
 }
@@ -81,56 +110,82 @@ int64_t data_len(Plan* P, int shot0, int nshots) {
 // Profiling brackets around a time loop.
 struct ProfScope {
     Plan* P; unsigned flags; int64_t launches, shots; hipEvent_t e0 = nullptr, e1 = nullptr;
-    ProfScope(Plan* p, unsigned f, int64_t n, int64_t ns) : P(p), flags(f), launches(n), shots(ns) {
-        if (!P->prof_on || n <= 0) return;
+    ProfScope(Plan* p, unsigned f, int64_t ns) : P(p), flags(f), launches(0), shots(ns) {
+        if (!P->prof_on) return;
         if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) { e0 = e1 = nullptr; return; }
         hipEventRecord(e0, P->stream);
     }
     ~ProfScope() {
         if (!e0) return;
         hipEventRecord(e1, P->stream);
-        P->prof_pending.push_back({flags, launches, launches * shots, e0, e1});
+        if (launches > 0) P->prof_pending.push_back({flags, launches, launches * shots, e0, e1});
+        else { hipEventDestroy(e0); hipEventDestroy(e1); }
     }
 };
 
-// Forward time loop over [n0, n1) on `ring` (slot n&1 holds u^n).  Optional
-// checkpoint saves of (u^n, d^n) at n = k*K into ckpt[s][k][2][fsize].
-esi_status_t forward_loop(Plan* P, StepArgs a, unsigned flags, float* ring, int n0, int n1,
-                          float* ckpt = nullptr, int K = 0, int nseg = 0) {
-    ProfScope prof(P, flags, n1 - n0, a.nshots);
-    for (int n = n0; n < n1; ++n) {
+// Forward time loop over [n0, n1) on `ring` whose state is in slot *cs.
+// Two-step launches are used where allowed; a checkpoint of (u^n, d^n) is
+// saved at every n = k*K into ckpt[s][k][2][fsize] (two-step launches never
+// straddle a checkpoint).  Profiling records two-step launches with bit 1<<15.
+esi_status_t forward_loop(Plan* P, StepArgs a, unsigned flags, float* ring, int* cs, int n0,
+                          int n1, float* ckpt = nullptr, int K = 0, int nseg = 0) {
+    ProfScope p1(P, flags, a.nshots), p2(P, flags | (1u << 15), a.nshots);
+    TileLists* L2;
+    ESI_TRY(t2_lists(P, &L2));
+    const bool t2 = L2 != nullptr;
+    StepArgs b = a;
+    if (t2) apply_lists(b, L2);
+    a.dir = b.dir = 1;
+    for (int n = n0; n < n1;) {
         if (ckpt && n % K == 0) {
             const int k = n / K;
-            const int64_t cs = (int64_t)nseg * 2 * P->fsize;   // per-shot checkpoint stride
-            ESI_TRY(launch_copy_shots(P, ckpt + (int64_t)k * 2 * P->fsize, cs,
-                                      ring + (int64_t)(n & 1) * P->fsize, RING * P->fsize, P->fsize,
+            const int64_t cstr = (int64_t)nseg * 2 * P->fsize;   // per-shot checkpoint stride
+            ESI_TRY(launch_copy_shots(P, ckpt + (int64_t)k * 2 * P->fsize, cstr,
+                                      ring + (int64_t)(*cs) * P->fsize, RING * P->fsize, P->fsize,
                                       a.nshots));
-            ESI_TRY(launch_copy_shots(P, ckpt + (int64_t)k * 2 * P->fsize + P->fsize, cs,
-                                      ring + 2 * P->fsize, RING * P->fsize, P->fsize, a.nshots));
+            ESI_TRY(launch_copy_shots(P, ckpt + (int64_t)k * 2 * P->fsize + P->fsize, cstr,
+                                      ring + (int64_t)(2 + *cs) * P->fsize, RING * P->fsize,
+                                      P->fsize, a.nshots));
         }
-        a.step = n;
-        a.cur = ring + (int64_t)(n & 1) * P->fsize;
-        a.nxt = ring + (int64_t)((n + 1) & 1) * P->fsize;
-        a.dvel = ring + 2 * P->fsize;
-        if (flags & F_STORE) a.store_slot = K > 0 ? n % K : n;
-        ESI_TRY(launch_step(P, flags, a));
+        const bool two = t2 && n + 1 < n1 && !(ckpt && (n + 1) % K == 0);
+        StepArgs& c = two ? b : a;
+        c.step = n;
+        set_fields(P, c, ring, *cs);
+        if (flags & F_STORE) {
+            c.store_slot = K > 0 ? n % K : n;
+            c.store_slot2 = K > 0 ? (n + 1) % K : n + 1;
+        }
+        ESI_TRY(launch_step(P, flags, c, two));
+        (two ? p2 : p1).launches++;
+        *cs ^= 1;
+        n += two ? 2 : 1;
     }
     return ESI_OK;
 }
 
-// Adjoint time loop over j = j1-1 .. j0 on `ring`; `k` counts steps since the
-// start of the whole backward sweep (slot k&1 holds mu^{j+1}).
-esi_status_t adjoint_loop(Plan* P, StepArgs a, unsigned flags, float* ring, int j0, int j1,
-                          int K = 0) {
-    ProfScope prof(P, flags, j1 - j0, a.nshots);
-    for (int j = j1 - 1; j >= j0; --j) {
-        const int k = P->nt - 1 - j;
-        a.step = j;
-        a.cur = ring + (int64_t)(k & 1) * P->fsize;
-        a.nxt = ring + (int64_t)((k + 1) & 1) * P->fsize;
-        a.dvel = ring + 2 * P->fsize;
-        if (flags & F_CORR) a.store_slot = K > 0 ? j % K : j;
-        ESI_TRY(launch_step(P, flags, a));
+// Adjoint time loop over j = j1-1 .. j0 on `ring` whose state is in slot *cs.
+esi_status_t adjoint_loop(Plan* P, StepArgs a, unsigned flags, float* ring, int* cs, int j0,
+                          int j1, int K = 0) {
+    ProfScope p1(P, flags, a.nshots), p2(P, flags | (1u << 15), a.nshots);
+    TileLists* L2;
+    ESI_TRY(t2_lists(P, &L2));
+    const bool t2 = L2 != nullptr;
+    StepArgs b = a;
+    if (t2) apply_lists(b, L2);
+    a.dir = b.dir = -1;
+    for (int j = j1 - 1; j >= j0;) {
+        const bool two = t2 && j - 1 >= j0;
+        StepArgs& c = two ? b : a;
+        c.step = j;
+        set_fields(P, c, ring, *cs);
+        if (flags & F_CORR) {
+            c.store_slot = K > 0 ? j % K : j;
+            c.store_slot2 = K > 0 ? (j - 1) % K : j - 1;
+        }
+        ESI_TRY(launch_step(P, flags, c, two));
+        (two ? p2 : p1).launches++;
+        *cs ^= 1;
+        j -= two ? 2 : 1;
     }
     return ESI_OK;
 }
@@ -143,41 +198,49 @@ esi_status_t do_forward(Plan* P, int shot0, int ns, int kind, const float* src, 
     if (kind == ESI_SRC_POINT) { fl |= F_SRC_POINT; a.wavelet = src; }
     else { fl |= F_SRC_DENSE; a.dsrc = src; }
     a.gat_data = data;
-    ESI_TRY(forward_loop(P, a, fl, P->ring, 0, P->nt));
-    return launch_final_gather(P, P->ring + (int64_t)(P->nt & 1) * P->fsize, RING * P->fsize, data,
-                               shot0, ns);
+    int cs = 0;
+    ESI_TRY(forward_loop(P, a, fl, P->ring, &cs, 0, P->nt));
+    return launch_final_gather(P, P->ring + (int64_t)cs * P->fsize, RING * P->fsize, data, shot0, ns);
 }
 
 // N p into Ap (+ p.Np partials in P->part [ns][tiles]) for the active shots.
+// With cg_fuse the forward pass first forms p_new = r + beta p (p = p_old is
+// read, p_new written to `pnew`) and x += alpha p_old; N is applied to p_new.
+// Ap may be the p_old buffer (it is dead once the forward pass has run).
 esi_status_t do_normal(Plan* P, int shot0, int ns, const float* p, float* Ap, const TileLists* L,
-                       const int* active, bool cg_fuse, float* r, float* x, double* alpha,
-                       double* beta) {
+                       const int* active, bool cg_fuse, float* pnew, const float* r, float* x,
+                       const double* alpha, const double* beta) {
     const int64_t dl = data_len(P, shot0, ns);
     ESI_TRY(grow_t(&P->dscr, &P->dscr_cap, std::max<int64_t>(dl, 1), P->stream));
     ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
     StepArgs a = base_args(P, L, shot0, ns);
     a.active = active;
     a.gat_data = P->dscr;
+    int cs = 0;
     if (cg_fuse) {
-        a.cg_r = r; a.cg_p = (float*)p; a.cg_x = x; a.cg_alpha = alpha; a.cg_beta = beta;
-        ESI_TRY(forward_loop(P, a, F_CG_FUSE | F_GATHER, P->ring, 0, P->nt));
+        a.cg_r = r; a.cg_p = p; a.cg_pn = pnew; a.cg_x = x; a.cg_alpha = alpha; a.cg_beta = beta;
+        ESI_TRY(forward_loop(P, a, F_CG_FUSE | F_GATHER, P->ring, &cs, 0, P->nt));
     } else {
         a.dsrc = p;
-        ESI_TRY(forward_loop(P, a, F_SRC_DENSE | F_GATHER, P->ring, 0, P->nt));
+        ESI_TRY(forward_loop(P, a, F_SRC_DENSE | F_GATHER, P->ring, &cs, 0, P->nt));
     }
-    ESI_TRY(launch_final_gather(P, P->ring + (int64_t)(P->nt & 1) * P->fsize, RING * P->fsize, P->dscr,
+    ESI_TRY(launch_final_gather(P, P->ring + (int64_t)cs * P->fsize, RING * P->fsize, P->dscr,
                                 shot0, ns));
     ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
-    ESI_TRY(grow_t(&P->part, &P->part_cap, (int64_t)ns * L->tiles, P->stream));
-    hipError_t e = hipMemsetAsync(P->part, 0, (size_t)ns * L->tiles * sizeof(double), P->stream);
-    if (e != hipSuccess) return fail(ESI_ERR_HIP, hipGetErrorString(e));
+    TileLists* L2;
+    ESI_TRY(t2_lists(P, &L2));
+    P->part_stride = std::max(L->tiles, L2 ? L2->tiles : 0);
+    ESI_TRY(grow_t(&P->part, &P->part_cap, (int64_t)ns * P->part_stride, P->stream));
+    ESI_TRY(launch_fill_d(P, P->part, (int64_t)ns * P->part_stride));
     StepArgs b = base_args(P, L, shot0, ns);
     b.active = active;
     b.inj_data = P->dscr;
-    b.dp = p;
+    b.dp = cg_fuse ? pnew : p;
     b.dout = Ap;
     b.part = P->part;
-    return adjoint_loop(P, b, F_INJ | F_NORMAL, P->ring, 0, P->nt);
+    b.part_stride = P->part_stride;
+    cs = 0;
+    return adjoint_loop(P, b, F_INJ | F_NORMAL, P->ring, &cs, 0, P->nt);
 }
 
 }  // namespace
@@ -212,7 +275,8 @@ extern "C" esi_status_t esi_adjoint(esi_plan_t plan, int32_t shot0, int32_t nsho
     StepArgs a = base_args(P, L, shot0, nshots);
     a.inj_data = data;
     a.dout = out;
-    return adjoint_loop(P, a, F_INJ | F_OUT, P->ring, 0, P->nt);
+    int cs = 0;
+    return adjoint_loop(P, a, F_INJ | F_OUT, P->ring, &cs, 0, P->nt);
 }
 
 extern "C" esi_status_t esi_normal_apply(esi_plan_t plan, int32_t shot0, int32_t nshots,
@@ -226,8 +290,9 @@ extern "C" esi_status_t esi_normal_apply(esi_plan_t plan, int32_t shot0, int32_t
     if ((Ap < p + n) && (p < Ap + n)) return fail(ESI_ERR_ARG, "p and Ap overlap");
     TileLists* L;
     ESI_TRY(lists_for(P, &L));
-    ESI_TRY(do_normal(P, shot0, nshots, p, Ap, L, nullptr, false, nullptr, nullptr, nullptr, nullptr));
-    if (pAp) ESI_TRY(launch_reduce_parts(P, P->part, L->tiles, nshots, pAp));
+    ESI_TRY(do_normal(P, shot0, nshots, p, Ap, L, nullptr, false, nullptr, nullptr, nullptr, nullptr,
+                      nullptr));
+    if (pAp) ESI_TRY(launch_reduce_parts(P, P->part, P->part_stride, nshots, pAp));
     return ESI_OK;
 }
 
@@ -244,6 +309,9 @@ extern "C" esi_status_t esi_cg_solve(esi_plan_t plan, int32_t shot0, int32_t ns,
     TileLists* L;
     ESI_TRY(lists_for(P, &L));
     const int64_t len = (int64_t)P->nt * P->nphys;
+    // the direction and N p buffers trade places every iteration: the forward
+    // pass writes p_{k} into the buffer that held N p_{k-1}, and the adjoint
+    // pass writes N p_k over p_{k-1}
     float* r = work;
     float* p = work + (int64_t)ns * len;
     float* Ap = work + 2 * (int64_t)ns * len;
@@ -262,7 +330,8 @@ extern "C" esi_status_t esi_cg_solve(esi_plan_t plan, int32_t shot0, int32_t ns,
         StepArgs a = base_args(P, L, shot0, ns);
         a.inj_data = d_obs;
         a.dout = r;
-        ESI_TRY(adjoint_loop(P, a, F_INJ | F_OUT, P->ring, 0, P->nt));
+        int cs = 0;
+        ESI_TRY(adjoint_loop(P, a, F_INJ | F_OUT, P->ring, &cs, 0, P->nt));
     }
     ESI_TRY(launch_copy(P, p, r, ns * len));
     ESI_TRY(launch_fill(P, x, ns * len, 0.f));
@@ -291,8 +360,13 @@ extern "C" esi_status_t esi_cg_solve(esi_plan_t plan, int32_t shot0, int32_t ns,
     for (int k = 0; k < max_iter && nact > 0; ++k) {
         // N p_k (the first direction is p_0 = r_0; later ones are formed in the
         // forward pass: p_k = r_k + beta p_{k-1}, x_k = x_{k-1} + alpha p_{k-1})
-        ESI_TRY(do_normal(P, shot0, ns, p, Ap, L, active, k > 0, r, x, alpha, beta));
-        ESI_TRY(launch_reduce_parts(P, P->part, L->tiles, ns, pAp));
+        if (k == 0) {
+            ESI_TRY(do_normal(P, shot0, ns, p, Ap, L, active, false, nullptr, r, x, alpha, beta));
+        } else {
+            ESI_TRY(do_normal(P, shot0, ns, p, p, L, active, true, Ap, r, x, alpha, beta));
+            std::swap(p, Ap);
+        }
+        ESI_TRY(launch_reduce_parts(P, P->part, P->part_stride, ns, pAp));
         ESI_TRY(launch_cg_alpha(P, rr, pAp, alpha, ns));
         ESI_TRY(launch_r_update(P, r, Ap, alpha, active, ns, len, rr_new));
         ESI_HIP_TRY(hipMemcpyAsync(h_rr.data(), rr_new, ns * sizeof(double), hipMemcpyDeviceToHost, P->stream));
@@ -367,7 +441,8 @@ extern "C" esi_status_t esi_gradient(esi_plan_t plan, int32_t shot0, int32_t ns,
         StepArgs a = base_args(P, L, shot0, ns);
         a.dsrc = src;
         a.gacc = P->gshot;
-        ESI_TRY(forward_loop(P, a, F_SRC_DENSE | F_PENALTY, P->ring, 0, P->nt));
+        int cs = 0;
+        ESI_TRY(forward_loop(P, a, F_SRC_DENSE | F_PENALTY, P->ring, &cs, 0, P->nt));
         return launch_sum_shots(P, P->gshot, ns, nph, 1.f, grad_m);
     }
 
@@ -388,16 +463,17 @@ extern "C" esi_status_t esi_gradient(esi_plan_t plan, int32_t shot0, int32_t ns,
     a.store = P->store;
     a.store_stride = (int64_t)slots * nph;
     const float* G = data;
+    int fcs = 0;
     if (mode == ESI_GRAD_ADJOINT) {
         a.gat_data = P->dscr;
-        ESI_TRY(forward_loop(P, a, srcfl | F_GATHER | (ckpt ? 0u : F_STORE), P->ring, 0, nt,
+        ESI_TRY(forward_loop(P, a, srcfl | F_GATHER | (ckpt ? 0u : F_STORE), P->ring, &fcs, 0, nt,
                              ckpt ? P->ckpt : nullptr, Kc, nseg));
-        ESI_TRY(launch_final_gather(P, P->ring + (int64_t)(nt & 1) * P->fsize, RING * P->fsize, P->dscr,
+        ESI_TRY(launch_final_gather(P, P->ring + (int64_t)fcs * P->fsize, RING * P->fsize, P->dscr,
                                     shot0, ns));
         ESI_TRY(launch_sub(P, P->dscr, P->dscr, data, dl));   // G = S q - d_obs
         G = P->dscr;
     } else {
-        ESI_TRY(forward_loop(P, a, srcfl | (ckpt ? 0u : F_STORE), P->ring, 0, nt,
+        ESI_TRY(forward_loop(P, a, srcfl | (ckpt ? 0u : F_STORE), P->ring, &fcs, 0, nt,
                              ckpt ? P->ckpt : nullptr, Kc, nseg));
     }
     // backward sweep
@@ -414,19 +490,21 @@ extern "C" esi_status_t esi_gradient(esi_plan_t plan, int32_t shot0, int32_t ns,
         if (src_kind == ESI_SRC_DENSE) { bfl |= F_OUT; b.dout = grad_src; }
         else { bfl |= F_SRC_REC; b.src_rec = grad_src; }
     }
+    int acs = 0;
     if (!ckpt) {
-        ESI_TRY(adjoint_loop(P, b, bfl, adj_ring, 0, nt));
+        ESI_TRY(adjoint_loop(P, b, bfl, adj_ring, &acs, 0, nt));
     } else {
         for (int k = nseg - 1; k >= 0; --k) {
             const int n0 = k * K, n1 = std::min(nt, n0 + K);
-            // restore (u^{n0}, d^{n0}) into the recompute ring: slot n0&1 holds u^{n0}
-            const int64_t cs = (int64_t)nseg * 2 * P->fsize;
-            ESI_TRY(launch_copy_shots(P, P->ring2 + (int64_t)(n0 & 1) * P->fsize, RING * P->fsize,
-                                      P->ckpt + (int64_t)k * 2 * P->fsize, cs, P->fsize, ns));
+            // restore (u^{n0}, d^{n0}) into slot 0 of the recompute ring
+            const int64_t cstr = (int64_t)nseg * 2 * P->fsize;
+            ESI_TRY(launch_copy_shots(P, P->ring2, RING * P->fsize,
+                                      P->ckpt + (int64_t)k * 2 * P->fsize, cstr, P->fsize, ns));
             ESI_TRY(launch_copy_shots(P, P->ring2 + 2 * P->fsize, RING * P->fsize,
-                                      P->ckpt + (int64_t)k * 2 * P->fsize + P->fsize, cs, P->fsize, ns));
-            ESI_TRY(forward_loop(P, a, srcfl | F_STORE, P->ring2, n0, n1, nullptr, K, nseg));
-            ESI_TRY(adjoint_loop(P, b, bfl, adj_ring, n0, n1, K));
+                                      P->ckpt + (int64_t)k * 2 * P->fsize + P->fsize, cstr, P->fsize, ns));
+            int rcs = 0;
+            ESI_TRY(forward_loop(P, a, srcfl | F_STORE, P->ring2, &rcs, n0, n1, nullptr, K, nseg));
+            ESI_TRY(adjoint_loop(P, b, bfl, adj_ring, &acs, n0, n1, K));
         }
     }
     // ADJOINT: lambda = S^T (d_obs - S q) = -S^T G; SEED: grad_m = -sum S^T G (dA/dm) u
@@ -471,5 +549,13 @@ extern "C" esi_status_t esi_plan_profile_read(esi_plan_t plan, int32_t cap, int3
         shot_launches[i] = P->prof_tot[i].shot_launches;
         ms[i] = P->prof_tot[i].ms;
     }
+    return ESI_OK;
+}
+
+extern "C" esi_status_t esi_plan_set_time_block(esi_plan_t plan, int32_t steps) {
+    set_error("");
+    if (!plan) return fail(ESI_ERR_ARG, "null plan");
+    if (steps != 1 && steps != 2) return fail(ESI_ERR_ARG, "time block must be 1 or 2");
+    ((Plan*)plan)->time_block = steps;
     return ESI_OK;
 }

@@ -13,6 +13,8 @@
 namespace esi {
 
 constexpr int HALO = 4;          // 8th-order stencil half width
+constexpr int GH = 8;            // zero ghost cells around the padded grid in storage
+                                 // (two stencil radii: enough for two-step blocking)
 constexpr int XCDS = 8;          // MI355X: 8 accelerator complex dies, 32 CUs each
 
 // Thread-local error text.
@@ -52,6 +54,13 @@ struct TileLists {
     int32_t* gat_rid = nullptr;          // receiver index within its shot
     int32_t* src_tile = nullptr;         // [nshots]
     int32_t* src_cell = nullptr;         // [nshots]
+    // injection cells of the tile grown by one stencil radius (two-step
+    // launches inject on that region in their first step); cells are indexed
+    // on the grown tile, (tz + 8) x (tx + 8) in 2D
+    int32_t* inj2_ptr = nullptr;
+    int32_t* inj2_cell = nullptr;
+    int32_t* inj2_rptr = nullptr;
+    int32_t* inj2_rid = nullptr;
 };
 
 struct Plan {
@@ -84,7 +93,7 @@ struct Plan {
     float lap_w[5] = {0, 0, 0, 0, 0};    // a_0..a_4 rounded once to float32
 
     // scratch, grown on demand
-    float* ring = nullptr;               // [cap][3][fsize]: u slots 0/1, increment d
+    float* ring = nullptr;               // [cap][4][fsize]: u slots 0/1, increment d slots 0/1
     int ring_cap = 0;
     float* ring2 = nullptr;              // second ring (gradient recompute)
     int ring2_cap = 0;
@@ -94,6 +103,7 @@ struct Plan {
     int64_t dscr2_cap = 0;
     double* part = nullptr;              // reduction partials
     int64_t part_cap = 0;
+    int part_stride = 0;                 // partials per shot of the last N p
     double* scal = nullptr;              // CG scalars [8][nshots]
     float* gshot = nullptr;              // per-shot gradient accumulators
     int64_t gshot_cap = 0;
@@ -104,6 +114,7 @@ struct Plan {
     int* flags = nullptr;                // per-shot active flags [nshots]
 
     std::vector<TileLists*> lists;       // one per tile shape used
+    int time_block = 2;                  // steps per launch where allowed (1 or 2)
 
     // profiling: event pairs around time loops, folded into totals on read
     struct ProfRec { unsigned flags; int64_t launches, shot_launches; hipEvent_t e0, e1; };
@@ -131,8 +142,10 @@ esi_status_t get_lists(Plan* P, int tx, int tz, int ty, TileLists** out);
 struct StepArgs {
     // fields
     const float* cur;        // u^n (shot 0); shots are fstride apart
-    float* nxt;              // u^{n+1} out
-    float* dvel;             // d^n = u^n - u^{n-1} in, d^{n+1} out
+    float* nxt;              // u^{n+1} (or u^{n+2} for a two-step launch) out
+    const float* din;        // d^n = u^n - u^{n-1} in
+    float* dnx;              // d^{n+1} (or d^{n+2}) out
+    int dir;                 // +1 forward in time, -1 adjoint (two-step launches)
     int64_t fstride;
     const float* c2;
     const float* kx;
@@ -158,6 +171,7 @@ struct StepArgs {
     const int32_t* inj_ptr; const int32_t* inj_cell; const int32_t* inj_rptr; const int32_t* inj_rid;
     const int32_t* gat_ptr; const int32_t* gat_cell; const int32_t* gat_rid;
     const int32_t* src_tile; const int32_t* src_cell;
+    const int32_t* inj2_ptr; const int32_t* inj2_cell; const int32_t* inj2_rptr; const int32_t* inj2_rid;
     // sparse values
     const float* wavelet;    // point source [nshots][nt]
     const float* inj_data;   // data injected (adjoint), CSR layout
@@ -167,9 +181,11 @@ struct StepArgs {
     float* dout;             // dense output (adjoint mu^j, or N p)
     const float* dp;         // p for N p = mu + beta B^2 p
     double* part;            // per-(shot, tile) float64 partial sums, accumulated
+    int part_stride;         // partials per shot (the largest tile count in use)
     // CG fused direction update (forward): p = r + b p_old; x += a p_old
     const float* cg_r;
-    float* cg_p;
+    const float* cg_p;       // p_old (read)
+    float* cg_pn;            // p_new (written; a different buffer from cg_p)
     float* cg_x;
     const double* cg_alpha;  // [nshots]
     const double* cg_beta;   // [nshots]
@@ -178,6 +194,7 @@ struct StepArgs {
     float* store;            // (dA/dm)u store [nshots][slots][phys]
     int64_t store_stride;    // floats per shot in store
     int store_slot;          // slot of this step
+    int store_slot2;         // slot of the second step of a two-step launch
     float* src_rec;          // [nshots][nt] adjoint field at the source cell
 };
 

@@ -82,7 +82,7 @@ __global__ void k_model_c2(float* __restrict__ c2, const float* __restrict__ vel
         int64_t rest = i / XS;
         int sy = (int)(rest % YS);
         int sz = (int)(rest / YS);
-        int x = sx - HALO, z = sz - HALO, y = ndim == 3 ? sy - HALO : sy;
+        int x = sx - GH, z = sz - GH, y = ndim == 3 ? sy - GH : sy;
         float out = 0.f;
         if (x >= 0 && x < nxp && z >= 0 && z < nzp && y >= 0 && y < nyp) {
             int jx = min(max(x - nb, 0), nx - 1);
@@ -191,6 +191,10 @@ esi_status_t get_lists(Plan* P, int tx, int tz, int ty, TileLists** out) {
     std::vector<int32_t> inj_ptr((size_t)S * (T + 1)), gat_ptr((size_t)S * (T + 1));
     std::vector<int32_t> inj_cell, inj_rptr{0}, inj_rid, gat_cell, gat_rid;
     std::vector<int32_t> src_tile(S), src_cell(S);
+    // grown-tile injection lists (2D): a receiver belongs to every tile whose
+    // region [x0-4, x0+tx+4) x [z0-4, z0+tz+4) holds it
+    std::vector<int32_t> inj2_ptr((size_t)S * (T + 1)), inj2_cell, inj2_rptr{0}, inj2_rid;
+    const int gw = tx + 2 * HALO, gh = tz + 2 * HALO;
     for (int s = 0; s < S; ++s) {
         int64_t r0 = P->h_rec_ptr[s], r1 = P->h_rec_ptr[s + 1];
         // (tile, cell, rid) for every receiver of this shot, sorted
@@ -224,6 +228,36 @@ esi_status_t get_lists(Plan* P, int tx, int tz, int ty, TileLists** out) {
         }
         ip[T] = (int32_t)inj_cell.size();
         gp[T] = (int32_t)gat_cell.size();
+        if (nd == 2) {
+            // (tile, grown cell, rid) for every tile region holding each receiver
+            std::vector<std::array<int32_t, 3>> g2;
+            for (int64_t r = r0; r < r1; ++r) {
+                const int32_t* pr = &P->h_rec[r * nd];
+                const int x = pr[0] + P->nb, z = pr[1] + P->nb;
+                for (int tzi = 0; tzi < L->tiles_z; ++tzi) {
+                    const int gz = z - (tzi * tz - HALO);
+                    if (gz < 0 || gz >= gh) continue;
+                    for (int txi = 0; txi < L->tiles_x; ++txi) {
+                        const int gx = x - (txi * tx - HALO);
+                        if (gx < 0 || gx >= gw) continue;
+                        g2.push_back({tzi * L->tiles_x + txi, gz * gw + gx, (int32_t)(r - r0)});
+                    }
+                }
+            }
+            std::sort(g2.begin(), g2.end());
+            size_t q = 0;
+            int32_t* ip2 = &inj2_ptr[(size_t)s * (T + 1)];
+            for (int t = 0; t < T; ++t) {
+                ip2[t] = (int32_t)inj2_cell.size();
+                while (q < g2.size() && g2[q][0] == t) {
+                    const int32_t cell = g2[q][1];
+                    inj2_cell.push_back(cell);
+                    while (q < g2.size() && g2[q][0] == t && g2[q][1] == cell) inj2_rid.push_back(g2[q++][2]);
+                    inj2_rptr.push_back((int32_t)inj2_rid.size());
+                }
+            }
+            ip2[T] = (int32_t)inj2_cell.size();
+        }
         const int32_t* ps = &P->h_src[(size_t)s * nd];
         locate(ps[0] + P->nb, ps[1] + P->nb, nd == 3 ? ps[2] + P->nb : 0, &src_tile[s], &src_cell[s]);
     }
@@ -243,6 +277,10 @@ esi_status_t get_lists(Plan* P, int tx, int tz, int ty, TileLists** out) {
     ESI_TRY(up(gat_rid, &L->gat_rid));
     ESI_TRY(up(src_tile, &L->src_tile));
     ESI_TRY(up(src_cell, &L->src_cell));
+    ESI_TRY(up(inj2_ptr, &L->inj2_ptr));
+    ESI_TRY(up(inj2_cell, &L->inj2_cell));
+    ESI_TRY(up(inj2_rptr, &L->inj2_rptr));
+    ESI_TRY(up(inj2_rid, &L->inj2_rid));
     P->lists.push_back(L);
     *out = L;
     return ESI_OK;
@@ -252,6 +290,7 @@ static void free_lists(TileLists* L) {
     hipFree(L->inj_ptr); hipFree(L->inj_cell); hipFree(L->inj_rptr); hipFree(L->inj_rid);
     hipFree(L->gat_ptr); hipFree(L->gat_cell); hipFree(L->gat_rid);
     hipFree(L->src_tile); hipFree(L->src_cell);
+    hipFree(L->inj2_ptr); hipFree(L->inj2_cell); hipFree(L->inj2_rptr); hipFree(L->inj2_rid);
     delete L;
 }
 
@@ -311,9 +350,12 @@ extern "C" esi_status_t esi_plan_create(esi_plan_t* plan, const esi_grid_t* g, c
     P->nxp = g->nx + 2 * g->nb;
     P->nyp = nd == 3 ? g->ny + 2 * g->nb : 1;
     // storage: zero ghost halo of HALO cells beyond every tile that may be used
-    P->XS = round_up(round_up(P->nxp, 256) + 2 * HALO, 32);
-    P->ZS = round_up(P->nzp, 64) + 2 * HALO;
-    P->YS = nd == 3 ? round_up(P->nyp, 64) + 2 * HALO : 1;
+    // wide enough for every tile shape used: 64- to 256-wide tiles over
+    // round_up(nxp, 256) plus the ghost frame, and 56-wide two-step tiles whose
+    // staged region reaches 72 columns past the last tile origin
+    P->XS = round_up(std::max(round_up(P->nxp, 256) + 2 * GH, P->nxp + 80), 32);
+    P->ZS = round_up(P->nzp, 64) + 2 * GH;
+    P->YS = nd == 3 ? round_up(P->nyp, 64) + 2 * GH : 1;
     P->fsize = (int64_t)P->ZS * P->YS * P->XS;
     P->nphys = (int64_t)g->nz * g->ny * g->nx;
     double w[5];

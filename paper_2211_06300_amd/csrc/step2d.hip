@@ -1,29 +1,53 @@
-// One time step of the 2D 8th-order acoustic scheme (Sec. 4.1) with the fused
+// Time steps of the 2D 8th-order acoustic scheme (Sec. 4.1) with the fused
 // work of the hot path: point / dense source injection (Sec. 2.1, eq. newq2),
 // receiver recording R and adjoint injection R^T (Sec. 2.1, Sec. 3), the CG
 // direction update (Algorithm 1), the normal-operator output N p = mu + beta
 // B^2 p with its p.Np partials (eq. axb), and the zero-lag correlations of the
 // gradient (eq. gradewi).
 //
-// Layout: each shot's state is u^n, u^{n+1} (two slots used in turn) and the
-// increment d^n = u^n - u^{n-1}, each on a storage grid with a zero ghost halo
-// of 4 cells beyond the padded grid, rows XS floats apart, so stencil loads
-// need no bounds checks.  A 256-thread workgroup owns a 64 x (4*RZ) tile: the tile
-// of u^n plus its halo is staged in LDS with coalesced row loads, each lane
-// owns one column and sweeps RZ rows, z neighbours come from registers, x
-// neighbours from LDS.  Workgroup ids are remapped so that consecutive tiles
-// land on the same XCD (8 XCDs take workgroups round-robin), keeping a
-// tile's halo neighbours in the same L2.
+// State per shot: u (two slots) and the increment d = u^n - u^{n-1} (two
+// slots), each on a storage grid with a zero ghost frame of GH = 8 cells
+// around the padded grid (rows XS floats apart), so stencil loads of a tile
+// grown by two stencil radii never need bounds checks.  A launch reads the
+// current slots and writes the other ones.
+//
+// k_step2d<FL>:    one step; a 256-thread workgroup owns a 64 x 32 tile.  The
+//                  tile of u^n plus a 4-cell halo is staged in LDS, each lane
+//                  owns a column and 8 rows, z neighbours from registers, x
+//                  neighbours from LDS.
+// k_step2d_t2<FL>: two steps per launch (time blocking) on 56 x 32 tiles.
+//                  u^n is staged on the tile grown by 8 cells, the first step
+//                  is computed on the tile grown by 4 cells (64 columns: one
+//                  wave across) into LDS, the second on the tile.  The
+//                  wavefield state crosses HBM once per two steps.
+//
+// Workgroup ids are remapped so that consecutive tiles land on the same XCD
+// (8 XCDs take workgroups round-robin), keeping halo neighbours in one L2.
 #include "esi_internal.h"
 
 namespace esi {
 
 namespace {
 
-constexpr int TX = 64;     // tile width (one wave of lanes)
-constexpr int WZ = 4;      // waves stacked along z
-constexpr int RZ = 8;      // rows per lane
+#ifndef ESI_RZ
+#define ESI_RZ 8
+#endif
+#ifndef ESI_TX
+#define ESI_TX 64
+#endif
+#ifndef ESI_MINW
+#define ESI_MINW 1
+#endif
+#ifndef ESI_MINW2
+#define ESI_MINW2 1
+#endif
+constexpr int TX = ESI_TX;   // tile width: WX waves of 64 lanes side by side
+constexpr int WX = TX / 64;
+constexpr int WZ = 4 / WX;   // waves stacked along z (4 waves per workgroup)
+constexpr int RZ = ESI_RZ;   // rows per lane
+static_assert(TX % 64 == 0 && 4 % WX == 0, "tile width must be 64, 128 or 256");
 constexpr int TZ = WZ * RZ;
+// one-step kernel: tile + one radius
 constexpr int LW = TX + 2 * HALO;
 constexpr int LH = TZ + 2 * HALO;
 
@@ -39,15 +63,96 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Laplacian (times dx^2) at an LDS cell from neighbour differences: the centre
+// weight is -2 sum_k a_k, and for a smooth field each u_{+-k} - u is exact in
+// float32, so the weighted sum carries no cancellation error.  `p` points at
+// the cell, `stride` is the LDS row pitch.
+__device__ __forceinline__ float lap_lds(const StepArgs& a, const float* p, int stride) {
+    const float cv = p[0];
+    float lx = a.w1 * ((p[-1] - cv) + (p[1] - cv));
+    lx = fmaf(a.w2, (p[-2] - cv) + (p[2] - cv), lx);
+    lx = fmaf(a.w3, (p[-3] - cv) + (p[3] - cv), lx);
+    lx = fmaf(a.w4, (p[-4] - cv) + (p[4] - cv), lx);
+    float lz = a.w1 * ((p[-stride] - cv) + (p[stride] - cv));
+    lz = fmaf(a.w2, (p[-2 * stride] - cv) + (p[2 * stride] - cv), lz);
+    lz = fmaf(a.w3, (p[-3 * stride] - cv) + (p[3 * stride] - cv), lz);
+    lz = fmaf(a.w4, (p[-4 * stride] - cv) + (p[4 * stride] - cv), lz);
+    return lx + lz;
+}
+
+// (1+k) u^{n+1} = 2u^n - (1-k) u^{n-1} + c lq advanced through the increment
+// d^n = u^n - u^{n-1}: (1+k) d^{n+1} = (1-k) d^n + c lq, u^{n+1} = u^n + d^{n+1}.
+// Keeping d in its own array stops the rounding of u from leaking into the
+// velocity, where it would persist.
+// The division by 1 + k uses the hardware reciprocal (within 1 ulp): k = 0 on
+// every physical cell, where rcp(1) = 1 exactly and the update is unchanged.
+__device__ __forceinline__ float incr(float c2v, float lq, float dv, float kap) {
+    return fmaf(c2v, lq, (1.f - kap) * dv) * __builtin_amdgcn_rcpf(1.f + kap);
+}
+
+// Element access through a uniform base and a 32-bit byte offset, so that the
+// compiler can use scalar-base + 32-bit-offset addressing (every array a
+// kernel indexes this way is below 4 GiB from its base).
+template <class T>
+__device__ __forceinline__ T& at(T* base, uint32_t i) {
+    return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ const T& at(const T* base, uint32_t i) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (uint32_t)sizeof(T));
+}
+
+// Base pointers of one step's dense streams (uniform: shot and step fixed).
+struct StepPtrs {
+    float* dout;         // adjoint output or N p, this step's slice
+    float* gacc;         // this shot's gradient accumulator
+    float* store;        // this step's (dA/dm)u slot
+    const float* stin;   // stored (dA/dm)u of this step (CORR)
+};
+
+__device__ __forceinline__ StepPtrs step_ptrs(const StepArgs& a, int s, int64_t vbase, int slot) {
+    StepPtrs q;
+    q.dout = a.dout ? a.dout + vbase : nullptr;
+    q.gacc = a.gacc ? a.gacc + (int64_t)s * a.nphys : nullptr;
+    q.store = a.store ? a.store + s * a.store_stride + (int64_t)slot * a.nphys : nullptr;
+    q.stin = q.store;
+    return q;
+}
+
+// Fused per-cell outputs of one step at a physical cell of the tile.
+//  un: new field, q: source term, lq: lap + dx^2 q, c2v: c / dx^2,
+//  pv: p^t (NORMAL), stv: stored (dA/dm)u (CORR).
 template <unsigned FL>
-__global__ __launch_bounds__(256) void k_step2d(const StepArgs a) {
+__device__ __forceinline__ void cell_outputs(const StepArgs& a, const StepPtrs& o, uint32_t pi,
+                                             float un, float q, float lq, float c2v, float pv,
+                                             float stv, float wb, double& acc) {
+    if constexpr ((FL & F_OUT) != 0) at(o.dout, pi) = un;
+    if constexpr ((FL & F_NORMAL) != 0) {
+        const float np = fmaf(wb, pv, un);
+        at(o.dout, pi) = np;
+        acc += (double)pv * (double)np;
+    }
+    if constexpr ((FL & F_PENALTY) != 0) at(o.gacc, pi) = fmaf(wb * q, c2v * a.inv_dt2 * lq, at(o.gacc, pi));
+    if constexpr ((FL & F_STORE) != 0) at(o.store, pi) = c2v * a.inv_dt2 * lq;
+    if constexpr ((FL & F_CORR) != 0) at(o.gacc, pi) = fmaf(un, stv, at(o.gacc, pi));
+}
+
+__device__ __forceinline__ float annih_w(const StepArgs& a, int ix, int iz, float sx, float sz) {
+    const float ddx = (float)ix - sx, ddz = (float)iz - sz;
+    const float bb = sqrtf(ddx * ddx + ddz * ddz) + a.b_eps;
+    return a.beta * (bb * bb);
+}
+
+// ---------------------------------------------------------------------------
+template <unsigned FL>
+__global__ __launch_bounds__(256, ESI_MINW) void k_step2d(const StepArgs a) {
     __shared__ float sh[LH * LW];
     __shared__ float sinj[(FL & F_INJ) ? TZ * TX : 1];
-    __shared__ double sred[WZ];
+    __shared__ double sred[4];
 
     // tile index fastest within a shot: each XCD streams a contiguous stretch
-    // of one shot's fields (tried shot-fastest to share c2 in L2: fewer bytes
-    // fetched but slower, the scattered streams cost more than they save)
+    // of one shot's fields (shot-fastest, to share c2 in L2, fetched fewer
+    // bytes but ran slower: the scattered streams cost more than they save)
     const int L = xcd_remap(blockIdx.x, gridDim.x);
     const int s = L / a.tiles;
     const int t = L - s * a.tiles;
@@ -55,93 +160,100 @@ __global__ __launch_bounds__(256) void k_step2d(const StepArgs a) {
     const int gs = a.shot0 + s;
     const int tzi = t / a.tiles_x, txi = t - tzi * a.tiles_x;
     const int x0 = txi * TX, z0 = tzi * TZ;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index: uniform
     const int XS = a.XS;
     // every storage offset of a shot's field fits in 32 bits
     const float* __restrict__ cur = a.cur + s * a.fstride;
     float* __restrict__ nxt = a.nxt + s * a.fstride;
-    float* __restrict__ dvel = a.dvel + s * a.fstride;
+    const float* __restrict__ din = a.din + s * a.fstride;
+    float* __restrict__ dnx = a.dnx + s * a.fstride;
 
-    // LDS (r, c) <- storage (z0 + r, x0 + c), i.e. padded (z0 + r - 4, x0 + c - 4).
-    // Wave w stages rows w, w + 4, ...: 64 lanes take the row body, 8 the halo
-    // (the other lanes repeat a halo load so every load is unconditional).
-    // All rows are loaded into registers before the first LDS write.
-    constexpr int RPW = LH / WZ;
-    static_assert(LH % WZ == 0, "tile rows must split evenly over the waves");
-    float tb[RPW], th[RPW];
+    // LDS (r, c) <- padded (z0 + r - 4, x0 + c - 4).  Wave w stages rows w,
+    // w + 4, ...: 64 lanes take the row body, 8 the halo (the other lanes
+    // repeat a halo load so every load is unconditional).  All rows are loaded
+    // into registers before the first LDS write.
+    constexpr int RPW = LH / 4;
+    static_assert(LH % 4 == 0, "tile rows must split evenly over the waves");
+    float tb[RPW][WX], th[RPW];
     {
-        const float* src = cur + (z0 + wv) * XS + x0;
+        const float* src = cur + (z0 + GH - HALO + wv) * XS + x0 + GH - HALO;
 #pragma unroll
         for (int k = 0; k < RPW; ++k) {
-            tb[k] = src[k * WZ * XS + lane];
-            th[k] = src[k * WZ * XS + TX + (lane & (2 * HALO - 1))];
+#pragma unroll
+            for (int j = 0; j < WX; ++j) tb[k][j] = at(src, (uint32_t)(k * 4 * XS + 64 * j) + (uint32_t)lane);
+            th[k] = at(src, (uint32_t)(k * 4 * XS + TX) + (uint32_t)(lane & (2 * HALO - 1)));
         }
     }
+    const int wx = wv % WX, wz = wv / WX;
 
-    // Per-lane column and rows of this lane: issue every global load first.
-    const int x = x0 + lane;
-    const bool xin = x < a.nxp;
-    const float kxv = a.kx[min(x, a.nxp - 1)];
+    // this lane's column and rows: issue every global load first
+    const int xl = wx * 64 + lane;                       // tile-local column
+    const int x = x0 + xl;
+    const float kxv = at(a.kx, (uint32_t)min(x, a.nxp - 1));
     const int ix = x - a.nb;
     const bool xphys = ix >= 0 && ix < a.nx;
-    const int zb = z0 + wv * RZ;                         // first row of this lane
-    const int so0 = (zb + HALO) * XS + x + HALO;         // storage offset of that row
+    const int zb = z0 + wz * RZ;
+    const uint32_t so0 = (uint32_t)((zb + GH) * XS + x + GH);
     const int64_t vbase = ((int64_t)s * a.nt + a.step) * a.nphys;
+    const StepPtrs o1 = step_ptrs(a, s, vbase, a.store_slot);
     float c2v[RZ], dv[RZ], kzv[RZ], qv[RZ];
-    int pi[RZ];
+    uint32_t pi[RZ];
     bool ph[RZ];
 #pragma unroll
     for (int i = 0; i < RZ; ++i) {
         const int z = zb + i;
-        c2v[i] = a.c2[so0 + i * XS];
-        dv[i] = dvel[so0 + i * XS];
-        kzv[i] = a.kz[min(z, a.nzp - 1)];
+        c2v[i] = at(a.c2, so0 + (uint32_t)(i * XS));
+        dv[i] = at(din, so0 + (uint32_t)(i * XS));
+        kzv[i] = at(a.kz, (uint32_t)min(z, a.nzp - 1));
         const int iz = z - a.nb;
         ph[i] = xphys && iz >= 0 && iz < a.nz;
-        pi[i] = ph[i] ? iz * a.nx + ix : 0;             // clamped: loads stay unconditional
+        pi[i] = ph[i] ? (uint32_t)(iz * a.nx + ix) : 0u;   // clamped: loads stay unconditional
         qv[i] = 0.f;
     }
-    float po[RZ], pn[RZ], pv[RZ];
     if constexpr ((FL & F_SRC_DENSE) != 0) {
         const float* __restrict__ q = a.dsrc + vbase;
 #pragma unroll
-        for (int i = 0; i < RZ; ++i) qv[i] = ph[i] ? q[pi[i]] : 0.f;
+        for (int i = 0; i < RZ; ++i) qv[i] = ph[i] ? at(q, pi[i]) : 0.f;
     }
     if constexpr ((FL & F_CG_FUSE) != 0) {
         const float alp = (float)a.cg_alpha[s];
         const float bet = (float)a.cg_beta[s];
-        float* __restrict__ p = a.cg_p + vbase;
+        const float* __restrict__ p = a.cg_p + vbase;
+        float* __restrict__ pnew = a.cg_pn + vbase;
         const float* __restrict__ r = a.cg_r + vbase;
         float* __restrict__ xv = a.cg_x + vbase;
-        float rv[RZ], xo[RZ];
+        float po[RZ], rv[RZ], xo[RZ];
 #pragma unroll
-        for (int i = 0; i < RZ; ++i) { po[i] = p[pi[i]]; rv[i] = r[pi[i]]; xo[i] = xv[pi[i]]; }
+        for (int i = 0; i < RZ; ++i) { po[i] = at(p, pi[i]); rv[i] = at(r, pi[i]); xo[i] = at(xv, pi[i]); }
 #pragma unroll
         for (int i = 0; i < RZ; ++i) {
-            pn[i] = fmaf(bet, po[i], rv[i]);
+            const float pn = fmaf(bet, po[i], rv[i]);
             if (ph[i]) {
-                p[pi[i]] = pn[i];
-                if (alp != 0.f) xv[pi[i]] = fmaf(alp, po[i], xo[i]);
+                at(pnew, pi[i]) = pn;
+                if (alp != 0.f) at(xv, pi[i]) = fmaf(alp, po[i], xo[i]);
             }
-            qv[i] = ph[i] ? pn[i] : 0.f;
+            qv[i] = ph[i] ? pn : 0.f;
         }
     }
+    float pv[RZ], stv[RZ];
+#pragma unroll
+    for (int i = 0; i < RZ; ++i) { pv[i] = 0.f; stv[i] = 0.f; }
     if constexpr ((FL & F_NORMAL) != 0) {
         const float* __restrict__ p = a.dp + vbase;
 #pragma unroll
-        for (int i = 0; i < RZ; ++i) pv[i] = p[pi[i]];
+        for (int i = 0; i < RZ; ++i) pv[i] = at(p, pi[i]);
     }
-    float stv[RZ];
     if constexpr ((FL & F_CORR) != 0) {
-        const float* __restrict__ st = a.store + s * a.store_stride + (int64_t)a.store_slot * a.nphys;
 #pragma unroll
-        for (int i = 0; i < RZ; ++i) stv[i] = st[pi[i]];
+        for (int i = 0; i < RZ; ++i) stv[i] = at(o1.stin, pi[i]);
     }
 
 #pragma unroll
     for (int k = 0; k < RPW; ++k) {
-        const int r = wv + k * WZ;
-        sh[r * LW + lane] = tb[k];
+        const int r = wv + k * 4;
+#pragma unroll
+        for (int j = 0; j < WX; ++j) sh[r * LW + 64 * j + lane] = tb[k][j];
         if (lane < 2 * HALO) sh[r * LW + TX + lane] = th[k];
     }
 
@@ -191,75 +303,35 @@ __global__ __launch_bounds__(256) void k_step2d(const StepArgs a) {
         sz = (float)a.src_pos[gs * 3 + 1];
     }
 
-    float col[RZ + 2 * HALO];
-#pragma unroll
-    for (int k = 0; k < RZ + 2 * HALO; ++k) col[k] = sh[(wv * RZ + k) * LW + lane + HALO];
-
     double acc = 0.0;
 #pragma unroll
     for (int i = 0; i < RZ; ++i) {
-        const int zl = wv * RZ + i;
+        const int zl = wz * RZ + i;
         const int z = z0 + zl;
-        const bool valid = xin && z < a.nzp;
-        const float* row = sh + (zl + HALO) * LW + lane + HALO;
-        const float cv = col[i + HALO];
-        // Laplacian from neighbour differences: the centre weight is -2 sum_k a_k,
-        // and for a smooth field each u_{+-k} - u is exact in float32, so the
-        // weighted sum carries no cancellation error.
-        float lx = a.w1 * ((row[-1] - cv) + (row[1] - cv));
-        lx = fmaf(a.w2, (row[-2] - cv) + (row[2] - cv), lx);
-        lx = fmaf(a.w3, (row[-3] - cv) + (row[3] - cv), lx);
-        lx = fmaf(a.w4, (row[-4] - cv) + (row[4] - cv), lx);
-        float lz = a.w1 * ((col[i + 3] - cv) + (col[i + 5] - cv));
-        lz = fmaf(a.w2, (col[i + 2] - cv) + (col[i + 6] - cv), lz);
-        lz = fmaf(a.w3, (col[i + 1] - cv) + (col[i + 7] - cv), lz);
-        lz = fmaf(a.w4, (col[i + 0] - cv) + (col[i + 8] - cv), lz);
-        const float lap = lx + lz;
-
+        const float* cp = sh + (zl + HALO) * LW + xl + HALO;
+        const float lap = lap_lds(a, cp, LW);
         float q = qv[i];
         if constexpr ((FL & F_SRC_POINT) != 0) {
-            if (zl * TX + lane == src_cell) q += src_val;
+            if (zl * TX + xl == src_cell) q += src_val;
         }
         if constexpr ((FL & F_INJ) != 0) {
-            if (has_inj) q += sinj[zl * TX + lane];
+            if (has_inj) q += sinj[zl * TX + xl];
         }
         const float kap = kxv + kzv[i];
         const float lq = fmaf(a.dx2, q, lap);
-        // (1+k) u^{n+1} = 2u^n - (1-k) u^{n-1} + c lq advanced through the
-        // increment d^n = u^n - u^{n-1}: (1+k) d^{n+1} = (1-k) d^n + c lq and
-        // u^{n+1} = u^n + d^{n+1}.  Keeping d in its own array stops the rounding
-        // of u from leaking into the velocity, where it would persist.
-        const float dn = fmaf(c2v[i], lq, (1.f - kap) * dv[i]) / (1.f + kap);
-        const float un = cv + dn;
-        if (valid) {
-            dvel[so0 + i * XS] = dn;
-            nxt[so0 + i * XS] = un;
-        }
+        const float dn = incr(c2v[i], lq, dv[i], kap);
+        const float un = cp[0] + dn;
+        // cells past the padded grid sit in the zero ghost frame (c2 = u = d = 0)
+        // and compute exactly 0, so the stores need no mask
+        at(dnx, so0 + (uint32_t)(i * XS)) = dn;
+        at(nxt, so0 + (uint32_t)(i * XS)) = un;
         if (!ph[i]) continue;
-        if constexpr ((FL & F_OUT) != 0) a.dout[vbase + pi[i]] = un;
         if constexpr ((FL & F_SRC_REC) != 0) {
-            if (zl * TX + lane == src_cell) a.src_rec[(int64_t)s * a.nt + a.step] = un;
+            if (zl * TX + xl == src_cell) a.src_rec[(int64_t)s * a.nt + a.step] = un;
         }
-        if constexpr ((FL & (F_NORMAL | F_PENALTY)) != 0) {
-            const float ddx = (float)ix - sx, ddz = (float)(z - a.nb) - sz;
-            const float bb = sqrtf(ddx * ddx + ddz * ddz) + a.b_eps;
-            const float wb = a.beta * (bb * bb);
-            if constexpr ((FL & F_NORMAL) != 0) {
-                const float np = fmaf(wb, pv[i], un);
-                a.dout[vbase + pi[i]] = np;
-                acc += (double)pv[i] * (double)np;
-            }
-            if constexpr ((FL & F_PENALTY) != 0) {
-                float* g = a.gacc + (int64_t)s * a.nphys + pi[i];
-                *g = fmaf(wb * q, c2v[i] * a.inv_dt2 * lq, *g);
-            }
-        }
-        if constexpr ((FL & F_STORE) != 0)
-            a.store[s * a.store_stride + (int64_t)a.store_slot * a.nphys + pi[i]] = c2v[i] * a.inv_dt2 * lq;
-        if constexpr ((FL & F_CORR) != 0) {
-            float* g = a.gacc + (int64_t)s * a.nphys + pi[i];
-            *g = fmaf(un, stv[i], *g);
-        }
+        float wb = 0.f;
+        if constexpr ((FL & (F_NORMAL | F_PENALTY)) != 0) wb = annih_w(a, ix, z - a.nb, sx, sz);
+        cell_outputs<FL>(a, o1, pi[i], un, q, lq, c2v[i], pv[i], stv[i], wb, acc);
     }
 
     if constexpr ((FL & F_NORMAL) != 0) {
@@ -268,8 +340,324 @@ __global__ __launch_bounds__(256) void k_step2d(const StepArgs a) {
         __syncthreads();
         if (tid == 0) {
             double sum = 0.0;
-            for (int w = 0; w < WZ; ++w) sum += sred[w];
-            a.part[(int64_t)s * a.tiles + t] += sum;
+            for (int w = 0; w < 4; ++w) sum += sred[w];
+            a.part[(int64_t)s * a.part_stride + t] += sum;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Two steps, tA = a.step and tB = a.step + a.dir, in one launch, on 56 x 32
+// output tiles.  The first step runs on the tile grown by 4 cells, 64 x 40:
+// one lane per column (a wave spans it exactly), 10 rows per wave, z
+// neighbours from a register window.  The second step runs on the tile, one
+// lane per column (lanes 56..63 idle), 8 rows per wave.
+constexpr int T2W = 56, T2Z = 32;                 // output tile
+constexpr int A_W = T2W + 2 * HALO;               // 64: first-step region width
+constexpr int A_H = T2Z + 2 * HALO;               // 40
+constexpr int A_RZ = A_H / 4;                     // first-step rows per wave
+constexpr int B_RZ = T2Z / 4;                     // second-step rows per wave
+constexpr int U0W = T2W + 4 * HALO, U0H = T2Z + 4 * HALO;   // 72 x 48
+static_assert(A_W == 64 && A_H % 4 == 0 && U0H % 4 == 0, "two-step tile geometry");
+
+template <unsigned FL>
+__global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) {
+    __shared__ float U0[U0H * U0W];                     // u^{tA}: tile + 8
+    __shared__ float U1[A_H * A_W];                     // u after the first step: tile + 4
+    __shared__ float D1[T2Z * T2W];                     // d after the first step: tile
+    __shared__ float sinj[(FL & F_INJ) ? A_H * A_W : 1];
+    __shared__ double sred[4];
+
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    const int s = L / a.tiles;
+    const int t = L - s * a.tiles;
+    if (a.active && !a.active[s]) return;   // uniform over the workgroup
+    const int gs = a.shot0 + s;
+    const int tzi = t / a.tiles_x, txi = t - tzi * a.tiles_x;
+    const int x0 = txi * T2W, z0 = tzi * T2Z;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index: uniform
+    const int XS = a.XS;
+    const int tA = a.step, tB = a.step + a.dir;
+    const float* __restrict__ cur = a.cur + s * a.fstride;
+    float* __restrict__ nxt = a.nxt + s * a.fstride;
+    const float* __restrict__ din = a.din + s * a.fstride;
+    float* __restrict__ dnx = a.dnx + s * a.fstride;
+    const int64_t vA = ((int64_t)s * a.nt + tA) * a.nphys;
+    const int64_t vB = ((int64_t)s * a.nt + tB) * a.nphys;
+    const StepPtrs oA = step_ptrs(a, s, vA, a.store_slot);
+    const StepPtrs oB = step_ptrs(a, s, vB, a.store_slot2);
+
+    // U0 (r, c) <- padded (z0 - 8 + r, x0 - 8 + c) = storage (z0 + r, x0 + c)
+    constexpr int RPW0 = U0H / 4;
+    float tb[RPW0], th[RPW0];
+    {
+        const float* src = cur + (z0 + GH - 2 * HALO + wv) * XS + x0 + GH - 2 * HALO;
+#pragma unroll
+        for (int k = 0; k < RPW0; ++k) {
+            tb[k] = at(src, (uint32_t)(k * 4 * XS) + (uint32_t)lane);
+            th[k] = at(src, (uint32_t)(k * 4 * XS + 64) + (uint32_t)(lane & 7));
+        }
+    }
+
+    // ---- first-step loads: lane = region column, rows wv*A_RZ + i of the region
+    const int xa = x0 - HALO + lane;                      // padded column
+    const bool xa_in = xa >= 0 && xa < a.nxp;
+    const float kxa = at(a.kx, (uint32_t)min(max(xa, 0), a.nxp - 1));
+    const int ixa = xa - a.nb;
+    const bool xa_phys = ixa >= 0 && ixa < a.nx;
+    const bool xa_tile = lane >= HALO && lane < HALO + T2W;
+    const int zra = wv * A_RZ;                            // first region row of this wave
+    const uint32_t soA = (uint32_t)((z0 - HALO + zra + GH) * XS + xa + GH);
+    float cA[A_RZ], dA[A_RZ], kA[A_RZ], qA[A_RZ], pvA[A_RZ], stA[A_RZ], poA[A_RZ], xoA[A_RZ];
+    uint32_t piA[A_RZ];
+    bool inA[A_RZ], phA[A_RZ];
+#pragma unroll
+    for (int i = 0; i < A_RZ; ++i) {
+        const int z = z0 - HALO + zra + i;
+        cA[i] = at(a.c2, soA + (uint32_t)(i * XS));
+        dA[i] = at(din, soA + (uint32_t)(i * XS));
+        kA[i] = kxa + at(a.kz, (uint32_t)min(max(z, 0), a.nzp - 1));
+        inA[i] = xa_in && z >= 0 && z < a.nzp;
+        const int iz = z - a.nb;
+        phA[i] = xa_phys && iz >= 0 && iz < a.nz;
+        piA[i] = phA[i] ? (uint32_t)(iz * a.nx + ixa) : 0u;
+        qA[i] = 0.f; pvA[i] = 0.f; stA[i] = 0.f; poA[i] = 0.f; xoA[i] = 0.f;
+    }
+    if constexpr ((FL & F_SRC_DENSE) != 0) {
+        const float* __restrict__ q = a.dsrc + vA;
+#pragma unroll
+        for (int i = 0; i < A_RZ; ++i) qA[i] = phA[i] ? at(q, piA[i]) : 0.f;
+    }
+    float alp = 0.f, bet = 0.f;
+    if constexpr ((FL & F_CG_FUSE) != 0) {
+        alp = (float)a.cg_alpha[s];
+        bet = (float)a.cg_beta[s];
+        const float* __restrict__ p = a.cg_p + vA;
+        const float* __restrict__ r = a.cg_r + vA;
+        const float* __restrict__ xv = a.cg_x + vA;
+#pragma unroll
+        for (int i = 0; i < A_RZ; ++i) { poA[i] = at(p, piA[i]); qA[i] = at(r, piA[i]); xoA[i] = at(xv, piA[i]); }
+    }
+    if constexpr ((FL & F_NORMAL) != 0) {
+        const float* __restrict__ p = a.dp + vA;
+#pragma unroll
+        for (int i = 0; i < A_RZ; ++i) pvA[i] = at(p, piA[i]);
+    }
+    if constexpr ((FL & F_CORR) != 0) {
+#pragma unroll
+        for (int i = 0; i < A_RZ; ++i) stA[i] = at(oA.stin, piA[i]);
+    }
+
+#pragma unroll
+    for (int k = 0; k < RPW0; ++k) {
+        const int r = wv + k * 4;
+        U0[r * U0W + lane] = tb[k];
+        if (lane < 2 * HALO) U0[r * U0W + 64 + lane] = th[k];
+    }
+
+    const int64_t nrec_s = (FL & (F_INJ | F_GATHER)) ? a.rec_ptr[gs + 1] - a.rec_ptr[gs] : 0;
+    const int64_t doff = (FL & (F_INJ | F_GATHER)) ? (int64_t)a.nt * (a.rec_ptr[gs] - a.rec_ptr[a.shot0]) : 0;
+    int ibeg = 0, iend = 0;
+    if constexpr ((FL & F_INJ) != 0) {
+        const int32_t* ip = a.inj2_ptr + (int64_t)gs * (a.tiles + 1);
+        ibeg = ip[t];
+        iend = ip[t + 1];
+        if (iend > ibeg) {
+            for (int i = tid; i < A_H * A_W; i += 256) sinj[i] = 0.f;
+            __syncthreads();
+            const float* dj = a.inj_data + doff + (int64_t)tA * nrec_s;
+            for (int e = ibeg + tid; e < iend; e += 256) {
+                float v = 0.f;
+                for (int k = a.inj2_rptr[e]; k < a.inj2_rptr[e + 1]; ++k) v += dj[a.inj2_rid[k]];
+                sinj[a.inj2_cell[e]] = v;
+            }
+        }
+    }
+    __syncthreads();
+
+    const int32_t* gp = (FL & F_GATHER) ? a.gat_ptr + (int64_t)gs * (a.tiles + 1) : nullptr;
+    if constexpr ((FL & F_GATHER) != 0) {
+        // d^{tA-1} = R u^{tA} (forward only)
+        if (tA > 0) {
+            float* dn = a.gat_data + doff + (int64_t)(tA - 1) * nrec_s;
+            for (int e = gp[t] + tid; e < gp[t + 1]; e += 256) {
+                const int cell = a.gat_cell[e];
+                const int r = cell / T2W, c = cell - r * T2W;
+                dn[a.gat_rid[e]] = U0[(r + 2 * HALO) * U0W + c + 2 * HALO];
+            }
+        }
+    }
+
+    // the point source and the source-cell record
+    int srcA = -1, srcB = -1;
+    float sx = 0.f, sz = 0.f;
+    if constexpr ((FL & (F_SRC_POINT | F_SRC_REC | F_NORMAL | F_PENALTY)) != 0) {
+        sx = (float)a.src_pos[gs * 3 + 0];
+        sz = (float)a.src_pos[gs * 3 + 1];
+        const int gz = a.src_pos[gs * 3 + 1] + a.nb - (z0 - HALO);
+        const int gx = a.src_pos[gs * 3 + 0] + a.nb - (x0 - HALO);
+        if (gz >= 0 && gz < A_H && gx >= 0 && gx < A_W) srcA = gz * A_W + gx;
+        const int lz = gz - HALO, lx = gx - HALO;
+        if (lz >= 0 && lz < T2Z && lx >= 0 && lx < T2W) srcB = lz * T2W + lx;
+    }
+
+    // ---- first step
+    float colA[A_RZ + 2 * HALO];
+#pragma unroll
+    for (int k = 0; k < A_RZ + 2 * HALO; ++k) colA[k] = U0[(zra + k) * U0W + lane + HALO];
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < A_RZ; ++i) {
+        const int zr = zra + i;
+        const float* cp = U0 + (zr + HALO) * U0W + lane + HALO;
+        const float lap = lap_lds(a, cp, U0W);
+        float q = qA[i];
+        if constexpr ((FL & F_CG_FUSE) != 0) q = phA[i] ? fmaf(bet, poA[i], qA[i]) : 0.f;
+        if constexpr ((FL & F_SRC_POINT) != 0) {
+            if (zr * A_W + lane == srcA) q += a.wavelet[(int64_t)s * a.nt + tA];
+        }
+        if constexpr ((FL & F_INJ) != 0) {
+            if (iend > ibeg) q += sinj[zr * A_W + lane];
+        }
+        const float lq = fmaf(a.dx2, q, lap);
+        const float dn = incr(cA[i], lq, dA[i], kA[i]);
+        const float un = colA[i + HALO] + dn;
+        U1[zr * A_W + lane] = inA[i] ? un : 0.f;
+        const bool tile = xa_tile && zr >= HALO && zr < HALO + T2Z;
+        if (tile) {
+            D1[(zr - HALO) * T2W + lane - HALO] = dn;
+            if (phA[i]) {
+                if constexpr ((FL & F_CG_FUSE) != 0) {
+                    at(a.cg_pn + vA, piA[i]) = q;
+                    if (alp != 0.f) at(a.cg_x + vA, piA[i]) = fmaf(alp, poA[i], xoA[i]);
+                }
+                if constexpr ((FL & F_SRC_REC) != 0) {
+                    if (zr * A_W + lane == srcA) a.src_rec[(int64_t)s * a.nt + tA] = un;
+                }
+                float wb = 0.f;
+                if constexpr ((FL & (F_NORMAL | F_PENALTY)) != 0)
+                    wb = annih_w(a, ixa, z0 - HALO + zr - a.nb, sx, sz);
+                cell_outputs<FL>(a, oA, piA[i], un, q, lq, cA[i], pvA[i], stA[i], wb, acc);
+            }
+        }
+    }
+    __syncthreads();
+
+    if constexpr ((FL & F_GATHER) != 0) {
+        // d^{tA} = R u^{tA+1}
+        float* dn = a.gat_data + doff + (int64_t)tA * nrec_s;
+        for (int e = gp[t] + tid; e < gp[t + 1]; e += 256) {
+            const int cell = a.gat_cell[e];
+            const int r = cell / T2W, c = cell - r * T2W;
+            dn[a.gat_rid[e]] = U1[(r + HALO) * A_W + c + HALO];
+        }
+    }
+    if constexpr ((FL & F_INJ) != 0) {
+        if (iend > ibeg) {
+            for (int i = tid; i < A_H * A_W; i += 256) sinj[i] = 0.f;
+            __syncthreads();
+            const float* dj = a.inj_data + doff + (int64_t)tB * nrec_s;
+            for (int e = ibeg + tid; e < iend; e += 256) {
+                float v = 0.f;
+                for (int k = a.inj2_rptr[e]; k < a.inj2_rptr[e + 1]; ++k) v += dj[a.inj2_rid[k]];
+                sinj[a.inj2_cell[e]] = v;
+            }
+            __syncthreads();
+        }
+    }
+
+    // ---- second step on the tile: lane = column (lanes >= 56 idle), 8 rows per wave
+    const int lc = min(lane, T2W - 1);
+    const bool lane_on = lane < T2W;
+    const int x = x0 + lc;
+    const float kxv = at(a.kx, (uint32_t)min(x, a.nxp - 1));
+    const int ix = x - a.nb;
+    const bool xphys = lane_on && ix >= 0 && ix < a.nx;
+    const int zb = z0 + wv * B_RZ;
+    const uint32_t so0 = (uint32_t)((zb + GH) * XS + x + GH);
+    float c2v[B_RZ], kzv[B_RZ], qv[B_RZ], pvB[B_RZ], stB[B_RZ], poB[B_RZ], xoB[B_RZ];
+    uint32_t pi[B_RZ];
+    bool ph[B_RZ];
+#pragma unroll
+    for (int i = 0; i < B_RZ; ++i) {
+        const int z = zb + i;
+        c2v[i] = at(a.c2, so0 + (uint32_t)(i * XS));
+        kzv[i] = at(a.kz, (uint32_t)min(z, a.nzp - 1));
+        const int iz = z - a.nb;
+        ph[i] = xphys && iz >= 0 && iz < a.nz;
+        pi[i] = ph[i] ? (uint32_t)(iz * a.nx + ix) : 0u;
+        qv[i] = 0.f; pvB[i] = 0.f; stB[i] = 0.f; poB[i] = 0.f; xoB[i] = 0.f;
+    }
+    if constexpr ((FL & F_SRC_DENSE) != 0) {
+        const float* __restrict__ q = a.dsrc + vB;
+#pragma unroll
+        for (int i = 0; i < B_RZ; ++i) qv[i] = ph[i] ? at(q, pi[i]) : 0.f;
+    }
+    if constexpr ((FL & F_CG_FUSE) != 0) {
+        const float* __restrict__ p = a.cg_p + vB;
+        const float* __restrict__ r = a.cg_r + vB;
+        const float* __restrict__ xv = a.cg_x + vB;
+#pragma unroll
+        for (int i = 0; i < B_RZ; ++i) { poB[i] = at(p, pi[i]); qv[i] = at(r, pi[i]); xoB[i] = at(xv, pi[i]); }
+    }
+    if constexpr ((FL & F_NORMAL) != 0) {
+        const float* __restrict__ p = a.dp + vB;
+#pragma unroll
+        for (int i = 0; i < B_RZ; ++i) pvB[i] = at(p, pi[i]);
+    }
+    if constexpr ((FL & F_CORR) != 0) {
+#pragma unroll
+        for (int i = 0; i < B_RZ; ++i) stB[i] = at(oB.stin, pi[i]);
+    }
+
+    float colB[B_RZ + 2 * HALO];
+#pragma unroll
+    for (int k = 0; k < B_RZ + 2 * HALO; ++k) colB[k] = U1[(wv * B_RZ + k) * A_W + lc + HALO];
+#pragma unroll
+    for (int i = 0; i < B_RZ; ++i) {
+        const int zl = wv * B_RZ + i;
+        const int z = z0 + zl;
+        const float* cp = U1 + (zl + HALO) * A_W + lc + HALO;
+        const float lap = lap_lds(a, cp, A_W);
+        float q = qv[i];
+        if constexpr ((FL & F_CG_FUSE) != 0) q = ph[i] ? fmaf(bet, poB[i], qv[i]) : 0.f;
+        if constexpr ((FL & F_SRC_POINT) != 0) {
+            if (lane_on && zl * T2W + lc == srcB) q += a.wavelet[(int64_t)s * a.nt + tB];
+        }
+        if constexpr ((FL & F_INJ) != 0) {
+            if (iend > ibeg) q += sinj[(zl + HALO) * A_W + lc + HALO];
+        }
+        const float kap = kxv + kzv[i];
+        const float lq = fmaf(a.dx2, q, lap);
+        const float dn = incr(c2v[i], lq, D1[zl * T2W + lc], kap);
+        const float un = colB[i + HALO] + dn;
+        // cells past the padded grid sit in the zero ghost frame and compute 0
+        if (lane_on) {
+            at(dnx, so0 + (uint32_t)(i * XS)) = dn;
+            at(nxt, so0 + (uint32_t)(i * XS)) = un;
+        }
+        if (!ph[i]) continue;
+        if constexpr ((FL & F_CG_FUSE) != 0) {
+            at(a.cg_pn + vB, pi[i]) = q;
+            if (alp != 0.f) at(a.cg_x + vB, pi[i]) = fmaf(alp, poB[i], xoB[i]);
+        }
+        if constexpr ((FL & F_SRC_REC) != 0) {
+            if (zl * T2W + lc == srcB) a.src_rec[(int64_t)s * a.nt + tB] = un;
+        }
+        float wb = 0.f;
+        if constexpr ((FL & (F_NORMAL | F_PENALTY)) != 0) wb = annih_w(a, ix, z - a.nb, sx, sz);
+        cell_outputs<FL>(a, oB, pi[i], un, q, lq, c2v[i], pvB[i], stB[i], wb, acc);
+    }
+
+    if constexpr ((FL & F_NORMAL) != 0) {
+        acc = wave_sum(acc);
+        if (lane == 0) sred[wv] = acc;
+        __syncthreads();
+        if (tid == 0) {
+            double sum = 0.0;
+            for (int w = 0; w < 4; ++w) sum += sred[w];
+            a.part[(int64_t)s * a.part_stride + t] += sum;
         }
     }
 }
@@ -288,44 +676,56 @@ __global__ void k_final_gather(const float* __restrict__ field, int64_t fstride,
         while (rec_ptr[shot0 + s + 1] <= r) ++s;   // shots per call are few
         const int64_t nrec_s = rec_ptr[shot0 + s + 1] - rec_ptr[shot0 + s];
         const int64_t rid = r - rec_ptr[shot0 + s];
-        const int x = rec[r * 3 + 0] + nb + HALO, z = rec[r * 3 + 1] + nb + HALO;
-        const int y = ndim == 3 ? rec[r * 3 + 2] + nb + HALO : 0;
+        const int x = rec[r * 3 + 0] + nb + GH, z = rec[r * 3 + 1] + nb + GH;
+        const int y = ndim == 3 ? rec[r * 3 + 2] + nb + GH : 0;
         const float v = field[s * fstride + ((int64_t)z * YS + y) * XS + x];
         data[(int64_t)nt * (rec_ptr[shot0 + s] - base) + (int64_t)(nt - 1) * nrec_s + rid] = v;
     }
 }
 
-template <unsigned FL>
+template <unsigned FL, bool T2>
 esi_status_t launch2d(Plan* P, const StepArgs& a) {
     const int blocks = a.tiles * a.nshots;
-    hipLaunchKernelGGL(k_step2d<FL>, dim3(blocks), dim3(256), 0, P->stream, a);
+    if constexpr (T2)
+        hipLaunchKernelGGL(k_step2d_t2<FL>, dim3(blocks), dim3(256), 0, P->stream, a);
+    else
+        hipLaunchKernelGGL(k_step2d<FL>, dim3(blocks), dim3(256), 0, P->stream, a);
     ESI_HIP_TRY(hipGetLastError());
     return ESI_OK;
 }
 
-}  // namespace
-
-esi_status_t launch_step2d(Plan* P, unsigned flags, const StepArgs& a) {
+template <bool T2>
+esi_status_t dispatch2d(Plan* P, unsigned flags, const StepArgs& a) {
     switch (flags) {
-        case F_SRC_POINT | F_GATHER: return launch2d<F_SRC_POINT | F_GATHER>(P, a);
-        case F_SRC_POINT | F_GATHER | F_STORE: return launch2d<F_SRC_POINT | F_GATHER | F_STORE>(P, a);
-        case F_SRC_POINT | F_STORE: return launch2d<F_SRC_POINT | F_STORE>(P, a);
-        case F_SRC_POINT: return launch2d<F_SRC_POINT>(P, a);
-        case F_SRC_DENSE | F_GATHER: return launch2d<F_SRC_DENSE | F_GATHER>(P, a);
-        case F_SRC_DENSE | F_GATHER | F_STORE: return launch2d<F_SRC_DENSE | F_GATHER | F_STORE>(P, a);
-        case F_SRC_DENSE | F_STORE: return launch2d<F_SRC_DENSE | F_STORE>(P, a);
-        case F_SRC_DENSE | F_PENALTY: return launch2d<F_SRC_DENSE | F_PENALTY>(P, a);
-        case F_CG_FUSE | F_GATHER: return launch2d<F_CG_FUSE | F_GATHER>(P, a);
-        case F_INJ | F_OUT: return launch2d<F_INJ | F_OUT>(P, a);
-        case F_INJ | F_NORMAL: return launch2d<F_INJ | F_NORMAL>(P, a);
-        case F_INJ | F_CORR: return launch2d<F_INJ | F_CORR>(P, a);
-        case F_INJ | F_CORR | F_OUT: return launch2d<F_INJ | F_CORR | F_OUT>(P, a);
-        case F_INJ | F_CORR | F_SRC_REC: return launch2d<F_INJ | F_CORR | F_SRC_REC>(P, a);
+#define ESI_CASE(F) case (F): return launch2d<(F), T2>(P, a);
+        ESI_CASE(F_SRC_POINT | F_GATHER)
+        ESI_CASE(F_SRC_POINT | F_GATHER | F_STORE)
+        ESI_CASE(F_SRC_POINT | F_STORE)
+        ESI_CASE(F_SRC_POINT)
+        ESI_CASE(F_SRC_DENSE | F_GATHER)
+        ESI_CASE(F_SRC_DENSE | F_GATHER | F_STORE)
+        ESI_CASE(F_SRC_DENSE | F_STORE)
+        ESI_CASE(F_SRC_DENSE)
+        ESI_CASE(F_SRC_DENSE | F_PENALTY)
+        ESI_CASE(F_CG_FUSE | F_GATHER)
+        ESI_CASE(F_INJ | F_OUT)
+        ESI_CASE(F_INJ | F_NORMAL)
+        ESI_CASE(F_INJ | F_CORR)
+        ESI_CASE(F_INJ | F_CORR | F_OUT)
+        ESI_CASE(F_INJ | F_CORR | F_SRC_REC)
+#undef ESI_CASE
         default: return fail(ESI_ERR_ARG, "internal: unsupported 2D step flags " + std::to_string(flags));
     }
 }
 
+}  // namespace
+
+esi_status_t launch_step2d(Plan* P, unsigned flags, const StepArgs& a, bool two_steps) {
+    return two_steps ? dispatch2d<true>(P, flags, a) : dispatch2d<false>(P, flags, a);
+}
+
 void step2d_tile_shape(int* tx, int* tz) { *tx = TX; *tz = TZ; }
+void step2d_t2_tile_shape(int* tx, int* tz) { *tx = T2W; *tz = T2Z; }
 
 esi_status_t launch_final_gather(Plan* P, const float* field, int64_t fstride, float* data,
                                  int shot0, int nshots) {

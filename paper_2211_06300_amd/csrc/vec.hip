@@ -32,6 +32,11 @@ __global__ void k_fill(float* __restrict__ p, int64_t n, float v) {
         p[i] = v;
 }
 
+__global__ void k_fill_d(double* __restrict__ p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+        p[i] = 0.0;
+}
+
 __global__ void k_copy(float* __restrict__ d, const float* __restrict__ s, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
         d[i] = s[i];
@@ -178,6 +183,14 @@ int bps_for(int64_t len) { return (int)std::max<int64_t>(1, std::min<int64_t>(51
 esi_status_t launch_fill(Plan* P, float* p, int64_t n, float v) {
     if (n <= 0) return ESI_OK;
     hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(NT), 0, P->stream, p, n, v);
+    ESI_HIP_TRY(hipGetLastError());
+    return ESI_OK;
+}
+
+// zero a float64 array with a kernel (no memset nodes: calls may be captured)
+esi_status_t launch_fill_d(Plan* P, double* p, int64_t n) {
+    if (n <= 0) return ESI_OK;
+    hipLaunchKernelGGL(k_fill_d, dim3(grid_for(n)), dim3(NT), 0, P->stream, p, n);
     ESI_HIP_TRY(hipGetLastError());
     return ESI_OK;
 }

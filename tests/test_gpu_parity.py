@@ -290,3 +290,42 @@ def test_single_step_and_errors(esi):
     with pytest.raises(esi.EsiError) as e:
         _plan(esi, cfg, v=fast)
     assert e.value.code == 3
+
+
+def test_time_block_bitwise(esi):
+    """Two steps per launch give the same bits as one step per launch for
+    modelling, adjoint modelling, N p and the gradients (odd nt: the last step
+    of each pass runs alone)."""
+    cfg = _ragged_cfg(nt=41)
+    q = torch.from_numpy(inputs.random_field((cfg.nshots, cfg.nt, cfg.nz, cfg.nx), 11)).to(DEV)
+    w = torch.from_numpy(np.stack([cfg.wavelet] * cfg.nshots).astype(np.float32)).to(DEV)
+    outs = []
+    for tb in (1, 2):
+        plan = _plan(esi, cfg)
+        plan.set_time_block(tb)
+        dd = torch.from_numpy(inputs.random_field(plan.data_shape(), 12)).to(DEV)
+        r = [plan.forward(w, esi.SRC_POINT), plan.forward(q, esi.SRC_DENSE), plan.adjoint(dd),
+             plan.normal_apply(q)[0], plan.gradient(esi.GRAD_PENALTY, q),
+             plan.gradient(esi.GRAD_ADJOINT, q, dd), plan.gradient(esi.GRAD_ADJOINT, q, dd, ckpt_every=5)]
+        outs.append([t.cpu().numpy() for t in r])
+        plan.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_time_block_cg(esi):
+    """CG with two-step launches matches one-step launches (p.Np partials are
+    summed in another order, so the match is to rounding, not bitwise)."""
+    cfg = _ragged_cfg(nt=40)
+    xs = []
+    for tb in (1, 2):
+        plan = _plan(esi, cfg)
+        plan.set_time_block(tb)
+        g, m = _oracle_model(cfg)
+        d_obs = [core.forward(m, cfg.wavelet.astype(np.float64), cfg.shot_rec(s), src_pos=cfg.src[s])
+                 .astype(np.float32) for s in range(cfg.nshots)]
+        flat = torch.from_numpy(np.concatenate([d.ravel() for d in d_obs])).to(DEV)
+        xs.append(plan.cg_solve(flat, max_iter=5)[0].cpu().numpy())
+        plan.close()
+    for s in range(2):
+        assert _rel(xs[1][s], xs[0][s]) < 1e-6
