@@ -72,7 +72,7 @@ typedef enum {
 } esi_status_t;
 
 enum { ESI_SRC_POINT = 0, ESI_SRC_DENSE = 1 };
-enum { ESI_GRAD_PENALTY = 0, ESI_GRAD_ADJOINT = 1, ESI_GRAD_SEED = 2 };
+enum { ESI_GRAD_PENALTY = 0, ESI_GRAD_ADJOINT = 1, ESI_GRAD_SEED = 2, ESI_GRAD_SEED_REUSE = 3 };
 
 typedef struct {
     int32_t ndim;       /* 2 or 3 */
@@ -179,6 +179,11 @@ esi_status_t esi_cg_solve(esi_plan_t plan, int32_t shot0, int32_t nshots, const 
  *                     grad_src is not NULL, writes dL/dq to grad_src
  *                     ([nshots][nt] for a point source, [nshots][nt][phys] for a
  *                     dense one).  src_kind as in esi_forward.
+ *   ESI_GRAD_SEED_REUSE: as SEED, but the forward pass is not run again: the
+ *                     wavefield checkpoints saved by the last esi_forward_ckpt
+ *                     call are used (same shot0, nshots, src_kind, src pointer
+ *                     and ckpt_every, model unchanged since); ESI_ERR_ARG if the
+ *                     plan holds no such checkpoints.
  *   ckpt_every: 0 stores (dA/dm)u for every step (nshots*nt*phys floats of plan
  *               scratch); K > 0 stores two time levels every K steps and
  *               recomputes each K-step segment during the backward pass.
@@ -186,6 +191,25 @@ esi_status_t esi_cg_solve(esi_plan_t plan, int32_t shot0, int32_t nshots, const 
 esi_status_t esi_gradient(esi_plan_t plan, int32_t shot0, int32_t nshots, int32_t mode,
                           int32_t src_kind, const float* src, const float* data,
                           float* grad_m, float* grad_src, int32_t ckpt_every);
+
+/*
+ * Forward modelling as esi_forward that also keeps wavefield checkpoints (two
+ * time levels every ckpt_every steps, 2 * ceil(nt/K) padded fields per shot of
+ * plan scratch) for a following esi_gradient(ESI_GRAD_SEED_REUSE) call: the
+ * differentiation pattern in which the forward pass stores checkpoints and the
+ * backward pass recomputes K-step segments (the storage remedy of Sec. 5.1).
+ * Any esi_gradient call in ADJOINT, SEED or SEED_REUSE mode, or another
+ * esi_forward_ckpt call, releases the checkpoints.  ckpt_every >= 1.
+ */
+esi_status_t esi_forward_ckpt(esi_plan_t plan, int32_t shot0, int32_t nshots, int32_t src_kind,
+                              const float* src, float* data, int32_t ckpt_every);
+
+/*
+ * Chain rule from m = 1/v^2 to v: grad_v = -2 grad_m / v^3 on the physical
+ * grid (device [phys] each; grad_v may alias grad_m).
+ */
+esi_status_t esi_grad_velocity(esi_plan_t plan, const float* vel, const float* grad_m,
+                               float* grad_v);
 
 /*
  * Time blocking of the 2D kernels: 2 (default) advances two time steps per

@@ -420,8 +420,14 @@ extern "C" esi_status_t esi_gradient(esi_plan_t plan, int32_t shot0, int32_t ns,
     if (!plan) return fail(ESI_ERR_ARG, "null plan");
     Plan* P = (Plan*)plan;
     ESI_TRY(check_shots(P, shot0, ns));
-    if (mode != ESI_GRAD_PENALTY && mode != ESI_GRAD_ADJOINT && mode != ESI_GRAD_SEED)
+    if (mode != ESI_GRAD_PENALTY && mode != ESI_GRAD_ADJOINT && mode != ESI_GRAD_SEED &&
+        mode != ESI_GRAD_SEED_REUSE)
         return fail(ESI_ERR_ARG, "bad gradient mode");
+    const bool reuse = mode == ESI_GRAD_SEED_REUSE;
+    if (reuse && !(P->ck_valid && P->ck_shot0 == shot0 && P->ck_nshots == ns &&
+                   P->ck_kind == src_kind && P->ck_src == src && P->ck_K == K))
+        return fail(ESI_ERR_ARG, "no checkpoints from esi_forward_ckpt for these shots, source and K");
+    if (reuse) mode = ESI_GRAD_SEED;
     if (src_kind != ESI_SRC_POINT && src_kind != ESI_SRC_DENSE) return fail(ESI_ERR_ARG, "bad src_kind");
     if (mode != ESI_GRAD_SEED && src_kind != ESI_SRC_DENSE)
         return fail(ESI_ERR_ARG, "PENALTY and ADJOINT modes take a dense extended source");
@@ -450,7 +456,8 @@ extern "C" esi_status_t esi_gradient(esi_plan_t plan, int32_t shot0, int32_t ns,
     // correlated with the stored or recomputed (dA/dm) u.
     const int nt = P->nt;
     const int64_t dl = data_len(P, shot0, ns);
-    const bool ckpt = K > 0 && K < nt;
+    const bool ckpt = reuse || (K > 0 && K < nt);
+    P->ck_valid = false;
     const int Kc = ckpt ? K : 0;
     const int nseg = ckpt ? (nt + K - 1) / K : 1;
     const int slots = ckpt ? K : nt;
@@ -472,7 +479,7 @@ extern "C" esi_status_t esi_gradient(esi_plan_t plan, int32_t shot0, int32_t ns,
                                     shot0, ns));
         ESI_TRY(launch_sub(P, P->dscr, P->dscr, data, dl));   // G = S q - d_obs
         G = P->dscr;
-    } else {
+    } else if (!reuse) {
         ESI_TRY(forward_loop(P, a, srcfl | (ckpt ? 0u : F_STORE), P->ring, &fcs, 0, nt,
                              ckpt ? P->ckpt : nullptr, Kc, nseg));
     }
@@ -558,4 +565,43 @@ extern "C" esi_status_t esi_plan_set_time_block(esi_plan_t plan, int32_t steps) 
     if (steps != 1 && steps != 2) return fail(ESI_ERR_ARG, "time block must be 1 or 2");
     ((Plan*)plan)->time_block = steps;
     return ESI_OK;
+}
+
+extern "C" esi_status_t esi_forward_ckpt(esi_plan_t plan, int32_t shot0, int32_t nshots,
+                                         int32_t src_kind, const float* src, float* data,
+                                         int32_t K) {
+    set_error("");
+    if (!plan) return fail(ESI_ERR_ARG, "null plan");
+    Plan* P = (Plan*)plan;
+    ESI_TRY(check_shots(P, shot0, nshots));
+    if (src_kind != ESI_SRC_POINT && src_kind != ESI_SRC_DENSE) return fail(ESI_ERR_ARG, "bad src_kind");
+    if (!src) return fail(ESI_ERR_ARG, "null src");
+    if (!data && data_len(P, shot0, nshots) > 0) return fail(ESI_ERR_ARG, "null data");
+    if (K < 1) return fail(ESI_ERR_ARG, "ckpt_every must be >= 1");
+    TileLists* L;
+    ESI_TRY(lists_for(P, &L));
+    P->ck_valid = false;
+    const int nseg = (P->nt + K - 1) / K;
+    ESI_TRY(grow_t(&P->ckpt, &P->ckpt_cap, (int64_t)nshots * nseg * 2 * P->fsize, P->stream));
+    ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, nshots));
+    StepArgs a = base_args(P, L, shot0, nshots);
+    unsigned fl = F_GATHER;
+    if (src_kind == ESI_SRC_POINT) { fl |= F_SRC_POINT; a.wavelet = src; }
+    else { fl |= F_SRC_DENSE; a.dsrc = src; }
+    a.gat_data = data;
+    int cs = 0;
+    ESI_TRY(forward_loop(P, a, fl, P->ring, &cs, 0, P->nt, P->ckpt, K, nseg));
+    ESI_TRY(launch_final_gather(P, P->ring + (int64_t)cs * P->fsize, RING * P->fsize, data, shot0,
+                                nshots));
+    P->ck_valid = true;
+    P->ck_shot0 = shot0; P->ck_nshots = nshots; P->ck_kind = src_kind; P->ck_src = src; P->ck_K = K;
+    return ESI_OK;
+}
+
+extern "C" esi_status_t esi_grad_velocity(esi_plan_t plan, const float* vel, const float* grad_m,
+                                          float* grad_v) {
+    set_error("");
+    if (!plan || !vel || !grad_m || !grad_v) return fail(ESI_ERR_ARG, "null argument");
+    Plan* P = (Plan*)plan;
+    return launch_grad_velocity(P, vel, grad_m, grad_v, P->nphys);
 }

@@ -115,6 +115,11 @@ struct Plan {
 
     std::vector<TileLists*> lists;       // one per tile shape used
     int time_block = 2;                  // steps per launch where allowed (1 or 2)
+    // checkpoints retained by esi_forward_ckpt for a SEED_REUSE gradient
+    bool ck_valid = false;
+    int ck_shot0 = 0, ck_nshots = 0, ck_kind = 0, ck_K = 0;
+    const float* ck_src = nullptr;
+    int64_t model_version = 0;
 
     // profiling: event pairs around time loops, folded into totals on read
     struct ProfRec { unsigned flags; int64_t launches, shot_launches; hipEvent_t e0, e1; };
@@ -241,5 +246,7 @@ esi_status_t launch_sum_shots(Plan* P, const float* gacc, int nshots, int64_t le
 esi_status_t launch_sub(Plan* P, float* out, const float* a, const float* b, int64_t n);
 // grad_src point: out[s][n] = mu at the source cell, from a dense [nshots][nt][phys] field
 esi_status_t launch_trace_at_src(Plan* P, const float* dense, int shot0, int nshots, float* out);
+// grad_v = -2 grad_m / v^3
+esi_status_t launch_grad_velocity(Plan* P, const float* vel, const float* gm, float* gv, int64_t n);
 
 }  // namespace esi

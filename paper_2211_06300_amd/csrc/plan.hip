@@ -350,12 +350,19 @@ extern "C" esi_status_t esi_plan_create(esi_plan_t* plan, const esi_grid_t* g, c
     P->nxp = g->nx + 2 * g->nb;
     P->nyp = nd == 3 ? g->ny + 2 * g->nb : 1;
     // storage: zero ghost halo of HALO cells beyond every tile that may be used
-    // wide enough for every tile shape used: 64- to 256-wide tiles over
-    // round_up(nxp, 256) plus the ghost frame, and 56-wide two-step tiles whose
-    // staged region reaches 72 columns past the last tile origin
-    P->XS = round_up(std::max(round_up(P->nxp, 256) + 2 * GH, P->nxp + 80), 32);
-    P->ZS = round_up(P->nzp, 64) + 2 * GH;
-    P->YS = nd == 3 ? round_up(P->nyp, 64) + 2 * GH : 1;
+    if (nd == 2) {
+        // wide enough for every tile shape used: 64- to 256-wide tiles over
+        // round_up(nxp, 256) plus the ghost frame, and 56-wide two-step tiles
+        // whose staged region reaches 72 columns past the last tile origin
+        P->XS = round_up(std::max(round_up(P->nxp, 256) + 2 * GH, P->nxp + 80), 32);
+        P->ZS = round_up(P->nzp, 64) + 2 * GH;
+        P->YS = 1;
+    } else {
+        // 64 x 8 column blocks, 32-plane chunks, plus the ghost frame
+        P->XS = round_up(round_up(P->nxp, 64) + 2 * GH, 32);
+        P->YS = round_up(P->nyp, 8) + 2 * GH;
+        P->ZS = round_up(P->nzp, 32) + 2 * GH;
+    }
     P->fsize = (int64_t)P->ZS * P->YS * P->XS;
     P->nphys = (int64_t)g->nz * g->ny * g->nx;
     double w[5];
@@ -398,6 +405,8 @@ extern "C" esi_status_t esi_plan_create(esi_plan_t* plan, const esi_grid_t* g, c
 extern "C" esi_status_t esi_plan_set_model(esi_plan_t plan, const float* vel) {
     set_error("");
     if (!plan || !vel) return fail(ESI_ERR_ARG, "null argument");
+    ((Plan*)plan)->model_version++;
+    ((Plan*)plan)->ck_valid = false;   // checkpoints belong to the old model
     return set_model((Plan*)plan, vel, false, 0.0);
 }
 

@@ -1,13 +1,301 @@
-// 3D time step (not built yet in this file's first version).
+// One time step of the 3D 8th-order acoustic scheme (Sec. 4.1) with the same
+// fused work as the 2D kernels (injection, recording, CG direction update,
+// N p with p.Np partials, gradient correlations).
+//
+// 2.5D sweep: a 512-thread workgroup owns a 64 (x) x 8 (y) block of columns
+// and a chunk of 32 z-planes.  Each thread keeps the 9-value z window of its
+// column in registers; the current plane of the block plus a 4-cell x/y halo
+// is staged in a double-buffered LDS plane, so one barrier per plane suffices.
+// Receiver injection is applied per plane through a small LDS plane; the
+// recording reads u^n straight from memory.  Storage is the padded grid with
+// a zero ghost frame of GH cells, planes YS x XS floats apart.
 #include "esi_internal.h"
 
 namespace esi {
 
-esi_status_t launch_step3d(Plan* P, unsigned flags, const StepArgs& a) {
-    (void)P; (void)flags; (void)a;
-    return fail(ESI_ERR_ARG, "3D kernels are not available in this build");
+namespace {
+
+constexpr int TX = 64, TY = 8, TZC = 32;   // block of columns, z-chunk
+constexpr int NTH = TX * TY;               // 512 threads
+constexpr int PW = TX + 2 * HALO, PH = TY + 2 * HALO;   // staged plane 72 x 16
+constexpr int NHALO = PW * PH - TX * TY;   // 640 halo cells per plane
+
+__device__ __forceinline__ int xcd_remap(int b, int nblocks) {
+    const int per = nblocks / XCDS, rem = nblocks % XCDS;
+    const int xcd = b % XCDS, idx = b / XCDS;
+    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
 }
 
-void step3d_tile_shape(int* tx, int* ty, int* tz) { *tx = 64; *ty = 4; *tz = 1; }
+template <class T>
+__device__ __forceinline__ T& at(T* base, uint32_t i) {
+    return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ const T& at(const T* base, uint32_t i) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (uint32_t)sizeof(T));
+}
+
+template <unsigned FL>
+__global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
+    __shared__ float P[2][PH * PW];
+    __shared__ float sinj[(FL & F_INJ) ? TX * TY : 1];
+    __shared__ double sred[NTH / 64];
+
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    const int s = L / a.tiles;
+    const int t = L - s * a.tiles;
+    if (a.active && !a.active[s]) return;   // uniform over the workgroup
+    const int gs = a.shot0 + s;
+    const int tzi = t / (a.tiles_x * a.tiles_y);
+    const int rem = t - tzi * a.tiles_x * a.tiles_y;
+    const int tyi = rem / a.tiles_x, txi = rem - tyi * a.tiles_x;
+    const int x0 = txi * TX, y0 = tyi * TY, zc0 = tzi * TZC;
+    const int tid = threadIdx.x, lx = tid & 63;
+    const int ly = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int XS = a.XS, YS = a.YS;
+    const uint32_t PS = (uint32_t)(YS * XS);                 // plane stride
+    const float* __restrict__ cur = a.cur + s * a.fstride;
+    float* __restrict__ nxt = a.nxt + s * a.fstride;
+    const float* __restrict__ din = a.din + s * a.fstride;
+    float* __restrict__ dnx = a.dnx + s * a.fstride;
+
+    const int x = x0 + lx, y = y0 + ly;
+    const uint32_t col = (uint32_t)((y + GH) * XS + x + GH);   // column offset within a plane
+    // halo cells this thread stages: LDS index and in-plane storage offset
+    int hl[2];
+    uint32_t ho[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        int h = tid + k * NTH;
+        hl[k] = -1;
+        ho[k] = 0;
+        if (h < NHALO) {
+            int ry, rx;
+            if (h < 2 * HALO * PW) {                          // y-halo slabs, full width
+                ry = h / PW;
+                rx = h - ry * PW;
+                if (ry >= HALO) ry += TY;
+            } else {                                          // x-halo, body rows
+                h -= 2 * HALO * PW;
+                ry = HALO + h / (2 * HALO);
+                rx = h % (2 * HALO);
+                if (rx >= HALO) rx += TX;
+            }
+            hl[k] = ry * PW + rx;
+            ho[k] = (uint32_t)((y0 - HALO + ry + GH) * XS + x0 - HALO + rx + GH);
+        }
+    }
+
+    const float kxy = at(a.kx, (uint32_t)min(x, a.nxp - 1)) + at(a.ky, (uint32_t)min(y, a.nyp - 1));
+    const int ix = x - a.nb, iy = y - a.nb;
+    const bool xyphys = ix >= 0 && ix < a.nx && iy >= 0 && iy < a.ny;
+    const int64_t vbase = ((int64_t)s * a.nt + a.step) * a.nphys;
+    const float* dsrc = (FL & F_SRC_DENSE) ? a.dsrc + vbase : nullptr;
+    float* dout = (FL & (F_OUT | F_NORMAL)) ? a.dout + vbase : nullptr;
+    const float* dp = (FL & F_NORMAL) ? a.dp + vbase : nullptr;
+    float* gacc = (FL & (F_PENALTY | F_CORR)) ? a.gacc + (int64_t)s * a.nphys : nullptr;
+    float* store = (FL & (F_STORE | F_CORR)) ? a.store + s * a.store_stride + (int64_t)a.store_slot * a.nphys : nullptr;
+    float alp = 0.f, bet = 0.f;
+    const float* cgp = nullptr; const float* cgr = nullptr; float* cgpn = nullptr; float* cgx = nullptr;
+    if constexpr ((FL & F_CG_FUSE) != 0) {
+        alp = (float)a.cg_alpha[s];
+        bet = (float)a.cg_beta[s];
+        cgp = a.cg_p + vbase; cgr = a.cg_r + vbase; cgpn = a.cg_pn + vbase; cgx = a.cg_x + vbase;
+    }
+
+    const int64_t nrec_s = (FL & (F_INJ | F_GATHER)) ? a.rec_ptr[gs + 1] - a.rec_ptr[gs] : 0;
+    const int64_t doff = (FL & (F_INJ | F_GATHER)) ? (int64_t)a.nt * (a.rec_ptr[gs] - a.rec_ptr[a.shot0]) : 0;
+    if constexpr ((FL & F_GATHER) != 0) {
+        // d^{n-1} = R u^n for the receivers of this block, straight from u^n
+        if (a.step > 0) {
+            const int32_t* gp = a.gat_ptr + (int64_t)gs * (a.tiles + 1);
+            float* dn = a.gat_data + doff + (int64_t)(a.step - 1) * nrec_s;
+            for (int e = gp[t] + tid; e < gp[t + 1]; e += NTH) {
+                const int cell = a.gat_cell[e];
+                const int lz = cell / (TX * TY), r2 = cell - lz * TX * TY;
+                const int cy = r2 / TX, cx = r2 - cy * TX;
+                dn[a.gat_rid[e]] = cur[((zc0 + lz + GH) * YS + y0 + cy + GH) * XS + x0 + cx + GH];
+            }
+        }
+    }
+    int ie = 0, iend = 0;
+    const float* dj = nullptr;
+    if constexpr ((FL & F_INJ) != 0) {
+        const int32_t* ip = a.inj_ptr + (int64_t)gs * (a.tiles + 1);
+        ie = ip[t];
+        iend = ip[t + 1];
+        dj = a.inj_data + doff + (int64_t)a.step * nrec_s;
+    }
+    int src_cell = -1;
+    float src_val = 0.f;
+    if constexpr ((FL & (F_SRC_POINT | F_SRC_REC)) != 0) {
+        if (a.src_tile[gs] == t) {
+            src_cell = a.src_cell[gs];
+            if constexpr ((FL & F_SRC_POINT) != 0) src_val = a.wavelet[(int64_t)s * a.nt + a.step];
+        }
+    }
+    float sx = 0.f, sy = 0.f, sz = 0.f;
+    if constexpr ((FL & (F_NORMAL | F_PENALTY)) != 0) {
+        sx = (float)a.src_pos[gs * 3 + 0];
+        sz = (float)a.src_pos[gs * 3 + 1];
+        sy = (float)a.src_pos[gs * 3 + 2];
+    }
+
+    // z window of this column: w[k] = u at z - 4 + k
+    float w[2 * HALO + 1];
+#pragma unroll
+    for (int k = 0; k < 2 * HALO; ++k) w[k] = at(cur, (uint32_t)(zc0 - HALO + k + GH) * PS + col);
+    const int zend = min(zc0 + TZC, a.nzp);
+    double acc = 0.0;
+    for (int z = zc0; z < zend; ++z) {
+        const int lz = z - zc0;
+        const uint32_t pz = (uint32_t)(z + GH) * PS;
+        w[2 * HALO] = at(cur, pz + 4u * PS + col);
+        float* Pb = P[lz & 1];
+        Pb[(ly + HALO) * PW + lx + HALO] = w[HALO];
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+            if (hl[k] >= 0) Pb[hl[k]] = at(cur, pz + ho[k]);
+        // this plane's loads
+        const uint32_t so = pz + col;
+        const float c2v = at(a.c2, so);
+        const float dv = at(din, so);
+        const float kap = kxy + at(a.kz, (uint32_t)min(z, a.nzp - 1));
+        const int iz = z - a.nb;
+        const bool ph = xyphys && iz >= 0 && iz < a.nz;
+        const uint32_t pi = ph ? (uint32_t)((iz * a.ny + iy) * a.nx + ix) : 0u;
+        float q = 0.f;
+        if constexpr ((FL & F_SRC_DENSE) != 0) q = ph ? at(dsrc, pi) : 0.f;
+        float po = 0.f, xo = 0.f;
+        if constexpr ((FL & F_CG_FUSE) != 0) {
+            po = at(cgp, pi);
+            xo = at(cgx, pi);
+            q = ph ? fmaf(bet, po, at(cgr, pi)) : 0.f;
+        }
+        float pv = 0.f, stv = 0.f;
+        if constexpr ((FL & F_NORMAL) != 0) pv = at(dp, pi);
+        if constexpr ((FL & F_CORR) != 0) stv = at(store, pi);
+        bool inj_here = false;
+        if constexpr ((FL & F_INJ) != 0) {
+            // entries are sorted by cell, i.e. by plane first
+            if (ie < iend && a.inj_cell[ie] / (TX * TY) == lz) {
+                inj_here = true;
+                __syncthreads();                  // the last injection plane has been read
+                sinj[tid] = 0.f;
+                __syncthreads();
+                int e = ie + tid;
+                while (e < iend && a.inj_cell[e] / (TX * TY) == lz) {
+                    float v = 0.f;
+                    for (int k = a.inj_rptr[e]; k < a.inj_rptr[e + 1]; ++k) v += dj[a.inj_rid[k]];
+                    sinj[a.inj_cell[e] - lz * TX * TY] = v;
+                    e += NTH;
+                }
+                while (ie < iend && a.inj_cell[ie] / (TX * TY) == lz) ++ie;
+            }
+        }
+        __syncthreads();
+        const float* cp = Pb + (ly + HALO) * PW + lx + HALO;
+        const float cv = w[HALO];
+        float lx_ = a.w1 * ((cp[-1] - cv) + (cp[1] - cv));
+        lx_ = fmaf(a.w2, (cp[-2] - cv) + (cp[2] - cv), lx_);
+        lx_ = fmaf(a.w3, (cp[-3] - cv) + (cp[3] - cv), lx_);
+        lx_ = fmaf(a.w4, (cp[-4] - cv) + (cp[4] - cv), lx_);
+        float ly_ = a.w1 * ((cp[-PW] - cv) + (cp[PW] - cv));
+        ly_ = fmaf(a.w2, (cp[-2 * PW] - cv) + (cp[2 * PW] - cv), ly_);
+        ly_ = fmaf(a.w3, (cp[-3 * PW] - cv) + (cp[3 * PW] - cv), ly_);
+        ly_ = fmaf(a.w4, (cp[-4 * PW] - cv) + (cp[4 * PW] - cv), ly_);
+        float lz_ = a.w1 * ((w[3] - cv) + (w[5] - cv));
+        lz_ = fmaf(a.w2, (w[2] - cv) + (w[6] - cv), lz_);
+        lz_ = fmaf(a.w3, (w[1] - cv) + (w[7] - cv), lz_);
+        lz_ = fmaf(a.w4, (w[0] - cv) + (w[8] - cv), lz_);
+        const float lap = (lx_ + ly_) + lz_;
+        const int cell = lz * TX * TY + ly * TX + lx;
+        if constexpr ((FL & F_SRC_POINT) != 0) {
+            if (cell == src_cell) q += src_val;
+        }
+        if constexpr ((FL & F_INJ) != 0) {
+            if (inj_here) q += sinj[tid];
+        }
+        const float lq = fmaf(a.dx2, q, lap);
+        const float dn = fmaf(c2v, lq, (1.f - kap) * dv) * __builtin_amdgcn_rcpf(1.f + kap);
+        const float un = cv + dn;
+        // cells past the padded grid sit in the zero ghost frame and compute 0
+        at(dnx, so) = dn;
+        at(nxt, so) = un;
+        if (ph) {
+            if constexpr ((FL & F_CG_FUSE) != 0) {
+                at(cgpn, pi) = q;
+                if (alp != 0.f) at(cgx, pi) = fmaf(alp, po, xo);
+            }
+            if constexpr ((FL & F_OUT) != 0) at(dout, pi) = un;
+            if constexpr ((FL & F_SRC_REC) != 0) {
+                if (cell == src_cell) a.src_rec[(int64_t)s * a.nt + a.step] = un;
+            }
+            float wb = 0.f;
+            if constexpr ((FL & (F_NORMAL | F_PENALTY)) != 0) {
+                const float ddx = (float)ix - sx, ddy = (float)iy - sy, ddz = (float)iz - sz;
+                const float bb = sqrtf(ddx * ddx + ddy * ddy + ddz * ddz) + a.b_eps;
+                wb = a.beta * (bb * bb);
+            }
+            if constexpr ((FL & F_NORMAL) != 0) {
+                const float np = fmaf(wb, pv, un);
+                at(dout, pi) = np;
+                acc += (double)pv * (double)np;
+            }
+            if constexpr ((FL & F_PENALTY) != 0) at(gacc, pi) = fmaf(wb * q, c2v * a.inv_dt2 * lq, at(gacc, pi));
+            if constexpr ((FL & F_STORE) != 0) at(store, pi) = c2v * a.inv_dt2 * lq;
+            if constexpr ((FL & F_CORR) != 0) at(gacc, pi) = fmaf(un, stv, at(gacc, pi));
+        }
+#pragma unroll
+        for (int k = 0; k < 2 * HALO; ++k) w[k] = w[k + 1];
+    }
+
+    if constexpr ((FL & F_NORMAL) != 0) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (lx == 0) sred[ly] = acc;
+        __syncthreads();
+        if (tid == 0) {
+            double sum = 0.0;
+            for (int k = 0; k < NTH / 64; ++k) sum += sred[k];
+            a.part[(int64_t)s * a.part_stride + t] += sum;
+        }
+    }
+}
+
+template <unsigned FL>
+esi_status_t launch3d(Plan* P, const StepArgs& a) {
+    const int blocks = a.tiles * a.nshots;
+    hipLaunchKernelGGL(k_step3d<FL>, dim3(blocks), dim3(NTH), 0, P->stream, a);
+    ESI_HIP_TRY(hipGetLastError());
+    return ESI_OK;
+}
+
+}  // namespace
+
+esi_status_t launch_step3d(Plan* P, unsigned flags, const StepArgs& a) {
+    switch (flags) {
+#define ESI_CASE(F) case (F): return launch3d<(F)>(P, a);
+        ESI_CASE(F_SRC_POINT | F_GATHER)
+        ESI_CASE(F_SRC_POINT | F_GATHER | F_STORE)
+        ESI_CASE(F_SRC_POINT | F_STORE)
+        ESI_CASE(F_SRC_POINT)
+        ESI_CASE(F_SRC_DENSE | F_GATHER)
+        ESI_CASE(F_SRC_DENSE | F_GATHER | F_STORE)
+        ESI_CASE(F_SRC_DENSE | F_STORE)
+        ESI_CASE(F_SRC_DENSE)
+        ESI_CASE(F_SRC_DENSE | F_PENALTY)
+        ESI_CASE(F_CG_FUSE | F_GATHER)
+        ESI_CASE(F_INJ | F_OUT)
+        ESI_CASE(F_INJ | F_NORMAL)
+        ESI_CASE(F_INJ | F_CORR)
+        ESI_CASE(F_INJ | F_CORR | F_OUT)
+        ESI_CASE(F_INJ | F_CORR | F_SRC_REC)
+#undef ESI_CASE
+        default: return fail(ESI_ERR_ARG, "internal: unsupported 3D step flags " + std::to_string(flags));
+    }
+}
+
+void step3d_tile_shape(int* tx, int* ty, int* tz) { *tx = TX; *ty = TY; *tz = TZC; }
 
 }  // namespace esi

@@ -174,6 +174,13 @@ __global__ void k_copy_shots(float* __restrict__ d, int64_t ds, const float* __r
         d[s * ds + i] = src[s * ss + i];
 }
 
+__global__ void k_grad_velocity(const float* __restrict__ v, const float* gm, float* gv, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+        const float vi = v[i];
+        gv[i] = -2.f * gm[i] / (vi * vi * vi);
+    }
+}
+
 int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + NT - 1) / NT, 8192)); }
 
 int bps_for(int64_t len) { return (int)std::max<int64_t>(1, std::min<int64_t>(512, (len + 4095) / 4096)); }
@@ -272,6 +279,13 @@ esi_status_t launch_sum_shots(Plan* P, const float* gacc, int nshots, int64_t le
                               float* grad) {
     hipLaunchKernelGGL(k_sum_shots, dim3(grid_for(len)), dim3(NT), 0, P->stream, gacc, nshots, len,
                        sign, grad);
+    ESI_HIP_TRY(hipGetLastError());
+    return ESI_OK;
+}
+
+esi_status_t launch_grad_velocity(Plan* P, const float* vel, const float* gm, float* gv, int64_t n) {
+    if (n <= 0) return ESI_OK;
+    hipLaunchKernelGGL(k_grad_velocity, dim3(grid_for(n)), dim3(NT), 0, P->stream, vel, gm, gv, n);
     ESI_HIP_TRY(hipGetLastError());
     return ESI_OK;
 }

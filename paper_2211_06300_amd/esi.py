@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libesi.so")
 
 SRC_POINT, SRC_DENSE = 0, 1
-GRAD_PENALTY, GRAD_ADJOINT, GRAD_SEED = 0, 1, 2
+GRAD_PENALTY, GRAD_ADJOINT, GRAD_SEED, GRAD_SEED_REUSE = 0, 1, 2, 3
 _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_SHAPE", 3: "ERR_CFL", 4: "ERR_OOM", 5: "ERR_HIP",
            6: "ERR_BREAKDOWN", 7: "ERR_NONFINITE"}
 
@@ -47,7 +47,8 @@ class _CgReport(ctypes.Structure):
 _lib = None
 EXPORTS = ["esi_plan_create", "esi_plan_set_model", "esi_plan_destroy", "esi_last_error",
            "esi_forward", "esi_adjoint", "esi_normal_apply", "esi_cg_solve", "esi_gradient",
-           "esi_plan_profile", "esi_plan_profile_read", "esi_plan_set_time_block"]
+           "esi_plan_profile", "esi_plan_profile_read", "esi_plan_set_time_block",
+           "esi_forward_ckpt", "esi_grad_velocity"]
 # time-step kernel variants (bit set of fused work), as in include/esi.h
 K_FLAGS = {1: "SRC_POINT", 2: "SRC_DENSE", 4: "CG_FUSE", 8: "INJ", 16: "GATHER", 32: "OUT",
            64: "NORMAL", 128: "PENALTY", 256: "STORE", 512: "CORR", 1024: "SRC_REC",
@@ -76,6 +77,8 @@ def load_library(path: str = LIB_PATH):
     L.esi_gradient.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp, vp, i32]
     L.esi_plan_profile.argtypes = [vp, i32]
     L.esi_plan_set_time_block.argtypes = [vp, i32]
+    L.esi_forward_ckpt.argtypes = [vp, i32, i32, i32, vp, vp, i32]
+    L.esi_grad_velocity.argtypes = [vp, vp, vp, vp]
     L.esi_plan_profile_read.argtypes = [vp, i32, vp, vp, vp, vp, vp]
     for f in EXPORTS:
         if f != "esi_last_error":
@@ -190,6 +193,25 @@ class Plan:
         out = self.new_data(shot0, nshots) if out is None else out
         _check(self._lib.esi_forward(self._h, shot0, nshots, kind, _f32(src, shape, "src"),
                                      _f32(out, self.data_shape(shot0, nshots), "data")))
+        return out
+
+    def forward_ckpt(self, src, ckpt_every, kind=SRC_POINT, shot0=0, nshots=None, out=None):
+        """Forward modelling that keeps wavefield checkpoints every `ckpt_every`
+        steps for a following gradient(GRAD_SEED_REUSE, ...)."""
+        shot0, nshots = self._range(shot0, nshots)
+        shape = (nshots, self.nt) if kind == SRC_POINT else self.vec_shape(nshots)
+        out = self.new_data(shot0, nshots) if out is None else out
+        _check(self._lib.esi_forward_ckpt(self._h, shot0, nshots, kind, _f32(src, shape, "src"),
+                                          _f32(out, self.data_shape(shot0, nshots), "data"),
+                                          int(ckpt_every)))
+        return out
+
+    def grad_velocity(self, vel, grad_m, out=None):
+        """grad_v = -2 grad_m / v^3 (device kernel)."""
+        out = torch.empty_like(grad_m) if out is None else out
+        _check(self._lib.esi_grad_velocity(self._h, _f32(vel, self.phys_shape, "vel"),
+                                           _f32(grad_m, self.phys_shape, "grad_m"),
+                                           _f32(out, self.phys_shape, "grad_v")))
         return out
 
     def adjoint(self, data, shot0=0, nshots=None, out=None):

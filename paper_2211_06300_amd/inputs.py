@@ -151,3 +151,54 @@ def cfg_tiny(nz: int = 8, nx: int = 8, nt: int = 24, nb: int = 4, seed: int = 7,
 def random_field(shape, seed: int) -> np.ndarray:
     """Seeded N(0, 1) float32 array (dot-test and parity vectors)."""
     return np.random.default_rng(seed).standard_normal(shape).astype(np.float32)
+
+
+def gaussian_random_field(shape, sigma: float, seed: int) -> np.ndarray:
+    """White N(0, 1) noise smoothed by a Gaussian of sigma cells (periodic FFT
+    filter), standardized to zero mean and unit variance; float64."""
+    rng = np.random.default_rng(seed)
+    white = rng.standard_normal(shape)
+    k = [np.fft.fftfreq(n) for n in shape]
+    kk = np.zeros(shape)
+    for ax, ka in enumerate(k):
+        sh = [1] * len(shape)
+        sh[ax] = -1
+        kk = kk + (ka.reshape(sh)) ** 2
+    field = np.real(np.fft.ifftn(np.fft.fftn(white) * np.exp(-2.0 * (np.pi * sigma) ** 2 * kk)))
+    return (field - field.mean()) / field.std()
+
+
+def cfg_diff3d(n: int = 256, nshots: int = 8, nt: int = 1500, rec_n: int = 128, seed: int = 3,
+               dx: float = 10.0, dt: float = 1e-3, f: float = 10.0, nb: int = 20) -> Config:
+    """3D n^3 grid, dx 10 m, v = 3000 + 300 * (Gaussian random field, sigma 16
+    cells) clipped to [2000, 4000] m/s (seed 3); `nshots` shots at depth cell 2
+    on a 2 x 4 lattice; a rec_n x rec_n receiver grid at depth cell 2, every
+    2nd cell; 10 Hz Ricker, nt steps of 1 ms (the differentiation workload)."""
+    field = gaussian_random_field((n, n, n), 16.0 * n / 256.0, seed)
+    v = np.clip(3000.0 + 300.0 * field, 2000.0, 4000.0).astype(np.float32)   # [z][y][x]
+    px = np.round(np.linspace(n / 8, n - n / 8, 4)).astype(int)
+    py = np.round(np.linspace(n / 4, n - n / 4, 2)).astype(int)
+    lattice = [(x, 2, y) for y in py for x in px][:nshots]
+    src = np.array(lattice, dtype=np.int32)                                  # (ix, iz, iy)
+    step = max(1, min(2, n // rec_n))
+    r1 = np.arange(rec_n) * step + (n - (rec_n - 1) * step - 1) // 2
+    ry, rx = np.meshgrid(r1, r1, indexing="ij")
+    rec1 = np.stack([rx.ravel(), np.full(rx.size, 2), ry.ravel()], axis=1).astype(np.int32)
+    ptr, rr = _csr([rec1] * len(src))
+    return Config(f"diff3d-{n}^3", 3, n, n, n, dx, dt, nt, nb, f, 1e-2, 0, v, v.copy(), src, ptr,
+                  rr, ricker_samples(nt, dt, f))
+
+
+def crop3d(cfg: Config, n: int, nt: int, rec_n: int) -> Config:
+    """Central n^3 block of a 3D workload with one shot at its top centre and a
+    rec_n x rec_n receiver grid (every 2nd cell) at depth cell 2."""
+    N = cfg.nz
+    o = (N - n) // 2
+    v = np.ascontiguousarray(cfg.v_true[o:o + n, o:o + n, o:o + n])
+    src = np.array([[n // 2, 2, n // 2]], dtype=np.int32)
+    r1 = np.arange(rec_n) * 2 + (n - (rec_n - 1) * 2 - 1) // 2
+    ry, rx = np.meshgrid(r1, r1, indexing="ij")
+    rec1 = np.stack([rx.ravel(), np.full(rx.size, 2), ry.ravel()], axis=1).astype(np.int32)
+    ptr, rr = _csr([rec1])
+    return Config(f"crop3d-{n}^3", 3, n, n, n, cfg.dx, cfg.dt, nt, min(cfg.nb, 12), cfg.freq,
+                  cfg.beta, 0, v, v.copy(), src, ptr, rr, ricker_samples(nt, cfg.dt, cfg.freq))
