@@ -42,6 +42,46 @@ DENSE_BYTES = {2: 4, 4: 20, 32: 4, 64: 8, 128: 8, 256: 4, 512: 12}
 
 TWO_STEP = 1 << 15
 
+# HBM counter summary of the 2D time-step kernels (two rocprofv3 --pmc passes,
+# FETCH_SIZE and WRITE_SIZE, calibrated on a copy of known size)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step2d_t2_single-solve-801x401_traffic.md")
+KERNEL_SOURCES = ["paper_2211_06300_amd/csrc/step2d.hip", "paper_2211_06300_amd/csrc/esi_internal.h"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(flags: int, shots_per_launch: float, path: str = TRAFFIC_FILE):
+    """HBM bytes per launch of the 2D step variant `flags` from the committed
+    counter summary, or None when the kernel sources changed since the counters
+    were taken or the launch shape differs."""
+    try:
+        with open(path) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    meta = {}
+    for line in text.splitlines():
+        for key in ("kernel-sources-sha256-16:", "calibration:", "shots-per-launch:"):
+            if line.startswith(key):
+                meta[key] = line[len(key):].split()
+    if meta.get("kernel-sources-sha256-16:", [None])[0] != kernel_source_hash():
+        return None
+    if float(meta["shots-per-launch:"][0]) != shots_per_launch or not flags & TWO_STEP:
+        return None
+    cf, cw = float(meta["calibration:"][1]), float(meta["calibration:"][3])
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 5 and cells[0] == str(flags & ~TWO_STEP):
+            return int((cf * float(cells[3]) + cw * float(cells[4])) * 1024)
+    return None
+
 
 def bytes_per_shot_launch(flags: int, npad: int, nphys: int) -> int:
     """Algorithmic bytes of one launch for one shot (a two-step launch counts
@@ -172,6 +212,7 @@ def main():
     shots_per_launch = rec["shot_launches"] / rec["launches"]
     alg_bytes = bytes_per_shot_launch(rec["flags"], npad, nphys) * shots_per_launch
     achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9
+    traffic = measured_traffic(rec["flags"], shots_per_launch)
     hist = np.concatenate([h for h in last_hist.values()])
     out = {
         "metric": METRIC,
@@ -193,7 +234,7 @@ def main():
         "roofline": {"bound": "hbm",
                      "kernel": ("k_step2d_t2" if rec["flags"] & TWO_STEP else "k_step2d") + f"<{name}>",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "alg_bytes_per_launch": int(alg_bytes),
                      "avg_launch_us": round(per_launch_ms * 1e3, 2)},
         "gpu_event_ms": round(gpu_ms, 1),

@@ -1,0 +1,40 @@
+"""Host logic of bench.py: algorithmic bytes and the counter-summary lookup."""
+import os
+
+import bench
+
+
+def test_alg_bytes_two_step_counts_both_steps():
+    one = bench.bytes_per_shot_launch(20, 1000, 800)
+    assert one == 16 * 1000 + 20 * 800
+    assert bench.bytes_per_shot_launch(20 | bench.TWO_STEP, 1000, 800) == 2 * one
+
+
+def test_measured_traffic_lookup(tmp_path):
+    h = bench.kernel_source_hash()
+    text = "\n".join([
+        f"kernel-sources-sha256-16: {h}  (note)",
+        "calibration: fetch 2.0 write 1.0",
+        "shots-per-launch: 16",
+        "| flags | variant | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB |",
+        "|---:|---|---:|---:|---:|",
+        "| 20 | CG_FUSE+GATHER | 10 | 100.0 | 50.0 |",
+        "| 72 | INJ+NORMAL | 10 | 10.0 | 5.0 |",
+    ])
+    p = tmp_path / "t.md"
+    p.write_text(text)
+    T = bench.TWO_STEP
+    assert bench.measured_traffic(20 | T, 16.0, str(p)) == (2 * 100 + 50) * 1024
+    assert bench.measured_traffic(72 | T, 16.0, str(p)) == (2 * 10 + 5) * 1024
+    assert bench.measured_traffic(20 | T, 8.0, str(p)) is None        # other launch shape
+    assert bench.measured_traffic(20, 16.0, str(p)) is None            # one-step variant
+    assert bench.measured_traffic(130 | T, 16.0, str(p)) is None       # not measured
+    p.write_text(text.replace(h, "0" * 16))
+    assert bench.measured_traffic(20 | T, 16.0, str(p)) is None        # kernels changed
+    assert bench.measured_traffic(20 | T, 16.0, str(tmp_path / "missing.md")) is None
+
+
+def test_committed_summary_parses():
+    v = bench.measured_traffic(20 | bench.TWO_STEP, 16.0)
+    assert v is None or v > 0
+    assert os.path.exists(bench.TRAFFIC_FILE)
