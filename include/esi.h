@@ -220,6 +220,19 @@ esi_status_t esi_grad_velocity(esi_plan_t plan, const float* vel, const float* g
 esi_status_t esi_plan_set_time_block(esi_plan_t plan, int32_t steps);
 
 /*
+ * CG iterations (Algorithm 1) replayed from captured HIP graphs.  With
+ * enable != 0, esi_cg_solve runs iteration 0 directly and captures iterations
+ * 1 and 2 once (one graph per parity of the iteration index, since the
+ * direction and N p buffers alternate); later iterations and later solves with
+ * the same shots, buffers, iteration limit and tolerance replay them.  The
+ * stopping test, the residual history and the retirement of converged shots
+ * run on the device, so the host only polls one counter per iteration.
+ * Results are identical bit for bit to enable = 0.  The plan owns a stream
+ * for capture and replay, ordered after its own stream by events.
+ */
+esi_status_t esi_plan_set_cg_graph(esi_plan_t plan, int32_t enable);
+
+/*
  * Kernel timing (the tracing facility of the library).  With profiling on,
  * every time loop of a call is bracketed by a pair of hipEvents on the plan's
  * stream; esi_plan_profile_read waits for them and reports, per time-step

@@ -296,6 +296,123 @@ extern "C" esi_status_t esi_normal_apply(esi_plan_t plan, int32_t shot0, int32_t
     return ESI_OK;
 }
 
+namespace esi {
+namespace {
+
+// Buffers and scalars of one CG solve (Algorithm 1, one system per shot).
+struct CgState {
+    int shot0, ns, max_iter;
+    double rtol;
+    int64_t len;
+    const TileLists* L;
+    float *x, *r, *p, *Ap;
+    double *rr, *pAp, *alpha, *beta, *rr_new, *rr0;
+    int *active, *finish, *iters, *status, *ctl;
+    double* hist;
+};
+
+// Enqueue iteration k (kernels only: no host decision, no allocation, so it
+// can be captured).  k = 0 applies N to p_0 = r_0; later iterations form
+// p_k = r_k + beta p_{k-1} and x_k = x_{k-1} + alpha p_{k-1} inside the forward
+// pass, writing p_k into the buffer that held N p_{k-1}, and N p_k over p_{k-1}.
+// The caller swaps p and Ap after every iteration k >= 1.
+esi_status_t cg_iteration(Plan* P, const CgState& c, int k, const float* p, float* Ap) {
+    const float* dir = p;
+    if (k == 0) {
+        ESI_TRY(do_normal(P, c.shot0, c.ns, p, Ap, c.L, c.active, false, nullptr, c.r, c.x,
+                          c.alpha, c.beta));
+    } else {
+        ESI_TRY(do_normal(P, c.shot0, c.ns, p, const_cast<float*>(p), c.L, c.active, true, Ap,
+                          c.r, c.x, c.alpha, c.beta));
+        dir = Ap;                        // p_k lives in the old N p buffer
+        Ap = const_cast<float*>(p);      // N p_k over p_{k-1}
+    }
+    ESI_TRY(launch_reduce_parts(P, P->part, P->part_stride, c.ns, c.pAp));
+    ESI_TRY(launch_cg_alpha(P, c.rr, c.pAp, c.alpha, c.ns));
+    ESI_TRY(launch_r_update(P, c.r, Ap, c.alpha, c.active, c.ns, c.len, c.rr_new));
+    ESI_TRY(launch_cg_control(P, c.rr0, c.rr_new, c.pAp, c.active, c.finish, c.iters, c.status,
+                              c.hist, c.max_iter + 1, c.ctl, c.rtol, c.max_iter, c.ns));
+    ESI_TRY(launch_cg_beta(P, c.rr_new, c.rr, c.beta, c.ns));
+    // shots leaving now take their last update x_{k+1} = x_k + alpha_k p_k
+    return launch_axpy_flag(P, c.x, dir, c.alpha, c.finish, 1, c.ns, c.len);
+}
+
+// Everything a captured iteration depends on besides its parity.
+std::vector<uintptr_t> cg_graph_key(Plan* P, const CgState& c) {
+    return {(uintptr_t)c.shot0, (uintptr_t)c.ns, (uintptr_t)c.max_iter,
+            (uintptr_t)std::llround(c.rtol * 1e18), (uintptr_t)c.L, (uintptr_t)c.x,
+            (uintptr_t)c.r, (uintptr_t)c.hist, (uintptr_t)P->ring, (uintptr_t)P->dscr,
+            (uintptr_t)P->part, (uintptr_t)P->time_block, (uintptr_t)P->part_stride};
+}
+
+void cg_graph_drop(Plan* P) {
+    for (int i = 0; i < 2; ++i) {
+        if (P->cg_exec[i]) hipGraphExecDestroy(P->cg_exec[i]);
+        if (P->cg_g[i]) hipGraphDestroy(P->cg_g[i]);
+        P->cg_exec[i] = nullptr;
+        P->cg_g[i] = nullptr;
+    }
+    P->cg_key.clear();
+}
+
+// Capture iteration k (parity k & 1, k >= 1) on the plan's capture stream.
+esi_status_t cg_graph_capture(Plan* P, const CgState& c, int k, const float* p, float* Ap) {
+    const int i = k & 1;
+    hipStream_t user = P->stream;
+    const bool prof = P->prof_on;
+    P->stream = P->cap_stream;
+    P->prof_on = false;
+    ESI_HIP_TRY(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+    esi_status_t st = cg_iteration(P, c, k, p, Ap);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(P->cap_stream, &g);
+    P->stream = user;
+    P->prof_on = prof;
+    if (st != ESI_OK) {
+        if (g) hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(ESI_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    P->cg_g[i] = g;
+    e = hipGraphInstantiate(&P->cg_exec[i], g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        P->cg_exec[i] = nullptr;
+        return fail(ESI_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    return ESI_OK;
+}
+
+// Replay a captured iteration after the work already queued on the plan's
+// stream, and make later work on that stream wait for it.
+esi_status_t cg_graph_launch(Plan* P, int i) {
+    ESI_HIP_TRY(hipEventRecord(P->cap_ev[0], P->stream));
+    ESI_HIP_TRY(hipStreamWaitEvent(P->cap_stream, P->cap_ev[0], 0));
+    ESI_HIP_TRY(hipGraphLaunch(P->cg_exec[i], P->cap_stream));
+    ESI_HIP_TRY(hipEventRecord(P->cap_ev[1], P->cap_stream));
+    ESI_HIP_TRY(hipStreamWaitEvent(P->stream, P->cap_ev[1], 0));
+    return ESI_OK;
+}
+
+}  // namespace
+}  // namespace esi
+
+extern "C" esi_status_t esi_plan_set_cg_graph(esi_plan_t plan, int32_t enable) {
+    set_error("");
+    if (!plan) return fail(ESI_ERR_ARG, "null plan");
+    Plan* P = (Plan*)plan;
+    if (enable && !P->cap_stream) {
+        ESI_HIP_TRY(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+        ESI_HIP_TRY(hipEventCreateWithFlags(&P->cap_ev[0], hipEventDisableTiming));
+        ESI_HIP_TRY(hipEventCreateWithFlags(&P->cap_ev[1], hipEventDisableTiming));
+    }
+    if (!enable) {
+        if (P->cap_stream) ESI_HIP_TRY(hipStreamSynchronize(P->cap_stream));
+        cg_graph_drop(P);
+    }
+    P->cg_graph = enable != 0;
+    return ESI_OK;
+}
+
 extern "C" esi_status_t esi_cg_solve(esi_plan_t plan, int32_t shot0, int32_t ns,
                                      const float* d_obs, float* x, float* work, int32_t max_iter,
                                      double rtol, esi_cg_report_t* rep) {
@@ -306,109 +423,86 @@ extern "C" esi_status_t esi_cg_solve(esi_plan_t plan, int32_t shot0, int32_t ns,
     if (!x || !work || (!d_obs && data_len(P, shot0, ns) > 0)) return fail(ESI_ERR_ARG, "null pointer");
     if (max_iter < 1) return fail(ESI_ERR_ARG, "max_iter must be >= 1");
     if (!(rtol >= 0)) return fail(ESI_ERR_ARG, "rtol must be >= 0");
-    TileLists* L;
-    ESI_TRY(lists_for(P, &L));
-    const int64_t len = (int64_t)P->nt * P->nphys;
-    // the direction and N p buffers trade places every iteration: the forward
-    // pass writes p_{k} into the buffer that held N p_{k-1}, and the adjoint
-    // pass writes N p_k over p_{k-1}
-    float* r = work;
-    float* p = work + (int64_t)ns * len;
-    float* Ap = work + 2 * (int64_t)ns * len;
     if (P->nshots < ns) return fail(ESI_ERR_ARG, "internal: scalar space");
-    double* rr = P->scal;
-    double* pAp = P->scal + P->nshots;
-    double* alpha = P->scal + 2 * P->nshots;
-    double* beta = P->scal + 3 * P->nshots;
-    double* rr_new = P->scal + 4 * P->nshots;
-    int* active = P->flags;
-    int* finish = P->flags + P->nshots;
+    CgState c;
+    ESI_TRY(lists_for(P, const_cast<TileLists**>(&c.L)));
+    c.shot0 = shot0; c.ns = ns; c.max_iter = max_iter; c.rtol = rtol;
+    c.len = (int64_t)P->nt * P->nphys;
+    c.x = x;
+    c.r = work;
+    c.p = work + (int64_t)ns * c.len;
+    c.Ap = work + 2 * (int64_t)ns * c.len;
+    c.rr = P->scal; c.pAp = P->scal + P->nshots; c.alpha = P->scal + 2 * P->nshots;
+    c.beta = P->scal + 3 * P->nshots; c.rr_new = P->scal + 4 * P->nshots;
+    c.rr0 = P->scal + 5 * P->nshots;
+    c.active = P->flags; c.finish = P->flags + P->nshots;
+    c.iters = P->cgi; c.status = P->cgi + P->nshots; c.ctl = P->cgi + 2 * P->nshots;
+    ESI_TRY(grow_t(&P->cg_hist, &P->cg_hist_cap, (int64_t)ns * (max_iter + 1), P->stream));
+    c.hist = P->cg_hist;
 
     // b = S^T d (adjoint modelling, Sec. 3); r_0 = b, p_0 = r_0, x_0 = 0
     ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
     {
-        StepArgs a = base_args(P, L, shot0, ns);
+        StepArgs a = base_args(P, c.L, shot0, ns);
         a.inj_data = d_obs;
-        a.dout = r;
+        a.dout = c.r;
         int cs = 0;
         ESI_TRY(adjoint_loop(P, a, F_INJ | F_OUT, P->ring, &cs, 0, P->nt));
     }
-    ESI_TRY(launch_copy(P, p, r, ns * len));
-    ESI_TRY(launch_fill(P, x, ns * len, 0.f));
-    ESI_TRY(launch_dot(P, r, r, ns, len, rr));
-
-    std::vector<double> h_rr0(ns), h_rr(ns), h_pAp(ns);
-    std::vector<int> h_active(ns, 1), h_finish(ns, 0), h_iters(ns, 0);
-    ESI_HIP_TRY(hipMemcpyAsync(h_rr0.data(), rr, ns * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+    ESI_TRY(launch_copy(P, c.p, c.r, ns * c.len));
+    ESI_TRY(launch_fill(P, x, ns * c.len, 0.f));
+    ESI_TRY(launch_dot(P, c.r, c.r, ns, c.len, c.rr));
+    ESI_HIP_TRY(hipMemcpyAsync(c.rr0, c.rr, ns * sizeof(double), hipMemcpyDeviceToDevice, P->stream));
+    ESI_TRY(launch_cg_init(P, c.rr0, c.active, c.finish, c.iters, c.status, c.hist, max_iter + 1,
+                           c.ctl, ns));
+    ESI_HIP_TRY(hipMemcpyAsync(P->h_ctl, c.ctl, 2 * sizeof(int), hipMemcpyDeviceToHost, P->stream));
     ESI_HIP_TRY(hipStreamSynchronize(P->stream));
-    if (rep && rep->res_hist)
-        for (int s = 0; s < ns; ++s) {
-            for (int k = 0; k <= max_iter; ++k) rep->res_hist[(int64_t)s * (max_iter + 1) + k] = -1.0;
-            rep->res_hist[(int64_t)s * (max_iter + 1)] = 1.0;
-        }
-    int nact = 0;
-    for (int s = 0; s < ns; ++s) {
-        if (!std::isfinite(h_rr0[s])) return fail(ESI_ERR_NONFINITE, "non-finite right-hand side");
-        if (h_rr0[s] == 0.0) h_active[s] = 0;   // b = 0: x = 0 is exact
-        nact += h_active[s];
-    }
-    ESI_HIP_TRY(hipMemcpyAsync(active, h_active.data(), ns * sizeof(int), hipMemcpyHostToDevice, P->stream));
-    ESI_HIP_TRY(hipMemcpyAsync(finish, h_finish.data(), ns * sizeof(int), hipMemcpyHostToDevice, P->stream));
 
+    std::vector<int> h_status(ns, 0);
+    auto read_status = [&]() -> esi_status_t {
+        ESI_HIP_TRY(hipMemcpyAsync(h_status.data(), c.status, ns * sizeof(int), hipMemcpyDeviceToHost,
+                                   P->stream));
+        ESI_HIP_TRY(hipStreamSynchronize(P->stream));
+        for (int s = 0; s < ns; ++s)
+            if (h_status[s] == ESI_ERR_NONFINITE) return fail(ESI_ERR_NONFINITE, "CG: non-finite scalar");
+        for (int s = 0; s < ns; ++s)
+            if (h_status[s] == ESI_ERR_BREAKDOWN) return fail(ESI_ERR_BREAKDOWN, "CG breakdown: p.Np <= 0");
+        return ESI_OK;
+    };
+    esi_status_t status = read_status();
+    if (status == ESI_ERR_NONFINITE) return fail(ESI_ERR_NONFINITE, "non-finite right-hand side");
+
+    const bool graph = P->cg_graph && P->cap_stream;
+    if (graph && P->cg_key != cg_graph_key(P, c)) cg_graph_drop(P);
+    float* p = c.p;
+    float* Ap = c.Ap;
     int done_iters = 0;
-    esi_status_t status = ESI_OK;
-    for (int k = 0; k < max_iter && nact > 0; ++k) {
-        // N p_k (the first direction is p_0 = r_0; later ones are formed in the
-        // forward pass: p_k = r_k + beta p_{k-1}, x_k = x_{k-1} + alpha p_{k-1})
-        if (k == 0) {
-            ESI_TRY(do_normal(P, shot0, ns, p, Ap, L, active, false, nullptr, r, x, alpha, beta));
+    for (int k = 0; k < max_iter && P->h_ctl[1] > 0; ++k) {
+        if (graph && k >= 1) {
+            const int i = k & 1;
+            if (!P->cg_exec[i]) {
+                ESI_TRY(cg_graph_capture(P, c, k, p, Ap));
+                P->cg_key = cg_graph_key(P, c);
+            }
+            ESI_TRY(cg_graph_launch(P, i));
         } else {
-            ESI_TRY(do_normal(P, shot0, ns, p, p, L, active, true, Ap, r, x, alpha, beta));
-            std::swap(p, Ap);
+            ESI_TRY(cg_iteration(P, c, k, p, Ap));
         }
-        ESI_TRY(launch_reduce_parts(P, P->part, P->part_stride, ns, pAp));
-        ESI_TRY(launch_cg_alpha(P, rr, pAp, alpha, ns));
-        ESI_TRY(launch_r_update(P, r, Ap, alpha, active, ns, len, rr_new));
-        ESI_HIP_TRY(hipMemcpyAsync(h_rr.data(), rr_new, ns * sizeof(double), hipMemcpyDeviceToHost, P->stream));
-        ESI_HIP_TRY(hipMemcpyAsync(h_pAp.data(), pAp, ns * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+        if (k >= 1) std::swap(p, Ap);
+        ESI_HIP_TRY(hipMemcpyAsync(P->h_ctl, c.ctl, 2 * sizeof(int), hipMemcpyDeviceToHost, P->stream));
         ESI_HIP_TRY(hipStreamSynchronize(P->stream));
         done_iters = k + 1;
-        int nfin = 0;
-        for (int s = 0; s < ns; ++s) {
-            h_finish[s] = 0;
-            if (!h_active[s]) continue;
-            h_iters[s] = k + 1;
-            if (!std::isfinite(h_pAp[s]) || !std::isfinite(h_rr[s])) status = ESI_ERR_NONFINITE;
-            else if (h_pAp[s] <= 0.0) status = ESI_ERR_BREAKDOWN;
-            const double rel = std::sqrt(h_rr[s] / h_rr0[s]);
-            if (rep && rep->res_hist) rep->res_hist[(int64_t)s * (max_iter + 1) + k + 1] = rel;
-            if (status != ESI_OK || rel < rtol || k == max_iter - 1) {
-                h_finish[s] = 1;
-                ++nfin;
-            }
-        }
-        if (status != ESI_OK) {
-            // keep x at the last finished iterate x_k: nothing more is applied
-            fail(status, status == ESI_ERR_BREAKDOWN ? "CG breakdown: p.Np <= 0"
-                                                     : "CG: non-finite scalar");
-            break;
-        }
-        ESI_TRY(launch_cg_beta(P, rr_new, rr, beta, ns));
-        if (nfin > 0) {
-            // shots leaving now take their last update x_{k+1} = x_k + alpha_k p_k here
-            ESI_HIP_TRY(hipMemcpyAsync(finish, h_finish.data(), ns * sizeof(int), hipMemcpyHostToDevice, P->stream));
-            ESI_TRY(launch_axpy_flag(P, x, p, alpha, finish, 1, ns, len));
-            for (int s = 0; s < ns; ++s)
-                if (h_finish[s]) { h_active[s] = 0; --nact; }
-            ESI_HIP_TRY(hipMemcpyAsync(active, h_active.data(), ns * sizeof(int), hipMemcpyHostToDevice, P->stream));
-            // the host vectors must outlive the queued copies
-            ESI_HIP_TRY(hipStreamSynchronize(P->stream));
-        }
     }
+    status = read_status();
     if (rep) {
         rep->iters = done_iters;
         if (rep->shot_iters)
-            for (int s = 0; s < ns; ++s) rep->shot_iters[s] = h_iters[s];
+            ESI_HIP_TRY(hipMemcpyAsync(rep->shot_iters, c.iters, ns * sizeof(int),
+                                       hipMemcpyDeviceToHost, P->stream));
+        if (rep->res_hist)
+            ESI_HIP_TRY(hipMemcpyAsync(rep->res_hist, c.hist, (size_t)ns * (max_iter + 1) * sizeof(double),
+                                       hipMemcpyDeviceToHost, P->stream));
+        ESI_HIP_TRY(hipStreamSynchronize(P->stream));
     }
     return status;
 }

@@ -111,7 +111,19 @@ struct Plan {
     int64_t store_cap = 0;
     float* ckpt = nullptr;               // checkpoints
     int64_t ckpt_cap = 0;
-    int* flags = nullptr;                // per-shot active flags [nshots]
+    int* flags = nullptr;                // per-shot active / finish flags [2][nshots]
+    int* cgi = nullptr;                  // CG bookkeeping: iters [nshots], status [nshots], ctl [2]
+    double* cg_hist = nullptr;           // residual history [nshots][max_iter + 1]
+    int64_t cg_hist_cap = 0;
+    int* h_ctl = nullptr;                // pinned host copy of ctl
+    // CG iterations captured as graphs (one per parity of the iteration index:
+    // the direction and N p buffers trade places every iteration)
+    bool cg_graph = false;
+    hipStream_t cap_stream = nullptr;    // capture and replay stream
+    hipEvent_t cap_ev[2] = {nullptr, nullptr};
+    hipGraph_t cg_g[2] = {nullptr, nullptr};
+    hipGraphExec_t cg_exec[2] = {nullptr, nullptr};
+    std::vector<uintptr_t> cg_key;       // what the captured graphs were built for
 
     std::vector<TileLists*> lists;       // one per tile shape used
     int time_block = 2;                  // steps per launch where allowed (1 or 2)
@@ -239,6 +251,11 @@ esi_status_t launch_reduce_parts(Plan* P, const double* part, int64_t n, int nsh
 esi_status_t launch_cg_alpha(Plan* P, const double* rr, const double* pAp, double* alpha,
                              int nshots);
 esi_status_t launch_cg_beta(Plan* P, const double* rr_new, double* rr, double* beta, int nshots);
+esi_status_t launch_cg_init(Plan* P, const double* rr0, int* active, int* finish, int* iters,
+                            int* status, double* hist, int hstride, int* ctl, int nshots);
+esi_status_t launch_cg_control(Plan* P, const double* rr0, const double* rr_new, const double* pAp,
+                               int* active, int* finish, int* iters, int* status, double* hist,
+                               int hstride, int* ctl, double rtol, int max_iter, int nshots);
 // grad[phys] += sum_s gacc[s][phys] (fixed order over s)
 esi_status_t launch_sum_shots(Plan* P, const float* gacc, int nshots, int64_t len, float sign,
                               float* grad);

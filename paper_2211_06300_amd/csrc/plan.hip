@@ -296,9 +296,16 @@ static void free_lists(TileLists* L) {
 
 static void free_plan(Plan* P) {
     for (TileLists* L : P->lists) free_lists(L);
+    for (int i = 0; i < 2; ++i) {
+        if (P->cg_exec[i]) hipGraphExecDestroy(P->cg_exec[i]);
+        if (P->cg_g[i]) hipGraphDestroy(P->cg_g[i]);
+        if (P->cap_ev[i]) hipEventDestroy(P->cap_ev[i]);
+    }
+    if (P->cap_stream) hipStreamDestroy(P->cap_stream);
+    if (P->h_ctl) hipHostFree(P->h_ctl);
     void* bufs[] = {P->d_src, P->d_rec_ptr, P->c2, P->kx, P->kz, P->ky, P->ring, P->ring2,
                     P->dscr, P->dscr2, P->part, P->scal, P->gshot, P->store, P->ckpt, P->flags,
-                    P->d_rec};
+                    P->d_rec, P->cgi, P->cg_hist};
     for (void* b : bufs)
         if (b) hipFree(b);
     delete P;
@@ -387,7 +394,9 @@ extern "C" esi_status_t esi_plan_create(esi_plan_t* plan, const esi_grid_t* g, c
             hipMalloc(&P->d_rec_ptr, (geo->nshots + 1) * 8) != hipSuccess ||
             hipMalloc(&P->d_rec, r3.size() * 4) != hipSuccess ||
             hipMalloc(&P->scal, (size_t)8 * geo->nshots * sizeof(double)) != hipSuccess ||
-            hipMalloc(&P->flags, (size_t)2 * geo->nshots * sizeof(int)) != hipSuccess)
+            hipMalloc(&P->flags, (size_t)2 * geo->nshots * sizeof(int)) != hipSuccess ||
+            hipMalloc(&P->cgi, ((size_t)2 * geo->nshots + 2) * sizeof(int)) != hipSuccess ||
+            hipHostMalloc((void**)&P->h_ctl, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess)
             return cleanup(fail(ESI_ERR_OOM, "plan allocation failed"));
         if (hipMemcpy(P->d_src, s3.data(), s3.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(P->d_rec_ptr, geo->rec_ptr, (geo->nshots + 1) * 8, hipMemcpyHostToDevice) != hipSuccess ||

@@ -143,6 +143,76 @@ __global__ void k_cg_beta(const double* rr_new, double* rr, double* beta, int n)
     }
 }
 
+// Device-side bookkeeping of Algorithm 1's stopping test, so that an iteration
+// needs no host decision and can be replayed from a captured graph.
+// ctl[0] = iterations done, ctl[1] = shots still iterating.  One workgroup.
+__global__ void k_cg_init(const double* __restrict__ rr0, int* __restrict__ active,
+                          int* __restrict__ finish, int* __restrict__ iters,
+                          int* __restrict__ status, double* __restrict__ hist, int hstride,
+                          int* __restrict__ ctl, int n) {
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    for (int s = threadIdx.x; s < n; s += blockDim.x) {
+        const double v = rr0[s];
+        const bool ok = isfinite(v);
+        const int a = (ok && v > 0.0) ? 1 : 0;   // b = 0: x = 0 is exact
+        active[s] = a;
+        finish[s] = 0;
+        iters[s] = 0;
+        status[s] = ok ? 0 : (int)ESI_ERR_NONFINITE;
+        hist[(int64_t)s * hstride] = 1.0;
+        for (int k = 1; k < hstride; ++k) hist[(int64_t)s * hstride + k] = -1.0;
+        if (a) atomicAdd(&cnt, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ctl[0] = 0;
+        ctl[1] = cnt;
+    }
+}
+
+// After iteration k (= ctl[0]) of every active shot: record ||r_{k+1}|| / ||r_0||,
+// flag shots that converged or reached max_iter (finish = 1: they take their
+// last update x += alpha p) or broke down (finish = 2: x stays at x_k), and
+// retire them.
+__global__ void k_cg_control(const double* __restrict__ rr0, const double* __restrict__ rr_new,
+                             const double* __restrict__ pAp, int* __restrict__ active,
+                             int* __restrict__ finish, int* __restrict__ iters,
+                             int* __restrict__ status, double* __restrict__ hist, int hstride,
+                             int* __restrict__ ctl, double rtol, int max_iter, int n) {
+    __shared__ int cnt;
+    const int k = ctl[0];
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    for (int s = threadIdx.x; s < n; s += blockDim.x) {
+        int f = 0;
+        if (active[s]) {
+            iters[s] = k + 1;
+            const double a = pAp[s], b = rr_new[s];
+            const double rel = sqrt(b / rr0[s]);
+            hist[(int64_t)s * hstride + k + 1] = rel;
+            if (!isfinite(a) || !isfinite(b)) {
+                status[s] = (int)ESI_ERR_NONFINITE;
+                f = 2;
+            } else if (a <= 0.0) {
+                status[s] = (int)ESI_ERR_BREAKDOWN;
+                f = 2;
+            } else if (rel < rtol || k == max_iter - 1) {
+                f = 1;
+            }
+            if (f) active[s] = 0;
+            else atomicAdd(&cnt, 1);
+        }
+        finish[s] = f;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ctl[0] = k + 1;
+        ctl[1] = cnt;
+    }
+}
+
 __global__ void k_sum_shots(const float* __restrict__ g, int nshots, int64_t len, float sign,
                             float* __restrict__ out) {
     for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < len; i += (int64_t)gridDim.x * NT) {
@@ -271,6 +341,23 @@ esi_status_t launch_cg_alpha(Plan* P, const double* rr, const double* pAp, doubl
 esi_status_t launch_cg_beta(Plan* P, const double* rr_new, double* rr, double* beta, int nshots) {
     hipLaunchKernelGGL(k_cg_beta, dim3((nshots + 63) / 64), dim3(64), 0, P->stream, rr_new, rr, beta,
                        nshots);
+    ESI_HIP_TRY(hipGetLastError());
+    return ESI_OK;
+}
+
+esi_status_t launch_cg_init(Plan* P, const double* rr0, int* active, int* finish, int* iters,
+                            int* status, double* hist, int hstride, int* ctl, int nshots) {
+    hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(256), 0, P->stream, rr0, active, finish, iters,
+                       status, hist, hstride, ctl, nshots);
+    ESI_HIP_TRY(hipGetLastError());
+    return ESI_OK;
+}
+
+esi_status_t launch_cg_control(Plan* P, const double* rr0, const double* rr_new, const double* pAp,
+                               int* active, int* finish, int* iters, int* status, double* hist,
+                               int hstride, int* ctl, double rtol, int max_iter, int nshots) {
+    hipLaunchKernelGGL(k_cg_control, dim3(1), dim3(256), 0, P->stream, rr0, rr_new, pAp, active,
+                       finish, iters, status, hist, hstride, ctl, rtol, max_iter, nshots);
     ESI_HIP_TRY(hipGetLastError());
     return ESI_OK;
 }

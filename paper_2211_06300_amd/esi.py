@@ -48,7 +48,7 @@ _lib = None
 EXPORTS = ["esi_plan_create", "esi_plan_set_model", "esi_plan_destroy", "esi_last_error",
            "esi_forward", "esi_adjoint", "esi_normal_apply", "esi_cg_solve", "esi_gradient",
            "esi_plan_profile", "esi_plan_profile_read", "esi_plan_set_time_block",
-           "esi_forward_ckpt", "esi_grad_velocity"]
+           "esi_forward_ckpt", "esi_grad_velocity", "esi_plan_set_cg_graph"]
 # time-step kernel variants (bit set of fused work), as in include/esi.h
 K_FLAGS = {1: "SRC_POINT", 2: "SRC_DENSE", 4: "CG_FUSE", 8: "INJ", 16: "GATHER", 32: "OUT",
            64: "NORMAL", 128: "PENALTY", 256: "STORE", 512: "CORR", 1024: "SRC_REC",
@@ -77,6 +77,7 @@ def load_library(path: str = LIB_PATH):
     L.esi_gradient.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp, vp, i32]
     L.esi_plan_profile.argtypes = [vp, i32]
     L.esi_plan_set_time_block.argtypes = [vp, i32]
+    L.esi_plan_set_cg_graph.argtypes = [vp, i32]
     L.esi_forward_ckpt.argtypes = [vp, i32, i32, i32, vp, vp, i32]
     L.esi_grad_velocity.argtypes = [vp, vp, vp, vp]
     L.esi_plan_profile_read.argtypes = [vp, i32, vp, vp, vp, vp, vp]
@@ -183,6 +184,9 @@ class Plan:
     # -- calls ------------------------------------------------------------------
     def set_time_block(self, steps: int):
         _check(self._lib.esi_plan_set_time_block(self._h, int(steps)))
+
+    def set_cg_graph(self, enable: bool):
+        _check(self._lib.esi_plan_set_cg_graph(self._h, int(bool(enable))))
 
     def set_model(self, vel: torch.Tensor):
         _check(self._lib.esi_plan_set_model(self._h, _f32(vel, self.phys_shape, "vel")))

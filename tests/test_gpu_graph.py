@@ -1,0 +1,103 @@
+"""CG iterations replayed from captured HIP graphs against the same solve run
+eagerly: identical bits in x, the residual history and the iteration counts,
+on every replay, with eager work and synchronizations between replays."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import core
+from paper_2211_06300_amd import inputs
+from tests.test_gpu_parity import _oracle_model, _plan, _ragged_cfg
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def esi():
+    from paper_2211_06300_amd import esi as _esi
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    _esi.load_library()
+    return _esi
+
+
+def _d_obs(cfg):
+    g, m = _oracle_model(cfg)
+    d = [core.forward(m, cfg.wavelet.astype(np.float64), cfg.shot_rec(s), src_pos=cfg.src[s])
+         .astype(np.float32) for s in range(cfg.nshots)]
+    return torch.from_numpy(np.concatenate([x.ravel() for x in d])).to(DEV)
+
+
+@pytest.mark.parametrize("time_block", [1, 2])
+def test_cg_graph_equals_eager(esi, time_block):
+    cfg = _ragged_cfg(nt=50)
+    cfg.v_start = (cfg.v_true * 1.03).astype(np.float32)
+    d = _d_obs(cfg)
+    plan = _plan(esi, cfg, v=cfg.v_start)
+    plan.set_time_block(time_block)
+    x0, rep0 = plan.cg_solve(d, max_iter=7, rtol=0.0)
+    x0 = x0.clone()
+    plan.set_cg_graph(True)
+    x = plan.new_vec(cfg.nshots)
+    work = torch.empty((3, *plan.vec_shape(cfg.nshots)), dtype=torch.float32, device=DEV)
+    for rep_i in range(3):
+        x.fill_(123.0)                                   # eager work between replays
+        _, rep = plan.cg_solve(d, max_iter=7, rtol=0.0, x=x, work=work)
+        torch.cuda.synchronize()
+        assert torch.equal(x, x0), rep_i
+        assert rep["iters"] == rep0["iters"]
+        np.testing.assert_array_equal(rep["shot_iters"], rep0["shot_iters"])
+        np.testing.assert_array_equal(rep["res_hist"], rep0["res_hist"])
+        plan.normal_apply(work[1])                       # unrelated eager call in between
+    plan.set_cg_graph(False)
+    x2, _ = plan.cg_solve(d, max_iter=7, rtol=0.0)
+    assert torch.equal(x2, x0)
+    plan.close()
+
+
+def test_cg_graph_early_exit(esi):
+    """Shots retire on the device at different iterations; replays after every
+    shot has left are no-ops."""
+    cfg = _ragged_cfg(nshots=2, nt=40)
+    d = _d_obs(cfg)
+    plan = _plan(esi, cfg)
+    x0, rep0 = plan.cg_solve(d, max_iter=30, rtol=0.2)
+    x0 = x0.clone()
+    plan.set_cg_graph(True)
+    for _ in range(2):
+        x, rep = plan.cg_solve(d, max_iter=30, rtol=0.2)
+        assert torch.equal(x, x0)
+        np.testing.assert_array_equal(rep["shot_iters"], rep0["shot_iters"])
+        np.testing.assert_array_equal(rep["res_hist"], rep0["res_hist"])
+    g, m = _oracle_model(cfg)
+    for s in range(2):
+        ref = core.esi_cg(m, cfg.src[s], cfg.shot_rec(s),
+                          d.cpu().numpy()[int(cfg.nt * cfg.rec_ptr[s]):int(cfg.nt * cfg.rec_ptr[s + 1])]
+                          .reshape(cfg.nt, -1).astype(np.float64), cfg.beta, 30, rtol=0.2)
+        assert rep["shot_iters"][s] == ref.iters
+    plan.close()
+
+
+def test_cg_graph_small_config_timing(esi):
+    """The small parity workload (201 x 201, 500 steps, 5 iterations), where
+    launches are short: graph replay matches eager bit for bit; both timings
+    are printed."""
+    import time
+    cfg = inputs.cfg_small()
+    d = _d_obs(cfg)
+    plan = _plan(esi, cfg)
+    out = {}
+    for mode in (False, True, True):
+        plan.set_cg_graph(mode)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x, rep = plan.cg_solve(d, max_iter=5)
+        torch.cuda.synchronize()
+        out.setdefault(mode, []).append((time.perf_counter() - t, x.clone()))
+    print(f"eager {out[False][0][0] * 1e3:.1f} ms, graph first {out[True][0][0] * 1e3:.1f} ms "
+          f"(captures), graph replay {out[True][1][0] * 1e3:.1f} ms")
+    assert torch.equal(out[True][0][1], out[False][0][1])
+    assert torch.equal(out[True][1][1], out[False][0][1])
+    plan.close()
