@@ -357,6 +357,63 @@ def cg(apply_N, b: np.ndarray, max_iter: int, rtol: float = 0.0,
     return CGResult(x, k + 1, hist, alphas, betas, res)
 
 
+@dataclass
+class FPCGResult:
+    x: np.ndarray
+    iters: int
+    res_hist: list          # ||r_k|| / ||r_0||
+    fallback_at: int | None  # iteration after which plain CG took over, or None
+
+
+def fpcg(apply_N, b: np.ndarray, precond, max_iter: int, rtol: float = 0.0,
+         stall: float = 0.99) -> FPCGResult:
+    """Flexible CG with truncation 1 (Notay 2000, FCG(1)) for N x = b.
+
+    x_0 = 0, r_0 = b, z_0 = M(r_0), p_0 = z_0; per iteration alpha = p.r / p.Np,
+    x += alpha p, r -= alpha Np; leave when ||r|| < rtol ||r_0|| or at
+    max_iter; z = M(r), beta = -z.Np / p.Np, p = z + beta p.  M may change from
+    one call to the next.
+
+    Fallback to plain CG (M = I from then on, direction restarted at p = r,
+    the recursively updated residual kept) when z.r <= 0, when z or z.r is not
+    finite, or when ||r_{k+1}|| > stall * ||r_{k-2}|| (no progress over three
+    iterations).  With M = I the iteration is CG with the Hestenes-Stiefel
+    form of beta, equal to Algorithm 1 in exact arithmetic.
+    """
+    x = np.zeros_like(b)
+    r = b.copy()
+    nb = np.sqrt(dot(b, b))
+    hist = [1.0]
+    fallback_at = None
+    z = precond(r)
+    zr = dot(z, r)
+    if not (np.all(np.isfinite(z)) and np.isfinite(zr) and zr > 0):
+        fallback_at, z = 0, r
+    p = z.copy()
+    k = 0
+    for k in range(max_iter):
+        Ap = apply_N(p)
+        pAp = dot(p, Ap)
+        alpha = dot(p, r) / pAp
+        x = x + alpha * p
+        r = r - alpha * Ap
+        hist.append(np.sqrt(dot(r, r)) / nb if nb > 0 else 0.0)
+        if hist[-1] < rtol or k == max_iter - 1:
+            break
+        if fallback_at is None:
+            z = precond(r)
+            zr = dot(z, r)
+            stalled = k >= 2 and hist[k + 1] > stall * hist[k - 2]
+            if stalled or not (np.all(np.isfinite(z)) and np.isfinite(zr) and zr > 0):
+                fallback_at = k + 1
+                p = r.copy()
+                continue
+        else:
+            z = r
+        p = z - (dot(z, Ap) / pAp) * p
+    return FPCGResult(x, k + 1, hist, fallback_at)
+
+
 def esi_cg(m: Model, src_pos, rec, d_obs, beta: float, max_iter: int, rtol: float = 0.0,
            eps: float = 1.0) -> CGResult:
     """Solve (S^T S + beta B^T B) q = S^T d (eq. (normalewi)) for one shot by CG."""

@@ -202,3 +202,15 @@ def crop3d(cfg: Config, n: int, nt: int, rec_n: int) -> Config:
     ptr, rr = _csr([rec1])
     return Config(f"crop3d-{n}^3", 3, n, n, n, cfg.dx, cfg.dt, nt, min(cfg.nb, 12), cfg.freq,
                   cfg.beta, 0, v, v.copy(), src, ptr, rr, ricker_samples(nt, cfg.dt, cfg.freq))
+
+
+def he_init(segments, seed: int) -> np.ndarray:
+    """Seeded initial network parameters: for each (n_weights, fan_in, n_bias)
+    segment, n_weights draws of N(0, 2 / fan_in) followed by n_bias zeros
+    (He et al. 2015); float32."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for n, fan, nb in segments:
+        parts.append(rng.standard_normal(n) * np.sqrt(2.0 / fan))
+        parts.append(np.zeros(nb))
+    return np.concatenate(parts).astype(np.float32)
