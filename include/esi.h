@@ -59,6 +59,7 @@ extern "C" {
 #endif
 
 typedef struct esi_plan_s* esi_plan_t;
+typedef struct esi_unet_s* esi_unet_t;
 
 typedef enum {
     ESI_OK = 0,
@@ -254,6 +255,63 @@ esi_status_t esi_plan_profile(esi_plan_t plan, int32_t enable);
  * shot_launches: host int64 [cap], launches weighted by the shots each covered. */
 esi_status_t esi_plan_profile_read(esi_plan_t plan, int32_t cap, int32_t* count, uint32_t* flags,
                                    int64_t* launches, int64_t* shot_launches, double* ms);
+
+/* ------------------------------------------------------------------------
+ * Learned preconditioner network.  The paper leaves preconditioning of its CG
+ * open (Sec. 4.2; Sec. 6 calls for a preconditioner that cuts the number of
+ * inner iterations); this library's is a four-level U-Net whose output o(x)
+ * scales the residual cell by cell, z = exp(o) r, recomputed every iteration
+ * of a flexible CG (esi_fpcg_solve).
+ *
+ * Architecture (channels 16/32/64/128, 3x3 convolutions with zero padding,
+ * ReLU, 2x2 average pooling, 2x2 stride-2 transposed convolutions, skip
+ * concatenation [upsampled, skip], 1x1 output):
+ *   c1a 3->16, c1b 16->16 | pool | c2a 16->32, c2b 32->32 | pool |
+ *   c3a 32->64, c3b 64->64 | pool | c4a 64->128, c4b 128->128 |
+ *   u3 128->64, d3a 128->64, d3b 64->64 | u2 64->32, d2a 64->32, d2b 32->32 |
+ *   u1 32->16, d1a 32->16, d1b 16->16 | out 16->1.
+ * Flat float32 parameter vector, layers in that order, each layer's weights
+ * then its bias; weight layouts conv3x3 [co][ci][3][3], convT [ci][co][2][2],
+ * out [1][16].  482033 parameters.
+ * Arithmetic: weights and activations bfloat16 (round to nearest even), bias,
+ * accumulation, the output o and all parameter gradients float32; gradients
+ * of activations are bfloat16.  Adam keeps float32 master parameters.
+ * The network runs on the stream given at creation; calls are asynchronous
+ * unless they return a host value.  A network handle is not thread-safe.
+ * ------------------------------------------------------------------------ */
+
+/* Number of parameters of the network (482033). */
+int64_t esi_unet_num_params(void);
+
+/* Network for images of H x W pixels (multiples of 8) and batches of up to
+ * max_batch images; activation memory about 700 B per pixel per image.
+ * Parameters start at zero: set them with esi_unet_set_params.
+ * ESI_ERR_SHAPE for other sizes, ESI_ERR_OOM when allocation fails. */
+esi_status_t esi_unet_create(esi_unet_t* net, int32_t H, int32_t W, int32_t max_batch, void* hip_stream);
+esi_status_t esi_unet_destroy(esi_unet_t net);
+
+/* Copy the float32 parameters in (theta: host or device [P]) and clear the
+ * Adam moments; get copies them out.  Both synchronise the network's stream. */
+esi_status_t esi_unet_set_params(esi_unet_t net, const float* theta);
+esi_status_t esi_unet_get_params(esi_unet_t net, float* theta);
+
+/* o = Net(x) for `batch` images: x device [batch][3][H][W] float32 (NCHW),
+ * o device [batch][H][W] float32. */
+esi_status_t esi_unet_forward(esi_unet_t net, const float* x, float* o, int32_t batch);
+
+/* Loss of the scaling preconditioner and its gradient.  For each image s,
+ * with a = sum_t r^2 and c = sum_t r e (device [batch][H][W], zero on padding
+ * pixels), L_s = sum_x (a e^{2o} - 2 c e^{o}) / sum_x a, i.e. the squared
+ * error of exp(o) r against e up to a constant; L = mean_s L_s.  Writes
+ * dL/dtheta into grad (device [P], overwritten) and L into *loss (host, may
+ * be NULL; non-NULL synchronises). */
+esi_status_t esi_unet_loss_grad(esi_unet_t net, const float* x, const float* a, const float* c,
+                                int32_t batch, float* grad, double* loss);
+
+/* One Adam step (Kingma & Ba) on the master parameters with gradient grad
+ * (device [P]); step counts from 1. */
+esi_status_t esi_unet_adam(esi_unet_t net, const float* grad, float lr, float beta1, float beta2,
+                           float eps, int32_t step);
 
 #ifdef __cplusplus
 }

@@ -48,7 +48,9 @@ _lib = None
 EXPORTS = ["esi_plan_create", "esi_plan_set_model", "esi_plan_destroy", "esi_last_error",
            "esi_forward", "esi_adjoint", "esi_normal_apply", "esi_cg_solve", "esi_gradient",
            "esi_plan_profile", "esi_plan_profile_read", "esi_plan_set_time_block",
-           "esi_forward_ckpt", "esi_grad_velocity", "esi_plan_set_cg_graph"]
+           "esi_forward_ckpt", "esi_grad_velocity", "esi_plan_set_cg_graph",
+           "esi_unet_num_params", "esi_unet_create", "esi_unet_destroy", "esi_unet_set_params",
+           "esi_unet_get_params", "esi_unet_forward", "esi_unet_loss_grad", "esi_unet_adam"]
 # time-step kernel variants (bit set of fused work), as in include/esi.h
 K_FLAGS = {1: "SRC_POINT", 2: "SRC_DENSE", 4: "CG_FUSE", 8: "INJ", 16: "GATHER", 32: "OUT",
            64: "NORMAL", 128: "PENALTY", 256: "STORE", 512: "CORR", 1024: "SRC_REC",
@@ -81,9 +83,18 @@ def load_library(path: str = LIB_PATH):
     L.esi_forward_ckpt.argtypes = [vp, i32, i32, i32, vp, vp, i32]
     L.esi_grad_velocity.argtypes = [vp, vp, vp, vp]
     L.esi_plan_profile_read.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+    L.esi_unet_num_params.argtypes = []
+    L.esi_unet_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, vp]
+    L.esi_unet_destroy.argtypes = [vp]
+    L.esi_unet_set_params.argtypes = [vp, vp]
+    L.esi_unet_get_params.argtypes = [vp, vp]
+    L.esi_unet_forward.argtypes = [vp, vp, vp, i32]
+    L.esi_unet_loss_grad.argtypes = [vp, vp, vp, vp, i32, vp, ctypes.POINTER(dbl)]
+    L.esi_unet_adam.argtypes = [vp, vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, i32]
     for f in EXPORTS:
         if f != "esi_last_error":
             getattr(L, f).restype = ctypes.c_int
+    L.esi_unet_num_params.restype = i64
     if path == LIB_PATH:
         _lib = L
     return L
@@ -284,3 +295,59 @@ class Plan:
             out[name] = {"flags": int(fl[i]), "launches": int(la[i]), "shot_launches": int(sl[i]),
                          "ms": float(ms[i])}
         return out
+
+
+class Unet:
+    """The preconditioner network (``esi_unet_create``): images of H x W pixels
+    (multiples of 8), batches of up to ``max_batch``; parameters as a flat
+    float32 CUDA tensor in the layout of include/esi.h."""
+
+    def __init__(self, H: int, W: int, max_batch: int, device="cuda", stream=None):
+        self._lib = load_library()
+        self.H, self.W, self.max_batch = int(H), int(W), int(max_batch)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.P = int(self._lib.esi_unet_num_params())
+        h = ctypes.c_void_p()
+        _check(self._lib.esi_unet_create(ctypes.byref(h), self.H, self.W, self.max_batch,
+                                         ctypes.c_void_p(self.stream.cuda_stream)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(self._lib.esi_unet_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, theta: torch.Tensor):
+        _check(self._lib.esi_unet_set_params(self._h, _f32(theta, (self.P,), "theta")))
+
+    def get_params(self) -> torch.Tensor:
+        t = torch.empty(self.P, dtype=torch.float32, device=self.device)
+        _check(self._lib.esi_unet_get_params(self._h, _ptr(t)))
+        return t
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        b = int(x.shape[0])
+        o = torch.empty((b, self.H, self.W), dtype=torch.float32, device=self.device)
+        _check(self._lib.esi_unet_forward(self._h, _f32(x, (b, 3, self.H, self.W), "x"), _ptr(o), b))
+        return o
+
+    def loss_grad(self, x, a, c, grad=None):
+        b = int(x.shape[0])
+        grad = torch.empty(self.P, dtype=torch.float32, device=self.device) if grad is None else grad
+        loss = ctypes.c_double()
+        shp = (b, self.H, self.W)
+        _check(self._lib.esi_unet_loss_grad(self._h, _f32(x, (b, 3, self.H, self.W), "x"),
+                                            _f32(a, shp, "a"), _f32(c, shp, "c"), b,
+                                            _f32(grad, (self.P,), "grad"), ctypes.byref(loss)))
+        return grad, loss.value
+
+    def adam(self, grad, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
+        _check(self._lib.esi_unet_adam(self._h, _f32(grad, (self.P,), "grad"), float(lr), float(beta1),
+                                       float(beta2), float(eps), int(step)))

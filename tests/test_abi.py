@@ -22,7 +22,7 @@ def lib():
 
 def declared():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^(?:esi_status_t|const char\*)\s+(esi_\w+)\(", text, re.M)))
+    return sorted(set(re.findall(r"^(?:esi_status_t|const char\*|int64_t)\s+(esi_\w+)\(", text, re.M)))
 
 
 def test_header_declares_the_calls():
