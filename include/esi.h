@@ -148,6 +148,15 @@ typedef struct {
     int32_t* shot_iters; /* host [nshots] out, or NULL */
     double* res_hist;    /* host [nshots][max_iter+1] out, or NULL: ||r_k|| / ||r_0|| of
                             the recursively updated residual; unused entries set to -1 */
+    /* esi_fpcg_solve only (ignored by esi_cg_solve; set to NULL there): */
+    int32_t* shot_fallback; /* host [nshots] out, or NULL: iteration after which plain CG
+                               took over, -1 if it never did */
+    const float* stat_xref; /* device [nshots][nt][phys] reference solution, or NULL */
+    float* stat_out;        /* device [max_iter+1][nshots][2][phys], or NULL: for the iterate
+                               x_k and residual r_k of every iteration k reached, the cell maps
+                               a = sum_t r_k^2 and c = sum_t r_k (x_ref - x_k) (training pairs
+                               of the learned preconditioner); entries of iterations a shot did
+                               not reach are left untouched */
 } esi_cg_report_t;
 
 /*
@@ -255,6 +264,49 @@ esi_status_t esi_plan_profile(esi_plan_t plan, int32_t enable);
  * shot_launches: host int64 [cap], launches weighted by the shots each covered. */
 esi_status_t esi_plan_profile_read(esi_plan_t plan, int32_t cap, int32_t* count, uint32_t* flags,
                                    int64_t* launches, int64_t* shot_launches, double* ms);
+
+/*
+ * Flexible conjugate gradients with truncation 1 (FCG(1), Notay 2000) on
+ * eq. (normalewi), one system per shot, x_0 = 0 (2D plans).  The paper solves
+ * the normal equation with plain CG (Algorithm 1) and leaves preconditioning
+ * open (Sec. 4.2, Sec. 6); this call adds it.  Per iteration: z_k = M(r_k),
+ * alpha = p.r / p.Np, x += alpha p, r -= alpha Np, beta = -z.Np / p.Np,
+ * p = z + beta p.  The preconditioner scales the residual cell by cell,
+ * z = s r, with
+ *   net != NULL:   s = exp(Net(features)) recomputed every iteration from the
+ *                  residual's per-cell energy (see esi_precond_features); the
+ *                  network must take Hp x Wp images (nz, nx rounded up to
+ *                  multiples of 8) in batches of at least nshots;
+ *   scale != NULL: a fixed s, device [nshots][phys];
+ *   both NULL:     s = 1 (CG with beta in Hestenes-Stiefel form).
+ * A shot falls back to plain CG (s = 1 from then on, the direction restarted
+ * at p = r) when z.r <= 0 or is not finite, or when ||r_{k+1}|| > 0.99
+ * ||r_{k-2}||.  Stopping as esi_cg_solve: ||r_{k+1}|| < rtol ||r_0|| of the
+ * recursively updated residual, or max_iter.
+ *   d_obs, x, work, max_iter, rtol: as esi_cg_solve (work: 3 vectors).
+ *   rep: as esi_cg_solve, plus shot_fallback and the training maps
+ *        (stat_xref / stat_out) when given.
+ * Errors as esi_cg_solve; ESI_ERR_ARG for 3D plans or both net and scale,
+ * ESI_ERR_SHAPE for a network of the wrong size.
+ */
+esi_status_t esi_fpcg_solve(esi_plan_t plan, int32_t shot0, int32_t nshots, const float* d_obs,
+                            float* x, float* work, int32_t max_iter, double rtol, esi_unet_t net,
+                            const float* scale, esi_cg_report_t* rep);
+
+/*
+ * Network input of the preconditioner for `nshots` shots of a 2D plan, on
+ * images padded to Hp x Wp (multiples of 8, at least nz x nx; zero outside
+ * the grid): channel 0 = rms_t(r) / mean_x rms_t(r) with rms_t(r) = sqrt(a/nt),
+ * channel 1 = v / 3000 m/s, channel 2 = B / 100 (B = |x - x_s| / dx + eps, in
+ * cells).
+ *   a:    device [nshots][phys], a = sum_t r^2 of each shot's residual.
+ *   cmap: device [nshots][phys] or NULL (copied into cpad when given).
+ *   xin:  device [nshots][3][Hp][Wp] out; apad, cpad: device [nshots][Hp][Wp]
+ *         out or NULL (a and cmap zero-padded).
+ */
+esi_status_t esi_precond_features(esi_plan_t plan, int32_t shot0, int32_t nshots, const float* a,
+                                  const float* cmap, int32_t Hp, int32_t Wp, float* xin, float* apad,
+                                  float* cpad);
 
 /* ------------------------------------------------------------------------
  * Learned preconditioner network.  The paper leaves preconditioning of its CG

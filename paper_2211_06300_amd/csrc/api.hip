@@ -209,7 +209,7 @@ esi_status_t do_forward(Plan* P, int shot0, int ns, int kind, const float* src, 
 // Ap may be the p_old buffer (it is dead once the forward pass has run).
 esi_status_t do_normal(Plan* P, int shot0, int ns, const float* p, float* Ap, const TileLists* L,
                        const int* active, bool cg_fuse, float* pnew, const float* r, float* x,
-                       const double* alpha, const double* beta) {
+                       const double* alpha, const double* beta, const float* cg_s = nullptr) {
     const int64_t dl = data_len(P, shot0, ns);
     ESI_TRY(grow_t(&P->dscr, &P->dscr_cap, std::max<int64_t>(dl, 1), P->stream));
     ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
@@ -219,7 +219,8 @@ esi_status_t do_normal(Plan* P, int shot0, int ns, const float* p, float* Ap, co
     int cs = 0;
     if (cg_fuse) {
         a.cg_r = r; a.cg_p = p; a.cg_pn = pnew; a.cg_x = x; a.cg_alpha = alpha; a.cg_beta = beta;
-        ESI_TRY(forward_loop(P, a, F_CG_FUSE | F_GATHER, P->ring, &cs, 0, P->nt));
+        a.cg_s = cg_s;
+        ESI_TRY(forward_loop(P, a, F_CG_FUSE | F_GATHER | (cg_s ? F_SCALE : 0u), P->ring, &cs, 0, P->nt));
     } else {
         a.dsrc = p;
         ESI_TRY(forward_loop(P, a, F_SRC_DENSE | F_GATHER, P->ring, &cs, 0, P->nt));
@@ -505,6 +506,171 @@ extern "C" esi_status_t esi_cg_solve(esi_plan_t plan, int32_t shot0, int32_t ns,
         ESI_HIP_TRY(hipStreamSynchronize(P->stream));
     }
     return status;
+}
+
+extern "C" esi_status_t esi_fpcg_solve(esi_plan_t plan, int32_t shot0, int32_t ns,
+                                       const float* d_obs, float* x, float* work, int32_t max_iter,
+                                       double rtol, esi_unet_t net, const float* scale,
+                                       esi_cg_report_t* rep) {
+    set_error("");
+    if (!plan) return fail(ESI_ERR_ARG, "null plan");
+    Plan* P = (Plan*)plan;
+    ESI_TRY(check_shots(P, shot0, ns));
+    if (P->ndim != 2) return fail(ESI_ERR_ARG, "flexible CG runs on 2D plans");
+    if (!x || !work || (!d_obs && data_len(P, shot0, ns) > 0)) return fail(ESI_ERR_ARG, "null pointer");
+    if (max_iter < 1) return fail(ESI_ERR_ARG, "max_iter must be >= 1");
+    if (!(rtol >= 0)) return fail(ESI_ERR_ARG, "rtol must be >= 0");
+    if (net && scale) return fail(ESI_ERR_ARG, "give a network or a fixed scale, not both");
+    const int Hp = (P->nz + 7) / 8 * 8, Wp = (P->nx + 7) / 8 * 8;
+    if (net) {
+        int H, W, mb;
+        ESI_TRY(unet_dims(net, &H, &W, &mb));
+        if (H != Hp || W != Wp || mb < ns)
+            return fail(ESI_ERR_SHAPE, "network must take " + std::to_string(Hp) + " x " + std::to_string(Wp) +
+                                           " images and batches of " + std::to_string(ns) + " shots");
+    }
+    const bool stats = rep && rep->stat_out;
+    if (stats && !rep->stat_xref) return fail(ESI_ERR_ARG, "stat_out needs stat_xref");
+    CgState c;
+    ESI_TRY(lists_for(P, const_cast<TileLists**>(&c.L)));
+    c.shot0 = shot0; c.ns = ns; c.max_iter = max_iter; c.rtol = rtol;
+    c.len = (int64_t)P->nt * P->nphys;
+    c.x = x;
+    c.r = work;
+    c.p = work + (int64_t)ns * c.len;
+    c.Ap = work + 2 * (int64_t)ns * c.len;
+    c.rr = P->scal; c.pAp = P->scal + P->nshots; c.alpha = P->scal + 2 * P->nshots;
+    c.beta = P->scal + 3 * P->nshots; c.rr_new = P->scal + 4 * P->nshots;
+    c.rr0 = P->scal + 5 * P->nshots;
+    c.active = P->flags; c.finish = P->flags + P->nshots;
+    c.iters = P->cgi; c.status = P->cgi + P->nshots; c.ctl = P->cgi + 2 * P->nshots;
+    ESI_TRY(grow_t(&P->cg_hist, &P->cg_hist_cap, (int64_t)ns * (max_iter + 1), P->stream));
+    c.hist = P->cg_hist;
+    const int64_t cells = (int64_t)ns * P->nphys;
+    ESI_TRY(grow_t(&P->fcg_s, &P->fcg_s_cap, cells, P->stream));
+    ESI_TRY(grow_t(&P->fcg_a, &P->fcg_a_cap, cells, P->stream));
+    ESI_TRY(grow_t(&P->fcg_d, &P->fcg_d_cap, (int64_t)4 * ns, P->stream));
+    ESI_TRY(grow_t(&P->fcg_i, &P->fcg_i_cap, (int64_t)3 * ns, P->stream));
+    if (net) {
+        ESI_TRY(grow_t(&P->fcg_in, &P->fcg_in_cap, (int64_t)ns * 3 * Hp * Wp, P->stream));
+        ESI_TRY(grow_t(&P->fcg_o, &P->fcg_o_cap, (int64_t)ns * Hp * Wp, P->stream));
+    }
+    float* S = P->fcg_s;
+    float* en = P->fcg_a;
+    double* pr = P->fcg_d;
+    double* zAp = P->fcg_d + ns;
+    double* zr = P->fcg_d + 2 * ns;
+    double* fmean = P->fcg_d + 3 * ns;
+    int* mode = P->fcg_i;
+    int* restart = P->fcg_i + ns;
+    int* fallback = P->fcg_i + 2 * ns;
+    const float* o = net ? P->fcg_o : nullptr;
+    const double stall = 0.99;
+
+    // z = M(r) for the shots still iterating, k = the iteration count so far
+    auto precondition = [&](int k) -> esi_status_t {
+        ESI_TRY(launch_energy(P, c.r, c.active, en, ns));
+        if (net) {
+            ESI_TRY(launch_features(P, shot0, ns, en, nullptr, fmean, Hp, Wp, P->fcg_in, nullptr, nullptr));
+            ESI_TRY(unet_forward_on(net, P->stream, P->fcg_in, P->fcg_o, ns));
+        }
+        return launch_fcg_zr_check_scale(P, o, scale, en, c.active, mode, restart, fallback, k, Hp, Wp, zr, S, ns);
+    };
+
+    // b = S^T d; r_0 = b, x_0 = 0
+    ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
+    {
+        StepArgs a = base_args(P, c.L, shot0, ns);
+        a.inj_data = d_obs;
+        a.dout = c.r;
+        int cs = 0;
+        ESI_TRY(adjoint_loop(P, a, F_INJ | F_OUT, P->ring, &cs, 0, P->nt));
+    }
+    ESI_TRY(launch_fill(P, x, ns * c.len, 0.f));
+    ESI_TRY(launch_dot(P, c.r, c.r, ns, c.len, c.rr));
+    ESI_HIP_TRY(hipMemcpyAsync(c.rr0, c.rr, ns * sizeof(double), hipMemcpyDeviceToDevice, P->stream));
+    ESI_TRY(launch_cg_init(P, c.rr0, c.active, c.finish, c.iters, c.status, c.hist, max_iter + 1, c.ctl, ns));
+    ESI_TRY(launch_fcg_init(P, mode, restart, fallback, ns));
+    if (stats) ESI_TRY(launch_stats(P, c.r, x, nullptr, nullptr, rep->stat_xref, c.iters, 0, rep->stat_out, ns));
+    ESI_HIP_TRY(hipMemcpyAsync(P->h_ctl, c.ctl, 2 * sizeof(int), hipMemcpyDeviceToHost, P->stream));
+    ESI_HIP_TRY(hipStreamSynchronize(P->stream));
+    std::vector<int> h_status(ns, 0);
+    ESI_HIP_TRY(hipMemcpy(h_status.data(), c.status, ns * sizeof(int), hipMemcpyDeviceToHost));
+    for (int s = 0; s < ns; ++s)
+        if (h_status[s] == ESI_ERR_NONFINITE) return fail(ESI_ERR_NONFINITE, "non-finite right-hand side");
+
+    // p_0 = z_0 = M(r_0)
+    ESI_TRY(precondition(0));
+    ESI_TRY(launch_scale_vec(P, c.p, c.r, S, ns));
+    float* p = c.p;
+    float* Ap = c.Ap;
+    int done_iters = 0;
+    const int64_t stat_stride = (int64_t)ns * 2 * P->nphys;
+    for (int k = 0; k < max_iter && P->h_ctl[1] > 0; ++k) {
+        // N p_k; from k = 1 on the forward pass forms p_k = S r_k + beta p_{k-1}
+        // and x_k = x_{k-1} + alpha p_{k-1} (into the old N p buffer)
+        float* dir = p;
+        float* Apk = Ap;
+        if (k == 0) {
+            ESI_TRY(do_normal(P, shot0, ns, p, Ap, c.L, c.active, false, nullptr, c.r, x, c.alpha, c.beta));
+        } else {
+            ESI_TRY(do_normal(P, shot0, ns, p, p, c.L, c.active, true, Ap, c.r, x, c.alpha, c.beta, S));
+            dir = Ap;
+            Apk = p;
+        }
+        ESI_TRY(launch_reduce_parts(P, P->part, P->part_stride, ns, c.pAp));
+        ESI_TRY(launch_dot(P, dir, c.r, ns, c.len, pr));
+        ESI_TRY(launch_cg_alpha(P, pr, c.pAp, c.alpha, ns));          // alpha = p.r / p.Np
+        ESI_TRY(launch_r_update(P, c.r, Apk, c.alpha, c.active, ns, c.len, c.rr_new));
+        ESI_TRY(launch_fcg_control(P, c.rr0, c.rr_new, c.pAp, c.active, c.finish, c.iters, c.status, c.hist,
+                                   max_iter + 1, c.ctl, rtol, max_iter, mode, restart, fallback, stall, ns));
+        if (stats)
+            ESI_TRY(launch_stats(P, c.r, x, dir, c.alpha, rep->stat_xref, c.iters, k + 1,
+                                 rep->stat_out + (k + 1) * stat_stride, ns));
+        ESI_TRY(launch_axpy_flag(P, x, dir, c.alpha, c.finish, 1, ns, c.len));
+        ESI_HIP_TRY(hipMemcpyAsync(P->h_ctl, c.ctl, 2 * sizeof(int), hipMemcpyDeviceToHost, P->stream));
+        ESI_HIP_TRY(hipStreamSynchronize(P->stream));
+        done_iters = k + 1;
+        if (k >= 1) std::swap(p, Ap);
+        if (P->h_ctl[1] == 0 || k == max_iter - 1) break;
+        // z_{k+1} = M(r_{k+1}); beta = -z.Np / p.Np (0 when the direction restarts)
+        ESI_TRY(precondition(k + 1));
+        ESI_TRY(launch_dot_scaled(P, c.r, Apk, S, ns, zAp));
+        ESI_TRY(launch_fcg_beta(P, zAp, c.pAp, restart, c.beta, ns));
+    }
+    std::vector<int> h_fb(ns, -1);
+    ESI_HIP_TRY(hipMemcpyAsync(h_status.data(), c.status, ns * sizeof(int), hipMemcpyDeviceToHost, P->stream));
+    ESI_HIP_TRY(hipMemcpyAsync(h_fb.data(), fallback, ns * sizeof(int), hipMemcpyDeviceToHost, P->stream));
+    if (rep) {
+        rep->iters = done_iters;
+        if (rep->shot_iters)
+            ESI_HIP_TRY(hipMemcpyAsync(rep->shot_iters, c.iters, ns * sizeof(int), hipMemcpyDeviceToHost, P->stream));
+        if (rep->res_hist)
+            ESI_HIP_TRY(hipMemcpyAsync(rep->res_hist, c.hist, (size_t)ns * (max_iter + 1) * sizeof(double),
+                                       hipMemcpyDeviceToHost, P->stream));
+    }
+    ESI_HIP_TRY(hipStreamSynchronize(P->stream));
+    if (rep && rep->shot_fallback)
+        for (int s = 0; s < ns; ++s) rep->shot_fallback[s] = h_fb[s];
+    for (int s = 0; s < ns; ++s)
+        if (h_status[s] == ESI_ERR_NONFINITE) return fail(ESI_ERR_NONFINITE, "flexible CG: non-finite scalar");
+    for (int s = 0; s < ns; ++s)
+        if (h_status[s] == ESI_ERR_BREAKDOWN) return fail(ESI_ERR_BREAKDOWN, "flexible CG breakdown: p.Np <= 0");
+    return ESI_OK;
+}
+
+extern "C" esi_status_t esi_precond_features(esi_plan_t plan, int32_t shot0, int32_t ns, const float* a,
+                                             const float* cmap, int32_t Hp, int32_t Wp, float* xin,
+                                             float* apad, float* cpad) {
+    set_error("");
+    if (!plan) return fail(ESI_ERR_ARG, "null plan");
+    Plan* P = (Plan*)plan;
+    ESI_TRY(check_shots(P, shot0, ns));
+    if (P->ndim != 2) return fail(ESI_ERR_ARG, "network features are 2D");
+    if (!a || !xin) return fail(ESI_ERR_ARG, "null pointer");
+    if (Hp < P->nz || Wp < P->nx || Hp % 8 || Wp % 8) return fail(ESI_ERR_SHAPE, "Hp, Wp: multiples of 8 covering the grid");
+    ESI_TRY(grow_t(&P->fcg_d, &P->fcg_d_cap, (int64_t)4 * std::max(ns, P->nshots), P->stream));
+    return launch_features(P, shot0, ns, a, cmap, P->fcg_d + 3 * ns, Hp, Wp, xin, apad, cpad);
 }
 
 extern "C" esi_status_t esi_gradient(esi_plan_t plan, int32_t shot0, int32_t ns, int32_t mode,

@@ -124,6 +124,15 @@ struct Plan {
     hipGraph_t cg_g[2] = {nullptr, nullptr};
     hipGraphExec_t cg_exec[2] = {nullptr, nullptr};
     std::vector<uintptr_t> cg_key;       // what the captured graphs were built for
+    float* vphys = nullptr;              // physical velocity [nphys] (network features)
+    // flexible CG scratch: cell scale and energy [nshots][nphys], network input
+    // [nshots][3][Hp][Wp] and output [nshots][Hp][Wp], scalars
+    float* fcg_s = nullptr; int64_t fcg_s_cap = 0;
+    float* fcg_a = nullptr; int64_t fcg_a_cap = 0;
+    float* fcg_in = nullptr; int64_t fcg_in_cap = 0;
+    float* fcg_o = nullptr; int64_t fcg_o_cap = 0;
+    double* fcg_d = nullptr; int64_t fcg_d_cap = 0;   // pr, zAp, zr [3][nshots]
+    int* fcg_i = nullptr; int64_t fcg_i_cap = 0;      // mode, restart, fallback_at [3][nshots]
 
     std::vector<TileLists*> lists;       // one per tile shape used
     int time_block = 2;                  // steps per launch where allowed (1 or 2)
@@ -204,6 +213,7 @@ struct StepArgs {
     const float* cg_p;       // p_old (read)
     float* cg_pn;            // p_new (written; a different buffer from cg_p)
     float* cg_x;
+    const float* cg_s;           // F_SCALE: per-shot cell scale [nshots][nphys], z = s r
     const double* cg_alpha;  // [nshots]
     const double* cg_beta;   // [nshots]
     // gradient
@@ -228,6 +238,7 @@ enum : unsigned {
     F_STORE = 1u << 8,       // store (dA/dm) u^n into store slot (forward)
     F_CORR = 1u << 9,        // gacc += mu^j * store slot (adjoint)
     F_SRC_REC = 1u << 10,    // src_rec[s][j] = mu^j at the shot's source cell (adjoint)
+    F_SCALE = 1u << 11,      // with F_CG_FUSE: the new direction is s r + beta p (flexible CG)
 };
 
 // Gather of the last trace d^{nt-1} = R u^{nt} (after the time loop).
@@ -265,5 +276,26 @@ esi_status_t launch_sub(Plan* P, float* out, const float* a, const float* b, int
 esi_status_t launch_trace_at_src(Plan* P, const float* dense, int shot0, int nshots, float* out);
 // grad_v = -2 grad_m / v^3
 esi_status_t launch_grad_velocity(Plan* P, const float* vel, const float* gm, float* gv, int64_t n);
+
+// flexible CG (fcg.hip) and the network (unet.hip)
+esi_status_t launch_energy(Plan* P, const float* r, const int* active, float* a, int ns);
+esi_status_t launch_stats(Plan* P, const float* r, const float* x, const float* p, const double* alpha,
+                          const float* xref, const int* iters, int k, float* out, int ns);
+esi_status_t launch_features(Plan* P, int shot0, int ns, const float* a, const float* c, double* mean, int Hp,
+                             int Wp, float* xin, float* apad, float* cpad);
+esi_status_t launch_fcg_zr_check_scale(Plan* P, const float* o, const float* fixed, const float* a,
+                                       const int* active, int* mode, int* restart, int* fallback, int k,
+                                       int Hp, int Wp, double* zr, float* S, int ns);
+esi_status_t launch_scale_vec(Plan* P, float* p, const float* r, const float* S, int ns);
+esi_status_t launch_dot_scaled(Plan* P, const float* r, const float* y, const float* S, int ns, double* out);
+esi_status_t launch_fcg_beta(Plan* P, const double* zAp, const double* pAp, const int* restart, double* beta,
+                             int ns);
+esi_status_t launch_fcg_init(Plan* P, int* mode, int* restart, int* fallback, int ns);
+esi_status_t launch_fcg_control(Plan* P, const double* rr0, const double* rr_new, const double* pAp, int* active,
+                                int* finish, int* iters, int* status, double* hist, int hstride, int* ctl,
+                                double rtol, int max_iter, int* mode, int* restart, int* fallback, double stall,
+                                int ns);
+esi_status_t unet_dims(esi_unet_t u, int* H, int* W, int* maxb);
+esi_status_t unet_forward_on(esi_unet_t u, hipStream_t stream, const float* x, float* o, int batch);
 
 }  // namespace esi

@@ -1,0 +1,336 @@
+// Kernels of the flexible CG with the learned preconditioner: per-cell residual
+// energy, network features, the scale z = s r, the products z.r and z.Np,
+// the stopping / stall / fallback bookkeeping of FCG(1) (Notay 2000), and the
+// (a, c) maps that make the network's training pairs.
+#include <cmath>
+
+#include "esi_internal.h"
+
+namespace esi {
+namespace {
+
+constexpr int NT = 256;
+
+int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + NT - 1) / NT, 16384)); }
+
+__device__ __forceinline__ double block_sum_d(double v, double* sm) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sm[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int k = 0; k < NT / 64; ++k) t += sm[k];
+    return t;
+}
+
+// a[s][x] = sum_t r[s][t][x]^2 for the shots still iterating.
+__global__ void k_energy(const float* __restrict__ r, const int* __restrict__ active, float* __restrict__ a,
+                         int ns, int nt, int64_t nphys) {
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < ns * nphys; i += (int64_t)gridDim.x * NT) {
+        const int s = (int)(i / nphys);
+        if (active && !active[s]) continue;
+        const int64_t x = i % nphys;
+        const float* rs = r + (int64_t)s * nt * nphys + x;
+        float acc = 0.f;
+        for (int t = 0; t < nt; ++t) {
+            const float v = rs[(int64_t)t * nphys];
+            acc = fmaf(v, v, acc);
+        }
+        a[i] = acc;
+    }
+}
+
+// Training maps of the shots that did iteration `k` (iters[s] == k; k = 0:
+// every shot): out[s][0][x] = sum_t r^2, out[s][1][x] = sum_t r (xref - xk)
+// with xk = x + alpha p (the update the shot has not applied yet; none at k = 0).
+__global__ void k_stats(const float* __restrict__ r, const float* __restrict__ x, const float* __restrict__ p,
+                        const double* __restrict__ alpha, const float* __restrict__ xref,
+                        const int* __restrict__ iters, int k, float* __restrict__ out, int ns, int nt,
+                        int64_t nphys) {
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < ns * nphys; i += (int64_t)gridDim.x * NT) {
+        const int s = (int)(i / nphys);
+        if (k > 0 && iters[s] != k) continue;
+        const int64_t c = i % nphys;
+        const int64_t base = (int64_t)s * nt * nphys + c;
+        const float al = p ? (float)alpha[s] : 0.f;
+        float aa = 0.f, cc = 0.f;
+        for (int t = 0; t < nt; ++t) {
+            const int64_t j = base + (int64_t)t * nphys;
+            const float rv = r[j];
+            const float xk = p ? fmaf(al, p[j], x[j]) : x[j];
+            aa = fmaf(rv, rv, aa);
+            cc = fmaf(rv, xref[j] - xk, cc);
+        }
+        out[((int64_t)s * 2) * nphys + c] = aa;
+        out[((int64_t)s * 2 + 1) * nphys + c] = cc;
+    }
+}
+
+// mean[s] = mean over cells of sqrt(a / nt).  One workgroup per shot.
+__global__ __launch_bounds__(NT) void k_feat_mean(const float* __restrict__ a, int64_t nphys, int nt,
+                                                  double* __restrict__ mean) {
+    __shared__ double sm[NT / 64];
+    const int s = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t x = threadIdx.x; x < nphys; x += NT) acc += sqrt((double)a[(int64_t)s * nphys + x] / nt);
+    const double t = block_sum_d(acc, sm);
+    if (threadIdx.x == 0) mean[s] = t / (double)nphys;
+}
+
+// Network input on the image padded to Hp x Wp (zero outside the grid):
+// [rms / mean(rms), v / 3000, B / 100] with rms = sqrt(a / nt) and B the
+// annihilator weight |x - x_s| / dx + eps (in cells); also the padded copies
+// of a and c when asked for.
+__global__ void k_features(const float* __restrict__ a, const float* __restrict__ c,
+                           const double* __restrict__ mean, const float* __restrict__ v,
+                           const int32_t* __restrict__ src, int shot0, float b_eps, int ns, int nz, int nx,
+                           int Hp, int Wp, int nt, float* __restrict__ xin, float* __restrict__ apad,
+                           float* __restrict__ cpad) {
+    const int64_t img = (int64_t)Hp * Wp;
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < ns * img; i += (int64_t)gridDim.x * NT) {
+        const int s = (int)(i / img);
+        const int64_t q = i % img;
+        const int iz = (int)(q / Wp), ix = (int)(q % Wp);
+        float f0 = 0.f, f1 = 0.f, f2 = 0.f, av = 0.f, cv = 0.f;
+        if (iz < nz && ix < nx) {
+            const int64_t cell = (int64_t)iz * nx + ix;
+            av = a[(int64_t)s * nz * nx + cell];
+            if (c) cv = c[(int64_t)s * nz * nx + cell];
+            const double m = mean[s];
+            const float rms = sqrtf(av / (float)nt);
+            f0 = m > 0.0 ? (float)(rms / m) : rms;
+            f1 = v[cell] / 3000.f;
+            const float dx = (float)(ix - src[3 * (shot0 + s)]), dz = (float)(iz - src[3 * (shot0 + s) + 1]);
+            f2 = (sqrtf(dx * dx + dz * dz) + b_eps) / 100.f;
+        }
+        float* xs = xin + (int64_t)s * 3 * img;
+        xs[q] = f0;
+        xs[img + q] = f1;
+        xs[2 * img + q] = f2;
+        if (apad) apad[i] = av;
+        if (cpad) cpad[i] = cv;
+    }
+}
+
+// Candidate scale of cell x of shot s: exp(o) from the network, a fixed scale,
+// or 1.
+__device__ __forceinline__ float cand_scale(const float* o, const float* fixed, int s, int iz, int ix, int nz,
+                                            int nx, int Hp, int Wp) {
+    if (o) return expf(o[((int64_t)s * Hp + iz) * Wp + ix]);
+    if (fixed) return fixed[((int64_t)s * nz + iz) * nx + ix];
+    return 1.f;
+}
+
+// zr[s] = sum_x s(x) a(x) = z.r for the candidate scale (1 for shots in CG mode).
+__global__ __launch_bounds__(NT) void k_fcg_zr(const float* __restrict__ o, const float* __restrict__ fixed,
+                                               const float* __restrict__ a, const int* __restrict__ mode, int nz,
+                                               int nx, int Hp, int Wp, double* __restrict__ zr) {
+    __shared__ double sm[NT / 64];
+    const int s = blockIdx.x;
+    const int64_t n = (int64_t)nz * nx;
+    const bool cg = mode[s] != 0;
+    double acc = 0.0;
+    for (int64_t x = threadIdx.x; x < n; x += NT) {
+        const int iz = (int)(x / nx), ix = (int)(x % nx);
+        const float sc = cg ? 1.f : cand_scale(o, fixed, s, iz, ix, nz, nx, Hp, Wp);
+        acc += (double)sc * (double)a[(int64_t)s * n + x];
+    }
+    const double t = block_sum_d(acc, sm);
+    if (threadIdx.x == 0) zr[s] = t;
+}
+
+// A shot whose preconditioned residual is not a descent direction (z.r <= 0
+// or not finite) hands over to plain CG after iteration k.
+__global__ void k_fcg_check(const double* __restrict__ zr, const int* __restrict__ active, int* __restrict__ mode,
+                            int* __restrict__ restart, int* __restrict__ fallback, int k, int n) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n || !active[s] || mode[s]) return;
+    const double z = zr[s];
+    if (!(isfinite(z) && z > 0.0)) {
+        mode[s] = 1;
+        restart[s] = 1;
+        fallback[s] = k;
+    }
+}
+
+// S[s][x] = candidate scale, or 1 in CG mode.
+__global__ void k_fcg_scale(const float* __restrict__ o, const float* __restrict__ fixed,
+                            const int* __restrict__ mode, float* __restrict__ S, int ns, int nz, int nx, int Hp,
+                            int Wp) {
+    const int64_t n = (int64_t)nz * nx;
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < ns * n; i += (int64_t)gridDim.x * NT) {
+        const int s = (int)(i / n);
+        const int64_t x = i % n;
+        S[i] = mode[s] ? 1.f : cand_scale(o, fixed, s, (int)(x / nx), (int)(x % nx), nz, nx, Hp, Wp);
+    }
+}
+
+// p[s][t][x] = S[s][x] r[s][t][x]
+__global__ void k_scale_vec(float* __restrict__ p, const float* __restrict__ r, const float* __restrict__ S,
+                            int ns, int nt, int64_t nphys) {
+    const int64_t len = (int64_t)nt * nphys;
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < ns * len; i += (int64_t)gridDim.x * NT) {
+        const int s = (int)(i / len);
+        p[i] = r[i] * S[(int64_t)s * nphys + (i % len) % nphys];
+    }
+}
+
+// part[s][b] = sum over the block's chunk of (S r) . y
+__global__ __launch_bounds__(NT) void k_dot_scaled(const float* __restrict__ r, const float* __restrict__ y,
+                                                   const float* __restrict__ S, int64_t len, int64_t nphys,
+                                                   double* __restrict__ part) {
+    __shared__ double sm[NT / 64];
+    const int s = blockIdx.y, b = blockIdx.x, bps = gridDim.x;
+    const int64_t chunk = (len + bps - 1) / bps;
+    const int64_t beg = (int64_t)b * chunk, end = min(len, beg + chunk);
+    const float* rs = r + (int64_t)s * len;
+    const float* ys = y + (int64_t)s * len;
+    const float* Ss = S + (int64_t)s * nphys;
+    double acc = 0.0;
+    for (int64_t i = beg + threadIdx.x; i < end; i += NT) acc += (double)(rs[i] * Ss[i % nphys]) * (double)ys[i];
+    const double t = block_sum_d(acc, sm);
+    if (threadIdx.x == 0) part[(int64_t)s * bps + b] = t;
+}
+
+// beta = -z.Np / p.Np, or 0 when the direction restarts.
+__global__ void k_fcg_beta(const double* __restrict__ zAp, const double* __restrict__ pAp,
+                           const int* __restrict__ restart, double* __restrict__ beta, int n) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) beta[s] = restart[s] ? 0.0 : -zAp[s] / pAp[s];
+}
+
+__global__ void k_fcg_init(int* __restrict__ mode, int* __restrict__ restart, int* __restrict__ fallback, int n) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) {
+        mode[s] = 0;
+        restart[s] = 0;
+        fallback[s] = -1;
+    }
+}
+
+// After iteration k of every active shot: the stopping test of k_cg_control,
+// then the stall test of the flexible iteration (||r_{k+1}|| > stall
+// ||r_{k-2}||: plain CG takes over, the direction restarts).
+__global__ void k_fcg_control(const double* __restrict__ rr0, const double* __restrict__ rr_new,
+                              const double* __restrict__ pAp, int* __restrict__ active, int* __restrict__ finish,
+                              int* __restrict__ iters, int* __restrict__ status, double* __restrict__ hist,
+                              int hstride, int* __restrict__ ctl, double rtol, int max_iter, int* __restrict__ mode,
+                              int* __restrict__ restart, int* __restrict__ fallback, double stall, int n) {
+    __shared__ int cnt;
+    const int k = ctl[0];
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    for (int s = threadIdx.x; s < n; s += blockDim.x) {
+        int f = 0;
+        restart[s] = 0;
+        if (active[s]) {
+            iters[s] = k + 1;
+            const double a = pAp[s], b = rr_new[s];
+            const double rel = sqrt(b / rr0[s]);
+            double* h = hist + (int64_t)s * hstride;
+            h[k + 1] = rel;
+            if (!isfinite(a) || !isfinite(b)) {
+                status[s] = (int)ESI_ERR_NONFINITE;
+                f = 2;
+            } else if (a <= 0.0) {
+                status[s] = (int)ESI_ERR_BREAKDOWN;
+                f = 2;
+            } else if (rel < rtol || k == max_iter - 1) {
+                f = 1;
+            } else if (!mode[s] && k >= 2 && rel > stall * h[k - 2]) {
+                mode[s] = 1;
+                restart[s] = 1;
+                fallback[s] = k + 1;
+            }
+            if (f) active[s] = 0;
+            else atomicAdd(&cnt, 1);
+        }
+        finish[s] = f;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ctl[0] = k + 1;
+        ctl[1] = cnt;
+    }
+}
+
+}  // namespace
+
+esi_status_t launch_energy(Plan* P, const float* r, const int* active, float* a, int ns) {
+    hipLaunchKernelGGL(k_energy, dim3(grid_for((int64_t)ns * P->nphys)), dim3(NT), 0, P->stream, r, active, a, ns,
+                       P->nt, P->nphys);
+    ESI_HIP_TRY(hipGetLastError());
+    return ESI_OK;
+}
+
+esi_status_t launch_stats(Plan* P, const float* r, const float* x, const float* p, const double* alpha,
+                          const float* xref, const int* iters, int k, float* out, int ns) {
+    hipLaunchKernelGGL(k_stats, dim3(grid_for((int64_t)ns * P->nphys)), dim3(NT), 0, P->stream, r, x, p, alpha,
+                       xref, iters, k, out, ns, P->nt, P->nphys);
+    ESI_HIP_TRY(hipGetLastError());
+    return ESI_OK;
+}
+
+esi_status_t launch_features(Plan* P, int shot0, int ns, const float* a, const float* c, double* mean, int Hp,
+                             int Wp, float* xin, float* apad, float* cpad) {
+    hipLaunchKernelGGL(k_feat_mean, dim3(ns), dim3(NT), 0, P->stream, a, P->nphys, P->nt, mean);
+    hipLaunchKernelGGL(k_features, dim3(grid_for((int64_t)ns * Hp * Wp)), dim3(NT), 0, P->stream, a, c, mean,
+                       P->vphys, P->d_src, shot0, (float)P->b_eps, ns, P->nz, P->nx, Hp, Wp, P->nt, xin, apad,
+                       cpad);
+    ESI_HIP_TRY(hipGetLastError());
+    return ESI_OK;
+}
+
+esi_status_t launch_fcg_zr_check_scale(Plan* P, const float* o, const float* fixed, const float* a,
+                                       const int* active, int* mode, int* restart, int* fallback, int k,
+                                       int Hp, int Wp, double* zr, float* S, int ns) {
+    hipLaunchKernelGGL(k_fcg_zr, dim3(ns), dim3(NT), 0, P->stream, o, fixed, a, mode, P->nz, P->nx, Hp, Wp, zr);
+    hipLaunchKernelGGL(k_fcg_check, dim3((ns + 63) / 64), dim3(64), 0, P->stream, zr, active, mode, restart,
+                       fallback, k, ns);
+    hipLaunchKernelGGL(k_fcg_scale, dim3(grid_for((int64_t)ns * P->nphys)), dim3(NT), 0, P->stream, o, fixed,
+                       mode, S, ns, P->nz, P->nx, Hp, Wp);
+    ESI_HIP_TRY(hipGetLastError());
+    return ESI_OK;
+}
+
+esi_status_t launch_scale_vec(Plan* P, float* p, const float* r, const float* S, int ns) {
+    hipLaunchKernelGGL(k_scale_vec, dim3(grid_for((int64_t)ns * P->nt * P->nphys)), dim3(NT), 0, P->stream, p, r,
+                       S, ns, P->nt, P->nphys);
+    ESI_HIP_TRY(hipGetLastError());
+    return ESI_OK;
+}
+
+esi_status_t launch_dot_scaled(Plan* P, const float* r, const float* y, const float* S, int ns, double* out) {
+    const int64_t len = (int64_t)P->nt * P->nphys;
+    const int bps = (int)std::max<int64_t>(1, std::min<int64_t>(512, (len + 4095) / 4096));
+    ESI_TRY(grow_t(&P->part, &P->part_cap, (int64_t)bps * ns, P->stream));
+    hipLaunchKernelGGL(k_dot_scaled, dim3(bps, ns), dim3(NT), 0, P->stream, r, y, S, len, P->nphys, P->part);
+    ESI_HIP_TRY(hipGetLastError());
+    return launch_reduce_parts(P, P->part, bps, ns, out);
+}
+
+esi_status_t launch_fcg_beta(Plan* P, const double* zAp, const double* pAp, const int* restart, double* beta,
+                             int ns) {
+    hipLaunchKernelGGL(k_fcg_beta, dim3((ns + 63) / 64), dim3(64), 0, P->stream, zAp, pAp, restart, beta, ns);
+    ESI_HIP_TRY(hipGetLastError());
+    return ESI_OK;
+}
+
+esi_status_t launch_fcg_init(Plan* P, int* mode, int* restart, int* fallback, int ns) {
+    hipLaunchKernelGGL(k_fcg_init, dim3((ns + 63) / 64), dim3(64), 0, P->stream, mode, restart, fallback, ns);
+    ESI_HIP_TRY(hipGetLastError());
+    return ESI_OK;
+}
+
+esi_status_t launch_fcg_control(Plan* P, const double* rr0, const double* rr_new, const double* pAp, int* active,
+                                int* finish, int* iters, int* status, double* hist, int hstride, int* ctl,
+                                double rtol, int max_iter, int* mode, int* restart, int* fallback, double stall,
+                                int ns) {
+    hipLaunchKernelGGL(k_fcg_control, dim3(1), dim3(256), 0, P->stream, rr0, rr_new, pAp, active, finish, iters,
+                       status, hist, hstride, ctl, rtol, max_iter, mode, restart, fallback, stall, ns);
+    ESI_HIP_TRY(hipGetLastError());
+    return ESI_OK;
+}
+
+}  // namespace esi

@@ -158,6 +158,8 @@ static esi_status_t set_model(Plan* P, const float* vel, bool first, double eta_
         }
         ESI_HIP_TRY(hipMalloc(&P->c2, P->fsize * sizeof(float)));
     }
+    if (first) ESI_HIP_TRY(hipMalloc(&P->vphys, P->nphys * sizeof(float)));
+    ESI_HIP_TRY(hipMemcpyAsync(P->vphys, vel, P->nphys * sizeof(float), hipMemcpyDeviceToDevice, P->stream));
     int64_t n = P->fsize;
     int blocks = (int)std::min<int64_t>((n + 255) / 256, 65536);
     hipLaunchKernelGGL(k_model_c2, dim3(blocks), dim3(256), 0, P->stream, P->c2, vel, P->nz, P->ny,
@@ -305,7 +307,8 @@ static void free_plan(Plan* P) {
     if (P->h_ctl) hipHostFree(P->h_ctl);
     void* bufs[] = {P->d_src, P->d_rec_ptr, P->c2, P->kx, P->kz, P->ky, P->ring, P->ring2,
                     P->dscr, P->dscr2, P->part, P->scal, P->gshot, P->store, P->ckpt, P->flags,
-                    P->d_rec, P->cgi, P->cg_hist};
+                    P->d_rec, P->cgi, P->cg_hist, P->vphys, P->fcg_s, P->fcg_a, P->fcg_in,
+                    P->fcg_o, P->fcg_d, P->fcg_i};
     for (void* b : bufs)
         if (b) hipFree(b);
     delete P;

@@ -226,6 +226,11 @@ __global__ __launch_bounds__(256, ESI_MINW) void k_step2d(const StepArgs a) {
         float po[RZ], rv[RZ], xo[RZ];
 #pragma unroll
         for (int i = 0; i < RZ; ++i) { po[i] = at(p, pi[i]); rv[i] = at(r, pi[i]); xo[i] = at(xv, pi[i]); }
+        if constexpr ((FL & F_SCALE) != 0) {
+            const float* __restrict__ sc = a.cg_s + (int64_t)s * a.nphys;
+#pragma unroll
+            for (int i = 0; i < RZ; ++i) rv[i] = rv[i] * at(sc, pi[i]);
+        }
 #pragma unroll
         for (int i = 0; i < RZ; ++i) {
             const float pn = fmaf(bet, po[i], rv[i]);
@@ -438,6 +443,11 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
         const float* __restrict__ xv = a.cg_x + vA;
 #pragma unroll
         for (int i = 0; i < A_RZ; ++i) { poA[i] = at(p, piA[i]); qA[i] = at(r, piA[i]); xoA[i] = at(xv, piA[i]); }
+        if constexpr ((FL & F_SCALE) != 0) {
+            const float* __restrict__ sc = a.cg_s + (int64_t)s * a.nphys;
+#pragma unroll
+            for (int i = 0; i < A_RZ; ++i) qA[i] = qA[i] * at(sc, piA[i]);
+        }
     }
     if constexpr ((FL & F_NORMAL) != 0) {
         const float* __restrict__ p = a.dp + vA;
@@ -600,6 +610,11 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
         const float* __restrict__ xv = a.cg_x + vB;
 #pragma unroll
         for (int i = 0; i < B_RZ; ++i) { poB[i] = at(p, pi[i]); qv[i] = at(r, pi[i]); xoB[i] = at(xv, pi[i]); }
+        if constexpr ((FL & F_SCALE) != 0) {
+            const float* __restrict__ sc = a.cg_s + (int64_t)s * a.nphys;
+#pragma unroll
+            for (int i = 0; i < B_RZ; ++i) qv[i] = qv[i] * at(sc, pi[i]);
+        }
     }
     if constexpr ((FL & F_NORMAL) != 0) {
         const float* __restrict__ p = a.dp + vB;
@@ -708,6 +723,7 @@ esi_status_t dispatch2d(Plan* P, unsigned flags, const StepArgs& a) {
         ESI_CASE(F_SRC_DENSE)
         ESI_CASE(F_SRC_DENSE | F_PENALTY)
         ESI_CASE(F_CG_FUSE | F_GATHER)
+        ESI_CASE(F_CG_FUSE | F_GATHER | F_SCALE)
         ESI_CASE(F_INJ | F_OUT)
         ESI_CASE(F_INJ | F_NORMAL)
         ESI_CASE(F_INJ | F_CORR)

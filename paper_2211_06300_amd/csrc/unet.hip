@@ -877,3 +877,26 @@ extern "C" esi_status_t esi_unet_adam(esi_unet_t u, const float* grad, float lr,
     ESI_HIP_TRY(hipGetLastError());
     return pack(U);
 }
+
+namespace esi {
+
+esi_status_t unet_dims(esi_unet_t u, int* H, int* W, int* maxb) {
+    if (!u) return fail(ESI_ERR_ARG, "null network");
+    Unet* U = as_unet(u);
+    *H = U->H; *W = U->W; *maxb = U->maxb;
+    return ESI_OK;
+}
+
+// Forward pass queued on `stream` (the caller's) instead of the network's own.
+esi_status_t unet_forward_on(esi_unet_t u, hipStream_t stream, const float* x, float* o, int batch) {
+    Unet* U = as_unet(u);
+    if (batch < 1 || batch > U->maxb) return fail(ESI_ERR_ARG, "batch outside [1, max_batch]");
+    hipStream_t own = U->stream;
+    U->stream = stream;
+    Ctx c{U, batch};
+    esi_status_t st = forward(c, x, o);
+    U->stream = own;
+    return st;
+}
+
+}  // namespace esi

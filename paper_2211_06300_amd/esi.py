@@ -41,7 +41,9 @@ class _Geom(ctypes.Structure):
 
 class _CgReport(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("shot_iters", ctypes.POINTER(ctypes.c_int32)),
-                ("res_hist", ctypes.POINTER(ctypes.c_double))]
+                ("res_hist", ctypes.POINTER(ctypes.c_double)),
+                ("shot_fallback", ctypes.POINTER(ctypes.c_int32)),
+                ("stat_xref", ctypes.c_void_p), ("stat_out", ctypes.c_void_p)]
 
 
 _lib = None
@@ -50,7 +52,8 @@ EXPORTS = ["esi_plan_create", "esi_plan_set_model", "esi_plan_destroy", "esi_las
            "esi_plan_profile", "esi_plan_profile_read", "esi_plan_set_time_block",
            "esi_forward_ckpt", "esi_grad_velocity", "esi_plan_set_cg_graph",
            "esi_unet_num_params", "esi_unet_create", "esi_unet_destroy", "esi_unet_set_params",
-           "esi_unet_get_params", "esi_unet_forward", "esi_unet_loss_grad", "esi_unet_adam"]
+           "esi_unet_get_params", "esi_unet_forward", "esi_unet_loss_grad", "esi_unet_adam",
+           "esi_fpcg_solve", "esi_precond_features"]
 # time-step kernel variants (bit set of fused work), as in include/esi.h
 K_FLAGS = {1: "SRC_POINT", 2: "SRC_DENSE", 4: "CG_FUSE", 8: "INJ", 16: "GATHER", 32: "OUT",
            64: "NORMAL", 128: "PENALTY", 256: "STORE", 512: "CORR", 1024: "SRC_REC",
@@ -83,6 +86,8 @@ def load_library(path: str = LIB_PATH):
     L.esi_forward_ckpt.argtypes = [vp, i32, i32, i32, vp, vp, i32]
     L.esi_grad_velocity.argtypes = [vp, vp, vp, vp]
     L.esi_plan_profile_read.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+    L.esi_fpcg_solve.argtypes = [vp, i32, i32, vp, vp, vp, i32, dbl, vp, vp, ctypes.POINTER(_CgReport)]
+    L.esi_precond_features.argtypes = [vp, i32, i32, vp, vp, i32, i32, vp, vp, vp]
     L.esi_unet_num_params.argtypes = []
     L.esi_unet_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, vp]
     L.esi_unet_destroy.argtypes = [vp]
@@ -260,6 +265,45 @@ class Plan:
                                       _f32(work, (3, *self.vec_shape(nshots)), "work"),
                                       int(max_iter), float(rtol), ctypes.byref(rep)))
         return x, {"iters": int(rep.iters), "shot_iters": iters, "res_hist": hist}
+
+    def fpcg_solve(self, d_obs, max_iter, rtol=0.0, net=None, scale=None, shot0=0, nshots=None,
+                   x=None, work=None, stat_xref=None, stat_out=None):
+        """Flexible CG (esi_fpcg_solve); net is a Unet, scale a [nshots, *phys]
+        tensor, or neither (M = I)."""
+        shot0, nshots = self._range(shot0, nshots)
+        x = self.new_vec(nshots) if x is None else x
+        if work is None:
+            work = torch.empty((3, *self.vec_shape(nshots)), dtype=torch.float32, device=self.device)
+        hist = np.zeros((nshots, max_iter + 1))
+        iters = np.zeros(nshots, dtype=np.int32)
+        fb = np.zeros(nshots, dtype=np.int32)
+        rep = _CgReport(0, iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                        hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                        fb.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                        None if stat_xref is None else _f32(stat_xref, self.vec_shape(nshots), "stat_xref"),
+                        None if stat_out is None else _f32(stat_out, (max_iter + 1, nshots, 2, self.nphys),
+                                                           "stat_out"))
+        sp = None if scale is None else _f32(scale, (nshots, *self.phys_shape), "scale")
+        _check(self._lib.esi_fpcg_solve(self._h, shot0, nshots,
+                                        _f32(d_obs, self.data_shape(shot0, nshots), "d_obs"),
+                                        _f32(x, self.vec_shape(nshots), "x"),
+                                        _f32(work, (3, *self.vec_shape(nshots)), "work"),
+                                        int(max_iter), float(rtol), None if net is None else net._h, sp,
+                                        ctypes.byref(rep)))
+        return x, {"iters": int(rep.iters), "shot_iters": iters, "res_hist": hist, "fallback": fb}
+
+    def precond_features(self, a, Hp, Wp, cmap=None, shot0=0, nshots=None, pads=False):
+        """Network input [nshots, 3, Hp, Wp] from a = sum_t r^2 [nshots, *phys];
+        with pads=True also the zero-padded a and cmap."""
+        shot0, nshots = self._range(shot0, nshots)
+        xin = torch.empty((nshots, 3, Hp, Wp), dtype=torch.float32, device=self.device)
+        ap = torch.empty((nshots, Hp, Wp), dtype=torch.float32, device=self.device) if pads else None
+        cp = torch.empty((nshots, Hp, Wp), dtype=torch.float32, device=self.device) if pads and cmap is not None else None
+        _check(self._lib.esi_precond_features(self._h, shot0, nshots,
+                                              _f32(a, (nshots, *self.phys_shape), "a"),
+                                              None if cmap is None else _f32(cmap, (nshots, *self.phys_shape), "cmap"),
+                                              int(Hp), int(Wp), _ptr(xin), _ptr(ap), _ptr(cp)))
+        return (xin, ap, cp) if pads else xin
 
     def gradient(self, mode, src, data=None, kind=SRC_DENSE, shot0=0, nshots=None, grad_m=None,
                  grad_src=None, ckpt_every=0):
