@@ -272,22 +272,22 @@ esi_status_t esi_plan_profile_read(esi_plan_t plan, int32_t cap, int32_t* count,
  * open (Sec. 4.2, Sec. 6); this call adds it.  Per iteration: z_k = M(r_k),
  * alpha = p.r / p.Np, x += alpha p, r -= alpha Np, beta = -z.Np / p.Np,
  * p = z + beta p.  The preconditioner scales the residual cell by cell,
- * z = s r, with
- *   net != NULL:   s = exp(Net(features)) recomputed every iteration from the
- *                  residual's per-cell energy (see esi_precond_features); the
- *                  network must take Hp x Wp images (nz, nx rounded up to
- *                  multiples of 8) in batches of at least nshots;
- *   scale != NULL: a fixed s, device [nshots][phys];
- *   both NULL:     s = 1 (CG with beta in Hestenes-Stiefel form).
+ * z = s r, with s = s0 exp(o):
+ *   scale: s0, device [nshots][phys], or NULL for s0 = 1;
+ *   net:   o = Net(features) recomputed every iteration from the residual's
+ *          per-cell energy (see esi_precond_features), or NULL for o = 0;
+ *          the network must take Hp x Wp images (nz, nx rounded up to
+ *          multiples of 8) in batches of at least nshots.
+ * Both NULL is CG with beta in Hestenes-Stiefel form.
  * A shot falls back to plain CG (s = 1 from then on, the direction restarted
- * at p = r) when z.r <= 0 or is not finite, or when ||r_{k+1}|| > 0.99
- * ||r_{k-2}||.  Stopping as esi_cg_solve: ||r_{k+1}|| < rtol ||r_0|| of the
+ * at p = r) when z.r <= 0 or is not finite, or when ||r|| has not reached a
+ * new best by 1 % for 10 iterations.  Stopping as esi_cg_solve: ||r_{k+1}|| < rtol ||r_0|| of the
  * recursively updated residual, or max_iter.
  *   d_obs, x, work, max_iter, rtol: as esi_cg_solve (work: 3 vectors).
  *   rep: as esi_cg_solve, plus shot_fallback and the training maps
  *        (stat_xref / stat_out) when given.
- * Errors as esi_cg_solve; ESI_ERR_ARG for 3D plans or both net and scale,
- * ESI_ERR_SHAPE for a network of the wrong size.
+ * Errors as esi_cg_solve; ESI_ERR_ARG for 3D plans, ESI_ERR_SHAPE for a
+ * network of the wrong size.
  */
 esi_status_t esi_fpcg_solve(esi_plan_t plan, int32_t shot0, int32_t nshots, const float* d_obs,
                             float* x, float* work, int32_t max_iter, double rtol, esi_unet_t net,
@@ -296,17 +296,19 @@ esi_status_t esi_fpcg_solve(esi_plan_t plan, int32_t shot0, int32_t nshots, cons
 /*
  * Network input of the preconditioner for `nshots` shots of a 2D plan, on
  * images padded to Hp x Wp (multiples of 8, at least nz x nx; zero outside
- * the grid): channel 0 = rms_t(r) / mean_x rms_t(r) with rms_t(r) = sqrt(a/nt),
- * channel 1 = v / 3000 m/s, channel 2 = B / 100 (B = |x - x_s| / dx + eps, in
- * cells).
+ * the grid): channel 0 = log(1 + rms_t(r) / mean_x rms_t(r)) with
+ * rms_t(r) = sqrt(a/nt), channel 1 = v / 3000 m/s, channel 2 = B / 100
+ * (B = |x - x_s| / dx + eps, in cells).
  *   a:    device [nshots][phys], a = sum_t r^2 of each shot's residual.
- *   cmap: device [nshots][phys] or NULL (copied into cpad when given).
+ *   cmap: device [nshots][phys] or NULL (c = sum_t r e of a training pair).
+ *   base: device [nshots][phys] base scale s0, or NULL for 1.
  *   xin:  device [nshots][3][Hp][Wp] out; apad, cpad: device [nshots][Hp][Wp]
- *         out or NULL (a and cmap zero-padded).
+ *         out or NULL: a s0^2 and cmap s0 zero-padded (the training maps of
+ *         the correction exp(o) on top of s0, see esi_unet_loss_grad).
  */
 esi_status_t esi_precond_features(esi_plan_t plan, int32_t shot0, int32_t nshots, const float* a,
-                                  const float* cmap, int32_t Hp, int32_t Wp, float* xin, float* apad,
-                                  float* cpad);
+                                  const float* cmap, const float* base, int32_t Hp, int32_t Wp,
+                                  float* xin, float* apad, float* cpad);
 
 /* ------------------------------------------------------------------------
  * Learned preconditioner network.  The paper leaves preconditioning of its CG
@@ -353,17 +355,19 @@ esi_status_t esi_unet_forward(esi_unet_t net, const float* x, float* o, int32_t 
 
 /* Loss of the scaling preconditioner and its gradient.  For each image s,
  * with a = sum_t r^2 and c = sum_t r e (device [batch][H][W], zero on padding
- * pixels), L_s = sum_x (a e^{2o} - 2 c e^{o}) / sum_x a, i.e. the squared
- * error of exp(o) r against e up to a constant; L = mean_s L_s.  Writes
+ * pixels), L_s = sum_x (a e^{2o} - 2 c e^{o}) sum_x a / (sum_x c)^2: the
+ * squared error of exp(o) r against e up to a constant, scaled so that 0 is
+ * no correction and -1 the best single scale; L = mean_s L_s.  Writes
  * dL/dtheta into grad (device [P], overwritten) and L into *loss (host, may
  * be NULL; non-NULL synchronises). */
 esi_status_t esi_unet_loss_grad(esi_unet_t net, const float* x, const float* a, const float* c,
                                 int32_t batch, float* grad, double* loss);
 
 /* One Adam step (Kingma & Ba) on the master parameters with gradient grad
- * (device [P]); step counts from 1. */
+ * (device [P]); step counts from 1.  clip_norm > 0 first scales the gradient
+ * to norm at most clip_norm (computed on the device). */
 esi_status_t esi_unet_adam(esi_unet_t net, const float* grad, float lr, float beta1, float beta2,
-                           float eps, int32_t step);
+                           float eps, int32_t step, float clip_norm);
 
 #ifdef __cplusplus
 }

@@ -366,7 +366,7 @@ class FPCGResult:
 
 
 def fpcg(apply_N, b: np.ndarray, precond, max_iter: int, rtol: float = 0.0,
-         stall: float = 0.99) -> FPCGResult:
+         stall: float = 0.99, window: int = 10) -> FPCGResult:
     """Flexible CG with truncation 1 (Notay 2000, FCG(1)) for N x = b.
 
     x_0 = 0, r_0 = b, z_0 = M(r_0), p_0 = z_0; per iteration alpha = p.r / p.Np,
@@ -376,9 +376,11 @@ def fpcg(apply_N, b: np.ndarray, precond, max_iter: int, rtol: float = 0.0,
 
     Fallback to plain CG (M = I from then on, direction restarted at p = r,
     the recursively updated residual kept) when z.r <= 0, when z or z.r is not
-    finite, or when ||r_{k+1}|| > stall * ||r_{k-2}|| (no progress over three
-    iterations).  With M = I the iteration is CG with the Hestenes-Stiefel
-    form of beta, equal to Algorithm 1 in exact arithmetic.
+    finite, or when the residual norm has not set a new best by the factor
+    `stall` for `window` iterations (a preconditioned iteration minimises the
+    error in the N-norm, so ||r|| may pause for a few iterations while it
+    still converges).  With M = I the iteration is CG with the
+    Hestenes-Stiefel form of beta, equal to Algorithm 1 in exact arithmetic.
     """
     x = np.zeros_like(b)
     r = b.copy()
@@ -390,6 +392,7 @@ def fpcg(apply_N, b: np.ndarray, precond, max_iter: int, rtol: float = 0.0,
     if not (np.all(np.isfinite(z)) and np.isfinite(zr) and zr > 0):
         fallback_at, z = 0, r
     p = z.copy()
+    best, kbest = 1.0, 0
     k = 0
     for k in range(max_iter):
         Ap = apply_N(p)
@@ -400,10 +403,12 @@ def fpcg(apply_N, b: np.ndarray, precond, max_iter: int, rtol: float = 0.0,
         hist.append(np.sqrt(dot(r, r)) / nb if nb > 0 else 0.0)
         if hist[-1] < rtol or k == max_iter - 1:
             break
+        if hist[-1] < stall * best:
+            best, kbest = hist[-1], k + 1
         if fallback_at is None:
             z = precond(r)
             zr = dot(z, r)
-            stalled = k >= 2 and hist[k + 1] > stall * hist[k - 2]
+            stalled = k + 1 - kbest >= window
             if stalled or not (np.all(np.isfinite(z)) and np.isfinite(zr) and zr > 0):
                 fallback_at = k + 1
                 p = r.copy()

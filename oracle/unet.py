@@ -30,8 +30,10 @@ conv1x1 [co][ci].
 Loss of the scaling preconditioner: the network maps the inputs of one shot
 to o(x) and the correction is z = exp(o) r.  With a(x) = sum_t r^2 and
 c(x) = sum_t r e (e the error x_ref - x_k), the squared error sum_{x,t}
-(exp(o) r - e)^2 equals sum_x a exp(2o) - 2 c exp(o) + const; the loss is that
-sum divided by sum_x a, averaged over the batch.
+(exp(o) r - e)^2 equals sum_x a exp(2o) - 2 c exp(o) + const.  Per sample the
+loss is that sum times sum_x a / (sum_x c)^2: 0 for z = 0 and -1 for the best
+single scale sum c / sum a, lower for a better cell scaling; the batch loss
+is the mean over samples.
 """
 from __future__ import annotations
 
@@ -233,19 +235,26 @@ def backward(flat, cache, go):
 def scaling_loss(o, a, c):
     """Loss of the scaling preconditioner and dL/do.
 
-    o, a, c: [n,1,H,W]; per sample L_s = sum_x (a e^{2o} - 2 c e^{o}) / sum_x a,
-    L = mean_s L_s.
+    o, a, c: [n,1,H,W]; per sample L_s = sum_x (a e^{2o} - 2 c e^{o}) sum_x a /
+    (sum_x c)^2; L = mean_s L_s.
     """
     n = o.shape[0]
-    den = a.reshape(n, -1).sum(axis=1)[:, None, None, None]
+    sa = a.reshape(n, -1).sum(axis=1)
+    sc = c.reshape(n, -1).sum(axis=1)
+    den = (sc * sc / sa)[:, None, None, None]
     s = np.exp(o)
     L = float(np.mean(((a * s * s - 2.0 * c * s) / den).reshape(n, -1).sum(axis=1)))
     go = (2.0 * a * s * s - 2.0 * c * s) / den / n
     return L, go
 
 
-def adam_step(theta, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
-    """One Adam update (Kingma & Ba 2015) of flat float64 arrays; t counts from 1."""
+def adam_step(theta, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8, clip=0.0):
+    """One Adam update (Kingma & Ba 2015) of flat float64 arrays; t counts from
+    1.  With clip > 0 the gradient is first scaled to norm at most clip."""
+    if clip > 0:
+        nrm = np.sqrt(np.sum(g * g))
+        if nrm > clip:
+            g = g * (clip / nrm)
     m = b1 * m + (1.0 - b1) * g
     v = b2 * v + (1.0 - b2) * g * g
     mh = m / (1.0 - b1 ** t)
@@ -254,7 +263,7 @@ def adam_step(theta, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
 
 
 def precond_inputs(r, v, w2):
-    """Network input of one shot: [rms_t r / mean_x(rms_t r), v / 3000, B / 100].
+    """Network input of one shot: [log(1 + rms_t r / mean_x(rms_t r)), v / 3000, B / 100].
 
     r: [nt, nz, nx] residual; v: [nz, nx] m/s; w2 = B^2 on the physical grid.
     Also returns a = sum_t r^2, the per-cell energy of r.
@@ -262,5 +271,5 @@ def precond_inputs(r, v, w2):
     a = np.sum(np.asarray(r, np.float64) ** 2, axis=0)
     rms = np.sqrt(a / r.shape[0])
     mu = rms.mean()
-    ch0 = rms / mu if mu > 0 else rms
+    ch0 = np.log1p(rms / mu if mu > 0 else rms)
     return np.stack([ch0, np.asarray(v, np.float64) / 3000.0, np.sqrt(w2) / 100.0]), a

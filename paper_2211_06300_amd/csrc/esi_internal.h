@@ -282,7 +282,7 @@ esi_status_t launch_energy(Plan* P, const float* r, const int* active, float* a,
 esi_status_t launch_stats(Plan* P, const float* r, const float* x, const float* p, const double* alpha,
                           const float* xref, const int* iters, int k, float* out, int ns);
 esi_status_t launch_features(Plan* P, int shot0, int ns, const float* a, const float* c, double* mean, int Hp,
-                             int Wp, float* xin, float* apad, float* cpad);
+                             int Wp, const float* base, float* xin, float* apad, float* cpad);
 esi_status_t launch_fcg_zr_check_scale(Plan* P, const float* o, const float* fixed, const float* a,
                                        const int* active, int* mode, int* restart, int* fallback, int k,
                                        int Hp, int Wp, double* zr, float* S, int ns);
@@ -290,11 +290,11 @@ esi_status_t launch_scale_vec(Plan* P, float* p, const float* r, const float* S,
 esi_status_t launch_dot_scaled(Plan* P, const float* r, const float* y, const float* S, int ns, double* out);
 esi_status_t launch_fcg_beta(Plan* P, const double* zAp, const double* pAp, const int* restart, double* beta,
                              int ns);
-esi_status_t launch_fcg_init(Plan* P, int* mode, int* restart, int* fallback, int ns);
+esi_status_t launch_fcg_init(Plan* P, int* mode, int* restart, int* fallback, double* best, int* kbest, int ns);
 esi_status_t launch_fcg_control(Plan* P, const double* rr0, const double* rr_new, const double* pAp, int* active,
                                 int* finish, int* iters, int* status, double* hist, int hstride, int* ctl,
                                 double rtol, int max_iter, int* mode, int* restart, int* fallback, double stall,
-                                int ns);
+                                int window, double* best, int* kbest, int ns);
 esi_status_t unet_dims(esi_unet_t u, int* H, int* W, int* maxb);
 esi_status_t unet_forward_on(esi_unet_t u, hipStream_t stream, const float* x, float* o, int batch);
 

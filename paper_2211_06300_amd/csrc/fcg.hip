@@ -79,47 +79,50 @@ __global__ __launch_bounds__(NT) void k_feat_mean(const float* __restrict__ a, i
 }
 
 // Network input on the image padded to Hp x Wp (zero outside the grid):
-// [rms / mean(rms), v / 3000, B / 100] with rms = sqrt(a / nt) and B the
+// [log(1 + rms / mean(rms)), v / 3000, B / 100] with rms = sqrt(a / nt) and B the
 // annihilator weight |x - x_s| / dx + eps (in cells); also the padded copies
-// of a and c when asked for.
+// of a and c when asked for, as a s0^2 and c s0 for a base scale s0 (the
+// training maps of the correction exp(o) on top of s0).
 __global__ void k_features(const float* __restrict__ a, const float* __restrict__ c,
                            const double* __restrict__ mean, const float* __restrict__ v,
                            const int32_t* __restrict__ src, int shot0, float b_eps, int ns, int nz, int nx,
-                           int Hp, int Wp, int nt, float* __restrict__ xin, float* __restrict__ apad,
-                           float* __restrict__ cpad) {
+                           int Hp, int Wp, int nt, const float* __restrict__ base, float* __restrict__ xin,
+                           float* __restrict__ apad, float* __restrict__ cpad) {
     const int64_t img = (int64_t)Hp * Wp;
     for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < ns * img; i += (int64_t)gridDim.x * NT) {
         const int s = (int)(i / img);
         const int64_t q = i % img;
         const int iz = (int)(q / Wp), ix = (int)(q % Wp);
-        float f0 = 0.f, f1 = 0.f, f2 = 0.f, av = 0.f, cv = 0.f;
+        float f0 = 0.f, f1 = 0.f, f2 = 0.f, av = 0.f, cv = 0.f, av_out = 0.f, cv_out = 0.f;
         if (iz < nz && ix < nx) {
             const int64_t cell = (int64_t)iz * nx + ix;
             av = a[(int64_t)s * nz * nx + cell];
             if (c) cv = c[(int64_t)s * nz * nx + cell];
+            const float b0 = base ? base[(int64_t)s * nz * nx + cell] : 1.f;
             const double m = mean[s];
             const float rms = sqrtf(av / (float)nt);
-            f0 = m > 0.0 ? (float)(rms / m) : rms;
+            f0 = log1pf(m > 0.0 ? (float)(rms / m) : rms);
             f1 = v[cell] / 3000.f;
             const float dx = (float)(ix - src[3 * (shot0 + s)]), dz = (float)(iz - src[3 * (shot0 + s) + 1]);
             f2 = (sqrtf(dx * dx + dz * dz) + b_eps) / 100.f;
+            av_out = av * b0 * b0;
+            cv_out = cv * b0;
         }
         float* xs = xin + (int64_t)s * 3 * img;
         xs[q] = f0;
         xs[img + q] = f1;
         xs[2 * img + q] = f2;
-        if (apad) apad[i] = av;
-        if (cpad) cpad[i] = cv;
+        if (apad) apad[i] = av_out;
+        if (cpad) cpad[i] = cv_out;
     }
 }
 
-// Candidate scale of cell x of shot s: exp(o) from the network, a fixed scale,
-// or 1.
+// Candidate scale of cell x of shot s: the fixed scale (or 1) times exp(o)
+// when the network runs.
 __device__ __forceinline__ float cand_scale(const float* o, const float* fixed, int s, int iz, int ix, int nz,
                                             int nx, int Hp, int Wp) {
-    if (o) return expf(o[((int64_t)s * Hp + iz) * Wp + ix]);
-    if (fixed) return fixed[((int64_t)s * nz + iz) * nx + ix];
-    return 1.f;
+    const float f = fixed ? fixed[((int64_t)s * nz + iz) * nx + ix] : 1.f;
+    return o ? f * expf(o[((int64_t)s * Hp + iz) * Wp + ix]) : f;
 }
 
 // zr[s] = sum_x s(x) a(x) = z.r for the candidate scale (1 for shots in CG mode).
@@ -200,23 +203,28 @@ __global__ void k_fcg_beta(const double* __restrict__ zAp, const double* __restr
     if (s < n) beta[s] = restart[s] ? 0.0 : -zAp[s] / pAp[s];
 }
 
-__global__ void k_fcg_init(int* __restrict__ mode, int* __restrict__ restart, int* __restrict__ fallback, int n) {
+__global__ void k_fcg_init(int* __restrict__ mode, int* __restrict__ restart, int* __restrict__ fallback,
+                           double* __restrict__ best, int* __restrict__ kbest, int n) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s < n) {
         mode[s] = 0;
         restart[s] = 0;
         fallback[s] = -1;
+        best[s] = 1.0;
+        kbest[s] = 0;
     }
 }
 
 // After iteration k of every active shot: the stopping test of k_cg_control,
-// then the stall test of the flexible iteration (||r_{k+1}|| > stall
-// ||r_{k-2}||: plain CG takes over, the direction restarts).
+// then the stall test of the flexible iteration (no new best ||r|| by the
+// factor `stall` for `window` iterations: plain CG takes over, the direction
+// restarts).  best / kbest: best relative residual so far and its iteration.
 __global__ void k_fcg_control(const double* __restrict__ rr0, const double* __restrict__ rr_new,
                               const double* __restrict__ pAp, int* __restrict__ active, int* __restrict__ finish,
                               int* __restrict__ iters, int* __restrict__ status, double* __restrict__ hist,
                               int hstride, int* __restrict__ ctl, double rtol, int max_iter, int* __restrict__ mode,
-                              int* __restrict__ restart, int* __restrict__ fallback, double stall, int n) {
+                              int* __restrict__ restart, int* __restrict__ fallback, double stall, int window,
+                              double* __restrict__ best, int* __restrict__ kbest, int n) {
     __shared__ int cnt;
     const int k = ctl[0];
     if (threadIdx.x == 0) cnt = 0;
@@ -238,10 +246,16 @@ __global__ void k_fcg_control(const double* __restrict__ rr0, const double* __re
                 f = 2;
             } else if (rel < rtol || k == max_iter - 1) {
                 f = 1;
-            } else if (!mode[s] && k >= 2 && rel > stall * h[k - 2]) {
-                mode[s] = 1;
-                restart[s] = 1;
-                fallback[s] = k + 1;
+            } else {
+                if (rel < stall * best[s]) {
+                    best[s] = rel;
+                    kbest[s] = k + 1;
+                }
+                if (!mode[s] && k + 1 - kbest[s] >= window) {
+                    mode[s] = 1;
+                    restart[s] = 1;
+                    fallback[s] = k + 1;
+                }
             }
             if (f) active[s] = 0;
             else atomicAdd(&cnt, 1);
@@ -273,11 +287,11 @@ esi_status_t launch_stats(Plan* P, const float* r, const float* x, const float* 
 }
 
 esi_status_t launch_features(Plan* P, int shot0, int ns, const float* a, const float* c, double* mean, int Hp,
-                             int Wp, float* xin, float* apad, float* cpad) {
+                             int Wp, const float* base, float* xin, float* apad, float* cpad) {
     hipLaunchKernelGGL(k_feat_mean, dim3(ns), dim3(NT), 0, P->stream, a, P->nphys, P->nt, mean);
     hipLaunchKernelGGL(k_features, dim3(grid_for((int64_t)ns * Hp * Wp)), dim3(NT), 0, P->stream, a, c, mean,
-                       P->vphys, P->d_src, shot0, (float)P->b_eps, ns, P->nz, P->nx, Hp, Wp, P->nt, xin, apad,
-                       cpad);
+                       P->vphys, P->d_src, shot0, (float)P->b_eps, ns, P->nz, P->nx, Hp, Wp, P->nt, base, xin,
+                       apad, cpad);
     ESI_HIP_TRY(hipGetLastError());
     return ESI_OK;
 }
@@ -317,8 +331,9 @@ esi_status_t launch_fcg_beta(Plan* P, const double* zAp, const double* pAp, cons
     return ESI_OK;
 }
 
-esi_status_t launch_fcg_init(Plan* P, int* mode, int* restart, int* fallback, int ns) {
-    hipLaunchKernelGGL(k_fcg_init, dim3((ns + 63) / 64), dim3(64), 0, P->stream, mode, restart, fallback, ns);
+esi_status_t launch_fcg_init(Plan* P, int* mode, int* restart, int* fallback, double* best, int* kbest, int ns) {
+    hipLaunchKernelGGL(k_fcg_init, dim3((ns + 63) / 64), dim3(64), 0, P->stream, mode, restart, fallback, best,
+                       kbest, ns);
     ESI_HIP_TRY(hipGetLastError());
     return ESI_OK;
 }
@@ -326,9 +341,10 @@ esi_status_t launch_fcg_init(Plan* P, int* mode, int* restart, int* fallback, in
 esi_status_t launch_fcg_control(Plan* P, const double* rr0, const double* rr_new, const double* pAp, int* active,
                                 int* finish, int* iters, int* status, double* hist, int hstride, int* ctl,
                                 double rtol, int max_iter, int* mode, int* restart, int* fallback, double stall,
-                                int ns) {
+                                int window, double* best, int* kbest, int ns) {
     hipLaunchKernelGGL(k_fcg_control, dim3(1), dim3(256), 0, P->stream, rr0, rr_new, pAp, active, finish, iters,
-                       status, hist, hstride, ctl, rtol, max_iter, mode, restart, fallback, stall, ns);
+                       status, hist, hstride, ctl, rtol, max_iter, mode, restart, fallback, stall, window, best,
+                       kbest, ns);
     ESI_HIP_TRY(hipGetLastError());
     return ESI_OK;
 }

@@ -365,9 +365,9 @@ __global__ void k_out_back(const float* __restrict__ go, const bf16_t* __restric
     }
 }
 
-// Scaling loss per sample s: L_s = sum_x (a e^{2o} - 2 c e^{o}) / sum_x a and
-// go = (2 a e^{2o} - 2 c e^{o}) / sum_x a / nbatch.  One workgroup per sample;
-// loss[s] in float64.
+// Scaling loss per sample s: L_s = sum_x (a e^{2o} - 2 c e^{o}) / q with
+// q = (sum_x c)^2 / sum_x a, and go = (2 a e^{2o} - 2 c e^{o}) / q / nbatch.
+// One workgroup per sample; loss[s] in float64.
 __global__ __launch_bounds__(NT) void k_scaling_loss(const float* __restrict__ o, const float* __restrict__ a,
                                                      const float* __restrict__ c, int64_t npix, int nbatch,
                                                      float* __restrict__ go, double* __restrict__ loss) {
@@ -386,9 +386,14 @@ __global__ __launch_bounds__(NT) void k_scaling_loss(const float* __restrict__ o
         for (int k = 0; k < NT / 64; ++k) t += red[k];
         return t;
     };
-    double sa = 0.0;
-    for (int64_t p = threadIdx.x; p < npix; p += NT) sa += as[p];
-    sa = block_sum(sa);
+    double suma = 0.0, sumc = 0.0;
+    for (int64_t p = threadIdx.x; p < npix; p += NT) {
+        suma += as[p];
+        sumc += cs[p];
+    }
+    suma = block_sum(suma);
+    sumc = block_sum(sumc);
+    const double sa = suma > 0.0 ? sumc * sumc / suma : 0.0;
     const float inv = sa > 0.0 ? (float)(1.0 / sa) : 0.f;
     double sl = 0.0;
     for (int64_t p = threadIdx.x; p < npix; p += NT) {
@@ -401,12 +406,39 @@ __global__ __launch_bounds__(NT) void k_scaling_loss(const float* __restrict__ o
     if (threadIdx.x == 0) loss[s] = sl * (sa > 0.0 ? 1.0 / sa : 0.0);
 }
 
-// Adam (Kingma & Ba 2015) on the float32 master parameters.
+// Squared gradient norm: partials per block, summed by k_norm_finish.
+__global__ __launch_bounds__(NT) void k_sqnorm(const float* __restrict__ g, int64_t n, double* __restrict__ part) {
+    __shared__ double red[NT / 64];
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+        acc += (double)g[i] * (double)g[i];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < NT / 64; ++k) t += red[k];
+        part[blockIdx.x] = t;
+    }
+}
+
+// factor[0] = min(1, clip / ||g||) from the block partials (one thread).
+__global__ void k_clip_factor(const double* __restrict__ part, int nb, float clip, float* __restrict__ factor) {
+    if (threadIdx.x != 0) return;
+    double t = 0.0;
+    for (int k = 0; k < nb; ++k) t += part[k];
+    const double nrm = sqrt(t);
+    factor[0] = (clip > 0.f && nrm > clip) ? (float)(clip / nrm) : 1.f;
+}
+
+// Adam (Kingma & Ba 2015) on the float32 master parameters, the gradient
+// scaled by factor[0] (gradient-norm clipping) when factor is given.
 __global__ void k_adam(float* __restrict__ th, float* __restrict__ m, float* __restrict__ v,
                        const float* __restrict__ g, int64_t n, float lr, float b1, float b2, float eps,
-                       float bc1, float bc2) {
+                       float bc1, float bc2, const float* __restrict__ factor) {
+    const float f = factor ? factor[0] : 1.f;
     for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
-        const float gi = g[i];
+        const float gi = g[i] * f;
         const float mi = b1 * m[i] + (1.f - b1) * gi;
         const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
         m[i] = mi;
@@ -865,15 +897,24 @@ extern "C" esi_status_t esi_unet_loss_grad(esi_unet_t u, const float* x, const f
 }
 
 extern "C" esi_status_t esi_unet_adam(esi_unet_t u, const float* grad, float lr, float beta1, float beta2,
-                                      float eps, int32_t step) {
+                                      float eps, int32_t step, float clip_norm) {
     set_error("");
     if (!u || !grad) return fail(ESI_ERR_ARG, "null argument");
     if (step < 1) return fail(ESI_ERR_ARG, "Adam step counts from 1");
     Unet* U = as_unet(u);
     const float bc1 = (float)(1.0 - std::pow((double)beta1, step));
     const float bc2 = (float)(1.0 - std::pow((double)beta2, step));
+    float* factor = nullptr;
+    if (clip_norm > 0.f) {
+        const int nb = 256;
+        ESI_TRY(grow_t(&U->part, &U->part_cap, (int64_t)2 * nb + 2, U->stream));
+        double* part = reinterpret_cast<double*>(U->part);
+        factor = U->part + 2 * nb;
+        hipLaunchKernelGGL(k_sqnorm, dim3(nb), dim3(NT), 0, U->stream, grad, U->P, part);
+        hipLaunchKernelGGL(k_clip_factor, dim3(1), dim3(64), 0, U->stream, part, nb, clip_norm, factor);
+    }
     hipLaunchKernelGGL(k_adam, dim3(grid_for(U->P)), dim3(NT), 0, U->stream, U->theta, U->m, U->v, grad, U->P,
-                       lr, beta1, beta2, eps, bc1, bc2);
+                       lr, beta1, beta2, eps, bc1, bc2, factor);
     ESI_HIP_TRY(hipGetLastError());
     return pack(U);
 }

@@ -87,7 +87,7 @@ def load_library(path: str = LIB_PATH):
     L.esi_grad_velocity.argtypes = [vp, vp, vp, vp]
     L.esi_plan_profile_read.argtypes = [vp, i32, vp, vp, vp, vp, vp]
     L.esi_fpcg_solve.argtypes = [vp, i32, i32, vp, vp, vp, i32, dbl, vp, vp, ctypes.POINTER(_CgReport)]
-    L.esi_precond_features.argtypes = [vp, i32, i32, vp, vp, i32, i32, vp, vp, vp]
+    L.esi_precond_features.argtypes = [vp, i32, i32, vp, vp, vp, i32, i32, vp, vp, vp]
     L.esi_unet_num_params.argtypes = []
     L.esi_unet_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, vp]
     L.esi_unet_destroy.argtypes = [vp]
@@ -95,7 +95,8 @@ def load_library(path: str = LIB_PATH):
     L.esi_unet_get_params.argtypes = [vp, vp]
     L.esi_unet_forward.argtypes = [vp, vp, vp, i32]
     L.esi_unet_loss_grad.argtypes = [vp, vp, vp, vp, i32, vp, ctypes.POINTER(dbl)]
-    L.esi_unet_adam.argtypes = [vp, vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, i32]
+    L.esi_unet_adam.argtypes = [vp, vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, i32,
+                                ctypes.c_float]
     for f in EXPORTS:
         if f != "esi_last_error":
             getattr(L, f).restype = ctypes.c_int
@@ -292,9 +293,9 @@ class Plan:
                                         ctypes.byref(rep)))
         return x, {"iters": int(rep.iters), "shot_iters": iters, "res_hist": hist, "fallback": fb}
 
-    def precond_features(self, a, Hp, Wp, cmap=None, shot0=0, nshots=None, pads=False):
+    def precond_features(self, a, Hp, Wp, cmap=None, base=None, shot0=0, nshots=None, pads=False):
         """Network input [nshots, 3, Hp, Wp] from a = sum_t r^2 [nshots, *phys];
-        with pads=True also the zero-padded a and cmap."""
+        with pads=True also the zero-padded a base^2 and cmap base."""
         shot0, nshots = self._range(shot0, nshots)
         xin = torch.empty((nshots, 3, Hp, Wp), dtype=torch.float32, device=self.device)
         ap = torch.empty((nshots, Hp, Wp), dtype=torch.float32, device=self.device) if pads else None
@@ -302,6 +303,7 @@ class Plan:
         _check(self._lib.esi_precond_features(self._h, shot0, nshots,
                                               _f32(a, (nshots, *self.phys_shape), "a"),
                                               None if cmap is None else _f32(cmap, (nshots, *self.phys_shape), "cmap"),
+                                              None if base is None else _f32(base, (nshots, *self.phys_shape), "base"),
                                               int(Hp), int(Wp), _ptr(xin), _ptr(ap), _ptr(cp)))
         return (xin, ap, cp) if pads else xin
 
@@ -392,6 +394,6 @@ class Unet:
                                             _f32(grad, (self.P,), "grad"), ctypes.byref(loss)))
         return grad, loss.value
 
-    def adam(self, grad, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
+    def adam(self, grad, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, clip=0.0):
         _check(self._lib.esi_unet_adam(self._h, _f32(grad, (self.P,), "grad"), float(lr), float(beta1),
-                                       float(beta2), float(eps), int(step)))
+                                       float(beta2), float(eps), int(step), float(clip)))

@@ -214,3 +214,23 @@ def he_init(segments, seed: int) -> np.ndarray:
         parts.append(rng.standard_normal(n) * np.sqrt(2.0 / fan))
         parts.append(np.zeros(nb))
     return np.concatenate(parts).astype(np.float32)
+
+
+def cfg_precond(seed: int, nx: int = 401, nz: int = 201, nshots: int = 4, nt: int = 1500,
+                sigma: float | None = None) -> Config:
+    """A model of the learned-preconditioner workloads: the single-solve
+    recipe (water over 5 layers with 3 anomalies, dx 12.5 m, 8 Hz Ricker,
+    receivers every 2nd cell and shots at depth cell 2, beta 1e-2) on an
+    nx x nz grid with `nshots` evenly spaced shots and nt steps of 1 ms; start
+    model smoothed with sigma = 10 nz / 401 cells.  Training models use seeds
+    5000..5199 at 401 x 201, held-out models seeds 6000..6009 at 801 x 401."""
+    v_true = layered_model(nz, nx, seed)
+    v_start = smooth_model(v_true, 10.0 * nz / 401.0 if sigma is None else sigma)
+    xs = np.round(np.linspace(12, nx - 13, nshots)).astype(np.int32)
+    src = np.stack([xs, np.full(nshots, 2)], axis=1).astype(np.int32)
+    rx = np.arange(0, nx, 2)
+    rec1 = np.stack([rx, np.full(rx.size, 2)], axis=1).astype(np.int32)
+    ptr, rr = _csr([rec1] * nshots)
+    return Config(f"precond-{nx}x{nz}-seed{seed}", 2, nz, nx, 1, 12.5, 1e-3, nt, 20, 8.0, 1e-2, 0,
+                  v_true.astype(np.float32), v_start.astype(np.float32), src, ptr, rr,
+                  ricker_samples(nt, 1e-3, 8.0))

@@ -98,11 +98,18 @@ def test_precond_features_match_oracle(esi):
     r = inputs.random_field((2, cfg.nt, cfg.nz, cfg.nx), 50)
     a = (r.astype(np.float64) ** 2).sum(axis=1).astype(np.float32)
     Hp, Wp = 40, 72
-    xin = plan.precond_features(torch.from_numpy(a).to(DEV), Hp, Wp).cpu().numpy()
+    c = inputs.random_field((2, cfg.nz, cfg.nx), 51)
+    base = (np.random.default_rng(52).random((2, cfg.nz, cfg.nx)) + 0.5).astype(np.float32)
+    xin, ap, cp = plan.precond_features(torch.from_numpy(a).to(DEV), Hp, Wp, cmap=torch.from_numpy(c).to(DEV),
+                                        base=torch.from_numpy(base).to(DEV), pads=True)
+    xin, ap, cp = xin.cpu().numpy(), ap.cpu().numpy(), cp.cpu().numpy()
     for s in range(2):
         ref, a_ref = ounet.precond_inputs(r[s], cfg.v_start, core.annihilator_sq(g, cfg.src[s]))
         np.testing.assert_allclose(xin[s, :, :cfg.nz, :cfg.nx], ref, rtol=2e-6, atol=1e-7)
         assert np.all(xin[s, :, cfg.nz:, :] == 0) and np.all(xin[s, :, :, cfg.nx:] == 0)
+        np.testing.assert_allclose(ap[s, :cfg.nz, :cfg.nx], a[s] * base[s] ** 2, rtol=1e-6)
+        np.testing.assert_allclose(cp[s, :cfg.nz, :cfg.nx], c[s] * base[s], rtol=1e-6)
+        assert np.all(ap[s, cfg.nz:, :] == 0) and np.all(cp[s, :, cfg.nx:] == 0)
 
 
 def test_fpcg_training_maps(esi):
@@ -134,7 +141,9 @@ def test_fpcg_with_network(esi):
     theta = inputs.he_init(ounet.fan_segments(), 3)
     theta[:] *= 0.3
     net.set_params(torch.from_numpy(theta).to(DEV))
-    x, rep = plan.fpcg_solve(flat, max_iter=40, rtol=0.05, net=net)
+    S0 = torch.from_numpy(np.stack([(1.0 / (cfg.beta * core.annihilator_sq(g, cfg.src[s]) + 0.03))
+                                    .astype(np.float32) for s in range(2)])).to(DEV)
+    x, rep = plan.fpcg_solve(flat, max_iter=40, rtol=0.05, net=net, scale=S0)
     print("network FCG iterations", rep["shot_iters"], "fallback", rep["fallback"])
     assert np.all(np.isfinite(x.cpu().numpy()))
     b = plan.adjoint(flat)

@@ -73,9 +73,9 @@ def test_unet_adam_step(esi):
                          torch.from_numpy(c).to(DEV))
     gh = g.cpu().numpy().astype(np.float64)
     net.adam(g, lr=1e-3, step=1)
-    net.adam(g, lr=1e-3, step=2)
+    net.adam(g, lr=1e-3, step=2, clip=0.5 * float(np.linalg.norm(gh)))
     th = net.get_params().cpu().numpy()
     ref, m, v = ounet.adam_step(theta.astype(np.float64), gh, 0 * gh, 0 * gh, 1, 1e-3)
-    ref, m, v = ounet.adam_step(ref, gh, m, v, 2, 1e-3)
+    ref, m, v = ounet.adam_step(ref, gh, m, v, 2, 1e-3, clip=0.5 * float(np.linalg.norm(gh)))
     assert np.max(np.abs(th - ref)) < 1e-6
     net.close()
