@@ -116,6 +116,63 @@ def cpu_baseline(cfg, nt_sample: int, iters: int = 3):
                       f"{cfg.nx}x{cfg.nz} grid in {t:.1f} s"}
 
 
+def unet_flops(H: int, W: int) -> int:
+    """Multiply-adds x 2 of one network forward pass on an H x W image (real
+    channel counts; the 3 input channels count as 3)."""
+    from paper_2211_06300_amd import unet_layout
+    lvl = {"c1a": 0, "c1b": 0, "c2a": 1, "c2b": 1, "c3a": 2, "c3b": 2, "c4a": 3, "c4b": 3, "u3": 3,
+           "d3a": 2, "d3b": 2, "u2": 2, "d2a": 1, "d2b": 1, "u1": 1, "d1a": 0, "d1b": 0, "out": 0}
+    macs = 0
+    for name, kind, ci, co in unet_layout.LAYERS:
+        px = (H >> lvl[name]) * (W >> lvl[name])
+        macs += px * ci * co * {"c3": 9, "t2": 4, "c1": 1}[kind]
+    return 2 * macs
+
+
+def solver_comparison(args, torch, dev):
+    """Plain CG vs flexible CG (analytic scale, learned correction) to a
+    relative residual of 1e-3 on a held-out model, and the network's forward
+    throughput on the MFMA units."""
+    from paper_2211_06300_amd import esi, inputs, precond
+    wpath = os.path.join(ROOT, "paper_2211_06300_amd", "weights", "precond_unet.npy")
+    theta = torch.from_numpy(np.load(wpath)).to(dev)
+    cfg = inputs.cfg_precond(args.solve_seed, nx=801, nz=401, nshots=args.solve_shots, nt=args.nt)
+    log(f"solver comparison on {cfg.name}: {cfg.nshots} shots, nt {cfg.nt}, to 1e-3")
+    res = precond.compare_solvers(cfg, theta, rtol=1e-3, max_iter=args.solve_iters, log=log)
+    # network forward throughput (batch = shots, 408 x 808 images)
+    H, W = precond.pad8(cfg.nz), precond.pad8(cfg.nx)
+    net = esi.Unet(H, W, cfg.nshots, device=dev)
+    net.set_params(theta)
+    x = torch.rand((cfg.nshots, 3, H, W), dtype=torch.float32, device=dev)
+    for _ in range(3):
+        net.forward(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        net.forward(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    net.close()
+    flops = unet_flops(H, W) * cfg.nshots
+    tfs = flops / (ms * 1e-3) / 1e12
+    out = {"workload": cfg.name, "shots": cfg.nshots, "nt": cfg.nt, "rtol": 1e-3,
+           "max_iter": args.solve_iters}
+    for k, v in res.items():
+        out[k] = {"iterations": v["iters"], "seconds": round(v["seconds"], 3),
+                  "reached_rtol": v["converged"],
+                  "true_residual_max": round(max(v["true_residual"]), 6),
+                  "fallback": v["fallback"]}
+    if "learned" in res and "plain" in res:
+        out["speedup_learned_vs_plain_wall"] = round(res["plain"]["seconds"] / res["learned"]["seconds"], 3)
+        out["speedup_learned_vs_analytic_wall"] = round(res["analytic"]["seconds"] / res["learned"]["seconds"], 3)
+    out["network_forward"] = {"images": cfg.nshots, "image": f"{W}x{H}", "ms": round(ms, 3),
+                              "tflops": round(tfs, 2), "bound": "mfma", "peak_tflops": 2500.0,
+                              "frac": round(tfs / 2500.0, 4), "dtype": "bf16 (fp32 accumulate)"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,6 +184,10 @@ def main():
     ap.add_argument("--nt", type=int, default=2000)
     ap.add_argument("--cpu-nt", type=int, default=1000, help="steps in the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-solve", action="store_true", help="skip the plain vs learned CG comparison")
+    ap.add_argument("--solve-seed", type=int, default=6000)
+    ap.add_argument("--solve-shots", type=int, default=8)
+    ap.add_argument("--solve-iters", type=int, default=500)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="also run one elementwise copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -241,6 +302,11 @@ def main():
         "cg_final_rel_residual_max": float(np.max(hist[:, -1])),
         "kernel_loops": {k: {"launches": v["launches"], "ms": round(v["ms"], 1)} for k, v in prof.items()},
     }
+    plan.close()
+    del plan, x, work, d_obs
+    torch.cuda.empty_cache()
+    if not args.no_solve:
+        out["solve_to_1e-3"] = solver_comparison(args, torch, dev)
     if not args.no_cpu:
         log("timing the oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_nt)

@@ -149,8 +149,10 @@ typedef struct {
     double* res_hist;    /* host [nshots][max_iter+1] out, or NULL: ||r_k|| / ||r_0|| of
                             the recursively updated residual; unused entries set to -1 */
     /* esi_fpcg_solve only (ignored by esi_cg_solve; set to NULL there): */
-    int32_t* shot_fallback; /* host [nshots] out, or NULL: iteration after which plain CG
-                               took over, -1 if it never did */
+    int32_t* shot_fallback; /* host [nshots] out, or NULL: iteration after which the first
+                               preconditioner was given up, -1 if never */
+    int32_t* shot_cg;       /* host [nshots] out, or NULL: iteration after which plain CG
+                               took over, -1 if never */
     const float* stat_xref; /* device [nshots][nt][phys] reference solution, or NULL */
     float* stat_out;        /* device [max_iter+1][nshots][2][phys], or NULL: for the iterate
                                x_k and residual r_k of every iteration k reached, the cell maps
@@ -274,14 +276,18 @@ esi_status_t esi_plan_profile_read(esi_plan_t plan, int32_t cap, int32_t* count,
  * p = z + beta p.  The preconditioner scales the residual cell by cell,
  * z = s r, with s = s0 exp(o):
  *   scale: s0, device [nshots][phys], or NULL for s0 = 1;
- *   net:   o = Net(features) recomputed every iteration from the residual's
- *          per-cell energy (see esi_precond_features), or NULL for o = 0;
- *          the network must take Hp x Wp images (nz, nx rounded up to
- *          multiples of 8) in batches of at least nshots.
+ *   net:   o = Net(features) from the residual's per-cell energy (see
+ *          esi_precond_features), or NULL for o = 0; the network must take
+ *          Hp x Wp images (nz, nx rounded up to multiples of 8) in batches of
+ *          at least nshots.  It runs on r_0 and then every net_every-th
+ *          iteration (net_every = 0: once, so the preconditioner is fixed
+ *          and the iteration is preconditioned CG).
  * Both NULL is CG with beta in Hestenes-Stiefel form.
- * A shot falls back to plain CG (s = 1 from then on, the direction restarted
- * at p = r) when z.r <= 0 or is not finite, or when ||r|| has not reached a
- * new best by 1 % for 10 iterations.  Stopping as esi_cg_solve: ||r_{k+1}|| < rtol ||r_0|| of the
+ * A shot gives up its preconditioner when z.r <= 0 or is not finite, or when
+ * ||r|| has not reached a new best by 1 % for 20 iterations: with a network
+ * it drops the correction (s = s0), then, and without one at once, it falls
+ * back to plain CG (s = 1); each switch restarts the direction at p = z and
+ * the 20-iteration window.  Stopping as esi_cg_solve: ||r_{k+1}|| < rtol ||r_0|| of the
  * recursively updated residual, or max_iter.
  *   d_obs, x, work, max_iter, rtol: as esi_cg_solve (work: 3 vectors).
  *   rep: as esi_cg_solve, plus shot_fallback and the training maps
@@ -291,13 +297,13 @@ esi_status_t esi_plan_profile_read(esi_plan_t plan, int32_t cap, int32_t* count,
  */
 esi_status_t esi_fpcg_solve(esi_plan_t plan, int32_t shot0, int32_t nshots, const float* d_obs,
                             float* x, float* work, int32_t max_iter, double rtol, esi_unet_t net,
-                            const float* scale, esi_cg_report_t* rep);
+                            int32_t net_every, const float* scale, esi_cg_report_t* rep);
 
 /*
  * Network input of the preconditioner for `nshots` shots of a 2D plan, on
  * images padded to Hp x Wp (multiples of 8, at least nz x nx; zero outside
  * the grid): channel 0 = log(1 + rms_t(r) / mean_x rms_t(r)) with
- * rms_t(r) = sqrt(a/nt), channel 1 = v / 3000 m/s, channel 2 = B / 100
+ * rms_t(r) = sqrt(a/nt), channel 1 = v / 3000 m/s, channel 2 = log(B) / 4
  * (B = |x - x_s| / dx + eps, in cells).
  *   a:    device [nshots][phys], a = sum_t r^2 of each shot's residual.
  *   cmap: device [nshots][phys] or NULL (c = sum_t r e of a training pair).
@@ -355,13 +361,21 @@ esi_status_t esi_unet_forward(esi_unet_t net, const float* x, float* o, int32_t 
 
 /* Loss of the scaling preconditioner and its gradient.  For each image s,
  * with a = sum_t r^2 and c = sum_t r e (device [batch][H][W], zero on padding
- * pixels), L_s = sum_x (a e^{2o} - 2 c e^{o}) sum_x a / (sum_x c)^2: the
- * squared error of exp(o) r against e up to a constant, scaled so that 0 is
- * no correction and -1 the best single scale; L = mean_s L_s.  Writes
- * dL/dtheta into grad (device [P], overwritten) and L into *loss (host, may
- * be NULL; non-NULL synchronises). */
+ * pixels), L_s = w_s sum_x (a e^{2o} - 2 c e^{o}): the squared error of
+ * exp(o) r against e up to a constant; L = mean_s L_s.  weight: device
+ * [batch] w_s, or NULL for the default of each image (esi_unet_loss_weights),
+ * which scales the loss so that 0 is no correction and -1 the best single
+ * scale.  Writes dL/dtheta into grad (device [P], overwritten) and L into
+ * *loss (host, may be NULL; non-NULL synchronises). */
 esi_status_t esi_unet_loss_grad(esi_unet_t net, const float* x, const float* a, const float* c,
-                                int32_t batch, float* grad, double* loss);
+                                const float* weight, int32_t batch, float* grad, double* loss);
+
+/* Default loss weights of `batch` images of npix pixels on `hip_stream`:
+ * w = sum a / (sum c)^2, 0 when sum c <= 0 (a, c device [batch][npix], w
+ * device [batch] out).  Tiles cut from a larger image take the whole image's
+ * weight. */
+esi_status_t esi_unet_loss_weights(const float* a, const float* c, int32_t batch, int64_t npix,
+                                   float* w, void* hip_stream);
 
 /* One Adam step (Kingma & Ba) on the master parameters with gradient grad
  * (device [P]); step counts from 1.  clip_norm > 0 first scales the gradient

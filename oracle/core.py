@@ -362,11 +362,12 @@ class FPCGResult:
     x: np.ndarray
     iters: int
     res_hist: list          # ||r_k|| / ||r_0||
-    fallback_at: int | None  # iteration after which plain CG took over, or None
+    fallback_at: int | None  # iteration after which the first preconditioner was given up, or None
+    cg_at: int | None        # iteration after which plain CG took over, or None
 
 
 def fpcg(apply_N, b: np.ndarray, precond, max_iter: int, rtol: float = 0.0,
-         stall: float = 0.99, window: int = 10) -> FPCGResult:
+         stall: float = 0.99, window: int = 20, precond_fallback=None) -> FPCGResult:
     """Flexible CG with truncation 1 (Notay 2000, FCG(1)) for N x = b.
 
     x_0 = 0, r_0 = b, z_0 = M(r_0), p_0 = z_0; per iteration alpha = p.r / p.Np,
@@ -374,23 +375,37 @@ def fpcg(apply_N, b: np.ndarray, precond, max_iter: int, rtol: float = 0.0,
     max_iter; z = M(r), beta = -z.Np / p.Np, p = z + beta p.  M may change from
     one call to the next.
 
-    Fallback to plain CG (M = I from then on, direction restarted at p = r,
-    the recursively updated residual kept) when z.r <= 0, when z or z.r is not
-    finite, or when the residual norm has not set a new best by the factor
-    `stall` for `window` iterations (a preconditioned iteration minimises the
-    error in the N-norm, so ||r|| may pause for a few iterations while it
-    still converges).  With M = I the iteration is CG with the
-    Hestenes-Stiefel form of beta, equal to Algorithm 1 in exact arithmetic.
+    The preconditioner is given up when z.r <= 0, when z or z.r is not finite,
+    or when the residual norm has not set a new best by the factor `stall` for
+    `window` iterations (a preconditioned iteration minimises the error in the
+    N-norm, so ||r|| may pause for a while and still converge).  It is then
+    replaced by `precond_fallback` if given and by plain CG (M = I) after
+    that; each switch restarts the direction at p = z, keeps the recursively
+    updated residual and opens a fresh stall window.  With M = I the iteration
+    is CG with the Hestenes-Stiefel form of beta, equal to Algorithm 1 in exact
+    arithmetic.
     """
+    stages = [precond] + ([precond_fallback] if precond_fallback is not None else []) + [None]
+    stage = 0
     x = np.zeros_like(b)
     r = b.copy()
     nb = np.sqrt(dot(b, b))
     hist = [1.0]
-    fallback_at = None
-    z = precond(r)
-    zr = dot(z, r)
-    if not (np.all(np.isfinite(z)) and np.isfinite(zr) and zr > 0):
-        fallback_at, z = 0, r
+    marks = []                      # iterations of the switches
+
+    def apply_m(res):
+        m = stages[stage]
+        return res.copy() if m is None else m(res)
+
+    def usable(z, res):
+        zr = dot(z, res)
+        return bool(np.all(np.isfinite(z)) and np.isfinite(zr) and zr > 0)
+
+    z = apply_m(r)
+    while stages[stage] is not None and not usable(z, r):
+        stage += 1
+        marks.append(0)
+        z = apply_m(r)
     p = z.copy()
     best, kbest = 1.0, 0
     k = 0
@@ -405,18 +420,21 @@ def fpcg(apply_N, b: np.ndarray, precond, max_iter: int, rtol: float = 0.0,
             break
         if hist[-1] < stall * best:
             best, kbest = hist[-1], k + 1
-        if fallback_at is None:
-            z = precond(r)
-            zr = dot(z, r)
-            stalled = k + 1 - kbest >= window
-            if stalled or not (np.all(np.isfinite(z)) and np.isfinite(zr) and zr > 0):
-                fallback_at = k + 1
-                p = r.copy()
-                continue
-        else:
-            z = r
+        z = apply_m(r)
+        if stages[stage] is not None and (k + 1 - kbest >= window or not usable(z, r)):
+            while True:                # give up this preconditioner: restart the direction
+                stage += 1
+                marks.append(k + 1)
+                z = apply_m(r)
+                if stages[stage] is None or usable(z, r):
+                    break
+            kbest, best = k + 1, hist[-1]
+            p = z.copy()
+            continue
         p = z - (dot(z, Ap) / pAp) * p
-    return FPCGResult(x, k + 1, hist, fallback_at)
+    fb = marks[0] if marks else None
+    cg = marks[-1] if marks and stages[stage] is None else None
+    return FPCGResult(x, k + 1, hist, fb, cg)
 
 
 def esi_cg(m: Model, src_pos, rec, d_obs, beta: float, max_iter: int, rtol: float = 0.0,

@@ -31,9 +31,10 @@ Loss of the scaling preconditioner: the network maps the inputs of one shot
 to o(x) and the correction is z = exp(o) r.  With a(x) = sum_t r^2 and
 c(x) = sum_t r e (e the error x_ref - x_k), the squared error sum_{x,t}
 (exp(o) r - e)^2 equals sum_x a exp(2o) - 2 c exp(o) + const.  Per sample the
-loss is that sum times sum_x a / (sum_x c)^2: 0 for z = 0 and -1 for the best
-single scale sum c / sum a, lower for a better cell scaling; the batch loss
-is the mean over samples.
+loss is that sum times a weight w, by default w = sum_x a / (sum_x c)^2 (0
+when sum_x c <= 0): 0 for z = 0 and -1 for the best single scale sum c /
+sum a, lower for a better cell scaling; the batch loss is the mean over
+samples.  Tiles of a larger image take the weight of the whole image.
 """
 from __future__ import annotations
 
@@ -232,19 +233,26 @@ def backward(flat, cache, go):
     return pack(G)
 
 
-def scaling_loss(o, a, c):
-    """Loss of the scaling preconditioner and dL/do.
-
-    o, a, c: [n,1,H,W]; per sample L_s = sum_x (a e^{2o} - 2 c e^{o}) sum_x a /
-    (sum_x c)^2; L = mean_s L_s.
-    """
-    n = o.shape[0]
+def loss_weights(a, c):
+    """Default per-sample weight sum_x a / (sum_x c)^2, 0 when sum_x c <= 0."""
+    n = a.shape[0]
     sa = a.reshape(n, -1).sum(axis=1)
     sc = c.reshape(n, -1).sum(axis=1)
-    den = (sc * sc / sa)[:, None, None, None]
+    return np.where((sc > 0) & (sa > 0), sa / np.where(sc > 0, sc * sc, 1.0), 0.0)
+
+
+def scaling_loss(o, a, c, w=None):
+    """Loss of the scaling preconditioner and dL/do.
+
+    o, a, c: [n,1,H,W]; per sample L_s = w_s sum_x (a e^{2o} - 2 c e^{o}) with
+    w = loss_weights(a, c) unless given; L = mean_s L_s.
+    """
+    n = o.shape[0]
+    w = loss_weights(a, c) if w is None else np.asarray(w, np.float64)
     s = np.exp(o)
-    L = float(np.mean(((a * s * s - 2.0 * c * s) / den).reshape(n, -1).sum(axis=1)))
-    go = (2.0 * a * s * s - 2.0 * c * s) / den / n
+    ww = w[:, None, None, None]
+    L = float(np.mean((ww * (a * s * s - 2.0 * c * s)).reshape(n, -1).sum(axis=1)))
+    go = ww * (2.0 * a * s * s - 2.0 * c * s) / n
     return L, go
 
 
@@ -263,7 +271,7 @@ def adam_step(theta, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8, clip=0.0):
 
 
 def precond_inputs(r, v, w2):
-    """Network input of one shot: [log(1 + rms_t r / mean_x(rms_t r)), v / 3000, B / 100].
+    """Network input of one shot: [log(1 + rms_t r / mean_x(rms_t r)), v / 3000, log(B) / 4].
 
     r: [nt, nz, nx] residual; v: [nz, nx] m/s; w2 = B^2 on the physical grid.
     Also returns a = sum_t r^2, the per-cell energy of r.
@@ -272,4 +280,4 @@ def precond_inputs(r, v, w2):
     rms = np.sqrt(a / r.shape[0])
     mu = rms.mean()
     ch0 = np.log1p(rms / mu if mu > 0 else rms)
-    return np.stack([ch0, np.asarray(v, np.float64) / 3000.0, np.sqrt(w2) / 100.0]), a
+    return np.stack([ch0, np.asarray(v, np.float64) / 3000.0, np.log(np.sqrt(w2)) / 4.0]), a

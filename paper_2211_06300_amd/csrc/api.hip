@@ -510,7 +510,7 @@ extern "C" esi_status_t esi_cg_solve(esi_plan_t plan, int32_t shot0, int32_t ns,
 
 extern "C" esi_status_t esi_fpcg_solve(esi_plan_t plan, int32_t shot0, int32_t ns,
                                        const float* d_obs, float* x, float* work, int32_t max_iter,
-                                       double rtol, esi_unet_t net, const float* scale,
+                                       double rtol, esi_unet_t net, int32_t net_every, const float* scale,
                                        esi_cg_report_t* rep) {
     set_error("");
     if (!plan) return fail(ESI_ERR_ARG, "null plan");
@@ -520,6 +520,7 @@ extern "C" esi_status_t esi_fpcg_solve(esi_plan_t plan, int32_t shot0, int32_t n
     if (!x || !work || (!d_obs && data_len(P, shot0, ns) > 0)) return fail(ESI_ERR_ARG, "null pointer");
     if (max_iter < 1) return fail(ESI_ERR_ARG, "max_iter must be >= 1");
     if (!(rtol >= 0)) return fail(ESI_ERR_ARG, "rtol must be >= 0");
+    if (net_every < 0) return fail(ESI_ERR_ARG, "net_every must be >= 0");
     const int Hp = (P->nz + 7) / 8 * 8, Wp = (P->nx + 7) / 8 * 8;
     if (net) {
         int H, W, mb;
@@ -548,8 +549,8 @@ extern "C" esi_status_t esi_fpcg_solve(esi_plan_t plan, int32_t shot0, int32_t n
     const int64_t cells = (int64_t)ns * P->nphys;
     ESI_TRY(grow_t(&P->fcg_s, &P->fcg_s_cap, cells, P->stream));
     ESI_TRY(grow_t(&P->fcg_a, &P->fcg_a_cap, cells, P->stream));
-    ESI_TRY(grow_t(&P->fcg_d, &P->fcg_d_cap, (int64_t)5 * ns, P->stream));
-    ESI_TRY(grow_t(&P->fcg_i, &P->fcg_i_cap, (int64_t)4 * ns, P->stream));
+    ESI_TRY(grow_t(&P->fcg_d, &P->fcg_d_cap, (int64_t)7 * ns, P->stream));
+    ESI_TRY(grow_t(&P->fcg_i, &P->fcg_i_cap, (int64_t)5 * ns, P->stream));
     if (net) {
         ESI_TRY(grow_t(&P->fcg_in, &P->fcg_in_cap, (int64_t)ns * 3 * Hp * Wp, P->stream));
         ESI_TRY(grow_t(&P->fcg_o, &P->fcg_o_cap, (int64_t)ns * Hp * Wp, P->stream));
@@ -558,26 +559,28 @@ extern "C" esi_status_t esi_fpcg_solve(esi_plan_t plan, int32_t shot0, int32_t n
     float* en = P->fcg_a;
     double* pr = P->fcg_d;
     double* zAp = P->fcg_d + ns;
-    double* zr = P->fcg_d + 2 * ns;
-    double* fmean = P->fcg_d + 3 * ns;
-    double* best = P->fcg_d + 4 * ns;
+    double* zr = P->fcg_d + 2 * ns;          // [ns][3]
+    double* fmean = P->fcg_d + 5 * ns;
+    double* best = P->fcg_d + 6 * ns;
     int* mode = P->fcg_i;
     int* restart = P->fcg_i + ns;
     int* fallback = P->fcg_i + 2 * ns;
     int* kbest = P->fcg_i + 3 * ns;
+    int* cg_at = P->fcg_i + 4 * ns;
     const float* o = net ? P->fcg_o : nullptr;
     const double stall = 0.99;
-    const int window = 10;
+    const int window = 20;
 
     // z = M(r) for the shots still iterating, k = the iteration count so far
     auto precondition = [&](int k) -> esi_status_t {
         ESI_TRY(launch_energy(P, c.r, c.active, en, ns));
-        if (net) {
+        if (net && (k == 0 || (net_every > 0 && k % net_every == 0))) {
             ESI_TRY(launch_features(P, shot0, ns, en, nullptr, fmean, Hp, Wp, nullptr, P->fcg_in, nullptr,
                                     nullptr));
             ESI_TRY(unet_forward_on(net, P->stream, P->fcg_in, P->fcg_o, ns));
         }
-        return launch_fcg_zr_check_scale(P, o, scale, en, c.active, mode, restart, fallback, k, Hp, Wp, zr, S, ns);
+        return launch_fcg_zr_check_scale(P, o, scale, en, c.active, mode, restart, fallback, cg_at, best, kbest,
+                                         c.hist, max_iter + 1, k, Hp, Wp, zr, S, ns);
     };
 
     // b = S^T d; r_0 = b, x_0 = 0
@@ -593,7 +596,7 @@ extern "C" esi_status_t esi_fpcg_solve(esi_plan_t plan, int32_t shot0, int32_t n
     ESI_TRY(launch_dot(P, c.r, c.r, ns, c.len, c.rr));
     ESI_HIP_TRY(hipMemcpyAsync(c.rr0, c.rr, ns * sizeof(double), hipMemcpyDeviceToDevice, P->stream));
     ESI_TRY(launch_cg_init(P, c.rr0, c.active, c.finish, c.iters, c.status, c.hist, max_iter + 1, c.ctl, ns));
-    ESI_TRY(launch_fcg_init(P, mode, restart, fallback, best, kbest, ns));
+    ESI_TRY(launch_fcg_init(P, mode, restart, fallback, cg_at, best, kbest, ns));
     if (stats) ESI_TRY(launch_stats(P, c.r, x, nullptr, nullptr, rep->stat_xref, c.iters, 0, rep->stat_out, ns));
     ESI_HIP_TRY(hipMemcpyAsync(P->h_ctl, c.ctl, 2 * sizeof(int), hipMemcpyDeviceToHost, P->stream));
     ESI_HIP_TRY(hipStreamSynchronize(P->stream));
@@ -626,8 +629,8 @@ extern "C" esi_status_t esi_fpcg_solve(esi_plan_t plan, int32_t shot0, int32_t n
         ESI_TRY(launch_cg_alpha(P, pr, c.pAp, c.alpha, ns));          // alpha = p.r / p.Np
         ESI_TRY(launch_r_update(P, c.r, Apk, c.alpha, c.active, ns, c.len, c.rr_new));
         ESI_TRY(launch_fcg_control(P, c.rr0, c.rr_new, c.pAp, c.active, c.finish, c.iters, c.status, c.hist,
-                                   max_iter + 1, c.ctl, rtol, max_iter, mode, restart, fallback, stall, window,
-                                   best, kbest, ns));
+                                   max_iter + 1, c.ctl, rtol, max_iter, mode, restart, fallback, cg_at, stall,
+                                   window, best, kbest, net != nullptr, ns));
         if (stats)
             ESI_TRY(launch_stats(P, c.r, x, dir, c.alpha, rep->stat_xref, c.iters, k + 1,
                                  rep->stat_out + (k + 1) * stat_stride, ns));
@@ -642,9 +645,10 @@ extern "C" esi_status_t esi_fpcg_solve(esi_plan_t plan, int32_t shot0, int32_t n
         ESI_TRY(launch_dot_scaled(P, c.r, Apk, S, ns, zAp));
         ESI_TRY(launch_fcg_beta(P, zAp, c.pAp, restart, c.beta, ns));
     }
-    std::vector<int> h_fb(ns, -1);
+    std::vector<int> h_fb(ns, -1), h_cg(ns, -1);
     ESI_HIP_TRY(hipMemcpyAsync(h_status.data(), c.status, ns * sizeof(int), hipMemcpyDeviceToHost, P->stream));
     ESI_HIP_TRY(hipMemcpyAsync(h_fb.data(), fallback, ns * sizeof(int), hipMemcpyDeviceToHost, P->stream));
+    ESI_HIP_TRY(hipMemcpyAsync(h_cg.data(), cg_at, ns * sizeof(int), hipMemcpyDeviceToHost, P->stream));
     if (rep) {
         rep->iters = done_iters;
         if (rep->shot_iters)
@@ -656,6 +660,8 @@ extern "C" esi_status_t esi_fpcg_solve(esi_plan_t plan, int32_t shot0, int32_t n
     ESI_HIP_TRY(hipStreamSynchronize(P->stream));
     if (rep && rep->shot_fallback)
         for (int s = 0; s < ns; ++s) rep->shot_fallback[s] = h_fb[s];
+    if (rep && rep->shot_cg)
+        for (int s = 0; s < ns; ++s) rep->shot_cg[s] = h_cg[s];
     for (int s = 0; s < ns; ++s)
         if (h_status[s] == ESI_ERR_NONFINITE) return fail(ESI_ERR_NONFINITE, "flexible CG: non-finite scalar");
     for (int s = 0; s < ns; ++s)
@@ -673,8 +679,8 @@ extern "C" esi_status_t esi_precond_features(esi_plan_t plan, int32_t shot0, int
     if (P->ndim != 2) return fail(ESI_ERR_ARG, "network features are 2D");
     if (!a || !xin) return fail(ESI_ERR_ARG, "null pointer");
     if (Hp < P->nz || Wp < P->nx || Hp % 8 || Wp % 8) return fail(ESI_ERR_SHAPE, "Hp, Wp: multiples of 8 covering the grid");
-    ESI_TRY(grow_t(&P->fcg_d, &P->fcg_d_cap, (int64_t)4 * std::max(ns, P->nshots), P->stream));
-    return launch_features(P, shot0, ns, a, cmap, P->fcg_d + 3 * ns, Hp, Wp, base, xin, apad, cpad);
+    ESI_TRY(grow_t(&P->fcg_d, &P->fcg_d_cap, (int64_t)7 * std::max(ns, P->nshots), P->stream));
+    return launch_features(P, shot0, ns, a, cmap, P->fcg_d + 5 * ns, Hp, Wp, base, xin, apad, cpad);
 }
 
 extern "C" esi_status_t esi_gradient(esi_plan_t plan, int32_t shot0, int32_t ns, int32_t mode,

@@ -131,8 +131,8 @@ struct Plan {
     float* fcg_a = nullptr; int64_t fcg_a_cap = 0;
     float* fcg_in = nullptr; int64_t fcg_in_cap = 0;
     float* fcg_o = nullptr; int64_t fcg_o_cap = 0;
-    double* fcg_d = nullptr; int64_t fcg_d_cap = 0;   // pr, zAp, zr [3][nshots]
-    int* fcg_i = nullptr; int64_t fcg_i_cap = 0;      // mode, restart, fallback_at [3][nshots]
+    double* fcg_d = nullptr; int64_t fcg_d_cap = 0;   // pr, zAp, zr[3], mean, best [7][nshots]
+    int* fcg_i = nullptr; int64_t fcg_i_cap = 0;      // mode, restart, fallback, kbest, cg_at [5][nshots]
 
     std::vector<TileLists*> lists;       // one per tile shape used
     int time_block = 2;                  // steps per launch where allowed (1 or 2)
@@ -284,17 +284,19 @@ esi_status_t launch_stats(Plan* P, const float* r, const float* x, const float* 
 esi_status_t launch_features(Plan* P, int shot0, int ns, const float* a, const float* c, double* mean, int Hp,
                              int Wp, const float* base, float* xin, float* apad, float* cpad);
 esi_status_t launch_fcg_zr_check_scale(Plan* P, const float* o, const float* fixed, const float* a,
-                                       const int* active, int* mode, int* restart, int* fallback, int k,
+                                       const int* active, int* mode, int* restart, int* fallback, int* cg_at,
+                                       double* best, int* kbest, const double* hist, int hstride, int k,
                                        int Hp, int Wp, double* zr, float* S, int ns);
 esi_status_t launch_scale_vec(Plan* P, float* p, const float* r, const float* S, int ns);
 esi_status_t launch_dot_scaled(Plan* P, const float* r, const float* y, const float* S, int ns, double* out);
 esi_status_t launch_fcg_beta(Plan* P, const double* zAp, const double* pAp, const int* restart, double* beta,
                              int ns);
-esi_status_t launch_fcg_init(Plan* P, int* mode, int* restart, int* fallback, double* best, int* kbest, int ns);
+esi_status_t launch_fcg_init(Plan* P, int* mode, int* restart, int* fallback, int* cg_at, double* best, int* kbest,
+                             int ns);
 esi_status_t launch_fcg_control(Plan* P, const double* rr0, const double* rr_new, const double* pAp, int* active,
                                 int* finish, int* iters, int* status, double* hist, int hstride, int* ctl,
-                                double rtol, int max_iter, int* mode, int* restart, int* fallback, double stall,
-                                int window, double* best, int* kbest, int ns);
+                                double rtol, int max_iter, int* mode, int* restart, int* fallback, int* cg_at,
+                                double stall, int window, double* best, int* kbest, bool has_net, int ns);
 esi_status_t unet_dims(esi_unet_t u, int* H, int* W, int* maxb);
 esi_status_t unet_forward_on(esi_unet_t u, hipStream_t stream, const float* x, float* o, int batch);
 

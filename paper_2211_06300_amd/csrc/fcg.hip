@@ -79,7 +79,7 @@ __global__ __launch_bounds__(NT) void k_feat_mean(const float* __restrict__ a, i
 }
 
 // Network input on the image padded to Hp x Wp (zero outside the grid):
-// [log(1 + rms / mean(rms)), v / 3000, B / 100] with rms = sqrt(a / nt) and B the
+// [log(1 + rms / mean(rms)), v / 3000, log(B) / 4] with rms = sqrt(a / nt) and B the
 // annihilator weight |x - x_s| / dx + eps (in cells); also the padded copies
 // of a and c when asked for, as a s0^2 and c s0 for a base scale s0 (the
 // training maps of the correction exp(o) on top of s0).
@@ -104,7 +104,7 @@ __global__ void k_features(const float* __restrict__ a, const float* __restrict_
             f0 = log1pf(m > 0.0 ? (float)(rms / m) : rms);
             f1 = v[cell] / 3000.f;
             const float dx = (float)(ix - src[3 * (shot0 + s)]), dz = (float)(iz - src[3 * (shot0 + s) + 1]);
-            f2 = (sqrtf(dx * dx + dz * dz) + b_eps) / 100.f;
+            f2 = logf(sqrtf(dx * dx + dz * dz) + b_eps) * 0.25f;
             av_out = av * b0 * b0;
             cv_out = cv * b0;
         }
@@ -117,47 +117,71 @@ __global__ void k_features(const float* __restrict__ a, const float* __restrict_
     }
 }
 
-// Candidate scale of cell x of shot s: the fixed scale (or 1) times exp(o)
-// when the network runs.
-__device__ __forceinline__ float cand_scale(const float* o, const float* fixed, int s, int iz, int ix, int nz,
-                                            int nx, int Hp, int Wp) {
+// Preconditioner stages of a shot: 0 = the full scale s0 exp(o) (s0 = the
+// fixed scale or 1, exp(o) only when the network runs), 1 = s0 alone (only
+// when the network runs), 2 = plain CG (1).  A shot moves down the stages
+// when its preconditioner is given up.
+__device__ __forceinline__ int next_stage(int st, bool has_net) { return (st == 0 && has_net) ? 1 : 2; }
+
+__device__ __forceinline__ float stage_scale(int st, const float* o, const float* fixed, int s, int iz, int ix,
+                                             int nz, int nx, int Hp, int Wp) {
+    if (st == 2) return 1.f;
     const float f = fixed ? fixed[((int64_t)s * nz + iz) * nx + ix] : 1.f;
-    return o ? f * expf(o[((int64_t)s * Hp + iz) * Wp + ix]) : f;
+    return (st == 0 && o) ? f * expf(o[((int64_t)s * Hp + iz) * Wp + ix]) : f;
 }
 
-// zr[s] = sum_x s(x) a(x) = z.r for the candidate scale (1 for shots in CG mode).
+// zr[3 s + st] = sum_x scale_st(x) a(x) = z.r for each stage st.
 __global__ __launch_bounds__(NT) void k_fcg_zr(const float* __restrict__ o, const float* __restrict__ fixed,
-                                               const float* __restrict__ a, const int* __restrict__ mode, int nz,
-                                               int nx, int Hp, int Wp, double* __restrict__ zr) {
+                                               const float* __restrict__ a, int nz, int nx, int Hp, int Wp,
+                                               double* __restrict__ zr) {
     __shared__ double sm[NT / 64];
     const int s = blockIdx.x;
     const int64_t n = (int64_t)nz * nx;
-    const bool cg = mode[s] != 0;
-    double acc = 0.0;
+    double acc[3] = {0.0, 0.0, 0.0};
     for (int64_t x = threadIdx.x; x < n; x += NT) {
         const int iz = (int)(x / nx), ix = (int)(x % nx);
-        const float sc = cg ? 1.f : cand_scale(o, fixed, s, iz, ix, nz, nx, Hp, Wp);
-        acc += (double)sc * (double)a[(int64_t)s * n + x];
+        const double av = a[(int64_t)s * n + x];
+        for (int st = 0; st < 3; ++st) acc[st] += (double)stage_scale(st, o, fixed, s, iz, ix, nz, nx, Hp, Wp) * av;
     }
-    const double t = block_sum_d(acc, sm);
-    if (threadIdx.x == 0) zr[s] = t;
+    for (int st = 0; st < 3; ++st) {
+        const double t = block_sum_d(acc[st], sm);
+        if (threadIdx.x == 0) zr[3 * s + st] = t;
+    }
+}
+
+__device__ __forceinline__ void leave_stage(int s, int k, bool has_net, int* mode, int* restart, int* fallback,
+                                            int* cg_at) {
+    const int st = next_stage(mode[s], has_net);
+    if (fallback[s] < 0) fallback[s] = k;
+    if (st == 2) cg_at[s] = k;
+    mode[s] = st;
+    restart[s] = 1;
 }
 
 // A shot whose preconditioned residual is not a descent direction (z.r <= 0
-// or not finite) hands over to plain CG after iteration k.
+// or not finite) gives up that preconditioner after iteration k, moving down
+// the stages until one is usable (plain CG always is); a switch restarts the
+// direction and the stall window.
 __global__ void k_fcg_check(const double* __restrict__ zr, const int* __restrict__ active, int* __restrict__ mode,
-                            int* __restrict__ restart, int* __restrict__ fallback, int k, int n) {
+                            int* __restrict__ restart, int* __restrict__ fallback, int* __restrict__ cg_at,
+                            double* __restrict__ best, int* __restrict__ kbest, const double* __restrict__ hist,
+                            int hstride, int k, int has_net, int n) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n || !active[s] || mode[s]) return;
-    const double z = zr[s];
-    if (!(isfinite(z) && z > 0.0)) {
-        mode[s] = 1;
-        restart[s] = 1;
-        fallback[s] = k;
+    if (s >= n || !active[s]) return;
+    bool moved = false;
+    while (mode[s] < 2) {
+        const double z = zr[3 * s + mode[s]];
+        if (isfinite(z) && z > 0.0) break;
+        leave_stage(s, k, has_net != 0, mode, restart, fallback, cg_at);
+        moved = true;
+    }
+    if (moved && k > 0) {
+        kbest[s] = k;
+        best[s] = hist[(int64_t)s * hstride + k];
     }
 }
 
-// S[s][x] = candidate scale, or 1 in CG mode.
+// S[s][x] = the scale of the shot's current stage.
 __global__ void k_fcg_scale(const float* __restrict__ o, const float* __restrict__ fixed,
                             const int* __restrict__ mode, float* __restrict__ S, int ns, int nz, int nx, int Hp,
                             int Wp) {
@@ -165,7 +189,7 @@ __global__ void k_fcg_scale(const float* __restrict__ o, const float* __restrict
     for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < ns * n; i += (int64_t)gridDim.x * NT) {
         const int s = (int)(i / n);
         const int64_t x = i % n;
-        S[i] = mode[s] ? 1.f : cand_scale(o, fixed, s, (int)(x / nx), (int)(x % nx), nz, nx, Hp, Wp);
+        S[i] = stage_scale(mode[s], o, fixed, s, (int)(x / nx), (int)(x % nx), nz, nx, Hp, Wp);
     }
 }
 
@@ -204,12 +228,13 @@ __global__ void k_fcg_beta(const double* __restrict__ zAp, const double* __restr
 }
 
 __global__ void k_fcg_init(int* __restrict__ mode, int* __restrict__ restart, int* __restrict__ fallback,
-                           double* __restrict__ best, int* __restrict__ kbest, int n) {
+                           int* __restrict__ cg_at, double* __restrict__ best, int* __restrict__ kbest, int n) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s < n) {
         mode[s] = 0;
         restart[s] = 0;
         fallback[s] = -1;
+        cg_at[s] = -1;
         best[s] = 1.0;
         kbest[s] = 0;
     }
@@ -223,8 +248,9 @@ __global__ void k_fcg_control(const double* __restrict__ rr0, const double* __re
                               const double* __restrict__ pAp, int* __restrict__ active, int* __restrict__ finish,
                               int* __restrict__ iters, int* __restrict__ status, double* __restrict__ hist,
                               int hstride, int* __restrict__ ctl, double rtol, int max_iter, int* __restrict__ mode,
-                              int* __restrict__ restart, int* __restrict__ fallback, double stall, int window,
-                              double* __restrict__ best, int* __restrict__ kbest, int n) {
+                              int* __restrict__ restart, int* __restrict__ fallback, int* __restrict__ cg_at,
+                              double stall, int window, double* __restrict__ best, int* __restrict__ kbest,
+                              int has_net, int n) {
     __shared__ int cnt;
     const int k = ctl[0];
     if (threadIdx.x == 0) cnt = 0;
@@ -251,10 +277,10 @@ __global__ void k_fcg_control(const double* __restrict__ rr0, const double* __re
                     best[s] = rel;
                     kbest[s] = k + 1;
                 }
-                if (!mode[s] && k + 1 - kbest[s] >= window) {
-                    mode[s] = 1;
-                    restart[s] = 1;
-                    fallback[s] = k + 1;
+                if (mode[s] < 2 && k + 1 - kbest[s] >= window) {
+                    leave_stage(s, k + 1, has_net != 0, mode, restart, fallback, cg_at);
+                    kbest[s] = k + 1;
+                    best[s] = rel;
                 }
             }
             if (f) active[s] = 0;
@@ -297,11 +323,12 @@ esi_status_t launch_features(Plan* P, int shot0, int ns, const float* a, const f
 }
 
 esi_status_t launch_fcg_zr_check_scale(Plan* P, const float* o, const float* fixed, const float* a,
-                                       const int* active, int* mode, int* restart, int* fallback, int k,
+                                       const int* active, int* mode, int* restart, int* fallback, int* cg_at,
+                                       double* best, int* kbest, const double* hist, int hstride, int k,
                                        int Hp, int Wp, double* zr, float* S, int ns) {
-    hipLaunchKernelGGL(k_fcg_zr, dim3(ns), dim3(NT), 0, P->stream, o, fixed, a, mode, P->nz, P->nx, Hp, Wp, zr);
+    hipLaunchKernelGGL(k_fcg_zr, dim3(ns), dim3(NT), 0, P->stream, o, fixed, a, P->nz, P->nx, Hp, Wp, zr);
     hipLaunchKernelGGL(k_fcg_check, dim3((ns + 63) / 64), dim3(64), 0, P->stream, zr, active, mode, restart,
-                       fallback, k, ns);
+                       fallback, cg_at, best, kbest, hist, hstride, k, o ? 1 : 0, ns);
     hipLaunchKernelGGL(k_fcg_scale, dim3(grid_for((int64_t)ns * P->nphys)), dim3(NT), 0, P->stream, o, fixed,
                        mode, S, ns, P->nz, P->nx, Hp, Wp);
     ESI_HIP_TRY(hipGetLastError());
@@ -331,20 +358,21 @@ esi_status_t launch_fcg_beta(Plan* P, const double* zAp, const double* pAp, cons
     return ESI_OK;
 }
 
-esi_status_t launch_fcg_init(Plan* P, int* mode, int* restart, int* fallback, double* best, int* kbest, int ns) {
-    hipLaunchKernelGGL(k_fcg_init, dim3((ns + 63) / 64), dim3(64), 0, P->stream, mode, restart, fallback, best,
-                       kbest, ns);
+esi_status_t launch_fcg_init(Plan* P, int* mode, int* restart, int* fallback, int* cg_at, double* best, int* kbest,
+                             int ns) {
+    hipLaunchKernelGGL(k_fcg_init, dim3((ns + 63) / 64), dim3(64), 0, P->stream, mode, restart, fallback, cg_at,
+                       best, kbest, ns);
     ESI_HIP_TRY(hipGetLastError());
     return ESI_OK;
 }
 
 esi_status_t launch_fcg_control(Plan* P, const double* rr0, const double* rr_new, const double* pAp, int* active,
                                 int* finish, int* iters, int* status, double* hist, int hstride, int* ctl,
-                                double rtol, int max_iter, int* mode, int* restart, int* fallback, double stall,
-                                int window, double* best, int* kbest, int ns) {
+                                double rtol, int max_iter, int* mode, int* restart, int* fallback, int* cg_at,
+                                double stall, int window, double* best, int* kbest, bool has_net, int ns) {
     hipLaunchKernelGGL(k_fcg_control, dim3(1), dim3(256), 0, P->stream, rr0, rr_new, pAp, active, finish, iters,
-                       status, hist, hstride, ctl, rtol, max_iter, mode, restart, fallback, stall, window, best,
-                       kbest, ns);
+                       status, hist, hstride, ctl, rtol, max_iter, mode, restart, fallback, cg_at, stall, window,
+                       best, kbest, has_net ? 1 : 0, ns);
     ESI_HIP_TRY(hipGetLastError());
     return ESI_OK;
 }

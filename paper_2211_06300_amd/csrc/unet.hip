@@ -365,12 +365,41 @@ __global__ void k_out_back(const float* __restrict__ go, const bf16_t* __restric
     }
 }
 
-// Scaling loss per sample s: L_s = sum_x (a e^{2o} - 2 c e^{o}) / q with
-// q = (sum_x c)^2 / sum_x a, and go = (2 a e^{2o} - 2 c e^{o}) / q / nbatch.
-// One workgroup per sample; loss[s] in float64.
+// Default per-sample loss weight sum_x a / (sum_x c)^2 (0 when sum_x c <= 0).
+// One workgroup per sample.
+__global__ __launch_bounds__(NT) void k_loss_weights(const float* __restrict__ a, const float* __restrict__ c,
+                                                     int64_t npix, float* __restrict__ w) {
+    __shared__ double red[2][NT / 64];
+    const int s = blockIdx.x;
+    double sa = 0.0, sc = 0.0;
+    for (int64_t p = threadIdx.x; p < npix; p += NT) {
+        sa += a[(int64_t)s * npix + p];
+        sc += c[(int64_t)s * npix + p];
+    }
+    for (int k = 32; k > 0; k >>= 1) {
+        sa += __shfl_xor(sa, k, 64);
+        sc += __shfl_xor(sc, k, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = sa;
+        red[1][threadIdx.x >> 6] = sc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ta = 0.0, tc = 0.0;
+        for (int k = 0; k < NT / 64; ++k) { ta += red[0][k]; tc += red[1][k]; }
+        w[s] = (tc > 0.0 && ta > 0.0) ? (float)(ta / (tc * tc)) : 0.f;
+    }
+}
+
+// Scaling loss per sample s: L_s = w_s sum_x (a e^{2o} - 2 c e^{o}) and
+// go = w_s (2 a e^{2o} - 2 c e^{o}) / nbatch, with w from `weight` or the
+// default sum_x a / (sum_x c)^2 of the image.  One workgroup per sample;
+// loss[s] in float64.
 __global__ __launch_bounds__(NT) void k_scaling_loss(const float* __restrict__ o, const float* __restrict__ a,
-                                                     const float* __restrict__ c, int64_t npix, int nbatch,
-                                                     float* __restrict__ go, double* __restrict__ loss) {
+                                                     const float* __restrict__ c, const float* __restrict__ weight,
+                                                     int64_t npix, int nbatch, float* __restrict__ go,
+                                                     double* __restrict__ loss) {
     __shared__ double red[NT / 64];
     const int s = blockIdx.x;
     const float* os = o + (int64_t)s * npix;
@@ -386,15 +415,20 @@ __global__ __launch_bounds__(NT) void k_scaling_loss(const float* __restrict__ o
         for (int k = 0; k < NT / 64; ++k) t += red[k];
         return t;
     };
-    double suma = 0.0, sumc = 0.0;
-    for (int64_t p = threadIdx.x; p < npix; p += NT) {
-        suma += as[p];
-        sumc += cs[p];
+    double wt;
+    if (weight) {
+        wt = weight[s];
+    } else {
+        double suma = 0.0, sumc = 0.0;
+        for (int64_t p = threadIdx.x; p < npix; p += NT) {
+            suma += as[p];
+            sumc += cs[p];
+        }
+        suma = block_sum(suma);
+        sumc = block_sum(sumc);
+        wt = (sumc > 0.0 && suma > 0.0) ? (double)(float)(suma / (sumc * sumc)) : 0.0;
     }
-    suma = block_sum(suma);
-    sumc = block_sum(sumc);
-    const double sa = suma > 0.0 ? sumc * sumc / suma : 0.0;
-    const float inv = sa > 0.0 ? (float)(1.0 / sa) : 0.f;
+    const float inv = (float)wt;
     double sl = 0.0;
     for (int64_t p = threadIdx.x; p < npix; p += NT) {
         const float e = expf(os[p]);
@@ -403,7 +437,7 @@ __global__ __launch_bounds__(NT) void k_scaling_loss(const float* __restrict__ o
         go[(int64_t)s * npix + p] = (2.f * ae * e - 2.f * ce * e) * inv / (float)nbatch;
     }
     sl = block_sum(sl);
-    if (threadIdx.x == 0) loss[s] = sl * (sa > 0.0 ? 1.0 / sa : 0.0);
+    if (threadIdx.x == 0) loss[s] = sl * wt;
 }
 
 // Squared gradient norm: partials per block, summed by k_norm_finish.
@@ -871,8 +905,18 @@ extern "C" esi_status_t esi_unet_forward(esi_unet_t u, const float* x, float* o,
     return forward(c, x, o);
 }
 
+extern "C" esi_status_t esi_unet_loss_weights(const float* a, const float* c, int32_t batch, int64_t npix,
+                                              float* w, void* stream) {
+    set_error("");
+    if (!a || !c || !w) return fail(ESI_ERR_ARG, "null argument");
+    if (batch < 1 || npix < 1) return fail(ESI_ERR_ARG, "empty batch");
+    hipLaunchKernelGGL(k_loss_weights, dim3(batch), dim3(NT), 0, (hipStream_t)stream, a, c, npix, w);
+    ESI_HIP_TRY(hipGetLastError());
+    return ESI_OK;
+}
+
 extern "C" esi_status_t esi_unet_loss_grad(esi_unet_t u, const float* x, const float* a, const float* cc,
-                                           int32_t batch, float* grad, double* loss) {
+                                           const float* weight, int32_t batch, float* grad, double* loss) {
     set_error("");
     if (!u || !x || !a || !cc || !grad) return fail(ESI_ERR_ARG, "null argument");
     Unet* U = as_unet(u);
@@ -882,7 +926,8 @@ extern "C" esi_status_t esi_unet_loss_grad(esi_unet_t u, const float* x, const f
     ESI_TRY(grow_t(&U->part, &U->part_cap, (int64_t)batch * npix, U->stream));   // o scratch
     float* o = U->part;
     ESI_TRY(forward(c, x, o));
-    hipLaunchKernelGGL(k_scaling_loss, dim3(batch), dim3(NT), 0, U->stream, o, a, cc, npix, batch, U->go, U->dloss);
+    hipLaunchKernelGGL(k_scaling_loss, dim3(batch), dim3(NT), 0, U->stream, o, a, cc, weight, npix, batch, U->go,
+                       U->dloss);
     ESI_HIP_TRY(hipGetLastError());
     ESI_TRY(backward(c, grad));
     if (loss) {

@@ -43,6 +43,7 @@ class _CgReport(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("shot_iters", ctypes.POINTER(ctypes.c_int32)),
                 ("res_hist", ctypes.POINTER(ctypes.c_double)),
                 ("shot_fallback", ctypes.POINTER(ctypes.c_int32)),
+                ("shot_cg", ctypes.POINTER(ctypes.c_int32)),
                 ("stat_xref", ctypes.c_void_p), ("stat_out", ctypes.c_void_p)]
 
 
@@ -53,7 +54,7 @@ EXPORTS = ["esi_plan_create", "esi_plan_set_model", "esi_plan_destroy", "esi_las
            "esi_forward_ckpt", "esi_grad_velocity", "esi_plan_set_cg_graph",
            "esi_unet_num_params", "esi_unet_create", "esi_unet_destroy", "esi_unet_set_params",
            "esi_unet_get_params", "esi_unet_forward", "esi_unet_loss_grad", "esi_unet_adam",
-           "esi_fpcg_solve", "esi_precond_features"]
+           "esi_fpcg_solve", "esi_precond_features", "esi_unet_loss_weights"]
 # time-step kernel variants (bit set of fused work), as in include/esi.h
 K_FLAGS = {1: "SRC_POINT", 2: "SRC_DENSE", 4: "CG_FUSE", 8: "INJ", 16: "GATHER", 32: "OUT",
            64: "NORMAL", 128: "PENALTY", 256: "STORE", 512: "CORR", 1024: "SRC_REC",
@@ -86,7 +87,7 @@ def load_library(path: str = LIB_PATH):
     L.esi_forward_ckpt.argtypes = [vp, i32, i32, i32, vp, vp, i32]
     L.esi_grad_velocity.argtypes = [vp, vp, vp, vp]
     L.esi_plan_profile_read.argtypes = [vp, i32, vp, vp, vp, vp, vp]
-    L.esi_fpcg_solve.argtypes = [vp, i32, i32, vp, vp, vp, i32, dbl, vp, vp, ctypes.POINTER(_CgReport)]
+    L.esi_fpcg_solve.argtypes = [vp, i32, i32, vp, vp, vp, i32, dbl, vp, i32, vp, ctypes.POINTER(_CgReport)]
     L.esi_precond_features.argtypes = [vp, i32, i32, vp, vp, vp, i32, i32, vp, vp, vp]
     L.esi_unet_num_params.argtypes = []
     L.esi_unet_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, vp]
@@ -94,7 +95,8 @@ def load_library(path: str = LIB_PATH):
     L.esi_unet_set_params.argtypes = [vp, vp]
     L.esi_unet_get_params.argtypes = [vp, vp]
     L.esi_unet_forward.argtypes = [vp, vp, vp, i32]
-    L.esi_unet_loss_grad.argtypes = [vp, vp, vp, vp, i32, vp, ctypes.POINTER(dbl)]
+    L.esi_unet_loss_grad.argtypes = [vp, vp, vp, vp, vp, i32, vp, ctypes.POINTER(dbl)]
+    L.esi_unet_loss_weights.argtypes = [vp, vp, i32, i64, vp, vp]
     L.esi_unet_adam.argtypes = [vp, vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, i32,
                                 ctypes.c_float]
     for f in EXPORTS:
@@ -268,9 +270,10 @@ class Plan:
         return x, {"iters": int(rep.iters), "shot_iters": iters, "res_hist": hist}
 
     def fpcg_solve(self, d_obs, max_iter, rtol=0.0, net=None, scale=None, shot0=0, nshots=None,
-                   x=None, work=None, stat_xref=None, stat_out=None):
+                   x=None, work=None, stat_xref=None, stat_out=None, net_every=0):
         """Flexible CG (esi_fpcg_solve); net is a Unet, scale a [nshots, *phys]
-        tensor, or neither (M = I)."""
+        tensor, or neither (M = I); the network runs on r_0 and every
+        net_every-th iteration (0: once)."""
         shot0, nshots = self._range(shot0, nshots)
         x = self.new_vec(nshots) if x is None else x
         if work is None:
@@ -278,9 +281,11 @@ class Plan:
         hist = np.zeros((nshots, max_iter + 1))
         iters = np.zeros(nshots, dtype=np.int32)
         fb = np.zeros(nshots, dtype=np.int32)
+        cg = np.zeros(nshots, dtype=np.int32)
         rep = _CgReport(0, iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                         hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                         fb.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                        cg.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                         None if stat_xref is None else _f32(stat_xref, self.vec_shape(nshots), "stat_xref"),
                         None if stat_out is None else _f32(stat_out, (max_iter + 1, nshots, 2, self.nphys),
                                                            "stat_out"))
@@ -289,9 +294,9 @@ class Plan:
                                         _f32(d_obs, self.data_shape(shot0, nshots), "d_obs"),
                                         _f32(x, self.vec_shape(nshots), "x"),
                                         _f32(work, (3, *self.vec_shape(nshots)), "work"),
-                                        int(max_iter), float(rtol), None if net is None else net._h, sp,
-                                        ctypes.byref(rep)))
-        return x, {"iters": int(rep.iters), "shot_iters": iters, "res_hist": hist, "fallback": fb}
+                                        int(max_iter), float(rtol), None if net is None else net._h,
+                                        int(net_every), sp, ctypes.byref(rep)))
+        return x, {"iters": int(rep.iters), "shot_iters": iters, "res_hist": hist, "fallback": fb, "cg_at": cg}
 
     def precond_features(self, a, Hp, Wp, cmap=None, base=None, shot0=0, nshots=None, pads=False):
         """Network input [nshots, 3, Hp, Wp] from a = sum_t r^2 [nshots, *phys];
@@ -384,15 +389,25 @@ class Unet:
         _check(self._lib.esi_unet_forward(self._h, _f32(x, (b, 3, self.H, self.W), "x"), _ptr(o), b))
         return o
 
-    def loss_grad(self, x, a, c, grad=None):
+    def loss_grad(self, x, a, c, grad=None, weight=None):
         b = int(x.shape[0])
         grad = torch.empty(self.P, dtype=torch.float32, device=self.device) if grad is None else grad
         loss = ctypes.c_double()
         shp = (b, self.H, self.W)
         _check(self._lib.esi_unet_loss_grad(self._h, _f32(x, (b, 3, self.H, self.W), "x"),
-                                            _f32(a, shp, "a"), _f32(c, shp, "c"), b,
+                                            _f32(a, shp, "a"), _f32(c, shp, "c"),
+                                            None if weight is None else _f32(weight, (b,), "weight"), b,
                                             _f32(grad, (self.P,), "grad"), ctypes.byref(loss)))
         return grad, loss.value
+
+    def loss_weights(self, a, c):
+        """Default loss weights of whole images a, c [n, ...] (any size)."""
+        n = int(a.shape[0])
+        npix = int(a[0].numel())
+        w = torch.empty(n, dtype=torch.float32, device=self.device)
+        _check(self._lib.esi_unet_loss_weights(_f32(a, tuple(a.shape), "a"), _f32(c, tuple(c.shape), "c"), n,
+                                               npix, _ptr(w), ctypes.c_void_p(self.stream.cuda_stream)))
+        return w
 
     def adam(self, grad, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, clip=0.0):
         _check(self._lib.esi_unet_adam(self._h, _f32(grad, (self.P,), "grad"), float(lr), float(beta1),

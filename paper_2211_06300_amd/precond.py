@@ -52,6 +52,37 @@ def observed_data(cfg, device="cuda") -> torch.Tensor:
 GAMMA0 = 0.03
 
 
+def tiles(X, A, C, Wt, th, tw):
+    """Cut padded images larger than th x tw into tiles of that size (first
+    and last offset along each axis); every tile keeps its image's loss
+    weight Wt."""
+    H, W = X.shape[2], X.shape[3]
+    if (H, W) == (th, tw):
+        return X, A, C, Wt
+    ro = sorted({0, H - th}) if H > th else [0]
+    co = sorted({0, W - tw}) if W > tw else [0]
+    xs, as_, cs, ws = [], [], [], []
+    for r in ro:
+        for c in co:
+            xs.append(X[:, :, r:r + th, c:c + tw])
+            as_.append(A[:, r:r + th, c:c + tw])
+            cs.append(C[:, r:r + th, c:c + tw])
+            ws.append(Wt)
+    return (torch.cat(xs).contiguous(), torch.cat(as_).contiguous(), torch.cat(cs).contiguous(),
+            torch.cat(ws).contiguous())
+
+
+def loss_weights(A, C) -> torch.Tensor:
+    """Default loss weights of whole images (esi_unet_loss_weights)."""
+    lib = esi.load_library()
+    n = int(A.shape[0])
+    w = torch.empty(n, dtype=torch.float32, device=A.device)
+    esi._check(lib.esi_unet_loss_weights(esi._ptr(A.contiguous()), esi._ptr(C.contiguous()), n,
+                                         int(A[0].numel()), esi._ptr(w),
+                                         __import__("ctypes").c_void_p(torch.cuda.current_stream(A.device).cuda_stream)))
+    return w
+
+
 def model_pairs(cfg, k_plain=25, k_fcg=130, fcg_every=5, gamma=GAMMA0, ref_rtol=2e-4, ref_iters=600,
                 device="cuda", log=None):
     """Samples (x_in [n, 3, Hp, Wp], a [n, Hp, Wp], c [n, Hp, Wp]) of one model."""
@@ -91,15 +122,21 @@ def model_pairs(cfg, k_plain=25, k_fcg=130, fcg_every=5, gamma=GAMMA0, ref_rtol=
     return torch.cat(X), torch.cat(A), torch.cat(C)
 
 
-def build_dataset(seeds, nx=401, nz=201, nshots=4, nt=1500, device="cuda", log=None, **kw):
-    Xs, As, Cs = [], [], []
+def build_dataset(seeds, nx=401, nz=201, nshots=4, nt=1500, device="cuda", log=None, tile=(208, 408), **kw):
+    """Samples (x_in, a, c, loss weight) of the models `seeds` at nx x nz,
+    cut into tiles of `tile`; samples whose weight is 0 are dropped."""
+    Xs, As, Cs, Ws = [], [], [], []
     for sd in seeds:
         cfg = inputs.cfg_precond(int(sd), nx=nx, nz=nz, nshots=nshots, nt=nt)
         X, A, C = model_pairs(cfg, device=device, log=log, **kw)
+        Wt = loss_weights(A, C)
+        keep = torch.nonzero(Wt > 0).flatten()
+        X, A, C, Wt = tiles(X[keep], A[keep], C[keep], Wt[keep], *tile)
         Xs.append(X)
         As.append(A)
         Cs.append(C)
-    return torch.cat(Xs), torch.cat(As), torch.cat(Cs)
+        Ws.append(Wt)
+    return torch.cat(Xs), torch.cat(As), torch.cat(Cs), torch.cat(Ws)
 
 
 def init_params(seed: int, A: torch.Tensor, C: torch.Tensor) -> torch.Tensor:
@@ -113,7 +150,7 @@ def init_params(seed: int, A: torch.Tensor, C: torch.Tensor) -> torch.Tensor:
     return torch.from_numpy(theta).to(A.device)
 
 
-def train(X, A, C, epochs=8, batch=16, lr=3e-4, clip=1.0, seed=0, val_frac=0.05, log=None):
+def train(X, A, C, Wt, epochs=8, batch=16, lr=3e-4, clip=1.0, seed=0, val_frac=0.05, log=None):
     """Adam (gradient norm clipped to `clip`, cosine learning-rate decay) on
     the scaling loss; returns (theta, history)."""
     n = X.shape[0]
@@ -133,7 +170,8 @@ def train(X, A, C, epochs=8, batch=16, lr=3e-4, clip=1.0, seed=0, val_frac=0.05,
         tot = 0.0
         for i in range(0, nval, batch):
             idx = torch.from_numpy(val[i:i + batch]).to(X.device)
-            _, L = net.loss_grad(X[idx].contiguous(), A[idx].contiguous(), C[idx].contiguous(), grad)
+            _, L = net.loss_grad(X[idx].contiguous(), A[idx].contiguous(), C[idx].contiguous(), grad,
+                                 weight=Wt[idx].contiguous())
             tot += L * len(idx)
         return tot / nval
 
@@ -144,7 +182,8 @@ def train(X, A, C, epochs=8, batch=16, lr=3e-4, clip=1.0, seed=0, val_frac=0.05,
         tl, cnt = 0.0, 0
         for i in range(0, len(order) - batch + 1, batch):
             idx = torch.from_numpy(order[i:i + batch]).to(X.device)
-            _, L = net.loss_grad(X[idx].contiguous(), A[idx].contiguous(), C[idx].contiguous(), grad)
+            _, L = net.loss_grad(X[idx].contiguous(), A[idx].contiguous(), C[idx].contiguous(), grad,
+                                 weight=Wt[idx].contiguous())
             step += 1
             net.adam(grad, lr_ep, step, clip=clip)
             tl += L
@@ -160,13 +199,13 @@ def train(X, A, C, epochs=8, batch=16, lr=3e-4, clip=1.0, seed=0, val_frac=0.05,
     return theta, hist
 
 
-def cell_optimum_loss(A, C) -> float:
+def cell_optimum_loss(A, C, Wt) -> float:
     """Mean loss of the per-cell optimum exp(o) = c / a (a bound no cell
-    scaling beats; the best single scale scores -1)."""
+    scaling beats; the best single scale of a whole image scores -1)."""
     a = A.double().flatten(1)
     c = C.double().flatten(1)
     q = torch.where(a > 0, c * c / a.clamp_min(1e-300), torch.zeros_like(a)).sum(1)
-    return float((-q * a.sum(1) / c.sum(1) ** 2).mean())
+    return float((-q * Wt.double()).mean())
 
 
 def true_residual(plan, b, x):
@@ -179,8 +218,9 @@ def true_residual(plan, b, x):
 def compare_solvers(cfg, theta=None, rtol=1e-3, max_iter=600, gamma=GAMMA0, device="cuda", log=None,
                     methods=("plain", "analytic", "learned")):
     """Plain CG, flexible CG with the analytic scale s0, and flexible CG with
-    the learned correction s0 exp(Net) on one model, each to a relative
-    residual `rtol`: iterations per shot, wall time, true residual."""
+    the learned correction s0 exp(Net) ("learned": the network on every
+    iteration's residual; "learned_fixed": once, on r_0) on one model, each to
+    a relative residual `rtol`: iterations per shot, wall time, true residual."""
     d = observed_data(cfg, device)
     plan = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_start).to(device))
     ns = cfg.nshots
@@ -188,13 +228,13 @@ def compare_solvers(cfg, theta=None, rtol=1e-3, max_iter=600, gamma=GAMMA0, devi
     x = plan.new_vec(ns)
     S0 = analytic_scale(cfg, gamma, device)
     net = None
-    if theta is not None and "learned" in methods:
+    if theta is not None and any(m.startswith("learned") for m in methods):
         net = esi.Unet(pad8(cfg.nz), pad8(cfg.nx), ns, device=device)
         net.set_params(theta)
     b = plan.adjoint(d)
     out = {}
     for m in methods:
-        if m == "learned" and net is None:
+        if m.startswith("learned") and net is None:
             continue
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -202,8 +242,8 @@ def compare_solvers(cfg, theta=None, rtol=1e-3, max_iter=600, gamma=GAMMA0, devi
             _, rep = plan.cg_solve(d, max_iter, rtol, x=x, work=work)
             rep["fallback"] = np.full(ns, -1)
         else:
-            _, rep = plan.fpcg_solve(d, max_iter, rtol, net=net if m == "learned" else None, scale=S0, x=x,
-                                     work=work)
+            _, rep = plan.fpcg_solve(d, max_iter, rtol, net=net if m.startswith("learned") else None, scale=S0,
+                                     x=x, work=work, net_every=0 if m == "learned_fixed" else 1)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         its = rep["shot_iters"]

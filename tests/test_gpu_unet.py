@@ -79,3 +79,23 @@ def test_unet_adam_step(esi):
     ref, m, v = ounet.adam_step(ref, gh, m, v, 2, 1e-3, clip=0.5 * float(np.linalg.norm(gh)))
     assert np.max(np.abs(th - ref)) < 1e-6
     net.close()
+
+
+def test_unet_loss_weights(esi):
+    """esi_unet_loss_weights equals the oracle's default weights (including
+    the zero weight of a sample whose sum c is negative), and passing them
+    explicitly reproduces the default loss."""
+    theta, x, a, c = _case(16, 24, 3, 13)
+    c[2] = -np.abs(c[2])
+    net = esi.Unet(16, 24, 3)
+    net.set_params(torch.from_numpy(theta).to(DEV))
+    at, ct, xt = (torch.from_numpy(v).to(DEV) for v in (a, c, x))
+    w = net.loss_weights(at, ct).cpu().numpy()
+    np.testing.assert_allclose(w, ounet.loss_weights(a[:, None].astype(np.float64), c[:, None].astype(np.float64)),
+                               rtol=1e-6)
+    assert w[2] == 0.0
+    g1, L1 = net.loss_grad(xt, at, ct)
+    g2, L2 = net.loss_grad(xt, at, ct, weight=torch.from_numpy(w).to(DEV))
+    assert abs(L1 - L2) <= 1e-6 * abs(L1)
+    assert _rel(g2.cpu().numpy(), g1.cpu().numpy()) < 1e-6
+    net.close()

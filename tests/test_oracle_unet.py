@@ -133,6 +133,24 @@ def test_scaling_loss_minimum():
     assert abs(L0) < 1e-20
 
 
+def test_loss_weights_tiles():
+    """Explicit weights: the default weights reproduce the default loss, and
+    the loss of an image equals the summed losses of its disjoint tiles
+    weighted by the whole image's weight; non-positive sum c gives weight 0."""
+    rng = _rng(9)
+    o = rng.standard_normal((2, 1, 8, 8)) * 0.3
+    a = rng.random((2, 1, 8, 8)) + 0.1
+    c = rng.random((2, 1, 8, 8))
+    L, g = unet.scaling_loss(o, a, c)
+    L2, g2 = unet.scaling_loss(o, a, c, unet.loss_weights(a, c))
+    assert L == L2 and np.array_equal(g, g2)
+    w = unet.loss_weights(a, c)
+    parts = [unet.scaling_loss(o[:, :, i:i + 4, j:j + 4], a[:, :, i:i + 4, j:j + 4], c[:, :, i:i + 4, j:j + 4], w)[0]
+             for i in (0, 4) for j in (0, 4)]
+    assert abs(sum(parts) - L) < 1e-12 * abs(L)
+    assert unet.loss_weights(a, -c)[0] == 0.0
+
+
 def test_bf16_forward_close_to_fp64():
     """bf16 emulation perturbs the output by about the bf16 unit roundoff."""
     rng = _rng(8)
@@ -170,7 +188,7 @@ def test_precond_inputs_constant_residual():
     x, a = unet.precond_inputs(r, v, w2)
     np.testing.assert_allclose(x[0], np.log(2.0))
     np.testing.assert_allclose(x[1], 1.0)
-    np.testing.assert_allclose(x[2], 0.2)
+    np.testing.assert_allclose(x[2], np.log(20.0) / 4.0)
     np.testing.assert_allclose(a, 45.0)
 
 
@@ -215,16 +233,22 @@ def test_fpcg_exact_inverse_one_iteration(tiny_system):
 
 
 def test_fpcg_fallback(tiny_system):
-    """An indefinite preconditioner (z.r < 0) hands over to CG at once, and a
-    preconditioner that stalls is replaced after ten iterations without a new
-    best residual; both still reach the CG solution."""
+    """An indefinite preconditioner (z.r < 0) hands over at once, and one that
+    stalls is replaced after 20 iterations without a new best residual: by the
+    fallback preconditioner when given (which equals running with it from
+    that point), then by plain CG; the result still converges."""
     N, b = tiny_system["N"], tiny_system["b"]
     ref = core.cg(lambda p: N @ p, b, 6)
     neg = core.fpcg(lambda p: N @ p, b, lambda r: -r, 6)
-    assert neg.fallback_at == 0
+    assert neg.fallback_at == 0 and neg.cg_at == 0
     np.testing.assert_allclose(neg.res_hist, ref.res_hist, rtol=1e-7)
+    D = 1.0 / np.diag(N)
+    neg2 = core.fpcg(lambda p: N @ p, b, lambda r: -r, 6, precond_fallback=lambda r: D * r)
+    pcg = core.fpcg(lambda p: N @ p, b, lambda r: D * r, 6)
+    assert neg2.fallback_at == 0 and neg2.cg_at is None
+    np.testing.assert_allclose(neg2.res_hist, pcg.res_hist, rtol=1e-7)
     e0 = np.zeros_like(b)
     e0[0] = 1.0
-    stuck = core.fpcg(lambda p: N @ p, b, lambda r: e0 * (r @ e0) + 1e-30 * r, 60)
-    assert stuck.fallback_at is not None and stuck.fallback_at >= 10
-    assert stuck.res_hist[-1] < ref.res_hist[-1]
+    stuck = core.fpcg(lambda p: N @ p, b, lambda r: e0 * (r @ e0) + 1e-30 * r, 80)
+    assert stuck.fallback_at is not None and stuck.fallback_at >= 20 and stuck.cg_at == stuck.fallback_at
+    assert stuck.res_hist[-1] < core.cg(lambda p: N @ p, b, 40).res_hist[-1]
