@@ -232,6 +232,22 @@ esi_status_t esi_grad_velocity(esi_plan_t plan, const float* vel, const float* g
 esi_status_t esi_plan_set_time_block(esi_plan_t plan, int32_t steps);
 
 /*
+ * Autotuner of the launch configuration.  For the plan's grid and a batch of
+ * nshots shots it times each candidate (2D: one or two time steps per launch,
+ * chosen separately for forward-type and adjoint-type loops) on one
+ * application of the normal operator with p (device [nshots][nt][phys],
+ * contents irrelevant; Ap is overwritten), after a warm-up run of each, with
+ * the plan's hipEvent profiling, and keeps the faster one of each direction.
+ * Results are cached per process for (ndim, padded shape, nshots); force != 0
+ * measures again.  Propagations are bitwise the same for every candidate;
+ * dot products (p.Np) sum their partials over a different tiling, so CG
+ * results agree to rounding.  choice: host int[2] out (forward, adjoint steps per
+ * launch) or NULL.  3D plans have a single configuration (1, 1).
+ */
+esi_status_t esi_plan_autotune(esi_plan_t plan, int32_t shot0, int32_t nshots, const float* p,
+                               float* Ap, int32_t force, int32_t* choice);
+
+/*
  * CG iterations (Algorithm 1) replayed from captured HIP graphs.  With
  * enable != 0, esi_cg_solve runs iteration 0 directly and captures iterations
  * 1 and 2 once (one graph per parity of the iteration index, since the

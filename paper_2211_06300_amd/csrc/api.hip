@@ -45,7 +45,7 @@ esi_status_t launch_step(Plan* P, unsigned flags, const StepArgs& a, bool two) {
     return P->ndim == 2 ? launch_step2d(P, flags, a, two) : launch_step3d(P, flags, a);
 }
 
-bool two_step_ok(Plan* P) { return P->ndim == 2 && P->time_block == 2; }
+bool two_step_ok(Plan* P, bool adjoint) { return P->ndim == 2 && (adjoint ? P->tb_adj : P->tb_fwd) == 2; }
 
 // Point the tile fields and sparse lists of `a` at the tiling `L`.
 void apply_lists(StepArgs& a, const TileLists* L) {
@@ -56,10 +56,11 @@ void apply_lists(StepArgs& a, const TileLists* L) {
     a.inj2_ptr = L->inj2_ptr; a.inj2_cell = L->inj2_cell; a.inj2_rptr = L->inj2_rptr; a.inj2_rid = L->inj2_rid;
 }
 
-// Tiling of two-step launches (nullptr when they are not used).
-esi_status_t t2_lists(Plan* P, TileLists** L2) {
+// Tiling of two-step launches of forward or adjoint loops (nullptr when they
+// are not used).
+esi_status_t t2_lists(Plan* P, TileLists** L2, bool adjoint) {
     *L2 = nullptr;
-    if (!two_step_ok(P)) return ESI_OK;
+    if (!two_step_ok(P, adjoint)) return ESI_OK;
     int tx, tz;
     step2d_t2_tile_shape(&tx, &tz);
     return get_lists(P, tx, tz, 1, L2);
@@ -131,7 +132,7 @@ esi_status_t forward_loop(Plan* P, StepArgs a, unsigned flags, float* ring, int*
                           int n1, float* ckpt = nullptr, int K = 0, int nseg = 0) {
     ProfScope p1(P, flags, a.nshots), p2(P, flags | (1u << 15), a.nshots);
     TileLists* L2;
-    ESI_TRY(t2_lists(P, &L2));
+    ESI_TRY(t2_lists(P, &L2, false));
     const bool t2 = L2 != nullptr;
     StepArgs b = a;
     if (t2) apply_lists(b, L2);
@@ -168,7 +169,7 @@ esi_status_t adjoint_loop(Plan* P, StepArgs a, unsigned flags, float* ring, int*
                           int j1, int K = 0) {
     ProfScope p1(P, flags, a.nshots), p2(P, flags | (1u << 15), a.nshots);
     TileLists* L2;
-    ESI_TRY(t2_lists(P, &L2));
+    ESI_TRY(t2_lists(P, &L2, true));
     const bool t2 = L2 != nullptr;
     StepArgs b = a;
     if (t2) apply_lists(b, L2);
@@ -229,7 +230,7 @@ esi_status_t do_normal(Plan* P, int shot0, int ns, const float* p, float* Ap, co
                                 shot0, ns));
     ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
     TileLists* L2;
-    ESI_TRY(t2_lists(P, &L2));
+    ESI_TRY(t2_lists(P, &L2, true));
     P->part_stride = std::max(L->tiles, L2 ? L2->tiles : 0);
     ESI_TRY(grow_t(&P->part, &P->part_cap, (int64_t)ns * P->part_stride, P->stream));
     ESI_TRY(launch_fill_d(P, P->part, (int64_t)ns * P->part_stride));
@@ -343,7 +344,7 @@ std::vector<uintptr_t> cg_graph_key(Plan* P, const CgState& c) {
     return {(uintptr_t)c.shot0, (uintptr_t)c.ns, (uintptr_t)c.max_iter,
             (uintptr_t)std::llround(c.rtol * 1e18), (uintptr_t)c.L, (uintptr_t)c.x,
             (uintptr_t)c.r, (uintptr_t)c.hist, (uintptr_t)P->ring, (uintptr_t)P->dscr,
-            (uintptr_t)P->part, (uintptr_t)P->time_block, (uintptr_t)P->part_stride};
+            (uintptr_t)P->part, (uintptr_t)(P->tb_fwd * 4 + P->tb_adj), (uintptr_t)P->part_stride};
 }
 
 void cg_graph_drop(Plan* P) {
@@ -800,6 +801,10 @@ extern "C" esi_status_t esi_plan_profile(esi_plan_t plan, int32_t enable) {
     return ESI_OK;
 }
 
+namespace {
+esi_status_t fold_profile(Plan* P);
+}
+
 extern "C" esi_status_t esi_plan_profile_read(esi_plan_t plan, int32_t cap, int32_t* count,
                                               uint32_t* flags, int64_t* launches,
                                               int64_t* shot_launches, double* ms) {
@@ -807,18 +812,7 @@ extern "C" esi_status_t esi_plan_profile_read(esi_plan_t plan, int32_t cap, int3
     if (!plan || !count) return fail(ESI_ERR_ARG, "null argument");
     if (cap > 0 && (!flags || !launches || !shot_launches || !ms)) return fail(ESI_ERR_ARG, "null output array");
     Plan* P = (Plan*)plan;
-    for (auto& r : P->prof_pending) {
-        ESI_HIP_TRY(hipEventSynchronize(r.e1));
-        float t = 0.f;
-        ESI_HIP_TRY(hipEventElapsedTime(&t, r.e0, r.e1));
-        bool found = false;
-        for (auto& q : P->prof_tot)
-            if (q.flags == r.flags) { q.launches += r.launches; q.shot_launches += r.shot_launches; q.ms += t; found = true; }
-        if (!found) P->prof_tot.push_back({r.flags, r.launches, r.shot_launches, (double)t});
-        hipEventDestroy(r.e0);
-        hipEventDestroy(r.e1);
-    }
-    P->prof_pending.clear();
+    ESI_TRY(fold_profile(P));
     *count = (int32_t)P->prof_tot.size();
     for (int i = 0; i < cap && i < (int)P->prof_tot.size(); ++i) {
         flags[i] = P->prof_tot[i].flags;
@@ -833,7 +827,98 @@ extern "C" esi_status_t esi_plan_set_time_block(esi_plan_t plan, int32_t steps) 
     set_error("");
     if (!plan) return fail(ESI_ERR_ARG, "null plan");
     if (steps != 1 && steps != 2) return fail(ESI_ERR_ARG, "time block must be 1 or 2");
-    ((Plan*)plan)->time_block = steps;
+    ((Plan*)plan)->tb_fwd = ((Plan*)plan)->tb_adj = steps;
+    return ESI_OK;
+}
+
+namespace {
+
+// Fold the pending event pairs of the plan's profile into its totals.
+esi_status_t fold_profile(Plan* P) {
+    for (auto& r : P->prof_pending) {
+        ESI_HIP_TRY(hipEventSynchronize(r.e1));
+        float t = 0.f;
+        ESI_HIP_TRY(hipEventElapsedTime(&t, r.e0, r.e1));
+        bool found = false;
+        for (auto& q : P->prof_tot)
+            if (q.flags == r.flags) { q.launches += r.launches; q.shot_launches += r.shot_launches; q.ms += t; found = true; }
+        if (!found) P->prof_tot.push_back({r.flags, r.launches, r.shot_launches, (double)t});
+        hipEventDestroy(r.e0);
+        hipEventDestroy(r.e1);
+    }
+    P->prof_pending.clear();
+    return ESI_OK;
+}
+
+// Process-wide cache of tuned choices: (ndim, nzp, nyp, nxp, nshots) -> (fwd, adj).
+struct TuneEntry { int key[5]; int fwd, adj; };
+std::vector<TuneEntry> g_tune_cache;
+
+}  // namespace
+
+extern "C" esi_status_t esi_plan_autotune(esi_plan_t plan, int32_t shot0, int32_t ns, const float* p,
+                                          float* Ap, int32_t force, int32_t* choice) {
+    set_error("");
+    if (!plan) return fail(ESI_ERR_ARG, "null plan");
+    Plan* P = (Plan*)plan;
+    ESI_TRY(check_shots(P, shot0, ns));
+    if (!p || !Ap) return fail(ESI_ERR_ARG, "null pointer");
+    const int64_t n = (int64_t)ns * P->nt * P->nphys;
+    if ((Ap < p + n) && (p < Ap + n)) return fail(ESI_ERR_ARG, "p and Ap overlap");
+    if (P->ndim != 2) {
+        // one configuration only: the 3D kernel has no two-step variant
+        if (choice) { choice[0] = 1; choice[1] = 1; }
+        return ESI_OK;
+    }
+    const int key[5] = {P->ndim, P->nzp, P->nyp, P->nxp, ns};
+    if (!force)
+        for (const TuneEntry& e : g_tune_cache)
+            if (std::equal(key, key + 5, e.key)) {
+                P->tb_fwd = e.fwd;
+                P->tb_adj = e.adj;
+                if (choice) { choice[0] = e.fwd; choice[1] = e.adj; }
+                return ESI_OK;
+            }
+    TileLists* L;
+    ESI_TRY(lists_for(P, &L));
+    // keep the caller's profile aside and time each candidate on its own
+    const bool prof = P->prof_on;
+    std::vector<Plan::ProfRec> pend;
+    std::vector<Plan::ProfTot> tot;
+    pend.swap(P->prof_pending);
+    tot.swap(P->prof_tot);
+    double best_f = 1e300, best_a = 1e300;
+    int tb_f = 2, tb_a = 2;
+    esi_status_t st = ESI_OK;
+    for (int tb = 1; tb <= 2 && st == ESI_OK; ++tb) {
+        P->tb_fwd = P->tb_adj = tb;
+        P->prof_on = false;   // first run builds the tile lists of this choice
+        st = do_normal(P, shot0, ns, p, Ap, L, nullptr, false, nullptr, nullptr, nullptr, nullptr, nullptr);
+        if (st != ESI_OK) break;
+        P->prof_on = true;
+        st = do_normal(P, shot0, ns, p, Ap, L, nullptr, false, nullptr, nullptr, nullptr, nullptr, nullptr);
+        if (st != ESI_OK) break;
+        P->prof_on = false;
+        st = fold_profile(P);
+        if (st != ESI_OK) break;
+        double f = 0.0, a = 0.0;
+        for (const auto& q : P->prof_tot) (q.flags & F_NORMAL ? a : f) += q.ms;
+        P->prof_tot.clear();
+        if (f < best_f) { best_f = f; tb_f = tb; }
+        if (a < best_a) { best_a = a; tb_a = tb; }
+    }
+    P->prof_on = prof;
+    P->prof_pending.swap(pend);
+    P->prof_tot.swap(tot);
+    if (st != ESI_OK) return st;
+    P->tb_fwd = tb_f;
+    P->tb_adj = tb_a;
+    TuneEntry e;
+    std::copy(key, key + 5, e.key);
+    e.fwd = tb_f;
+    e.adj = tb_a;
+    g_tune_cache.push_back(e);
+    if (choice) { choice[0] = tb_f; choice[1] = tb_a; }
     return ESI_OK;
 }
 

@@ -135,7 +135,7 @@ struct Plan {
     int* fcg_i = nullptr; int64_t fcg_i_cap = 0;      // mode, restart, fallback, kbest, cg_at [5][nshots]
 
     std::vector<TileLists*> lists;       // one per tile shape used
-    int time_block = 2;                  // steps per launch where allowed (1 or 2)
+    int tb_fwd = 2, tb_adj = 2;          // 2D steps per launch (1 or 2) of forward / adjoint loops
     // checkpoints retained by esi_forward_ckpt for a SEED_REUSE gradient
     bool ck_valid = false;
     int ck_shot0 = 0, ck_nshots = 0, ck_kind = 0, ck_K = 0;

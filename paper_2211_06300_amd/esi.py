@@ -54,7 +54,7 @@ EXPORTS = ["esi_plan_create", "esi_plan_set_model", "esi_plan_destroy", "esi_las
            "esi_forward_ckpt", "esi_grad_velocity", "esi_plan_set_cg_graph",
            "esi_unet_num_params", "esi_unet_create", "esi_unet_destroy", "esi_unet_set_params",
            "esi_unet_get_params", "esi_unet_forward", "esi_unet_loss_grad", "esi_unet_adam",
-           "esi_fpcg_solve", "esi_precond_features", "esi_unet_loss_weights"]
+           "esi_fpcg_solve", "esi_precond_features", "esi_unet_loss_weights", "esi_plan_autotune"]
 # time-step kernel variants (bit set of fused work), as in include/esi.h
 K_FLAGS = {1: "SRC_POINT", 2: "SRC_DENSE", 4: "CG_FUSE", 8: "INJ", 16: "GATHER", 32: "OUT",
            64: "NORMAL", 128: "PENALTY", 256: "STORE", 512: "CORR", 1024: "SRC_REC",
@@ -84,6 +84,7 @@ def load_library(path: str = LIB_PATH):
     L.esi_plan_profile.argtypes = [vp, i32]
     L.esi_plan_set_time_block.argtypes = [vp, i32]
     L.esi_plan_set_cg_graph.argtypes = [vp, i32]
+    L.esi_plan_autotune.argtypes = [vp, i32, i32, vp, vp, i32, vp]
     L.esi_forward_ckpt.argtypes = [vp, i32, i32, i32, vp, vp, i32]
     L.esi_grad_velocity.argtypes = [vp, vp, vp, vp]
     L.esi_plan_profile_read.argtypes = [vp, i32, vp, vp, vp, vp, vp]
@@ -203,6 +204,17 @@ class Plan:
     # -- calls ------------------------------------------------------------------
     def set_time_block(self, steps: int):
         _check(self._lib.esi_plan_set_time_block(self._h, int(steps)))
+
+    def autotune(self, shot0=0, nshots=None, force=False, p=None, Ap=None):
+        """esi_plan_autotune; returns (forward, adjoint) steps per launch."""
+        shot0, nshots = self._range(shot0, nshots)
+        p = self.new_vec(nshots) if p is None else p
+        Ap = self.new_vec(nshots) if Ap is None else Ap
+        ch = np.zeros(2, dtype=np.int32)
+        _check(self._lib.esi_plan_autotune(self._h, shot0, nshots, _f32(p, self.vec_shape(nshots), "p"),
+                                           _f32(Ap, self.vec_shape(nshots), "Ap"), int(bool(force)),
+                                           ch.ctypes.data_as(ctypes.c_void_p)))
+        return int(ch[0]), int(ch[1])
 
     def set_cg_graph(self, enable: bool):
         _check(self._lib.esi_plan_set_cg_graph(self._h, int(bool(enable))))

@@ -101,3 +101,25 @@ def test_cg_graph_small_config_timing(esi):
     assert torch.equal(out[True][0][1], out[False][0][1])
     assert torch.equal(out[True][1][1], out[False][0][1])
     plan.close()
+
+
+def test_autotune_choice_and_results(esi):
+    """The autotuner picks one or two steps per launch for each direction on
+    the plan's shapes and caches it; CG results agree with the untuned ones
+    to rounding (only the p.Np partials are summed over another tiling), and
+    propagations are bitwise the same."""
+    cfg = _ragged_cfg(nt=40)
+    d = _d_obs(cfg)
+    plan = _plan(esi, cfg)
+    x0, _ = plan.cg_solve(d, max_iter=4)
+    x0 = x0.clone()
+    ch = plan.autotune()
+    assert ch[0] in (1, 2) and ch[1] in (1, 2)
+    assert plan.autotune() == ch                     # cached
+    x1, _ = plan.cg_solve(d, max_iter=4)
+    assert float(torch.linalg.norm(x1 - x0) / torch.linalg.norm(x0)) < 1e-6
+    w = torch.from_numpy(np.tile(cfg.wavelet, (cfg.nshots, 1))).to(DEV)
+    y0 = plan.forward(w, esi.SRC_POINT).clone()
+    plan.set_time_block(1)
+    assert torch.equal(plan.forward(w, esi.SRC_POINT), y0)
+    plan.close()
