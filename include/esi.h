@@ -91,6 +91,15 @@ typedef struct {
     const int32_t* src;     /* host [nshots][ndim] source cells */
     const int64_t* rec_ptr; /* host [nshots+1], rec_ptr[0] = 0, non-decreasing */
     const int32_t* rec;     /* host [rec_ptr[nshots]][ndim] receiver cells */
+    const int32_t* window;  /* host [nshots][2] or NULL (2D only): shot s propagates on the
+                               physical columns [window[2s], window[2s+1]) alone (its aperture),
+                               with the absorbing layer around that window (the model beyond the
+                               window edge fills the layer, edge copies beyond the grid); its
+                               source and receivers must lie in the window.  Dense vectors keep
+                               the whole-grid layout and are zero outside the window.  Launches
+                               cover only the tiles that meet a window, so a batch of shots of
+                               uneven aperture costs the sum of their windows.  NULL: every
+                               shot uses the whole grid. */
 } esi_geom_t;
 
 /*

@@ -230,6 +230,26 @@ def make_model(g: Grid, v: np.ndarray, eta_max: float | None = None) -> Model:
     return Model(g, np.asarray(v, np.float64).reshape(g.phys_shape), c, kap, eta_max)
 
 
+def window_model(m: Model, x0: int, x1: int) -> Model:
+    """The model a 2D shot with aperture [x0, x1) propagates on (reading of the
+    uneven-aperture workload: each shot is modelled on its window alone).
+
+    Its physical columns are x0 .. x1-1; its absorbing layer of nb cells on
+    every side holds the padded model beyond the window (the true model where
+    the grid continues, edge copies beyond the grid), i.e. columns x0 ..
+    x1 + 2 nb - 1 of the whole padded model; the damping profile surrounds
+    the window, with the whole model's eta_max.  Positions in the window are
+    the grid's minus x0.
+    """
+    g = m.g
+    if g.ndim != 2:
+        raise ValueError("apertures are 2D")
+    gw = Grid(2, g.nz, x1 - x0, nb=g.nb, nt=g.nt, dx=g.dx, dt=g.dt)
+    c = np.ascontiguousarray(m.c[:, x0:x1 + 2 * g.nb])
+    kap = np.ascontiguousarray(damping(gw, m.eta_max))
+    return Model(gw, np.ascontiguousarray(m.v_phys[:, x0:x1]), c, kap, m.eta_max)
+
+
 # ---------------------------------------------------------------------------
 # Modelling S = R A^{-1} and adjoint S^T (Sec. 2.1, eq. (wave), eq. (FWI_lambda);
 # Sec. 3 first bullet: the right-hand side by adjoint modelling)

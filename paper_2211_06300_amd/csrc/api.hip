@@ -54,6 +54,13 @@ void apply_lists(StepArgs& a, const TileLists* L) {
     a.gat_ptr = L->gat_ptr; a.gat_cell = L->gat_cell; a.gat_rid = L->gat_rid;
     a.src_tile = L->src_tile; a.src_cell = L->src_cell;
     a.inj2_ptr = L->inj2_ptr; a.inj2_cell = L->inj2_cell; a.inj2_rptr = L->inj2_rptr; a.inj2_rid = L->inj2_rid;
+    if (L->work) {
+        a.work = L->work + L->work_ptr[a.shot0];
+        a.nwork = (int)(L->work_ptr[a.shot0 + a.nshots] - L->work_ptr[a.shot0]);
+    } else {
+        a.work = nullptr;
+        a.nwork = 0;
+    }
 }
 
 // Tiling of two-step launches of forward or adjoint loops (nullptr when they
@@ -83,6 +90,8 @@ StepArgs base_args(Plan* P, const TileLists* L, int shot0, int nshots) {
     a.dir = 1;
     a.nshots = nshots; a.shot0 = shot0;
     a.src_pos = P->d_src; a.rec_ptr = P->d_rec_ptr;
+    a.win = P->d_win;
+    a.kx_stride = P->d_win ? P->nxp : 0;
     apply_lists(a, L);
     return a;
 }

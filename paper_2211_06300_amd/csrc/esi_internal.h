@@ -61,6 +61,10 @@ struct TileLists {
     int32_t* inj2_cell = nullptr;
     int32_t* inj2_rptr = nullptr;
     int32_t* inj2_rid = nullptr;
+    // with apertures: the (shot, tile) items whose tile meets the shot's
+    // window plus its absorbing layer, shot-major; work_ptr[gs] indexes it
+    int32_t* work = nullptr;
+    std::vector<int64_t> work_ptr;
 };
 
 struct Plan {
@@ -125,6 +129,8 @@ struct Plan {
     hipGraphExec_t cg_exec[2] = {nullptr, nullptr};
     std::vector<uintptr_t> cg_key;       // what the captured graphs were built for
     float* vphys = nullptr;              // physical velocity [nphys] (network features)
+    std::vector<int32_t> h_win;          // per-shot apertures [nshots][2] (empty: whole grid)
+    int32_t* d_win = nullptr;
     // flexible CG scratch: cell scale and energy [nshots][nphys], network input
     // [nshots][3][Hp][Wp] and output [nshots][Hp][Wp], scalars
     float* fcg_s = nullptr; int64_t fcg_s_cap = 0;
@@ -214,6 +220,14 @@ struct StepArgs {
     float* cg_pn;            // p_new (written; a different buffer from cg_p)
     float* cg_x;
     const float* cg_s;           // F_SCALE: per-shot cell scale [nshots][nphys], z = s r
+    // per-shot apertures (2D): physical columns [win[2 gs], win[2 gs + 1]) of
+    // global shot gs, or nullptr for the whole grid; damping table of shot gs
+    // at kx + kx_stride * gs; work list of (shot, tile) items gs * tiles + t
+    // of this batch (nwork of them), or nullptr for every tile of every shot
+    const int32_t* win;
+    int kx_stride;
+    const int32_t* work;
+    int nwork;
     const double* cg_alpha;  // [nshots]
     const double* cg_beta;   // [nshots]
     // gradient

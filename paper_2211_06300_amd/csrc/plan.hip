@@ -148,7 +148,22 @@ static esi_status_t set_model(Plan* P, const float* vel, bool first, double eta_
             ESI_HIP_TRY(hipMemcpy(*dst, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
             return ESI_OK;
         };
-        ESI_TRY(prof(P->nx, &P->kx));
+        if (P->h_win.empty()) {
+            ESI_TRY(prof(P->nx, &P->kx));
+        } else {
+            // one profile per shot, around its window [x0, x1) (padded x0 .. x1 + 2 nb)
+            std::vector<float> h((size_t)P->nshots * P->nxp);
+            for (int s = 0; s < P->nshots; ++s) {
+                const int x0 = P->h_win[2 * s], x1 = P->h_win[2 * s + 1];
+                for (int i = 0; i < P->nxp; ++i) {
+                    int d = std::max(std::max(x0 + P->nb - i, i - (x1 + P->nb - 1)), 0);
+                    double r = (double)d / P->nb;
+                    h[(size_t)s * P->nxp + i] = (float)(P->eta_max * r * r * P->dt / 2.0);
+                }
+            }
+            ESI_HIP_TRY(hipMalloc(&P->kx, h.size() * sizeof(float)));
+            ESI_HIP_TRY(hipMemcpy(P->kx, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
+        }
         ESI_TRY(prof(P->nz, &P->kz));
         if (P->ndim == 3) {
             ESI_TRY(prof(P->ny, &P->ky));
@@ -283,6 +298,21 @@ esi_status_t get_lists(Plan* P, int tx, int tz, int ty, TileLists** out) {
     ESI_TRY(up(inj2_cell, &L->inj2_cell));
     ESI_TRY(up(inj2_rptr, &L->inj2_rptr));
     ESI_TRY(up(inj2_rid, &L->inj2_rid));
+    if (!P->h_win.empty()) {
+        // the (shot, tile) items whose tile columns meet the shot's window plus layer
+        std::vector<int32_t> work;
+        L->work_ptr.assign(P->nshots + 1, 0);
+        for (int s = 0; s < P->nshots; ++s) {
+            const int lo = P->h_win[2 * s], hi = P->h_win[2 * s + 1] + 2 * P->nb;   // padded [lo, hi)
+            for (int t = 0; t < L->tiles; ++t) {
+                const int txi = t % L->tiles_x;
+                const int a0 = txi * tx, a1 = a0 + tx;
+                if (a0 < hi && a1 > lo) work.push_back(s * L->tiles + t);
+            }
+            L->work_ptr[s + 1] = (int64_t)work.size();
+        }
+        ESI_TRY(up(work, &L->work));
+    }
     P->lists.push_back(L);
     *out = L;
     return ESI_OK;
@@ -293,6 +323,7 @@ static void free_lists(TileLists* L) {
     hipFree(L->gat_ptr); hipFree(L->gat_cell); hipFree(L->gat_rid);
     hipFree(L->src_tile); hipFree(L->src_cell);
     hipFree(L->inj2_ptr); hipFree(L->inj2_cell); hipFree(L->inj2_rptr); hipFree(L->inj2_rid);
+    if (L->work) hipFree(L->work);
     delete L;
 }
 
@@ -307,7 +338,7 @@ static void free_plan(Plan* P) {
     if (P->h_ctl) hipHostFree(P->h_ctl);
     void* bufs[] = {P->d_src, P->d_rec_ptr, P->c2, P->kx, P->kz, P->ky, P->ring, P->ring2,
                     P->dscr, P->dscr2, P->part, P->scal, P->gshot, P->store, P->ckpt, P->flags,
-                    P->d_rec, P->cgi, P->cg_hist, P->vphys, P->fcg_s, P->fcg_a, P->fcg_in,
+                    P->d_rec, P->cgi, P->cg_hist, P->vphys, P->d_win, P->fcg_s, P->fcg_a, P->fcg_in,
                     P->fcg_o, P->fcg_d, P->fcg_i};
     for (void* b : bufs)
         if (b) hipFree(b);
@@ -349,6 +380,19 @@ extern "C" esi_status_t esi_plan_create(esi_plan_t* plan, const esi_grid_t* g, c
         if (!inside(geo->src + (size_t)s * nd)) return fail(ESI_ERR_SHAPE, "source " + std::to_string(s) + " outside the grid");
     for (int64_t r = 0; r < nrec; ++r)
         if (!inside(geo->rec + r * nd)) return fail(ESI_ERR_SHAPE, "receiver " + std::to_string(r) + " outside the grid");
+    if (geo->window) {
+        if (nd != 2) return fail(ESI_ERR_ARG, "shot apertures are supported on 2D grids");
+        for (int s = 0; s < geo->nshots; ++s) {
+            const int32_t x0 = geo->window[2 * s], x1 = geo->window[2 * s + 1];
+            if (!(x0 >= 0 && x0 < x1 && x1 <= g->nx))
+                return fail(ESI_ERR_SHAPE, "window of shot " + std::to_string(s) + " outside [0, nx)");
+            const int32_t sx = geo->src[(size_t)s * nd];
+            if (sx < x0 || sx >= x1) return fail(ESI_ERR_SHAPE, "source " + std::to_string(s) + " outside its window");
+            for (int64_t r = geo->rec_ptr[s]; r < geo->rec_ptr[s + 1]; ++r)
+                if (geo->rec[r * nd] < x0 || geo->rec[r * nd] >= x1)
+                    return fail(ESI_ERR_SHAPE, "receiver " + std::to_string(r) + " outside its shot's window");
+        }
+    }
 
     Plan* P = new (std::nothrow) Plan();
     if (!P) return fail(ESI_ERR_OOM, "host allocation failed");
@@ -381,6 +425,7 @@ extern "C" esi_status_t esi_plan_create(esi_plan_t* plan, const esi_grid_t* g, c
     P->nshots = geo->nshots;
     P->h_src.assign(geo->src, geo->src + (size_t)geo->nshots * nd);
     P->h_rec_ptr.assign(geo->rec_ptr, geo->rec_ptr + geo->nshots + 1);
+    if (geo->window) P->h_win.assign(geo->window, geo->window + 2 * (size_t)geo->nshots);
     P->h_rec.assign(geo->rec, geo->rec + nrec * nd);
     for (int s = 0; s < geo->nshots; ++s)
         P->max_nrec = std::max<int>(P->max_nrec, (int)(geo->rec_ptr[s + 1] - geo->rec_ptr[s]));
@@ -405,6 +450,10 @@ extern "C" esi_status_t esi_plan_create(esi_plan_t* plan, const esi_grid_t* g, c
             hipMemcpy(P->d_rec_ptr, geo->rec_ptr, (geo->nshots + 1) * 8, hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(P->d_rec, r3.data(), r3.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
             return cleanup(fail(ESI_ERR_HIP, "geometry upload failed"));
+        if (!P->h_win.empty() &&
+            (hipMalloc(&P->d_win, P->h_win.size() * 4) != hipSuccess ||
+             hipMemcpy(P->d_win, P->h_win.data(), P->h_win.size() * 4, hipMemcpyHostToDevice) != hipSuccess))
+            return cleanup(fail(ESI_ERR_HIP, "aperture upload failed"));
     }
     esi_status_t st = set_model(P, vel, true, g->eta_max);
     if (st != ESI_OK) return cleanup(st);

@@ -110,6 +110,35 @@ struct StepPtrs {
     const float* stin;   // stored (dA/dm)u of this step (CORR)
 };
 
+// Shot and tile of workgroup L: from the batch's work list when shots have
+// apertures, else tile fastest within a shot.
+__device__ __forceinline__ void work_item(const StepArgs& a, int L, int* s, int* t) {
+    if (a.work) {
+        const int w = a.work[L];
+        const int gs = w / a.tiles;
+        *s = gs - a.shot0;
+        *t = w - gs * a.tiles;
+    } else {
+        *s = L / a.tiles;
+        *t = L - *s * a.tiles;
+    }
+}
+
+// Physical columns [lo, hi) of global shot gs and its damping table.  Cells
+// outside the aperture plus its absorbing layer see c2 = 0, so their zero
+// state stays zero: the shot propagates on its window alone.
+struct Aperture {
+    int lo, hi;
+    const float* kx;
+};
+__device__ __forceinline__ Aperture aperture(const StepArgs& a, int gs) {
+    Aperture ap;
+    ap.lo = a.win ? a.win[2 * gs] : 0;
+    ap.hi = a.win ? a.win[2 * gs + 1] : a.nx;
+    ap.kx = a.kx + (int64_t)a.kx_stride * gs;
+    return ap;
+}
+
 __device__ __forceinline__ StepPtrs step_ptrs(const StepArgs& a, int s, int64_t vbase, int slot) {
     StepPtrs q;
     q.dout = a.dout ? a.dout + vbase : nullptr;
@@ -153,11 +182,11 @@ __global__ __launch_bounds__(256, ESI_MINW) void k_step2d(const StepArgs a) {
     // tile index fastest within a shot: each XCD streams a contiguous stretch
     // of one shot's fields (shot-fastest, to share c2 in L2, fetched fewer
     // bytes but ran slower: the scattered streams cost more than they save)
-    const int L = xcd_remap(blockIdx.x, gridDim.x);
-    const int s = L / a.tiles;
-    const int t = L - s * a.tiles;
+    int s, t;
+    work_item(a, xcd_remap(blockIdx.x, gridDim.x), &s, &t);
     if (a.active && !a.active[s]) return;   // uniform over the workgroup
     const int gs = a.shot0 + s;
+    const Aperture ap = aperture(a, gs);
     const int tzi = t / a.tiles_x, txi = t - tzi * a.tiles_x;
     const int x0 = txi * TX, z0 = tzi * TZ;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -190,9 +219,10 @@ __global__ __launch_bounds__(256, ESI_MINW) void k_step2d(const StepArgs a) {
     // this lane's column and rows: issue every global load first
     const int xl = wx * 64 + lane;                       // tile-local column
     const int x = x0 + xl;
-    const float kxv = at(a.kx, (uint32_t)min(x, a.nxp - 1));
+    const float kxv = at(ap.kx, (uint32_t)min(x, a.nxp - 1));
     const int ix = x - a.nb;
-    const bool xphys = ix >= 0 && ix < a.nx;
+    const bool xphys = ix >= ap.lo && ix < ap.hi;
+    const bool xwin = x >= ap.lo && x < ap.hi + 2 * a.nb;
     const int zb = z0 + wz * RZ;
     const uint32_t so0 = (uint32_t)((zb + GH) * XS + x + GH);
     const int64_t vbase = ((int64_t)s * a.nt + a.step) * a.nphys;
@@ -203,7 +233,7 @@ __global__ __launch_bounds__(256, ESI_MINW) void k_step2d(const StepArgs a) {
 #pragma unroll
     for (int i = 0; i < RZ; ++i) {
         const int z = zb + i;
-        c2v[i] = at(a.c2, so0 + (uint32_t)(i * XS));
+        c2v[i] = xwin ? at(a.c2, so0 + (uint32_t)(i * XS)) : 0.f;
         dv[i] = at(din, so0 + (uint32_t)(i * XS));
         kzv[i] = at(a.kz, (uint32_t)min(z, a.nzp - 1));
         const int iz = z - a.nb;
@@ -373,11 +403,11 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
     __shared__ float sinj[(FL & F_INJ) ? A_H * A_W : 1];
     __shared__ double sred[4];
 
-    const int L = xcd_remap(blockIdx.x, gridDim.x);
-    const int s = L / a.tiles;
-    const int t = L - s * a.tiles;
+    int s, t;
+    work_item(a, xcd_remap(blockIdx.x, gridDim.x), &s, &t);
     if (a.active && !a.active[s]) return;   // uniform over the workgroup
     const int gs = a.shot0 + s;
+    const Aperture ap = aperture(a, gs);
     const int tzi = t / a.tiles_x, txi = t - tzi * a.tiles_x;
     const int x0 = txi * T2W, z0 = tzi * T2Z;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -408,9 +438,10 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
     // ---- first-step loads: lane = region column, rows wv*A_RZ + i of the region
     const int xa = x0 - HALO + lane;                      // padded column
     const bool xa_in = xa >= 0 && xa < a.nxp;
-    const float kxa = at(a.kx, (uint32_t)min(max(xa, 0), a.nxp - 1));
+    const float kxa = at(ap.kx, (uint32_t)min(max(xa, 0), a.nxp - 1));
     const int ixa = xa - a.nb;
-    const bool xa_phys = ixa >= 0 && ixa < a.nx;
+    const bool xa_phys = ixa >= ap.lo && ixa < ap.hi;
+    const bool xa_win = xa >= ap.lo && xa < ap.hi + 2 * a.nb;
     const bool xa_tile = lane >= HALO && lane < HALO + T2W;
     const int zra = wv * A_RZ;                            // first region row of this wave
     const uint32_t soA = (uint32_t)((z0 - HALO + zra + GH) * XS + xa + GH);
@@ -420,7 +451,7 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
 #pragma unroll
     for (int i = 0; i < A_RZ; ++i) {
         const int z = z0 - HALO + zra + i;
-        cA[i] = at(a.c2, soA + (uint32_t)(i * XS));
+        cA[i] = xa_win ? at(a.c2, soA + (uint32_t)(i * XS)) : 0.f;
         dA[i] = at(din, soA + (uint32_t)(i * XS));
         kA[i] = kxa + at(a.kz, (uint32_t)min(max(z, 0), a.nzp - 1));
         inA[i] = xa_in && z >= 0 && z < a.nzp;
@@ -581,9 +612,10 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
     const int lc = min(lane, T2W - 1);
     const bool lane_on = lane < T2W;
     const int x = x0 + lc;
-    const float kxv = at(a.kx, (uint32_t)min(x, a.nxp - 1));
+    const float kxv = at(ap.kx, (uint32_t)min(x, a.nxp - 1));
     const int ix = x - a.nb;
-    const bool xphys = lane_on && ix >= 0 && ix < a.nx;
+    const bool xphys = lane_on && ix >= ap.lo && ix < ap.hi;
+    const bool xwin = x >= ap.lo && x < ap.hi + 2 * a.nb;
     const int zb = z0 + wv * B_RZ;
     const uint32_t so0 = (uint32_t)((zb + GH) * XS + x + GH);
     float c2v[B_RZ], kzv[B_RZ], qv[B_RZ], pvB[B_RZ], stB[B_RZ], poB[B_RZ], xoB[B_RZ];
@@ -592,7 +624,7 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
 #pragma unroll
     for (int i = 0; i < B_RZ; ++i) {
         const int z = zb + i;
-        c2v[i] = at(a.c2, so0 + (uint32_t)(i * XS));
+        c2v[i] = xwin ? at(a.c2, so0 + (uint32_t)(i * XS)) : 0.f;
         kzv[i] = at(a.kz, (uint32_t)min(z, a.nzp - 1));
         const int iz = z - a.nb;
         ph[i] = xphys && iz >= 0 && iz < a.nz;
@@ -700,7 +732,8 @@ __global__ void k_final_gather(const float* __restrict__ field, int64_t fstride,
 
 template <unsigned FL, bool T2>
 esi_status_t launch2d(Plan* P, const StepArgs& a) {
-    const int blocks = a.tiles * a.nshots;
+    const int blocks = a.work ? a.nwork : a.tiles * a.nshots;
+    if (blocks == 0) return ESI_OK;
     if constexpr (T2)
         hipLaunchKernelGGL(k_step2d_t2<FL>, dim3(blocks), dim3(256), 0, P->stream, a);
     else

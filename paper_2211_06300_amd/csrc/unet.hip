@@ -176,22 +176,25 @@ __global__ __launch_bounds__(64) void k_conv3_wgrad(const bf16_t* __restrict__ G
 }
 
 // Sum the chunk partials of a 3x3 layer into the flat gradient: weights in
-// [co][ci][3][3] for ci < cin_real, then the bias.
+// [co][ci][3][3] for ci < cin_real, then the bias.  Threads walk the partials
+// in their own layout (ci fastest) so the reads over chunks are coalesced.
 __global__ void k_conv3_wgrad_reduce(const float* __restrict__ part, const float* __restrict__ bpart,
                                      int nchunks, int Cout, int Cin, int cin_real,
                                      float* __restrict__ gflat) {
-    const int64_t nw = (int64_t)Cout * cin_real * 9;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nw + Cout;
+    const int64_t per = (int64_t)9 * Cout * Cin;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < per + Cout;
          i += (int64_t)gridDim.x * blockDim.x) {
         float s = 0.f;
-        if (i < nw) {
-            const int tap = (int)(i % 9), ci = (int)((i / 9) % cin_real), co = (int)(i / (9 * cin_real));
-            for (int c = 0; c < nchunks; ++c) s += part[(((int64_t)c * 9 + tap) * Cout + co) * Cin + ci];
+        if (i < per) {
+            const int ci = (int)(i % Cin), co = (int)((i / Cin) % Cout), tap = (int)(i / ((int64_t)Cin * Cout));
+            if (ci >= cin_real) continue;
+            for (int c = 0; c < nchunks; ++c) s += part[(int64_t)c * per + i];
+            gflat[((int64_t)co * cin_real + ci) * 9 + tap] = s;
         } else {
-            const int co = (int)(i - nw);
+            const int co = (int)(i - per);
             for (int c = 0; c < nchunks; ++c) s += bpart[(int64_t)c * Cout + co];
+            gflat[(int64_t)Cout * cin_real * 9 + co] = s;
         }
-        gflat[i] = s;
     }
 }
 
@@ -237,75 +240,189 @@ __global__ void k_relu_mask(bf16_t* __restrict__ G, int sg, const bf16_t* __rest
     }
 }
 
-// Transposed 2x2 convolution, stride 2: Y[n][2i+a][2j+d][co] = b[co] +
-// sum_ci Wt[ci][co][a][d] X[n][i][j][ci] (bf16 out, no activation).
-__global__ void k_convT(const bf16_t* __restrict__ X, int sx, int Cin, const bf16_t* __restrict__ Wt,
-                        const float* __restrict__ bias, bf16_t* __restrict__ Y, int sy, int Cout, int N,
-                        int Hi, int Wi) {
-    const int64_t total = (int64_t)N * 2 * Hi * 2 * Wi * Cout;
-    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < total; i += (int64_t)gridDim.x * NT) {
-        const int co = (int)(i % Cout);
-        const int64_t pix = i / Cout;
-        const int xo = (int)(pix % (2 * Wi)), yo = (int)((pix / (2 * Wi)) % (2 * Hi));
-        const int n = (int)(pix / ((int64_t)4 * Hi * Wi));
-        const int a = yo & 1, d = xo & 1;
-        const bf16_t* xp = X + (((int64_t)n * Hi + (yo >> 1)) * Wi + (xo >> 1)) * sx;
-        float s = bias[co];
-        for (int ci = 0; ci < Cin; ++ci) s += bf2f(Wt[((int64_t)ci * Cout + co) * 4 + a * 2 + d]) * bf2f(xp[ci]);
-        Y[pix * sy + co] = f2bf(s);
+// Transposed 2x2 convolution, stride 2, as a GEMM per input pixel on
+// v_mfma_f32_16x16x16_bf16: D[(a d) Cout + co][pixel] = sum_ci W4[(a d) Cout +
+// co][ci] X[pixel][ci], stored with its bias at output pixel (2i + a, 2j + d).
+// W4 is [4 Cout][Cin] bf16.  Workgroup: 4 waves, one input row each, 64 input
+// pixels x 16 CB rows of D.
+template <int CB>
+__global__ __launch_bounds__(NT) void k_convT_mfma(const bf16_t* __restrict__ X, int sx, int Cin,
+                                                   const bf16_t* __restrict__ W4, const float* __restrict__ bias,
+                                                   bf16_t* __restrict__ Y, int sy, int Cout, int Hi, int Wi) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int M = 4 * Cout;
+    const int ncog = M / (16 * CB);
+    const int n = blockIdx.z / ncog;
+    const int m0 = (blockIdx.z % ncog) * 16 * CB;
+    const int y = blockIdx.y * 4 + wave;
+    if (y >= Hi) return;
+    const int x0 = blockIdx.x * 64;
+    const int jl = lane & 15, kq = (lane >> 4) * 4;
+    f4 acc[4][CB];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) acc[p][c] = f4{0.f, 0.f, 0.f, 0.f};
+    const bf16_t* Xr = X + ((int64_t)n * Hi + y) * Wi * sx;
+    for (int ci = 0; ci < Cin; ci += 16) {
+        s4 b[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int xx = x0 + p * 16 + jl;
+            b[p] = xx < Wi ? *reinterpret_cast<const s4*>(Xr + (int64_t)xx * sx + ci + kq) : s4{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const s4 av = *reinterpret_cast<const s4*>(W4 + (int64_t)(m0 + c * 16 + jl) * Cin + ci + kq);
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+                acc[p][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, b[p], acc[p][c], 0, 0, 0);
+        }
+    }
+    const int Wo = 2 * Wi;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int xx = x0 + p * 16 + jl;
+        if (xx >= Wi) continue;
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const int mrow = m0 + c * 16 + kq;            // four consecutive rows: same (a, d)
+            const int ad = mrow / Cout, co = mrow - ad * Cout;
+            const int yo = 2 * y + (ad >> 1), xo = 2 * xx + (ad & 1);
+            s4 o;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[e] = (short)f2bf(acc[p][c][e] + bias[co + e]);
+            *reinterpret_cast<s4*>(Y + (((int64_t)n * 2 * Hi + yo) * Wo + xo) * sy + co) = o;
+        }
     }
 }
 
-// Data gradient of the transposed convolution:
-// GX[n][i][j][ci] = bf16(sum_{a,d,co} Wt[ci][co][a][d] GY[n][2i+a][2j+d][co]).
-__global__ void k_convT_dgrad(const bf16_t* __restrict__ GY, int sg, int Cout, const bf16_t* __restrict__ Wt,
-                              bf16_t* __restrict__ GX, int sx, int Cin, int N, int Hi, int Wi) {
-    const int64_t total = (int64_t)N * Hi * Wi * Cin;
-    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < total; i += (int64_t)gridDim.x * NT) {
-        const int ci = (int)(i % Cin);
-        const int64_t pix = i / Cin;
-        const int j = (int)(pix % Wi), ii = (int)((pix / Wi) % Hi), n = (int)(pix / ((int64_t)Hi * Wi));
-        float s = 0.f;
-        for (int a = 0; a < 2; ++a)
-            for (int d = 0; d < 2; ++d) {
-                const bf16_t* g = GY + (((int64_t)n * 2 * Hi + 2 * ii + a) * (2 * Wi) + 2 * j + d) * sg;
-                for (int co = 0; co < Cout; ++co)
-                    s += bf2f(Wt[((int64_t)ci * Cout + co) * 4 + a * 2 + d]) * bf2f(g[co]);
-            }
-        GX[pix * sx + ci] = f2bf(s);
+// Data gradient of the transposed convolution: D[ci][pixel] = sum over
+// (a d, co) of WT[ci][(a d) Cout + co] GY[(2i + a, 2j + d)][co]; WT is
+// [Cin][4 Cout] bf16.  Same workgroup shape as k_convT_mfma.
+template <int CB>
+__global__ __launch_bounds__(NT) void k_convT_dgrad_mfma(const bf16_t* __restrict__ GY, int sg, int Cout,
+                                                         const bf16_t* __restrict__ WT, bf16_t* __restrict__ GX,
+                                                         int sx, int Cin, int Hi, int Wi) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ncog = Cin / (16 * CB);
+    const int n = blockIdx.z / ncog;
+    const int c0 = (blockIdx.z % ncog) * 16 * CB;
+    const int y = blockIdx.y * 4 + wave;
+    if (y >= Hi) return;
+    const int x0 = blockIdx.x * 64;
+    const int jl = lane & 15, kq = (lane >> 4) * 4;
+    const int K = 4 * Cout, Wo = 2 * Wi;
+    f4 acc[4][CB];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) acc[p][c] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < K; k += 16) {
+        const int ad = k / Cout, co = k - ad * Cout;
+        const bf16_t* Gr = GY + (((int64_t)n * 2 * Hi + 2 * y + (ad >> 1)) * Wo + (ad & 1)) * sg + co + kq;
+        s4 b[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int xx = x0 + p * 16 + jl;
+            b[p] = xx < Wi ? *reinterpret_cast<const s4*>(Gr + (int64_t)2 * xx * sg) : s4{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const s4 av = *reinterpret_cast<const s4*>(WT + (int64_t)(c0 + c * 16 + jl) * K + k + kq);
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+                acc[p][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, b[p], acc[p][c], 0, 0, 0);
+        }
+    }
+    bf16_t* Gxr = GX + ((int64_t)n * Hi + y) * Wi * sx;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int xx = x0 + p * 16 + jl;
+        if (xx >= Wi) continue;
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            s4 o;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[e] = (short)f2bf(acc[p][c][e]);
+            *reinterpret_cast<s4*>(Gxr + (int64_t)xx * sx + c0 + c * 16 + kq) = o;
+        }
     }
 }
 
-// Weight and bias gradient partials of the transposed convolution over a
-// chunk of input pixels: part[chunk][ci][co][a][d] and, after the weights,
-// part[chunk][nw + co] = the bias partial.
-__global__ void k_convT_wgrad(const bf16_t* __restrict__ X, int sx, int Cin, const bf16_t* __restrict__ GY,
-                              int sg, int Cout, int N, int Hi, int Wi, int pix_per_chunk,
-                              float* __restrict__ part) {
-    const int nw = Cin * Cout * 4;
-    const int chunk = blockIdx.y;
-    const int npix = N * Hi * Wi;
-    const int p0 = chunk * pix_per_chunk, p1 = min(npix, p0 + pix_per_chunk);
-    for (int i = blockIdx.x * NT + threadIdx.x; i < nw + Cout; i += gridDim.x * NT) {
-        const bool is_w = i < nw;
-        const int ad = is_w ? i % 4 : 0, co = is_w ? (i / 4) % Cout : i - nw, ci = is_w ? i / (4 * Cout) : 0;
-        const int a = ad >> 1, d = ad & 1;
-        int j = p0 % Wi, ii = (p0 / Wi) % Hi, n = p0 / (Hi * Wi);
-        float s = 0.f;
-        for (int p = p0; p < p1; ++p) {
-            const int64_t q = ((int64_t)n * 2 * Hi + 2 * ii) * (2 * Wi) + 2 * j;   // output (2ii, 2j)
-            if (is_w) {
-                s += bf2f(X[(int64_t)p * sx + ci]) * bf2f(GY[(q + (int64_t)a * 2 * Wi + d) * sg + co]);
-            } else {
-                s += bf2f(GY[q * sg + co]) + bf2f(GY[(q + 1) * sg + co]) +
-                     bf2f(GY[(q + 2 * Wi) * sg + co]) + bf2f(GY[(q + 2 * Wi + 1) * sg + co]);
+// Weight gradient of the transposed convolution: part[chunk][ad][co][ci] =
+// sum over the chunk's input rows of GY[(2i + a, 2j + d)][co] X[(i, j)][ci]
+// (a GEMM over pixels per sub-position ad), and bpart[chunk][co] = the sum of
+// GY over the chunk's output pixels (ci-block 0 waves).  One wave per (chunk,
+// co block, ci block).
+__global__ __launch_bounds__(64) void k_convT_wgrad_mfma(const bf16_t* __restrict__ X, int sx, int Cin,
+                                                         const bf16_t* __restrict__ GY, int sg, int Cout, int Hi,
+                                                         int Wi, int nrows, int rows_per_chunk,
+                                                         float* __restrict__ part, float* __restrict__ bpart) {
+    const int lane = threadIdx.x;
+    const int nci = Cin / 16;
+    const int co0 = (blockIdx.y / nci) * 16, ci0 = (blockIdx.y % nci) * 16;
+    const int chunk = blockIdx.x;
+    const int r0 = chunk * rows_per_chunk, r1 = min(nrows, r0 + rows_per_chunk);
+    const int jl = lane & 15, kq = (lane >> 4) * 4;
+    const int Wo = 2 * Wi;
+    f4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;
+    for (int r = r0; r < r1; ++r) {                       // r = n Hi + i
+        const int n = r / Hi, i = r - n * Hi;
+        const bf16_t* Xr = X + (int64_t)r * Wi * sx;
+        for (int x0 = 0; x0 < Wi; x0 += 16) {
+            s4 b;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int xp = x0 + kq + e;
+                b[e] = xp < Wi ? (short)Xr[(int64_t)xp * sx + ci0 + jl] : (short)0;
             }
-            if (++j == Wi) {
-                j = 0;
-                if (++ii == Hi) { ii = 0; ++n; }
+#pragma unroll
+            for (int ad = 0; ad < 4; ++ad) {
+                const bf16_t* Gr = GY + (((int64_t)n * 2 * Hi + 2 * i + (ad >> 1)) * Wo + (ad & 1)) * sg + co0 + jl;
+                s4 av;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int xp = x0 + kq + e;
+                    av[e] = xp < Wi ? (short)Gr[(int64_t)2 * xp * sg] : (short)0;
+                    bsum += bf2f((bf16_t)av[e]);
+                }
+                acc[ad] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, b, acc[ad], 0, 0, 0);
             }
         }
-        part[(int64_t)chunk * (nw + Cout) + i] = s;
+    }
+    // D[co][ci]: lane holds ci = ci0 + jl, co = co0 + kq + e
+#pragma unroll
+    for (int ad = 0; ad < 4; ++ad)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            part[(((int64_t)chunk * 4 + ad) * Cout + co0 + kq + e) * Cin + ci0 + jl] = acc[ad][e];
+    if (ci0 == 0) {
+        bsum += __shfl_xor(bsum, 16, 64);
+        bsum += __shfl_xor(bsum, 32, 64);
+        if (lane < 16) bpart[(int64_t)chunk * Cout + co0 + lane] = bsum;
+    }
+}
+
+// Transposed-convolution partials into the flat gradient [ci][co][a][d] + bias.
+__global__ void k_convT_wgrad_reduce(const float* __restrict__ part, const float* __restrict__ bpart, int nchunks,
+                                     int Cout, int Cin, float* __restrict__ gflat) {
+    const int64_t per = (int64_t)4 * Cout * Cin;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < per + Cout;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.f;
+        if (i < per) {
+            const int ci = (int)(i % Cin), co = (int)((i / Cin) % Cout), ad = (int)(i / ((int64_t)Cin * Cout));
+            for (int c = 0; c < nchunks; ++c) s += part[(int64_t)c * per + i];
+            gflat[((int64_t)ci * Cout + co) * 4 + ad] = s;
+        } else {
+            const int co = (int)(i - per);
+            for (int c = 0; c < nchunks; ++c) s += bpart[(int64_t)c * Cout + co];
+            gflat[per + co] = s;
+        }
     }
 }
 
@@ -495,6 +612,19 @@ __global__ void k_pack_conv3(const float* __restrict__ w, int Cout, int cin_real
     }
 }
 
+// bf16 copies of transposed-convolution weights from [ci][co][a][d]: forward
+// W4[(a d) Cout + co][ci] and data-gradient WT[ci][(a d) Cout + co].
+__global__ void k_pack_convT(const float* __restrict__ w, int Cin, int Cout, bf16_t* __restrict__ w4,
+                             bf16_t* __restrict__ wt) {
+    const int64_t n = (int64_t)4 * Cin * Cout;
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+        const int ad = (int)(i % 4), co = (int)((i / 4) % Cout), ci = (int)(i / (4 * Cout));
+        const bf16_t h = f2bf(w[i]);
+        w4[((int64_t)ad * Cout + co) * Cin + ci] = h;
+        wt[(int64_t)ci * 4 * Cout + ad * Cout + co] = h;
+    }
+}
+
 __global__ void k_to_bf16(const float* __restrict__ w, bf16_t* __restrict__ o, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) o[i] = f2bf(w[i]);
 }
@@ -615,7 +745,7 @@ esi_status_t conv3_wgrad(const Ctx& c, const bf16_t* GY, int sg, int Cout, const
     float* bpart = U->part + np;
     hipLaunchKernelGGL(k_conv3_wgrad, dim3(nchunks, nblocks), dim3(64), 0, U->stream, GY, sg, Cout, X, sx,
                        Cin, H, W, nrows, rpc, part, bpart);
-    const int64_t nout = (int64_t)Cout * cin_real * 9 + Cout;
+    const int64_t nout = (int64_t)9 * Cout * Cin + Cout;
     hipLaunchKernelGGL(k_conv3_wgrad_reduce, dim3(grid_for(nout)), dim3(NT), 0, U->stream, part, bpart, nchunks,
                        Cout, Cin, cin_real, gflat);
     ESI_HIP_TRY(hipGetLastError());
@@ -625,9 +755,17 @@ esi_status_t conv3_wgrad(const Ctx& c, const bf16_t* GY, int sg, int Cout, const
 esi_status_t convT_fwd(const Ctx& c, int layer, const bf16_t* X, int sx, bf16_t* Y, int sy, int lvl_in) {
     Unet* U = c.U;
     const Layer& Ly = U->L[layer];
-    const int64_t n = c.pix(lvl_in) * 4 * Ly.cout;
-    hipLaunchKernelGGL(k_convT, dim3(grid_for(n)), dim3(NT), 0, U->stream, X, sx, Ly.cin, Ly.wf,
-                       U->theta + Ly.off + Ly.nw, Y, sy, Ly.cout, c.N, c.h(lvl_in), c.w(lvl_in));
+    const int Hi = c.h(lvl_in), Wi = c.w(lvl_in);
+    const int M = 4 * Ly.cout;
+    const int cb = M >= 64 ? 4 : M / 16;
+    dim3 grid((Wi + 63) / 64, (Hi + 3) / 4, c.N * (M / (16 * cb)));
+    const float* bias = U->theta + Ly.off + Ly.nw;
+    if (cb == 4)
+        hipLaunchKernelGGL(k_convT_mfma<4>, grid, dim3(NT), 0, U->stream, X, sx, Ly.cin, Ly.wf, bias, Y, sy,
+                           Ly.cout, Hi, Wi);
+    else
+        hipLaunchKernelGGL(k_convT_mfma<1>, grid, dim3(NT), 0, U->stream, X, sx, Ly.cin, Ly.wf, bias, Y, sy,
+                           Ly.cout, Hi, Wi);
     ESI_HIP_TRY(hipGetLastError());
     return ESI_OK;
 }
@@ -636,18 +774,30 @@ esi_status_t convT_back(const Ctx& c, int layer, const bf16_t* X, int sx, const 
                         bf16_t* GX, int sgx, int lvl_in, float* gflat) {
     Unet* U = c.U;
     const Layer& Ly = U->L[layer];
-    const int64_t npx = c.pix(lvl_in);
-    hipLaunchKernelGGL(k_convT_dgrad, dim3(grid_for(npx * Ly.cin)), dim3(NT), 0, U->stream, GY, sg, Ly.cout,
-                       Ly.wf, GX, sgx, Ly.cin, c.N, c.h(lvl_in), c.w(lvl_in));
-    const int64_t nw = Ly.nw + Ly.cout;
-    // about 4M partials: enough chunks to fill the chip, bounded scratch
-    const int nchunks = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)1 << 22, npx * nw) / nw);
-    const int ppc = (int)((npx + nchunks - 1) / nchunks);
-    ESI_TRY(need_part(U, nchunks * nw));
-    hipLaunchKernelGGL(k_convT_wgrad, dim3((unsigned)((nw + NT - 1) / NT), nchunks), dim3(NT), 0, U->stream, X,
-                       sx, Ly.cin, GY, sg, Ly.cout, c.N, c.h(lvl_in), c.w(lvl_in), ppc, U->part);
-    hipLaunchKernelGGL(k_sum_chunks, dim3(grid_for(nw)), dim3(NT), 0, U->stream, U->part, nchunks, nw,
-                       gflat + Ly.off);
+    const int Hi = c.h(lvl_in), Wi = c.w(lvl_in);
+    {
+        const int cb = Ly.cin >= 64 ? 4 : Ly.cin / 16;
+        dim3 grid((Wi + 63) / 64, (Hi + 3) / 4, c.N * (Ly.cin / (16 * cb)));
+        if (cb == 4)
+            hipLaunchKernelGGL(k_convT_dgrad_mfma<4>, grid, dim3(NT), 0, U->stream, GY, sg, Ly.cout, Ly.wb, GX,
+                               sgx, Ly.cin, Hi, Wi);
+        else
+            hipLaunchKernelGGL(k_convT_dgrad_mfma<2>, grid, dim3(NT), 0, U->stream, GY, sg, Ly.cout, Ly.wb, GX,
+                               sgx, Ly.cin, Hi, Wi);
+    }
+    const int nrows = c.N * Hi;
+    const int nblocks = (Ly.cout / 16) * (Ly.cin / 16);
+    const int want = std::max(1, std::min(nrows, 2048 / nblocks));
+    const int rpc = (nrows + want - 1) / want;
+    const int nchunks = (nrows + rpc - 1) / rpc;
+    const int64_t per = (int64_t)4 * Ly.cout * Ly.cin;
+    ESI_TRY(need_part(U, nchunks * per + (int64_t)nchunks * Ly.cout));
+    float* part = U->part;
+    float* bpart = U->part + nchunks * per;
+    hipLaunchKernelGGL(k_convT_wgrad_mfma, dim3(nchunks, nblocks), dim3(64), 0, U->stream, X, sx, Ly.cin, GY, sg,
+                       Ly.cout, Hi, Wi, nrows, rpc, part, bpart);
+    hipLaunchKernelGGL(k_convT_wgrad_reduce, dim3(grid_for(per + Ly.cout)), dim3(NT), 0, U->stream, part, bpart,
+                       nchunks, Ly.cout, Ly.cin, gflat + Ly.off);
     ESI_HIP_TRY(hipGetLastError());
     return ESI_OK;
 }
@@ -774,6 +924,9 @@ esi_status_t pack(Unet* U) {
             const int64_t n = (int64_t)9 * Ly.cout * cpad;
             hipLaunchKernelGGL(k_pack_conv3, dim3(grid_for(n)), dim3(NT), 0, U->stream, w, Ly.cout, Ly.cin, cpad,
                                Ly.wf, Ly.wb);
+        } else if (Ly.kind == 1) {
+            hipLaunchKernelGGL(k_pack_convT, dim3(grid_for(Ly.nw)), dim3(NT), 0, U->stream, w, Ly.cin, Ly.cout,
+                               Ly.wf, Ly.wb);
         } else {
             hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(Ly.nw)), dim3(NT), 0, U->stream, w, Ly.wf, Ly.nw);
         }
@@ -851,6 +1004,7 @@ extern "C" esi_status_t esi_unet_create(esi_unet_t* out, int32_t H, int32_t W, i
         const int64_t nf = Ly.kind == 0 ? (int64_t)9 * Ly.cout * cpad : Ly.nw;
         if (hipMalloc(&Ly.wf, nf * 2) != hipSuccess) return fail_oom();
         if (Ly.kind == 0 && hipMalloc(&Ly.wb, (int64_t)9 * Ly.cin * Ly.cout * 2) != hipSuccess) return fail_oom();
+        if (Ly.kind == 1 && hipMalloc(&Ly.wb, Ly.nw * 2) != hipSuccess) return fail_oom();
     }
     // zero everything so unused padding channels never hold garbage
     if (hipMemsetAsync(U->act, 0, aoff * 2, U->stream) != hipSuccess ||

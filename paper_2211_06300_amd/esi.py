@@ -36,7 +36,8 @@ class _Grid(ctypes.Structure):
 
 class _Geom(ctypes.Structure):
     _fields_ = [("nshots", ctypes.c_int32), ("src", ctypes.POINTER(ctypes.c_int32)),
-                ("rec_ptr", ctypes.POINTER(ctypes.c_int64)), ("rec", ctypes.POINTER(ctypes.c_int32))]
+                ("rec_ptr", ctypes.POINTER(ctypes.c_int64)), ("rec", ctypes.POINTER(ctypes.c_int32)),
+                ("window", ctypes.POINTER(ctypes.c_int32))]
 
 
 class _CgReport(ctypes.Structure):
@@ -141,7 +142,7 @@ class Plan:
     """
 
     def __init__(self, *, ndim, nz, nx, ny=1, nb, nt, dx, dt, beta, b_eps=1.0, eta_max=-1.0,
-                 src, rec_ptr, rec, vel: torch.Tensor, stream=None):
+                 src, rec_ptr, rec, vel: torch.Tensor, stream=None, window=None):
         self._lib = load_library()
         self.ndim, self.nz, self.nx, self.ny, self.nb, self.nt = ndim, nz, nx, ny, nb, nt
         self.dx, self.dt, self.beta = dx, dt, beta
@@ -152,9 +153,11 @@ class Plan:
         self.rec = np.ascontiguousarray(rec, dtype=np.int32).reshape(-1, ndim)
         self.nshots = self.src.shape[0]
         g = _Grid(ndim, nz, nx, ny, nb, nt, dx, dt, eta_max, beta, b_eps)
+        self.window = None if window is None else np.ascontiguousarray(window, dtype=np.int32).reshape(-1, 2)
         geo = _Geom(self.nshots, self.src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                     self.rec_ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                    self.rec.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+                    self.rec.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                    None if self.window is None else self.window.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
         self.device = vel.device
         self.stream = stream if stream is not None else torch.cuda.current_stream(vel.device)
         h = ctypes.c_void_p()
@@ -167,6 +170,7 @@ class Plan:
     def from_config(cls, cfg, vel: torch.Tensor | None = None, device="cuda", **kw):
         if vel is None:
             vel = torch.from_numpy(np.ascontiguousarray(cfg.v_start)).to(device)
+        kw.setdefault("window", getattr(cfg, "window", None))
         return cls(ndim=cfg.ndim, nz=cfg.nz, nx=cfg.nx, ny=cfg.ny, nb=cfg.nb, nt=cfg.nt,
                    dx=cfg.dx, dt=cfg.dt, beta=cfg.beta, b_eps=cfg.b_eps, src=cfg.src,
                    rec_ptr=cfg.rec_ptr, rec=cfg.rec, vel=vel, **kw)

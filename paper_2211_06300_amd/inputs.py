@@ -56,6 +56,7 @@ class Config:
     wavelet: np.ndarray                # float32 [nt]
     b_eps: float = 1.0
     notes: dict = field(default_factory=dict)
+    window: np.ndarray | None = None    # int32 [nshots][2] physical columns [x0, x1) per shot
 
     @property
     def nshots(self) -> int:
@@ -234,3 +235,54 @@ def cfg_precond(seed: int, nx: int = 401, nz: int = 201, nshots: int = 4, nt: in
     return Config(f"precond-{nx}x{nz}-seed{seed}", 2, nz, nx, 1, 12.5, 1e-3, nt, 20, 8.0, 1e-2, 0,
                   v_true.astype(np.float32), v_start.astype(np.float32), src, ptr, rr,
                   ricker_samples(nt, 1e-3, 8.0))
+
+
+def layered_fault_model(nz: int, nx: int, seed: int, vmin: float = 1500.0, vmax: float = 5000.0,
+                        nlayers: int = 8) -> np.ndarray:
+    """nlayers layers from vmin at the top to vmax (velocities jittered by
+    U[-5, 5] % and sorted, tops at sorted U[20, 0.95 nz] cells below a vmin
+    layer) cut by one normal fault: dip U[20, 40] degrees, throw U[20, 40]
+    cells, through a point at x U[0.3, 0.7] nx on the surface; the hanging
+    wall (right of the fault plane) drops by the throw; float64."""
+    rng = np.random.default_rng(seed)
+    vel = np.linspace(vmin, vmax, nlayers) * (1.0 + rng.uniform(-0.05, 0.05, nlayers))
+    vel = np.clip(np.sort(vel), vmin, vmax)
+    tops = np.sort(rng.uniform(20.0, 0.95 * nz, nlayers - 1))
+    dip = np.deg2rad(rng.uniform(20.0, 40.0))
+    throw = rng.uniform(20.0, 40.0)
+    xf = rng.uniform(0.3, 0.7) * nx
+    zz, xx = np.meshgrid(np.arange(nz, dtype=np.float64), np.arange(nx, dtype=np.float64), indexing="ij")
+    hanging = xx > xf + zz / np.tan(dip)
+    depth = np.where(hanging, zz - throw, zz)
+    v = np.full((nz, nx), vel[0])
+    for vk, tk in zip(vel[1:], tops):
+        v = np.where(depth >= tk, vk, v)
+    return v
+
+
+def cfg_batching(nshots: int = 128, nx: int = 1601, nz: int = 601, nt: int = 4000, seed: int = 2,
+                 dt: float = 0.8e-3, f: float = 10.0, margin: int = 50) -> Config:
+    """The uneven-aperture batching workload: 1601 x 601 grid, dx 10 m, layered
+    model with one normal fault, 1500-5000 m/s (seed 2); `nshots` shots at
+    depth cell 2, x evenly from 50 to nx - 51; each shot records on a
+    split spread of U{101..801} receivers at 1-cell spacing around its source
+    (clipped to the grid); its aperture is the receiver span plus `margin`
+    cells each side; 10 Hz Ricker, nt steps of 0.8 ms."""
+    rng = np.random.default_rng(seed)
+    v = layered_fault_model(nz, nx, seed).astype(np.float32)
+    xs = np.round(np.linspace(50, nx - 51, nshots)).astype(np.int32)
+    src = np.stack([xs, np.full(nshots, 2)], axis=1).astype(np.int32)
+    recs, win = [], []
+    for s in range(nshots):
+        n = int(rng.integers(101, 802))
+        lo = max(0, int(xs[s]) - n // 2)
+        hi = min(nx, lo + n)
+        lo = max(0, hi - n)
+        rx = np.arange(lo, hi)
+        recs.append(np.stack([rx, np.full(rx.size, 2)], axis=1))
+        win.append([max(0, lo - margin), min(nx, hi + margin)])
+    ptr, rr = _csr(recs)
+    cfg = Config(f"batching-{nx}x{nz}-{nshots}shots", 2, nz, nx, 1, 10.0, dt, nt, 20, f, 1e-2, 0, v, v.copy(),
+                 src, ptr, rr, ricker_samples(nt, dt, f))
+    cfg.window = np.asarray(win, dtype=np.int32)
+    return cfg

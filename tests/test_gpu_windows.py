@@ -1,0 +1,152 @@
+"""Shots of uneven aperture in one launch: each shot propagates on its own
+window (plus absorbing layer) of the grid; the GPU batch is compared with the
+FP64 oracle run on each shot's window model."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import core
+from paper_2211_06300_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def esi():
+    from paper_2211_06300_amd import esi as _esi
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    _esi.load_library()
+    return _esi
+
+
+def _rel(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _cfg(nt=60, seed=21):
+    """37 x 70 grid, nb 8 (ragged tiles), three shots with windows [0, 30),
+    [22, 70) and [5, 61), receivers inside each window (a corner, duplicates)."""
+    rng = np.random.default_rng(seed)
+    nz, nx = 37, 70
+    cfg = inputs.cfg_tiny(nz=nz, nx=nx, nt=nt, nb=8, nrec=5, seed=seed)
+    cfg.v_true = (1800.0 + 900.0 * rng.random((nz, nx))).astype(np.float32)
+    cfg.v_start = cfg.v_true
+    cfg.beta = 0.05
+    cfg.window = np.array([[0, 30], [22, 70], [5, 61]], dtype=np.int32)
+    cfg.src = np.array([[3, 2], [50, 20], [30, 36]], dtype=np.int32)
+    recs = [np.array([[0, 0], [29, 36], [10, 2], [10, 2], [11, 2]]),
+            np.stack([rng.integers(22, 70, 25), rng.integers(0, nz, 25)], axis=1),
+            np.stack([rng.integers(5, 61, 30), np.full(30, 1)], axis=1)]
+    cfg.rec_ptr = np.concatenate([[0], np.cumsum([len(r) for r in recs])]).astype(np.int64)
+    cfg.rec = np.concatenate(recs).astype(np.int32)
+    return cfg
+
+
+def _models(cfg):
+    g = core.Grid(2, cfg.nz, cfg.nx, nb=cfg.nb, nt=cfg.nt, dx=cfg.dx, dt=cfg.dt)
+    m = core.make_model(g, cfg.v_true)
+    return g, m, [core.window_model(m, int(x0), int(x1)) for x0, x1 in cfg.window]
+
+
+def _split(cfg, flat):
+    out, off = [], 0
+    for s in range(cfg.nshots):
+        n = int(cfg.rec_ptr[s + 1] - cfg.rec_ptr[s])
+        out.append(flat[off:off + cfg.nt * n].reshape(cfg.nt, n))
+        off += cfg.nt * n
+    return out
+
+
+def _local(cfg, s, pts):
+    return np.asarray(pts) - np.array([cfg.window[s][0], 0])
+
+
+@pytest.mark.parametrize("tb", [1, 2])
+def test_windowed_forward(esi, tb):
+    cfg = _cfg()
+    plan = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_true).to(DEV))
+    plan.set_time_block(tb)
+    g, m, mw = _models(cfg)
+    w = np.stack([cfg.wavelet, -cfg.wavelet, 0.5 * cfg.wavelet]).astype(np.float32)
+    d = plan.forward(torch.from_numpy(w).to(DEV), esi.SRC_POINT).cpu().numpy()
+    for s, ds in enumerate(_split(cfg, d)):
+        ref = core.forward(mw[s], w[s].astype(np.float64), _local(cfg, s, cfg.shot_rec(s)),
+                           src_pos=_local(cfg, s, cfg.src[s]))
+        assert _rel(ds, ref) < 1e-5, s
+    q = inputs.random_field((cfg.nshots, cfg.nt, cfg.nz, cfg.nx), 61)
+    d = plan.forward(torch.from_numpy(q).to(DEV), esi.SRC_DENSE).cpu().numpy()
+    for s, ds in enumerate(_split(cfg, d)):
+        x0, x1 = cfg.window[s]
+        ref = core.forward(mw[s], q[s][:, :, x0:x1].astype(np.float64), _local(cfg, s, cfg.shot_rec(s)))
+        assert _rel(ds, ref) < 1e-5, s
+    plan.close()
+
+
+def test_windowed_adjoint_normal(esi):
+    cfg = _cfg()
+    plan = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_true).to(DEV))
+    g, m, mw = _models(cfg)
+    dd = inputs.random_field(plan.data_shape(), 62)
+    out = plan.adjoint(torch.from_numpy(dd).to(DEV)).cpu().numpy()
+    for s, ds in enumerate(_split(cfg, dd)):
+        x0, x1 = cfg.window[s]
+        ref = core.adjoint(mw[s], _local(cfg, s, cfg.shot_rec(s)), ds.astype(np.float64))
+        assert _rel(out[s][:, :, x0:x1], ref) < 1e-5, s
+        assert not np.any(out[s][:, :, :x0]) and not np.any(out[s][:, :, x1:])
+    p = inputs.random_field((cfg.nshots, cfg.nt, cfg.nz, cfg.nx), 63)
+    Np, _ = plan.normal_apply(torch.from_numpy(p).to(DEV))
+    Np = Np.cpu().numpy()
+    for s in range(cfg.nshots):
+        x0, x1 = cfg.window[s]
+        w2 = core.annihilator_sq(mw[s].g, _local(cfg, s, cfg.src[s]))
+        ref = core.normal_apply(mw[s], _local(cfg, s, cfg.shot_rec(s)), w2, cfg.beta,
+                                p[s][:, :, x0:x1].astype(np.float64))
+        assert _rel(Np[s][:, :, x0:x1], ref) < 1e-5, s
+    plan.close()
+
+
+def test_windowed_gradient_ckpt(esi):
+    """SEED gradient (point sources, checkpoints every 9 steps) of the batch
+    against the sum of the oracle's window gradients placed in the grid."""
+    cfg = _cfg(nt=54)
+    plan = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_true).to(DEV))
+    g, m, mw = _models(cfg)
+    w = np.stack([cfg.wavelet] * 3).astype(np.float32)
+    G = inputs.random_field(plan.data_shape(), 64)
+    gm = plan.gradient(esi.GRAD_SEED, torch.from_numpy(w).to(DEV), torch.from_numpy(G).to(DEV),
+                       kind=esi.SRC_POINT, ckpt_every=9).cpu().numpy()
+    ref = np.zeros((cfg.nz, cfg.nx))
+    for s, Gs in enumerate(_split(cfg, G)):
+        x0, x1 = cfg.window[s]
+        gs, _ = core.gradient_seed(mw[s], w[s].astype(np.float64), _local(cfg, s, cfg.shot_rec(s)),
+                                   Gs.astype(np.float64), src_pos=_local(cfg, s, cfg.src[s]))
+        ref[:, x0:x1] += gs
+    assert _rel(gm, ref) < 1e-4
+    plan.close()
+
+
+def test_full_windows_equal_no_windows(esi):
+    """Windows that cover the grid give the same bits as a plan without them."""
+    cfg = _cfg()
+    w = torch.from_numpy(np.stack([cfg.wavelet] * 3)).to(DEV)
+    cfg.window[:] = [0, cfg.nx]
+    a = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_true).to(DEV))
+    da = a.forward(w, esi.SRC_POINT)
+    cfg.window = None
+    b = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_true).to(DEV))
+    db = b.forward(w, esi.SRC_POINT)
+    assert torch.equal(da, db)
+    a.close()
+    b.close()
+
+
+def test_window_validation(esi):
+    cfg = _cfg()
+    cfg.window[1] = [40, 70]          # its source at x = 50 is inside, receivers are not all
+    with pytest.raises(esi.EsiError):
+        esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_true).to(DEV))

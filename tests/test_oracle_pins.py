@@ -438,3 +438,30 @@ def test_esi_reduced_gradient_vs_fd():
         return core.misfit_esi(mo, qq, rec, d_obs, w2, beta)
     fd = (Jred(m0 + dm_s) - Jred(m0 - dm_s)) / 2.0
     assert abs(fd - core.dot(grad, dm_s)) / abs(fd) < 1e-6
+
+
+def test_window_model():
+    """A window covering the grid is the grid's own model; a narrower window
+    takes its columns (and the layer beyond it) from the padded model, with
+    a damping profile of its own width; a window's solution for a shot whose
+    wave stays inside it matches the whole grid's in the window's interior."""
+    from paper_2211_06300_amd import inputs
+    cfg = inputs.cfg_tiny(nz=20, nx=40, nt=30, nb=6, nrec=6)
+    g = core.Grid(2, cfg.nz, cfg.nx, nb=cfg.nb, nt=cfg.nt, dx=cfg.dx, dt=cfg.dt)
+    m = core.make_model(g, cfg.v_true)
+    full = core.window_model(m, 0, cfg.nx)
+    assert np.array_equal(full.c, m.c) and np.array_equal(full.kap, m.kap)
+    w = core.window_model(m, 10, 30)
+    assert w.g.nx == 20 and w.c.shape == (cfg.nz + 12, 32)
+    np.testing.assert_array_equal(w.c, m.c[:, 10:42])
+    np.testing.assert_array_equal(w.kap, core.damping(w.g, m.eta_max))
+    assert w.kap[10, 0] > 0 and w.kap[10, 6] == 0 and m.kap[10, 16] == 0
+    # a short record at the window centre: the wave has not reached the
+    # window's layer, so the two models give the same traces
+    src = np.array([20, 10])
+    rec = np.array([[18, 10], [22, 12]])
+    wav = cfg.wavelet.astype(np.float64)
+    d_full = core.forward(core.Model(m.g, m.v_phys, m.c, m.kap * 0, 0.0), wav, rec, src_pos=src)
+    d_win = core.forward(core.Model(w.g, w.v_phys, w.c, w.kap * 0, 0.0), wav, rec - [10, 0],
+                         src_pos=src - [10, 0])
+    np.testing.assert_allclose(d_win, d_full, rtol=1e-12, atol=1e-14)
