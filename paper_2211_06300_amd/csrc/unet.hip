@@ -32,6 +32,11 @@ typedef short s4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int NT = 256;
+#ifndef ESI_CONV_TAPG
+#define ESI_CONV_TAPG 3
+#endif
+constexpr int TG = ESI_CONV_TAPG;   // 3x3 taps whose operands are loaded together (1, 3 or 9)
+static_assert(9 % TG == 0, "tap groups must split the 9 taps");
 
 __device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float((uint32_t)h << 16); }
 // round to nearest even (finite inputs)
@@ -71,29 +76,36 @@ __global__ __launch_bounds__(NT) void k_conv3(const bf16_t* __restrict__ X, int 
 #pragma unroll
         for (int c = 0; c < CB; ++c) acc[p][c] = f4{0.f, 0.f, 0.f, 0.f};
     const bf16_t* Xn = X + (int64_t)n * H * W * sx;
-    for (int tap = 0; tap < 9; ++tap) {
-        const int yy = y + tap / 3 - 1;
-        const bool rowok = yy >= 0 && yy < H;
-        const int dx = tap % 3 - 1;
-        for (int ci = 0; ci < Cin; ci += 16) {
-            s4 b[4];
+    for (int ci = 0; ci < Cin; ci += 16) {
+        // the operands of TG taps first (TG x 4 pixel groups, TG x CB weight
+        // blocks), so their loads overlap; then the MFMAs
 #pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                const int xx = x0 + p * 16 + jl + dx;
-                if (rowok && xx >= 0 && xx < W)
-                    b[p] = *reinterpret_cast<const s4*>(Xn + ((int64_t)yy * W + xx) * sx + ci + kq);
-                else
-                    b[p] = s4{0, 0, 0, 0};
-            }
-            s4 a[CB];
+        for (int t0 = 0; t0 < 9; t0 += TG) {
+            s4 b[TG][4], a[TG][CB];
 #pragma unroll
-            for (int c = 0; c < CB; ++c)
-                a[c] = *reinterpret_cast<const s4*>(Wp + ((int64_t)tap * Cout + co0 + c * 16 + jl) * Cin + ci + kq);
+            for (int g = 0; g < TG; ++g) {
+                const int tap = t0 + g;
+                const int yy = y + tap / 3 - 1;
+                const bool rowok = yy >= 0 && yy < H;
+                const int dx = tap % 3 - 1;
 #pragma unroll
-            for (int p = 0; p < 4; ++p)
+                for (int p = 0; p < 4; ++p) {
+                    const int xx = x0 + p * 16 + jl + dx;
+                    b[g][p] = (rowok && xx >= 0 && xx < W)
+                                  ? *reinterpret_cast<const s4*>(Xn + ((int64_t)yy * W + xx) * sx + ci + kq)
+                                  : s4{0, 0, 0, 0};
+                }
 #pragma unroll
                 for (int c = 0; c < CB; ++c)
-                    acc[p][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[c], b[p], acc[p][c], 0, 0, 0);
+                    a[g][c] = *reinterpret_cast<const s4*>(Wp + ((int64_t)tap * Cout + co0 + c * 16 + jl) * Cin + ci + kq);
+            }
+#pragma unroll
+            for (int g = 0; g < TG; ++g)
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+#pragma unroll
+                    for (int c = 0; c < CB; ++c)
+                        acc[p][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[g][c], b[g][p], acc[p][c], 0, 0, 0);
         }
     }
     bf16_t* Yn = Y + (int64_t)n * H * W * sy;
