@@ -244,8 +244,8 @@ def main():
                     help="also run one elementwise copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(shots shard across GPUs by design, see DESIGN.md)"}))
+        print(json.dumps({"error": "bench.py runs on one GPU; --gpus must be 1 "
+                                   "(a multi-GPU run would give each GPU its own group of shots)"}))
         sys.exit(2)
 
     import torch
