@@ -217,12 +217,22 @@ esi_status_t do_forward(Plan* P, int shot0, int ns, int kind, const float* src, 
 // With cg_fuse the forward pass first forms p_new = r + beta p (p = p_old is
 // read, p_new written to `pnew`) and x += alpha p_old; N is applied to p_new.
 // Ap may be the p_old buffer (it is dead once the forward pass has run).
+//
+// With cg_s (flexible CG) the forward pass forms p = s r + beta p_old and
+// writes the per-shot p . r (FP64) to pr.
 esi_status_t do_normal(Plan* P, int shot0, int ns, const float* p, float* Ap, const TileLists* L,
                        const int* active, bool cg_fuse, float* pnew, const float* r, float* x,
-                       const double* alpha, const double* beta, const float* cg_s = nullptr) {
+                       const double* alpha, const double* beta, const float* cg_s = nullptr,
+                       double* pr = nullptr) {
+    if (cg_s && (!cg_fuse || !pr)) return fail(ESI_ERR_ARG, "internal: scaled direction needs p.r output");
     const int64_t dl = data_len(P, shot0, ns);
     ESI_TRY(grow_t(&P->dscr, &P->dscr_cap, std::max<int64_t>(dl, 1), P->stream));
     ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
+    TileLists *L2f, *L2a;
+    ESI_TRY(t2_lists(P, &L2f, false));
+    ESI_TRY(t2_lists(P, &L2a, true));
+    P->part_stride = std::max({L->tiles, L2f ? L2f->tiles : 0, L2a ? L2a->tiles : 0});
+    ESI_TRY(grow_t(&P->part, &P->part_cap, (int64_t)ns * P->part_stride, P->stream));
     StepArgs a = base_args(P, L, shot0, ns);
     a.active = active;
     a.gat_data = P->dscr;
@@ -230,7 +240,13 @@ esi_status_t do_normal(Plan* P, int shot0, int ns, const float* p, float* Ap, co
     if (cg_fuse) {
         a.cg_r = r; a.cg_p = p; a.cg_pn = pnew; a.cg_x = x; a.cg_alpha = alpha; a.cg_beta = beta;
         a.cg_s = cg_s;
+        if (cg_s) {
+            ESI_TRY(launch_fill_d(P, P->part, (int64_t)ns * P->part_stride));
+            a.part = P->part;
+            a.part_stride = P->part_stride;
+        }
         ESI_TRY(forward_loop(P, a, F_CG_FUSE | F_GATHER | (cg_s ? F_SCALE : 0u), P->ring, &cs, 0, P->nt));
+        if (cg_s) ESI_TRY(launch_reduce_parts(P, P->part, P->part_stride, ns, pr));
     } else {
         a.dsrc = p;
         ESI_TRY(forward_loop(P, a, F_SRC_DENSE | F_GATHER, P->ring, &cs, 0, P->nt));
@@ -238,10 +254,6 @@ esi_status_t do_normal(Plan* P, int shot0, int ns, const float* p, float* Ap, co
     ESI_TRY(launch_final_gather(P, P->ring + (int64_t)cs * P->fsize, RING * P->fsize, P->dscr,
                                 shot0, ns));
     ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
-    TileLists* L2;
-    ESI_TRY(t2_lists(P, &L2, true));
-    P->part_stride = std::max(L->tiles, L2 ? L2->tiles : 0);
-    ESI_TRY(grow_t(&P->part, &P->part_cap, (int64_t)ns * P->part_stride, P->stream));
     ESI_TRY(launch_fill_d(P, P->part, (int64_t)ns * P->part_stride));
     StepArgs b = base_args(P, L, shot0, ns);
     b.active = active;
@@ -559,6 +571,7 @@ extern "C" esi_status_t esi_fpcg_solve(esi_plan_t plan, int32_t shot0, int32_t n
     const int64_t cells = (int64_t)ns * P->nphys;
     ESI_TRY(grow_t(&P->fcg_s, &P->fcg_s_cap, cells, P->stream));
     ESI_TRY(grow_t(&P->fcg_a, &P->fcg_a_cap, cells, P->stream));
+    ESI_TRY(grow_t(&P->fcg_g, &P->fcg_g_cap, cells, P->stream));
     ESI_TRY(grow_t(&P->fcg_d, &P->fcg_d_cap, (int64_t)7 * ns, P->stream));
     ESI_TRY(grow_t(&P->fcg_i, &P->fcg_i_cap, (int64_t)5 * ns, P->stream));
     if (net) {
@@ -581,9 +594,11 @@ extern "C" esi_status_t esi_fpcg_solve(esi_plan_t plan, int32_t shot0, int32_t n
     const double stall = 0.99;
     const int window = 20;
 
-    // z = M(r) for the shots still iterating, k = the iteration count so far
+    double* rnp = P->fcg_g;                  // sum_t r Np per cell (FP64)
+
+    // z = M(r) for the shots still iterating, k = the iteration count so far;
+    // `en` holds sum_t r^2 per cell of the current r
     auto precondition = [&](int k) -> esi_status_t {
-        ESI_TRY(launch_energy(P, c.r, c.active, en, ns));
         if (net && (k == 0 || (net_every > 0 && k % net_every == 0))) {
             ESI_TRY(launch_features(P, shot0, ns, en, nullptr, fmean, Hp, Wp, nullptr, P->fcg_in, nullptr,
                                     nullptr));
@@ -616,6 +631,7 @@ extern "C" esi_status_t esi_fpcg_solve(esi_plan_t plan, int32_t shot0, int32_t n
         if (h_status[s] == ESI_ERR_NONFINITE) return fail(ESI_ERR_NONFINITE, "non-finite right-hand side");
 
     // p_0 = z_0 = M(r_0)
+    ESI_TRY(launch_energy(P, c.r, c.active, en, ns));
     ESI_TRY(precondition(0));
     ESI_TRY(launch_scale_vec(P, c.p, c.r, S, ns));
     float* p = c.p;
@@ -630,14 +646,15 @@ extern "C" esi_status_t esi_fpcg_solve(esi_plan_t plan, int32_t shot0, int32_t n
         if (k == 0) {
             ESI_TRY(do_normal(P, shot0, ns, p, Ap, c.L, c.active, false, nullptr, c.r, x, c.alpha, c.beta));
         } else {
-            ESI_TRY(do_normal(P, shot0, ns, p, p, c.L, c.active, true, Ap, c.r, x, c.alpha, c.beta, S));
+            ESI_TRY(do_normal(P, shot0, ns, p, p, c.L, c.active, true, Ap, c.r, x, c.alpha, c.beta, S, pr));
             dir = Ap;
             Apk = p;
         }
         ESI_TRY(launch_reduce_parts(P, P->part, P->part_stride, ns, c.pAp));
-        ESI_TRY(launch_dot(P, dir, c.r, ns, c.len, pr));
+        if (k == 0) ESI_TRY(launch_dot(P, dir, c.r, ns, c.len, pr));
         ESI_TRY(launch_cg_alpha(P, pr, c.pAp, c.alpha, ns));          // alpha = p.r / p.Np
-        ESI_TRY(launch_r_update(P, c.r, Apk, c.alpha, c.active, ns, c.len, c.rr_new));
+        // r -= alpha Np, with sum_t r^2 (network input, z.r) and sum_t r Np (z.Np) per cell
+        ESI_TRY(launch_r_update_cells(P, c.r, Apk, c.alpha, c.active, ns, en, rnp, c.rr_new));
         ESI_TRY(launch_fcg_control(P, c.rr0, c.rr_new, c.pAp, c.active, c.finish, c.iters, c.status, c.hist,
                                    max_iter + 1, c.ctl, rtol, max_iter, mode, restart, fallback, cg_at, stall,
                                    window, best, kbest, net != nullptr, ns));
@@ -652,7 +669,7 @@ extern "C" esi_status_t esi_fpcg_solve(esi_plan_t plan, int32_t shot0, int32_t n
         if (P->h_ctl[1] == 0 || k == max_iter - 1) break;
         // z_{k+1} = M(r_{k+1}); beta = -z.Np / p.Np (0 when the direction restarts)
         ESI_TRY(precondition(k + 1));
-        ESI_TRY(launch_dot_scaled(P, c.r, Apk, S, ns, zAp));
+        ESI_TRY(launch_dot_cells(P, S, rnp, ns, zAp));                // z.Np = sum_x s(x) sum_t r Np
         ESI_TRY(launch_fcg_beta(P, zAp, c.pAp, restart, c.beta, ns));
     }
     std::vector<int> h_fb(ns, -1), h_cg(ns, -1);

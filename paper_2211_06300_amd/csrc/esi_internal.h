@@ -131,10 +131,11 @@ struct Plan {
     float* vphys = nullptr;              // physical velocity [nphys] (network features)
     std::vector<int32_t> h_win;          // per-shot apertures [nshots][2] (empty: whole grid)
     int32_t* d_win = nullptr;
-    // flexible CG scratch: cell scale and energy [nshots][nphys], network input
-    // [nshots][3][Hp][Wp] and output [nshots][Hp][Wp], scalars
+    // flexible CG scratch: cell scale, sum_t r^2 and sum_t r Np [nshots][nphys],
+    // network input [nshots][3][Hp][Wp] and output [nshots][Hp][Wp], scalars
     float* fcg_s = nullptr; int64_t fcg_s_cap = 0;
     float* fcg_a = nullptr; int64_t fcg_a_cap = 0;
+    double* fcg_g = nullptr; int64_t fcg_g_cap = 0;
     float* fcg_in = nullptr; int64_t fcg_in_cap = 0;
     float* fcg_o = nullptr; int64_t fcg_o_cap = 0;
     double* fcg_d = nullptr; int64_t fcg_d_cap = 0;   // pr, zAp, zr[3], mean, best [7][nshots]
@@ -252,7 +253,8 @@ enum : unsigned {
     F_STORE = 1u << 8,       // store (dA/dm) u^n into store slot (forward)
     F_CORR = 1u << 9,        // gacc += mu^j * store slot (adjoint)
     F_SRC_REC = 1u << 10,    // src_rec[s][j] = mu^j at the shot's source cell (adjoint)
-    F_SCALE = 1u << 11,      // with F_CG_FUSE: the new direction is s r + beta p (flexible CG)
+    F_SCALE = 1u << 11,      // with F_CG_FUSE: the new direction is s r + beta p (flexible CG);
+                             // p_new . r accumulates into the (shot, tile) partials
 };
 
 // Gather of the last trace d^{nt-1} = R u^{nt} (after the time loop).
@@ -302,7 +304,12 @@ esi_status_t launch_fcg_zr_check_scale(Plan* P, const float* o, const float* fix
                                        double* best, int* kbest, const double* hist, int hstride, int k,
                                        int Hp, int Wp, double* zr, float* S, int ns);
 esi_status_t launch_scale_vec(Plan* P, float* p, const float* r, const float* S, int ns);
-esi_status_t launch_dot_scaled(Plan* P, const float* r, const float* y, const float* S, int ns, double* out);
+// r -= alpha Np for active shots; per cell en = sum_t r^2 and rnp = sum_t r Np of
+// the new r; rr_out[s] = sum of r^2 (all FP64 sums)
+esi_status_t launch_r_update_cells(Plan* P, float* r, const float* Np, const double* alpha, const int* active,
+                                   int ns, float* en, double* rnp, double* rr_out);
+// out[s] = sum_x S[s][x] g[s][x]
+esi_status_t launch_dot_cells(Plan* P, const float* S, const double* g, int ns, double* out);
 esi_status_t launch_fcg_beta(Plan* P, const double* zAp, const double* pAp, const int* restart, double* beta,
                              int ns);
 esi_status_t launch_fcg_init(Plan* P, int* mode, int* restart, int* fallback, int* cg_at, double* best, int* kbest,

@@ -13,6 +13,9 @@ constexpr int NT = 256;
 
 int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + NT - 1) / NT, 16384)); }
 
+// blocks per shot for reductions over the cells of one shot
+int cell_blocks(int64_t nphys) { return (int)std::max<int64_t>(1, std::min<int64_t>(64, (nphys + 4095) / 4096)); }
+
 __device__ __forceinline__ double block_sum_d(double v, double* sm) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -133,19 +136,19 @@ __device__ __forceinline__ float stage_scale(int st, const float* o, const float
 // zr[3 s + st] = sum_x scale_st(x) a(x) = z.r for each stage st.
 __global__ __launch_bounds__(NT) void k_fcg_zr(const float* __restrict__ o, const float* __restrict__ fixed,
                                                const float* __restrict__ a, int nz, int nx, int Hp, int Wp,
-                                               double* __restrict__ zr) {
+                                               double* __restrict__ part) {
     __shared__ double sm[NT / 64];
-    const int s = blockIdx.x;
+    const int s = blockIdx.y, b = blockIdx.x, bps = gridDim.x;
     const int64_t n = (int64_t)nz * nx;
     double acc[3] = {0.0, 0.0, 0.0};
-    for (int64_t x = threadIdx.x; x < n; x += NT) {
+    for (int64_t x = (int64_t)b * NT + threadIdx.x; x < n; x += (int64_t)bps * NT) {
         const int iz = (int)(x / nx), ix = (int)(x % nx);
         const double av = a[(int64_t)s * n + x];
         for (int st = 0; st < 3; ++st) acc[st] += (double)stage_scale(st, o, fixed, s, iz, ix, nz, nx, Hp, Wp) * av;
     }
     for (int st = 0; st < 3; ++st) {
         const double t = block_sum_d(acc[st], sm);
-        if (threadIdx.x == 0) zr[3 * s + st] = t;
+        if (threadIdx.x == 0) part[(int64_t)(3 * s + st) * bps + b] = t;
     }
 }
 
@@ -203,21 +206,68 @@ __global__ void k_scale_vec(float* __restrict__ p, const float* __restrict__ r, 
     }
 }
 
-// part[s][b] = sum over the block's chunk of (S r) . y
-__global__ __launch_bounds__(NT) void k_dot_scaled(const float* __restrict__ r, const float* __restrict__ y,
-                                                   const float* __restrict__ S, int64_t len, int64_t nphys,
-                                                   double* __restrict__ part) {
+// The residual update of a flexible CG iteration, one thread per cell walking
+// the time axis: r -= alpha Np, and per cell the FP64 sums over t of r^2 (for
+// z.r and the network's input) and of r Np (for z.Np, since z = s r with s
+// constant in time).  part[s][b] = block sums of r^2.
+__global__ __launch_bounds__(NT) void k_r_update_cells(float* __restrict__ r, const float* __restrict__ Np,
+                                                       const double* __restrict__ alpha,
+                                                       const int* __restrict__ active, int nt, int64_t nphys,
+                                                       float* __restrict__ en, double* __restrict__ rnp,
+                                                       double* __restrict__ part) {
     __shared__ double sm[NT / 64];
     const int s = blockIdx.y, b = blockIdx.x, bps = gridDim.x;
-    const int64_t chunk = (len + bps - 1) / bps;
-    const int64_t beg = (int64_t)b * chunk, end = min(len, beg + chunk);
-    const float* rs = r + (int64_t)s * len;
-    const float* ys = y + (int64_t)s * len;
-    const float* Ss = S + (int64_t)s * nphys;
+    if (active && !active[s]) {   // uniform over the block
+        if (threadIdx.x == 0) part[(int64_t)s * bps + b] = 0.0;
+        return;
+    }
+    const int64_t c = (int64_t)b * NT + threadIdx.x;
+    double e = 0.0, g = 0.0;
+    if (c < nphys) {
+        const float al = (float)alpha[s];
+        float* rs = r + (int64_t)s * nt * nphys + c;
+        const float* as = Np + (int64_t)s * nt * nphys + c;
+        constexpr int U = 8;
+        int t0 = 0;
+        for (; t0 + U <= nt; t0 += U) {
+            float rv[U], av[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                rv[j] = rs[(int64_t)(t0 + j) * nphys];
+                av[j] = as[(int64_t)(t0 + j) * nphys];
+            }
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const float v = fmaf(-al, av[j], rv[j]);
+                rs[(int64_t)(t0 + j) * nphys] = v;
+                e += (double)v * (double)v;
+                g += (double)v * (double)av[j];
+            }
+        }
+        for (; t0 < nt; ++t0) {
+            const float a = as[(int64_t)t0 * nphys];
+            const float v = fmaf(-al, a, rs[(int64_t)t0 * nphys]);
+            rs[(int64_t)t0 * nphys] = v;
+            e += (double)v * (double)v;
+            g += (double)v * (double)a;
+        }
+        en[(int64_t)s * nphys + c] = (float)e;
+        rnp[(int64_t)s * nphys + c] = g;
+    }
+    const double tot = block_sum_d(e, sm);
+    if (threadIdx.x == 0) part[(int64_t)s * bps + b] = tot;
+}
+
+// part[s][b] = block sums of S[s][x] g[s][x].
+__global__ __launch_bounds__(NT) void k_dot_cells(const float* __restrict__ S, const double* __restrict__ g,
+                                                  int64_t nphys, double* __restrict__ part) {
+    __shared__ double sm[NT / 64];
+    const int s = blockIdx.y, b = blockIdx.x, bps = gridDim.x;
     double acc = 0.0;
-    for (int64_t i = beg + threadIdx.x; i < end; i += NT) acc += (double)(rs[i] * Ss[i % nphys]) * (double)ys[i];
-    const double t = block_sum_d(acc, sm);
-    if (threadIdx.x == 0) part[(int64_t)s * bps + b] = t;
+    for (int64_t x = (int64_t)b * NT + threadIdx.x; x < nphys; x += (int64_t)bps * NT)
+        acc += (double)S[(int64_t)s * nphys + x] * g[(int64_t)s * nphys + x];
+    const double tot = block_sum_d(acc, sm);
+    if (threadIdx.x == 0) part[(int64_t)s * bps + b] = tot;
 }
 
 // beta = -z.Np / p.Np, or 0 when the direction restarts.
@@ -326,7 +376,10 @@ esi_status_t launch_fcg_zr_check_scale(Plan* P, const float* o, const float* fix
                                        const int* active, int* mode, int* restart, int* fallback, int* cg_at,
                                        double* best, int* kbest, const double* hist, int hstride, int k,
                                        int Hp, int Wp, double* zr, float* S, int ns) {
-    hipLaunchKernelGGL(k_fcg_zr, dim3(ns), dim3(NT), 0, P->stream, o, fixed, a, P->nz, P->nx, Hp, Wp, zr);
+    const int bps = cell_blocks(P->nphys);
+    ESI_TRY(grow_t(&P->part, &P->part_cap, (int64_t)3 * bps * ns, P->stream));
+    hipLaunchKernelGGL(k_fcg_zr, dim3(bps, ns), dim3(NT), 0, P->stream, o, fixed, a, P->nz, P->nx, Hp, Wp, P->part);
+    ESI_TRY(launch_reduce_parts(P, P->part, bps, 3 * ns, zr));      // zr[s][stage]
     hipLaunchKernelGGL(k_fcg_check, dim3((ns + 63) / 64), dim3(64), 0, P->stream, zr, active, mode, restart,
                        fallback, cg_at, best, kbest, hist, hstride, k, o ? 1 : 0, ns);
     hipLaunchKernelGGL(k_fcg_scale, dim3(grid_for((int64_t)ns * P->nphys)), dim3(NT), 0, P->stream, o, fixed,
@@ -342,11 +395,20 @@ esi_status_t launch_scale_vec(Plan* P, float* p, const float* r, const float* S,
     return ESI_OK;
 }
 
-esi_status_t launch_dot_scaled(Plan* P, const float* r, const float* y, const float* S, int ns, double* out) {
-    const int64_t len = (int64_t)P->nt * P->nphys;
-    const int bps = (int)std::max<int64_t>(1, std::min<int64_t>(512, (len + 4095) / 4096));
+esi_status_t launch_r_update_cells(Plan* P, float* r, const float* Np, const double* alpha, const int* active,
+                                   int ns, float* en, double* rnp, double* rr_out) {
+    const int bps = (int)((P->nphys + NT - 1) / NT);
     ESI_TRY(grow_t(&P->part, &P->part_cap, (int64_t)bps * ns, P->stream));
-    hipLaunchKernelGGL(k_dot_scaled, dim3(bps, ns), dim3(NT), 0, P->stream, r, y, S, len, P->nphys, P->part);
+    hipLaunchKernelGGL(k_r_update_cells, dim3(bps, ns), dim3(NT), 0, P->stream, r, Np, alpha, active, P->nt,
+                       P->nphys, en, rnp, P->part);
+    ESI_HIP_TRY(hipGetLastError());
+    return launch_reduce_parts(P, P->part, bps, ns, rr_out);
+}
+
+esi_status_t launch_dot_cells(Plan* P, const float* S, const double* g, int ns, double* out) {
+    const int bps = cell_blocks(P->nphys);
+    ESI_TRY(grow_t(&P->part, &P->part_cap, (int64_t)bps * ns, P->stream));
+    hipLaunchKernelGGL(k_dot_cells, dim3(bps, ns), dim3(NT), 0, P->stream, S, g, P->nphys, P->part);
     ESI_HIP_TRY(hipGetLastError());
     return launch_reduce_parts(P, P->part, bps, ns, out);
 }

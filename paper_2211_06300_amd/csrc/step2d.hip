@@ -246,6 +246,7 @@ __global__ __launch_bounds__(256, ESI_MINW) void k_step2d(const StepArgs a) {
 #pragma unroll
         for (int i = 0; i < RZ; ++i) qv[i] = ph[i] ? at(q, pi[i]) : 0.f;
     }
+    double pr_acc = 0.0;   // p_new . r partial (F_SCALE)
     if constexpr ((FL & F_CG_FUSE) != 0) {
         const float alp = (float)a.cg_alpha[s];
         const float bet = (float)a.cg_beta[s];
@@ -253,13 +254,13 @@ __global__ __launch_bounds__(256, ESI_MINW) void k_step2d(const StepArgs a) {
         float* __restrict__ pnew = a.cg_pn + vbase;
         const float* __restrict__ r = a.cg_r + vbase;
         float* __restrict__ xv = a.cg_x + vbase;
-        float po[RZ], rv[RZ], xo[RZ];
+        float po[RZ], rv[RZ], xo[RZ], rraw[RZ];
 #pragma unroll
         for (int i = 0; i < RZ; ++i) { po[i] = at(p, pi[i]); rv[i] = at(r, pi[i]); xo[i] = at(xv, pi[i]); }
         if constexpr ((FL & F_SCALE) != 0) {
             const float* __restrict__ sc = a.cg_s + (int64_t)s * a.nphys;
 #pragma unroll
-            for (int i = 0; i < RZ; ++i) rv[i] = rv[i] * at(sc, pi[i]);
+            for (int i = 0; i < RZ; ++i) { rraw[i] = rv[i]; rv[i] = rv[i] * at(sc, pi[i]); }
         }
 #pragma unroll
         for (int i = 0; i < RZ; ++i) {
@@ -267,6 +268,7 @@ __global__ __launch_bounds__(256, ESI_MINW) void k_step2d(const StepArgs a) {
             if (ph[i]) {
                 at(pnew, pi[i]) = pn;
                 if (alp != 0.f) at(xv, pi[i]) = fmaf(alp, po[i], xo[i]);
+                if constexpr ((FL & F_SCALE) != 0) pr_acc += (double)pn * (double)rraw[i];
             }
             qv[i] = ph[i] ? pn : 0.f;
         }
@@ -369,8 +371,8 @@ __global__ __launch_bounds__(256, ESI_MINW) void k_step2d(const StepArgs a) {
         cell_outputs<FL>(a, o1, pi[i], un, q, lq, c2v[i], pv[i], stv[i], wb, acc);
     }
 
-    if constexpr ((FL & F_NORMAL) != 0) {
-        acc = wave_sum(acc);
+    if constexpr ((FL & (F_NORMAL | F_SCALE)) != 0) {
+        acc = wave_sum(acc + pr_acc);
         if (lane == 0) sred[wv] = acc;
         __syncthreads();
         if (tid == 0) {
@@ -445,7 +447,7 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
     const bool xa_tile = lane >= HALO && lane < HALO + T2W;
     const int zra = wv * A_RZ;                            // first region row of this wave
     const uint32_t soA = (uint32_t)((z0 - HALO + zra + GH) * XS + xa + GH);
-    float cA[A_RZ], dA[A_RZ], kA[A_RZ], qA[A_RZ], pvA[A_RZ], stA[A_RZ], poA[A_RZ], xoA[A_RZ];
+    float cA[A_RZ], dA[A_RZ], kA[A_RZ], qA[A_RZ], pvA[A_RZ], stA[A_RZ], poA[A_RZ], xoA[A_RZ], rA[A_RZ];
     uint32_t piA[A_RZ];
     bool inA[A_RZ], phA[A_RZ];
 #pragma unroll
@@ -477,7 +479,7 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
         if constexpr ((FL & F_SCALE) != 0) {
             const float* __restrict__ sc = a.cg_s + (int64_t)s * a.nphys;
 #pragma unroll
-            for (int i = 0; i < A_RZ; ++i) qA[i] = qA[i] * at(sc, piA[i]);
+            for (int i = 0; i < A_RZ; ++i) { rA[i] = qA[i]; qA[i] = qA[i] * at(sc, piA[i]); }
         }
     }
     if constexpr ((FL & F_NORMAL) != 0) {
@@ -572,6 +574,7 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
                 if constexpr ((FL & F_CG_FUSE) != 0) {
                     at(a.cg_pn + vA, piA[i]) = q;
                     if (alp != 0.f) at(a.cg_x + vA, piA[i]) = fmaf(alp, poA[i], xoA[i]);
+                    if constexpr ((FL & F_SCALE) != 0) acc += (double)q * (double)rA[i];
                 }
                 if constexpr ((FL & F_SRC_REC) != 0) {
                     if (zr * A_W + lane == srcA) a.src_rec[(int64_t)s * a.nt + tA] = un;
@@ -618,7 +621,7 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
     const bool xwin = x >= ap.lo && x < ap.hi + 2 * a.nb;
     const int zb = z0 + wv * B_RZ;
     const uint32_t so0 = (uint32_t)((zb + GH) * XS + x + GH);
-    float c2v[B_RZ], kzv[B_RZ], qv[B_RZ], pvB[B_RZ], stB[B_RZ], poB[B_RZ], xoB[B_RZ];
+    float c2v[B_RZ], kzv[B_RZ], qv[B_RZ], pvB[B_RZ], stB[B_RZ], poB[B_RZ], xoB[B_RZ], rB[B_RZ];
     uint32_t pi[B_RZ];
     bool ph[B_RZ];
 #pragma unroll
@@ -645,7 +648,7 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
         if constexpr ((FL & F_SCALE) != 0) {
             const float* __restrict__ sc = a.cg_s + (int64_t)s * a.nphys;
 #pragma unroll
-            for (int i = 0; i < B_RZ; ++i) qv[i] = qv[i] * at(sc, pi[i]);
+            for (int i = 0; i < B_RZ; ++i) { rB[i] = qv[i]; qv[i] = qv[i] * at(sc, pi[i]); }
         }
     }
     if constexpr ((FL & F_NORMAL) != 0) {
@@ -688,6 +691,7 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
         if constexpr ((FL & F_CG_FUSE) != 0) {
             at(a.cg_pn + vB, pi[i]) = q;
             if (alp != 0.f) at(a.cg_x + vB, pi[i]) = fmaf(alp, poB[i], xoB[i]);
+            if constexpr ((FL & F_SCALE) != 0) acc += (double)q * (double)rB[i];
         }
         if constexpr ((FL & F_SRC_REC) != 0) {
             if (zl * T2W + lc == srcB) a.src_rec[(int64_t)s * a.nt + tB] = un;
@@ -697,7 +701,7 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
         cell_outputs<FL>(a, oB, pi[i], un, q, lq, c2v[i], pvB[i], stB[i], wb, acc);
     }
 
-    if constexpr ((FL & F_NORMAL) != 0) {
+    if constexpr ((FL & (F_NORMAL | F_SCALE)) != 0) {
         acc = wave_sum(acc);
         if (lane == 0) sred[wv] = acc;
         __syncthreads();
