@@ -513,3 +513,60 @@ def misfit_esi(m: Model, q: np.ndarray, rec, d_obs, w2: np.ndarray, beta: float)
     """J_ESI = 1/2 ||R u - d||^2 + beta/2 ||B q||^2 with u = A^{-1} q (eq. (esi))."""
     d = forward(m, q, rec)
     return 0.5 * dot(d - d_obs, d - d_obs) + 0.5 * beta * dot(w2[None] * q, q)
+
+
+# ---------------------------------------------------------------------------
+# WRI (Sec. 2.2: eq. (wridSf), eq. (normalwri), Table (compare), WRI row).
+# The extension q is added to the physical source f (u = A^{-1}(f + q)) and
+# penalised without a weight (B = I).
+# ---------------------------------------------------------------------------
+
+def with_point_source(g: Grid, q: np.ndarray, wavelet, src_pos) -> np.ndarray:
+    """The dense source f + q: the wavelet added at the source cell of q (the
+    point source of the forward modelling is that same dense source)."""
+    out = np.array(q, dtype=np.float64, copy=True)
+    sp = np.asarray(src_pos)
+    if g.ndim == 2:
+        out[:, sp[1], sp[0]] += wavelet
+    else:
+        out[:, sp[1], sp[2], sp[0]] += wavelet
+    return out
+
+
+def wri_rhs(m: Model, wavelet, src_pos, rec, d_obs) -> np.ndarray:
+    """Right-hand side S^T (d - S f) of eq. (normalwri)."""
+    d_f = forward(m, np.asarray(wavelet, np.float64), rec, src_pos=src_pos)
+    return adjoint(m, rec, d_obs - d_f)
+
+
+def wri_cg(m: Model, wavelet, src_pos, rec, d_obs, beta: float, max_iter: int,
+           rtol: float = 0.0) -> CGResult:
+    """Solve (S^T S + beta I) q = S^T (d - S f) (eq. (normalwri)) for one shot by
+    CG (Algorithm 1)."""
+    ones = np.ones(m.g.phys_shape)
+    b = wri_rhs(m, wavelet, src_pos, rec, d_obs)
+    return cg(lambda p: normal_apply(m, rec, ones, beta, p), b, max_iter, rtol)
+
+
+def misfit_wri(m: Model, wavelet, src_pos, q: np.ndarray, rec, d_obs, beta: float) -> float:
+    """J_WRI = 1/2 ||S (f + q) - d||^2 + beta/2 ||q||^2 (eq. (wridSf))."""
+    d = forward(m, with_point_source(m.g, q, wavelet, src_pos), rec)
+    return 0.5 * dot(d - d_obs, d - d_obs) + 0.5 * beta * dot(q, q)
+
+
+def gradient_wri_penalty(m: Model, wavelet, src_pos, q: np.ndarray, beta: float) -> np.ndarray:
+    """grad_m = sum_n lambda^n (dA/dm) u^n with lambda = beta q (the WRI adjoint
+    field of Table (compare) at the solution of eq. (normalwri)) and
+    u = A^{-1}(f + q).  m = 1/v^2."""
+    g = m.g
+    _, dtt = forward(m, with_point_source(g, q, wavelet, src_pos),
+                     np.zeros((0, g.ndim), dtype=np.int64), want_dtt=True)
+    return np.sum(beta * q * dtt, axis=0)
+
+
+def gradient_wri_adjoint(m: Model, wavelet, src_pos, q: np.ndarray, rec, d_obs) -> np.ndarray:
+    """grad_m = sum_n lambda^n (dA/dm) u^n with lambda = S^T (d - R u) and
+    u = A^{-1}(f + q): the gradient of J_WRI in m at fixed q.  m = 1/v^2."""
+    d_syn, dtt = forward(m, with_point_source(m.g, q, wavelet, src_pos), rec, want_dtt=True)
+    lam = adjoint(m, rec, d_obs - d_syn)
+    return np.sum(lam * dtt, axis=0)
