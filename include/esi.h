@@ -226,6 +226,47 @@ esi_status_t esi_forward_ckpt(esi_plan_t plan, int32_t shot0, int32_t nshots, in
                               const float* src, float* data, int32_t ckpt_every);
 
 /*
+ * Penalty weight of the plan (Sec. 2.2-2.3, Table compare):
+ *   ESI_WEIGHT_ANNIHILATOR (default): B = |x - x_s| / dx + b_eps, the ESI
+ *     annihilator (eq. esi);
+ *   ESI_WEIGHT_IDENTITY: B = I, the WRI penalty (eq. wridSf); the normal
+ *     operator becomes S^T S + beta I (eq. normalwri).
+ * It applies to every later call (normal operator, CG, PENALTY gradients).
+ * esi_fpcg_solve refuses identity-weight plans (its cell scales model the
+ * annihilator).  ESI_ERR_ARG for another kind.
+ */
+enum { ESI_WEIGHT_ANNIHILATOR = 0, ESI_WEIGHT_IDENTITY = 1 };
+esi_status_t esi_plan_set_weight(esi_plan_t plan, int32_t kind);
+
+/*
+ * Data residual of the physical source, the WRI right-hand side data
+ * (eq. wridSf / eq. normalwri):  d_res = d_obs - S f, with f = the point
+ * wavelets ([nshots][nt], device) at the shots' sources.  d_obs and d_res are
+ * device data arrays of the shots (layout as esi_forward's data; d_res may
+ * alias d_obs).  esi_cg_solve(d_res) then solves (S^T S + beta W) q =
+ * S^T (d - S f).
+ */
+esi_status_t esi_data_residual(esi_plan_t plan, int32_t shot0, int32_t nshots,
+                               const float* wavelet, const float* d_obs, float* d_res);
+
+/*
+ * WRI gradient with respect to m = 1/v^2 (Sec. 2.2, Table compare), summed
+ * over the shots and ADDED to grad_m (device [phys]):
+ *   g(x) = sum_n lambda^n(x) v(x)^2 (L u^n + P(f + q)^n)(x),  u = A^{-1}(f + q),
+ * with f the point wavelets ([nshots][nt], device) and q the dense extension
+ * ([nshots][nt][phys], device).
+ *   ESI_GRAD_PENALTY: lambda = beta W q (W = B^T B of the plan; I for WRI):
+ *                     one forward pass, no storage, d_obs unused.  Equal to
+ *                     ADJOINT when q solves the normal equation.
+ *   ESI_GRAD_ADJOINT: lambda = S^T (d_obs - S(f + q)): the gradient of
+ *                     J_WRI at fixed q.  ckpt_every as in esi_gradient.
+ * ESI_ERR_ARG for other modes or null pointers.
+ */
+esi_status_t esi_wri_gradient(esi_plan_t plan, int32_t shot0, int32_t nshots, int32_t mode,
+                              const float* wavelet, const float* q, const float* d_obs,
+                              float* grad_m, int32_t ckpt_every);
+
+/*
  * Chain rule from m = 1/v^2 to v: grad_v = -2 grad_m / v^3 on the physical
  * grid (device [phys] each; grad_v may alias grad_m).
  */

@@ -86,6 +86,7 @@ StepArgs base_args(Plan* P, const TileLists* L, int shot0, int nshots) {
     a.inv_dt2 = (float)(1.0 / (P->dt * P->dt));
     a.beta = (float)P->beta;
     a.b_eps = (float)P->b_eps;
+    a.w_identity = P->w_identity;
     a.nt = P->nt;
     a.dir = 1;
     a.nshots = nshots; a.shot0 = shot0;
@@ -365,7 +366,8 @@ std::vector<uintptr_t> cg_graph_key(Plan* P, const CgState& c) {
     return {(uintptr_t)c.shot0, (uintptr_t)c.ns, (uintptr_t)c.max_iter,
             (uintptr_t)std::llround(c.rtol * 1e18), (uintptr_t)c.L, (uintptr_t)c.x,
             (uintptr_t)c.r, (uintptr_t)c.hist, (uintptr_t)P->ring, (uintptr_t)P->dscr,
-            (uintptr_t)P->part, (uintptr_t)(P->tb_fwd * 4 + P->tb_adj), (uintptr_t)P->part_stride};
+            (uintptr_t)P->part, (uintptr_t)(P->tb_fwd * 4 + P->tb_adj), (uintptr_t)P->part_stride,
+            (uintptr_t)P->w_identity};
 }
 
 void cg_graph_drop(Plan* P) {
@@ -539,6 +541,7 @@ extern "C" esi_status_t esi_fpcg_solve(esi_plan_t plan, int32_t shot0, int32_t n
     Plan* P = (Plan*)plan;
     ESI_TRY(check_shots(P, shot0, ns));
     if (P->ndim != 2) return fail(ESI_ERR_ARG, "flexible CG runs on 2D plans");
+    if (P->w_identity) return fail(ESI_ERR_ARG, "flexible CG scales model the annihilator weight, not B = I");
     if (!x || !work || (!d_obs && data_len(P, shot0, ns) > 0)) return fail(ESI_ERR_ARG, "null pointer");
     if (max_iter < 1) return fail(ESI_ERR_ARG, "max_iter must be >= 1");
     if (!(rtol >= 0)) return fail(ESI_ERR_ARG, "rtol must be >= 0");
@@ -710,13 +713,15 @@ extern "C" esi_status_t esi_precond_features(esi_plan_t plan, int32_t shot0, int
     return launch_features(P, shot0, ns, a, cmap, P->fcg_d + 5 * ns, Hp, Wp, base, xin, apad, cpad);
 }
 
-extern "C" esi_status_t esi_gradient(esi_plan_t plan, int32_t shot0, int32_t ns, int32_t mode,
-                                     int32_t src_kind, const float* src, const float* data,
-                                     float* grad_m, float* grad_src, int32_t K) {
-    set_error("");
-    if (!plan) return fail(ESI_ERR_ARG, "null plan");
-    Plan* P = (Plan*)plan;
-    ESI_TRY(check_shots(P, shot0, ns));
+namespace esi {
+namespace {
+
+// The gradients of esi_gradient; bg (nullable, [nshots][nt]) adds the physical
+// point source f to the forward pass of the PENALTY and ADJOINT modes, so that
+// u = A^{-1}(f + q) (WRI).
+esi_status_t gradient_impl(Plan* P, int32_t shot0, int32_t ns, int32_t mode, int32_t src_kind,
+                           const float* src, const float* bg, const float* data, float* grad_m,
+                           float* grad_src, int32_t K) {
     if (mode != ESI_GRAD_PENALTY && mode != ESI_GRAD_ADJOINT && mode != ESI_GRAD_SEED &&
         mode != ESI_GRAD_SEED_REUSE)
         return fail(ESI_ERR_ARG, "bad gradient mode");
@@ -731,21 +736,24 @@ extern "C" esi_status_t esi_gradient(esi_plan_t plan, int32_t shot0, int32_t ns,
     if (!src || !grad_m) return fail(ESI_ERR_ARG, "null pointer");
     if (mode != ESI_GRAD_PENALTY && !data && data_len(P, shot0, ns) > 0) return fail(ESI_ERR_ARG, "null data");
     if (K < 0) return fail(ESI_ERR_ARG, "ckpt_every must be >= 0");
+    if (bg && mode != ESI_GRAD_PENALTY && mode != ESI_GRAD_ADJOINT)
+        return fail(ESI_ERR_ARG, "internal: a physical source applies to PENALTY and ADJOINT");
     TileLists* L;
     ESI_TRY(lists_for(P, &L));
     const int64_t nph = P->nphys;
     ESI_TRY(grow_t(&P->gshot, &P->gshot_cap, (int64_t)ns * nph, P->stream));
     ESI_TRY(launch_fill(P, P->gshot, (int64_t)ns * nph, 0.f));
-    const unsigned srcfl = src_kind == ESI_SRC_POINT ? F_SRC_POINT : F_SRC_DENSE;
+    const unsigned srcfl = (src_kind == ESI_SRC_POINT ? F_SRC_POINT : F_SRC_DENSE) | (bg ? F_SRC_POINT : 0u);
 
     if (mode == ESI_GRAD_PENALTY) {
-        // one forward pass of q correlating beta B^2 q with (dA/dm) u (Algorithm 2)
+        // one forward pass of q (plus f) correlating beta B^2 q with (dA/dm) u (Algorithm 2)
         ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
         StepArgs a = base_args(P, L, shot0, ns);
         a.dsrc = src;
+        a.wavelet = bg;
         a.gacc = P->gshot;
         int cs = 0;
-        ESI_TRY(forward_loop(P, a, F_SRC_DENSE | F_PENALTY, P->ring, &cs, 0, P->nt));
+        ESI_TRY(forward_loop(P, a, srcfl | F_PENALTY, P->ring, &cs, 0, P->nt));
         return launch_sum_shots(P, P->gshot, ns, nph, 1.f, grad_m);
     }
 
@@ -764,6 +772,7 @@ extern "C" esi_status_t esi_gradient(esi_plan_t plan, int32_t shot0, int32_t ns,
     ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
     StepArgs a = base_args(P, L, shot0, ns);
     if (src_kind == ESI_SRC_POINT) a.wavelet = src; else a.dsrc = src;
+    if (bg) a.wavelet = bg;
     a.store = P->store;
     a.store_stride = (int64_t)slots * nph;
     const float* G = data;
@@ -813,6 +822,58 @@ extern "C" esi_status_t esi_gradient(esi_plan_t plan, int32_t shot0, int32_t ns,
     }
     // ADJOINT: lambda = S^T (d_obs - S q) = -S^T G; SEED: grad_m = -sum S^T G (dA/dm) u
     return launch_sum_shots(P, P->gshot, ns, nph, -1.f, grad_m);
+}
+
+}  // namespace
+}  // namespace esi
+
+extern "C" esi_status_t esi_gradient(esi_plan_t plan, int32_t shot0, int32_t ns, int32_t mode,
+                                     int32_t src_kind, const float* src, const float* data,
+                                     float* grad_m, float* grad_src, int32_t K) {
+    set_error("");
+    if (!plan) return fail(ESI_ERR_ARG, "null plan");
+    Plan* P = (Plan*)plan;
+    ESI_TRY(check_shots(P, shot0, ns));
+    return gradient_impl(P, shot0, ns, mode, src_kind, src, nullptr, data, grad_m, grad_src, K);
+}
+
+extern "C" esi_status_t esi_wri_gradient(esi_plan_t plan, int32_t shot0, int32_t ns, int32_t mode,
+                                         const float* wavelet, const float* q, const float* d_obs,
+                                         float* grad_m, int32_t ckpt_every) {
+    set_error("");
+    if (!plan) return fail(ESI_ERR_ARG, "null plan");
+    Plan* P = (Plan*)plan;
+    ESI_TRY(check_shots(P, shot0, ns));
+    if (mode != ESI_GRAD_PENALTY && mode != ESI_GRAD_ADJOINT)
+        return fail(ESI_ERR_ARG, "WRI gradient modes are PENALTY and ADJOINT");
+    if (!wavelet) return fail(ESI_ERR_ARG, "null wavelet");
+    return gradient_impl(P, shot0, ns, mode, ESI_SRC_DENSE, q, wavelet, d_obs, grad_m, nullptr, ckpt_every);
+}
+
+extern "C" esi_status_t esi_data_residual(esi_plan_t plan, int32_t shot0, int32_t ns, const float* wavelet,
+                                          const float* d_obs, float* d_res) {
+    set_error("");
+    if (!plan) return fail(ESI_ERR_ARG, "null plan");
+    Plan* P = (Plan*)plan;
+    ESI_TRY(check_shots(P, shot0, ns));
+    const int64_t dl = data_len(P, shot0, ns);
+    if (!wavelet || (dl > 0 && (!d_obs || !d_res))) return fail(ESI_ERR_ARG, "null pointer");
+    TileLists* L;
+    ESI_TRY(lists_for(P, &L));
+    if (dl == 0) return ESI_OK;
+    // S f into plan scratch, so that d_res may alias d_obs
+    ESI_TRY(grow_t(&P->dscr2, &P->dscr2_cap, dl, P->stream));
+    ESI_TRY(do_forward(P, shot0, ns, ESI_SRC_POINT, wavelet, P->dscr2, L));
+    return launch_sub(P, d_res, d_obs, P->dscr2, dl);                         // d - S f
+}
+
+extern "C" esi_status_t esi_plan_set_weight(esi_plan_t plan, int32_t kind) {
+    set_error("");
+    if (!plan) return fail(ESI_ERR_ARG, "null plan");
+    if (kind != ESI_WEIGHT_ANNIHILATOR && kind != ESI_WEIGHT_IDENTITY) return fail(ESI_ERR_ARG, "bad weight kind");
+    Plan* P = (Plan*)plan;
+    P->w_identity = kind == ESI_WEIGHT_IDENTITY;
+    return ESI_OK;
 }
 
 extern "C" esi_status_t esi_plan_profile(esi_plan_t plan, int32_t enable) {

@@ -71,6 +71,7 @@ struct Plan {
     // grid
     int ndim = 2, nz = 0, nx = 0, ny = 1, nb = 0, nt = 0;
     double dx = 0, dt = 0, eta_max = 0, beta = 0, b_eps = 1;
+    int w_identity = 0;                  // penalty weight B = I (WRI) instead of the annihilator
     int nzp = 0, nyp = 1, nxp = 0;       // padded grid
     int ZS = 0, YS = 1, XS = 0;          // storage grid (padded + zero ghost halo)
     int64_t fsize = 0;                   // floats per stored field (one shot)
@@ -192,6 +193,7 @@ struct StepArgs {
     float inv_dt2;           // 1 / dt^2
     float beta;
     float b_eps;
+    int w_identity;          // 1: beta B^2 = beta (WRI); 0: B = distance to the source + b_eps
     int step;                // n (forward) or j (adjoint)
     int nt;
     int tiles_x, tiles_y, tiles_z, tiles;   // per shot

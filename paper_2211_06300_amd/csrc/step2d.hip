@@ -167,6 +167,7 @@ __device__ __forceinline__ void cell_outputs(const StepArgs& a, const StepPtrs& 
 }
 
 __device__ __forceinline__ float annih_w(const StepArgs& a, int ix, int iz, float sx, float sz) {
+    if (a.w_identity) return a.beta;   // uniform over the launch
     const float ddx = (float)ix - sx, ddz = (float)iz - sz;
     const float bb = sqrtf(ddx * ddx + ddz * ddz) + a.b_eps;
     return a.beta * (bb * bb);
@@ -348,6 +349,7 @@ __global__ __launch_bounds__(256, ESI_MINW) void k_step2d(const StepArgs a) {
         const float* cp = sh + (zl + HALO) * LW + xl + HALO;
         const float lap = lap_lds(a, cp, LW);
         float q = qv[i];
+        const float qd = q;   // the extended (dense) part of the source
         if constexpr ((FL & F_SRC_POINT) != 0) {
             if (zl * TX + xl == src_cell) q += src_val;
         }
@@ -368,7 +370,7 @@ __global__ __launch_bounds__(256, ESI_MINW) void k_step2d(const StepArgs a) {
         }
         float wb = 0.f;
         if constexpr ((FL & (F_NORMAL | F_PENALTY)) != 0) wb = annih_w(a, ix, z - a.nb, sx, sz);
-        cell_outputs<FL>(a, o1, pi[i], un, q, lq, c2v[i], pv[i], stv[i], wb, acc);
+        cell_outputs<FL>(a, o1, pi[i], un, qd, lq, c2v[i], pv[i], stv[i], wb, acc);
     }
 
     if constexpr ((FL & (F_NORMAL | F_SCALE)) != 0) {
@@ -557,6 +559,7 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
         const float lap = lap_lds(a, cp, U0W);
         float q = qA[i];
         if constexpr ((FL & F_CG_FUSE) != 0) q = phA[i] ? fmaf(bet, poA[i], qA[i]) : 0.f;
+        const float qd = q;   // the extended (dense) part of the source
         if constexpr ((FL & F_SRC_POINT) != 0) {
             if (zr * A_W + lane == srcA) q += a.wavelet[(int64_t)s * a.nt + tA];
         }
@@ -572,9 +575,9 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
             D1[(zr - HALO) * T2W + lane - HALO] = dn;
             if (phA[i]) {
                 if constexpr ((FL & F_CG_FUSE) != 0) {
-                    at(a.cg_pn + vA, piA[i]) = q;
+                    at(a.cg_pn + vA, piA[i]) = qd;
                     if (alp != 0.f) at(a.cg_x + vA, piA[i]) = fmaf(alp, poA[i], xoA[i]);
-                    if constexpr ((FL & F_SCALE) != 0) acc += (double)q * (double)rA[i];
+                    if constexpr ((FL & F_SCALE) != 0) acc += (double)qd * (double)rA[i];
                 }
                 if constexpr ((FL & F_SRC_REC) != 0) {
                     if (zr * A_W + lane == srcA) a.src_rec[(int64_t)s * a.nt + tA] = un;
@@ -582,7 +585,7 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
                 float wb = 0.f;
                 if constexpr ((FL & (F_NORMAL | F_PENALTY)) != 0)
                     wb = annih_w(a, ixa, z0 - HALO + zr - a.nb, sx, sz);
-                cell_outputs<FL>(a, oA, piA[i], un, q, lq, cA[i], pvA[i], stA[i], wb, acc);
+                cell_outputs<FL>(a, oA, piA[i], un, qd, lq, cA[i], pvA[i], stA[i], wb, acc);
             }
         }
     }
@@ -672,6 +675,7 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
         const float lap = lap_lds(a, cp, A_W);
         float q = qv[i];
         if constexpr ((FL & F_CG_FUSE) != 0) q = ph[i] ? fmaf(bet, poB[i], qv[i]) : 0.f;
+        const float qd = q;   // the extended (dense) part of the source
         if constexpr ((FL & F_SRC_POINT) != 0) {
             if (lane_on && zl * T2W + lc == srcB) q += a.wavelet[(int64_t)s * a.nt + tB];
         }
@@ -689,16 +693,16 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
         }
         if (!ph[i]) continue;
         if constexpr ((FL & F_CG_FUSE) != 0) {
-            at(a.cg_pn + vB, pi[i]) = q;
+            at(a.cg_pn + vB, pi[i]) = qd;
             if (alp != 0.f) at(a.cg_x + vB, pi[i]) = fmaf(alp, poB[i], xoB[i]);
-            if constexpr ((FL & F_SCALE) != 0) acc += (double)q * (double)rB[i];
+            if constexpr ((FL & F_SCALE) != 0) acc += (double)qd * (double)rB[i];
         }
         if constexpr ((FL & F_SRC_REC) != 0) {
             if (zl * T2W + lc == srcB) a.src_rec[(int64_t)s * a.nt + tB] = un;
         }
         float wb = 0.f;
         if constexpr ((FL & (F_NORMAL | F_PENALTY)) != 0) wb = annih_w(a, ix, z - a.nb, sx, sz);
-        cell_outputs<FL>(a, oB, pi[i], un, q, lq, c2v[i], pvB[i], stB[i], wb, acc);
+        cell_outputs<FL>(a, oB, pi[i], un, qd, lq, c2v[i], pvB[i], stB[i], wb, acc);
     }
 
     if constexpr ((FL & (F_NORMAL | F_SCALE)) != 0) {
@@ -759,6 +763,10 @@ esi_status_t dispatch2d(Plan* P, unsigned flags, const StepArgs& a) {
         ESI_CASE(F_SRC_DENSE | F_STORE)
         ESI_CASE(F_SRC_DENSE)
         ESI_CASE(F_SRC_DENSE | F_PENALTY)
+        ESI_CASE(F_SRC_POINT | F_SRC_DENSE | F_PENALTY)
+        ESI_CASE(F_SRC_POINT | F_SRC_DENSE | F_GATHER)
+        ESI_CASE(F_SRC_POINT | F_SRC_DENSE | F_GATHER | F_STORE)
+        ESI_CASE(F_SRC_POINT | F_SRC_DENSE | F_STORE)
         ESI_CASE(F_CG_FUSE | F_GATHER)
         ESI_CASE(F_CG_FUSE | F_GATHER | F_SCALE)
         ESI_CASE(F_INJ | F_OUT)

@@ -210,6 +210,7 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
         lz_ = fmaf(a.w4, (w[0] - cv) + (w[8] - cv), lz_);
         const float lap = (lx_ + ly_) + lz_;
         const int cell = lz * TX * TY + ly * TX + lx;
+        const float qd = q;   // the extended (dense) part of the source
         if constexpr ((FL & F_SRC_POINT) != 0) {
             if (cell == src_cell) q += src_val;
         }
@@ -233,16 +234,20 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
             }
             float wb = 0.f;
             if constexpr ((FL & (F_NORMAL | F_PENALTY)) != 0) {
-                const float ddx = (float)ix - sx, ddy = (float)iy - sy, ddz = (float)iz - sz;
-                const float bb = sqrtf(ddx * ddx + ddy * ddy + ddz * ddz) + a.b_eps;
-                wb = a.beta * (bb * bb);
+                if (a.w_identity) {
+                    wb = a.beta;
+                } else {
+                    const float ddx = (float)ix - sx, ddy = (float)iy - sy, ddz = (float)iz - sz;
+                    const float bb = sqrtf(ddx * ddx + ddy * ddy + ddz * ddz) + a.b_eps;
+                    wb = a.beta * (bb * bb);
+                }
             }
             if constexpr ((FL & F_NORMAL) != 0) {
                 const float np = fmaf(wb, pv, un);
                 at(dout, pi) = np;
                 acc += (double)pv * (double)np;
             }
-            if constexpr ((FL & F_PENALTY) != 0) at(gacc, pi) = fmaf(wb * q, c2v * a.inv_dt2 * lq, at(gacc, pi));
+            if constexpr ((FL & F_PENALTY) != 0) at(gacc, pi) = fmaf(wb * qd, c2v * a.inv_dt2 * lq, at(gacc, pi));
             if constexpr ((FL & F_STORE) != 0) at(store, pi) = c2v * a.inv_dt2 * lq;
             if constexpr ((FL & F_CORR) != 0) at(gacc, pi) = fmaf(un, stv, at(gacc, pi));
         }
@@ -285,6 +290,10 @@ esi_status_t launch_step3d(Plan* P, unsigned flags, const StepArgs& a) {
         ESI_CASE(F_SRC_DENSE | F_STORE)
         ESI_CASE(F_SRC_DENSE)
         ESI_CASE(F_SRC_DENSE | F_PENALTY)
+        ESI_CASE(F_SRC_POINT | F_SRC_DENSE | F_PENALTY)
+        ESI_CASE(F_SRC_POINT | F_SRC_DENSE | F_GATHER)
+        ESI_CASE(F_SRC_POINT | F_SRC_DENSE | F_GATHER | F_STORE)
+        ESI_CASE(F_SRC_POINT | F_SRC_DENSE | F_STORE)
         ESI_CASE(F_CG_FUSE | F_GATHER)
         ESI_CASE(F_INJ | F_OUT)
         ESI_CASE(F_INJ | F_NORMAL)

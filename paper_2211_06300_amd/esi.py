@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libesi.so")
 
 SRC_POINT, SRC_DENSE = 0, 1
 GRAD_PENALTY, GRAD_ADJOINT, GRAD_SEED, GRAD_SEED_REUSE = 0, 1, 2, 3
+WEIGHT_ANNIHILATOR, WEIGHT_IDENTITY = 0, 1
 _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_SHAPE", 3: "ERR_CFL", 4: "ERR_OOM", 5: "ERR_HIP",
            6: "ERR_BREAKDOWN", 7: "ERR_NONFINITE"}
 
@@ -55,7 +56,8 @@ EXPORTS = ["esi_plan_create", "esi_plan_set_model", "esi_plan_destroy", "esi_las
            "esi_forward_ckpt", "esi_grad_velocity", "esi_plan_set_cg_graph",
            "esi_unet_num_params", "esi_unet_create", "esi_unet_destroy", "esi_unet_set_params",
            "esi_unet_get_params", "esi_unet_forward", "esi_unet_loss_grad", "esi_unet_adam",
-           "esi_fpcg_solve", "esi_precond_features", "esi_unet_loss_weights", "esi_plan_autotune"]
+           "esi_fpcg_solve", "esi_precond_features", "esi_unet_loss_weights", "esi_plan_autotune",
+           "esi_plan_set_weight", "esi_data_residual", "esi_wri_gradient"]
 # time-step kernel variants (bit set of fused work), as in include/esi.h
 K_FLAGS = {1: "SRC_POINT", 2: "SRC_DENSE", 4: "CG_FUSE", 8: "INJ", 16: "GATHER", 32: "OUT",
            64: "NORMAL", 128: "PENALTY", 256: "STORE", 512: "CORR", 1024: "SRC_REC",
@@ -82,6 +84,9 @@ def load_library(path: str = LIB_PATH):
     L.esi_normal_apply.argtypes = [vp, i32, i32, vp, vp, vp]
     L.esi_cg_solve.argtypes = [vp, i32, i32, vp, vp, vp, i32, dbl, ctypes.POINTER(_CgReport)]
     L.esi_gradient.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp, vp, i32]
+    L.esi_plan_set_weight.argtypes = [vp, i32]
+    L.esi_data_residual.argtypes = [vp, i32, i32, vp, vp, vp]
+    L.esi_wri_gradient.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, i32]
     L.esi_plan_profile.argtypes = [vp, i32]
     L.esi_plan_set_time_block.argtypes = [vp, i32]
     L.esi_plan_set_cg_graph.argtypes = [vp, i32]
@@ -219,6 +224,31 @@ class Plan:
                                            _f32(Ap, self.vec_shape(nshots), "Ap"), int(bool(force)),
                                            ch.ctypes.data_as(ctypes.c_void_p)))
         return int(ch[0]), int(ch[1])
+
+    def set_weight(self, kind: int):
+        """esi_plan_set_weight: WEIGHT_ANNIHILATOR (ESI) or WEIGHT_IDENTITY (WRI, B = I)."""
+        _check(self._lib.esi_plan_set_weight(self._h, int(kind)))
+
+    def data_residual(self, wavelet, d_obs, shot0=0, nshots=None, out=None):
+        """d_obs - S f for point wavelets f [nshots][nt] (the WRI right-hand side data)."""
+        shot0, nshots = self._range(shot0, nshots)
+        dshape = self.data_shape(shot0, nshots)
+        out = self.new_data(shot0, nshots) if out is None else out
+        _check(self._lib.esi_data_residual(self._h, shot0, nshots, _f32(wavelet, (nshots, self.nt), "wavelet"),
+                                           _f32(d_obs, dshape, "d_obs"), _f32(out, dshape, "d_res")))
+        return out
+
+    def wri_gradient(self, mode, wavelet, q, d_obs=None, shot0=0, nshots=None, grad_m=None, ckpt_every=0):
+        """esi_wri_gradient: gradient in m with u = A^{-1}(f + q), added to grad_m."""
+        shot0, nshots = self._range(shot0, nshots)
+        grad_m = torch.zeros(self.phys_shape, dtype=torch.float32, device=self.device) \
+            if grad_m is None else grad_m
+        dptr = None if d_obs is None else _f32(d_obs, self.data_shape(shot0, nshots), "d_obs")
+        _check(self._lib.esi_wri_gradient(self._h, shot0, nshots, int(mode),
+                                          _f32(wavelet, (nshots, self.nt), "wavelet"),
+                                          _f32(q, self.vec_shape(nshots), "q"), dptr,
+                                          _f32(grad_m, self.phys_shape, "grad_m"), int(ckpt_every)))
+        return grad_m
 
     def set_cg_graph(self, enable: bool):
         _check(self._lib.esi_plan_set_cg_graph(self._h, int(bool(enable))))
