@@ -222,6 +222,58 @@ def batching_run(args, torch, dev):
             "dominant_loop": {"variant": name, "launches": rec["launches"], "ms": round(rec["ms"], 1)}}
 
 
+def wri_run(args, torch, dev):
+    """The WRI variant on the single-solve workload: per group of shots the data
+    residual d - S f, the right-hand side S^T (d - S f), CG on
+    (S^T S + beta I) q and the PENALTY gradient with u = A^{-1}(f + q)
+    (2 + 2 * cg_iters + 1 propagations per shot)."""
+    from paper_2211_06300_amd import esi, inputs
+    cfg = inputs.cfg_single_solve(nshots=args.shots, nt=args.nt)
+    npad = (cfg.nz + 2 * cfg.nb) * (cfg.nx + 2 * cfg.nb)
+    G = min(args.group, cfg.nshots)
+    groups = [(s, min(G, cfg.nshots - s)) for s in range(0, cfg.nshots, G)]
+    plan_true = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_true).to(dev))
+    wav = torch.from_numpy(np.tile(cfg.wavelet, (cfg.nshots, 1))).to(dev)
+    d_obs = plan_true.forward(wav, esi.SRC_POINT)
+    plan_true.close()
+    plan = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_start).to(dev))
+    plan.set_weight(esi.WEIGHT_IDENTITY)
+    x = plan.new_vec(G)
+    work = torch.empty((3, *plan.vec_shape(G)), dtype=torch.float32, device=dev)
+    grad = torch.zeros(plan.phys_shape, dtype=torch.float32, device=dev)
+    offs = [int(cfg.nt * cfg.rec_ptr[s]) for s in range(cfg.nshots + 1)]
+    plan.autotune(nshots=G, p=work[0], Ap=work[1])
+    hists = {}
+
+    def one(iters):
+        grad.zero_()
+        for s0, ns in groups:
+            d_res = plan.data_residual(wav[s0:s0 + ns], d_obs[offs[s0]:offs[s0 + ns]], shot0=s0, nshots=ns)
+            xs, ws = x[:ns], work[:, :ns]
+            _, rep = plan.cg_solve(d_res, iters, 0.0, shot0=s0, nshots=ns, x=xs, work=ws)
+            plan.wri_gradient(esi.GRAD_PENALTY, wav[s0:s0 + ns], xs, shot0=s0, nshots=ns, grad_m=grad)
+            hists[s0] = rep["res_hist"]
+
+    one(2)                                            # warm-up: every kernel once
+    torch.cuda.synchronize()
+    plan.profile(True)
+    t0 = time.perf_counter()
+    one(args.cg_iters)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = plan.profile_read()
+    plan.profile(False)
+    plan.close()
+    props = 2 + 2 * args.cg_iters + 1
+    name, rec = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    hist = np.concatenate(list(hists.values()))
+    return {"workload": "wri-" + cfg.name, "shots": cfg.nshots, "shot_group": G, "nt": cfg.nt,
+            "cg_iters": args.cg_iters, "beta": cfg.beta, "propagations_per_shot": props,
+            "seconds": round(wall, 3), "gpts_per_s": round(cfg.nshots * props * npad * cfg.nt / wall / 1e9, 2),
+            "cg_final_rel_residual_max": float(np.max(hist[:, -1])),
+            "dominant_loop": {"variant": name, "launches": rec["launches"], "ms": round(rec["ms"], 1)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,6 +292,7 @@ def main():
     ap.add_argument("--no-batching", action="store_true", help="skip the uneven-aperture batching run")
     ap.add_argument("--batch-shots", type=int, default=128)
     ap.add_argument("--batch-nt", type=int, default=4000)
+    ap.add_argument("--no-wri", action="store_true", help="skip the WRI run on the single-solve workload")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="also run one elementwise copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -365,6 +418,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_batching:
         out["batching"] = batching_run(args, torch, dev)
+        torch.cuda.empty_cache()
+    if not args.no_wri:
+        out["wri"] = wri_run(args, torch, dev)
         torch.cuda.empty_cache()
     if not args.no_cpu:
         log("timing the oracle on the host cores")
