@@ -267,6 +267,77 @@ esi_status_t esi_wri_gradient(esi_plan_t plan, int32_t shot0, int32_t nshots, in
                               float* grad_m, int32_t ckpt_every);
 
 /*
+ * Penalty parameter beta of the plan (Sec. 2.4): used by every later call.
+ * ESI_ERR_ARG unless finite and >= 0.
+ */
+esi_status_t esi_plan_set_beta(esi_plan_t plan, double beta);
+
+/*
+ * The outer loop of Algorithm 2 (nested loops for variable projection between
+ * m = 1/v^2 and q), run by the library:
+ *   per outer iteration: the inner loop (CG on the normal equation, Algorithm 1,
+ *   cg_iters iterations or cg_rtol) for every shot; the PENALTY gradient
+ *   (lambda = beta W q, u = A^{-1} q); a direction -H g with H the L-BFGS
+ *   inverse-Hessian approximation (two-loop recursion, lbfgs_mem pairs, a pair
+ *   kept when s'y > 0); a backtracking line search (step halved at most ls_max
+ *   times) with the Armijo condition J(m_t) <= J(m) + c1 g'(m_t - m) on the
+ *   model clipped to [v_min, v_max].  Without curvature pairs the first trial
+ *   is -g scaled to max |dm| = first_step * max m.
+ *   J(m) = sum over shots of 1/2 ||S q - d||^2 + beta/2 ||B q||^2 for the inner
+ *   loop's q (eq. esi).  With wavelet != NULL (WRI, Sec. 2.2; set the plan's
+ *   weight to ESI_WEIGHT_IDENTITY) the inner loop solves for q with
+ *   right-hand side S^T(d - S f), u = A^{-1}(f + q) and
+ *   J = 1/2 ||S(f + q) - d||^2 + beta/2 ||q||^2 (eq. wridSf).
+ *   beta_rule ESI_BETA_DISCREPANCY (Sec. 2.4, Sec. 4.3): before each outer
+ *   iteration, while the relative data misfit ||S q - d|| / ||d|| is below
+ *   misfit_lo beta is multiplied by beta_factor, while above misfit_hi it is
+ *   divided by it (at most beta_tries changes; each re-solves and clears the
+ *   L-BFGS memory).  ESI_BETA_FIXED keeps the plan's beta.
+ * d_obs: device data of the shots (layout of esi_forward); wavelet: device
+ * [nshots][nt] or NULL; vel: device [phys], the starting model on entry and
+ * the last accepted model on return (the plan is left at that model and at
+ * the final beta); grad_mask: device [phys] multiplying the gradient, or NULL;
+ * x: device [shot_group][nt][phys] and work: device [3][shot_group][nt][phys],
+ * the inner solves' vectors (shots are solved shot_group at a time).  The
+ * library allocates its FP64 model-space vectors (2 lbfgs_mem + 6 of [phys])
+ * per call.
+ * rep (optional) receives the counts and, through its non-NULL host arrays,
+ * the histories.  Returns ESI_ERR_ARG for bad options; a failed line search is
+ * not an error (rep->status = 1, vel = the last accepted model).
+ */
+enum { ESI_BETA_FIXED = 0, ESI_BETA_DISCREPANCY = 1 };
+typedef struct {
+    int32_t outer_iters;   /* N_outer >= 0 */
+    int32_t cg_iters;      /* inner CG iterations >= 1 */
+    double cg_rtol;        /* inner stopping tolerance (0: run cg_iters) */
+    int32_t shot_group;    /* shots per inner solve, 1..nshots */
+    int32_t lbfgs_mem;     /* >= 1 */
+    int32_t ls_max;        /* line-search trials >= 1 */
+    double armijo_c1;      /* in (0, 1) */
+    double first_step;     /* > 0 */
+    double v_min, v_max;   /* 0 < v_min < v_max (m/s); v_max must meet the CFL limit */
+    int32_t beta_rule;     /* ESI_BETA_FIXED or ESI_BETA_DISCREPANCY */
+    double misfit_lo, misfit_hi;   /* discrepancy band, 0 <= lo <= hi */
+    double beta_factor;    /* > 1 */
+    int32_t beta_tries;    /* >= 0 */
+} esi_invert_opts_t;
+typedef struct {
+    int32_t outer_done;    /* accepted outer iterations */
+    int32_t evals;         /* objective evaluations */
+    int32_t status;        /* 0: ran outer_iters iterations, 1: a line search failed */
+    double beta_final;
+    double* J;             /* host [outer_iters + 1] or NULL: J at the accepted models */
+    double* misfit;        /* host [outer_iters + 1] or NULL: relative data misfit there */
+    double* beta;          /* host [outer_iters + 1] or NULL: beta of each J */
+    double* beta_iter;     /* host [outer_iters] or NULL: beta of each outer iteration */
+    double* step;          /* host [outer_iters] or NULL: accepted step lengths */
+    int32_t* trials;       /* host [outer_iters] or NULL: line-search trials */
+} esi_invert_report_t;
+esi_status_t esi_invert(esi_plan_t plan, int32_t shot0, int32_t nshots, const float* d_obs,
+                        const float* wavelet, float* vel, const float* grad_mask, float* x,
+                        float* work, const esi_invert_opts_t* opts, esi_invert_report_t* rep);
+
+/*
  * Chain rule from m = 1/v^2 to v: grad_v = -2 grad_m / v^3 on the physical
  * grid (device [phys] each; grad_v may alias grad_m).
  */

@@ -361,13 +361,19 @@ esi_status_t cg_iteration(Plan* P, const CgState& c, int k, const float* p, floa
     return launch_axpy_flag(P, c.x, dir, c.alpha, c.finish, 1, c.ns, c.len);
 }
 
+uintptr_t beta_bits(double b) {
+    uint64_t u;
+    std::memcpy(&u, &b, sizeof u);
+    return (uintptr_t)u;
+}
+
 // Everything a captured iteration depends on besides its parity.
 std::vector<uintptr_t> cg_graph_key(Plan* P, const CgState& c) {
     return {(uintptr_t)c.shot0, (uintptr_t)c.ns, (uintptr_t)c.max_iter,
             (uintptr_t)std::llround(c.rtol * 1e18), (uintptr_t)c.L, (uintptr_t)c.x,
             (uintptr_t)c.r, (uintptr_t)c.hist, (uintptr_t)P->ring, (uintptr_t)P->dscr,
             (uintptr_t)P->part, (uintptr_t)(P->tb_fwd * 4 + P->tb_adj), (uintptr_t)P->part_stride,
-            (uintptr_t)P->w_identity};
+            (uintptr_t)P->w_identity, beta_bits(P->beta)};
 }
 
 void cg_graph_drop(Plan* P) {
@@ -825,6 +831,34 @@ esi_status_t gradient_impl(Plan* P, int32_t shot0, int32_t ns, int32_t mode, int
 }
 
 }  // namespace
+
+// One forward pass of q (plus the point wavelets bg, when given) that adds each
+// shot's PENALTY gradient (lambda = beta W q) to gshot [ns][phys], records
+// S q (or S(f + q)) into dsyn and writes the per-shot penalty sum of
+// beta W q^2 to pen (device, FP64 [ns]).
+esi_status_t penalty_eval(Plan* P, int shot0, int ns, const float* q, const float* bg, float* gshot,
+                          float* dsyn, double* pen) {
+    TileLists *L, *L2f;
+    ESI_TRY(lists_for(P, &L));
+    ESI_TRY(t2_lists(P, &L2f, false));
+    P->part_stride = std::max(L->tiles, L2f ? L2f->tiles : 0);
+    ESI_TRY(grow_t(&P->part, &P->part_cap, (int64_t)ns * P->part_stride, P->stream));
+    ESI_TRY(launch_fill_d(P, P->part, (int64_t)ns * P->part_stride));
+    ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
+    StepArgs a = base_args(P, L, shot0, ns);
+    a.dsrc = q;
+    a.wavelet = bg;
+    a.gacc = gshot;
+    a.gat_data = dsyn;
+    a.part = P->part;
+    a.part_stride = P->part_stride;
+    int cs = 0;
+    ESI_TRY(forward_loop(P, a, F_SRC_DENSE | F_PENALTY | F_GATHER | (bg ? F_SRC_POINT : 0u), P->ring, &cs, 0,
+                         P->nt));
+    ESI_TRY(launch_final_gather(P, P->ring + (int64_t)cs * P->fsize, RING * P->fsize, dsyn, shot0, ns));
+    return launch_reduce_parts(P, P->part, P->part_stride, ns, pen);
+}
+
 }  // namespace esi
 
 extern "C" esi_status_t esi_gradient(esi_plan_t plan, int32_t shot0, int32_t ns, int32_t mode,
@@ -835,6 +869,14 @@ extern "C" esi_status_t esi_gradient(esi_plan_t plan, int32_t shot0, int32_t ns,
     Plan* P = (Plan*)plan;
     ESI_TRY(check_shots(P, shot0, ns));
     return gradient_impl(P, shot0, ns, mode, src_kind, src, nullptr, data, grad_m, grad_src, K);
+}
+
+extern "C" esi_status_t esi_plan_set_beta(esi_plan_t plan, double beta) {
+    set_error("");
+    if (!plan) return fail(ESI_ERR_ARG, "null plan");
+    if (!(beta >= 0) || !std::isfinite(beta)) return fail(ESI_ERR_ARG, "beta must be finite and >= 0");
+    ((Plan*)plan)->beta = beta;
+    return ESI_OK;
 }
 
 extern "C" esi_status_t esi_wri_gradient(esi_plan_t plan, int32_t shot0, int32_t ns, int32_t mode,

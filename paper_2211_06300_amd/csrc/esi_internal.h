@@ -295,6 +295,12 @@ esi_status_t launch_trace_at_src(Plan* P, const float* dense, int shot0, int nsh
 // grad_v = -2 grad_m / v^3
 esi_status_t launch_grad_velocity(Plan* P, const float* vel, const float* gm, float* gv, int64_t n);
 
+// forward pass of q (+ point wavelets bg) with the PENALTY correlation into
+// gshot, the data S(q [+ f]) into dsyn and the per-shot penalty beta W q^2 sums
+// into pen (api.hip; used by the outer loop)
+esi_status_t penalty_eval(Plan* P, int shot0, int ns, const float* q, const float* bg, float* gshot,
+                          float* dsyn, double* pen);
+
 // flexible CG (fcg.hip) and the network (unet.hip)
 esi_status_t launch_energy(Plan* P, const float* r, const int* active, float* a, int ns);
 esi_status_t launch_stats(Plan* P, const float* r, const float* x, const float* p, const double* alpha,

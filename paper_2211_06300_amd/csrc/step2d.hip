@@ -161,7 +161,10 @@ __device__ __forceinline__ void cell_outputs(const StepArgs& a, const StepPtrs& 
         at(o.dout, pi) = np;
         acc += (double)pv * (double)np;
     }
-    if constexpr ((FL & F_PENALTY) != 0) at(o.gacc, pi) = fmaf(wb * q, c2v * a.inv_dt2 * lq, at(o.gacc, pi));
+    if constexpr ((FL & F_PENALTY) != 0) {
+        at(o.gacc, pi) = fmaf(wb * q, c2v * a.inv_dt2 * lq, at(o.gacc, pi));
+        acc += (double)(wb * q) * (double)q;   // penalty term beta W q^2 (kept when a.part is set)
+    }
     if constexpr ((FL & F_STORE) != 0) at(o.store, pi) = c2v * a.inv_dt2 * lq;
     if constexpr ((FL & F_CORR) != 0) at(o.gacc, pi) = fmaf(un, stv, at(o.gacc, pi));
 }
@@ -373,14 +376,16 @@ __global__ __launch_bounds__(256, ESI_MINW) void k_step2d(const StepArgs a) {
         cell_outputs<FL>(a, o1, pi[i], un, qd, lq, c2v[i], pv[i], stv[i], wb, acc);
     }
 
-    if constexpr ((FL & (F_NORMAL | F_SCALE)) != 0) {
-        acc = wave_sum(acc + pr_acc);
-        if (lane == 0) sred[wv] = acc;
-        __syncthreads();
-        if (tid == 0) {
-            double sum = 0.0;
-            for (int w = 0; w < 4; ++w) sum += sred[w];
-            a.part[(int64_t)s * a.part_stride + t] += sum;
+    if constexpr ((FL & (F_NORMAL | F_SCALE | F_PENALTY)) != 0) {
+        if (a.part) {   // uniform over the launch
+            acc = wave_sum(acc + pr_acc);
+            if (lane == 0) sred[wv] = acc;
+            __syncthreads();
+            if (tid == 0) {
+                double sum = 0.0;
+                for (int w = 0; w < 4; ++w) sum += sred[w];
+                a.part[(int64_t)s * a.part_stride + t] += sum;
+            }
         }
     }
 }
@@ -705,14 +710,16 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
         cell_outputs<FL>(a, oB, pi[i], un, qd, lq, c2v[i], pvB[i], stB[i], wb, acc);
     }
 
-    if constexpr ((FL & (F_NORMAL | F_SCALE)) != 0) {
-        acc = wave_sum(acc);
-        if (lane == 0) sred[wv] = acc;
-        __syncthreads();
-        if (tid == 0) {
-            double sum = 0.0;
-            for (int w = 0; w < 4; ++w) sum += sred[w];
-            a.part[(int64_t)s * a.part_stride + t] += sum;
+    if constexpr ((FL & (F_NORMAL | F_SCALE | F_PENALTY)) != 0) {
+        if (a.part) {   // uniform over the launch
+            acc = wave_sum(acc);
+            if (lane == 0) sred[wv] = acc;
+            __syncthreads();
+            if (tid == 0) {
+                double sum = 0.0;
+                for (int w = 0; w < 4; ++w) sum += sred[w];
+                a.part[(int64_t)s * a.part_stride + t] += sum;
+            }
         }
     }
 }
@@ -764,6 +771,8 @@ esi_status_t dispatch2d(Plan* P, unsigned flags, const StepArgs& a) {
         ESI_CASE(F_SRC_DENSE)
         ESI_CASE(F_SRC_DENSE | F_PENALTY)
         ESI_CASE(F_SRC_POINT | F_SRC_DENSE | F_PENALTY)
+        ESI_CASE(F_SRC_DENSE | F_PENALTY | F_GATHER)
+        ESI_CASE(F_SRC_POINT | F_SRC_DENSE | F_PENALTY | F_GATHER)
         ESI_CASE(F_SRC_POINT | F_SRC_DENSE | F_GATHER)
         ESI_CASE(F_SRC_POINT | F_SRC_DENSE | F_GATHER | F_STORE)
         ESI_CASE(F_SRC_POINT | F_SRC_DENSE | F_STORE)

@@ -247,7 +247,10 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
                 at(dout, pi) = np;
                 acc += (double)pv * (double)np;
             }
-            if constexpr ((FL & F_PENALTY) != 0) at(gacc, pi) = fmaf(wb * qd, c2v * a.inv_dt2 * lq, at(gacc, pi));
+            if constexpr ((FL & F_PENALTY) != 0) {
+                at(gacc, pi) = fmaf(wb * qd, c2v * a.inv_dt2 * lq, at(gacc, pi));
+                acc += (double)(wb * qd) * (double)qd;   // penalty term (kept when a.part is set)
+            }
             if constexpr ((FL & F_STORE) != 0) at(store, pi) = c2v * a.inv_dt2 * lq;
             if constexpr ((FL & F_CORR) != 0) at(gacc, pi) = fmaf(un, stv, at(gacc, pi));
         }
@@ -255,15 +258,17 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
         for (int k = 0; k < 2 * HALO; ++k) w[k] = w[k + 1];
     }
 
-    if constexpr ((FL & F_NORMAL) != 0) {
+    if constexpr ((FL & (F_NORMAL | F_PENALTY)) != 0) {
+        if (a.part) {   // uniform over the launch
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-        if (lx == 0) sred[ly] = acc;
-        __syncthreads();
-        if (tid == 0) {
-            double sum = 0.0;
-            for (int k = 0; k < NTH / 64; ++k) sum += sred[k];
-            a.part[(int64_t)s * a.part_stride + t] += sum;
+            for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+            if (lx == 0) sred[ly] = acc;
+            __syncthreads();
+            if (tid == 0) {
+                double sum = 0.0;
+                for (int k = 0; k < NTH / 64; ++k) sum += sred[k];
+                a.part[(int64_t)s * a.part_stride + t] += sum;
+            }
         }
     }
 }
@@ -291,6 +296,8 @@ esi_status_t launch_step3d(Plan* P, unsigned flags, const StepArgs& a) {
         ESI_CASE(F_SRC_DENSE)
         ESI_CASE(F_SRC_DENSE | F_PENALTY)
         ESI_CASE(F_SRC_POINT | F_SRC_DENSE | F_PENALTY)
+        ESI_CASE(F_SRC_DENSE | F_PENALTY | F_GATHER)
+        ESI_CASE(F_SRC_POINT | F_SRC_DENSE | F_PENALTY | F_GATHER)
         ESI_CASE(F_SRC_POINT | F_SRC_DENSE | F_GATHER)
         ESI_CASE(F_SRC_POINT | F_SRC_DENSE | F_GATHER | F_STORE)
         ESI_CASE(F_SRC_POINT | F_SRC_DENSE | F_STORE)

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libesi.so")
 SRC_POINT, SRC_DENSE = 0, 1
 GRAD_PENALTY, GRAD_ADJOINT, GRAD_SEED, GRAD_SEED_REUSE = 0, 1, 2, 3
 WEIGHT_ANNIHILATOR, WEIGHT_IDENTITY = 0, 1
+BETA_FIXED, BETA_DISCREPANCY = 0, 1
 _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_SHAPE", 3: "ERR_CFL", 4: "ERR_OOM", 5: "ERR_HIP",
            6: "ERR_BREAKDOWN", 7: "ERR_NONFINITE"}
 
@@ -49,6 +50,21 @@ class _CgReport(ctypes.Structure):
                 ("stat_xref", ctypes.c_void_p), ("stat_out", ctypes.c_void_p)]
 
 
+class _InvertOpts(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int32), ("cg_iters", ctypes.c_int32), ("cg_rtol", ctypes.c_double),
+                ("shot_group", ctypes.c_int32), ("lbfgs_mem", ctypes.c_int32), ("ls_max", ctypes.c_int32),
+                ("armijo_c1", ctypes.c_double), ("first_step", ctypes.c_double), ("v_min", ctypes.c_double),
+                ("v_max", ctypes.c_double), ("beta_rule", ctypes.c_int32), ("misfit_lo", ctypes.c_double),
+                ("misfit_hi", ctypes.c_double), ("beta_factor", ctypes.c_double), ("beta_tries", ctypes.c_int32)]
+
+
+class _InvertReport(ctypes.Structure):
+    _fields_ = [("outer_done", ctypes.c_int32), ("evals", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("beta_final", ctypes.c_double), ("J", ctypes.c_void_p), ("misfit", ctypes.c_void_p),
+                ("beta", ctypes.c_void_p), ("beta_iter", ctypes.c_void_p), ("step", ctypes.c_void_p),
+                ("trials", ctypes.c_void_p)]
+
+
 _lib = None
 EXPORTS = ["esi_plan_create", "esi_plan_set_model", "esi_plan_destroy", "esi_last_error",
            "esi_forward", "esi_adjoint", "esi_normal_apply", "esi_cg_solve", "esi_gradient",
@@ -57,7 +73,8 @@ EXPORTS = ["esi_plan_create", "esi_plan_set_model", "esi_plan_destroy", "esi_las
            "esi_unet_num_params", "esi_unet_create", "esi_unet_destroy", "esi_unet_set_params",
            "esi_unet_get_params", "esi_unet_forward", "esi_unet_loss_grad", "esi_unet_adam",
            "esi_fpcg_solve", "esi_precond_features", "esi_unet_loss_weights", "esi_plan_autotune",
-           "esi_plan_set_weight", "esi_data_residual", "esi_wri_gradient"]
+           "esi_plan_set_weight", "esi_data_residual", "esi_wri_gradient", "esi_plan_set_beta",
+           "esi_invert"]
 # time-step kernel variants (bit set of fused work), as in include/esi.h
 K_FLAGS = {1: "SRC_POINT", 2: "SRC_DENSE", 4: "CG_FUSE", 8: "INJ", 16: "GATHER", 32: "OUT",
            64: "NORMAL", 128: "PENALTY", 256: "STORE", 512: "CORR", 1024: "SRC_REC",
@@ -85,6 +102,9 @@ def load_library(path: str = LIB_PATH):
     L.esi_cg_solve.argtypes = [vp, i32, i32, vp, vp, vp, i32, dbl, ctypes.POINTER(_CgReport)]
     L.esi_gradient.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp, vp, i32]
     L.esi_plan_set_weight.argtypes = [vp, i32]
+    L.esi_plan_set_beta.argtypes = [vp, dbl]
+    L.esi_invert.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(_InvertOpts),
+                             ctypes.POINTER(_InvertReport)]
     L.esi_data_residual.argtypes = [vp, i32, i32, vp, vp, vp]
     L.esi_wri_gradient.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, i32]
     L.esi_plan_profile.argtypes = [vp, i32]
@@ -249,6 +269,42 @@ class Plan:
                                           _f32(q, self.vec_shape(nshots), "q"), dptr,
                                           _f32(grad_m, self.phys_shape, "grad_m"), int(ckpt_every)))
         return grad_m
+
+    def set_beta(self, beta: float):
+        _check(self._lib.esi_plan_set_beta(self._h, float(beta)))
+
+    def invert(self, d_obs, vel, *, wavelet=None, mask=None, shot0=0, nshots=None, shot_group=None,
+               x=None, work=None, outer_iters=3, cg_iters=10, cg_rtol=0.0, lbfgs_mem=5, ls_max=6,
+               armijo_c1=1e-4, first_step=0.02, v_min=1000.0, v_max=6000.0, beta_rule=BETA_FIXED,
+               misfit_lo=0.05, misfit_hi=0.2, beta_factor=2.0, beta_tries=4):
+        """esi_invert: the outer loop of Algorithm 2.  vel (device [phys]) holds
+        the starting model and receives the last accepted one; returns the
+        report as a dict of counts and histories."""
+        shot0, nshots = self._range(shot0, nshots)
+        G = nshots if shot_group is None else int(shot_group)
+        x = self.new_vec(G) if x is None else x
+        if work is None:
+            work = torch.empty((3, *self.vec_shape(G)), dtype=torch.float32, device=self.device)
+        o = _InvertOpts(int(outer_iters), int(cg_iters), float(cg_rtol), G, int(lbfgs_mem), int(ls_max),
+                        float(armijo_c1), float(first_step), float(v_min), float(v_max), int(beta_rule),
+                        float(misfit_lo), float(misfit_hi), float(beta_factor), int(beta_tries))
+        k = int(outer_iters)
+        h = {"J": np.zeros(k + 1), "misfit": np.zeros(k + 1), "beta": np.zeros(k + 1),
+             "beta_iter": np.zeros(k), "step": np.zeros(k), "trials": np.zeros(k, dtype=np.int32)}
+        r = _InvertReport(0, 0, 0, 0.0, *[a.ctypes.data if a.size else None for a in h.values()])
+        _check(self._lib.esi_invert(self._h, shot0, nshots, _f32(d_obs, self.data_shape(shot0, nshots), "d_obs"),
+                                    None if wavelet is None else _f32(wavelet, (nshots, self.nt), "wavelet"),
+                                    _f32(vel, self.phys_shape, "vel"),
+                                    None if mask is None else _f32(mask, self.phys_shape, "mask"),
+                                    _f32(x, self.vec_shape(G), "x"), _f32(work, (3, *self.vec_shape(G)), "work"),
+                                    ctypes.byref(o), ctypes.byref(r)))
+        n = r.outer_done
+        return {"outer_done": n, "evals": r.evals, "status": r.status, "beta_final": r.beta_final,
+                "J": h["J"][:n + 1].tolist(), "misfit": h["misfit"][:n + 1].tolist(),
+                "beta": h["beta"][:n + 1].tolist(),
+                "beta_iter": h["beta_iter"][:n + (1 if r.status else 0)].tolist(),
+                "step": h["step"][:n].tolist(),
+                "trials": h["trials"][:n + (1 if r.status else 0)].tolist()}
 
     def set_cg_graph(self, enable: bool):
         _check(self._lib.esi_plan_set_cg_graph(self._h, int(bool(enable))))
