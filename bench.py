@@ -274,6 +274,44 @@ def wri_run(args, torch, dev):
             "dominant_loop": {"variant": name, "launches": rec["launches"], "ms": round(rec["ms"], 1)}}
 
 
+def invert_run(args, torch, dev):
+    """The outer loop of Algorithm 2 on one group of shots of the single-solve
+    workload: per evaluation the inner solve (flexible CG with the analytic
+    cell scale, invert_cg iterations) and one fused pass for the PENALTY
+    gradient, the data and the penalty; L-BFGS with an Armijo line search."""
+    from paper_2211_06300_amd import esi, inputs
+    cfg = inputs.cfg_single_solve(nshots=args.shots, nt=args.nt)
+    ns = min(args.group, cfg.nshots)
+    npad = (cfg.nz + 2 * cfg.nb) * (cfg.nx + 2 * cfg.nb)
+    plan_true = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_true).to(dev))
+    wav = torch.from_numpy(np.tile(cfg.wavelet, (ns, 1))).to(dev)
+    d_obs = plan_true.forward(wav, esi.SRC_POINT, shot0=0, nshots=ns)
+    plan_true.close()
+    plan = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_start).to(dev))
+    plan.set_beta(args.invert_beta)
+    vel = torch.from_numpy(cfg.v_start.copy()).to(dev)
+    mask = torch.ones(plan.phys_shape, dtype=torch.float32, device=dev)
+    mask[:5] = 0.0                                    # source and receiver rows keep their model
+    x = plan.new_vec(ns)
+    work = torch.empty((3, *plan.vec_shape(ns)), dtype=torch.float32, device=dev)
+    plan.autotune(nshots=ns, p=work[0], Ap=work[1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rep = plan.invert(d_obs, vel, mask=mask, nshots=ns, x=x, work=work, outer_iters=args.invert_iters,
+                      cg_iters=args.invert_cg, first_step=0.02, v_min=1400.0, v_max=5000.0,
+                      inner=esi.INNER_FCG_SCALE)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan.close()
+    props = 2 * args.invert_cg + 2                   # per shot and evaluation
+    return {"workload": "invert-" + cfg.name, "shots": ns, "nt": cfg.nt, "beta": args.invert_beta,
+            "outer_iters": rep["outer_done"], "inner": "fcg-analytic-scale", "inner_iters": args.invert_cg,
+            "evals": rep["evals"], "line_search_trials": rep["trials"], "J": [round(j, 6) for j in rep["J"]],
+            "data_misfit": [round(e, 6) for e in rep["misfit"]], "status": rep["status"],
+            "seconds": round(wall, 3), "seconds_per_eval": round(wall / max(rep["evals"], 1), 3),
+            "gpts_per_s": round(rep["evals"] * ns * props * npad * cfg.nt / wall / 1e9, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -293,6 +331,10 @@ def main():
     ap.add_argument("--batch-shots", type=int, default=128)
     ap.add_argument("--batch-nt", type=int, default=4000)
     ap.add_argument("--no-wri", action="store_true", help="skip the WRI run on the single-solve workload")
+    ap.add_argument("--no-invert", action="store_true", help="skip the outer-loop (Algorithm 2) run")
+    ap.add_argument("--invert-iters", type=int, default=2)
+    ap.add_argument("--invert-cg", type=int, default=30)
+    ap.add_argument("--invert-beta", type=float, default=100.0)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="also run one elementwise copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -421,6 +463,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_wri:
         out["wri"] = wri_run(args, torch, dev)
+        torch.cuda.empty_cache()
+    if not args.no_invert:
+        out["invert"] = invert_run(args, torch, dev)
         torch.cuda.empty_cache()
     if not args.no_cpu:
         log("timing the oracle on the host cores")

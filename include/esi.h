@@ -301,11 +301,17 @@ esi_status_t esi_plan_set_beta(esi_plan_t plan, double beta);
  * the inner solves' vectors (shots are solved shot_group at a time).  The
  * library allocates its FP64 model-space vectors (2 lbfgs_mem + 6 of [phys])
  * per call.
+ * The inner solver is Algorithm 1 (ESI_INNER_CG) or, for ESI, the flexible CG
+ * of esi_fpcg_solve preconditioned by the analytic cell scale
+ * 1 / (beta B^2 + inner_gamma), recomputed whenever beta changes
+ * (ESI_INNER_FCG_SCALE): the inner loop then converges in far fewer
+ * iterations, as Sec. 3 asks of it.
  * rep (optional) receives the counts and, through its non-NULL host arrays,
  * the histories.  Returns ESI_ERR_ARG for bad options; a failed line search is
  * not an error (rep->status = 1, vel = the last accepted model).
  */
 enum { ESI_BETA_FIXED = 0, ESI_BETA_DISCREPANCY = 1 };
+enum { ESI_INNER_CG = 0, ESI_INNER_FCG_SCALE = 1 };
 typedef struct {
     int32_t outer_iters;   /* N_outer >= 0 */
     int32_t cg_iters;      /* inner CG iterations >= 1 */
@@ -320,6 +326,9 @@ typedef struct {
     double misfit_lo, misfit_hi;   /* discrepancy band, 0 <= lo <= hi */
     double beta_factor;    /* > 1 */
     int32_t beta_tries;    /* >= 0 */
+    int32_t inner;         /* ESI_INNER_CG: Algorithm 1; ESI_INNER_FCG_SCALE: esi_fpcg_solve with
+                              the cell scale 1 / (beta B^2 + inner_gamma) (ESI only) */
+    double inner_gamma;    /* > 0 */
 } esi_invert_opts_t;
 typedef struct {
     int32_t outer_done;    /* accepted outer iterations */

@@ -146,12 +146,16 @@ def minimize(evaluate, m0: np.ndarray, beta0: float, opts: OuterOptions) -> Oute
 
 
 def esi_objective(g: core.Grid, shots, cg_iters: int, cg_rtol: float = 0.0, eta_max=None,
-                  wavelet=None, mask=None, eps: float = 1.0):
+                  wavelet=None, mask=None, eps: float = 1.0, inner: str = "cg", gamma: float = 0.03):
     """evaluate(m, beta) of the reduced ESI (or, with `wavelet`, WRI) objective:
     per shot the CG iterate q of the normal equation, J = sum of eq. (esi) (or
     eq. (wridSf)), the PENALTY gradient of Algorithm 2 (lambda = beta W q with
     u = A^{-1} q, or A^{-1}(f + q) for WRI) times `mask`, and the relative data
     misfit ||S q - d|| / ||d|| over all shots.
+
+    inner "cg" solves by Algorithm 1; "fcg" (ESI) by flexible CG (``core.fpcg``)
+    preconditioned by the cell scale 1 / (beta B^2 + gamma), with its fallback to
+    plain CG.
 
     shots: list of (src_pos, rec, d_obs)."""
     dd = sum(core.dot(d, d) for _, _, d in shots)
@@ -163,7 +167,12 @@ def esi_objective(g: core.Grid, shots, cg_iters: int, cg_rtol: float = 0.0, eta_
         for s, (src, rec, d) in enumerate(shots):
             if wavelet is None:
                 w2 = core.annihilator_sq(g, src, eps)
-                q = core.esi_cg(mod, src, rec, d, beta, cg_iters, cg_rtol, eps=eps).x
+                if inner == "fcg":
+                    s0 = 1.0 / (beta * w2 + gamma)
+                    q = core.fpcg(lambda p: core.normal_apply(mod, rec, w2, beta, p), core.adjoint(mod, rec, d),
+                                  lambda r: s0[None] * r, cg_iters, cg_rtol).x
+                else:
+                    q = core.esi_cg(mod, src, rec, d, beta, cg_iters, cg_rtol, eps=eps).x
                 d_syn = core.forward(mod, q, rec)
                 J += 0.5 * core.dot(d_syn - d, d_syn - d) + 0.5 * beta * core.dot(w2[None] * q, q)
                 grad += core.gradient_penalty(mod, q, w2, beta)

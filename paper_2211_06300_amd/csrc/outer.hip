@@ -90,6 +90,20 @@ __global__ void k_trial(const double* __restrict__ m, const double* __restrict__
         mt[i] = fmin(fmax(m[i] + alpha * d[i], lo), hi);
 }
 
+// s[k][x] = 1 / (beta B^2 + gamma), B = |x - x_s| + b_eps in cells, for shots s0 + k
+__global__ void k_cell_scale(const int32_t* __restrict__ src, int s0, int ns, int nz, int nx, double beta,
+                             double b_eps, double gamma, float* __restrict__ out) {
+    const int64_t n = (int64_t)nz * nx;
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < ns * n; i += (int64_t)gridDim.x * NT) {
+        const int k = (int)(i / n);
+        const int64_t c = i - k * n;
+        const int iz = (int)(c / nx), ix = (int)(c - (int64_t)iz * nx);
+        const double dx = ix - src[(s0 + k) * 3 + 0], dz = iz - src[(s0 + k) * 3 + 1];
+        const double b = sqrt(dx * dx + dz * dz) + b_eps;
+        out[i] = (float)(1.0 / (beta * b * b + gamma));
+    }
+}
+
 // g = gm (* mask)
 __global__ void k_grad_d(const float* __restrict__ gm, const float* __restrict__ mask, double* __restrict__ g,
                          int64_t n) {
@@ -139,6 +153,7 @@ struct Outer {
     float* gm;            // summed gradient (float)
     float* dsyn;          // synthetic data of a group
     float* dres;          // WRI right-hand side data of a group
+    float* scale;         // inner FCG cell scale of a group [G][phys]
     double* pen;          // [G] per-shot penalty sums
     double dd = 0.0;      // ||d_obs||^2
 
@@ -207,7 +222,14 @@ struct Outer {
             }
             esi_cg_report_t rep;
             std::memset(&rep, 0, sizeof rep);
-            ESI_TRY(esi_cg_solve(plan, s0, k, rhs, x, work, o->cg_iters, o->cg_rtol, &rep));
+            if (o->inner == ESI_INNER_FCG_SCALE) {
+                hipLaunchKernelGGL(k_cell_scale, dim3(grid_for((int64_t)k * n)), dim3(NT), 0, P->stream, P->d_src,
+                                   s0, k, P->nz, P->nx, beta, P->b_eps, o->inner_gamma, scale);
+                ESI_HIP_TRY(hipGetLastError());
+                ESI_TRY(esi_fpcg_solve(plan, s0, k, rhs, x, work, o->cg_iters, o->cg_rtol, nullptr, 0, scale, &rep));
+            } else {
+                ESI_TRY(esi_cg_solve(plan, s0, k, rhs, x, work, o->cg_iters, o->cg_rtol, &rep));
+            }
             ESI_TRY(grow_t(&P->gshot, &P->gshot_cap, (int64_t)k * n, P->stream));
             ESI_TRY(launch_fill(P, P->gshot, (int64_t)k * n, 0.f));
             ESI_TRY(penalty_eval(P, s0, k, x, f, P->gshot, dsyn, pen));
@@ -236,7 +258,8 @@ esi_status_t check_opts(const esi_invert_opts_t* o, int ns) {
     if (o->outer_iters < 0 || o->cg_iters < 1 || !(o->cg_rtol >= 0) || o->shot_group < 1 || o->shot_group > ns ||
         o->lbfgs_mem < 1 || o->ls_max < 1 || !(o->armijo_c1 > 0 && o->armijo_c1 < 1) || !(o->first_step > 0) ||
         !(o->v_min > 0 && o->v_max > o->v_min) || (o->beta_rule != ESI_BETA_FIXED && o->beta_rule != ESI_BETA_DISCREPANCY) ||
-        !(o->misfit_lo >= 0 && o->misfit_hi >= o->misfit_lo) || !(o->beta_factor > 1) || o->beta_tries < 0)
+        !(o->misfit_lo >= 0 && o->misfit_hi >= o->misfit_lo) || !(o->beta_factor > 1) || o->beta_tries < 0 ||
+        (o->inner != ESI_INNER_CG && o->inner != ESI_INNER_FCG_SCALE) || !(o->inner_gamma > 0))
         return fail(ESI_ERR_ARG, "invalid outer-loop options");
     return ESI_OK;
 }
@@ -256,6 +279,8 @@ extern "C" esi_status_t esi_invert(esi_plan_t plan, int32_t shot0, int32_t ns, c
     ESI_TRY(check_opts(opts, ns));
     const int64_t dl = (int64_t)P->nt * (P->h_rec_ptr[shot0 + ns] - P->h_rec_ptr[shot0]);
     if (!vel || !x || !work || (dl > 0 && !d_obs)) return fail(ESI_ERR_ARG, "null pointer");
+    if (opts->inner == ESI_INNER_FCG_SCALE && (wavelet || P->ndim != 2))
+        return fail(ESI_ERR_ARG, "the scaled inner solver is for 2D ESI");
     const esi_invert_opts_t& o = *opts;
     Outer S;
     S.P = P; S.plan = plan; S.shot0 = shot0; S.ns = ns; S.G = o.shot_group;
@@ -280,6 +305,7 @@ extern "C" esi_status_t esi_invert(esi_plan_t plan, int32_t shot0, int32_t ns, c
     }
     ESI_TRY(sc.alloc(&S.red, RB)); ESI_TRY(sc.alloc(&S.vt, n)); ESI_TRY(sc.alloc(&S.gm, n));
     ESI_TRY(sc.alloc(&S.dsyn, gdl)); ESI_TRY(sc.alloc(&S.dres, wavelet ? gdl : 1)); ESI_TRY(sc.alloc(&S.pen, S.G));
+    ESI_TRY(sc.alloc(&S.scale, o.inner == ESI_INNER_FCG_SCALE ? (int64_t)S.G * n : 1));
 
     const double lo = 1.0 / (o.v_max * o.v_max), hi = 1.0 / (o.v_min * o.v_min);
     hipLaunchKernelGGL(k_m_from_vel, dim3(grid_for(n)), dim3(NT), 0, P->stream, vel, lo, hi, m, n);

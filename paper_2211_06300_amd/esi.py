@@ -19,6 +19,7 @@ SRC_POINT, SRC_DENSE = 0, 1
 GRAD_PENALTY, GRAD_ADJOINT, GRAD_SEED, GRAD_SEED_REUSE = 0, 1, 2, 3
 WEIGHT_ANNIHILATOR, WEIGHT_IDENTITY = 0, 1
 BETA_FIXED, BETA_DISCREPANCY = 0, 1
+INNER_CG, INNER_FCG_SCALE = 0, 1
 _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_SHAPE", 3: "ERR_CFL", 4: "ERR_OOM", 5: "ERR_HIP",
            6: "ERR_BREAKDOWN", 7: "ERR_NONFINITE"}
 
@@ -55,7 +56,8 @@ class _InvertOpts(ctypes.Structure):
                 ("shot_group", ctypes.c_int32), ("lbfgs_mem", ctypes.c_int32), ("ls_max", ctypes.c_int32),
                 ("armijo_c1", ctypes.c_double), ("first_step", ctypes.c_double), ("v_min", ctypes.c_double),
                 ("v_max", ctypes.c_double), ("beta_rule", ctypes.c_int32), ("misfit_lo", ctypes.c_double),
-                ("misfit_hi", ctypes.c_double), ("beta_factor", ctypes.c_double), ("beta_tries", ctypes.c_int32)]
+                ("misfit_hi", ctypes.c_double), ("beta_factor", ctypes.c_double), ("beta_tries", ctypes.c_int32),
+                ("inner", ctypes.c_int32), ("inner_gamma", ctypes.c_double)]
 
 
 class _InvertReport(ctypes.Structure):
@@ -276,7 +278,7 @@ class Plan:
     def invert(self, d_obs, vel, *, wavelet=None, mask=None, shot0=0, nshots=None, shot_group=None,
                x=None, work=None, outer_iters=3, cg_iters=10, cg_rtol=0.0, lbfgs_mem=5, ls_max=6,
                armijo_c1=1e-4, first_step=0.02, v_min=1000.0, v_max=6000.0, beta_rule=BETA_FIXED,
-               misfit_lo=0.05, misfit_hi=0.2, beta_factor=2.0, beta_tries=4):
+               misfit_lo=0.05, misfit_hi=0.2, beta_factor=2.0, beta_tries=4, inner=INNER_CG, inner_gamma=0.03):
         """esi_invert: the outer loop of Algorithm 2.  vel (device [phys]) holds
         the starting model and receives the last accepted one; returns the
         report as a dict of counts and histories."""
@@ -287,7 +289,8 @@ class Plan:
             work = torch.empty((3, *self.vec_shape(G)), dtype=torch.float32, device=self.device)
         o = _InvertOpts(int(outer_iters), int(cg_iters), float(cg_rtol), G, int(lbfgs_mem), int(ls_max),
                         float(armijo_c1), float(first_step), float(v_min), float(v_max), int(beta_rule),
-                        float(misfit_lo), float(misfit_hi), float(beta_factor), int(beta_tries))
+                        float(misfit_lo), float(misfit_hi), float(beta_factor), int(beta_tries), int(inner),
+                        float(inner_gamma))
         k = int(outer_iters)
         h = {"J": np.zeros(k + 1), "misfit": np.zeros(k + 1), "beta": np.zeros(k + 1),
              "beta_iter": np.zeros(k), "step": np.zeros(k), "trials": np.zeros(k, dtype=np.int32)}

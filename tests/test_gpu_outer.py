@@ -79,11 +79,10 @@ def _run_gpu(esi, cfg, d_obs, mask, wavelet=None, weight=None, **opts):
     return vel.cpu().numpy(), rep
 
 
-def _run_oracle(cfg, g, eta, d_obs, mask, wavelet=None, cg_iters=8, beta=None, **opts):
-    rec = cfg.shot_rec(0)
+def _run_oracle(cfg, g, eta, d_obs, mask, wavelet=None, cg_iters=8, beta=None, inner="cg", **opts):
     shots = [(tuple(cfg.src[s]), cfg.shot_rec(s), d_obs[s].astype(np.float64)) for s in range(2)]
     ev = outer.esi_objective(g, shots, cg_iters, eta_max=eta, mask=mask.astype(np.float64),
-                             wavelet=None if wavelet is None else wavelet.astype(np.float64))
+                             wavelet=None if wavelet is None else wavelet.astype(np.float64), inner=inner)
     m0 = 1.0 / cfg.v_start.astype(np.float64) ** 2
     return outer.minimize(ev, m0, cfg.beta if beta is None else beta,
                           outer.OuterOptions(cg_iters=cg_iters, **opts)), m0
@@ -122,6 +121,20 @@ def test_esi_outer_loop_matches_oracle(esi):
     assert _rel(m - m0, ref.m - m0) < 1e-3
     assert np.all(vel[:3] == cfg.v_start[:3])           # masked rows keep their model
     assert rep["J"][-1] < rep["J"][0]
+
+
+def test_scaled_inner_solver_matches_oracle(esi):
+    """Inner solves by flexible CG with the cell scale 1 / (beta B^2 + 0.03):
+    objective at the start and one outer iteration."""
+    cfg, g, eta, d_obs, mask = _case()
+    opts = dict(outer_iters=1, first_step=0.03)
+    vel, rep = _run_gpu(esi, cfg, d_obs, mask, cg_iters=8, inner=esi.INNER_FCG_SCALE, **opts)
+    ref, m0 = _run_oracle(cfg, g, eta, d_obs, mask, inner="fcg", **opts)
+    assert rep["trials"] == ref.trials and rep["status"] == 0
+    np.testing.assert_allclose(rep["J"], ref.J, rtol=1e-4)
+    np.testing.assert_allclose(rep["misfit"], ref.misfit, rtol=1e-4)
+    m = 1.0 / vel.astype(np.float64) ** 2
+    assert _rel(m - m0, ref.m - m0) < 1e-3
 
 
 def test_outer_loop_deterministic_and_grouping(esi):
