@@ -347,6 +347,46 @@ esi_status_t esi_invert(esi_plan_t plan, int32_t shot0, int32_t nshots, const fl
                         float* work, const esi_invert_opts_t* opts, esi_invert_report_t* rep);
 
 /*
+ * Frequency-domain ESI with time-domain modelling (Sec. 5.2, eq. (dtft),
+ * eq. (idtft), eq. (normaldtft)), 2D plans.  Frequency vectors are device
+ * float32 arrays [nshots][nf][phys][2] of (re, im) pairs: the DTFT
+ * (F u)_m = sum_n u_n exp(+j 2 pi f_m n dt) of a [nt][phys] field at the
+ * plan's nf frequencies.  G s = (1/nt) Re sum_m s_m exp(-j 2 pi f_m n dt) is
+ * the inverse (the real part: the modelling needs a real source), so that
+ * G = F^* / nt under the real inner product Re sum conj(a) b.  The time loops
+ * never store a time axis: G feeds the forward pass inside the stencil kernel
+ * and F of the adjoint field accumulates in complex float32 slices.
+ *
+ * esi_dtft_set_freqs: nf (1..32) frequencies in Hz (host array); the plan
+ *   keeps the twiddle table and F G (a 2nf x 2nf real matrix).  ESI_ERR_ARG
+ *   for a bad count or a negative or non-finite frequency.
+ * esi_dtft_normal_apply: Mp = F (S^T S + beta W) G p with the plan's weight W;
+ *   pMp (device double [nshots], nullable) = Re p^H M p.  p and Mp must not
+ *   alias.
+ * esi_dtft_rhs: b = F S^T G F d_obs (the data represented through the inverse
+ *   DTFT of their DTFT); d_obs as in esi_forward.
+ * esi_dtft_cg_solve: Algorithm 1 on M x = F S^T G F d_obs with the real inner
+ *   product, per shot, FP64 dots and step lengths; x: frequency vectors; work:
+ *   three more; rep and errors as esi_cg_solve.
+ * esi_dtft_to_time: q = G x, device [nshots][nt][phys].
+ * esi_dtft_gradient: Algorithm 2's PENALTY gradient with the time-domain source
+ *   q = G x formed on the fly (lambda = beta W q, u = A^{-1} q), summed over
+ *   the shots and ADDED to grad_m (device [phys]).
+ * Each returns ESI_ERR_ARG when esi_dtft_set_freqs has not been called or the
+ * plan is 3D.
+ */
+esi_status_t esi_dtft_set_freqs(esi_plan_t plan, int32_t nf, const double* freqs_hz);
+esi_status_t esi_dtft_normal_apply(esi_plan_t plan, int32_t shot0, int32_t nshots, const float* p,
+                                   float* Mp, double* pMp);
+esi_status_t esi_dtft_rhs(esi_plan_t plan, int32_t shot0, int32_t nshots, const float* d_obs, float* b);
+esi_status_t esi_dtft_cg_solve(esi_plan_t plan, int32_t shot0, int32_t nshots, const float* d_obs,
+                               float* x, float* work, int32_t max_iter, double rtol,
+                               esi_cg_report_t* rep);
+esi_status_t esi_dtft_to_time(esi_plan_t plan, int32_t shot0, int32_t nshots, const float* x, float* q);
+esi_status_t esi_dtft_gradient(esi_plan_t plan, int32_t shot0, int32_t nshots, const float* x,
+                               float* grad_m);
+
+/*
  * Chain rule from m = 1/v^2 to v: grad_v = -2 grad_m / v^3 on the physical
  * grid (device [phys] each; grad_v may alias grad_m).
  */

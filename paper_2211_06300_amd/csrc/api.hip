@@ -20,12 +20,6 @@ esi_status_t launch_copy_shots(Plan* P, float* dst, int64_t dst_stride, const fl
                                int64_t src_stride, int64_t n, int nshots);
 esi_status_t launch_fill_d(Plan* P, double* p, int64_t n);
 
-namespace {
-
-// per-shot ring: u slot 0, u slot 1, d slot 0, d slot 1.  The current state is
-// (u[cs], d[cs]); every launch writes (u[1-cs], d[1-cs]) and flips cs.
-constexpr int RING = 4;
-
 esi_status_t check_shots(Plan* P, int shot0, int nshots) {
     if (nshots < 1 || shot0 < 0 || shot0 + nshots > P->nshots)
         return fail(ESI_ERR_ARG, "shot range [" + std::to_string(shot0) + ", " +
@@ -139,7 +133,7 @@ struct ProfScope {
 // saved at every n = k*K into ckpt[s][k][2][fsize] (two-step launches never
 // straddle a checkpoint).  Profiling records two-step launches with bit 1<<15.
 esi_status_t forward_loop(Plan* P, StepArgs a, unsigned flags, float* ring, int* cs, int n0,
-                          int n1, float* ckpt = nullptr, int K = 0, int nseg = 0) {
+                          int n1, float* ckpt, int K, int nseg) {
     ProfScope p1(P, flags, a.nshots), p2(P, flags | (1u << 15), a.nshots);
     TileLists* L2;
     ESI_TRY(t2_lists(P, &L2, false));
@@ -176,7 +170,7 @@ esi_status_t forward_loop(Plan* P, StepArgs a, unsigned flags, float* ring, int*
 
 // Adjoint time loop over j = j1-1 .. j0 on `ring` whose state is in slot *cs.
 esi_status_t adjoint_loop(Plan* P, StepArgs a, unsigned flags, float* ring, int* cs, int j0,
-                          int j1, int K = 0) {
+                          int j1, int K) {
     ProfScope p1(P, flags, a.nshots), p2(P, flags | (1u << 15), a.nshots);
     TileLists* L2;
     ESI_TRY(t2_lists(P, &L2, true));
@@ -213,6 +207,8 @@ esi_status_t do_forward(Plan* P, int shot0, int ns, int kind, const float* src, 
     ESI_TRY(forward_loop(P, a, fl, P->ring, &cs, 0, P->nt));
     return launch_final_gather(P, P->ring + (int64_t)cs * P->fsize, RING * P->fsize, data, shot0, ns);
 }
+
+namespace {
 
 // N p into Ap (+ p.Np partials in P->part [ns][tiles]) for the active shots.
 // With cg_fuse the forward pass first forms p_new = r + beta p (p = p_old is

@@ -72,6 +72,11 @@ struct Plan {
     int ndim = 2, nz = 0, nx = 0, ny = 1, nb = 0, nt = 0;
     double dx = 0, dt = 0, eta_max = 0, beta = 0, b_eps = 1;
     int w_identity = 0;                  // penalty weight B = I (WRI) instead of the annihilator
+    // DTFT frequencies (Hz), twiddle table [nt][nf] (cos, sin) and F G as a
+    // real 2nf x 2nf matrix (row (k, re/im), column (m, re/im))
+    std::vector<double> dft_freqs;
+    float2* dft_tw = nullptr;
+    double* dft_C = nullptr;
     int nzp = 0, nyp = 1, nxp = 0;       // padded grid
     int ZS = 0, YS = 1, XS = 0;          // storage grid (padded + zero ghost halo)
     int64_t fsize = 0;                   // floats per stored field (one shot)
@@ -240,6 +245,13 @@ struct StepArgs {
     int store_slot;          // slot of this step
     int store_slot2;         // slot of the second step of a two-step launch
     float* src_rec;          // [nshots][nt] adjoint field at the source cell
+    // DTFT at dft_nf frequencies; frequency vectors [nshots][dft_nf][phys] of
+    // (re, im) pairs; dft_tw[n][m] = (cos w_m t_n, sin w_m t_n)
+    const float2* dft_src;   // F_DTFT_SRC: q^n = inv_nt sum_m Re(src_m exp(-j w_m t_n))
+    float2* dft_acc;         // F_DTFT_ACC: acc_m += mu^j exp(+j w_m t_j)
+    const float2* dft_tw;
+    int dft_nf;
+    float inv_nt;
 };
 
 // kernel flag bits
@@ -257,6 +269,8 @@ enum : unsigned {
     F_SRC_REC = 1u << 10,    // src_rec[s][j] = mu^j at the shot's source cell (adjoint)
     F_SCALE = 1u << 11,      // with F_CG_FUSE: the new direction is s r + beta p (flexible CG);
                              // p_new . r accumulates into the (shot, tile) partials
+    F_DTFT_SRC = 1u << 12,   // dense source from frequency slices (inverse DTFT on the fly)
+    F_DTFT_ACC = 1u << 13,   // accumulate the DTFT of the output mu^j (adjoint)
 };
 
 // Gather of the last trace d^{nt-1} = R u^{nt} (after the time loop).
@@ -294,6 +308,24 @@ esi_status_t launch_sub(Plan* P, float* out, const float* a, const float* b, int
 esi_status_t launch_trace_at_src(Plan* P, const float* dense, int shot0, int nshots, float* out);
 // grad_v = -2 grad_m / v^3
 esi_status_t launch_grad_velocity(Plan* P, const float* vel, const float* gm, float* gv, int64_t n);
+
+// per-shot ring: u slot 0, u slot 1, d slot 0, d slot 1.  The current state is
+// (u[cs], d[cs]); every launch writes (u[1-cs], d[1-cs]) and flips cs.
+constexpr int RING = 4;
+
+// time-loop plumbing of the entry points (api.hip)
+esi_status_t check_shots(Plan* P, int shot0, int nshots);
+esi_status_t lists_for(Plan* P, TileLists** L);
+esi_status_t t2_lists(Plan* P, TileLists** L2, bool adjoint);
+StepArgs base_args(Plan* P, const TileLists* L, int shot0, int nshots);
+esi_status_t ring_for(Plan* P, float** ring, int* cap, int nshots);
+int64_t data_len(Plan* P, int shot0, int nshots);
+// forward steps [n0, n1) (checkpoints of (u, d) every K steps into ckpt when given)
+esi_status_t forward_loop(Plan* P, StepArgs a, unsigned flags, float* ring, int* cs, int n0, int n1,
+                          float* ckpt = nullptr, int K = 0, int nseg = 0);
+// adjoint steps j = j1 - 1 down to j0 (segment length K for the store slots)
+esi_status_t adjoint_loop(Plan* P, StepArgs a, unsigned flags, float* ring, int* cs, int j0, int j1,
+                          int K = 0);
 
 // forward pass of q (+ point wavelets bg) with the PENALTY correlation into
 // gshot, the data S(q [+ f]) into dsyn and the per-shot penalty beta W q^2 sums

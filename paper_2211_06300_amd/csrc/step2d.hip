@@ -151,6 +151,49 @@ __device__ __forceinline__ StepPtrs step_ptrs(const StepArgs& a, int s, int64_t 
 // Fused per-cell outputs of one step at a physical cell of the tile.
 //  un: new field, q: source term, lq: lap + dx^2 q, c2v: c / dx^2,
 //  pv: p^t (NORMAL), stv: stored (dA/dm)u (CORR).
+//
+// (The DTFT helpers below: the source of step n from the frequency slices,
+// q = inv_nt sum_m (re_m cos w_m t_n + im_m sin w_m t_n), and the update of a
+// cell's accumulators acc_m += mu (cos, sin)(w_m t), for the earlier step tA
+// first when a two-step launch passes its output muA.)
+template <int R>
+__device__ __forceinline__ void dtft_source(const StepArgs& a, int s, int step, const uint32_t* pi, const bool* ph,
+                                            float* q) {
+    const float2* __restrict__ tw = a.dft_tw + (int64_t)step * a.dft_nf;
+    const float2* __restrict__ sb = a.dft_src + (int64_t)s * a.dft_nf * a.nphys;
+    float acc[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) acc[i] = 0.f;
+    for (int m = 0; m < a.dft_nf; ++m) {
+        const float2 w = tw[m];
+        const float2* __restrict__ sm = sb + (int64_t)m * a.nphys;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const float2 v = sm[pi[i]];
+            acc[i] = fmaf(v.y, w.y, fmaf(v.x, w.x, acc[i]));
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) q[i] = ph[i] ? acc[i] * a.inv_nt : 0.f;
+}
+
+__device__ __forceinline__ void dtft_accumulate(const StepArgs& a, int s, uint32_t pi, int step, float mu, int stepA,
+                                                float muA) {
+    float2* __restrict__ acc = a.dft_acc + (int64_t)s * a.dft_nf * a.nphys + pi;
+    const float2* __restrict__ tw = a.dft_tw + (int64_t)step * a.dft_nf;
+    const float2* __restrict__ twA = a.dft_tw + (int64_t)(stepA < 0 ? 0 : stepA) * a.dft_nf;
+    for (int m = 0; m < a.dft_nf; ++m) {
+        float2 v = acc[(int64_t)m * a.nphys];
+        if (stepA >= 0) {
+            v.x = fmaf(muA, twA[m].x, v.x);
+            v.y = fmaf(muA, twA[m].y, v.y);
+        }
+        v.x = fmaf(mu, tw[m].x, v.x);
+        v.y = fmaf(mu, tw[m].y, v.y);
+        acc[(int64_t)m * a.nphys] = v;
+    }
+}
+
 template <unsigned FL>
 __device__ __forceinline__ void cell_outputs(const StepArgs& a, const StepPtrs& o, uint32_t pi,
                                              float un, float q, float lq, float c2v, float pv,
@@ -250,6 +293,7 @@ __global__ __launch_bounds__(256, ESI_MINW) void k_step2d(const StepArgs a) {
 #pragma unroll
         for (int i = 0; i < RZ; ++i) qv[i] = ph[i] ? at(q, pi[i]) : 0.f;
     }
+    if constexpr ((FL & F_DTFT_SRC) != 0) dtft_source<RZ>(a, s, a.step, pi, ph, qv);
     double pr_acc = 0.0;   // p_new . r partial (F_SCALE)
     if constexpr ((FL & F_CG_FUSE) != 0) {
         const float alp = (float)a.cg_alpha[s];
@@ -371,6 +415,7 @@ __global__ __launch_bounds__(256, ESI_MINW) void k_step2d(const StepArgs a) {
         if constexpr ((FL & F_SRC_REC) != 0) {
             if (zl * TX + xl == src_cell) a.src_rec[(int64_t)s * a.nt + a.step] = un;
         }
+        if constexpr ((FL & F_DTFT_ACC) != 0) dtft_accumulate(a, s, pi[i], a.step, un, -1, 0.f);
         float wb = 0.f;
         if constexpr ((FL & (F_NORMAL | F_PENALTY)) != 0) wb = annih_w(a, ix, z - a.nb, sx, sz);
         cell_outputs<FL>(a, o1, pi[i], un, qd, lq, c2v[i], pv[i], stv[i], wb, acc);
@@ -474,6 +519,7 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
 #pragma unroll
         for (int i = 0; i < A_RZ; ++i) qA[i] = phA[i] ? at(q, piA[i]) : 0.f;
     }
+    if constexpr ((FL & F_DTFT_SRC) != 0) dtft_source<A_RZ>(a, s, tA, piA, phA, qA);
     float alp = 0.f, bet = 0.f;
     if constexpr ((FL & F_CG_FUSE) != 0) {
         alp = (float)a.cg_alpha[s];
@@ -647,6 +693,7 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
 #pragma unroll
         for (int i = 0; i < B_RZ; ++i) qv[i] = ph[i] ? at(q, pi[i]) : 0.f;
     }
+    if constexpr ((FL & F_DTFT_SRC) != 0) dtft_source<B_RZ>(a, s, tB, pi, ph, qv);
     if constexpr ((FL & F_CG_FUSE) != 0) {
         const float* __restrict__ p = a.cg_p + vB;
         const float* __restrict__ r = a.cg_r + vB;
@@ -697,6 +744,8 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
             at(nxt, so0 + (uint32_t)(i * XS)) = un;
         }
         if (!ph[i]) continue;
+        if constexpr ((FL & F_DTFT_ACC) != 0)
+            dtft_accumulate(a, s, pi[i], tB, un, tA, U1[(zl + HALO) * A_W + lc + HALO]);
         if constexpr ((FL & F_CG_FUSE) != 0) {
             at(a.cg_pn + vB, pi[i]) = qd;
             if (alp != 0.f) at(a.cg_x + vB, pi[i]) = fmaf(alp, poB[i], xoB[i]);
@@ -778,6 +827,9 @@ esi_status_t dispatch2d(Plan* P, unsigned flags, const StepArgs& a) {
         ESI_CASE(F_SRC_POINT | F_SRC_DENSE | F_STORE)
         ESI_CASE(F_CG_FUSE | F_GATHER)
         ESI_CASE(F_CG_FUSE | F_GATHER | F_SCALE)
+        ESI_CASE(F_DTFT_SRC | F_GATHER)
+        ESI_CASE(F_DTFT_SRC | F_PENALTY)
+        ESI_CASE(F_INJ | F_DTFT_ACC)
         ESI_CASE(F_INJ | F_OUT)
         ESI_CASE(F_INJ | F_NORMAL)
         ESI_CASE(F_INJ | F_CORR)

@@ -76,7 +76,8 @@ EXPORTS = ["esi_plan_create", "esi_plan_set_model", "esi_plan_destroy", "esi_las
            "esi_unet_get_params", "esi_unet_forward", "esi_unet_loss_grad", "esi_unet_adam",
            "esi_fpcg_solve", "esi_precond_features", "esi_unet_loss_weights", "esi_plan_autotune",
            "esi_plan_set_weight", "esi_data_residual", "esi_wri_gradient", "esi_plan_set_beta",
-           "esi_invert"]
+           "esi_invert", "esi_dtft_set_freqs", "esi_dtft_normal_apply", "esi_dtft_rhs", "esi_dtft_cg_solve",
+           "esi_dtft_to_time", "esi_dtft_gradient"]
 # time-step kernel variants (bit set of fused work), as in include/esi.h
 K_FLAGS = {1: "SRC_POINT", 2: "SRC_DENSE", 4: "CG_FUSE", 8: "INJ", 16: "GATHER", 32: "OUT",
            64: "NORMAL", 128: "PENALTY", 256: "STORE", 512: "CORR", 1024: "SRC_REC",
@@ -105,6 +106,12 @@ def load_library(path: str = LIB_PATH):
     L.esi_gradient.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp, vp, i32]
     L.esi_plan_set_weight.argtypes = [vp, i32]
     L.esi_plan_set_beta.argtypes = [vp, dbl]
+    L.esi_dtft_set_freqs.argtypes = [vp, i32, vp]
+    L.esi_dtft_normal_apply.argtypes = [vp, i32, i32, vp, vp, vp]
+    L.esi_dtft_rhs.argtypes = [vp, i32, i32, vp, vp]
+    L.esi_dtft_cg_solve.argtypes = [vp, i32, i32, vp, vp, vp, i32, dbl, ctypes.POINTER(_CgReport)]
+    L.esi_dtft_to_time.argtypes = [vp, i32, i32, vp, vp]
+    L.esi_dtft_gradient.argtypes = [vp, i32, i32, vp, vp]
     L.esi_invert.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(_InvertOpts),
                              ctypes.POINTER(_InvertReport)]
     L.esi_data_residual.argtypes = [vp, i32, i32, vp, vp, vp]
@@ -270,6 +277,62 @@ class Plan:
                                           _f32(wavelet, (nshots, self.nt), "wavelet"),
                                           _f32(q, self.vec_shape(nshots), "q"), dptr,
                                           _f32(grad_m, self.phys_shape, "grad_m"), int(ckpt_every)))
+        return grad_m
+
+    # -- DTFT variant (frequency vectors [nshots][nf][*phys][2] float32) ------------
+    def dtft_set_freqs(self, freqs):
+        f = np.ascontiguousarray(freqs, dtype=np.float64)
+        _check(self._lib.esi_dtft_set_freqs(self._h, int(f.size), f.ctypes.data))
+        self.dtft_freqs = f
+
+    def dtft_shape(self, nshots):
+        return (nshots, len(self.dtft_freqs), *self.phys_shape, 2)
+
+    def dtft_normal_apply(self, p, shot0=0, nshots=None, out=None):
+        shot0, nshots = self._range(shot0, nshots)
+        sh = self.dtft_shape(nshots)
+        out = torch.empty(sh, dtype=torch.float32, device=self.device) if out is None else out
+        pMp = torch.zeros(nshots, dtype=torch.float64, device=self.device)
+        _check(self._lib.esi_dtft_normal_apply(self._h, shot0, nshots, _f32(p, sh, "p"), _f32(out, sh, "Mp"),
+                                               _ptr(pMp)))
+        return out, pMp
+
+    def dtft_rhs(self, d_obs, shot0=0, nshots=None):
+        shot0, nshots = self._range(shot0, nshots)
+        sh = self.dtft_shape(nshots)
+        b = torch.empty(sh, dtype=torch.float32, device=self.device)
+        _check(self._lib.esi_dtft_rhs(self._h, shot0, nshots, _f32(d_obs, self.data_shape(shot0, nshots), "d_obs"),
+                                      _f32(b, sh, "b")))
+        return b
+
+    def dtft_cg_solve(self, d_obs, max_iter, rtol=0.0, shot0=0, nshots=None, x=None, work=None):
+        shot0, nshots = self._range(shot0, nshots)
+        sh = self.dtft_shape(nshots)
+        x = torch.empty(sh, dtype=torch.float32, device=self.device) if x is None else x
+        work = torch.empty((3, *sh), dtype=torch.float32, device=self.device) if work is None else work
+        hist = np.zeros((nshots, max_iter + 1))
+        iters = np.zeros(nshots, dtype=np.int32)
+        rep = _CgReport(0, iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                        hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, None, None, None)
+        _check(self._lib.esi_dtft_cg_solve(self._h, shot0, nshots,
+                                           _f32(d_obs, self.data_shape(shot0, nshots), "d_obs"),
+                                           _f32(x, sh, "x"), _f32(work, (3, *sh), "work"), int(max_iter),
+                                           float(rtol), ctypes.byref(rep)))
+        return x, {"iters": rep.iters, "shot_iters": iters, "res_hist": hist}
+
+    def dtft_to_time(self, x, shot0=0, nshots=None):
+        shot0, nshots = self._range(shot0, nshots)
+        q = self.new_vec(nshots)
+        _check(self._lib.esi_dtft_to_time(self._h, shot0, nshots, _f32(x, self.dtft_shape(nshots), "x"),
+                                          _f32(q, self.vec_shape(nshots), "q")))
+        return q
+
+    def dtft_gradient(self, x, shot0=0, nshots=None, grad_m=None):
+        shot0, nshots = self._range(shot0, nshots)
+        grad_m = torch.zeros(self.phys_shape, dtype=torch.float32, device=self.device) \
+            if grad_m is None else grad_m
+        _check(self._lib.esi_dtft_gradient(self._h, shot0, nshots, _f32(x, self.dtft_shape(nshots), "x"),
+                                           _f32(grad_m, self.phys_shape, "grad_m")))
         return grad_m
 
     def set_beta(self, beta: float):
