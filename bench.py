@@ -312,6 +312,50 @@ def invert_run(args, torch, dev):
             "gpts_per_s": round(rep["evals"] * ns * props * npad * cfg.nt / wall / 1e9, 2)}
 
 
+def dtft_run(args, torch, dev):
+    """The DTFT variant on one group of shots of the single-solve workload:
+    CG on the frequency vectors at nf frequencies (the inverse DTFT feeds the
+    forward pass, the DTFT of the adjoint field accumulates in the adjoint
+    pass), then the PENALTY gradient of G x."""
+    from paper_2211_06300_amd import esi, inputs
+    cfg = inputs.cfg_single_solve(nshots=args.shots, nt=args.nt)
+    ns = min(args.group, cfg.nshots)
+    npad = (cfg.nz + 2 * cfg.nb) * (cfg.nx + 2 * cfg.nb)
+    freqs = np.arange(1, args.dtft_nf + 1) * 2.0            # 2, 4, ... Hz
+    plan_true = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_true).to(dev))
+    wav = torch.from_numpy(np.tile(cfg.wavelet, (ns, 1))).to(dev)
+    d_obs = plan_true.forward(wav, esi.SRC_POINT, shot0=0, nshots=ns)
+    plan_true.close()
+    plan = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_start).to(dev))
+    plan.dtft_set_freqs(freqs)
+    sh = plan.dtft_shape(ns)
+    x = torch.empty(sh, dtype=torch.float32, device=dev)
+    work = torch.empty((3, *sh), dtype=torch.float32, device=dev)
+    grad = torch.zeros(plan.phys_shape, dtype=torch.float32, device=dev)
+    plan.autotune(nshots=ns)
+    plan.dtft_cg_solve(d_obs, 1, nshots=ns, x=x, work=work)       # warm-up: every kernel once
+    torch.cuda.synchronize()
+    plan.profile(True)
+    t0 = time.perf_counter()
+    _, rep = plan.dtft_cg_solve(d_obs, args.cg_iters, nshots=ns, x=x, work=work)
+    plan.dtft_gradient(x, nshots=ns, grad_m=grad)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = plan.profile_read()
+    plan.profile(False)
+    plan.close()
+    props = 2 * args.cg_iters + 2
+    name, rec = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    vec_gb = 4 * ns * len(freqs) * cfg.nz * cfg.nx * 8 / 1e9
+    return {"workload": "dtft-" + cfg.name, "shots": ns, "nt": cfg.nt, "freqs_hz": freqs.tolist(),
+            "cg_iters": args.cg_iters, "propagations_per_shot": props, "seconds": round(wall, 3),
+            "gpts_per_s": round(ns * props * npad * cfg.nt / wall / 1e9, 2),
+            "cg_final_rel_residual_max": float(np.max(rep["res_hist"][:, -1])),
+            "cg_vectors_gb": round(vec_gb, 2),
+            "time_domain_cg_vectors_gb": round(4 * ns * cfg.nt * cfg.nz * cfg.nx * 4 / 1e9, 1),
+            "dominant_loop": {"variant": name, "launches": rec["launches"], "ms": round(rec["ms"], 1)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -332,6 +376,8 @@ def main():
     ap.add_argument("--batch-nt", type=int, default=4000)
     ap.add_argument("--no-wri", action="store_true", help="skip the WRI run on the single-solve workload")
     ap.add_argument("--no-invert", action="store_true", help="skip the outer-loop (Algorithm 2) run")
+    ap.add_argument("--no-dtft", action="store_true", help="skip the DTFT-variant run")
+    ap.add_argument("--dtft-nf", type=int, default=8)
     ap.add_argument("--invert-iters", type=int, default=2)
     ap.add_argument("--invert-cg", type=int, default=30)
     ap.add_argument("--invert-beta", type=float, default=100.0)
@@ -466,6 +512,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_invert:
         out["invert"] = invert_run(args, torch, dev)
+        torch.cuda.empty_cache()
+    if not args.no_dtft:
+        out["dtft"] = dtft_run(args, torch, dev)
         torch.cuda.empty_cache()
     if not args.no_cpu:
         log("timing the oracle on the host cores")

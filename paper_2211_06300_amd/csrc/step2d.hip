@@ -177,20 +177,33 @@ __device__ __forceinline__ void dtft_source(const StepArgs& a, int s, int step, 
     for (int i = 0; i < R; ++i) q[i] = ph[i] ? acc[i] * a.inv_nt : 0.f;
 }
 
+// Frequencies go in chunks whose loads are all issued before any store, so a
+// cell's read-modify-writes overlap instead of waiting one on another.
 __device__ __forceinline__ void dtft_accumulate(const StepArgs& a, int s, uint32_t pi, int step, float mu, int stepA,
                                                 float muA) {
+    constexpr int CH = 8;
     float2* __restrict__ acc = a.dft_acc + (int64_t)s * a.dft_nf * a.nphys + pi;
     const float2* __restrict__ tw = a.dft_tw + (int64_t)step * a.dft_nf;
     const float2* __restrict__ twA = a.dft_tw + (int64_t)(stepA < 0 ? 0 : stepA) * a.dft_nf;
-    for (int m = 0; m < a.dft_nf; ++m) {
-        float2 v = acc[(int64_t)m * a.nphys];
-        if (stepA >= 0) {
-            v.x = fmaf(muA, twA[m].x, v.x);
-            v.y = fmaf(muA, twA[m].y, v.y);
+    for (int m0 = 0; m0 < a.dft_nf; m0 += CH) {
+        float2 v[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k)
+            if (m0 + k < a.dft_nf) v[k] = acc[(int64_t)(m0 + k) * a.nphys];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            if (m0 + k < a.dft_nf) {
+                if (stepA >= 0) {
+                    v[k].x = fmaf(muA, twA[m0 + k].x, v[k].x);
+                    v[k].y = fmaf(muA, twA[m0 + k].y, v[k].y);
+                }
+                v[k].x = fmaf(mu, tw[m0 + k].x, v[k].x);
+                v[k].y = fmaf(mu, tw[m0 + k].y, v[k].y);
+            }
         }
-        v.x = fmaf(mu, tw[m].x, v.x);
-        v.y = fmaf(mu, tw[m].y, v.y);
-        acc[(int64_t)m * a.nphys] = v;
+#pragma unroll
+        for (int k = 0; k < CH; ++k)
+            if (m0 + k < a.dft_nf) acc[(int64_t)(m0 + k) * a.nphys] = v[k];
     }
 }
 

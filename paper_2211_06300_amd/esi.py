@@ -81,7 +81,7 @@ EXPORTS = ["esi_plan_create", "esi_plan_set_model", "esi_plan_destroy", "esi_las
 # time-step kernel variants (bit set of fused work), as in include/esi.h
 K_FLAGS = {1: "SRC_POINT", 2: "SRC_DENSE", 4: "CG_FUSE", 8: "INJ", 16: "GATHER", 32: "OUT",
            64: "NORMAL", 128: "PENALTY", 256: "STORE", 512: "CORR", 1024: "SRC_REC",
-           32768: "TWO_STEP"}
+           2048: "SCALE", 4096: "DTFT_SRC", 8192: "DTFT_ACC", 32768: "TWO_STEP"}
 
 
 def load_library(path: str = LIB_PATH):
