@@ -387,6 +387,24 @@ esi_status_t esi_dtft_gradient(esi_plan_t plan, int32_t shot0, int32_t nshots, c
                                float* grad_m);
 
 /*
+ * Data-space solution of the normal equation (Sec. 5.1, eq. (vd), eq. (wv),
+ * eq. (q): the Sherman-Morrison-Woodbury route), 2D plans, beta > 0:
+ *   CG (Algorithm 1, per shot, FP64 dots) on (beta I + S W^{-1} S^T) w = v,
+ *   v = S W^{-1} S^T d, with W = B^T B of the plan (I for ESI_WEIGHT_IDENTITY);
+ *   then, when q != NULL, q = (beta W)^{-1} S^T (d - w).
+ * An application of S W^{-1} S^T is an adjoint pass that stores the adjoint
+ * field (plan scratch, nshots * nt * phys floats) and a forward pass with that
+ * field times W^{-1} as its source.  For WRI pass d - S f (esi_data_residual).
+ * d, w: device data of the shots (layout of esi_forward's data); w receives
+ * the synthetic data.  q: device [nshots][nt][phys] or NULL.  work: device,
+ * 3 data vectors.  rep as esi_cg_solve (residuals of the data-space system).
+ * ESI_ERR_ARG for a 3D plan, beta <= 0, shots without receivers, or null
+ * pointers; ESI_ERR_BREAKDOWN / ESI_ERR_NONFINITE as esi_cg_solve.
+ */
+esi_status_t esi_ds_cg_solve(esi_plan_t plan, int32_t shot0, int32_t nshots, const float* d, float* w,
+                             float* q, float* work, int32_t max_iter, double rtol, esi_cg_report_t* rep);
+
+/*
  * Chain rule from m = 1/v^2 to v: grad_v = -2 grad_m / v^3 on the physical
  * grid (device [phys] each; grad_v may alias grad_m).
  */

@@ -77,6 +77,11 @@ struct Plan {
     std::vector<double> dft_freqs;
     float2* dft_tw = nullptr;
     double* dft_C = nullptr;
+    // data-space solver scratch: adjoint field [nshots][nt][phys], W^{-1}
+    // [nshots][phys], data segment offsets [nshots + 1]
+    float* ds_mu = nullptr; int64_t ds_mu_cap = 0;
+    float* ds_winv = nullptr; int64_t ds_winv_cap = 0;
+    int64_t* ds_seg = nullptr; int64_t ds_seg_cap = 0;
     int nzp = 0, nyp = 1, nxp = 0;       // padded grid
     int ZS = 0, YS = 1, XS = 0;          // storage grid (padded + zero ghost halo)
     int64_t fsize = 0;                   // floats per stored field (one shot)
@@ -268,7 +273,8 @@ enum : unsigned {
     F_CORR = 1u << 9,        // gacc += mu^j * store slot (adjoint)
     F_SRC_REC = 1u << 10,    // src_rec[s][j] = mu^j at the shot's source cell (adjoint)
     F_SCALE = 1u << 11,      // with F_CG_FUSE: the new direction is s r + beta p (flexible CG);
-                             // p_new . r accumulates into the (shot, tile) partials
+                             // p_new . r accumulates into the (shot, tile) partials;
+                             // with F_SRC_DENSE: the dense source times the cell scale cg_s
     F_DTFT_SRC = 1u << 12,   // dense source from frequency slices (inverse DTFT on the fly)
     F_DTFT_ACC = 1u << 13,   // accumulate the DTFT of the output mu^j (adjoint)
 };

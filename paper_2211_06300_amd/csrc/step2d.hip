@@ -305,6 +305,11 @@ __global__ __launch_bounds__(256, ESI_MINW) void k_step2d(const StepArgs a) {
         const float* __restrict__ q = a.dsrc + vbase;
 #pragma unroll
         for (int i = 0; i < RZ; ++i) qv[i] = ph[i] ? at(q, pi[i]) : 0.f;
+        if constexpr ((FL & F_SCALE) != 0) {   // cell-scaled dense source
+            const float* __restrict__ sc = a.cg_s + (int64_t)s * a.nphys;
+#pragma unroll
+            for (int i = 0; i < RZ; ++i) qv[i] = qv[i] * at(sc, pi[i]);
+        }
     }
     if constexpr ((FL & F_DTFT_SRC) != 0) dtft_source<RZ>(a, s, a.step, pi, ph, qv);
     double pr_acc = 0.0;   // p_new . r partial (F_SCALE)
@@ -531,6 +536,11 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
         const float* __restrict__ q = a.dsrc + vA;
 #pragma unroll
         for (int i = 0; i < A_RZ; ++i) qA[i] = phA[i] ? at(q, piA[i]) : 0.f;
+        if constexpr ((FL & F_SCALE) != 0) {
+            const float* __restrict__ sc = a.cg_s + (int64_t)s * a.nphys;
+#pragma unroll
+            for (int i = 0; i < A_RZ; ++i) qA[i] = qA[i] * at(sc, piA[i]);
+        }
     }
     if constexpr ((FL & F_DTFT_SRC) != 0) dtft_source<A_RZ>(a, s, tA, piA, phA, qA);
     float alp = 0.f, bet = 0.f;
@@ -705,6 +715,11 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
         const float* __restrict__ q = a.dsrc + vB;
 #pragma unroll
         for (int i = 0; i < B_RZ; ++i) qv[i] = ph[i] ? at(q, pi[i]) : 0.f;
+        if constexpr ((FL & F_SCALE) != 0) {
+            const float* __restrict__ sc = a.cg_s + (int64_t)s * a.nphys;
+#pragma unroll
+            for (int i = 0; i < B_RZ; ++i) qv[i] = qv[i] * at(sc, pi[i]);
+        }
     }
     if constexpr ((FL & F_DTFT_SRC) != 0) dtft_source<B_RZ>(a, s, tB, pi, ph, qv);
     if constexpr ((FL & F_CG_FUSE) != 0) {
@@ -841,6 +856,7 @@ esi_status_t dispatch2d(Plan* P, unsigned flags, const StepArgs& a) {
         ESI_CASE(F_CG_FUSE | F_GATHER)
         ESI_CASE(F_CG_FUSE | F_GATHER | F_SCALE)
         ESI_CASE(F_DTFT_SRC | F_GATHER)
+        ESI_CASE(F_SRC_DENSE | F_SCALE | F_GATHER)
         ESI_CASE(F_DTFT_SRC | F_PENALTY)
         ESI_CASE(F_INJ | F_DTFT_ACC)
         ESI_CASE(F_INJ | F_OUT)

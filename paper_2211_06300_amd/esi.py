@@ -77,7 +77,7 @@ EXPORTS = ["esi_plan_create", "esi_plan_set_model", "esi_plan_destroy", "esi_las
            "esi_fpcg_solve", "esi_precond_features", "esi_unet_loss_weights", "esi_plan_autotune",
            "esi_plan_set_weight", "esi_data_residual", "esi_wri_gradient", "esi_plan_set_beta",
            "esi_invert", "esi_dtft_set_freqs", "esi_dtft_normal_apply", "esi_dtft_rhs", "esi_dtft_cg_solve",
-           "esi_dtft_to_time", "esi_dtft_gradient"]
+           "esi_dtft_to_time", "esi_dtft_gradient", "esi_ds_cg_solve"]
 # time-step kernel variants (bit set of fused work), as in include/esi.h
 K_FLAGS = {1: "SRC_POINT", 2: "SRC_DENSE", 4: "CG_FUSE", 8: "INJ", 16: "GATHER", 32: "OUT",
            64: "NORMAL", 128: "PENALTY", 256: "STORE", 512: "CORR", 1024: "SRC_REC",
@@ -112,6 +112,7 @@ def load_library(path: str = LIB_PATH):
     L.esi_dtft_cg_solve.argtypes = [vp, i32, i32, vp, vp, vp, i32, dbl, ctypes.POINTER(_CgReport)]
     L.esi_dtft_to_time.argtypes = [vp, i32, i32, vp, vp]
     L.esi_dtft_gradient.argtypes = [vp, i32, i32, vp, vp]
+    L.esi_ds_cg_solve.argtypes = [vp, i32, i32, vp, vp, vp, vp, i32, dbl, ctypes.POINTER(_CgReport)]
     L.esi_invert.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(_InvertOpts),
                              ctypes.POINTER(_InvertReport)]
     L.esi_data_residual.argtypes = [vp, i32, i32, vp, vp, vp]
@@ -334,6 +335,24 @@ class Plan:
         _check(self._lib.esi_dtft_gradient(self._h, shot0, nshots, _f32(x, self.dtft_shape(nshots), "x"),
                                            _f32(grad_m, self.phys_shape, "grad_m")))
         return grad_m
+
+    def ds_cg_solve(self, d, max_iter, rtol=0.0, shot0=0, nshots=None, want_q=True, w=None, q=None, work=None):
+        """esi_ds_cg_solve: data-space CG; returns (w, q or None, report)."""
+        shot0, nshots = self._range(shot0, nshots)
+        dsh = self.data_shape(shot0, nshots)
+        w = self.new_data(shot0, nshots) if w is None else w
+        if want_q and q is None:
+            q = self.new_vec(nshots)
+        work = torch.empty((3 * int(np.prod(dsh)),), dtype=torch.float32, device=self.device) if work is None else work
+        hist = np.zeros((nshots, max_iter + 1))
+        iters = np.zeros(nshots, dtype=np.int32)
+        rep = _CgReport(0, iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                        hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, None, None, None)
+        _check(self._lib.esi_ds_cg_solve(self._h, shot0, nshots, _f32(d, dsh, "d"), _f32(w, dsh, "w"),
+                                         None if q is None else _f32(q, self.vec_shape(nshots), "q"),
+                                         _f32(work, (3 * int(np.prod(dsh)),), "work"), int(max_iter), float(rtol),
+                                         ctypes.byref(rep)))
+        return w, q, {"iters": rep.iters, "shot_iters": iters, "res_hist": hist}
 
     def set_beta(self, beta: float):
         _check(self._lib.esi_plan_set_beta(self._h, float(beta)))
