@@ -356,6 +356,44 @@ def dtft_run(args, torch, dev):
             "dominant_loop": {"variant": name, "launches": rec["launches"], "ms": round(rec["ms"], 1)}}
 
 
+def dataspace_run(args, torch, dev):
+    """The data-space solver on one group of shots of the single-solve
+    workload: CG on (beta I + S W^-1 S^T) w = v (cg_iters iterations) and the
+    extended source q = (beta W)^-1 S^T (d - w)."""
+    from paper_2211_06300_amd import esi, inputs
+    cfg = inputs.cfg_single_solve(nshots=args.shots, nt=args.nt)
+    ns = min(args.group, cfg.nshots)
+    npad = (cfg.nz + 2 * cfg.nb) * (cfg.nx + 2 * cfg.nb)
+    plan_true = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_true).to(dev))
+    wav = torch.from_numpy(np.tile(cfg.wavelet, (ns, 1))).to(dev)
+    d_obs = plan_true.forward(wav, esi.SRC_POINT, shot0=0, nshots=ns)
+    plan_true.close()
+    plan = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_start).to(dev))
+    plan.autotune(nshots=ns)
+    q = plan.new_vec(ns)
+    plan.ds_cg_solve(d_obs, 1, nshots=ns, q=q)                 # warm-up: every kernel once
+    torch.cuda.synchronize()
+    plan.profile(True)
+    t0 = time.perf_counter()
+    w, q, rep = plan.ds_cg_solve(d_obs, args.cg_iters, nshots=ns, q=q)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = plan.profile_read()
+    plan.profile(False)
+    plan.close()
+    props = 2 * (args.cg_iters + 1) + 1
+    name, rec = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    dl = int(d_obs.numel())
+    return {"workload": "dataspace-" + cfg.name, "shots": ns, "nt": cfg.nt, "beta": cfg.beta,
+            "cg_iters": args.cg_iters, "propagations_per_shot": props, "seconds": round(wall, 3),
+            "gpts_per_s": round(ns * props * npad * cfg.nt / wall / 1e9, 2),
+            "cg_final_rel_residual_max": float(np.max(rep["res_hist"][:, -1])),
+            "cg_vectors_gb": round(4 * dl * 4 / 1e9, 3),
+            "adjoint_field_buffer_gb": round(ns * cfg.nt * cfg.nz * cfg.nx * 4 / 1e9, 1),
+            "time_domain_cg_vectors_gb": round(4 * ns * cfg.nt * cfg.nz * cfg.nx * 4 / 1e9, 1),
+            "dominant_loop": {"variant": name, "launches": rec["launches"], "ms": round(rec["ms"], 1)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -377,6 +415,7 @@ def main():
     ap.add_argument("--no-wri", action="store_true", help="skip the WRI run on the single-solve workload")
     ap.add_argument("--no-invert", action="store_true", help="skip the outer-loop (Algorithm 2) run")
     ap.add_argument("--no-dtft", action="store_true", help="skip the DTFT-variant run")
+    ap.add_argument("--no-dataspace", action="store_true", help="skip the data-space solver run")
     ap.add_argument("--dtft-nf", type=int, default=8)
     ap.add_argument("--invert-iters", type=int, default=2)
     ap.add_argument("--invert-cg", type=int, default=30)
@@ -515,6 +554,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_dtft:
         out["dtft"] = dtft_run(args, torch, dev)
+        torch.cuda.empty_cache()
+    if not args.no_dataspace:
+        out["dataspace"] = dataspace_run(args, torch, dev)
         torch.cuda.empty_cache()
     if not args.no_cpu:
         log("timing the oracle on the host cores")
