@@ -297,15 +297,17 @@ def invert_run(args, torch, dev):
     plan.autotune(nshots=ns, p=work[0], Ap=work[1])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    inner = {"fcg": esi.INNER_FCG_SCALE, "ds": esi.INNER_DATASPACE, "cg": esi.INNER_CG}[args.invert_inner]
     rep = plan.invert(d_obs, vel, mask=mask, nshots=ns, x=x, work=work, outer_iters=args.invert_iters,
-                      cg_iters=args.invert_cg, first_step=0.02, v_min=1400.0, v_max=5000.0,
-                      inner=esi.INNER_FCG_SCALE)
+                      cg_iters=args.invert_cg, first_step=0.02, v_min=1400.0, v_max=5000.0, inner=inner)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     plan.close()
-    props = 2 * args.invert_cg + 2                   # per shot and evaluation
+    props = 2 * args.invert_cg + (4 if args.invert_inner == "ds" else 2)   # per shot and evaluation
     return {"workload": "invert-" + cfg.name, "shots": ns, "nt": cfg.nt, "beta": args.invert_beta,
-            "outer_iters": rep["outer_done"], "inner": "fcg-analytic-scale", "inner_iters": args.invert_cg,
+            "outer_iters": rep["outer_done"], "inner": {"fcg": "fcg-analytic-scale", "ds": "data-space-cg",
+                                                         "cg": "cg"}[args.invert_inner],
+            "inner_iters": args.invert_cg,
             "evals": rep["evals"], "line_search_trials": rep["trials"], "J": [round(j, 6) for j in rep["J"]],
             "data_misfit": [round(e, 6) for e in rep["misfit"]], "status": rep["status"],
             "seconds": round(wall, 3), "seconds_per_eval": round(wall / max(rep["evals"], 1), 3),
@@ -380,6 +382,10 @@ def dataspace_run(args, torch, dev):
     wall = time.perf_counter() - t0
     prof = plan.profile_read()
     plan.profile(False)
+    # how well the extended source explains the data: ||S q - d|| / ||d|| (untimed)
+    d_q = plan.forward(q, esi.SRC_DENSE, nshots=ns)
+    q_misfit = float(torch.linalg.vector_norm((d_q - d_obs).double()) / torch.linalg.vector_norm(d_obs.double()))
+    w_misfit = float(torch.linalg.vector_norm((w - d_obs).double()) / torch.linalg.vector_norm(d_obs.double()))
     plan.close()
     props = 2 * (args.cg_iters + 1) + 1
     name, rec = max(prof.items(), key=lambda kv: kv[1]["ms"])
@@ -388,6 +394,7 @@ def dataspace_run(args, torch, dev):
             "cg_iters": args.cg_iters, "propagations_per_shot": props, "seconds": round(wall, 3),
             "gpts_per_s": round(ns * props * npad * cfg.nt / wall / 1e9, 2),
             "cg_final_rel_residual_max": float(np.max(rep["res_hist"][:, -1])),
+            "data_misfit_w": round(w_misfit, 6), "data_misfit_Sq": round(q_misfit, 6),
             "cg_vectors_gb": round(4 * dl * 4 / 1e9, 3),
             "adjoint_field_buffer_gb": round(ns * cfg.nt * cfg.nz * cfg.nx * 4 / 1e9, 1),
             "time_domain_cg_vectors_gb": round(4 * ns * cfg.nt * cfg.nz * cfg.nx * 4 / 1e9, 1),
@@ -420,6 +427,7 @@ def main():
     ap.add_argument("--invert-iters", type=int, default=2)
     ap.add_argument("--invert-cg", type=int, default=30)
     ap.add_argument("--invert-beta", type=float, default=100.0)
+    ap.add_argument("--invert-inner", choices=["fcg", "ds", "cg"], default="fcg")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="also run one elementwise copy of this many MiB (counter calibration)")
     args = ap.parse_args()

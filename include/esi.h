@@ -305,13 +305,14 @@ esi_status_t esi_plan_set_beta(esi_plan_t plan, double beta);
  * of esi_fpcg_solve preconditioned by the analytic cell scale
  * 1 / (beta B^2 + inner_gamma), recomputed whenever beta changes
  * (ESI_INNER_FCG_SCALE): the inner loop then converges in far fewer
- * iterations, as Sec. 3 asks of it.
+ * iterations, as Sec. 3 asks of it; or the data-space CG of esi_ds_cg_solve
+ * (ESI_INNER_DATASPACE, cg_iters iterations of the data-space system).
  * rep (optional) receives the counts and, through its non-NULL host arrays,
  * the histories.  Returns ESI_ERR_ARG for bad options; a failed line search is
  * not an error (rep->status = 1, vel = the last accepted model).
  */
 enum { ESI_BETA_FIXED = 0, ESI_BETA_DISCREPANCY = 1 };
-enum { ESI_INNER_CG = 0, ESI_INNER_FCG_SCALE = 1 };
+enum { ESI_INNER_CG = 0, ESI_INNER_FCG_SCALE = 1, ESI_INNER_DATASPACE = 2 };
 typedef struct {
     int32_t outer_iters;   /* N_outer >= 0 */
     int32_t cg_iters;      /* inner CG iterations >= 1 */
@@ -327,7 +328,8 @@ typedef struct {
     double beta_factor;    /* > 1 */
     int32_t beta_tries;    /* >= 0 */
     int32_t inner;         /* ESI_INNER_CG: Algorithm 1; ESI_INNER_FCG_SCALE: esi_fpcg_solve with
-                              the cell scale 1 / (beta B^2 + inner_gamma) (ESI only) */
+                              the cell scale 1 / (beta B^2 + inner_gamma) (ESI only);
+                              ESI_INNER_DATASPACE: esi_ds_cg_solve (2D, beta > 0) */
     double inner_gamma;    /* > 0 */
 } esi_invert_opts_t;
 typedef struct {

@@ -35,7 +35,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import core
+from . import core, dataspace
 
 
 @dataclass
@@ -155,7 +155,7 @@ def esi_objective(g: core.Grid, shots, cg_iters: int, cg_rtol: float = 0.0, eta_
 
     inner "cg" solves by Algorithm 1; "fcg" (ESI) by flexible CG (``core.fpcg``)
     preconditioned by the cell scale 1 / (beta B^2 + gamma), with its fallback to
-    plain CG.
+    plain CG; "ds" by the data-space CG of ``dataspace.cg`` (Sec. 5.1).
 
     shots: list of (src_pos, rec, d_obs)."""
     dd = sum(core.dot(d, d) for _, _, d in shots)
@@ -167,7 +167,9 @@ def esi_objective(g: core.Grid, shots, cg_iters: int, cg_rtol: float = 0.0, eta_
         for s, (src, rec, d) in enumerate(shots):
             if wavelet is None:
                 w2 = core.annihilator_sq(g, src, eps)
-                if inner == "fcg":
+                if inner == "ds":
+                    q = dataspace.cg(mod, src, rec, d, beta, cg_iters, cg_rtol, eps=eps)[1]
+                elif inner == "fcg":
                     s0 = 1.0 / (beta * w2 + gamma)
                     q = core.fpcg(lambda p: core.normal_apply(mod, rec, w2, beta, p), core.adjoint(mod, rec, d),
                                   lambda r: s0[None] * r, cg_iters, cg_rtol).x
@@ -178,7 +180,11 @@ def esi_objective(g: core.Grid, shots, cg_iters: int, cg_rtol: float = 0.0, eta_
                 grad += core.gradient_penalty(mod, q, w2, beta)
             else:
                 f = wavelet[s]
-                q = core.wri_cg(mod, f, src, rec, d, beta, cg_iters, cg_rtol).x
+                if inner == "ds":
+                    d_f = core.forward(mod, f, rec, src_pos=src)
+                    q = dataspace.cg(mod, src, rec, d - d_f, beta, cg_iters, cg_rtol, w2=np.ones(g.phys_shape))[1]
+                else:
+                    q = core.wri_cg(mod, f, src, rec, d, beta, cg_iters, cg_rtol).x
                 d_syn = core.forward(mod, core.with_point_source(g, q, f, src), rec)
                 J += 0.5 * core.dot(d_syn - d, d_syn - d) + 0.5 * beta * core.dot(q, q)
                 grad += core.gradient_wri_penalty(mod, f, src, q, beta)

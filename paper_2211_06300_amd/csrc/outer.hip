@@ -154,6 +154,7 @@ struct Outer {
     float* dsyn;          // synthetic data of a group
     float* dres;          // WRI right-hand side data of a group
     float* scale;         // inner FCG cell scale of a group [G][phys]
+    float* dw;            // data-space inner solve: synthetic data of a group
     double* pen;          // [G] per-shot penalty sums
     double dd = 0.0;      // ||d_obs||^2
 
@@ -222,7 +223,9 @@ struct Outer {
             }
             esi_cg_report_t rep;
             std::memset(&rep, 0, sizeof rep);
-            if (o->inner == ESI_INNER_FCG_SCALE) {
+            if (o->inner == ESI_INNER_DATASPACE) {
+                ESI_TRY(esi_ds_cg_solve(plan, s0, k, rhs, dw, x, work, o->cg_iters, o->cg_rtol, &rep));
+            } else if (o->inner == ESI_INNER_FCG_SCALE) {
                 hipLaunchKernelGGL(k_cell_scale, dim3(grid_for((int64_t)k * n)), dim3(NT), 0, P->stream, P->d_src,
                                    s0, k, P->nz, P->nx, beta, P->b_eps, o->inner_gamma, scale);
                 ESI_HIP_TRY(hipGetLastError());
@@ -259,7 +262,8 @@ esi_status_t check_opts(const esi_invert_opts_t* o, int ns) {
         o->lbfgs_mem < 1 || o->ls_max < 1 || !(o->armijo_c1 > 0 && o->armijo_c1 < 1) || !(o->first_step > 0) ||
         !(o->v_min > 0 && o->v_max > o->v_min) || (o->beta_rule != ESI_BETA_FIXED && o->beta_rule != ESI_BETA_DISCREPANCY) ||
         !(o->misfit_lo >= 0 && o->misfit_hi >= o->misfit_lo) || !(o->beta_factor > 1) || o->beta_tries < 0 ||
-        (o->inner != ESI_INNER_CG && o->inner != ESI_INNER_FCG_SCALE) || !(o->inner_gamma > 0))
+        (o->inner != ESI_INNER_CG && o->inner != ESI_INNER_FCG_SCALE && o->inner != ESI_INNER_DATASPACE) ||
+        !(o->inner_gamma > 0))
         return fail(ESI_ERR_ARG, "invalid outer-loop options");
     return ESI_OK;
 }
@@ -306,6 +310,8 @@ extern "C" esi_status_t esi_invert(esi_plan_t plan, int32_t shot0, int32_t ns, c
     ESI_TRY(sc.alloc(&S.red, RB)); ESI_TRY(sc.alloc(&S.vt, n)); ESI_TRY(sc.alloc(&S.gm, n));
     ESI_TRY(sc.alloc(&S.dsyn, gdl)); ESI_TRY(sc.alloc(&S.dres, wavelet ? gdl : 1)); ESI_TRY(sc.alloc(&S.pen, S.G));
     ESI_TRY(sc.alloc(&S.scale, o.inner == ESI_INNER_FCG_SCALE ? (int64_t)S.G * n : 1));
+    ESI_TRY(sc.alloc(&S.dw, o.inner == ESI_INNER_DATASPACE ? gdl : 1));
+    if (o.inner == ESI_INNER_DATASPACE && P->ndim != 2) return fail(ESI_ERR_ARG, "the data-space inner solver is 2D");
 
     const double lo = 1.0 / (o.v_max * o.v_max), hi = 1.0 / (o.v_min * o.v_min);
     hipLaunchKernelGGL(k_m_from_vel, dim3(grid_for(n)), dim3(NT), 0, P->stream, vel, lo, hi, m, n);

@@ -19,7 +19,7 @@ SRC_POINT, SRC_DENSE = 0, 1
 GRAD_PENALTY, GRAD_ADJOINT, GRAD_SEED, GRAD_SEED_REUSE = 0, 1, 2, 3
 WEIGHT_ANNIHILATOR, WEIGHT_IDENTITY = 0, 1
 BETA_FIXED, BETA_DISCREPANCY = 0, 1
-INNER_CG, INNER_FCG_SCALE = 0, 1
+INNER_CG, INNER_FCG_SCALE, INNER_DATASPACE = 0, 1, 2
 _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_SHAPE", 3: "ERR_CFL", 4: "ERR_OOM", 5: "ERR_HIP",
            6: "ERR_BREAKDOWN", 7: "ERR_NONFINITE"}
 

@@ -137,6 +137,19 @@ def test_scaled_inner_solver_matches_oracle(esi):
     assert _rel(m - m0, ref.m - m0) < 1e-3
 
 
+def test_dataspace_inner_solver_matches_oracle(esi):
+    """Inner solves by the data-space CG (Sec. 5.1): two outer iterations."""
+    cfg, g, eta, d_obs, mask = _case()
+    opts = dict(outer_iters=2, first_step=0.03)
+    vel, rep = _run_gpu(esi, cfg, d_obs, mask, cg_iters=8, inner=esi.INNER_DATASPACE, **opts)
+    ref, m0 = _run_oracle(cfg, g, eta, d_obs, mask, inner="ds", **opts)
+    assert rep["status"] == 0 and rep["trials"] == ref.trials
+    np.testing.assert_allclose(rep["J"], ref.J, rtol=1e-4)
+    np.testing.assert_allclose(rep["misfit"], ref.misfit, rtol=1e-4)
+    m = 1.0 / vel.astype(np.float64) ** 2
+    assert _rel(m - m0, ref.m - m0) < 1e-3
+
+
 def test_outer_loop_deterministic_and_grouping(esi):
     """Two runs give the same bits; solving the shots one at a time gives the
     same result to rounding."""
