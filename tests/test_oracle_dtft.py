@@ -125,3 +125,23 @@ def test_dtft_cg_and_gradient_shapes():
     gp = dtft.gradient_penalty(m, res.x, w2, cfg.beta, freqs)
     ref = core.gradient_penalty(m, dtft.idtft(res.x, freqs, g.dt, g.nt), w2, cfg.beta)
     assert np.array_equal(gp, ref)
+
+
+def test_rhs_dense():
+    """F S^T G F d formed with the dense S and the DTFT as a real matrix."""
+    cfg, g, m = _tiny(nt=30)
+    rec = cfg.shot_rec(0)
+    freqs = np.array([20.0, 45.0])
+    rng = np.random.default_rng(6)
+    d = rng.standard_normal((g.nt, len(rec)))
+    b = dtft.rhs(m, rec, d, freqs)
+    nin = g.nt * g.nz * g.nx
+    S = dense.dense_matrix(lambda q: core.forward(m, q, rec), nin, (g.nt, g.nz, g.nx))
+    E = dtft.twiddles(freqs, g.nt, g.dt)                     # [nt, nf]
+    Fr = np.concatenate([E.real.T, E.imag.T])                # [2 nf, nt]
+    band = Fr.T @ Fr / g.nt                                  # G F on one trace: nt x nt
+    d_band = band @ d                                        # every receiver trace
+    St_d = (S.T @ d_band.ravel()).reshape(g.nt, g.nz * g.nx)
+    bv = Fr @ St_d                                           # [2 nf, cells]
+    nf = len(freqs)
+    assert _rel(bv[:nf] + 1j * bv[nf:], b.reshape(nf, -1)) < 1e-12
