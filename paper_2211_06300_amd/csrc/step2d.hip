@@ -469,11 +469,19 @@ static_assert(A_W == 64 && A_H % 4 == 0 && U0H % 4 == 0, "two-step tile geometry
 
 template <unsigned FL>
 __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) {
-    __shared__ float U0[U0H * U0W];                     // u^{tA}: tile + 8
-    __shared__ float U1[A_H * A_W];                     // u after the first step: tile + 4
-    __shared__ float D1[T2Z * T2W];                     // d after the first step: tile
-    __shared__ float sinj[(FL & F_INJ) ? A_H * A_W : 1];
+    // LDS: u^{tA} on the tile + 8 (dead after the first step, then holding the
+    // second step's injection), u after the first step on the tile + 4, and
+    // one buffer that holds the first step's injection until every lane has
+    // read it, then d after the first step on the tile.  Sharing keeps an
+    // injecting variant at 34 KB, four workgroups per CU.
+    __shared__ float U0[U0H * U0W];
+    __shared__ float U1[A_H * A_W];
+    __shared__ float SX[(FL & F_INJ) ? A_H * A_W : T2Z * T2W];
     __shared__ double sred[4];
+    float* const D1 = SX;
+    float* const sinjA = SX;
+    float* const sinjB = U0;
+    static_assert(U0H * U0W >= A_H * A_W && A_H * A_W >= T2Z * T2W, "two-step LDS sharing");
 
     int s, t;
     work_item(a, xcd_remap(blockIdx.x, gridDim.x), &s, &t);
@@ -583,13 +591,13 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
         ibeg = ip[t];
         iend = ip[t + 1];
         if (iend > ibeg) {
-            for (int i = tid; i < A_H * A_W; i += 256) sinj[i] = 0.f;
+            for (int i = tid; i < A_H * A_W; i += 256) sinjA[i] = 0.f;
             __syncthreads();
             const float* dj = a.inj_data + doff + (int64_t)tA * nrec_s;
             for (int e = ibeg + tid; e < iend; e += 256) {
                 float v = 0.f;
                 for (int k = a.inj2_rptr[e]; k < a.inj2_rptr[e + 1]; ++k) v += dj[a.inj2_rid[k]];
-                sinj[a.inj2_cell[e]] = v;
+                sinjA[a.inj2_cell[e]] = v;
             }
         }
     }
@@ -621,6 +629,16 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
         if (lz >= 0 && lz < T2Z && lx >= 0 && lx < T2W) srcB = lz * T2W + lx;
     }
 
+    // the first step's injection into registers: D1 takes its buffer below
+    float injA[(FL & F_INJ) ? A_RZ : 1];
+    if constexpr ((FL & F_INJ) != 0) {
+        if (iend > ibeg) {   // uniform over the workgroup
+#pragma unroll
+            for (int i = 0; i < A_RZ; ++i) injA[i] = sinjA[(zra + i) * A_W + lane];
+            __syncthreads();
+        }
+    }
+
     // ---- first step
     float colA[A_RZ + 2 * HALO];
 #pragma unroll
@@ -638,7 +656,7 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
             if (zr * A_W + lane == srcA) q += a.wavelet[(int64_t)s * a.nt + tA];
         }
         if constexpr ((FL & F_INJ) != 0) {
-            if (iend > ibeg) q += sinj[zr * A_W + lane];
+            if (iend > ibeg) q += injA[i];
         }
         const float lq = fmaf(a.dx2, q, lap);
         const float dn = incr(cA[i], lq, dA[i], kA[i]);
@@ -675,14 +693,14 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
         }
     }
     if constexpr ((FL & F_INJ) != 0) {
-        if (iend > ibeg) {
-            for (int i = tid; i < A_H * A_W; i += 256) sinj[i] = 0.f;
+        if (iend > ibeg) {   // U0 is dead since the barrier after the first step
+            for (int i = tid; i < A_H * A_W; i += 256) sinjB[i] = 0.f;
             __syncthreads();
             const float* dj = a.inj_data + doff + (int64_t)tB * nrec_s;
             for (int e = ibeg + tid; e < iend; e += 256) {
                 float v = 0.f;
                 for (int k = a.inj2_rptr[e]; k < a.inj2_rptr[e + 1]; ++k) v += dj[a.inj2_rid[k]];
-                sinj[a.inj2_cell[e]] = v;
+                sinjB[a.inj2_cell[e]] = v;
             }
             __syncthreads();
         }
@@ -760,7 +778,7 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
             if (lane_on && zl * T2W + lc == srcB) q += a.wavelet[(int64_t)s * a.nt + tB];
         }
         if constexpr ((FL & F_INJ) != 0) {
-            if (iend > ibeg) q += sinj[(zl + HALO) * A_W + lc + HALO];
+            if (iend > ibeg) q += sinjB[(zl + HALO) * A_W + lc + HALO];
         }
         const float kap = kxv + kzv[i];
         const float lq = fmaf(a.dx2, q, lap);
