@@ -41,6 +41,7 @@ DENSE_BYTES = {2: 4, 4: 20, 32: 4, 64: 8, 128: 8, 256: 4, 512: 12}
 
 
 TWO_STEP = 1 << 15
+RUPD = 1 << 14
 
 # HBM counter summary of the 2D time-step kernels (two rocprofv3 --pmc passes,
 # FETCH_SIZE and WRITE_SIZE, calibrated on a copy of known size)
@@ -90,6 +91,8 @@ def bytes_per_shot_launch(flags: int, npad: int, nphys: int) -> int:
     for bit, per in DENSE_BYTES.items():
         if flags & bit:
             b += per * nphys
+    if flags & RUPD and flags & 64:   # the fused residual update: r read and written, no N p written
+        b += 4 * nphys
     return b * (2 if flags & TWO_STEP else 1)
 
 
@@ -412,6 +415,8 @@ def main():
     ap.add_argument("--nt", type=int, default=2000)
     ap.add_argument("--cpu-nt", type=int, default=1000, help="steps in the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-rfuse", action="store_true",
+                    help="CG with the residual update as a separate pass (default: fused into the adjoint)")
     ap.add_argument("--no-solve", action="store_true", help="skip the plain vs learned CG comparison")
     ap.add_argument("--solve-seed", type=int, default=6000)
     ap.add_argument("--solve-shots", type=int, default=8)
@@ -462,6 +467,7 @@ def main():
     plan_true.close()
     del plan_true, wav
     plan = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_start).to(dev))
+    plan.set_cg_rfuse(not args.no_rfuse)
     x = plan.new_vec(G)
     work = torch.empty((3, *plan.vec_shape(G)), dtype=torch.float32, device=dev)
     grad = torch.zeros(plan.phys_shape, dtype=torch.float32, device=dev)
@@ -533,6 +539,7 @@ def main():
         "config": {"workload": cfg.name, "grid": f"{cfg.nx}x{cfg.nz}", "nb": cfg.nb,
                    "nt": cfg.nt, "shots": cfg.nshots, "shot_group": G,
                    "cg_iters": args.cg_iters, "beta": cfg.beta,
+                   "cg_residual_update": "separate pass" if args.no_rfuse else "fused into the adjoint",
                    "propagations_per_shot": props_per_shot,
                    "steps_per_launch": {"forward": tuned[0], "adjoint": tuned[1], "chosen_by": "autotuner"}},
         "roofline": {"bound": "hbm",

@@ -263,6 +263,53 @@ esi_status_t do_normal(Plan* P, int shot0, int ns, const float* p, float* Ap, co
     return adjoint_loop(P, b, F_INJ | F_NORMAL, P->ring, &cs, 0, P->nt);
 }
 
+// Iteration k >= 1 of Algorithm 1 (2D) with the residual update fused into
+// the normal operator.  The forward pass forms p_k = r_k + beta p_{k-1} into
+// pnew and x_k = x_{k-1} + alpha p_{k-1}, records S p_k and the partials of
+// beta B^2 p_k . p_k; with p_k . N p_k = ||S p_k||^2 + beta ||B p_k||^2 the
+// step length is known before the adjoint pass, which then takes
+// r_{k+1} = r_k - alpha_k N p_k cell by cell in place, with the partials of
+// ||r_{k+1}||^2.  N p_k is never stored: per step, the adjoint reads r and
+// writes it back instead of writing N p for a separate pass to read.
+esi_status_t do_normal_rupd(Plan* P, int shot0, int ns, const float* p, float* pnew, const TileLists* L,
+                            const int* active, float* r, float* x, double* alpha, const double* beta,
+                            const double* rr, double* pAp, double* rr_new) {
+    const int64_t dl = data_len(P, shot0, ns);
+    ESI_TRY(grow_t(&P->dscr, &P->dscr_cap, std::max<int64_t>(dl, 1), P->stream));
+    ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
+    TileLists *L2f, *L2a;
+    ESI_TRY(t2_lists(P, &L2f, false));
+    ESI_TRY(t2_lists(P, &L2a, true));
+    P->part_stride = std::max({L->tiles, L2f ? L2f->tiles : 0, L2a ? L2a->tiles : 0});
+    ESI_TRY(grow_t(&P->part, &P->part_cap, (int64_t)ns * std::max(P->part_stride, DATA_BLOCKS), P->stream));
+    ESI_TRY(launch_fill_d(P, P->part, (int64_t)ns * P->part_stride));
+    StepArgs a = base_args(P, L, shot0, ns);
+    a.active = active;
+    a.gat_data = P->dscr;
+    a.cg_r = r; a.cg_p = p; a.cg_pn = pnew; a.cg_x = x; a.cg_alpha = alpha; a.cg_beta = beta;
+    a.part = P->part;
+    a.part_stride = P->part_stride;
+    int cs = 0;
+    ESI_TRY(forward_loop(P, a, F_CG_FUSE | F_GATHER | F_RUPD, P->ring, &cs, 0, P->nt));
+    ESI_TRY(launch_final_gather(P, P->ring + (int64_t)cs * P->fsize, RING * P->fsize, P->dscr,
+                                shot0, ns));
+    ESI_TRY(launch_reduce_parts(P, P->part, P->part_stride, ns, pAp));
+    ESI_TRY(launch_cg_alpha_data(P, shot0, ns, P->dscr, active, rr, pAp, rr_new, alpha));
+    ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
+    ESI_TRY(launch_fill_d(P, P->part, (int64_t)ns * P->part_stride));
+    StepArgs b = base_args(P, L, shot0, ns);
+    b.active = active;
+    b.inj_data = P->dscr;
+    b.dp = pnew;
+    b.cg_rw = r;
+    b.cg_alpha = alpha;
+    b.part = P->part;
+    b.part_stride = P->part_stride;
+    cs = 0;
+    ESI_TRY(adjoint_loop(P, b, F_INJ | F_NORMAL | F_RUPD, P->ring, &cs, 0, P->nt));
+    return launch_reduce_parts(P, P->part, P->part_stride, ns, rr_new);
+}
+
 }  // namespace
 }  // namespace esi
 
@@ -338,6 +385,14 @@ struct CgState {
 // The caller swaps p and Ap after every iteration k >= 1.
 esi_status_t cg_iteration(Plan* P, const CgState& c, int k, const float* p, float* Ap) {
     const float* dir = p;
+    if (k >= 1 && P->ndim == 2 && P->cg_rfuse) {
+        ESI_TRY(do_normal_rupd(P, c.shot0, c.ns, p, Ap, c.L, c.active, c.r, c.x, c.alpha, c.beta, c.rr,
+                               c.pAp, c.rr_new));
+        ESI_TRY(launch_cg_control(P, c.rr0, c.rr_new, c.pAp, c.active, c.finish, c.iters, c.status,
+                                  c.hist, c.max_iter + 1, c.ctl, c.rtol, c.max_iter, c.ns));
+        ESI_TRY(launch_cg_beta(P, c.rr_new, c.rr, c.beta, c.ns));
+        return launch_axpy_flag(P, c.x, Ap, c.alpha, c.finish, 1, c.ns, c.len);   // p_k lives in Ap
+    }
     if (k == 0) {
         ESI_TRY(do_normal(P, c.shot0, c.ns, p, Ap, c.L, c.active, false, nullptr, c.r, c.x,
                           c.alpha, c.beta));
@@ -369,7 +424,7 @@ std::vector<uintptr_t> cg_graph_key(Plan* P, const CgState& c) {
             (uintptr_t)std::llround(c.rtol * 1e18), (uintptr_t)c.L, (uintptr_t)c.x,
             (uintptr_t)c.r, (uintptr_t)c.hist, (uintptr_t)P->ring, (uintptr_t)P->dscr,
             (uintptr_t)P->part, (uintptr_t)(P->tb_fwd * 4 + P->tb_adj), (uintptr_t)P->part_stride,
-            (uintptr_t)P->w_identity, beta_bits(P->beta)};
+            (uintptr_t)P->w_identity, beta_bits(P->beta), (uintptr_t)P->cg_rfuse};
 }
 
 void cg_graph_drop(Plan* P) {
@@ -440,6 +495,13 @@ extern "C" esi_status_t esi_plan_set_cg_graph(esi_plan_t plan, int32_t enable) {
     return ESI_OK;
 }
 
+extern "C" esi_status_t esi_plan_set_cg_rfuse(esi_plan_t plan, int32_t enable) {
+    set_error("");
+    if (!plan) return fail(ESI_ERR_ARG, "null plan");
+    ((Plan*)plan)->cg_rfuse = enable != 0;
+    return ESI_OK;
+}
+
 extern "C" esi_status_t esi_cg_solve(esi_plan_t plan, int32_t shot0, int32_t ns,
                                      const float* d_obs, float* x, float* work, int32_t max_iter,
                                      double rtol, esi_cg_report_t* rep) {
@@ -466,6 +528,8 @@ extern "C" esi_status_t esi_cg_solve(esi_plan_t plan, int32_t shot0, int32_t ns,
     c.iters = P->cgi; c.status = P->cgi + P->nshots; c.ctl = P->cgi + 2 * P->nshots;
     ESI_TRY(grow_t(&P->cg_hist, &P->cg_hist_cap, (int64_t)ns * (max_iter + 1), P->stream));
     c.hist = P->cg_hist;
+    // the fused-residual iterations' data partials (sized here, outside any capture)
+    ESI_TRY(grow_t(&P->part, &P->part_cap, (int64_t)ns * DATA_BLOCKS, P->stream));
 
     // b = S^T d (adjoint modelling, Sec. 3); r_0 = b, p_0 = r_0, x_0 = 0
     ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));

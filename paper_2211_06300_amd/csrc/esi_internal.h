@@ -134,6 +134,7 @@ struct Plan {
     // CG iterations captured as graphs (one per parity of the iteration index:
     // the direction and N p buffers trade places every iteration)
     bool cg_graph = false;
+    bool cg_rfuse = true;                // 2D CG: residual update fused into the adjoint pass
     hipStream_t cap_stream = nullptr;    // capture and replay stream
     hipEvent_t cap_ev[2] = {nullptr, nullptr};
     hipGraph_t cg_g[2] = {nullptr, nullptr};
@@ -233,6 +234,7 @@ struct StepArgs {
     float* cg_pn;            // p_new (written; a different buffer from cg_p)
     float* cg_x;
     const float* cg_s;           // F_SCALE: per-shot cell scale [nshots][nphys], z = s r
+    float* cg_rw;                // F_RUPD with F_NORMAL: r, updated in place (adjoint)
     // per-shot apertures (2D): physical columns [win[2 gs], win[2 gs + 1]) of
     // global shot gs, or nullptr for the whole grid; damping table of shot gs
     // at kx + kx_stride * gs; work list of (shot, tile) items gs * tiles + t
@@ -277,6 +279,10 @@ enum : unsigned {
                              // with F_SRC_DENSE: the dense source times the cell scale cg_s
     F_DTFT_SRC = 1u << 12,   // dense source from frequency slices (inverse DTFT on the fly)
     F_DTFT_ACC = 1u << 13,   // accumulate the DTFT of the output mu^j (adjoint)
+    F_RUPD = 1u << 14,       // CG residual update fused into the normal operator:
+                             // with F_CG_FUSE the partials of beta B^2 p_new . p_new;
+                             // with F_NORMAL r -= alpha (mu^j + beta B^2 p^j) in place
+                             // (cg_rw) and the partials of r . r, no dout
 };
 
 // Gather of the last trace d^{nt-1} = R u^{nt} (after the time loop).
@@ -294,6 +300,13 @@ esi_status_t launch_r_update(Plan* P, float* r, const float* Ap, const double* a
 esi_status_t launch_axpy_flag(Plan* P, float* x, const float* p, const double* alpha,
                               const int* flag, int which, int nshots, int64_t len);
 // out[s] = sum of part[s][0..n)
+// Fused-residual CG: pAp[s] holds sum beta B^2 p.p of shot s on entry and
+// leaves as that plus ||S p||^2 over the shot's data (data of shots shot0..
+// back to back, CSR layout); alpha[s] = rr[s] / pAp[s].  Needs P->part to
+// hold DATA_BLOCKS partials per shot; tmp takes nshots doubles.
+constexpr int DATA_BLOCKS = 64;
+esi_status_t launch_cg_alpha_data(Plan* P, int shot0, int nshots, const float* data, const int* active,
+                                  const double* rr, double* pAp, double* tmp, double* alpha);
 esi_status_t launch_reduce_parts(Plan* P, const double* part, int64_t n, int nshots,
                                  double* out);
 // per-shot scalar updates of CG

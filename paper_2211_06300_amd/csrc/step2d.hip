@@ -108,6 +108,8 @@ struct StepPtrs {
     float* gacc;         // this shot's gradient accumulator
     float* store;        // this step's (dA/dm)u slot
     const float* stin;   // stored (dA/dm)u of this step (CORR)
+    float* r;            // this step's slice of r (RUPD with NORMAL)
+    float al;            // the shot's CG step length (RUPD with NORMAL)
 };
 
 // Shot and tile of workgroup L: from the batch's work list when shots have
@@ -145,12 +147,14 @@ __device__ __forceinline__ StepPtrs step_ptrs(const StepArgs& a, int s, int64_t 
     q.gacc = a.gacc ? a.gacc + (int64_t)s * a.nphys : nullptr;
     q.store = a.store ? a.store + s * a.store_stride + (int64_t)slot * a.nphys : nullptr;
     q.stin = q.store;
+    q.r = a.cg_rw ? a.cg_rw + vbase : nullptr;
+    q.al = a.cg_rw ? (float)a.cg_alpha[s] : 0.f;
     return q;
 }
 
 // Fused per-cell outputs of one step at a physical cell of the tile.
 //  un: new field, q: source term, lq: lap + dx^2 q, c2v: c / dx^2,
-//  pv: p^t (NORMAL), stv: stored (dA/dm)u (CORR).
+//  pv: p^t (NORMAL), stv: stored (dA/dm)u (CORR), rv: r^t (NORMAL with RUPD).
 //
 // (The DTFT helpers below: the source of step n from the frequency slices,
 // q = inv_nt sum_m (re_m cos w_m t_n + im_m sin w_m t_n), and the update of a
@@ -210,13 +214,21 @@ __device__ __forceinline__ void dtft_accumulate(const StepArgs& a, int s, uint32
 template <unsigned FL>
 __device__ __forceinline__ void cell_outputs(const StepArgs& a, const StepPtrs& o, uint32_t pi,
                                              float un, float q, float lq, float c2v, float pv,
-                                             float stv, float wb, double& acc) {
+                                             float stv, float rv, float wb, double& acc) {
     if constexpr ((FL & F_OUT) != 0) at(o.dout, pi) = un;
     if constexpr ((FL & F_NORMAL) != 0) {
         const float np = fmaf(wb, pv, un);
-        at(o.dout, pi) = np;
-        acc += (double)pv * (double)np;
+        if constexpr ((FL & F_RUPD) != 0) {   // r -= alpha N p, as a separate pass would
+            const float rn = fmaf(-o.al, np, rv);
+            at(o.r, pi) = rn;
+            acc += (double)(rn * rn);
+        } else {
+            at(o.dout, pi) = np;
+            acc += (double)pv * (double)np;
+        }
     }
+    if constexpr ((FL & F_CG_FUSE) != 0 && (FL & F_RUPD) != 0)
+        acc += (double)(q * (wb * q));   // beta B^2 p.p of the new direction
     if constexpr ((FL & F_PENALTY) != 0) {
         at(o.gacc, pi) = fmaf(wb * q, c2v * a.inv_dt2 * lq, at(o.gacc, pi));
         acc += (double)(wb * q) * (double)q;   // penalty term beta W q^2 (kept when a.part is set)
@@ -228,7 +240,9 @@ __device__ __forceinline__ void cell_outputs(const StepArgs& a, const StepPtrs& 
 __device__ __forceinline__ float annih_w(const StepArgs& a, int ix, int iz, float sx, float sz) {
     if (a.w_identity) return a.beta;   // uniform over the launch
     const float ddx = (float)ix - sx, ddz = (float)iz - sz;
-    const float bb = sqrtf(ddx * ddx + ddz * ddz) + a.b_eps;
+    // the hardware square root (within 1 ulp; the argument is a sum of squared
+    // integers, never denormal) instead of the correctly rounded sequence
+    const float bb = __builtin_amdgcn_sqrtf(ddx * ddx + ddz * ddz) + a.b_eps;
     return a.beta * (bb * bb);
 }
 
@@ -339,13 +353,17 @@ __global__ __launch_bounds__(256, ESI_MINW) void k_step2d(const StepArgs a) {
             qv[i] = ph[i] ? pn : 0.f;
         }
     }
-    float pv[RZ], stv[RZ];
+    float pv[RZ], stv[RZ], rw[RZ];
 #pragma unroll
-    for (int i = 0; i < RZ; ++i) { pv[i] = 0.f; stv[i] = 0.f; }
+    for (int i = 0; i < RZ; ++i) { pv[i] = 0.f; stv[i] = 0.f; rw[i] = 0.f; }
     if constexpr ((FL & F_NORMAL) != 0) {
         const float* __restrict__ p = a.dp + vbase;
 #pragma unroll
         for (int i = 0; i < RZ; ++i) pv[i] = at(p, pi[i]);
+        if constexpr ((FL & F_RUPD) != 0) {
+#pragma unroll
+            for (int i = 0; i < RZ; ++i) rw[i] = at(o1.r, pi[i]);
+        }
     }
     if constexpr ((FL & F_CORR) != 0) {
 #pragma unroll
@@ -401,7 +419,7 @@ __global__ __launch_bounds__(256, ESI_MINW) void k_step2d(const StepArgs a) {
         }
     }
     float sx = 0.f, sz = 0.f;
-    if constexpr ((FL & (F_NORMAL | F_PENALTY)) != 0) {
+    if constexpr ((FL & (F_NORMAL | F_PENALTY | F_RUPD)) != 0) {
         sx = (float)a.src_pos[gs * 3 + 0];
         sz = (float)a.src_pos[gs * 3 + 1];
     }
@@ -435,11 +453,11 @@ __global__ __launch_bounds__(256, ESI_MINW) void k_step2d(const StepArgs a) {
         }
         if constexpr ((FL & F_DTFT_ACC) != 0) dtft_accumulate(a, s, pi[i], a.step, un, -1, 0.f);
         float wb = 0.f;
-        if constexpr ((FL & (F_NORMAL | F_PENALTY)) != 0) wb = annih_w(a, ix, z - a.nb, sx, sz);
-        cell_outputs<FL>(a, o1, pi[i], un, qd, lq, c2v[i], pv[i], stv[i], wb, acc);
+        if constexpr ((FL & (F_NORMAL | F_PENALTY | F_RUPD)) != 0) wb = annih_w(a, ix, z - a.nb, sx, sz);
+        cell_outputs<FL>(a, o1, pi[i], un, qd, lq, c2v[i], pv[i], stv[i], rw[i], wb, acc);
     }
 
-    if constexpr ((FL & (F_NORMAL | F_SCALE | F_PENALTY)) != 0) {
+    if constexpr ((FL & (F_NORMAL | F_SCALE | F_PENALTY | F_RUPD)) != 0) {
         if (a.part) {   // uniform over the launch
             acc = wave_sum(acc + pr_acc);
             if (lane == 0) sred[wv] = acc;
@@ -527,7 +545,7 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
     const uint32_t soA = (uint32_t)((z0 - HALO + zra + GH) * XS + xa + GH);
     float cA[A_RZ], dA[A_RZ], kA[A_RZ], qA[A_RZ], pvA[A_RZ], stA[A_RZ], poA[A_RZ], xoA[A_RZ], rA[A_RZ];
     uint32_t piA[A_RZ];
-    bool inA[A_RZ], phA[A_RZ];
+    bool inA[A_RZ], phA[A_RZ], tlA[A_RZ];   // tlA: physical cell of the output tile
 #pragma unroll
     for (int i = 0; i < A_RZ; ++i) {
         const int z = z0 - HALO + zra + i;
@@ -538,8 +556,12 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
         const int iz = z - a.nb;
         phA[i] = xa_phys && iz >= 0 && iz < a.nz;
         piA[i] = phA[i] ? (uint32_t)(iz * a.nx + ixa) : 0u;
-        qA[i] = 0.f; pvA[i] = 0.f; stA[i] = 0.f; poA[i] = 0.f; xoA[i] = 0.f;
+        tlA[i] = phA[i] && xa_tile && zra + i >= HALO && zra + i < HALO + T2Z;
+        qA[i] = 0.f; pvA[i] = 0.f; stA[i] = 0.f; poA[i] = 0.f; xoA[i] = 0.f; rA[i] = 0.f;
     }
+    // (values that only the output tile uses, x, p, r of N p and the stored
+    // (dA/dm)u, are loaded there alone: the grown region's ring is the
+    // neighbours' tiles)
     if constexpr ((FL & F_SRC_DENSE) != 0) {
         const float* __restrict__ q = a.dsrc + vA;
 #pragma unroll
@@ -559,7 +581,11 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
         const float* __restrict__ r = a.cg_r + vA;
         const float* __restrict__ xv = a.cg_x + vA;
 #pragma unroll
-        for (int i = 0; i < A_RZ; ++i) { poA[i] = at(p, piA[i]); qA[i] = at(r, piA[i]); xoA[i] = at(xv, piA[i]); }
+        for (int i = 0; i < A_RZ; ++i) {
+            poA[i] = at(p, piA[i]);
+            qA[i] = at(r, piA[i]);
+            xoA[i] = tlA[i] ? at(xv, piA[i]) : 0.f;
+        }
         if constexpr ((FL & F_SCALE) != 0) {
             const float* __restrict__ sc = a.cg_s + (int64_t)s * a.nphys;
 #pragma unroll
@@ -569,11 +595,15 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
     if constexpr ((FL & F_NORMAL) != 0) {
         const float* __restrict__ p = a.dp + vA;
 #pragma unroll
-        for (int i = 0; i < A_RZ; ++i) pvA[i] = at(p, piA[i]);
+        for (int i = 0; i < A_RZ; ++i) pvA[i] = tlA[i] ? at(p, piA[i]) : 0.f;
+        if constexpr ((FL & F_RUPD) != 0) {   // r^tA into rA (no F_SCALE here)
+#pragma unroll
+            for (int i = 0; i < A_RZ; ++i) rA[i] = tlA[i] ? at(oA.r, piA[i]) : 0.f;
+        }
     }
     if constexpr ((FL & F_CORR) != 0) {
 #pragma unroll
-        for (int i = 0; i < A_RZ; ++i) stA[i] = at(oA.stin, piA[i]);
+        for (int i = 0; i < A_RZ; ++i) stA[i] = tlA[i] ? at(oA.stin, piA[i]) : 0.f;
     }
 
 #pragma unroll
@@ -619,7 +649,7 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
     // the point source and the source-cell record
     int srcA = -1, srcB = -1;
     float sx = 0.f, sz = 0.f;
-    if constexpr ((FL & (F_SRC_POINT | F_SRC_REC | F_NORMAL | F_PENALTY)) != 0) {
+    if constexpr ((FL & (F_SRC_POINT | F_SRC_REC | F_NORMAL | F_PENALTY | F_RUPD)) != 0) {
         sx = (float)a.src_pos[gs * 3 + 0];
         sz = (float)a.src_pos[gs * 3 + 1];
         const int gz = a.src_pos[gs * 3 + 1] + a.nb - (z0 - HALO);
@@ -675,9 +705,9 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
                     if (zr * A_W + lane == srcA) a.src_rec[(int64_t)s * a.nt + tA] = un;
                 }
                 float wb = 0.f;
-                if constexpr ((FL & (F_NORMAL | F_PENALTY)) != 0)
+                if constexpr ((FL & (F_NORMAL | F_PENALTY | F_RUPD)) != 0)
                     wb = annih_w(a, ixa, z0 - HALO + zr - a.nb, sx, sz);
-                cell_outputs<FL>(a, oA, piA[i], un, qd, lq, cA[i], pvA[i], stA[i], wb, acc);
+                cell_outputs<FL>(a, oA, piA[i], un, qd, lq, cA[i], pvA[i], stA[i], rA[i], wb, acc);
             }
         }
     }
@@ -727,7 +757,7 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
         const int iz = z - a.nb;
         ph[i] = xphys && iz >= 0 && iz < a.nz;
         pi[i] = ph[i] ? (uint32_t)(iz * a.nx + ix) : 0u;
-        qv[i] = 0.f; pvB[i] = 0.f; stB[i] = 0.f; poB[i] = 0.f; xoB[i] = 0.f;
+        qv[i] = 0.f; pvB[i] = 0.f; stB[i] = 0.f; poB[i] = 0.f; xoB[i] = 0.f; rB[i] = 0.f;
     }
     if constexpr ((FL & F_SRC_DENSE) != 0) {
         const float* __restrict__ q = a.dsrc + vB;
@@ -756,6 +786,10 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
         const float* __restrict__ p = a.dp + vB;
 #pragma unroll
         for (int i = 0; i < B_RZ; ++i) pvB[i] = at(p, pi[i]);
+        if constexpr ((FL & F_RUPD) != 0) {   // r^tB into rB (no F_SCALE here)
+#pragma unroll
+            for (int i = 0; i < B_RZ; ++i) rB[i] = at(oB.r, pi[i]);
+        }
     }
     if constexpr ((FL & F_CORR) != 0) {
 #pragma unroll
@@ -801,11 +835,11 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
             if (zl * T2W + lc == srcB) a.src_rec[(int64_t)s * a.nt + tB] = un;
         }
         float wb = 0.f;
-        if constexpr ((FL & (F_NORMAL | F_PENALTY)) != 0) wb = annih_w(a, ix, z - a.nb, sx, sz);
-        cell_outputs<FL>(a, oB, pi[i], un, qd, lq, c2v[i], pvB[i], stB[i], wb, acc);
+        if constexpr ((FL & (F_NORMAL | F_PENALTY | F_RUPD)) != 0) wb = annih_w(a, ix, z - a.nb, sx, sz);
+        cell_outputs<FL>(a, oB, pi[i], un, qd, lq, c2v[i], pvB[i], stB[i], rB[i], wb, acc);
     }
 
-    if constexpr ((FL & (F_NORMAL | F_SCALE | F_PENALTY)) != 0) {
+    if constexpr ((FL & (F_NORMAL | F_SCALE | F_PENALTY | F_RUPD)) != 0) {
         if (a.part) {   // uniform over the launch
             acc = wave_sum(acc);
             if (lane == 0) sred[wv] = acc;
@@ -873,12 +907,14 @@ esi_status_t dispatch2d(Plan* P, unsigned flags, const StepArgs& a) {
         ESI_CASE(F_SRC_POINT | F_SRC_DENSE | F_STORE)
         ESI_CASE(F_CG_FUSE | F_GATHER)
         ESI_CASE(F_CG_FUSE | F_GATHER | F_SCALE)
+        ESI_CASE(F_CG_FUSE | F_GATHER | F_RUPD)
         ESI_CASE(F_DTFT_SRC | F_GATHER)
         ESI_CASE(F_SRC_DENSE | F_SCALE | F_GATHER)
         ESI_CASE(F_DTFT_SRC | F_PENALTY)
         ESI_CASE(F_INJ | F_DTFT_ACC)
         ESI_CASE(F_INJ | F_OUT)
         ESI_CASE(F_INJ | F_NORMAL)
+        ESI_CASE(F_INJ | F_NORMAL | F_RUPD)
         ESI_CASE(F_INJ | F_CORR)
         ESI_CASE(F_INJ | F_CORR | F_OUT)
         ESI_CASE(F_INJ | F_CORR | F_SRC_REC)

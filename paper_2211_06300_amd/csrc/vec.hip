@@ -135,6 +135,35 @@ __global__ void k_cg_alpha(const double* rr, const double* pAp, double* alpha, i
     if (s < n) alpha[s] = rr[s] / pAp[s];
 }
 
+// grid (DATA_BLOCKS, nshots): part[s][b] = block sums of d^2 over shot s's
+// traces (the data of shots shot0.. back to back, nt samples per receiver)
+__global__ __launch_bounds__(NT) void k_data_sq(const float* __restrict__ d, const int64_t* __restrict__ rec_ptr,
+                                                int shot0, int nt, const int* __restrict__ active,
+                                                double* __restrict__ part) {
+    __shared__ double sm[NT / 64];
+    const int s = blockIdx.y;
+    double acc = 0.0;
+    if (!active || active[s]) {   // uniform over the block
+        const int64_t base = rec_ptr[shot0];
+        const int64_t beg = (int64_t)nt * (rec_ptr[shot0 + s] - base);
+        const int64_t end = (int64_t)nt * (rec_ptr[shot0 + s + 1] - base);
+        for (int64_t i = beg + blockIdx.x * (int64_t)NT + threadIdx.x; i < end; i += (int64_t)gridDim.x * NT)
+            acc += (double)d[i] * (double)d[i];
+    }
+    const double t = block_sum(acc, sm);
+    if (threadIdx.x == 0) part[(int64_t)s * gridDim.x + blockIdx.x] = t;
+}
+
+// pAp = beta B^2 p.p (in pAp) + ||S p||^2 (in dsq); alpha = rr / pAp
+__global__ void k_cg_alpha_data(const double* rr, double* pAp, const double* dsq, double* alpha, int n) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) {
+        const double v = pAp[s] + dsq[s];
+        pAp[s] = v;
+        alpha[s] = rr[s] / v;
+    }
+}
+
 __global__ void k_cg_beta(const double* rr_new, double* rr, double* beta, int n) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s < n) {
@@ -333,6 +362,19 @@ esi_status_t launch_axpy_flag(Plan* P, float* x, const float* p, const double* a
 esi_status_t launch_cg_alpha(Plan* P, const double* rr, const double* pAp, double* alpha,
                              int nshots) {
     hipLaunchKernelGGL(k_cg_alpha, dim3((nshots + 63) / 64), dim3(64), 0, P->stream, rr, pAp, alpha,
+                       nshots);
+    ESI_HIP_TRY(hipGetLastError());
+    return ESI_OK;
+}
+
+esi_status_t launch_cg_alpha_data(Plan* P, int shot0, int nshots, const float* data, const int* active,
+                                  const double* rr, double* pAp, double* tmp, double* alpha) {
+    if (P->part_cap < (int64_t)DATA_BLOCKS * nshots) return fail(ESI_ERR_ARG, "internal: partials too small");
+    hipLaunchKernelGGL(k_data_sq, dim3(DATA_BLOCKS, nshots), dim3(NT), 0, P->stream, data, P->d_rec_ptr, shot0,
+                       P->nt, active, P->part);
+    ESI_HIP_TRY(hipGetLastError());
+    ESI_TRY(launch_reduce_parts(P, P->part, DATA_BLOCKS, nshots, tmp));
+    hipLaunchKernelGGL(k_cg_alpha_data, dim3((nshots + 63) / 64), dim3(64), 0, P->stream, rr, pAp, tmp, alpha,
                        nshots);
     ESI_HIP_TRY(hipGetLastError());
     return ESI_OK;

@@ -71,7 +71,7 @@ _lib = None
 EXPORTS = ["esi_plan_create", "esi_plan_set_model", "esi_plan_destroy", "esi_last_error",
            "esi_forward", "esi_adjoint", "esi_normal_apply", "esi_cg_solve", "esi_gradient",
            "esi_plan_profile", "esi_plan_profile_read", "esi_plan_set_time_block",
-           "esi_forward_ckpt", "esi_grad_velocity", "esi_plan_set_cg_graph",
+           "esi_forward_ckpt", "esi_grad_velocity", "esi_plan_set_cg_graph", "esi_plan_set_cg_rfuse",
            "esi_unet_num_params", "esi_unet_create", "esi_unet_destroy", "esi_unet_set_params",
            "esi_unet_get_params", "esi_unet_forward", "esi_unet_loss_grad", "esi_unet_adam",
            "esi_fpcg_solve", "esi_precond_features", "esi_unet_loss_weights", "esi_plan_autotune",
@@ -81,7 +81,7 @@ EXPORTS = ["esi_plan_create", "esi_plan_set_model", "esi_plan_destroy", "esi_las
 # time-step kernel variants (bit set of fused work), as in include/esi.h
 K_FLAGS = {1: "SRC_POINT", 2: "SRC_DENSE", 4: "CG_FUSE", 8: "INJ", 16: "GATHER", 32: "OUT",
            64: "NORMAL", 128: "PENALTY", 256: "STORE", 512: "CORR", 1024: "SRC_REC",
-           2048: "SCALE", 4096: "DTFT_SRC", 8192: "DTFT_ACC", 32768: "TWO_STEP"}
+           2048: "SCALE", 4096: "DTFT_SRC", 8192: "DTFT_ACC", 16384: "RUPD", 32768: "TWO_STEP"}
 
 
 def load_library(path: str = LIB_PATH):
@@ -120,6 +120,7 @@ def load_library(path: str = LIB_PATH):
     L.esi_plan_profile.argtypes = [vp, i32]
     L.esi_plan_set_time_block.argtypes = [vp, i32]
     L.esi_plan_set_cg_graph.argtypes = [vp, i32]
+    L.esi_plan_set_cg_rfuse.argtypes = [vp, i32]
     L.esi_plan_autotune.argtypes = [vp, i32, i32, vp, vp, i32, vp]
     L.esi_forward_ckpt.argtypes = [vp, i32, i32, i32, vp, vp, i32]
     L.esi_grad_velocity.argtypes = [vp, vp, vp, vp]
@@ -393,6 +394,10 @@ class Plan:
 
     def set_cg_graph(self, enable: bool):
         _check(self._lib.esi_plan_set_cg_graph(self._h, int(bool(enable))))
+
+    def set_cg_rfuse(self, enable: bool):
+        """2D CG with the residual update fused into the adjoint pass (default on)."""
+        _check(self._lib.esi_plan_set_cg_rfuse(self._h, int(bool(enable))))
 
     def set_model(self, vel: torch.Tensor):
         _check(self._lib.esi_plan_set_model(self._h, _f32(vel, self.phys_shape, "vel")))
