@@ -356,8 +356,9 @@ esi_status_t esi_invert(esi_plan_t plan, int32_t shot0, int32_t nshots, const fl
  * plan's nf frequencies.  G s = (1/nt) Re sum_m s_m exp(-j 2 pi f_m n dt) is
  * the inverse (the real part: the modelling needs a real source), so that
  * G = F^* / nt under the real inner product Re sum conj(a) b.  The time loops
- * never store a time axis: G feeds the forward pass inside the stencil kernel
- * and F of the adjoint field accumulates in complex float32 slices.
+ * never store a whole time axis: G feeds the forward pass as its source and F
+ * of the adjoint field accumulates in complex float32 slices (per step inside
+ * the stencil kernel, or per block of steps: esi_plan_set_dtft_block).
  *
  * esi_dtft_set_freqs: nf (1..32) frequencies in Hz (host array); the plan
  *   keeps the twiddle table and F G (a 2nf x 2nf real matrix).  ESI_ERR_ARG
@@ -387,6 +388,21 @@ esi_status_t esi_dtft_cg_solve(esi_plan_t plan, int32_t shot0, int32_t nshots, c
 esi_status_t esi_dtft_to_time(esi_plan_t plan, int32_t shot0, int32_t nshots, const float* x, float* q);
 esi_status_t esi_dtft_gradient(esi_plan_t plan, int32_t shot0, int32_t nshots, const float* x,
                                float* grad_m);
+
+/*
+ * How the DTFT calls above meet the frequency slices in their time loops.
+ * block = 0: inside the step kernel at every step (G x forms each step's
+ * source from the slices; F of the adjoint field is accumulated into them).
+ * block = K > 0 (default 64): per K steps, one kernel forms the K steps'
+ * sources into a K-step buffer that the forward pass reads as its dense
+ * source, and one kernel folds the K adjoint fields that the adjoint pass
+ * wrote into that buffer into the slices, so each slice crosses HBM once per
+ * K steps instead of at every step.  Each cell's operations run in the same
+ * order either way: the results are identical bit for bit.  The plan keeps a
+ * buffer of nshots x min(K, nt) x nz x nx floats.  ESI_ERR_ARG for a null
+ * plan or block outside 0..1024.
+ */
+esi_status_t esi_plan_set_dtft_block(esi_plan_t plan, int32_t block);
 
 /*
  * Data-space solution of the normal equation (Sec. 5.1, eq. (vd), eq. (wv),

@@ -7,6 +7,14 @@
 // with a time axis is ever stored: the CG vectors hold N_f slices per cell.
 // The penalty term uses F (beta W) G = beta W (F G), with F G a 2 N_f x 2 N_f
 // real matrix per plan.  Inner products are the real ones, Re sum conj(a) b.
+//
+// In blocks of K steps (the default), the slices meet the time loops once per
+// block instead of at every step: before the forward pass runs steps
+// [n0, n1), one kernel forms their sources G x_bar into a K-step buffer that
+// the pass reads as a dense source; after the adjoint pass has run steps
+// [j0, j1) writing its field into that buffer, one kernel folds the K fields
+// into the slices.  Each cell's operations run in the same order as inside
+// the step kernel, so both ways give the same bits.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -128,6 +136,59 @@ __global__ void k_to_time(const float2* __restrict__ xb, const float2* __restric
     }
 }
 
+// q[s][n % K][c] = inv_nt sum_m (re_m cos + im_m sin)(w_m t_n), n in [n0, n1):
+// the step kernel's per-step source, the frequencies in the same order.
+template <int NFC>
+__global__ __launch_bounds__(NT) void k_dtft_qgen(const float2* __restrict__ xb, const float2* __restrict__ tw,
+                                                  int nf, int n0, int n1, int K, int64_t n,
+                                                  const int* __restrict__ active, float inv_nt,
+                                                  float* __restrict__ q) {
+    const int s = blockIdx.y;
+    if (active && !active[s]) return;   // uniform over the block
+    for (int64_t c = blockIdx.x * (int64_t)NT + threadIdx.x; c < n; c += (int64_t)gridDim.x * NT) {
+        float2 v[NFC];
+#pragma unroll
+        for (int m = 0; m < NFC; ++m) v[m] = m < nf ? xb[((int64_t)s * nf + m) * n + c] : make_float2(0.f, 0.f);
+        for (int t = n0; t < n1; ++t) {
+            const float2* __restrict__ w = tw + (int64_t)t * nf;
+            float acc = 0.f;
+#pragma unroll
+            for (int m = 0; m < NFC; ++m)
+                if (m < nf) acc = fmaf(v[m].y, w[m].y, fmaf(v[m].x, w[m].x, acc));
+            q[((int64_t)s * K + t % K) * n + c] = acc * inv_nt;
+        }
+    }
+}
+
+// acc_m[s][c] += mu^j (cos, sin)(w_m t_j) for j = j1-1 down to j0, mu^j in
+// slot j % K: the step kernel's per-step accumulation, in the same order.
+template <int NFC>
+__global__ __launch_bounds__(NT) void k_dtft_bacc(float2* __restrict__ acc, const float* __restrict__ mu,
+                                                  const float2* __restrict__ tw, int nf, int j0, int j1, int K,
+                                                  int64_t n, const int* __restrict__ active) {
+    const int s = blockIdx.y;
+    if (active && !active[s]) return;   // uniform over the block
+    for (int64_t c = blockIdx.x * (int64_t)NT + threadIdx.x; c < n; c += (int64_t)gridDim.x * NT) {
+        float2 v[NFC];
+#pragma unroll
+        for (int m = 0; m < NFC; ++m) v[m] = m < nf ? acc[((int64_t)s * nf + m) * n + c] : make_float2(0.f, 0.f);
+        for (int j = j1 - 1; j >= j0; --j) {
+            const float u = mu[((int64_t)s * K + j % K) * n + c];
+            const float2* __restrict__ w = tw + (int64_t)j * nf;
+#pragma unroll
+            for (int m = 0; m < NFC; ++m) {
+                if (m < nf) {
+                    v[m].x = fmaf(u, w[m].x, v[m].x);
+                    v[m].y = fmaf(u, w[m].y, v[m].y);
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < NFC; ++m)
+            if (m < nf) acc[((int64_t)s * nf + m) * n + c] = v[m];
+    }
+}
+
 // CG update after the stopping test: x += alpha p for shots still active or
 // leaving normally; p = r + beta p for shots still active.
 __global__ void k_xp(float* __restrict__ x, float* __restrict__ p, const float* __restrict__ r,
@@ -153,12 +214,90 @@ esi_status_t need_freqs(Plan* P) {
     return ESI_OK;
 }
 
+int dft_block(Plan* P) { return P->dft_block > 0 ? std::min(P->dft_block, P->nt) : 0; }
+
+dim3 cell_grid(Plan* P, int ns) {
+    return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((P->nphys + NT - 1) / NT, 1024)), (unsigned)ns);
+}
+
+esi_status_t launch_qgen(Plan* P, const float2* xb, int n0, int n1, int K, int ns, const int* active, float* q) {
+    const int nf = (int)P->dft_freqs.size();
+    const float inv_nt = (float)(1.0 / P->nt);
+    const dim3 g = cell_grid(P, ns);
+    if (nf <= 8)
+        hipLaunchKernelGGL(k_dtft_qgen<8>, g, dim3(NT), 0, P->stream, xb, P->dft_tw, nf, n0, n1, K, P->nphys, active,
+                           inv_nt, q);
+    else if (nf <= 16)
+        hipLaunchKernelGGL(k_dtft_qgen<16>, g, dim3(NT), 0, P->stream, xb, P->dft_tw, nf, n0, n1, K, P->nphys, active,
+                           inv_nt, q);
+    else
+        hipLaunchKernelGGL(k_dtft_qgen<MAX_NF>, g, dim3(NT), 0, P->stream, xb, P->dft_tw, nf, n0, n1, K, P->nphys,
+                           active, inv_nt, q);
+    ESI_HIP_TRY(hipGetLastError());
+    return ESI_OK;
+}
+
+esi_status_t launch_bacc(Plan* P, float2* acc, const float* mu, int j0, int j1, int K, int ns, const int* active) {
+    const int nf = (int)P->dft_freqs.size();
+    const dim3 g = cell_grid(P, ns);
+    if (nf <= 8)
+        hipLaunchKernelGGL(k_dtft_bacc<8>, g, dim3(NT), 0, P->stream, acc, mu, P->dft_tw, nf, j0, j1, K, P->nphys,
+                           active);
+    else if (nf <= 16)
+        hipLaunchKernelGGL(k_dtft_bacc<16>, g, dim3(NT), 0, P->stream, acc, mu, P->dft_tw, nf, j0, j1, K, P->nphys,
+                           active);
+    else
+        hipLaunchKernelGGL(k_dtft_bacc<MAX_NF>, g, dim3(NT), 0, P->stream, acc, mu, P->dft_tw, nf, j0, j1, K,
+                           P->nphys, active);
+    ESI_HIP_TRY(hipGetLastError());
+    return ESI_OK;
+}
+
 StepArgs dft_args(Plan* P, const TileLists* L, int shot0, int ns) {
     StepArgs a = base_args(P, L, shot0, ns);
     a.dft_tw = P->dft_tw;
     a.dft_nf = (int)P->dft_freqs.size();
     a.inv_nt = (float)(1.0 / P->nt);
     return a;
+}
+
+// The forward pass over all steps with the dense source G x_bar and the
+// extra flags (F_GATHER, F_PENALTY); the ring state ends in slot *cs.
+esi_status_t dtft_forward(Plan* P, StepArgs a, unsigned extra, const float2* xb, int ns, int* cs) {
+    *cs = 0;
+    const int K = dft_block(P);
+    if (K == 0) {
+        a.dft_src = xb;
+        return forward_loop(P, a, F_DTFT_SRC | extra, P->ring, cs, 0, P->nt);
+    }
+    ESI_TRY(grow_t(&P->dft_blk, &P->dft_blk_cap, (int64_t)ns * K * P->nphys, P->stream));
+    a.dsrc = P->dft_blk;
+    a.blk_T = K;
+    for (int n0 = 0; n0 < P->nt; n0 += K) {
+        const int n1 = std::min(P->nt, n0 + K);
+        ESI_TRY(launch_qgen(P, xb, n0, n1, K, ns, a.active, P->dft_blk));
+        ESI_TRY(forward_loop(P, a, F_SRC_DENSE | extra, P->ring, cs, n0, n1));
+    }
+    return ESI_OK;
+}
+
+// The adjoint pass over all steps (injection set in b) with the DTFT of its
+// field accumulated into acc.
+esi_status_t dtft_adjoint(Plan* P, StepArgs b, float2* acc, int ns) {
+    int cs = 0;
+    const int K = dft_block(P);
+    if (K == 0) {
+        b.dft_acc = acc;
+        return adjoint_loop(P, b, F_INJ | F_DTFT_ACC, P->ring, &cs, 0, P->nt);
+    }
+    ESI_TRY(grow_t(&P->dft_blk, &P->dft_blk_cap, (int64_t)ns * K * P->nphys, P->stream));
+    b.dout = P->dft_blk;
+    b.blk_T = K;
+    for (int j1 = P->nt, j0 = ((P->nt - 1) / K) * K; j1 > 0; j1 = j0, j0 -= K) {
+        ESI_TRY(adjoint_loop(P, b, F_INJ | F_OUT, P->ring, &cs, j0, j1));
+        ESI_TRY(launch_bacc(P, acc, P->dft_blk, j0, j1, K, ns, b.active));
+    }
+    return ESI_OK;
 }
 
 // M p_bar into Mp (device [ns][nf][phys] (re, im)); p.Mp per shot into pMp
@@ -173,19 +312,16 @@ esi_status_t dtft_normal(Plan* P, int shot0, int ns, const float2* p, float2* Mp
     ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
     StepArgs a = dft_args(P, L, shot0, ns);
     a.active = active;
-    a.dft_src = p;
     a.gat_data = P->dscr;
     int cs = 0;
-    ESI_TRY(forward_loop(P, a, F_DTFT_SRC | F_GATHER, P->ring, &cs, 0, P->nt));
+    ESI_TRY(dtft_forward(P, a, F_GATHER, p, ns, &cs));
     ESI_TRY(launch_final_gather(P, P->ring + (int64_t)cs * P->fsize, RING * P->fsize, P->dscr, shot0, ns));
     ESI_TRY(launch_fill(P, (float*)Mp, (int64_t)ns * nf * P->nphys * 2, 0.f));
     ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
     StepArgs b = dft_args(P, L, shot0, ns);
     b.active = active;
     b.inj_data = P->dscr;
-    b.dft_acc = Mp;
-    cs = 0;
-    ESI_TRY(adjoint_loop(P, b, F_INJ | F_DTFT_ACC, P->ring, &cs, 0, P->nt));
+    ESI_TRY(dtft_adjoint(P, b, Mp, ns));
     const int bps = (int)std::max<int64_t>(1, std::min<int64_t>(64, (P->nphys + 4095) / 4096));
     ESI_TRY(grow_t(&P->part, &P->part_cap, (int64_t)bps * ns, P->stream));
     hipLaunchKernelGGL(k_dtft_finish, dim3(bps, ns), dim3(NT), 0, P->stream, Mp, p, P->dft_C, nf, P->nz, P->nx,
@@ -211,9 +347,7 @@ esi_status_t dtft_rhs(Plan* P, int shot0, int ns, const float* d_obs, float2* b)
     ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
     StepArgs a = dft_args(P, L, shot0, ns);
     a.inj_data = P->dscr;
-    a.dft_acc = b;
-    int cs = 0;
-    return adjoint_loop(P, a, F_INJ | F_DTFT_ACC, P->ring, &cs, 0, P->nt);
+    return dtft_adjoint(P, a, b, ns);
 }
 
 }  // namespace
@@ -267,6 +401,14 @@ extern "C" esi_status_t esi_dtft_set_freqs(esi_plan_t plan, int32_t nf, const do
     return ESI_OK;
 }
 
+extern "C" esi_status_t esi_plan_set_dtft_block(esi_plan_t plan, int32_t block) {
+    set_error("");
+    if (!plan) return fail(ESI_ERR_ARG, "null plan");
+    if (block < 0 || block > 1024) return fail(ESI_ERR_ARG, "DTFT block must be 0..1024 steps");
+    ((Plan*)plan)->dft_block = block;
+    return ESI_OK;
+}
+
 extern "C" esi_status_t esi_dtft_normal_apply(esi_plan_t plan, int32_t shot0, int32_t ns, const float* p,
                                               float* Mp, double* pMp) {
     set_error("");
@@ -317,10 +459,9 @@ extern "C" esi_status_t esi_dtft_gradient(esi_plan_t plan, int32_t shot0, int32_
     ESI_TRY(launch_fill(P, P->gshot, (int64_t)ns * P->nphys, 0.f));
     ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
     StepArgs a = dft_args(P, L, shot0, ns);
-    a.dft_src = (const float2*)xbar;
     a.gacc = P->gshot;
     int cs = 0;
-    ESI_TRY(forward_loop(P, a, F_DTFT_SRC | F_PENALTY, P->ring, &cs, 0, P->nt));
+    ESI_TRY(dtft_forward(P, a, F_PENALTY, (const float2*)xbar, ns, &cs));
     return launch_sum_shots(P, P->gshot, ns, P->nphys, 1.f, grad_m);
 }
 

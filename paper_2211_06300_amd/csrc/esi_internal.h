@@ -77,6 +77,10 @@ struct Plan {
     std::vector<double> dft_freqs;
     float2* dft_tw = nullptr;
     double* dft_C = nullptr;
+    // DTFT passes in blocks of dft_block steps (0: per step inside the step
+    // kernel): the block's dense sources or adjoint fields, [nshots][block][phys]
+    int dft_block = 64;
+    float* dft_blk = nullptr; int64_t dft_blk_cap = 0;
     // data-space solver scratch: adjoint field [nshots][nt][phys], W^{-1}
     // [nshots][phys], data segment offsets [nshots + 1]
     float* ds_mu = nullptr; int64_t ds_mu_cap = 0;
@@ -259,6 +263,9 @@ struct StepArgs {
     const float2* dft_tw;
     int dft_nf;
     float inv_nt;
+    // blk_T > 0: dsrc and dout hold blk_T steps, step n in slot n % blk_T
+    // ([nshots][blk_T][phys]); 0: the whole time axis
+    int blk_T;
 };
 
 // kernel flag bits

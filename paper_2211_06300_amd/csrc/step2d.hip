@@ -141,9 +141,15 @@ __device__ __forceinline__ Aperture aperture(const StepArgs& a, int gs) {
     return ap;
 }
 
-__device__ __forceinline__ StepPtrs step_ptrs(const StepArgs& a, int s, int64_t vbase, int slot) {
+// Offset of step `step` of shot s in dsrc / dout: vbase on the whole time
+// axis, slot step % blk_T of the shot's block otherwise.
+__device__ __forceinline__ int64_t blk_off(const StepArgs& a, int s, int step, int64_t vbase) {
+    return a.blk_T ? ((int64_t)s * a.blk_T + step % a.blk_T) * a.nphys : vbase;
+}
+
+__device__ __forceinline__ StepPtrs step_ptrs(const StepArgs& a, int s, int step, int64_t vbase, int slot) {
     StepPtrs q;
-    q.dout = a.dout ? a.dout + vbase : nullptr;
+    q.dout = a.dout ? a.dout + blk_off(a, s, step, vbase) : nullptr;
     q.gacc = a.gacc ? a.gacc + (int64_t)s * a.nphys : nullptr;
     q.store = a.store ? a.store + s * a.store_stride + (int64_t)slot * a.nphys : nullptr;
     q.stin = q.store;
@@ -300,7 +306,7 @@ __global__ __launch_bounds__(256, ESI_MINW) void k_step2d(const StepArgs a) {
     const int zb = z0 + wz * RZ;
     const uint32_t so0 = (uint32_t)((zb + GH) * XS + x + GH);
     const int64_t vbase = ((int64_t)s * a.nt + a.step) * a.nphys;
-    const StepPtrs o1 = step_ptrs(a, s, vbase, a.store_slot);
+    const StepPtrs o1 = step_ptrs(a, s, a.step, vbase, a.store_slot);
     float c2v[RZ], dv[RZ], kzv[RZ], qv[RZ];
     uint32_t pi[RZ];
     bool ph[RZ];
@@ -316,7 +322,7 @@ __global__ __launch_bounds__(256, ESI_MINW) void k_step2d(const StepArgs a) {
         qv[i] = 0.f;
     }
     if constexpr ((FL & F_SRC_DENSE) != 0) {
-        const float* __restrict__ q = a.dsrc + vbase;
+        const float* __restrict__ q = a.dsrc + blk_off(a, s, a.step, vbase);
 #pragma unroll
         for (int i = 0; i < RZ; ++i) qv[i] = ph[i] ? at(q, pi[i]) : 0.f;
         if constexpr ((FL & F_SCALE) != 0) {   // cell-scaled dense source
@@ -518,8 +524,8 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
     float* __restrict__ dnx = a.dnx + s * a.fstride;
     const int64_t vA = ((int64_t)s * a.nt + tA) * a.nphys;
     const int64_t vB = ((int64_t)s * a.nt + tB) * a.nphys;
-    const StepPtrs oA = step_ptrs(a, s, vA, a.store_slot);
-    const StepPtrs oB = step_ptrs(a, s, vB, a.store_slot2);
+    const StepPtrs oA = step_ptrs(a, s, tA, vA, a.store_slot);
+    const StepPtrs oB = step_ptrs(a, s, tB, vB, a.store_slot2);
 
     // U0 (r, c) <- padded (z0 - 8 + r, x0 - 8 + c) = storage (z0 + r, x0 + c)
     constexpr int RPW0 = U0H / 4;
@@ -563,7 +569,7 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
     // (dA/dm)u, are loaded there alone: the grown region's ring is the
     // neighbours' tiles)
     if constexpr ((FL & F_SRC_DENSE) != 0) {
-        const float* __restrict__ q = a.dsrc + vA;
+        const float* __restrict__ q = a.dsrc + blk_off(a, s, tA, vA);
 #pragma unroll
         for (int i = 0; i < A_RZ; ++i) qA[i] = phA[i] ? at(q, piA[i]) : 0.f;
         if constexpr ((FL & F_SCALE) != 0) {
@@ -760,7 +766,7 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
         qv[i] = 0.f; pvB[i] = 0.f; stB[i] = 0.f; poB[i] = 0.f; xoB[i] = 0.f; rB[i] = 0.f;
     }
     if constexpr ((FL & F_SRC_DENSE) != 0) {
-        const float* __restrict__ q = a.dsrc + vB;
+        const float* __restrict__ q = a.dsrc + blk_off(a, s, tB, vB);
 #pragma unroll
         for (int i = 0; i < B_RZ; ++i) qv[i] = ph[i] ? at(q, pi[i]) : 0.f;
         if constexpr ((FL & F_SCALE) != 0) {

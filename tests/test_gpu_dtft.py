@@ -104,6 +104,31 @@ def test_dtft_two_step_bitwise(esi):
     assert torch.equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("nf", [3, 12, 20])
+def test_dtft_block_bitwise(esi, nf):
+    """Blocks of K steps (sources formed per block, adjoint fields folded into
+    the slices per block) give the same bits as the per-step kernels, for K
+    dividing nt or not, K above nt, and nt odd (the last launch of a pass runs
+    one step): normal operator, right-hand side, gradient and 3 CG iterations."""
+    cfg = _cfg(nt=61)
+    freqs = np.linspace(10.0, 70.0, nf)
+    p = torch.from_numpy(inputs.random_field((cfg.nshots, nf, cfg.nz, cfg.nx, 2), 86)).to(DEV)
+    outs = []
+    for block in (0, 7, 32, 100):
+        plan = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_start).to(DEV))
+        plan.dtft_set_freqs(freqs)
+        plan.set_dtft_block(block)
+        dd = torch.from_numpy(inputs.random_field(plan.data_shape(), 87)).to(DEV)
+        Mp, pMp = plan.dtft_normal_apply(p)
+        x, rep = plan.dtft_cg_solve(dd, 3)
+        outs.append([Mp, pMp, plan.dtft_rhs(dd), plan.dtft_gradient(p), x,
+                     torch.from_numpy(np.asarray(rep["res_hist"]))])
+        plan.close()
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert torch.equal(a, b)
+
+
 def test_dtft_rhs_and_to_time(esi):
     cfg = _cfg()
     plan = _plan(esi, cfg, cfg.v_start)
@@ -163,4 +188,8 @@ def test_dtft_argument_errors(esi):
         plan.dtft_set_freqs(np.arange(40.0))
     with pytest.raises(esi.EsiError):
         plan.dtft_set_freqs([10.0, -1.0])
+    with pytest.raises(esi.EsiError):
+        plan.set_dtft_block(-1)
+    with pytest.raises(esi.EsiError):
+        plan.set_dtft_block(1025)
     plan.close()
