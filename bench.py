@@ -408,6 +408,36 @@ def dataspace_run(args, torch, dev):
             "dominant_loop": {"variant": name, "launches": rec["launches"], "ms": round(rec["ms"], 1)}}
 
 
+def forward3d_run(args, torch, dev):
+    """The 3D forward modelling of the differentiation workload (256^3, 8
+    shots at once, point sources, 128 x 128 receivers) over its first
+    args.nt3d steps: wall time of the pass, and the step kernel's average
+    launch time from the live profile against its algorithmic bytes."""
+    from paper_2211_06300_amd import esi, inputs
+    cfg = inputs.cfg_diff3d(n=256, nt=args.nt3d)
+    plan = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_true).to(dev))
+    w = torch.from_numpy(np.stack([cfg.wavelet] * cfg.nshots)).to(dev)
+    plan.forward(w, esi.SRC_POINT)                                  # warm-up
+    torch.cuda.synchronize()
+    plan.profile(True)
+    t0 = time.perf_counter()
+    plan.forward(w, esi.SRC_POINT)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = plan.profile_read()
+    plan.profile(False)
+    plan.close()
+    name, rec = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    per_us = rec["ms"] / rec["launches"] * 1e3
+    npad = (cfg.nz + 2 * cfg.nb) * (cfg.ny + 2 * cfg.nb) * (cfg.nx + 2 * cfg.nb)
+    alg = bytes_per_shot_launch(rec["flags"], npad, cfg.nz * cfg.ny * cfg.nx) * cfg.nshots
+    return {"workload": f"forward-3d-{cfg.nx}x{cfg.ny}x{cfg.nz}-{cfg.nshots}shots", "nt": cfg.nt,
+            "seconds": round(wall, 4), "gpts_per_s": round(cfg.nshots * npad * cfg.nt / wall / 1e9, 1),
+            "kernel": f"k_step3d<{name}>", "avg_launch_us": round(per_us, 1),
+            "alg_bytes_per_launch": int(alg), "alg_gbs": round(alg / per_us / 1e3, 1),
+            "frac": round(alg / per_us / 1e3 / HBM_PEAK_GBS, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -441,6 +471,9 @@ def main():
     ap.add_argument("--invert-inner", choices=["fcg", "ds", "cg"], default="fcg")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="also run one elementwise copy of this many MiB (counter calibration)")
+    ap.add_argument("--nt3d", type=int, default=100, help="steps of the 3D forward leg")
+    ap.add_argument("--only-3d", action="store_true",
+                    help="run the 3D forward leg alone and print its JSON object")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "bench.py runs on one GPU; --gpus must be 1 "
@@ -457,6 +490,9 @@ def main():
         b = torch.mul(a, 1.0)
         torch.cuda.synchronize()
         del a, b
+    if args.only_3d:
+        print(json.dumps({"forward3d": forward3d_run(args, torch, dev)}), flush=True)
+        return
     cfg = inputs.cfg_single_solve(nshots=args.shots, nt=args.nt)
     npad = (cfg.nz + 2 * cfg.nb) * (cfg.nx + 2 * cfg.nb)
     nphys = cfg.nz * cfg.nx

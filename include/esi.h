@@ -467,15 +467,15 @@ esi_status_t esi_plan_autotune(esi_plan_t plan, int32_t shot0, int32_t nshots, c
 esi_status_t esi_plan_set_cg_graph(esi_plan_t plan, int32_t enable);
 
 /*
- * CG iterations (Algorithm 1) on 2D plans with the residual update fused into
- * the normal operator; on by default.  From iteration 1 on, p_k . N p_k is
+ * CG iterations (Algorithm 1) with the residual update fused into the normal
+ * operator; on by default.  From iteration 1 on, p_k . N p_k is
  * taken as ||S p_k||^2 + beta ||B p_k||^2 from the forward pass (the two are
  * equal in exact arithmetic, S being the receiver data of the forward
  * modelling and N = S^T S + beta B^2), so alpha_k is known before the adjoint
  * pass, which updates r in place instead of storing N p_k for a separate
  * pass.  enable = 0 restores the separate pass (p_k . N p_k then comes from
- * N p_k itself); the two agree to float32 rounding, not bit for bit.  3D
- * plans, the flexible and preconditioned solvers keep the separate pass.
+ * N p_k itself); the two agree to float32 rounding, not bit for bit.  The
+ * flexible and preconditioned solvers keep the separate pass.
  * Errors: ESI_ERR_ARG for a null plan.
  */
 esi_status_t esi_plan_set_cg_rfuse(esi_plan_t plan, int32_t enable);

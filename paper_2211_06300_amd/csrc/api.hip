@@ -263,7 +263,7 @@ esi_status_t do_normal(Plan* P, int shot0, int ns, const float* p, float* Ap, co
     return adjoint_loop(P, b, F_INJ | F_NORMAL, P->ring, &cs, 0, P->nt);
 }
 
-// Iteration k >= 1 of Algorithm 1 (2D) with the residual update fused into
+// Iteration k >= 1 of Algorithm 1 with the residual update fused into
 // the normal operator.  The forward pass forms p_k = r_k + beta p_{k-1} into
 // pnew and x_k = x_{k-1} + alpha p_{k-1}, records S p_k and the partials of
 // beta B^2 p_k . p_k; with p_k . N p_k = ||S p_k||^2 + beta ||B p_k||^2 the
@@ -385,7 +385,7 @@ struct CgState {
 // The caller swaps p and Ap after every iteration k >= 1.
 esi_status_t cg_iteration(Plan* P, const CgState& c, int k, const float* p, float* Ap) {
     const float* dir = p;
-    if (k >= 1 && P->ndim == 2 && P->cg_rfuse) {
+    if (k >= 1 && P->cg_rfuse) {
         ESI_TRY(do_normal_rupd(P, c.shot0, c.ns, p, Ap, c.L, c.active, c.r, c.x, c.alpha, c.beta, c.rr,
                                c.pAp, c.rr_new));
         ESI_TRY(launch_cg_control(P, c.rr0, c.rr_new, c.pAp, c.active, c.finish, c.iters, c.status,

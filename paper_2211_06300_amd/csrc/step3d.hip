@@ -93,6 +93,8 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
     const float* dsrc = (FL & F_SRC_DENSE) ? a.dsrc + vbase : nullptr;
     float* dout = (FL & (F_OUT | F_NORMAL)) ? a.dout + vbase : nullptr;
     const float* dp = (FL & F_NORMAL) ? a.dp + vbase : nullptr;
+    float* rw = ((FL & F_NORMAL) && (FL & F_RUPD)) ? a.cg_rw + vbase : nullptr;
+    const float ral = ((FL & F_NORMAL) && (FL & F_RUPD)) ? (float)a.cg_alpha[s] : 0.f;
     float* gacc = (FL & (F_PENALTY | F_CORR)) ? a.gacc + (int64_t)s * a.nphys : nullptr;
     float* store = (FL & (F_STORE | F_CORR)) ? a.store + s * a.store_stride + (int64_t)a.store_slot * a.nphys : nullptr;
     float alp = 0.f, bet = 0.f;
@@ -135,31 +137,43 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
         }
     }
     float sx = 0.f, sy = 0.f, sz = 0.f;
-    if constexpr ((FL & (F_NORMAL | F_PENALTY)) != 0) {
+    if constexpr ((FL & (F_NORMAL | F_PENALTY | F_RUPD)) != 0) {
         sx = (float)a.src_pos[gs * 3 + 0];
         sz = (float)a.src_pos[gs * 3 + 1];
         sy = (float)a.src_pos[gs * 3 + 2];
     }
 
-    // z window of this column: w[k] = u at z - 4 + k
+    // z window of this column: w[k] = u at z - 4 + k.  A plane's own loads
+    // (the window's new value, the halo cells, c, d) are issued one plane
+    // ahead, before the barrier of the plane in between, so their latency
+    // overlaps that plane's stencil work.
     float w[2 * HALO + 1];
 #pragma unroll
     for (int k = 0; k < 2 * HALO; ++k) w[k] = at(cur, (uint32_t)(zc0 - HALO + k + GH) * PS + col);
     const int zend = min(zc0 + TZC, a.nzp);
+    float nw, nh[2], nc, nd;   // the next plane's loads
+    {
+        const uint32_t pz = (uint32_t)(zc0 + GH) * PS;
+        nw = at(cur, pz + 4u * PS + col);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) nh[k] = hl[k] >= 0 ? at(cur, pz + ho[k]) : 0.f;
+        nc = at(a.c2, pz + col);
+        nd = at(din, pz + col);
+    }
     double acc = 0.0;
     for (int z = zc0; z < zend; ++z) {
         const int lz = z - zc0;
         const uint32_t pz = (uint32_t)(z + GH) * PS;
-        w[2 * HALO] = at(cur, pz + 4u * PS + col);
+        w[2 * HALO] = nw;
         float* Pb = P[lz & 1];
         Pb[(ly + HALO) * PW + lx + HALO] = w[HALO];
 #pragma unroll
         for (int k = 0; k < 2; ++k)
-            if (hl[k] >= 0) Pb[hl[k]] = at(cur, pz + ho[k]);
+            if (hl[k] >= 0) Pb[hl[k]] = nh[k];
         // this plane's loads
         const uint32_t so = pz + col;
-        const float c2v = at(a.c2, so);
-        const float dv = at(din, so);
+        const float c2v = nc;
+        const float dv = nd;
         const float kap = kxy + at(a.kz, (uint32_t)min(z, a.nzp - 1));
         const int iz = z - a.nb;
         const bool ph = xyphys && iz >= 0 && iz < a.nz;
@@ -172,8 +186,9 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
             xo = at(cgx, pi);
             q = ph ? fmaf(bet, po, at(cgr, pi)) : 0.f;
         }
-        float pv = 0.f, stv = 0.f;
+        float pv = 0.f, stv = 0.f, rv = 0.f;
         if constexpr ((FL & F_NORMAL) != 0) pv = at(dp, pi);
+        if constexpr ((FL & F_NORMAL) != 0 && (FL & F_RUPD) != 0) rv = at(rw, pi);
         if constexpr ((FL & F_CORR) != 0) stv = at(store, pi);
         bool inj_here = false;
         if constexpr ((FL & F_INJ) != 0) {
@@ -192,6 +207,14 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
                 }
                 while (ie < iend && a.inj_cell[ie] / (TX * TY) == lz) ++ie;
             }
+        }
+        if (z + 1 < zend) {   // uniform over the workgroup
+            const uint32_t pn = pz + PS;
+            nw = at(cur, pn + 4u * PS + col);
+#pragma unroll
+            for (int k = 0; k < 2; ++k) nh[k] = hl[k] >= 0 ? at(cur, pn + ho[k]) : 0.f;
+            nc = at(a.c2, pn + col);
+            nd = at(din, pn + col);
         }
         __syncthreads();
         const float* cp = Pb + (ly + HALO) * PW + lx + HALO;
@@ -233,19 +256,29 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
                 if (cell == src_cell) a.src_rec[(int64_t)s * a.nt + a.step] = un;
             }
             float wb = 0.f;
-            if constexpr ((FL & (F_NORMAL | F_PENALTY)) != 0) {
+            if constexpr ((FL & (F_NORMAL | F_PENALTY | F_RUPD)) != 0) {
                 if (a.w_identity) {
                     wb = a.beta;
                 } else {
+                    // the hardware square root (within 1 ulp; the argument is
+                    // a sum of squared integers, never denormal)
                     const float ddx = (float)ix - sx, ddy = (float)iy - sy, ddz = (float)iz - sz;
-                    const float bb = sqrtf(ddx * ddx + ddy * ddy + ddz * ddz) + a.b_eps;
+                    const float bb = __builtin_amdgcn_sqrtf(ddx * ddx + ddy * ddy + ddz * ddz) + a.b_eps;
                     wb = a.beta * (bb * bb);
                 }
             }
+            if constexpr ((FL & F_CG_FUSE) != 0 && (FL & F_RUPD) != 0)
+                acc += (double)(q * (wb * q));   // beta B^2 p.p of the new direction
             if constexpr ((FL & F_NORMAL) != 0) {
                 const float np = fmaf(wb, pv, un);
-                at(dout, pi) = np;
-                acc += (double)pv * (double)np;
+                if constexpr ((FL & F_RUPD) != 0) {   // r -= alpha N p, as a separate pass would
+                    const float rn = fmaf(-ral, np, rv);
+                    at(rw, pi) = rn;
+                    acc += (double)(rn * rn);
+                } else {
+                    at(dout, pi) = np;
+                    acc += (double)pv * (double)np;
+                }
             }
             if constexpr ((FL & F_PENALTY) != 0) {
                 at(gacc, pi) = fmaf(wb * qd, c2v * a.inv_dt2 * lq, at(gacc, pi));
@@ -258,7 +291,7 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
         for (int k = 0; k < 2 * HALO; ++k) w[k] = w[k + 1];
     }
 
-    if constexpr ((FL & (F_NORMAL | F_PENALTY)) != 0) {
+    if constexpr ((FL & (F_NORMAL | F_PENALTY | F_RUPD)) != 0) {
         if (a.part) {   // uniform over the launch
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
@@ -302,8 +335,10 @@ esi_status_t launch_step3d(Plan* P, unsigned flags, const StepArgs& a) {
         ESI_CASE(F_SRC_POINT | F_SRC_DENSE | F_GATHER | F_STORE)
         ESI_CASE(F_SRC_POINT | F_SRC_DENSE | F_STORE)
         ESI_CASE(F_CG_FUSE | F_GATHER)
+        ESI_CASE(F_CG_FUSE | F_GATHER | F_RUPD)
         ESI_CASE(F_INJ | F_OUT)
         ESI_CASE(F_INJ | F_NORMAL)
+        ESI_CASE(F_INJ | F_NORMAL | F_RUPD)
         ESI_CASE(F_INJ | F_CORR)
         ESI_CASE(F_INJ | F_CORR | F_OUT)
         ESI_CASE(F_INJ | F_CORR | F_SRC_REC)

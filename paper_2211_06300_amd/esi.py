@@ -401,7 +401,7 @@ class Plan:
         _check(self._lib.esi_plan_set_dtft_block(self._h, int(block)))
 
     def set_cg_rfuse(self, enable: bool):
-        """2D CG with the residual update fused into the adjoint pass (default on)."""
+        """CG with the residual update fused into the adjoint pass (default on)."""
         _check(self._lib.esi_plan_set_cg_rfuse(self._h, int(bool(enable))))
 
     def set_model(self, vel: torch.Tensor):
