@@ -12,6 +12,8 @@
 
 namespace esi {
 
+void step3d_tile_shape(int* tx, int* ty, int* tz);   // step3d.hip
+
 static thread_local std::string g_err;
 
 void set_error(const std::string& s) { g_err = s; }
@@ -413,10 +415,13 @@ extern "C" esi_status_t esi_plan_create(esi_plan_t* plan, const esi_grid_t* g, c
         P->ZS = round_up(P->nzp, 64) + 2 * GH;
         P->YS = 1;
     } else {
-        // 64 x 8 column blocks, 32-plane chunks, plus the ghost frame
-        P->XS = round_up(round_up(P->nxp, 64) + 2 * GH, 32);
-        P->YS = round_up(P->nyp, 8) + 2 * GH;
-        P->ZS = round_up(P->nzp, 32) + 2 * GH;
+        // the 3D step kernel's column blocks (tx x ty) and z chunks (tz
+        // planes) over the padded grid, plus the ghost frame
+        int tx, ty, tz;
+        step3d_tile_shape(&tx, &ty, &tz);
+        P->XS = round_up(round_up(P->nxp, tx) + 2 * GH, 32);
+        P->YS = round_up(P->nyp, ty) + 2 * GH;
+        P->ZS = round_up(P->nzp, tz) + 2 * GH;
     }
     P->fsize = (int64_t)P->ZS * P->YS * P->XS;
     P->nphys = (int64_t)g->nz * g->ny * g->nx;

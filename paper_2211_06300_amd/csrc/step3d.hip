@@ -2,10 +2,13 @@
 // fused work as the 2D kernels (injection, recording, CG direction update,
 // N p with p.Np partials, gradient correlations).
 //
-// 2.5D sweep: a 512-thread workgroup owns a 64 (x) x 8 (y) block of columns
-// and a chunk of 32 z-planes.  Each thread keeps the 9-value z window of its
-// column in registers; the current plane of the block plus a 4-cell x/y halo
-// is staged in a double-buffered LDS plane, so one barrier per plane suffices.
+// 2.5D sweep: a 512-thread workgroup owns a 64 (x) x 16 (y) block of columns
+// and a chunk of 32 z-planes; a thread owns two columns, rows ly and ly + 8.
+// Each thread keeps the 9-value z windows of its columns in registers; the
+// current plane of the block plus a 4-cell x/y halo is staged in a
+// double-buffered LDS plane, so one barrier per plane suffices.  Sixteen rows
+// per block put the y halo at half the block's rows, where eight rows per
+// block read a plane's cells twice over.
 // Receiver injection is applied per plane through a small LDS plane; the
 // recording reads u^n straight from memory.  Storage is the padded grid with
 // a zero ghost frame of GH cells, planes YS x XS floats apart.
@@ -15,10 +18,12 @@ namespace esi {
 
 namespace {
 
-constexpr int TX = 64, TY = 8, TZC = 32;   // block of columns, z-chunk
-constexpr int NTH = TX * TY;               // 512 threads
-constexpr int PW = TX + 2 * HALO, PH = TY + 2 * HALO;   // staged plane 72 x 16
-constexpr int NHALO = PW * PH - TX * TY;   // 640 halo cells per plane
+constexpr int TX = 64, WY = 8, RY = 2;     // threads: 64 x 8, two rows each
+constexpr int TY = WY * RY, TZC = 32;      // block of columns, z-chunk
+constexpr int NTH = TX * WY;               // 512 threads
+constexpr int PW = TX + 2 * HALO, PH = TY + 2 * HALO;   // staged plane 72 x 24
+constexpr int NHALO = PW * PH - TX * TY;   // 704 halo cells per plane
+static_assert(NHALO <= 2 * NTH, "two halo cells per thread");
 
 __device__ __forceinline__ int xcd_remap(int b, int nblocks) {
     const int per = nblocks / XCDS, rem = nblocks % XCDS;
@@ -59,8 +64,21 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
     const float* __restrict__ din = a.din + s * a.fstride;
     float* __restrict__ dnx = a.dnx + s * a.fstride;
 
-    const int x = x0 + lx, y = y0 + ly;
-    const uint32_t col = (uint32_t)((y + GH) * XS + x + GH);   // column offset within a plane
+    // this thread's columns: rows yr = ly + r * WY of the block
+    const int x = x0 + lx;
+    const int ix = x - a.nb;
+    uint32_t col[RY];
+    float kxy[RY];
+    bool xyphys[RY];
+    int iy[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const int y = y0 + ly + r * WY;
+        col[r] = (uint32_t)((y + GH) * XS + x + GH);
+        kxy[r] = at(a.kx, (uint32_t)min(x, a.nxp - 1)) + at(a.ky, (uint32_t)min(y, a.nyp - 1));
+        iy[r] = y - a.nb;
+        xyphys[r] = ix >= 0 && ix < a.nx && iy[r] >= 0 && iy[r] < a.ny;
+    }
     // halo cells this thread stages: LDS index and in-plane storage offset
     int hl[2];
     uint32_t ho[2];
@@ -86,9 +104,6 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
         }
     }
 
-    const float kxy = at(a.kx, (uint32_t)min(x, a.nxp - 1)) + at(a.ky, (uint32_t)min(y, a.nyp - 1));
-    const int ix = x - a.nb, iy = y - a.nb;
-    const bool xyphys = ix >= 0 && ix < a.nx && iy >= 0 && iy < a.ny;
     const int64_t vbase = ((int64_t)s * a.nt + a.step) * a.nphys;
     const float* dsrc = (FL & F_SRC_DENSE) ? a.dsrc + vbase : nullptr;
     float* dout = (FL & (F_OUT | F_NORMAL)) ? a.dout + vbase : nullptr;
@@ -143,60 +158,72 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
         sy = (float)a.src_pos[gs * 3 + 2];
     }
 
-    // z window of this column: w[k] = u at z - 4 + k.  A plane's own loads
-    // (the window's new value, the halo cells, c, d) are issued one plane
-    // ahead, before the barrier of the plane in between, so their latency
-    // overlaps that plane's stencil work.
-    float w[2 * HALO + 1];
+    // z windows of this thread's columns: w[r][k] = u at z - 4 + k.  A plane's
+    // own loads (the windows' new values, the halo cells, c, d) are issued one
+    // plane ahead, before the barrier of the plane in between, so their
+    // latency overlaps that plane's stencil work.
+    float w[RY][2 * HALO + 1];
 #pragma unroll
-    for (int k = 0; k < 2 * HALO; ++k) w[k] = at(cur, (uint32_t)(zc0 - HALO + k + GH) * PS + col);
+    for (int r = 0; r < RY; ++r)
+#pragma unroll
+        for (int k = 0; k < 2 * HALO; ++k) w[r][k] = at(cur, (uint32_t)(zc0 - HALO + k + GH) * PS + col[r]);
     const int zend = min(zc0 + TZC, a.nzp);
-    float nw, nh[2], nc, nd;   // the next plane's loads
+    float nw[RY], nc[RY], nd[RY], nh[2];   // the next plane's loads
     {
         const uint32_t pz = (uint32_t)(zc0 + GH) * PS;
-        nw = at(cur, pz + 4u * PS + col);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            nw[r] = at(cur, pz + 4u * PS + col[r]);
+            nc[r] = at(a.c2, pz + col[r]);
+            nd[r] = at(din, pz + col[r]);
+        }
 #pragma unroll
         for (int k = 0; k < 2; ++k) nh[k] = hl[k] >= 0 ? at(cur, pz + ho[k]) : 0.f;
-        nc = at(a.c2, pz + col);
-        nd = at(din, pz + col);
     }
     double acc = 0.0;
     for (int z = zc0; z < zend; ++z) {
         const int lz = z - zc0;
         const uint32_t pz = (uint32_t)(z + GH) * PS;
-        w[2 * HALO] = nw;
         float* Pb = P[lz & 1];
-        Pb[(ly + HALO) * PW + lx + HALO] = w[HALO];
+        float c2v[RY], dv[RY];
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            w[r][2 * HALO] = nw[r];
+            Pb[(ly + r * WY + HALO) * PW + lx + HALO] = w[r][HALO];
+            c2v[r] = nc[r];
+            dv[r] = nd[r];
+        }
 #pragma unroll
         for (int k = 0; k < 2; ++k)
             if (hl[k] >= 0) Pb[hl[k]] = nh[k];
-        // this plane's loads
-        const uint32_t so = pz + col;
-        const float c2v = nc;
-        const float dv = nd;
-        const float kap = kxy + at(a.kz, (uint32_t)min(z, a.nzp - 1));
+        // this plane's dense loads
+        const float kz = at(a.kz, (uint32_t)min(z, a.nzp - 1));
         const int iz = z - a.nb;
-        const bool ph = xyphys && iz >= 0 && iz < a.nz;
-        const uint32_t pi = ph ? (uint32_t)((iz * a.ny + iy) * a.nx + ix) : 0u;
-        float q = 0.f;
-        if constexpr ((FL & F_SRC_DENSE) != 0) q = ph ? at(dsrc, pi) : 0.f;
-        float po = 0.f, xo = 0.f;
-        if constexpr ((FL & F_CG_FUSE) != 0) {
-            po = at(cgp, pi);
-            xo = at(cgx, pi);
-            q = ph ? fmaf(bet, po, at(cgr, pi)) : 0.f;
+        bool ph[RY];
+        uint32_t pi[RY];
+        float q[RY], po[RY], xo[RY], pv[RY], stv[RY], rv[RY];
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            ph[r] = xyphys[r] && iz >= 0 && iz < a.nz;
+            pi[r] = ph[r] ? (uint32_t)((iz * a.ny + iy[r]) * a.nx + ix) : 0u;
+            q[r] = 0.f; po[r] = 0.f; xo[r] = 0.f; pv[r] = 0.f; stv[r] = 0.f; rv[r] = 0.f;
+            if constexpr ((FL & F_SRC_DENSE) != 0) q[r] = ph[r] ? at(dsrc, pi[r]) : 0.f;
+            if constexpr ((FL & F_CG_FUSE) != 0) {
+                po[r] = at(cgp, pi[r]);
+                xo[r] = at(cgx, pi[r]);
+                q[r] = ph[r] ? fmaf(bet, po[r], at(cgr, pi[r])) : 0.f;
+            }
+            if constexpr ((FL & F_NORMAL) != 0) pv[r] = at(dp, pi[r]);
+            if constexpr ((FL & F_NORMAL) != 0 && (FL & F_RUPD) != 0) rv[r] = at(rw, pi[r]);
+            if constexpr ((FL & F_CORR) != 0) stv[r] = at(store, pi[r]);
         }
-        float pv = 0.f, stv = 0.f, rv = 0.f;
-        if constexpr ((FL & F_NORMAL) != 0) pv = at(dp, pi);
-        if constexpr ((FL & F_NORMAL) != 0 && (FL & F_RUPD) != 0) rv = at(rw, pi);
-        if constexpr ((FL & F_CORR) != 0) stv = at(store, pi);
         bool inj_here = false;
         if constexpr ((FL & F_INJ) != 0) {
             // entries are sorted by cell, i.e. by plane first
             if (ie < iend && a.inj_cell[ie] / (TX * TY) == lz) {
                 inj_here = true;
                 __syncthreads();                  // the last injection plane has been read
-                sinj[tid] = 0.f;
+                for (int i = tid; i < TX * TY; i += NTH) sinj[i] = 0.f;
                 __syncthreads();
                 int e = ie + tid;
                 while (e < iend && a.inj_cell[e] / (TX * TY) == lz) {
@@ -210,85 +237,97 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
         }
         if (z + 1 < zend) {   // uniform over the workgroup
             const uint32_t pn = pz + PS;
-            nw = at(cur, pn + 4u * PS + col);
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                nw[r] = at(cur, pn + 4u * PS + col[r]);
+                nc[r] = at(a.c2, pn + col[r]);
+                nd[r] = at(din, pn + col[r]);
+            }
 #pragma unroll
             for (int k = 0; k < 2; ++k) nh[k] = hl[k] >= 0 ? at(cur, pn + ho[k]) : 0.f;
-            nc = at(a.c2, pn + col);
-            nd = at(din, pn + col);
         }
         __syncthreads();
-        const float* cp = Pb + (ly + HALO) * PW + lx + HALO;
-        const float cv = w[HALO];
-        float lx_ = a.w1 * ((cp[-1] - cv) + (cp[1] - cv));
-        lx_ = fmaf(a.w2, (cp[-2] - cv) + (cp[2] - cv), lx_);
-        lx_ = fmaf(a.w3, (cp[-3] - cv) + (cp[3] - cv), lx_);
-        lx_ = fmaf(a.w4, (cp[-4] - cv) + (cp[4] - cv), lx_);
-        float ly_ = a.w1 * ((cp[-PW] - cv) + (cp[PW] - cv));
-        ly_ = fmaf(a.w2, (cp[-2 * PW] - cv) + (cp[2 * PW] - cv), ly_);
-        ly_ = fmaf(a.w3, (cp[-3 * PW] - cv) + (cp[3 * PW] - cv), ly_);
-        ly_ = fmaf(a.w4, (cp[-4 * PW] - cv) + (cp[4 * PW] - cv), ly_);
-        float lz_ = a.w1 * ((w[3] - cv) + (w[5] - cv));
-        lz_ = fmaf(a.w2, (w[2] - cv) + (w[6] - cv), lz_);
-        lz_ = fmaf(a.w3, (w[1] - cv) + (w[7] - cv), lz_);
-        lz_ = fmaf(a.w4, (w[0] - cv) + (w[8] - cv), lz_);
-        const float lap = (lx_ + ly_) + lz_;
-        const int cell = lz * TX * TY + ly * TX + lx;
-        const float qd = q;   // the extended (dense) part of the source
-        if constexpr ((FL & F_SRC_POINT) != 0) {
-            if (cell == src_cell) q += src_val;
-        }
-        if constexpr ((FL & F_INJ) != 0) {
-            if (inj_here) q += sinj[tid];
-        }
-        const float lq = fmaf(a.dx2, q, lap);
-        const float dn = fmaf(c2v, lq, (1.f - kap) * dv) * __builtin_amdgcn_rcpf(1.f + kap);
-        const float un = cv + dn;
-        // cells past the padded grid sit in the zero ghost frame and compute 0
-        at(dnx, so) = dn;
-        at(nxt, so) = un;
-        if (ph) {
-            if constexpr ((FL & F_CG_FUSE) != 0) {
-                at(cgpn, pi) = q;
-                if (alp != 0.f) at(cgx, pi) = fmaf(alp, po, xo);
-            }
-            if constexpr ((FL & F_OUT) != 0) at(dout, pi) = un;
-            if constexpr ((FL & F_SRC_REC) != 0) {
-                if (cell == src_cell) a.src_rec[(int64_t)s * a.nt + a.step] = un;
-            }
-            float wb = 0.f;
-            if constexpr ((FL & (F_NORMAL | F_PENALTY | F_RUPD)) != 0) {
-                if (a.w_identity) {
-                    wb = a.beta;
-                } else {
-                    // the hardware square root (within 1 ulp; the argument is
-                    // a sum of squared integers, never denormal)
-                    const float ddx = (float)ix - sx, ddy = (float)iy - sy, ddz = (float)iz - sz;
-                    const float bb = __builtin_amdgcn_sqrtf(ddx * ddx + ddy * ddy + ddz * ddz) + a.b_eps;
-                    wb = a.beta * (bb * bb);
-                }
-            }
-            if constexpr ((FL & F_CG_FUSE) != 0 && (FL & F_RUPD) != 0)
-                acc += (double)(q * (wb * q));   // beta B^2 p.p of the new direction
-            if constexpr ((FL & F_NORMAL) != 0) {
-                const float np = fmaf(wb, pv, un);
-                if constexpr ((FL & F_RUPD) != 0) {   // r -= alpha N p, as a separate pass would
-                    const float rn = fmaf(-ral, np, rv);
-                    at(rw, pi) = rn;
-                    acc += (double)(rn * rn);
-                } else {
-                    at(dout, pi) = np;
-                    acc += (double)pv * (double)np;
-                }
-            }
-            if constexpr ((FL & F_PENALTY) != 0) {
-                at(gacc, pi) = fmaf(wb * qd, c2v * a.inv_dt2 * lq, at(gacc, pi));
-                acc += (double)(wb * qd) * (double)qd;   // penalty term (kept when a.part is set)
-            }
-            if constexpr ((FL & F_STORE) != 0) at(store, pi) = c2v * a.inv_dt2 * lq;
-            if constexpr ((FL & F_CORR) != 0) at(gacc, pi) = fmaf(un, stv, at(gacc, pi));
-        }
 #pragma unroll
-        for (int k = 0; k < 2 * HALO; ++k) w[k] = w[k + 1];
+        for (int r = 0; r < RY; ++r) {
+            const int yl = ly + r * WY;                     // row within the block
+            const float* cp = Pb + (yl + HALO) * PW + lx + HALO;
+            const float cv = w[r][HALO];
+            float lx_ = a.w1 * ((cp[-1] - cv) + (cp[1] - cv));
+            lx_ = fmaf(a.w2, (cp[-2] - cv) + (cp[2] - cv), lx_);
+            lx_ = fmaf(a.w3, (cp[-3] - cv) + (cp[3] - cv), lx_);
+            lx_ = fmaf(a.w4, (cp[-4] - cv) + (cp[4] - cv), lx_);
+            float ly_ = a.w1 * ((cp[-PW] - cv) + (cp[PW] - cv));
+            ly_ = fmaf(a.w2, (cp[-2 * PW] - cv) + (cp[2 * PW] - cv), ly_);
+            ly_ = fmaf(a.w3, (cp[-3 * PW] - cv) + (cp[3 * PW] - cv), ly_);
+            ly_ = fmaf(a.w4, (cp[-4 * PW] - cv) + (cp[4 * PW] - cv), ly_);
+            float lz_ = a.w1 * ((w[r][3] - cv) + (w[r][5] - cv));
+            lz_ = fmaf(a.w2, (w[r][2] - cv) + (w[r][6] - cv), lz_);
+            lz_ = fmaf(a.w3, (w[r][1] - cv) + (w[r][7] - cv), lz_);
+            lz_ = fmaf(a.w4, (w[r][0] - cv) + (w[r][8] - cv), lz_);
+            const float lap = (lx_ + ly_) + lz_;
+            const int pcell = yl * TX + lx;                 // cell within the plane
+            const int cell = lz * TX * TY + pcell;
+            float qq = q[r];
+            const float qd = qq;   // the extended (dense) part of the source
+            if constexpr ((FL & F_SRC_POINT) != 0) {
+                if (cell == src_cell) qq += src_val;
+            }
+            if constexpr ((FL & F_INJ) != 0) {
+                if (inj_here) qq += sinj[pcell];
+            }
+            const float kap = kxy[r] + kz;
+            const float lq = fmaf(a.dx2, qq, lap);
+            const float dn = fmaf(c2v[r], lq, (1.f - kap) * dv[r]) * __builtin_amdgcn_rcpf(1.f + kap);
+            const float un = cv + dn;
+            // cells past the padded grid sit in the zero ghost frame and compute 0
+            const uint32_t so = pz + col[r];
+            at(dnx, so) = dn;
+            at(nxt, so) = un;
+            if (ph[r]) {
+                const uint32_t pr = pi[r];
+                if constexpr ((FL & F_CG_FUSE) != 0) {
+                    at(cgpn, pr) = qq;
+                    if (alp != 0.f) at(cgx, pr) = fmaf(alp, po[r], xo[r]);
+                }
+                if constexpr ((FL & F_OUT) != 0) at(dout, pr) = un;
+                if constexpr ((FL & F_SRC_REC) != 0) {
+                    if (cell == src_cell) a.src_rec[(int64_t)s * a.nt + a.step] = un;
+                }
+                float wb = 0.f;
+                if constexpr ((FL & (F_NORMAL | F_PENALTY | F_RUPD)) != 0) {
+                    if (a.w_identity) {
+                        wb = a.beta;
+                    } else {
+                        // the hardware square root (within 1 ulp; the argument
+                        // is a sum of squared integers, never denormal)
+                        const float ddx = (float)ix - sx, ddy = (float)iy[r] - sy, ddz = (float)iz - sz;
+                        const float bb = __builtin_amdgcn_sqrtf(ddx * ddx + ddy * ddy + ddz * ddz) + a.b_eps;
+                        wb = a.beta * (bb * bb);
+                    }
+                }
+                if constexpr ((FL & F_CG_FUSE) != 0 && (FL & F_RUPD) != 0)
+                    acc += (double)(qq * (wb * qq));   // beta B^2 p.p of the new direction
+                if constexpr ((FL & F_NORMAL) != 0) {
+                    const float np = fmaf(wb, pv[r], un);
+                    if constexpr ((FL & F_RUPD) != 0) {   // r -= alpha N p, as a separate pass would
+                        const float rn = fmaf(-ral, np, rv[r]);
+                        at(rw, pr) = rn;
+                        acc += (double)(rn * rn);
+                    } else {
+                        at(dout, pr) = np;
+                        acc += (double)pv[r] * (double)np;
+                    }
+                }
+                if constexpr ((FL & F_PENALTY) != 0) {
+                    at(gacc, pr) = fmaf(wb * qd, c2v[r] * a.inv_dt2 * lq, at(gacc, pr));
+                    acc += (double)(wb * qd) * (double)qd;   // penalty term (kept when a.part is set)
+                }
+                if constexpr ((FL & F_STORE) != 0) at(store, pr) = c2v[r] * a.inv_dt2 * lq;
+                if constexpr ((FL & F_CORR) != 0) at(gacc, pr) = fmaf(un, stv[r], at(gacc, pr));
+            }
+#pragma unroll
+            for (int k = 0; k < 2 * HALO; ++k) w[r][k] = w[r][k + 1];
+        }
     }
 
     if constexpr ((FL & (F_NORMAL | F_PENALTY | F_RUPD)) != 0) {
