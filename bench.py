@@ -378,6 +378,7 @@ def dataspace_run(args, torch, dev):
     d_obs = plan_true.forward(wav, esi.SRC_POINT, shot0=0, nshots=ns)
     plan_true.close()
     plan = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_start).to(dev))
+    plan.set_ds_ckpt(args.ds_ckpt)
     plan.autotune(nshots=ns)
     q = plan.new_vec(ns)
     plan.ds_cg_solve(d_obs, 1, nshots=ns, q=q)                 # warm-up: every kernel once
@@ -394,16 +395,27 @@ def dataspace_run(args, torch, dev):
     q_misfit = float(torch.linalg.vector_norm((d_q - d_obs).double()) / torch.linalg.vector_norm(d_obs.double()))
     w_misfit = float(torch.linalg.vector_norm((w - d_obs).double()) / torch.linalg.vector_norm(d_obs.double()))
     plan.close()
-    props = 2 * (args.cg_iters + 1) + 1
+    K = min(args.ds_ckpt, cfg.nt)
+    # an operator application: adjoint + forward, plus the recompute of the
+    # adjoint field when it is checkpointed (the first pass skips the last segment)
+    per_apply = 2 + ((cfg.nt - K) / cfg.nt if K > 0 else 0)
+    props = per_apply * (args.cg_iters + 1) + 1
     name, rec = max(prof.items(), key=lambda kv: kv[1]["ms"])
     dl = int(d_obs.numel())
+    if K > 0:
+        nseg = -(-cfg.nt // K)
+        field = {"adjoint_field": f"checkpointed every {K} steps",
+                 "segment_buffer_gb": round(ns * K * cfg.nz * cfg.nx * 4 / 1e9, 2),
+                 "checkpoints_gb": round(ns * nseg * 2 * npad * 4 / 1e9, 2)}
+    else:
+        field = {"adjoint_field": "resident",
+                 "adjoint_field_buffer_gb": round(ns * cfg.nt * cfg.nz * cfg.nx * 4 / 1e9, 1)}
     return {"workload": "dataspace-" + cfg.name, "shots": ns, "nt": cfg.nt, "beta": cfg.beta,
-            "cg_iters": args.cg_iters, "propagations_per_shot": props, "seconds": round(wall, 3),
+            "cg_iters": args.cg_iters, "propagations_per_shot": round(props, 2), "seconds": round(wall, 3),
             "gpts_per_s": round(ns * props * npad * cfg.nt / wall / 1e9, 2),
             "cg_final_rel_residual_max": float(np.max(rep["res_hist"][:, -1])),
             "data_misfit_w": round(w_misfit, 6), "data_misfit_Sq": round(q_misfit, 6),
-            "cg_vectors_gb": round(4 * dl * 4 / 1e9, 3),
-            "adjoint_field_buffer_gb": round(ns * cfg.nt * cfg.nz * cfg.nx * 4 / 1e9, 1),
+            "cg_vectors_gb": round(4 * dl * 4 / 1e9, 3), **field,
             "time_domain_cg_vectors_gb": round(4 * ns * cfg.nt * cfg.nz * cfg.nx * 4 / 1e9, 1),
             "dominant_loop": {"variant": name, "launches": rec["launches"], "ms": round(rec["ms"], 1)}}
 
@@ -463,6 +475,8 @@ def main():
     ap.add_argument("--no-dtft", action="store_true", help="skip the DTFT-variant run")
     ap.add_argument("--no-dataspace", action="store_true", help="skip the data-space solver run")
     ap.add_argument("--dtft-nf", type=int, default=8)
+    ap.add_argument("--ds-ckpt", type=int, default=0,
+                    help="data-space leg: checkpoint the adjoint field every K steps (0: resident)")
     ap.add_argument("--dtft-block", type=int, default=-1,
                     help="DTFT steps per block (0: slices met at every step; default: the library's 64)")
     ap.add_argument("--invert-iters", type=int, default=2)

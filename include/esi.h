@@ -423,6 +423,19 @@ esi_status_t esi_ds_cg_solve(esi_plan_t plan, int32_t shot0, int32_t nshots, con
                              float* q, float* work, int32_t max_iter, double rtol, esi_cg_report_t* rep);
 
 /*
+ * Storage of the adjoint field inside esi_ds_cg_solve (Sec. 5.1 names
+ * checkpointing as the remedy for the memory that field takes).  every = 0
+ * (default): the field of the whole time axis stays resident (nshots * nt *
+ * phys floats).  every = K > 0: one adjoint pass saves the adjoint state every
+ * K steps (nshots * ceil(nt / K) * 2 padded fields), and before the forward
+ * pass runs each K-step segment the segment's field is recomputed from the
+ * checkpoint above it into a K-step buffer (nshots * K * phys floats): one
+ * more adjoint propagation per operator application, results identical bit
+ * for bit.  ESI_ERR_ARG for a null plan or every < 0.
+ */
+esi_status_t esi_plan_set_ds_ckpt(esi_plan_t plan, int32_t every);
+
+/*
  * Chain rule from m = 1/v^2 to v: grad_v = -2 grad_m / v^3 on the physical
  * grid (device [phys] each; grad_v may alias grad_m).
  */

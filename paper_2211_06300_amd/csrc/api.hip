@@ -16,8 +16,6 @@ esi_status_t launch_step3d(Plan* P, unsigned flags, const StepArgs& a);
 void step3d_tile_shape(int* tx, int* ty, int* tz);
 esi_status_t launch_dot(Plan* P, const float* x, const float* y, int nshots, int64_t len,
                         double* out);
-esi_status_t launch_copy_shots(Plan* P, float* dst, int64_t dst_stride, const float* src,
-                               int64_t src_stride, int64_t n, int nshots);
 esi_status_t launch_fill_d(Plan* P, double* p, int64_t n);
 
 esi_status_t check_shots(Plan* P, int shot0, int nshots) {

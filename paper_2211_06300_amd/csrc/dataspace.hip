@@ -122,8 +122,63 @@ __global__ void k_ds_scale_q(float* __restrict__ q, const float* __restrict__ wi
 
 int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + NT - 1) / NT, 8192)); }
 
+// y = S W^{-1} S^T x with the adjoint field checkpointed: one adjoint pass
+// saves the adjoint state (mu, its increment) after every step j = kK, k >= 1;
+// then, segment by segment in forward time, the segment's field is recomputed
+// from the checkpoint above it into a K-step buffer and the forward pass runs
+// the segment with it as its source.  The same kernels run on the same
+// states, so y equals the resident-field result bit for bit.
+esi_status_t K_apply_ckpt(Plan* P, const TileLists* L, int shot0, int ns, const float* x, float* y,
+                          const int* active) {
+    const int nt = P->nt, K = std::min(P->ds_ckpt, nt), nseg = (nt + K - 1) / K;
+    const int64_t cstr = (int64_t)nseg * 2 * P->fsize;       // floats per shot of ds_ck
+    ESI_TRY(grow_t(&P->ds_ck, &P->ds_ck_cap, (int64_t)ns * cstr, P->stream));
+    ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
+    StepArgs a = base_args(P, L, shot0, ns);
+    a.active = active;
+    a.inj_data = x;
+    int cs = 0;
+    for (int k = nseg - 1; k >= 1; --k) {
+        ESI_TRY(adjoint_loop(P, a, F_INJ, P->ring, &cs, k * K, std::min(nt, (k + 1) * K)));
+        ESI_TRY(launch_copy_shots(P, P->ds_ck + (int64_t)k * 2 * P->fsize, cstr, P->ring + (int64_t)cs * P->fsize,
+                                  RING * P->fsize, P->fsize, ns));
+        ESI_TRY(launch_copy_shots(P, P->ds_ck + (int64_t)k * 2 * P->fsize + P->fsize, cstr,
+                                  P->ring + (int64_t)(2 + cs) * P->fsize, RING * P->fsize, P->fsize, ns));
+    }
+    ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
+    StepArgs b = base_args(P, L, shot0, ns);
+    b.active = active;
+    b.inj_data = x;
+    b.dout = P->ds_mu;
+    b.blk_T = K;
+    StepArgs f = base_args(P, L, shot0, ns);
+    f.active = active;
+    f.dsrc = P->ds_mu;
+    f.blk_T = K;
+    f.cg_s = P->ds_winv;
+    f.gat_data = y;
+    int fcs = 0;
+    for (int k = 0; k < nseg; ++k) {
+        const int j0 = k * K, j1 = std::min(nt, j0 + K);
+        // the adjoint state after step j1 into slot 0 of the recompute ring
+        // (zero above the last step)
+        ESI_TRY(ring_for(P, &P->ring2, &P->ring2_cap, ns));
+        if (k + 1 < nseg) {
+            ESI_TRY(launch_copy_shots(P, P->ring2, RING * P->fsize, P->ds_ck + (int64_t)(k + 1) * 2 * P->fsize, cstr,
+                                      P->fsize, ns));
+            ESI_TRY(launch_copy_shots(P, P->ring2 + 2 * P->fsize, RING * P->fsize,
+                                      P->ds_ck + (int64_t)(k + 1) * 2 * P->fsize + P->fsize, cstr, P->fsize, ns));
+        }
+        int rcs = 0;
+        ESI_TRY(adjoint_loop(P, b, F_INJ | F_OUT, P->ring2, &rcs, j0, j1));
+        ESI_TRY(forward_loop(P, f, F_SRC_DENSE | F_SCALE | F_GATHER, P->ring, &fcs, j0, j1));
+    }
+    return launch_final_gather(P, P->ring + (int64_t)fcs * P->fsize, RING * P->fsize, y, shot0, ns);
+}
+
 // y = S W^{-1} S^T x (data vectors of the call's shots)
 esi_status_t K_apply(Plan* P, const TileLists* L, int shot0, int ns, const float* x, float* y, const int* active) {
+    if (P->ds_ckpt > 0) return K_apply_ckpt(P, L, shot0, ns, x, y, active);
     ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
     StepArgs a = base_args(P, L, shot0, ns);
     a.active = active;
@@ -147,6 +202,14 @@ esi_status_t K_apply(Plan* P, const TileLists* L, int shot0, int ns, const float
 
 using namespace esi;
 
+extern "C" esi_status_t esi_plan_set_ds_ckpt(esi_plan_t plan, int32_t every) {
+    set_error("");
+    if (!plan) return fail(ESI_ERR_ARG, "null plan");
+    if (every < 0) return fail(ESI_ERR_ARG, "checkpoint interval must be >= 0");
+    ((Plan*)plan)->ds_ckpt = every;
+    return ESI_OK;
+}
+
 extern "C" esi_status_t esi_ds_cg_solve(esi_plan_t plan, int32_t shot0, int32_t ns, const float* d, float* w,
                                         float* q, float* work, int32_t max_iter, double rtol,
                                         esi_cg_report_t* rep) {
@@ -164,7 +227,8 @@ extern "C" esi_status_t esi_ds_cg_solve(esi_plan_t plan, int32_t shot0, int32_t 
     TileLists* L;
     ESI_TRY(lists_for(P, &L));
     const int64_t fl = (int64_t)ns * P->nt * P->nphys;
-    ESI_TRY(grow_t(&P->ds_mu, &P->ds_mu_cap, fl, P->stream));
+    const int64_t mu_len = (int64_t)ns * (P->ds_ckpt > 0 ? std::min(P->ds_ckpt, P->nt) : P->nt) * P->nphys;
+    ESI_TRY(grow_t(&P->ds_mu, &P->ds_mu_cap, mu_len, P->stream));
     ESI_TRY(grow_t(&P->ds_winv, &P->ds_winv_cap, (int64_t)ns * P->nphys, P->stream));
     ESI_TRY(grow_t(&P->ds_seg, &P->ds_seg_cap, (int64_t)ns + 1, P->stream));
     ESI_TRY(grow_t(&P->part, &P->part_cap, (int64_t)DB * ns, P->stream));

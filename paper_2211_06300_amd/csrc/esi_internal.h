@@ -84,6 +84,11 @@ struct Plan {
     // data-space solver scratch: adjoint field [nshots][nt][phys], W^{-1}
     // [nshots][phys], data segment offsets [nshots + 1]
     float* ds_mu = nullptr; int64_t ds_mu_cap = 0;
+    // ds_ckpt > 0: the adjoint field is not kept whole; the adjoint state is
+    // checkpointed every ds_ckpt steps into ds_ck [nshots][segments][2][fsize]
+    // and each segment's field recomputed into ds_mu [nshots][ds_ckpt][phys]
+    int ds_ckpt = 0;
+    float* ds_ck = nullptr; int64_t ds_ck_cap = 0;
     float* ds_winv = nullptr; int64_t ds_winv_cap = 0;
     int64_t* ds_seg = nullptr; int64_t ds_seg_cap = 0;
     int nzp = 0, nyp = 1, nxp = 0;       // padded grid
@@ -299,6 +304,9 @@ esi_status_t launch_final_gather(Plan* P, const float* field, int64_t fstride, f
 // ---- vector kernels (vec.hip) ---------------------------------------------
 esi_status_t launch_fill(Plan* P, float* p, int64_t n, float v);
 esi_status_t launch_copy(Plan* P, float* dst, const float* src, int64_t n);
+// per shot s < nshots: dst[s * dst_stride + i] = src[s * src_stride + i], i < n
+esi_status_t launch_copy_shots(Plan* P, float* dst, int64_t dst_stride, const float* src,
+                               int64_t src_stride, int64_t n, int nshots);
 // r -= alpha_s Np (float32), partial r.r (float64) per block into part;
 // then reduce into out[s].  Vectors are [nshots][len].
 esi_status_t launch_r_update(Plan* P, float* r, const float* Ap, const double* alpha,

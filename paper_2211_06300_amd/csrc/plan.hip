@@ -342,7 +342,7 @@ static void free_plan(Plan* P) {
                     P->dscr, P->dscr2, P->part, P->scal, P->gshot, P->store, P->ckpt, P->flags,
                     P->d_rec, P->cgi, P->cg_hist, P->vphys, P->d_win, P->fcg_s, P->fcg_a, P->fcg_g,
                     P->fcg_in, P->fcg_o, P->fcg_d, P->fcg_i, P->dft_tw, P->dft_C, P->ds_mu, P->ds_winv,
-                    P->ds_seg, P->dft_blk};
+                    P->ds_seg, P->dft_blk, P->ds_ck};
     for (void* b : bufs)
         if (b) hipFree(b);
     delete P;

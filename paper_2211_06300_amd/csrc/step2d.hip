@@ -918,6 +918,7 @@ esi_status_t dispatch2d(Plan* P, unsigned flags, const StepArgs& a) {
         ESI_CASE(F_SRC_DENSE | F_SCALE | F_GATHER)
         ESI_CASE(F_DTFT_SRC | F_PENALTY)
         ESI_CASE(F_INJ | F_DTFT_ACC)
+        ESI_CASE(F_INJ)
         ESI_CASE(F_INJ | F_OUT)
         ESI_CASE(F_INJ | F_NORMAL)
         ESI_CASE(F_INJ | F_NORMAL | F_RUPD)

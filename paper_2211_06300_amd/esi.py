@@ -77,7 +77,8 @@ EXPORTS = ["esi_plan_create", "esi_plan_set_model", "esi_plan_destroy", "esi_las
            "esi_fpcg_solve", "esi_precond_features", "esi_unet_loss_weights", "esi_plan_autotune",
            "esi_plan_set_weight", "esi_data_residual", "esi_wri_gradient", "esi_plan_set_beta",
            "esi_invert", "esi_dtft_set_freqs", "esi_dtft_normal_apply", "esi_dtft_rhs", "esi_dtft_cg_solve",
-           "esi_dtft_to_time", "esi_dtft_gradient", "esi_ds_cg_solve", "esi_plan_set_dtft_block"]
+           "esi_dtft_to_time", "esi_dtft_gradient", "esi_ds_cg_solve", "esi_plan_set_dtft_block",
+           "esi_plan_set_ds_ckpt"]
 # time-step kernel variants (bit set of fused work), as in include/esi.h
 K_FLAGS = {1: "SRC_POINT", 2: "SRC_DENSE", 4: "CG_FUSE", 8: "INJ", 16: "GATHER", 32: "OUT",
            64: "NORMAL", 128: "PENALTY", 256: "STORE", 512: "CORR", 1024: "SRC_REC",
@@ -122,6 +123,7 @@ def load_library(path: str = LIB_PATH):
     L.esi_plan_set_cg_graph.argtypes = [vp, i32]
     L.esi_plan_set_cg_rfuse.argtypes = [vp, i32]
     L.esi_plan_set_dtft_block.argtypes = [vp, i32]
+    L.esi_plan_set_ds_ckpt.argtypes = [vp, i32]
     L.esi_plan_autotune.argtypes = [vp, i32, i32, vp, vp, i32, vp]
     L.esi_forward_ckpt.argtypes = [vp, i32, i32, i32, vp, vp, i32]
     L.esi_grad_velocity.argtypes = [vp, vp, vp, vp]
@@ -395,6 +397,10 @@ class Plan:
 
     def set_cg_graph(self, enable: bool):
         _check(self._lib.esi_plan_set_cg_graph(self._h, int(bool(enable))))
+
+    def set_ds_ckpt(self, every: int):
+        """Data-space solver: adjoint field resident (0) or checkpointed every `every` steps."""
+        _check(self._lib.esi_plan_set_ds_ckpt(self._h, int(every)))
 
     def set_dtft_block(self, block: int):
         """DTFT time loops meet the frequency slices per `block` steps (0: at every step)."""

@@ -112,6 +112,29 @@ def test_dataspace_cg_wri(esi):
     plan.close()
 
 
+@pytest.mark.parametrize("tb", [1, 2])
+def test_dataspace_ckpt_bitwise(esi, tb):
+    """The adjoint field checkpointed every K steps (K dividing nt or not, K odd,
+    K above nt) gives the resident-field solve bit for bit: w, q and the
+    residual history."""
+    cfg = _cfg()
+    mt = core.make_model(core.Grid(2, cfg.nz, cfg.nx, nb=cfg.nb, nt=cfg.nt, dx=cfg.dx, dt=cfg.dt), cfg.v_true)
+    d_obs = [core.forward(mt, cfg.wavelet.astype(np.float64), cfg.shot_rec(s), src_pos=cfg.src[s])
+             .astype(np.float32) for s in range(cfg.nshots)]
+    flat = torch.from_numpy(np.concatenate([d.ravel() for d in d_obs])).to(DEV)
+    outs = []
+    for every in (0, 7, 10, 64):
+        plan = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_start).to(DEV))
+        plan.set_time_block(tb)
+        plan.set_ds_ckpt(every)
+        w, q, rep = plan.ds_cg_solve(flat, 4)
+        outs.append((w, q, torch.from_numpy(np.asarray(rep["res_hist"]))))
+        plan.close()
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert torch.equal(a, b)
+
+
 def test_dataspace_errors(esi):
     cfg = _cfg(nt=20)
     plan = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_true).to(DEV))
@@ -119,4 +142,6 @@ def test_dataspace_errors(esi):
     plan.set_beta(0.0)
     with pytest.raises(esi.EsiError):
         plan.ds_cg_solve(d, 2)
+    with pytest.raises(esi.EsiError):
+        plan.set_ds_ckpt(-1)
     plan.close()
