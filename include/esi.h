@@ -375,8 +375,9 @@ esi_status_t esi_invert(esi_plan_t plan, int32_t shot0, int32_t nshots, const fl
  * esi_dtft_gradient: Algorithm 2's PENALTY gradient with the time-domain source
  *   q = G x formed on the fly (lambda = beta W q, u = A^{-1} q), summed over
  *   the shots and ADDED to grad_m (device [phys]).
- * Each returns ESI_ERR_ARG when esi_dtft_set_freqs has not been called or the
- * plan is 3D.
+ * Each returns ESI_ERR_ARG when esi_dtft_set_freqs has not been called, or on
+ * a 3D plan set to meet the slices at every step (esi_plan_set_dtft_block
+ * with 0: that path lives inside the 2D stencil kernel).
  */
 esi_status_t esi_dtft_set_freqs(esi_plan_t plan, int32_t nf, const double* freqs_hz);
 esi_status_t esi_dtft_normal_apply(esi_plan_t plan, int32_t shot0, int32_t nshots, const float* p,
@@ -406,7 +407,7 @@ esi_status_t esi_plan_set_dtft_block(esi_plan_t plan, int32_t block);
 
 /*
  * Data-space solution of the normal equation (Sec. 5.1, eq. (vd), eq. (wv),
- * eq. (q): the Sherman-Morrison-Woodbury route), 2D plans, beta > 0:
+ * eq. (q): the Sherman-Morrison-Woodbury route), beta > 0:
  *   CG (Algorithm 1, per shot, FP64 dots) on (beta I + S W^{-1} S^T) w = v,
  *   v = S W^{-1} S^T d, with W = B^T B of the plan (I for ESI_WEIGHT_IDENTITY);
  *   then, when q != NULL, q = (beta W)^{-1} S^T (d - w).
@@ -416,8 +417,8 @@ esi_status_t esi_plan_set_dtft_block(esi_plan_t plan, int32_t block);
  * d, w: device data of the shots (layout of esi_forward's data); w receives
  * the synthetic data.  q: device [nshots][nt][phys] or NULL.  work: device,
  * 3 data vectors.  rep as esi_cg_solve (residuals of the data-space system).
- * ESI_ERR_ARG for a 3D plan, beta <= 0, shots without receivers, or null
- * pointers; ESI_ERR_BREAKDOWN / ESI_ERR_NONFINITE as esi_cg_solve.
+ * 2D and 3D plans.  ESI_ERR_ARG for beta <= 0, shots without receivers, or
+ * null pointers; ESI_ERR_BREAKDOWN / ESI_ERR_NONFINITE as esi_cg_solve.
  */
 esi_status_t esi_ds_cg_solve(esi_plan_t plan, int32_t shot0, int32_t nshots, const float* d, float* w,
                              float* q, float* work, int32_t max_iter, double rtol, esi_cg_report_t* rep);

@@ -27,10 +27,11 @@ __device__ __forceinline__ double block_sum(double v, double* sm) {
     return t;
 }
 
-// W^{-1} per cell of each shot: 1 / B^2, or 1 for B = I
-__global__ void k_winv(const int32_t* __restrict__ src, int shot0, int ns, int nz, int nx, double b_eps,
+// W^{-1} per cell of each shot: 1 / B^2, or 1 for B = I (cells [nz][ny][nx],
+// ny = 1 in 2D, where the source's third coordinate is 0)
+__global__ void k_winv(const int32_t* __restrict__ src, int shot0, int ns, int nz, int ny, int nx, double b_eps,
                        int identity, float* __restrict__ out) {
-    const int64_t n = (int64_t)nz * nx;
+    const int64_t n = (int64_t)nz * ny * nx;
     for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < ns * n; i += (int64_t)gridDim.x * NT) {
         const int k = (int)(i / n);
         const int64_t c = i - k * n;
@@ -38,9 +39,11 @@ __global__ void k_winv(const int32_t* __restrict__ src, int shot0, int ns, int n
             out[i] = 1.f;
             continue;
         }
-        const int iz = (int)(c / nx), ix = (int)(c - (int64_t)iz * nx);
-        const double dx = ix - src[(shot0 + k) * 3 + 0], dz = iz - src[(shot0 + k) * 3 + 1];
-        const double b = sqrt(dx * dx + dz * dz) + b_eps;
+        const int64_t zy = c / nx;
+        const int ix = (int)(c - zy * nx), iz = (int)(zy / ny), iy = (int)(zy - (int64_t)iz * ny);
+        const double dx = ix - src[(shot0 + k) * 3 + 0], dz = iz - src[(shot0 + k) * 3 + 1],
+                     dy = iy - src[(shot0 + k) * 3 + 2];
+        const double b = sqrt(dx * dx + dz * dz + dy * dy) + b_eps;
         out[i] = (float)(1.0 / (b * b));
     }
 }
@@ -217,7 +220,6 @@ extern "C" esi_status_t esi_ds_cg_solve(esi_plan_t plan, int32_t shot0, int32_t 
     if (!plan) return fail(ESI_ERR_ARG, "null plan");
     Plan* P = (Plan*)plan;
     ESI_TRY(check_shots(P, shot0, ns));
-    if (P->ndim != 2) return fail(ESI_ERR_ARG, "the data-space solver runs on 2D plans");
     const int64_t dl = data_len(P, shot0, ns);
     if (dl == 0) return fail(ESI_ERR_ARG, "the shots record no data");
     if (!d || !w || !work) return fail(ESI_ERR_ARG, "null pointer");
@@ -237,7 +239,7 @@ extern "C" esi_status_t esi_ds_cg_solve(esi_plan_t plan, int32_t shot0, int32_t 
     for (int s = 0; s <= ns; ++s) seg[s] = (int64_t)P->nt * (P->h_rec_ptr[shot0 + s] - P->h_rec_ptr[shot0]);
     ESI_HIP_TRY(hipMemcpyAsync(P->ds_seg, seg.data(), seg.size() * sizeof(int64_t), hipMemcpyHostToDevice, P->stream));
     hipLaunchKernelGGL(k_winv, dim3(grid_for((int64_t)ns * P->nphys)), dim3(NT), 0, P->stream, P->d_src, shot0, ns,
-                       P->nz, P->nx, P->b_eps, P->w_identity, P->ds_winv);
+                       P->nz, P->ny, P->nx, P->b_eps, P->w_identity, P->ds_winv);
     ESI_HIP_TRY(hipGetLastError());
     float* r = work;
     float* p = work + dl;

@@ -43,21 +43,23 @@ __device__ __forceinline__ double block_sum(double v, double* sm) {
 
 // out = acc + beta W (F G) p per cell, and part[s][b] = block sums of p . out.
 __global__ __launch_bounds__(NT) void k_dtft_finish(const float2* __restrict__ acc, const float2* __restrict__ p,
-                                                    const double* __restrict__ C, int nf, int nz, int nx,
+                                                    const double* __restrict__ C, int nf, int nz, int ny, int nx,
                                                     const int32_t* __restrict__ src, int shot0, double beta,
                                                     double b_eps, int w_identity, float2* __restrict__ out,
                                                     double* __restrict__ part) {
     __shared__ double sm[NT / 64];
     const int s = blockIdx.y, b = blockIdx.x, bps = gridDim.x;
-    const int64_t n = (int64_t)nz * nx;
+    const int64_t n = (int64_t)nz * ny * nx;
     const int64_t base = (int64_t)s * nf * n;
     double dot = 0.0;
     for (int64_t c = (int64_t)b * NT + threadIdx.x; c < n; c += (int64_t)bps * NT) {
         double w = beta;
         if (!w_identity) {
-            const int iz = (int)(c / nx), ix = (int)(c - (int64_t)iz * nx);
-            const double dx = ix - src[(shot0 + s) * 3 + 0], dz = iz - src[(shot0 + s) * 3 + 1];
-            const double bb = sqrt(dx * dx + dz * dz) + b_eps;
+            const int64_t zy = c / nx;   // cells [nz][ny][nx]; ny = 1 and source y = 0 in 2D
+            const int ix = (int)(c - zy * nx), iz = (int)(zy / ny), iy = (int)(zy - (int64_t)iz * ny);
+            const double dx = ix - src[(shot0 + s) * 3 + 0], dz = iz - src[(shot0 + s) * 3 + 1],
+                         dy = iy - src[(shot0 + s) * 3 + 2];
+            const double bb = sqrt(dx * dx + dz * dz + dy * dy) + b_eps;
             w = beta * bb * bb;
         }
         double pv[2 * MAX_NF];
@@ -210,7 +212,8 @@ __global__ void k_xp(float* __restrict__ x, float* __restrict__ p, const float* 
 
 esi_status_t need_freqs(Plan* P) {
     if (P->dft_freqs.empty() || !P->dft_tw) return fail(ESI_ERR_ARG, "no DTFT frequencies: call esi_dtft_set_freqs");
-    if (P->ndim != 2) return fail(ESI_ERR_ARG, "the DTFT variant runs on 2D plans");
+    if (P->ndim != 2 && P->dft_block <= 0)
+        return fail(ESI_ERR_ARG, "the per-step DTFT runs on 2D plans; 3D plans take blocks of steps");
     return ESI_OK;
 }
 
@@ -324,7 +327,7 @@ esi_status_t dtft_normal(Plan* P, int shot0, int ns, const float2* p, float2* Mp
     ESI_TRY(dtft_adjoint(P, b, Mp, ns));
     const int bps = (int)std::max<int64_t>(1, std::min<int64_t>(64, (P->nphys + 4095) / 4096));
     ESI_TRY(grow_t(&P->part, &P->part_cap, (int64_t)bps * ns, P->stream));
-    hipLaunchKernelGGL(k_dtft_finish, dim3(bps, ns), dim3(NT), 0, P->stream, Mp, p, P->dft_C, nf, P->nz, P->nx,
+    hipLaunchKernelGGL(k_dtft_finish, dim3(bps, ns), dim3(NT), 0, P->stream, Mp, p, P->dft_C, nf, P->nz, P->ny, P->nx,
                        P->d_src, shot0, P->beta, P->b_eps, P->w_identity, Mp, P->part);
     ESI_HIP_TRY(hipGetLastError());
     return pMp ? launch_reduce_parts(P, P->part, bps, ns, pMp) : ESI_OK;

@@ -105,8 +105,11 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
     }
 
     const int64_t vbase = ((int64_t)s * a.nt + a.step) * a.nphys;
-    const float* dsrc = (FL & F_SRC_DENSE) ? a.dsrc + vbase : nullptr;
-    float* dout = (FL & (F_OUT | F_NORMAL)) ? a.dout + vbase : nullptr;
+    // dsrc / dout hold the whole time axis, or blk_T steps (step n in slot n % blk_T)
+    const int64_t vblk = a.blk_T ? ((int64_t)s * a.blk_T + a.step % a.blk_T) * a.nphys : vbase;
+    const float* dsrc = (FL & F_SRC_DENSE) ? a.dsrc + vblk : nullptr;
+    float* dout = (FL & (F_OUT | F_NORMAL)) ? a.dout + vblk : nullptr;
+    const float* csc = ((FL & F_SRC_DENSE) && (FL & F_SCALE)) ? a.cg_s + (int64_t)s * a.nphys : nullptr;
     const float* dp = (FL & F_NORMAL) ? a.dp + vbase : nullptr;
     float* rw = ((FL & F_NORMAL) && (FL & F_RUPD)) ? a.cg_rw + vbase : nullptr;
     const float ral = ((FL & F_NORMAL) && (FL & F_RUPD)) ? (float)a.cg_alpha[s] : 0.f;
@@ -207,7 +210,10 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
             ph[r] = xyphys[r] && iz >= 0 && iz < a.nz;
             pi[r] = ph[r] ? (uint32_t)((iz * a.ny + iy[r]) * a.nx + ix) : 0u;
             q[r] = 0.f; po[r] = 0.f; xo[r] = 0.f; pv[r] = 0.f; stv[r] = 0.f; rv[r] = 0.f;
-            if constexpr ((FL & F_SRC_DENSE) != 0) q[r] = ph[r] ? at(dsrc, pi[r]) : 0.f;
+            if constexpr ((FL & F_SRC_DENSE) != 0) {
+                q[r] = ph[r] ? at(dsrc, pi[r]) : 0.f;
+                if constexpr ((FL & F_SCALE) != 0) q[r] = q[r] * at(csc, pi[r]);   // cell-scaled dense source
+            }
             if constexpr ((FL & F_CG_FUSE) != 0) {
                 po[r] = at(cgp, pi[r]);
                 xo[r] = at(cgx, pi[r]);
@@ -375,6 +381,8 @@ esi_status_t launch_step3d(Plan* P, unsigned flags, const StepArgs& a) {
         ESI_CASE(F_SRC_POINT | F_SRC_DENSE | F_STORE)
         ESI_CASE(F_CG_FUSE | F_GATHER)
         ESI_CASE(F_CG_FUSE | F_GATHER | F_RUPD)
+        ESI_CASE(F_SRC_DENSE | F_SCALE | F_GATHER)
+        ESI_CASE(F_INJ)
         ESI_CASE(F_INJ | F_OUT)
         ESI_CASE(F_INJ | F_NORMAL)
         ESI_CASE(F_INJ | F_NORMAL | F_RUPD)

@@ -127,6 +127,78 @@ def test_3d_cg_fused_residual(esi):
         plan.close()
 
 
+def _cplx(a):
+    return a[..., 0].astype(np.float64) + 1j * a[..., 1].astype(np.float64)
+
+
+def _rel_c(a, b):
+    a = np.asarray(a).astype(np.complex128).ravel()
+    b = np.asarray(b).astype(np.complex128).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_3d_dtft(esi):
+    """The DTFT variant on a 3D plan, slices met per block of steps (the
+    per-step path is 2D only and refused here): M p within 1e-5 and 3 CG
+    iterations within 1e-4 of the oracle."""
+    from oracle import dtft
+    cfg = _cfg3(nt=40)
+    g, m = _model(cfg)
+    freqs = np.array([20.0, 45.0, 70.0])
+    plan = _plan(esi, cfg)
+    plan.dtft_set_freqs(freqs)
+    plan.set_dtft_block(16)
+    p = inputs.random_field(plan.dtft_shape(cfg.nshots), 46)
+    Mp, pMp = plan.dtft_normal_apply(torch.from_numpy(p).to(DEV))
+    Mp = Mp.cpu().numpy()
+    for s in range(cfg.nshots):
+        ref = dtft.normal_apply(m, cfg.shot_rec(s), core.annihilator_sq(g, tuple(cfg.src[s])), cfg.beta,
+                                _cplx(p[s]), freqs)
+        assert _rel_c(_cplx(Mp[s]), ref) < 1e-5, s
+    d_obs = [core.forward(m, cfg.wavelet.astype(np.float64), cfg.shot_rec(s), src_pos=cfg.src[s])
+             .astype(np.float32) for s in range(cfg.nshots)]
+    flat = torch.from_numpy(np.concatenate([d.ravel() for d in d_obs])).to(DEV)
+    x, rep = plan.dtft_cg_solve(flat, 3)
+    x = x.cpu().numpy()
+    for s in range(cfg.nshots):
+        ref = dtft.cg(m, tuple(cfg.src[s]), cfg.shot_rec(s), d_obs[s].astype(np.float64), cfg.beta, freqs, 3)
+        assert _rel_c(_cplx(x[s]), ref.x) < 1e-4, s
+    plan.set_dtft_block(0)
+    with pytest.raises(esi.EsiError):
+        plan.dtft_normal_apply(torch.from_numpy(p).to(DEV))
+    plan.close()
+
+
+def test_3d_dataspace(esi):
+    """The data-space solver on a 3D plan: w within 1e-4 of the oracle after 4
+    iterations, q from the GPU's own w within 1e-5, and the checkpointed
+    adjoint field bit for bit equal to the resident one."""
+    from oracle import dataspace
+    cfg = _cfg3(nt=30)
+    g, m = _model(cfg)
+    v0 = (cfg.v_true * 1.03).astype(np.float32)
+    _, m0 = _model(cfg, v0)
+    d_obs = [core.forward(m, cfg.wavelet.astype(np.float64), cfg.shot_rec(s), src_pos=cfg.src[s])
+             .astype(np.float32) for s in range(cfg.nshots)]
+    flat = torch.from_numpy(np.concatenate([d.ravel() for d in d_obs])).to(DEV)
+    outs = []
+    for every in (0, 7):
+        plan = esi.Plan.from_config(cfg, vel=torch.from_numpy(v0).to(DEV))
+        plan.set_ds_ckpt(every)
+        outs.append(plan.ds_cg_solve(flat, 4))
+        plan.close()
+    w, q, rep = outs[0]
+    assert torch.equal(w, outs[1][0]) and torch.equal(q, outs[1][1])
+    w, q = w.cpu().numpy(), q.cpu().numpy()
+    for s, ws in enumerate(_split(cfg, w)):
+        d64 = d_obs[s].astype(np.float64)
+        rw, rq, res = dataspace.cg(m0, tuple(cfg.src[s]), cfg.shot_rec(s), d64, cfg.beta, 4)
+        assert _rel(ws, rw) < 1e-4, s
+        w2 = core.annihilator_sq(g, tuple(cfg.src[s]))
+        q_of_w = core.adjoint(m0, cfg.shot_rec(s), d64 - ws.astype(np.float64)) / (cfg.beta * w2[None])
+        assert _rel(q[s], q_of_w) < 1e-5, s
+
+
 def test_3d_gradient_seed_ckpt(esi):
     cfg = _cfg3(nt=60)
     plan = _plan(esi, cfg)
