@@ -138,56 +138,100 @@ __global__ void k_to_time(const float2* __restrict__ xb, const float2* __restric
     }
 }
 
+// The block kernels give a thread CPT cells 64 apart (a wave then moves runs
+// of 64 * CPT consecutive floats of a time step) and take a cell's frequency
+// slices in registers; CPT shrinks as the frequency count grows.
+
 // q[s][n % K][c] = inv_nt sum_m (re_m cos + im_m sin)(w_m t_n), n in [n0, n1):
 // the step kernel's per-step source, the frequencies in the same order.
-template <int NFC>
+template <int NFC, int CPT>
 __global__ __launch_bounds__(NT) void k_dtft_qgen(const float2* __restrict__ xb, const float2* __restrict__ tw,
                                                   int nf, int n0, int n1, int K, int64_t n,
                                                   const int* __restrict__ active, float inv_nt,
                                                   float* __restrict__ q) {
     const int s = blockIdx.y;
     if (active && !active[s]) return;   // uniform over the block
-    for (int64_t c = blockIdx.x * (int64_t)NT + threadIdx.x; c < n; c += (int64_t)gridDim.x * NT) {
-        float2 v[NFC];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int64_t c0 = ((int64_t)blockIdx.x * (NT / 64) + wv) * 64 * CPT + lane; c0 < n;
+         c0 += (int64_t)gridDim.x * NT * CPT) {
+        float2 v[CPT][NFC];
+        bool on[CPT];
 #pragma unroll
-        for (int m = 0; m < NFC; ++m) v[m] = m < nf ? xb[((int64_t)s * nf + m) * n + c] : make_float2(0.f, 0.f);
-        for (int t = n0; t < n1; ++t) {
-            const float2* __restrict__ w = tw + (int64_t)t * nf;
-            float acc = 0.f;
+        for (int j = 0; j < CPT; ++j) {
+            on[j] = c0 + 64 * j < n;
 #pragma unroll
             for (int m = 0; m < NFC; ++m)
-                if (m < nf) acc = fmaf(v[m].y, w[m].y, fmaf(v[m].x, w[m].x, acc));
-            q[((int64_t)s * K + t % K) * n + c] = acc * inv_nt;
+                v[j][m] = (on[j] && m < nf) ? xb[((int64_t)s * nf + m) * n + c0 + 64 * j] : make_float2(0.f, 0.f);
+        }
+        for (int t = n0; t < n1; ++t) {
+            const float2* __restrict__ w = tw + (int64_t)t * nf;
+            float* __restrict__ qt = q + ((int64_t)s * K + t % K) * n + c0;
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                float acc = 0.f;
+#pragma unroll
+                for (int m = 0; m < NFC; ++m)
+                    if (m < nf) acc = fmaf(v[j][m].y, w[m].y, fmaf(v[j][m].x, w[m].x, acc));
+                if (on[j]) qt[64 * j] = acc * inv_nt;
+            }
         }
     }
 }
 
 // acc_m[s][c] += mu^j (cos, sin)(w_m t_j) for j = j1-1 down to j0, mu^j in
-// slot j % K: the step kernel's per-step accumulation, in the same order.
-template <int NFC>
+// slot j % K: the step kernel's per-step accumulation, in the same order.  U
+// steps of mu are loaded before they are folded in.
+template <int NFC, int CPT>
 __global__ __launch_bounds__(NT) void k_dtft_bacc(float2* __restrict__ acc, const float* __restrict__ mu,
                                                   const float2* __restrict__ tw, int nf, int j0, int j1, int K,
                                                   int64_t n, const int* __restrict__ active) {
+    constexpr int U = 4;
     const int s = blockIdx.y;
     if (active && !active[s]) return;   // uniform over the block
-    for (int64_t c = blockIdx.x * (int64_t)NT + threadIdx.x; c < n; c += (int64_t)gridDim.x * NT) {
-        float2 v[NFC];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int64_t c0 = ((int64_t)blockIdx.x * (NT / 64) + wv) * 64 * CPT + lane; c0 < n;
+         c0 += (int64_t)gridDim.x * NT * CPT) {
+        float2 v[CPT][NFC];
+        bool on[CPT];
 #pragma unroll
-        for (int m = 0; m < NFC; ++m) v[m] = m < nf ? acc[((int64_t)s * nf + m) * n + c] : make_float2(0.f, 0.f);
-        for (int j = j1 - 1; j >= j0; --j) {
-            const float u = mu[((int64_t)s * K + j % K) * n + c];
-            const float2* __restrict__ w = tw + (int64_t)j * nf;
+        for (int j = 0; j < CPT; ++j) {
+            on[j] = c0 + 64 * j < n;
 #pragma unroll
-            for (int m = 0; m < NFC; ++m) {
-                if (m < nf) {
-                    v[m].x = fmaf(u, w[m].x, v[m].x);
-                    v[m].y = fmaf(u, w[m].y, v[m].y);
+            for (int m = 0; m < NFC; ++m)
+                v[j][m] = (on[j] && m < nf) ? acc[((int64_t)s * nf + m) * n + c0 + 64 * j] : make_float2(0.f, 0.f);
+        }
+        for (int jt = j1 - 1; jt >= j0; jt -= U) {
+            float u[U][CPT];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int jj = jt - k;
+                const float* __restrict__ mt = mu + ((int64_t)s * K + (jj >= j0 ? jj % K : 0)) * n + c0;
+#pragma unroll
+                for (int j = 0; j < CPT; ++j) u[k][j] = (on[j] && jj >= j0) ? mt[64 * j] : 0.f;
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                if (jt - k < j0) break;   // uniform over the block
+                const float2* __restrict__ w = tw + (int64_t)(jt - k) * nf;
+#pragma unroll
+                for (int j = 0; j < CPT; ++j) {
+#pragma unroll
+                    for (int m = 0; m < NFC; ++m) {
+                        if (m < nf) {
+                            v[j][m].x = fmaf(u[k][j], w[m].x, v[j][m].x);
+                            v[j][m].y = fmaf(u[k][j], w[m].y, v[j][m].y);
+                        }
+                    }
                 }
             }
         }
 #pragma unroll
-        for (int m = 0; m < NFC; ++m)
-            if (m < nf) acc[((int64_t)s * nf + m) * n + c] = v[m];
+        for (int j = 0; j < CPT; ++j) {
+            if (!on[j]) continue;
+#pragma unroll
+            for (int m = 0; m < NFC; ++m)
+                if (m < nf) acc[((int64_t)s * nf + m) * n + c0 + 64 * j] = v[j][m];
+        }
     }
 }
 
@@ -219,39 +263,39 @@ esi_status_t need_freqs(Plan* P) {
 
 int dft_block(Plan* P) { return P->dft_block > 0 ? std::min(P->dft_block, P->nt) : 0; }
 
+template <int CPT>
 dim3 cell_grid(Plan* P, int ns) {
-    return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((P->nphys + NT - 1) / NT, 1024)), (unsigned)ns);
+    const int64_t per = (int64_t)NT * CPT;
+    return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((P->nphys + per - 1) / per, 1024)), (unsigned)ns);
 }
 
 esi_status_t launch_qgen(Plan* P, const float2* xb, int n0, int n1, int K, int ns, const int* active, float* q) {
     const int nf = (int)P->dft_freqs.size();
     const float inv_nt = (float)(1.0 / P->nt);
-    const dim3 g = cell_grid(P, ns);
     if (nf <= 8)
-        hipLaunchKernelGGL(k_dtft_qgen<8>, g, dim3(NT), 0, P->stream, xb, P->dft_tw, nf, n0, n1, K, P->nphys, active,
-                           inv_nt, q);
+        hipLaunchKernelGGL((k_dtft_qgen<8, 4>), cell_grid<4>(P, ns), dim3(NT), 0, P->stream, xb, P->dft_tw, nf, n0,
+                           n1, K, P->nphys, active, inv_nt, q);
     else if (nf <= 16)
-        hipLaunchKernelGGL(k_dtft_qgen<16>, g, dim3(NT), 0, P->stream, xb, P->dft_tw, nf, n0, n1, K, P->nphys, active,
-                           inv_nt, q);
+        hipLaunchKernelGGL((k_dtft_qgen<16, 2>), cell_grid<2>(P, ns), dim3(NT), 0, P->stream, xb, P->dft_tw, nf, n0,
+                           n1, K, P->nphys, active, inv_nt, q);
     else
-        hipLaunchKernelGGL(k_dtft_qgen<MAX_NF>, g, dim3(NT), 0, P->stream, xb, P->dft_tw, nf, n0, n1, K, P->nphys,
-                           active, inv_nt, q);
+        hipLaunchKernelGGL((k_dtft_qgen<MAX_NF, 1>), cell_grid<1>(P, ns), dim3(NT), 0, P->stream, xb, P->dft_tw, nf,
+                           n0, n1, K, P->nphys, active, inv_nt, q);
     ESI_HIP_TRY(hipGetLastError());
     return ESI_OK;
 }
 
 esi_status_t launch_bacc(Plan* P, float2* acc, const float* mu, int j0, int j1, int K, int ns, const int* active) {
     const int nf = (int)P->dft_freqs.size();
-    const dim3 g = cell_grid(P, ns);
     if (nf <= 8)
-        hipLaunchKernelGGL(k_dtft_bacc<8>, g, dim3(NT), 0, P->stream, acc, mu, P->dft_tw, nf, j0, j1, K, P->nphys,
-                           active);
+        hipLaunchKernelGGL((k_dtft_bacc<8, 4>), cell_grid<4>(P, ns), dim3(NT), 0, P->stream, acc, mu, P->dft_tw, nf,
+                           j0, j1, K, P->nphys, active);
     else if (nf <= 16)
-        hipLaunchKernelGGL(k_dtft_bacc<16>, g, dim3(NT), 0, P->stream, acc, mu, P->dft_tw, nf, j0, j1, K, P->nphys,
-                           active);
+        hipLaunchKernelGGL((k_dtft_bacc<16, 2>), cell_grid<2>(P, ns), dim3(NT), 0, P->stream, acc, mu, P->dft_tw, nf,
+                           j0, j1, K, P->nphys, active);
     else
-        hipLaunchKernelGGL(k_dtft_bacc<MAX_NF>, g, dim3(NT), 0, P->stream, acc, mu, P->dft_tw, nf, j0, j1, K,
-                           P->nphys, active);
+        hipLaunchKernelGGL((k_dtft_bacc<MAX_NF, 1>), cell_grid<1>(P, ns), dim3(NT), 0, P->stream, acc, mu, P->dft_tw,
+                           nf, j0, j1, K, P->nphys, active);
     ESI_HIP_TRY(hipGetLastError());
     return ESI_OK;
 }
