@@ -10,6 +10,23 @@ def test_alg_bytes_two_step_counts_both_steps():
     assert bench.bytes_per_shot_launch(20 | bench.TWO_STEP, 1000, 800) == 2 * one
 
 
+def test_alg_bytes_fused_residual():
+    """The fused residual update adds r's read and write to the adjoint pass
+    (12 B per physical point with p's read, where N p's write was 4 of the 8)
+    and nothing to the forward pass."""
+    R = bench.RUPD
+    assert bench.bytes_per_shot_launch(72 | R, 1000, 800) == 16 * 1000 + 12 * 800
+    assert bench.bytes_per_shot_launch(20 | R, 1000, 800) == bench.bytes_per_shot_launch(20, 1000, 800)
+
+
+def test_committed_summary_has_the_dominant_kernel():
+    """The committed counter summary lists the fused forward and adjoint
+    variants of the main leg."""
+    text = open(bench.TRAFFIC_FILE).read()
+    rows = {line.split("|")[1].strip() for line in text.splitlines() if line.startswith("| ")}
+    assert {str(20 | bench.RUPD), str(72 | bench.RUPD)} <= rows
+
+
 def test_measured_traffic_lookup(tmp_path):
     h = bench.kernel_source_hash()
     text = "\n".join([
@@ -35,6 +52,6 @@ def test_measured_traffic_lookup(tmp_path):
 
 
 def test_committed_summary_parses():
-    v = bench.measured_traffic(20 | bench.TWO_STEP, 16.0)
+    v = bench.measured_traffic(20 | bench.RUPD | bench.TWO_STEP, 16.0)
     assert v is None or v > 0
     assert os.path.exists(bench.TRAFFIC_FILE)
