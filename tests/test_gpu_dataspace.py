@@ -128,7 +128,10 @@ def test_dataspace_ckpt_bitwise(esi, tb):
         plan.set_time_block(tb)
         plan.set_ds_ckpt(every)
         w, q, rep = plan.ds_cg_solve(flat, 4)
-        outs.append((w, q, torch.from_numpy(np.asarray(rep["res_hist"]))))
+        w2, _, rep2 = plan.ds_cg_solve(flat, 10, rtol=0.05, want_q=False)   # shots leave at different iterations
+        outs.append((w, q, torch.from_numpy(np.asarray(rep["res_hist"])), w2,
+                     torch.from_numpy(np.asarray(rep2["res_hist"])),
+                     torch.from_numpy(np.asarray(rep2["shot_iters"]))))
         plan.close()
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
