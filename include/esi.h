@@ -482,7 +482,7 @@ esi_status_t esi_plan_set_cg_graph(esi_plan_t plan, int32_t enable);
 
 /*
  * CG iterations (Algorithm 1) with the residual update fused into the normal
- * operator; on by default.  From iteration 1 on, p_k . N p_k is
+ * operator; on by default.  In every iteration p_k . N p_k is
  * taken as ||S p_k||^2 + beta ||B p_k||^2 from the forward pass (the two are
  * equal in exact arithmetic, S being the receiver data of the forward
  * modelling and N = S^T S + beta B^2), so alpha_k is known before the adjoint

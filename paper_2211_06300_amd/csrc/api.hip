@@ -261,17 +261,18 @@ esi_status_t do_normal(Plan* P, int shot0, int ns, const float* p, float* Ap, co
     return adjoint_loop(P, b, F_INJ | F_NORMAL, P->ring, &cs, 0, P->nt);
 }
 
-// Iteration k >= 1 of Algorithm 1 with the residual update fused into
-// the normal operator.  The forward pass forms p_k = r_k + beta p_{k-1} into
-// pnew and x_k = x_{k-1} + alpha p_{k-1}, records S p_k and the partials of
-// beta B^2 p_k . p_k; with p_k . N p_k = ||S p_k||^2 + beta ||B p_k||^2 the
+// Iteration k of Algorithm 1 with the residual update fused into the normal
+// operator.  For k >= 1 the forward pass forms p_k = r_k + beta p_{k-1} into
+// pnew and x_k = x_{k-1} + alpha p_{k-1}; for k = 0 (first) it takes p = p_0
+// as its dense source and pnew is unused.  It records S p_k and the partials
+// of beta B^2 p_k . p_k; with p_k . N p_k = ||S p_k||^2 + beta ||B p_k||^2 the
 // step length is known before the adjoint pass, which then takes
 // r_{k+1} = r_k - alpha_k N p_k cell by cell in place, with the partials of
 // ||r_{k+1}||^2.  N p_k is never stored: per step, the adjoint reads r and
 // writes it back instead of writing N p for a separate pass to read.
 esi_status_t do_normal_rupd(Plan* P, int shot0, int ns, const float* p, float* pnew, const TileLists* L,
                             const int* active, float* r, float* x, double* alpha, const double* beta,
-                            const double* rr, double* pAp, double* rr_new) {
+                            const double* rr, double* pAp, double* rr_new, bool first) {
     const int64_t dl = data_len(P, shot0, ns);
     ESI_TRY(grow_t(&P->dscr, &P->dscr_cap, std::max<int64_t>(dl, 1), P->stream));
     ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
@@ -284,11 +285,15 @@ esi_status_t do_normal_rupd(Plan* P, int shot0, int ns, const float* p, float* p
     StepArgs a = base_args(P, L, shot0, ns);
     a.active = active;
     a.gat_data = P->dscr;
-    a.cg_r = r; a.cg_p = p; a.cg_pn = pnew; a.cg_x = x; a.cg_alpha = alpha; a.cg_beta = beta;
+    if (first) {
+        a.dsrc = p;
+    } else {
+        a.cg_r = r; a.cg_p = p; a.cg_pn = pnew; a.cg_x = x; a.cg_alpha = alpha; a.cg_beta = beta;
+    }
     a.part = P->part;
     a.part_stride = P->part_stride;
     int cs = 0;
-    ESI_TRY(forward_loop(P, a, F_CG_FUSE | F_GATHER | F_RUPD, P->ring, &cs, 0, P->nt));
+    ESI_TRY(forward_loop(P, a, (first ? F_SRC_DENSE : F_CG_FUSE) | F_GATHER | F_RUPD, P->ring, &cs, 0, P->nt));
     ESI_TRY(launch_final_gather(P, P->ring + (int64_t)cs * P->fsize, RING * P->fsize, P->dscr,
                                 shot0, ns));
     ESI_TRY(launch_reduce_parts(P, P->part, P->part_stride, ns, pAp));
@@ -298,7 +303,7 @@ esi_status_t do_normal_rupd(Plan* P, int shot0, int ns, const float* p, float* p
     StepArgs b = base_args(P, L, shot0, ns);
     b.active = active;
     b.inj_data = P->dscr;
-    b.dp = pnew;
+    b.dp = first ? p : pnew;
     b.cg_rw = r;
     b.cg_alpha = alpha;
     b.part = P->part;
@@ -383,13 +388,14 @@ struct CgState {
 // The caller swaps p and Ap after every iteration k >= 1.
 esi_status_t cg_iteration(Plan* P, const CgState& c, int k, const float* p, float* Ap) {
     const float* dir = p;
-    if (k >= 1 && P->cg_rfuse) {
+    if (P->cg_rfuse) {
         ESI_TRY(do_normal_rupd(P, c.shot0, c.ns, p, Ap, c.L, c.active, c.r, c.x, c.alpha, c.beta, c.rr,
-                               c.pAp, c.rr_new));
+                               c.pAp, c.rr_new, k == 0));
         ESI_TRY(launch_cg_control(P, c.rr0, c.rr_new, c.pAp, c.active, c.finish, c.iters, c.status,
                                   c.hist, c.max_iter + 1, c.ctl, c.rtol, c.max_iter, c.ns));
         ESI_TRY(launch_cg_beta(P, c.rr_new, c.rr, c.beta, c.ns));
-        return launch_axpy_flag(P, c.x, Ap, c.alpha, c.finish, 1, c.ns, c.len);   // p_k lives in Ap
+        // shots leaving now take x += alpha p_k; p_k is p_0 itself at k = 0 and lives in Ap later
+        return launch_axpy_flag(P, c.x, k == 0 ? p : Ap, c.alpha, c.finish, 1, c.ns, c.len);
     }
     if (k == 0) {
         ESI_TRY(do_normal(P, c.shot0, c.ns, p, Ap, c.L, c.active, false, nullptr, c.r, c.x,

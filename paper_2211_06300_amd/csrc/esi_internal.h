@@ -292,7 +292,8 @@ enum : unsigned {
     F_DTFT_SRC = 1u << 12,   // dense source from frequency slices (inverse DTFT on the fly)
     F_DTFT_ACC = 1u << 13,   // accumulate the DTFT of the output mu^j (adjoint)
     F_RUPD = 1u << 14,       // CG residual update fused into the normal operator:
-                             // with F_CG_FUSE the partials of beta B^2 p_new . p_new;
+                             // with F_CG_FUSE (or F_SRC_DENSE: p is the dense source)
+                             // the partials of beta B^2 p . p;
                              // with F_NORMAL r -= alpha (mu^j + beta B^2 p^j) in place
                              // (cg_rw) and the partials of r . r, no dout
 };

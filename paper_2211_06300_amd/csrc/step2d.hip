@@ -233,8 +233,8 @@ __device__ __forceinline__ void cell_outputs(const StepArgs& a, const StepPtrs& 
             acc += (double)pv * (double)np;
         }
     }
-    if constexpr ((FL & F_CG_FUSE) != 0 && (FL & F_RUPD) != 0)
-        acc += (double)(q * (wb * q));   // beta B^2 p.p of the new direction
+    if constexpr ((FL & (F_CG_FUSE | F_SRC_DENSE)) != 0 && (FL & F_RUPD) != 0)
+        acc += (double)(q * (wb * q));   // beta B^2 p.p of the direction (dense source)
     if constexpr ((FL & F_PENALTY) != 0) {
         at(o.gacc, pi) = fmaf(wb * q, c2v * a.inv_dt2 * lq, at(o.gacc, pi));
         acc += (double)(wb * q) * (double)q;   // penalty term beta W q^2 (kept when a.part is set)
@@ -914,6 +914,7 @@ esi_status_t dispatch2d(Plan* P, unsigned flags, const StepArgs& a) {
         ESI_CASE(F_CG_FUSE | F_GATHER)
         ESI_CASE(F_CG_FUSE | F_GATHER | F_SCALE)
         ESI_CASE(F_CG_FUSE | F_GATHER | F_RUPD)
+        ESI_CASE(F_SRC_DENSE | F_GATHER | F_RUPD)
         ESI_CASE(F_DTFT_SRC | F_GATHER)
         ESI_CASE(F_SRC_DENSE | F_SCALE | F_GATHER)
         ESI_CASE(F_DTFT_SRC | F_PENALTY)

@@ -311,8 +311,8 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
                         wb = a.beta * (bb * bb);
                     }
                 }
-                if constexpr ((FL & F_CG_FUSE) != 0 && (FL & F_RUPD) != 0)
-                    acc += (double)(qq * (wb * qq));   // beta B^2 p.p of the new direction
+                if constexpr ((FL & (F_CG_FUSE | F_SRC_DENSE)) != 0 && (FL & F_RUPD) != 0)
+                    acc += (double)(qd * (wb * qd));   // beta B^2 p.p of the direction (dense source)
                 if constexpr ((FL & F_NORMAL) != 0) {
                     const float np = fmaf(wb, pv[r], un);
                     if constexpr ((FL & F_RUPD) != 0) {   // r -= alpha N p, as a separate pass would
@@ -381,6 +381,7 @@ esi_status_t launch_step3d(Plan* P, unsigned flags, const StepArgs& a) {
         ESI_CASE(F_SRC_POINT | F_SRC_DENSE | F_STORE)
         ESI_CASE(F_CG_FUSE | F_GATHER)
         ESI_CASE(F_CG_FUSE | F_GATHER | F_RUPD)
+        ESI_CASE(F_SRC_DENSE | F_GATHER | F_RUPD)
         ESI_CASE(F_SRC_DENSE | F_SCALE | F_GATHER)
         ESI_CASE(F_INJ)
         ESI_CASE(F_INJ | F_OUT)
