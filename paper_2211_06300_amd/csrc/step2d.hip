@@ -38,9 +38,6 @@ namespace {
 #ifndef ESI_MINW
 #define ESI_MINW 1
 #endif
-#ifndef ESI_MINW2
-#define ESI_MINW2 1
-#endif
 constexpr int TX = ESI_TX;   // tile width: WX waves of 64 lanes side by side
 constexpr int WX = TX / 64;
 constexpr int WZ = 4 / WX;   // waves stacked along z (4 waves per workgroup)
@@ -491,21 +488,23 @@ constexpr int B_RZ = T2Z / 4;                     // second-step rows per wave
 constexpr int U0W = T2W + 4 * HALO, U0H = T2Z + 4 * HALO;   // 72 x 48
 static_assert(A_W == 64 && A_H % 4 == 0 && U0H % 4 == 0, "two-step tile geometry");
 
+// Occupancy targets: five waves per SIMD for the injecting (adjoint)
+// variants, whose registers and LDS allow it without spilling, and at least
+// four for the others (the flexible-CG direction update would otherwise take
+// 129 VGPRs and drop to three).
 template <unsigned FL>
-__global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) {
-    // LDS: u^{tA} on the tile + 8 (dead after the first step, then holding the
-    // second step's injection), u after the first step on the tile + 4, and
-    // one buffer that holds the first step's injection until every lane has
-    // read it, then d after the first step on the tile.  Sharing keeps an
-    // injecting variant at 34 KB, four workgroups per CU.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((FL & F_INJ) != 0) ? 5 : 4)))
+void k_step2d_t2(const StepArgs a) {
+    // LDS (31 KB, five workgroups per CU): u^{tA} on the tile + 8 (dead after
+    // the first step, then holding the second step's injection), u after the
+    // first step on the tile + 4, d after the first step on the tile.  The
+    // first step's injection goes to registers.
     __shared__ float U0[U0H * U0W];
     __shared__ float U1[A_H * A_W];
-    __shared__ float SX[(FL & F_INJ) ? A_H * A_W : T2Z * T2W];
+    __shared__ float D1[T2Z * T2W];
     __shared__ double sred[4];
-    float* const D1 = SX;
-    float* const sinjA = SX;
     float* const sinjB = U0;
-    static_assert(U0H * U0W >= A_H * A_W && A_H * A_W >= T2Z * T2W, "two-step LDS sharing");
+    static_assert(U0H * U0W >= A_H * A_W, "the second step's injection fits the u^{tA} buffer");
 
     int s, t;
     work_item(a, xcd_remap(blockIdx.x, gridDim.x), &s, &t);
@@ -626,16 +625,6 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
         const int32_t* ip = a.inj2_ptr + (int64_t)gs * (a.tiles + 1);
         ibeg = ip[t];
         iend = ip[t + 1];
-        if (iend > ibeg) {
-            for (int i = tid; i < A_H * A_W; i += 256) sinjA[i] = 0.f;
-            __syncthreads();
-            const float* dj = a.inj_data + doff + (int64_t)tA * nrec_s;
-            for (int e = ibeg + tid; e < iend; e += 256) {
-                float v = 0.f;
-                for (int k = a.inj2_rptr[e]; k < a.inj2_rptr[e + 1]; ++k) v += dj[a.inj2_rid[k]];
-                sinjA[a.inj2_cell[e]] = v;
-            }
-        }
     }
     __syncthreads();
 
@@ -665,13 +654,26 @@ __global__ __launch_bounds__(256, ESI_MINW2) void k_step2d_t2(const StepArgs a) 
         if (lz >= 0 && lz < T2Z && lx >= 0 && lx < T2W) srcB = lz * T2W + lx;
     }
 
-    // the first step's injection into registers: D1 takes its buffer below
+    // the first step's injection straight into registers: every lane walks the
+    // tile's entries (uniform loads) and keeps those of its own column, so the
+    // injecting variants need no LDS plane for it
     float injA[(FL & F_INJ) ? A_RZ : 1];
     if constexpr ((FL & F_INJ) != 0) {
-        if (iend > ibeg) {   // uniform over the workgroup
 #pragma unroll
-            for (int i = 0; i < A_RZ; ++i) injA[i] = sinjA[(zra + i) * A_W + lane];
-            __syncthreads();
+        for (int i = 0; i < A_RZ; ++i) injA[i] = 0.f;
+        if (iend > ibeg) {   // uniform over the workgroup
+            const float* dj = a.inj_data + doff + (int64_t)tA * nrec_s;
+            for (int e = ibeg; e < iend; ++e) {
+                const int cell = a.inj2_cell[e];
+                const int zr = cell / A_W, col = cell - zr * A_W;
+                float v = 0.f;
+                for (int k = a.inj2_rptr[e]; k < a.inj2_rptr[e + 1]; ++k) v += dj[a.inj2_rid[k]];
+                if (col == lane) {
+#pragma unroll
+                    for (int i = 0; i < A_RZ; ++i)
+                        if (zr == zra + i) injA[i] = v;
+                }
+            }
         }
     }
 
