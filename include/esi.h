@@ -350,7 +350,7 @@ esi_status_t esi_invert(esi_plan_t plan, int32_t shot0, int32_t nshots, const fl
 
 /*
  * Frequency-domain ESI with time-domain modelling (Sec. 5.2, eq. (dtft),
- * eq. (idtft), eq. (normaldtft)), 2D plans.  Frequency vectors are device
+ * eq. (idtft), eq. (normaldtft)), 2D and 3D plans.  Frequency vectors are device
  * float32 arrays [nshots][nf][phys][2] of (re, im) pairs: the DTFT
  * (F u)_m = sum_n u_n exp(+j 2 pi f_m n dt) of a [nt][phys] field at the
  * plan's nf frequencies.  G s = (1/nt) Re sum_m s_m exp(-j 2 pi f_m n dt) is
