@@ -526,15 +526,21 @@ void k_step2d_t2(const StepArgs a) {
     const StepPtrs oA = step_ptrs(a, s, tA, vA, a.store_slot);
     const StepPtrs oB = step_ptrs(a, s, tB, vB, a.store_slot2);
 
-    // U0 (r, c) <- padded (z0 - 8 + r, x0 - 8 + c) = storage (z0 + r, x0 + c)
+    // U0 (r, c) <- padded (z0 - 8 + r, x0 - 8 + c) = storage (z0 + r, x0 + c).
+    // Cells off the padded grid sit in the zero ghost frame: they take 0
+    // without a load (the last tile column and row reach well into it).
     constexpr int RPW0 = U0H / 4;
     float tb[RPW0], th[RPW0];
     {
         const float* src = cur + (z0 + GH - 2 * HALO + wv) * XS + x0 + GH - 2 * HALO;
+        const int xb = x0 - 2 * HALO + lane, xh = x0 - 2 * HALO + 64 + (lane & 7);
+        const bool xbin = xb >= 0 && xb < a.nxp, xhin = xh >= 0 && xh < a.nxp;
 #pragma unroll
         for (int k = 0; k < RPW0; ++k) {
-            tb[k] = at(src, (uint32_t)(k * 4 * XS) + (uint32_t)lane);
-            th[k] = at(src, (uint32_t)(k * 4 * XS + 64) + (uint32_t)(lane & 7));
+            const int z = z0 - 2 * HALO + wv + 4 * k;
+            const bool zin = z >= 0 && z < a.nzp;
+            tb[k] = (zin && xbin) ? at(src, (uint32_t)(k * 4 * XS) + (uint32_t)lane) : 0.f;
+            th[k] = (zin && xhin) ? at(src, (uint32_t)(k * 4 * XS + 64) + (uint32_t)(lane & 7)) : 0.f;
         }
     }
 
@@ -826,8 +832,9 @@ void k_step2d_t2(const StepArgs a) {
         const float lq = fmaf(a.dx2, q, lap);
         const float dn = incr(c2v[i], lq, D1[zl * T2W + lc], kap);
         const float un = colB[i + HALO] + dn;
-        // cells past the padded grid sit in the zero ghost frame and compute 0
-        if (lane_on) {
+        // cells past the padded grid sit in the zero ghost frame (they would
+        // compute 0): not stored
+        if (lane_on && x < a.nxp && zb + i < a.nzp) {
             at(dnx, so0 + (uint32_t)(i * XS)) = dn;
             at(nxt, so0 + (uint32_t)(i * XS)) = un;
         }

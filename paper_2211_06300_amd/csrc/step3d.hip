@@ -69,7 +69,7 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
     const int ix = x - a.nb;
     uint32_t col[RY];
     float kxy[RY];
-    bool xyphys[RY];
+    bool xyphys[RY], cin[RY];   // cin: the column lies on the padded grid
     int iy[RY];
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
@@ -78,6 +78,7 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
         kxy[r] = at(a.kx, (uint32_t)min(x, a.nxp - 1)) + at(a.ky, (uint32_t)min(y, a.nyp - 1));
         iy[r] = y - a.nb;
         xyphys[r] = ix >= 0 && ix < a.nx && iy[r] >= 0 && iy[r] < a.ny;
+        cin[r] = x < a.nxp && y < a.nyp;
     }
     // halo cells this thread stages: LDS index and in-plane storage offset
     int hl[2];
@@ -99,8 +100,10 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
                 rx = h % (2 * HALO);
                 if (rx >= HALO) rx += TX;
             }
+            const int hx = x0 - HALO + rx, hy = y0 - HALO + ry;
+            // cells off the padded grid sit in the zero ghost frame: LDS takes 0, no load
             hl[k] = ry * PW + rx;
-            ho[k] = (uint32_t)((y0 - HALO + ry + GH) * XS + x0 - HALO + rx + GH);
+            ho[k] = (hx >= 0 && hx < a.nxp && hy >= 0 && hy < a.nyp) ? (uint32_t)((hy + GH) * XS + hx + GH) : ~0u;
         }
     }
 
@@ -169,19 +172,22 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
 #pragma unroll
     for (int r = 0; r < RY; ++r)
 #pragma unroll
-        for (int k = 0; k < 2 * HALO; ++k) w[r][k] = at(cur, (uint32_t)(zc0 - HALO + k + GH) * PS + col[r]);
+        for (int k = 0; k < 2 * HALO; ++k) {
+            const int zz = zc0 - HALO + k;
+            w[r][k] = (cin[r] && zz >= 0 && zz < a.nzp) ? at(cur, (uint32_t)(zz + GH) * PS + col[r]) : 0.f;
+        }
     const int zend = min(zc0 + TZC, a.nzp);
     float nw[RY], nc[RY], nd[RY], nh[2];   // the next plane's loads
     {
         const uint32_t pz = (uint32_t)(zc0 + GH) * PS;
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            nw[r] = at(cur, pz + 4u * PS + col[r]);
-            nc[r] = at(a.c2, pz + col[r]);
-            nd[r] = at(din, pz + col[r]);
+            nw[r] = (cin[r] && zc0 + 4 < a.nzp) ? at(cur, pz + 4u * PS + col[r]) : 0.f;
+            nc[r] = cin[r] ? at(a.c2, pz + col[r]) : 0.f;
+            nd[r] = cin[r] ? at(din, pz + col[r]) : 0.f;
         }
 #pragma unroll
-        for (int k = 0; k < 2; ++k) nh[k] = hl[k] >= 0 ? at(cur, pz + ho[k]) : 0.f;
+        for (int k = 0; k < 2; ++k) nh[k] = (hl[k] >= 0 && ho[k] != ~0u) ? at(cur, pz + ho[k]) : 0.f;
     }
     double acc = 0.0;
     for (int z = zc0; z < zend; ++z) {
@@ -245,12 +251,12 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
             const uint32_t pn = pz + PS;
 #pragma unroll
             for (int r = 0; r < RY; ++r) {
-                nw[r] = at(cur, pn + 4u * PS + col[r]);
-                nc[r] = at(a.c2, pn + col[r]);
-                nd[r] = at(din, pn + col[r]);
+                nw[r] = (cin[r] && z + 5 < a.nzp) ? at(cur, pn + 4u * PS + col[r]) : 0.f;
+                nc[r] = cin[r] ? at(a.c2, pn + col[r]) : 0.f;
+                nd[r] = cin[r] ? at(din, pn + col[r]) : 0.f;
             }
 #pragma unroll
-            for (int k = 0; k < 2; ++k) nh[k] = hl[k] >= 0 ? at(cur, pn + ho[k]) : 0.f;
+            for (int k = 0; k < 2; ++k) nh[k] = (hl[k] >= 0 && ho[k] != ~0u) ? at(cur, pn + ho[k]) : 0.f;
         }
         __syncthreads();
 #pragma unroll
@@ -285,10 +291,13 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
             const float lq = fmaf(a.dx2, qq, lap);
             const float dn = fmaf(c2v[r], lq, (1.f - kap) * dv[r]) * __builtin_amdgcn_rcpf(1.f + kap);
             const float un = cv + dn;
-            // cells past the padded grid sit in the zero ghost frame and compute 0
+            // cells past the padded grid sit in the zero ghost frame (they would
+            // compute 0): neither loaded nor stored
             const uint32_t so = pz + col[r];
-            at(dnx, so) = dn;
-            at(nxt, so) = un;
+            if (cin[r]) {
+                at(dnx, so) = dn;
+                at(nxt, so) = un;
+            }
             if (ph[r]) {
                 const uint32_t pr = pi[r];
                 if constexpr ((FL & F_CG_FUSE) != 0) {
