@@ -560,10 +560,13 @@ void k_step2d_t2(const StepArgs a) {
 #pragma unroll
     for (int i = 0; i < A_RZ; ++i) {
         const int z = z0 - HALO + zra + i;
-        cA[i] = xa_win ? at(a.c2, soA + (uint32_t)(i * XS)) : 0.f;
-        dA[i] = at(din, soA + (uint32_t)(i * XS));
-        kA[i] = kxa + at(a.kz, (uint32_t)min(max(z, 0), a.nzp - 1));
         inA[i] = xa_in && z >= 0 && z < a.nzp;
+        cA[i] = xa_win ? at(a.c2, soA + (uint32_t)(i * XS)) : 0.f;
+        // (the injecting variants load the ghost frame's zeros: the test would
+        // cost them their fifth wave's registers)
+        if constexpr ((FL & F_INJ) != 0) dA[i] = at(din, soA + (uint32_t)(i * XS));
+        else dA[i] = inA[i] ? at(din, soA + (uint32_t)(i * XS)) : 0.f;
+        kA[i] = kxa + at(a.kz, (uint32_t)min(max(z, 0), a.nzp - 1));
         const int iz = z - a.nb;
         phA[i] = xa_phys && iz >= 0 && iz < a.nz;
         piA[i] = phA[i] ? (uint32_t)(iz * a.nx + ixa) : 0u;
