@@ -96,6 +96,11 @@ def bytes_per_shot_launch(flags: int, npad: int, nphys: int) -> int:
     return b * (2 if flags & TWO_STEP else 1)
 
 
+def bench_dense_bytes(flags: int) -> int:
+    """Algorithmic dense-stream bytes per physical cell of one step of a variant."""
+    return bytes_per_shot_launch(flags & ~TWO_STEP, 0, 1)
+
+
 def cpu_baseline(cfg, nt_sample: int, iters: int = 3):
     """FP64 oracle (plain C loops, OpenMP over rows) on a bounded sample of the
     same solve: one shot, the first nt_sample steps of the time axis, the
@@ -217,12 +222,20 @@ def batching_run(args, torch, dev):
     full = cfg.nshots * (cfg.nx + 2 * cfg.nb) * (cfg.nz + 2 * cfg.nb)
     pts = 3 * cells * cfg.nt                         # forward, recompute, adjoint
     name, rec = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    # algorithmic bytes of one launch of the dominant loop over all shots' windows:
+    # 16 B per padded window cell plus the variant's dense streams per physical cell
+    phys = int(np.sum(cfg.window[:, 1] - cfg.window[:, 0]) * cfg.nz)
+    alg = (16 * cells + bench_dense_bytes(rec["flags"]) * phys) * (2 if rec["flags"] & TWO_STEP else 1)
+    per_launch_us = rec["ms"] / rec["launches"] * 1e3
+    achieved = alg / per_launch_us / 1e3
     return {"workload": cfg.name, "shots": cfg.nshots, "nt": cfg.nt, "dt": cfg.dt,
             "mean_window_columns": round(float(np.mean(cfg.window[:, 1] - cfg.window[:, 0])), 1),
             "seconds": round(wall, 3), "gpts_per_s": round(pts / wall / 1e9, 2),
             "padded_cells_all_windows": cells, "padded_cells_whole_grid_all_shots": full,
             "propagations": 3, "checkpoint_every": 50,
-            "dominant_loop": {"variant": name, "launches": rec["launches"], "ms": round(rec["ms"], 1)}}
+            "dominant_loop": {"variant": name, "launches": rec["launches"], "ms": round(rec["ms"], 1),
+                              "avg_launch_us": round(per_launch_us, 1), "alg_bytes_per_launch": int(alg),
+                              "alg_gbs": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4)}}
 
 
 def wri_run(args, torch, dev):
