@@ -209,27 +209,19 @@ __global__ void k_scale_vec(float* __restrict__ p, const float* __restrict__ r, 
 // The residual update of a flexible CG iteration, one thread per cell walking
 // the time axis: r -= alpha Np, and per cell the FP64 sums over t of r^2 (for
 // z.r and the network's input) and of r Np (for z.Np, since z = s r with s
-// constant in time).  A thread owns CPT cells 64 apart, so that a wave reads and
-// writes 64 * CPT consecutive floats of a time step (1 KB runs of each vector
-// instead of 256 B ones).  The time axis is cut into gridDim.z chunks of tcs
-// steps, so that the grid holds several rounds of resident waves, each of which
-// streams one chunk (with one chunk per thread walking all nt steps, a grid of
-// 1.6 rounds left the second round's slots idle for its whole length).  With one
-// chunk the per-cell sums go straight to en and rnp; otherwise chunk z writes
-// its partials to ep[z][s][x] and gp[z][s][x], which k_cell_fold adds in chunk
-// order.  part[s][z * bps + b] = block sums of r^2.
+// constant in time).  part[s][b] = block sums of r^2.  A thread owns CPT cells
+// 64 apart, so that a wave reads and writes 64 * CPT consecutive floats of a
+// time step (1 KB runs of each vector instead of 256 B ones).
 constexpr int CPT = 4;
 __global__ __launch_bounds__(NT) void k_r_update_cells(float* __restrict__ r, const float* __restrict__ Np,
                                                        const double* __restrict__ alpha,
-                                                       const int* __restrict__ active, int nt, int tcs,
-                                                       int64_t nphys, float* __restrict__ en,
-                                                       double* __restrict__ rnp, double* __restrict__ ep,
-                                                       double* __restrict__ gp, double* __restrict__ part) {
+                                                       const int* __restrict__ active, int nt, int64_t nphys,
+                                                       float* __restrict__ en, double* __restrict__ rnp,
+                                                       double* __restrict__ part) {
     __shared__ double sm[NT / 64];
-    const int s = blockIdx.y, b = blockIdx.x, bps = gridDim.x, z = blockIdx.z, ns = gridDim.y;
-    const int64_t pslot = (int64_t)s * bps * gridDim.z + (int64_t)z * bps + b;
+    const int s = blockIdx.y, b = blockIdx.x, bps = gridDim.x;
     if (active && !active[s]) {   // uniform over the block
-        if (threadIdx.x == 0) part[pslot] = 0.0;
+        if (threadIdx.x == 0) part[(int64_t)s * bps + b] = 0.0;
         return;
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -237,7 +229,6 @@ __global__ __launch_bounds__(NT) void k_r_update_cells(float* __restrict__ r, co
     const float al = (float)alpha[s];
     float* rs = r + (int64_t)s * nt * nphys;
     const float* as = Np + (int64_t)s * nt * nphys;
-    const int tb = z * tcs, te = min(nt, tb + tcs);
     double e[CPT], g[CPT];
     bool on[CPT];
 #pragma unroll
@@ -248,14 +239,14 @@ __global__ __launch_bounds__(NT) void k_r_update_cells(float* __restrict__ r, co
     }
     // U steps at a time: every load of the chunk is issued before its stores
     constexpr int U = 4;
-    for (int t0 = tb; t0 < te; t0 += U) {
+    for (int t0 = 0; t0 < nt; t0 += U) {
         float rv[U][CPT], av[U][CPT];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t o = (int64_t)(t0 + u) * nphys + c0;
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
-                const bool ld = on[j] && t0 + u < te;
+                const bool ld = on[j] && t0 + u < nt;
                 rv[u][j] = ld ? rs[o + 64 * j] : 0.f;
                 av[u][j] = ld ? as[o + 64 * j] : 0.f;
             }
@@ -266,47 +257,23 @@ __global__ __launch_bounds__(NT) void k_r_update_cells(float* __restrict__ r, co
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
                 const float v = fmaf(-al, av[u][j], rv[u][j]);
-                if (on[j] && t0 + u < te) rs[o + 64 * j] = v;
+                if (on[j] && t0 + u < nt) rs[o + 64 * j] = v;
                 e[j] += (double)v * (double)v;
                 g[j] += (double)v * (double)av[u][j];
             }
         }
     }
     double tot = 0.0;
-    const int64_t cs = ((int64_t)z * ns + s) * nphys;
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
         if (on[j]) {
-            if (ep) {
-                ep[cs + c0 + 64 * j] = e[j];
-                gp[cs + c0 + 64 * j] = g[j];
-            } else {
-                en[(int64_t)s * nphys + c0 + 64 * j] = (float)e[j];
-                rnp[(int64_t)s * nphys + c0 + 64 * j] = g[j];
-            }
+            en[(int64_t)s * nphys + c0 + 64 * j] = (float)e[j];
+            rnp[(int64_t)s * nphys + c0 + 64 * j] = g[j];
         }
         tot += e[j];
     }
     tot = block_sum_d(tot, sm);
-    if (threadIdx.x == 0) part[pslot] = tot;
-}
-
-// en[s][x] = sum over the nz time chunks of ep[z][s][x] (as float), rnp[s][x]
-// likewise of gp, added in chunk order; inactive shots are left as they are.
-__global__ void k_cell_fold(const double* __restrict__ ep, const double* __restrict__ gp,
-                            const int* __restrict__ active, int nz, int ns, int64_t nphys,
-                            float* __restrict__ en, double* __restrict__ rnp) {
-    const int s = blockIdx.y;
-    if (active && !active[s]) return;
-    for (int64_t x = blockIdx.x * (int64_t)NT + threadIdx.x; x < nphys; x += (int64_t)gridDim.x * NT) {
-        double e = 0.0, g = 0.0;
-        for (int z = 0; z < nz; ++z) {
-            e += ep[((int64_t)z * ns + s) * nphys + x];
-            g += gp[((int64_t)z * ns + s) * nphys + x];
-        }
-        en[(int64_t)s * nphys + x] = (float)e;
-        rnp[(int64_t)s * nphys + x] = g;
-    }
+    if (threadIdx.x == 0) part[(int64_t)s * bps + b] = tot;
 }
 
 // part[s][b] = block sums of S[s][x] g[s][x].
@@ -449,33 +416,11 @@ esi_status_t launch_scale_vec(Plan* P, float* p, const float* r, const float* S,
 esi_status_t launch_r_update_cells(Plan* P, float* r, const float* Np, const double* alpha, const int* active,
                                    int ns, float* en, double* rnp, double* rr_out) {
     const int bps = (int)((P->nphys + NT * CPT - 1) / (NT * CPT));
-    // time chunks: enough for about four rounds of resident waves (six 256-thread
-    // blocks' worth of waves per SIMD, four SIMDs per CU), at least 64 steps each,
-    // at most 8 (the per-cell partials take 16 B per chunk, shot and cell)
-    const int64_t waves = (int64_t)bps * ns * (NT / 64);
-    int dev = 0, ncu = 256;
-    ESI_HIP_TRY(hipGetDevice(&dev));
-    ESI_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    const int64_t slots = (int64_t)ncu * 4 * 6;
-    int nz = (int)std::min<int64_t>(8, std::max<int64_t>(1, (4 * slots + waves - 1) / waves));
-    nz = std::max(1, std::min(nz, P->nt / 64));
-    const int tcs = (P->nt + nz - 1) / nz;
-    nz = (P->nt + tcs - 1) / tcs;
-    const int64_t nparts = (int64_t)bps * ns * nz;
-    const int64_t off = (nparts + 63) / 64 * 64;                    // per-cell partials after the block sums
-    const int64_t cells = (int64_t)nz * ns * P->nphys;
-    ESI_TRY(grow_t(&P->part, &P->part_cap, nz > 1 ? off + 2 * cells : nparts, P->stream));
-    double* ep = nz > 1 ? P->part + off : nullptr;
-    double* gp = nz > 1 ? P->part + off + cells : nullptr;
-    hipLaunchKernelGGL(k_r_update_cells, dim3(bps, ns, nz), dim3(NT), 0, P->stream, r, Np, alpha, active, P->nt,
-                       tcs, P->nphys, en, rnp, ep, gp, P->part);
+    ESI_TRY(grow_t(&P->part, &P->part_cap, (int64_t)bps * ns, P->stream));
+    hipLaunchKernelGGL(k_r_update_cells, dim3(bps, ns), dim3(NT), 0, P->stream, r, Np, alpha, active, P->nt,
+                       P->nphys, en, rnp, P->part);
     ESI_HIP_TRY(hipGetLastError());
-    if (nz > 1) {
-        hipLaunchKernelGGL(k_cell_fold, dim3(grid_for(P->nphys), ns), dim3(NT), 0, P->stream, ep, gp, active, nz, ns,
-                           P->nphys, en, rnp);
-        ESI_HIP_TRY(hipGetLastError());
-    }
-    return launch_reduce_parts(P, P->part, (int64_t)bps * nz, ns, rr_out);
+    return launch_reduce_parts(P, P->part, bps, ns, rr_out);
 }
 
 esi_status_t launch_dot_cells(Plan* P, const float* S, const double* g, int ns, double* out) {
