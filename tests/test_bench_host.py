@@ -55,3 +55,16 @@ def test_committed_summary_parses():
     v = bench.measured_traffic(20 | bench.RUPD | bench.TWO_STEP, 16.0)
     assert v is None or v > 0
     assert os.path.exists(bench.TRAFFIC_FILE)
+
+
+def test_dense_bytes_per_cell_of_batching_variants():
+    """Dense-stream bytes per physical cell and step of the batching run's
+    variants, whatever the steps-per-launch bit: CORR|INJ (the adjoint with the
+    correlation) 12, SRC_POINT|STORE (the checkpointing forward) 4, and the
+    fused-residual adjoint 12."""
+    T = bench.TWO_STEP
+    assert bench.bench_dense_bytes(520 | T) == bench.bench_dense_bytes(520) == 12
+    assert bench.bench_dense_bytes(257) == 4
+    assert bench.bench_dense_bytes(72 | bench.RUPD) == 12
+    # a launch's algorithmic bytes split into the padded and the dense parts
+    assert bench.bytes_per_shot_launch(520 | T, 1000, 800) == 2 * (16 * 1000 + 12 * 800)
