@@ -51,6 +51,10 @@ def test_null_arguments_rejected(lib):
     assert lib.esi_normal_apply(None, 0, 1, None, None, None) == 1
     assert lib.esi_cg_solve(None, 0, 1, None, None, None, 5, 0.0, None) == 1
     assert lib.esi_gradient(None, 0, 1, 0, 1, None, None, None, None, 0) == 1
+    for setter, value in (("esi_plan_set_cg_rfuse", 1), ("esi_plan_set_dtft_block", 64),
+                          ("esi_plan_set_ds_ckpt", 50)):
+        assert getattr(lib, setter)(None, value) == 1, setter
+        assert b"null plan" in lib.esi_last_error(), setter
     assert lib.esi_plan_destroy(None) == 0
 
 
