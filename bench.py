@@ -37,31 +37,42 @@ def log(*a):
 
 # algorithmic bytes of one time-step launch, per shot: 16 B per padded point
 # (read u^n, u^{n-1}, c; write u^{n+1}) plus the dense streams of its variant
-DENSE_BYTES = {2: 4, 4: 20, 32: 4, 64: 8, 128: 8, 256: 4, 512: 12}
+# per physical point: SRC_DENSE reads q (4), CG_FUSE reads r, p, x and writes
+# p, x (20), OUT writes mu (4), NORMAL reads p and writes N p (8), STORE
+# writes (dA/dm)u (4), CORR reads it back (4).  The gradient images the
+# correlations add into (PENALTY, CORR) are accumulators, not streams of the
+# method: they count 0 (PENALTY's q read is SRC_DENSE's).
+DENSE_BYTES = {2: 4, 4: 20, 32: 4, 64: 8, 128: 0, 256: 4, 512: 4}
 
 
 TWO_STEP = 1 << 15
 RUPD = 1 << 14
 
-# HBM counter summary of the 2D time-step kernels (two rocprofv3 --pmc passes,
-# FETCH_SIZE and WRITE_SIZE, calibrated on a copy of known size)
+# HBM counter summaries of the time-step kernels (two rocprofv3 --pmc passes,
+# FETCH_SIZE and WRITE_SIZE, calibrated on a copy of known size), one per
+# workload, each tied to a hash of the kernel sources it was measured on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step2d_t2_single-solve-801x401_traffic.md")
+TRAFFIC_FILE_BATCHING = os.path.join(ROOT, "profiles", "k_step2d_t2_batching-1601x601-128shots_traffic.md")
+TRAFFIC_FILE_3D = os.path.join(ROOT, "profiles", "k_step3d_diff3d-256x256x256-8shots_traffic.md")
 KERNEL_SOURCES = ["paper_2211_06300_amd/csrc/step2d.hip", "paper_2211_06300_amd/csrc/esi_internal.h"]
+KERNEL_SOURCES_3D = ["paper_2211_06300_amd/csrc/step3d.hip", "paper_2211_06300_amd/csrc/esi_internal.h"]
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(flags: int, shots_per_launch: float, path: str = TRAFFIC_FILE):
-    """HBM bytes per launch of the 2D step variant `flags` from the committed
-    counter summary, or None when the kernel sources changed since the counters
-    were taken or the launch shape differs."""
+def measured_traffic(flags: int, shots_per_launch: float, path: str = TRAFFIC_FILE,
+                     sources=KERNEL_SOURCES, two_step: bool | None = None):
+    """HBM bytes per launch of the step variant `flags` from a committed counter
+    summary, or None when the kernel sources changed since the counters were
+    taken or the launch shape differs.  Rows name the variant's flag number
+    (without the two-step bit); a row "N (one step)" is the one-step launch."""
     try:
         with open(path) as fh:
             text = fh.read()
@@ -72,16 +83,62 @@ def measured_traffic(flags: int, shots_per_launch: float, path: str = TRAFFIC_FI
         for key in ("kernel-sources-sha256-16:", "calibration:", "shots-per-launch:"):
             if line.startswith(key):
                 meta[key] = line[len(key):].split()
-    if meta.get("kernel-sources-sha256-16:", [None])[0] != kernel_source_hash():
+    if meta.get("kernel-sources-sha256-16:", [None])[0] != kernel_source_hash(sources):
         return None
-    if float(meta["shots-per-launch:"][0]) != shots_per_launch or not flags & TWO_STEP:
+    if float(meta["shots-per-launch:"][0]) != shots_per_launch:
         return None
+    two = bool(flags & TWO_STEP) if two_step is None else two_step
+    key = str(flags & ~TWO_STEP) + ("" if two else " (one step)")
     cf, cw = float(meta["calibration:"][1]), float(meta["calibration:"][3])
     for line in text.splitlines():
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
-        if len(cells) >= 5 and cells[0] == str(flags & ~TWO_STEP):
+        if len(cells) >= 5 and cells[0] == key:
             return int((cf * float(cells[3]) + cw * float(cells[4])) * 1024)
     return None
+
+
+def copy_bandwidth(torch, dev, mib: int = 2048, reps: int = 10) -> float:
+    """Measured HBM bandwidth of a plain streaming kernel on this GPU: an
+    elementwise multiply by 1 of `mib` MiB (read and written once), GB/s."""
+    a = torch.ones(mib * 262144, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        torch.mul(a, 1.0, out=b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.mul(a, 1.0, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * mib * 1048576 / (ms * 1e-3) / 1e9
+
+
+def tune_report(esi, tuned, table):
+    """The autotuner's choice and candidate table (milliseconds of the timed
+    forward-type and adjoint-type loops per launch shape)."""
+    return {"forward": esi.LAUNCH_NAMES.get(tuned[0], str(tuned[0])),
+            "adjoint": esi.LAUNCH_NAMES.get(tuned[1], str(tuned[1])), "chosen_by": "autotuner",
+            "candidates_ms": {esi.LAUNCH_NAMES.get(sh, str(sh)): {"forward": round(f, 3), "adjoint": round(a, 3)}
+                              for sh, f, a in table}}
+
+
+def roofline(kernel: str, alg_bytes: float, launch_us: float, traffic, peak_measured):
+    """Roofline object of one kernel: algorithmic bytes per launch over the
+    average launch time against the 8 TB/s HBM peak, plus the counted HBM rate
+    when counters for this kernel and launch shape are committed."""
+    achieved = alg_bytes / launch_us / 1e3
+    out = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "alg_bytes_per_launch": int(alg_bytes), "avg_launch_us": round(launch_us, 2),
+           "hbm_frac_counted": None if traffic is None else round(traffic / launch_us / 1e3 / HBM_PEAK_GBS, 4)}
+    if peak_measured:
+        out["peak_measured"] = round(peak_measured, 1)
+        out["frac_of_measured"] = round(achieved / peak_measured, 4)
+        if traffic is not None:
+            out["hbm_frac_counted_of_measured"] = round(traffic / launch_us / 1e3 / peak_measured, 4)
+    return out
 
 
 def bytes_per_shot_launch(flags: int, npad: int, nphys: int) -> int:
@@ -119,9 +176,21 @@ def cpu_baseline(cfg, nt_sample: int, iters: int = 3):
     pts = (1 + 2 * iters) * npad * nt_sample
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": pts / t / 1e9, "unit": "GPts/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"1 shot of {cfg.nshots}, steps 0..{nt_sample - 1} of {cfg.nt}: right-hand "
                       f"side + {iters} CG iterations ({1 + 2 * iters} propagations) on the "
                       f"{cfg.nx}x{cfg.nz} grid in {t:.1f} s"}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def unet_flops(H: int, W: int) -> int:
@@ -188,7 +257,7 @@ def solver_comparison(args, torch, dev):
     return out
 
 
-def batching_run(args, torch, dev):
+def batching_run(args, torch, dev, peak_measured=None):
     """The uneven-aperture batching workload: one FWI-type gradient of all
     shots (forward keeping checkpoints every 50 steps, then the adjoint with
     segment recompute and the imaging correlation), every time step one launch
@@ -201,6 +270,12 @@ def batching_run(args, torch, dev):
     w = torch.from_numpy(np.tile(cfg.wavelet, (cfg.nshots, 1))).to(dev)
     seed = plan.forward(w, esi.SRC_POINT)          # adjoint seed with the observed data's shape
     grad = torch.zeros(plan.phys_shape, dtype=torch.float32, device=dev)
+    # launch shapes: propagation-only timing run of every candidate over all
+    # 128 shots' windows (the wavefield-sized vectors of a normal-operator run
+    # would not fit)
+    tuned = plan.autotune(probe=True)
+    table = plan.tune_table()
+    log(f"batching autotuner: forward {esi.LAUNCH_NAMES[tuned[0]]}, adjoint {esi.LAUNCH_NAMES[tuned[1]]}")
 
     def one():
         grad.zero_()
@@ -210,10 +285,14 @@ def batching_run(args, torch, dev):
     one()
     torch.cuda.synchronize()
     plan.profile(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    e0.record()
     one()
+    e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    gpu_ms = e0.elapsed_time(e1)
     prof = plan.profile_read()
     plan.profile(False)
     plan.close()
@@ -227,15 +306,18 @@ def batching_run(args, torch, dev):
     phys = int(np.sum(cfg.window[:, 1] - cfg.window[:, 0]) * cfg.nz)
     alg = (16 * cells + bench_dense_bytes(rec["flags"]) * phys) * (2 if rec["flags"] & TWO_STEP else 1)
     per_launch_us = rec["ms"] / rec["launches"] * 1e3
-    achieved = alg / per_launch_us / 1e3
+    traffic = measured_traffic(rec["flags"], rec["shot_launches"] / rec["launches"], TRAFFIC_FILE_BATCHING)
+    kern = ("k_step2d_t2" if rec["flags"] & TWO_STEP else "k_step2d") + f"<{name}>"
     return {"workload": cfg.name, "shots": cfg.nshots, "nt": cfg.nt, "dt": cfg.dt,
             "mean_window_columns": round(float(np.mean(cfg.window[:, 1] - cfg.window[:, 0])), 1),
             "seconds": round(wall, 3), "gpts_per_s": round(pts / wall / 1e9, 2),
             "padded_cells_all_windows": cells, "padded_cells_whole_grid_all_shots": full,
             "propagations": 3, "checkpoint_every": 50,
-            "dominant_loop": {"variant": name, "launches": rec["launches"], "ms": round(rec["ms"], 1),
-                              "avg_launch_us": round(per_launch_us, 1), "alg_bytes_per_launch": int(alg),
-                              "alg_gbs": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4)}}
+            "launch_shape": tune_report(esi, tuned, table),
+            "gpu_event_ms": round(gpu_ms, 1),
+            "dominant_loop": {"variant": name, "launches": rec["launches"], "ms": round(rec["ms"], 1)},
+            "roofline": roofline(kern, alg, per_launch_us, traffic, peak_measured),
+            "kernel_loops": {k: {"launches": v["launches"], "ms": round(v["ms"], 1)} for k, v in prof.items()}}
 
 
 def wri_run(args, torch, dev):
@@ -433,6 +515,54 @@ def dataspace_run(args, torch, dev):
             "dominant_loop": {"variant": name, "launches": rec["launches"], "ms": round(rec["ms"], 1)}}
 
 
+def diff3d_run(args, torch, dev, peak_measured=None):
+    """The 3D differentiation workload: 256^3 cells, 8 shots at once, point
+    sources, 128 x 128 receivers, nt steps.  One forward pass keeping
+    checkpoints every 50 steps (esi_forward_ckpt), then the backward pass that
+    recomputes each 50-step segment and runs the adjoint with the imaging
+    correlation (esi_gradient, SEED_REUSE): the two calls behind the autograd
+    Function's forward and backward."""
+    from paper_2211_06300_amd import esi, inputs
+    cfg = inputs.cfg_diff3d(n=256, nt=args.nt3d)
+    log(f"3D differentiation workload {cfg.name}: {cfg.nshots} shots, nt {cfg.nt}")
+    plan = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_true).to(dev))
+    w = torch.from_numpy(np.stack([cfg.wavelet] * cfg.nshots)).to(dev)
+    seed = plan.forward(w, esi.SRC_POINT)                           # adjoint seed of the data's shape
+    grad = torch.zeros(plan.phys_shape, dtype=torch.float32, device=dev)
+    K = 50
+
+    def one():
+        grad.zero_()
+        plan.forward_ckpt(w, K, kind=esi.SRC_POINT)
+        plan.gradient(esi.GRAD_SEED_REUSE, w, seed, kind=esi.SRC_POINT, grad_m=grad, ckpt_every=K)
+
+    one()                                                           # warm-up
+    torch.cuda.synchronize()
+    plan.profile(True)
+    t0 = time.perf_counter()
+    one()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = plan.profile_read()
+    plan.profile(False)
+    plan.close()
+    npad = (cfg.nz + 2 * cfg.nb) * (cfg.ny + 2 * cfg.nb) * (cfg.nx + 2 * cfg.nb)
+    nphys = cfg.nz * cfg.ny * cfg.nx
+    name, rec = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    per_us = rec["ms"] / rec["launches"] * 1e3
+    spl = rec["shot_launches"] / rec["launches"]
+    alg = bytes_per_shot_launch(rec["flags"], npad, nphys) * spl
+    two = bool(rec["flags"] & TWO_STEP)
+    traffic = measured_traffic(rec["flags"], spl, TRAFFIC_FILE_3D, KERNEL_SOURCES_3D)
+    kern = ("k_step3d_t2" if two else "k_step3d") + f"<{name}>"
+    return {"workload": f"diff3d-{cfg.nx}x{cfg.ny}x{cfg.nz}-{cfg.nshots}shots", "nt": cfg.nt,
+            "checkpoint_every": K, "propagations": 3, "seconds": round(wall, 3),
+            "gpts_per_s": round(3 * cfg.nshots * npad * cfg.nt / wall / 1e9, 1),
+            "dominant_loop": {"variant": name, "launches": rec["launches"], "ms": round(rec["ms"], 1)},
+            "roofline": roofline(kern, alg, per_us, traffic, peak_measured),
+            "kernel_loops": {k: {"launches": v["launches"], "ms": round(v["ms"], 1)} for k, v in prof.items()}}
+
+
 def forward3d_run(args, torch, dev):
     """The 3D forward modelling of the differentiation workload (256^3, 8
     shots at once, point sources, 128 x 128 receivers) over its first
@@ -498,9 +628,13 @@ def main():
     ap.add_argument("--invert-inner", choices=["fcg", "ds", "cg"], default="fcg")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="also run one elementwise copy of this many MiB (counter calibration)")
-    ap.add_argument("--nt3d", type=int, default=100, help="steps of the 3D forward leg")
+    ap.add_argument("--nt3d", type=int, default=1500, help="steps of the 3D differentiation leg")
+    ap.add_argument("--no-diff3d", action="store_true", help="skip the 3D differentiation run")
     ap.add_argument("--only-3d", action="store_true",
-                    help="run the 3D forward leg alone and print its JSON object")
+                    help="run the 3D forward modelling alone (--nt3d steps) and print its JSON object")
+    ap.add_argument("--only", default="", metavar="LEGS",
+                    help="comma list of legs to run alone (batching, diff3d, solve, wri, invert, dtft, "
+                         "dataspace); prints one JSON object of them, not the contract line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "bench.py runs on one GPU; --gpus must be 1 "
@@ -519,6 +653,22 @@ def main():
         del a, b
     if args.only_3d:
         print(json.dumps({"forward3d": forward3d_run(args, torch, dev)}), flush=True)
+        return
+    peak_measured = copy_bandwidth(torch, dev)
+    log(f"measured copy bandwidth: {peak_measured:.0f} GB/s")
+    legs = {"batching": lambda: batching_run(args, torch, dev, peak_measured),
+            "diff3d": lambda: diff3d_run(args, torch, dev, peak_measured),
+            "solve": lambda: solver_comparison(args, torch, dev),
+            "wri": lambda: wri_run(args, torch, dev),
+            "invert": lambda: invert_run(args, torch, dev),
+            "dtft": lambda: dtft_run(args, torch, dev),
+            "dataspace": lambda: dataspace_run(args, torch, dev)}
+    if args.only:
+        res = {"peak_measured_gbs": round(peak_measured, 1)}
+        for leg in args.only.split(","):
+            res[leg] = legs[leg]()
+            torch.cuda.empty_cache()
+        print(json.dumps(res), flush=True)
         return
     cfg = inputs.cfg_single_solve(nshots=args.shots, nt=args.nt)
     npad = (cfg.nz + 2 * cfg.nb) * (cfg.nx + 2 * cfg.nb)
@@ -542,7 +692,8 @@ def main():
     grad = torch.zeros(plan.phys_shape, dtype=torch.float32, device=dev)
     offs = [int(cfg.nt * cfg.rec_ptr[s]) for s in range(cfg.nshots + 1)]
     tuned = plan.autotune(nshots=G, p=work[0], Ap=work[1])
-    log(f"autotuned steps per launch (forward, adjoint): {tuned}")
+    tune_table = plan.tune_table()
+    log(f"autotuned launch shapes: forward {esi.LAUNCH_NAMES[tuned[0]]}, adjoint {esi.LAUNCH_NAMES[tuned[1]]}")
     log("setup done")
 
     last_hist = {}
@@ -589,7 +740,6 @@ def main():
     per_launch_ms = rec["ms"] / rec["launches"]
     shots_per_launch = rec["shot_launches"] / rec["launches"]
     alg_bytes = bytes_per_shot_launch(rec["flags"], npad, nphys) * shots_per_launch
-    achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9
     traffic = measured_traffic(rec["flags"], shots_per_launch)
     hist = np.concatenate([h for h in last_hist.values()])
     out = {
@@ -610,13 +760,9 @@ def main():
                    "cg_iters": args.cg_iters, "beta": cfg.beta,
                    "cg_residual_update": "separate pass" if args.no_rfuse else "fused into the adjoint",
                    "propagations_per_shot": props_per_shot,
-                   "steps_per_launch": {"forward": tuned[0], "adjoint": tuned[1], "chosen_by": "autotuner"}},
-        "roofline": {"bound": "hbm",
-                     "kernel": ("k_step2d_t2" if rec["flags"] & TWO_STEP else "k_step2d") + f"<{name}>",
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "alg_bytes_per_launch": int(alg_bytes),
-                     "avg_launch_us": round(per_launch_ms * 1e3, 2)},
+                   "launch_shape": tune_report(esi, tuned, tune_table)},
+        "roofline": roofline(("k_step2d_t2" if rec["flags"] & TWO_STEP else "k_step2d") + f"<{name}>",
+                             alg_bytes, per_launch_ms * 1e3, traffic, peak_measured),
         "gpu_event_ms": round(gpu_ms, 1),
         "cg_final_rel_residual_max": float(np.max(hist[:, -1])),
         "kernel_loops": {k: {"launches": v["launches"], "ms": round(v["ms"], 1)} for k, v in prof.items()},
@@ -628,7 +774,10 @@ def main():
         out["solve_to_1e-3"] = solver_comparison(args, torch, dev)
         torch.cuda.empty_cache()
     if not args.no_batching:
-        out["batching"] = batching_run(args, torch, dev)
+        out["batching"] = batching_run(args, torch, dev, peak_measured)
+        torch.cuda.empty_cache()
+    if not args.no_diff3d:
+        out["diff3d"] = diff3d_run(args, torch, dev, peak_measured)
         torch.cuda.empty_cache()
     if not args.no_wri:
         out["wri"] = wri_run(args, torch, dev)

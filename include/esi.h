@@ -187,6 +187,40 @@ esi_status_t esi_cg_solve(esi_plan_t plan, int32_t shot0, int32_t nshots, const 
                           esi_cg_report_t* rep);
 
 /*
+ * State of a CG solve between iterations, for saving a solve and resuming it
+ * later (Algorithm 1's (x, r, p, r.r, k) with the per-shot bookkeeping).  The
+ * vectors stay in the caller's buffers: x = x_k, work[0] = r_k, work[1] =
+ * p_{k-1} (work as in esi_cg_solve).  Host arrays, [nshots] unless stated:
+ */
+typedef struct {
+    int32_t k;          /* iterations done */
+    double* rr0;        /* ||r_0||^2 */
+    double* rr;         /* ||r_k||^2 */
+    double* beta;       /* beta_{k-1}: the next direction is r_k + beta p_{k-1} */
+    int32_t* iterating; /* 1 if the shot stopped only at the iteration limit */
+    int32_t* iters;     /* iterations done by the shot */
+    int32_t* status;    /* ESI_OK, ESI_ERR_BREAKDOWN or ESI_ERR_NONFINITE of the shot */
+    double* res_hist;   /* [nshots][hist_cap]: ||r_j|| / ||r_0||, j <= k (later entries -1) */
+    int32_t hist_cap;   /* row length of res_hist */
+} esi_cg_state_t;
+
+/*
+ * esi_cg_solve with save and resume.  resume = NULL starts from x_0 = 0 as
+ * esi_cg_solve does; otherwise the solve continues from the state (d_obs is
+ * not read; x and work hold the saved vectors; 1 <= resume->k <= max_iter;
+ * hist_cap >= k + 1) up to max_iter iterations in all, the shots flagged
+ * `iterating` taking part.  save, if not NULL (hist_cap >= max_iter + 1),
+ * receives the state after the last iteration, with p_{k-1} copied into
+ * work[1].  A solve paused after K iterations and resumed to K' gives the
+ * same x, r and residual history bit for bit as one solve of K' iterations
+ * (graph replay, esi_plan_set_cg_graph, is not used while resuming).
+ * Errors as esi_cg_solve; ESI_ERR_ARG for an inconsistent state.
+ */
+esi_status_t esi_cg_solve_state(esi_plan_t plan, int32_t shot0, int32_t nshots, const float* d_obs,
+                                float* x, float* work, int32_t max_iter, double rtol,
+                                const esi_cg_state_t* resume, esi_cg_state_t* save, esi_cg_report_t* rep);
+
+/*
  * Adjoint-state gradient with respect to m = 1/v^2, summed over the shots and
  * ADDED to grad_m (device [phys]):
  *   g(x) = sum_n lambda^n(x) v(x)^2 (L u^n + P q^n)(x),   u = A^{-1} q,
@@ -268,7 +302,10 @@ esi_status_t esi_wri_gradient(esi_plan_t plan, int32_t shot0, int32_t nshots, in
 
 /*
  * Penalty parameter beta of the plan (Sec. 2.4): used by every later call.
- * ESI_ERR_ARG unless finite and >= 0.
+ * ESI_ERR_ARG unless finite.  The normal operator is positive definite only
+ * for beta > 0 (Sec. 2.3); a negative beta makes it indefinite, and CG then
+ * stops with ESI_ERR_BREAKDOWN at the first p.Np <= 0, x holding the last
+ * iterate it finished.
  */
 esi_status_t esi_plan_set_beta(esi_plan_t plan, double beta);
 
@@ -446,26 +483,55 @@ esi_status_t esi_grad_velocity(esi_plan_t plan, const float* vel, const float* g
 /*
  * Time blocking of the 2D kernels: 2 (default) advances two time steps per
  * launch wherever a call allows it (the wavefield state then crosses HBM once
- * per two steps), 1 advances one step per launch.  Results are identical bit
- * for bit either way.  Returns ESI_ERR_ARG for other values.
+ * per two steps; launch shape ESI_LAUNCH_TWO_STEP_32), 1 advances one step per
+ * launch (ESI_LAUNCH_ONE_STEP).  Results are identical bit for bit either way.
+ * Returns ESI_ERR_ARG for other values.
  */
 esi_status_t esi_plan_set_time_block(esi_plan_t plan, int32_t steps);
 
 /*
- * Autotuner of the launch configuration.  For the plan's grid and a batch of
- * nshots shots it times each candidate (2D: one or two time steps per launch,
- * chosen separately for forward-type and adjoint-type loops) on one
- * application of the normal operator with p (device [nshots][nt][phys],
- * contents irrelevant; Ap is overwritten), after a warm-up run of each, with
- * the plan's hipEvent profiling, and keeps the faster one of each direction.
- * Results are cached per process for (ndim, padded shape, nshots); force != 0
- * measures again.  Propagations are bitwise the same for every candidate;
- * dot products (p.Np) sum their partials over a different tiling, so CG
- * results agree to rounding.  choice: host int[2] out (forward, adjoint steps per
- * launch) or NULL.  3D plans have a single configuration (1, 1).
+ * Launch shapes of the 2D time loops, the autotuner's candidates:
+ *   ESI_LAUNCH_ONE_STEP (1): one time step per launch on 64 x 32 tiles;
+ *   ESI_LAUNCH_TWO_STEP_32 (2, default), _24 (3), _40 (4): two time steps per
+ *   launch on 56-column tiles of 32, 24 or 40 rows (the wavefield state
+ *   crosses HBM once per two steps; the first step runs on the tile grown by
+ *   one stencil radius).
+ * Every shape gives the same wavefield, data, dense outputs and gradients bit
+ * for bit; float64 dot products sum their per-tile partials over a different
+ * tiling, so CG results agree to rounding.  Time-loop variants the shapes of
+ * 24 and 40 rows do not cover run on 32-row tiles.  3D plans run shape 1.
+ */
+enum { ESI_LAUNCH_ONE_STEP = 1, ESI_LAUNCH_TWO_STEP_32 = 2, ESI_LAUNCH_TWO_STEP_24 = 3,
+       ESI_LAUNCH_TWO_STEP_40 = 4 };
+
+/* Set the launch shapes of forward-type and adjoint-type loops (1 .. 4; 3D: 1).
+ * ESI_ERR_ARG otherwise. */
+esi_status_t esi_plan_set_launch_shape(esi_plan_t plan, int32_t forward, int32_t adjoint);
+
+/*
+ * Autotuner of the launch shape.  For the plan's grid and a batch of nshots
+ * shots it times every candidate shape (2D: the four above; 3D: one), after a
+ * warm-up run of each, with the plan's hipEvent profiling, and keeps the
+ * fastest for forward-type and for adjoint-type loops separately.
+ *   p, Ap device [nshots][nt][phys] (contents irrelevant; Ap is overwritten):
+ *     the candidates are timed on one application of the normal operator;
+ *   p = Ap = NULL: on a point-source forward pass over the first min(nt, 64)
+ *     steps and an adjoint pass injecting receiver data over the last ones
+ *     (propagation alone, for batches whose wavefield-sized vectors are too
+ *     large to allocate, e.g. many shots of long records).
+ * Choices and timings are cached per process for (ndim, padded shape,
+ * nshots, nt, the shots' apertures, timing kind); force != 0 measures again.
+ * choice: host int[2] out (forward, adjoint launch shape) or NULL.
  */
 esi_status_t esi_plan_autotune(esi_plan_t plan, int32_t shot0, int32_t nshots, const float* p,
                                float* Ap, int32_t force, int32_t* choice);
+
+/* The candidate table of the plan's last esi_plan_autotune call (also when it
+ * came from the cache): count rows (host out); for i < min(cap, count) the
+ * shape and the milliseconds of its forward-type and adjoint-type loops (host
+ * arrays [cap] out).  count = 0 for 3D plans. */
+esi_status_t esi_plan_tune_table(esi_plan_t plan, int32_t cap, int32_t* count, int32_t* shape,
+                                 double* fwd_ms, double* adj_ms);
 
 /*
  * CG iterations (Algorithm 1) replayed from captured HIP graphs.  With
@@ -548,6 +614,17 @@ esi_status_t esi_plan_profile_read(esi_plan_t plan, int32_t cap, int32_t* count,
 esi_status_t esi_fpcg_solve(esi_plan_t plan, int32_t shot0, int32_t nshots, const float* d_obs,
                             float* x, float* work, int32_t max_iter, double rtol, esi_unet_t net,
                             int32_t net_every, const float* scale, esi_cg_report_t* rep);
+
+/*
+ * The analytic cell scale of the flexible solver, s0(x) = 1 / (beta B(x)^2 +
+ * gamma) per shot, B = |x - x_s| / dx + b_eps in cells: the inverse of the
+ * penalty weight of eq. (esi) (the term beta B^T B of eq. normalewi) with
+ * gamma standing in for the part S^T S adds.  It is the base scale of
+ * esi_fpcg_solve and esi_precond_features.
+ *   out: device [nshots][phys] float32 out (computed in float64, rounded once).
+ * 2D annihilator-weight plans only (ESI_ERR_ARG otherwise); gamma > 0.
+ */
+esi_status_t esi_precond_scale(esi_plan_t plan, int32_t shot0, int32_t nshots, double gamma, float* out);
 
 /*
  * Network input of the preconditioner for `nshots` shots of a 2D plan, on

@@ -9,11 +9,15 @@
 
 namespace esi {
 
-esi_status_t launch_step2d(Plan* P, unsigned flags, const StepArgs& a, bool two_steps);
+esi_status_t launch_step2d(Plan* P, unsigned flags, const StepArgs& a, int shape);
+int step2d_loop_shape(unsigned flags, int shape);
 void step2d_tile_shape(int* tx, int* tz);
-void step2d_t2_tile_shape(int* tx, int* tz);
+void step2d_shape_tile(int shape, int* tx, int* tz);
 esi_status_t launch_step3d(Plan* P, unsigned flags, const StepArgs& a);
+esi_status_t launch_step3d_t2(Plan* P, unsigned flags, const StepArgs& a);
+bool step3d_t2_has(unsigned flags);
 void step3d_tile_shape(int* tx, int* ty, int* tz);
+void step3d_t2_tile_shape(int* tx, int* ty, int* tz);
 esi_status_t launch_dot(Plan* P, const float* x, const float* y, int nshots, int64_t len,
                         double* out);
 esi_status_t launch_fill_d(Plan* P, double* p, int64_t n);
@@ -33,11 +37,48 @@ esi_status_t lists_for(Plan* P, TileLists** L) {
     return get_lists(P, tx, tz, ty, L);
 }
 
-esi_status_t launch_step(Plan* P, unsigned flags, const StepArgs& a, bool two) {
-    return P->ndim == 2 ? launch_step2d(P, flags, a, two) : launch_step3d(P, flags, a);
+esi_status_t launch_step(Plan* P, unsigned flags, const StepArgs& a, int shape) {
+    if (P->ndim == 2) return launch_step2d(P, flags, a, shape);
+    return shape == LS_ONE ? launch_step3d(P, flags, a) : launch_step3d_t2(P, flags, a);
 }
 
-bool two_step_ok(Plan* P, bool adjoint) { return P->ndim == 2 && (adjoint ? P->tb_adj : P->tb_fwd) == 2; }
+// 2D: the plan's shape (32-row tiles for variants without other heights);
+// 3D: two steps per launch (LS_T2_32) for the variants the two-step kernel has
+int loop_shape(Plan* P, unsigned flags, bool adjoint) {
+    const int want = adjoint ? P->tb_adj : P->tb_fwd;
+    if (P->ndim == 2) return step2d_loop_shape(flags, want);
+    return want != LS_ONE && step3d_t2_has(flags) ? LS_T2_32 : LS_ONE;
+}
+
+void shape_tile(Plan* P, int shape, int* tx, int* ty, int* tz) {
+    *ty = 1;
+    if (P->ndim == 2) step2d_shape_tile(shape, tx, tz);
+    else if (shape == LS_ONE) step3d_tile_shape(tx, ty, tz);
+    else step3d_t2_tile_shape(tx, ty, tz);
+}
+
+esi_status_t shape_lists(Plan* P, int shape, TileLists** L) {
+    int tx, ty, tz;
+    shape_tile(P, shape, &tx, &ty, &tz);
+    return get_lists(P, tx, tz, ty, L);
+}
+
+int max_tiles(Plan* P) {
+    int m = 0;
+    for (const TileLists* L : P->lists) m = std::max(m, L->tiles);
+    return m;
+}
+
+namespace {
+// Build the tilings of the time loops of `fflags` (forward) and `aflags`
+// (adjoint) before per-tile partials are sized by max_tiles.
+esi_status_t loop_lists(Plan* P, unsigned fflags, unsigned aflags) {
+    TileLists* L;
+    ESI_TRY(lists_for(P, &L));
+    ESI_TRY(shape_lists(P, loop_shape(P, fflags, false), &L));
+    return shape_lists(P, loop_shape(P, aflags, true), &L);
+}
+}  // namespace
 
 // Point the tile fields and sparse lists of `a` at the tiling `L`.
 void apply_lists(StepArgs& a, const TileLists* L) {
@@ -53,16 +94,6 @@ void apply_lists(StepArgs& a, const TileLists* L) {
         a.work = nullptr;
         a.nwork = 0;
     }
-}
-
-// Tiling of two-step launches of forward or adjoint loops (nullptr when they
-// are not used).
-esi_status_t t2_lists(Plan* P, TileLists** L2, bool adjoint) {
-    *L2 = nullptr;
-    if (!two_step_ok(P, adjoint)) return ESI_OK;
-    int tx, tz;
-    step2d_t2_tile_shape(&tx, &tz);
-    return get_lists(P, tx, tz, 1, L2);
 }
 
 // Fill the fields every step of a call shares.
@@ -133,8 +164,9 @@ struct ProfScope {
 esi_status_t forward_loop(Plan* P, StepArgs a, unsigned flags, float* ring, int* cs, int n0,
                           int n1, float* ckpt, int K, int nseg) {
     ProfScope p1(P, flags, a.nshots), p2(P, flags | (1u << 15), a.nshots);
-    TileLists* L2;
-    ESI_TRY(t2_lists(P, &L2, false));
+    const int shape = loop_shape(P, flags, false);
+    TileLists* L2 = nullptr;
+    if (shape != LS_ONE) ESI_TRY(shape_lists(P, shape, &L2));
     const bool t2 = L2 != nullptr;
     StepArgs b = a;
     if (t2) apply_lists(b, L2);
@@ -158,7 +190,7 @@ esi_status_t forward_loop(Plan* P, StepArgs a, unsigned flags, float* ring, int*
             c.store_slot = K > 0 ? n % K : n;
             c.store_slot2 = K > 0 ? (n + 1) % K : n + 1;
         }
-        ESI_TRY(launch_step(P, flags, c, two));
+        ESI_TRY(launch_step(P, flags, c, two ? shape : LS_ONE));
         (two ? p2 : p1).launches++;
         *cs ^= 1;
         n += two ? 2 : 1;
@@ -170,8 +202,9 @@ esi_status_t forward_loop(Plan* P, StepArgs a, unsigned flags, float* ring, int*
 esi_status_t adjoint_loop(Plan* P, StepArgs a, unsigned flags, float* ring, int* cs, int j0,
                           int j1, int K) {
     ProfScope p1(P, flags, a.nshots), p2(P, flags | (1u << 15), a.nshots);
-    TileLists* L2;
-    ESI_TRY(t2_lists(P, &L2, true));
+    const int shape = loop_shape(P, flags, true);
+    TileLists* L2 = nullptr;
+    if (shape != LS_ONE) ESI_TRY(shape_lists(P, shape, &L2));
     const bool t2 = L2 != nullptr;
     StepArgs b = a;
     if (t2) apply_lists(b, L2);
@@ -185,7 +218,7 @@ esi_status_t adjoint_loop(Plan* P, StepArgs a, unsigned flags, float* ring, int*
             c.store_slot = K > 0 ? j % K : j;
             c.store_slot2 = K > 0 ? (j - 1) % K : j - 1;
         }
-        ESI_TRY(launch_step(P, flags, c, two));
+        ESI_TRY(launch_step(P, flags, c, two ? shape : LS_ONE));
         (two ? p2 : p1).launches++;
         *cs ^= 1;
         j -= two ? 2 : 1;
@@ -223,10 +256,9 @@ esi_status_t do_normal(Plan* P, int shot0, int ns, const float* p, float* Ap, co
     const int64_t dl = data_len(P, shot0, ns);
     ESI_TRY(grow_t(&P->dscr, &P->dscr_cap, std::max<int64_t>(dl, 1), P->stream));
     ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
-    TileLists *L2f, *L2a;
-    ESI_TRY(t2_lists(P, &L2f, false));
-    ESI_TRY(t2_lists(P, &L2a, true));
-    P->part_stride = std::max({L->tiles, L2f ? L2f->tiles : 0, L2a ? L2a->tiles : 0});
+    ESI_TRY(loop_lists(P, cg_fuse ? F_CG_FUSE | F_GATHER | (cg_s ? F_SCALE : 0u) : F_SRC_DENSE | F_GATHER,
+                       F_INJ | F_NORMAL));
+    P->part_stride = max_tiles(P);
     ESI_TRY(grow_t(&P->part, &P->part_cap, (int64_t)ns * P->part_stride, P->stream));
     StepArgs a = base_args(P, L, shot0, ns);
     a.active = active;
@@ -276,10 +308,8 @@ esi_status_t do_normal_rupd(Plan* P, int shot0, int ns, const float* p, float* p
     const int64_t dl = data_len(P, shot0, ns);
     ESI_TRY(grow_t(&P->dscr, &P->dscr_cap, std::max<int64_t>(dl, 1), P->stream));
     ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
-    TileLists *L2f, *L2a;
-    ESI_TRY(t2_lists(P, &L2f, false));
-    ESI_TRY(t2_lists(P, &L2a, true));
-    P->part_stride = std::max({L->tiles, L2f ? L2f->tiles : 0, L2a ? L2a->tiles : 0});
+    ESI_TRY(loop_lists(P, (first ? F_SRC_DENSE : F_CG_FUSE) | F_GATHER | F_RUPD, F_INJ | F_NORMAL | F_RUPD));
+    P->part_stride = max_tiles(P);
     ESI_TRY(grow_t(&P->part, &P->part_cap, (int64_t)ns * std::max(P->part_stride, DATA_BLOCKS), P->stream));
     ESI_TRY(launch_fill_d(P, P->part, (int64_t)ns * P->part_stride));
     StepArgs a = base_args(P, L, shot0, ns);
@@ -427,7 +457,7 @@ std::vector<uintptr_t> cg_graph_key(Plan* P, const CgState& c) {
     return {(uintptr_t)c.shot0, (uintptr_t)c.ns, (uintptr_t)c.max_iter,
             (uintptr_t)std::llround(c.rtol * 1e18), (uintptr_t)c.L, (uintptr_t)c.x,
             (uintptr_t)c.r, (uintptr_t)c.hist, (uintptr_t)P->ring, (uintptr_t)P->dscr,
-            (uintptr_t)P->part, (uintptr_t)(P->tb_fwd * 4 + P->tb_adj), (uintptr_t)P->part_stride,
+            (uintptr_t)P->part, (uintptr_t)(P->tb_fwd * 8 + P->tb_adj), (uintptr_t)P->part_stride,
             (uintptr_t)P->w_identity, beta_bits(P->beta), (uintptr_t)P->cg_rfuse};
 }
 
@@ -506,17 +536,26 @@ extern "C" esi_status_t esi_plan_set_cg_rfuse(esi_plan_t plan, int32_t enable) {
     return ESI_OK;
 }
 
-extern "C" esi_status_t esi_cg_solve(esi_plan_t plan, int32_t shot0, int32_t ns,
-                                     const float* d_obs, float* x, float* work, int32_t max_iter,
-                                     double rtol, esi_cg_report_t* rep) {
-    set_error("");
-    if (!plan) return fail(ESI_ERR_ARG, "null plan");
-    Plan* P = (Plan*)plan;
+namespace esi {
+namespace {
+
+// Algorithm 1 from x_0 = 0 (resume = NULL) or from a saved state, optionally
+// leaving the state of the last iteration in `save`.
+esi_status_t cg_solve_impl(Plan* P, int32_t shot0, int32_t ns, const float* d_obs, float* x, float* work,
+                           int32_t max_iter, double rtol, const esi_cg_state_t* resume, esi_cg_state_t* save,
+                           esi_cg_report_t* rep) {
     ESI_TRY(check_shots(P, shot0, ns));
-    if (!x || !work || (!d_obs && data_len(P, shot0, ns) > 0)) return fail(ESI_ERR_ARG, "null pointer");
+    if (!x || !work || (!resume && !d_obs && data_len(P, shot0, ns) > 0)) return fail(ESI_ERR_ARG, "null pointer");
     if (max_iter < 1) return fail(ESI_ERR_ARG, "max_iter must be >= 1");
     if (!(rtol >= 0)) return fail(ESI_ERR_ARG, "rtol must be >= 0");
     if (P->nshots < ns) return fail(ESI_ERR_ARG, "internal: scalar space");
+    auto state_ok = [](const esi_cg_state_t* st) {
+        return st->rr0 && st->rr && st->beta && st->iterating && st->iters && st->status && st->res_hist;
+    };
+    if (resume && (!state_ok(resume) || resume->k < 1 || resume->k > max_iter || resume->hist_cap < resume->k + 1))
+        return fail(ESI_ERR_ARG, "resume state: null arrays, or k outside [1, max_iter], or hist_cap < k + 1");
+    if (save && (!state_ok(save) || save->hist_cap < max_iter + 1))
+        return fail(ESI_ERR_ARG, "save state: null arrays or hist_cap < max_iter + 1");
     CgState c;
     ESI_TRY(lists_for(P, const_cast<TileLists**>(&c.L)));
     c.shot0 = shot0; c.ns = ns; c.max_iter = max_iter; c.rtol = rtol;
@@ -530,28 +569,11 @@ extern "C" esi_status_t esi_cg_solve(esi_plan_t plan, int32_t shot0, int32_t ns,
     c.rr0 = P->scal + 5 * P->nshots;
     c.active = P->flags; c.finish = P->flags + P->nshots;
     c.iters = P->cgi; c.status = P->cgi + P->nshots; c.ctl = P->cgi + 2 * P->nshots;
-    ESI_TRY(grow_t(&P->cg_hist, &P->cg_hist_cap, (int64_t)ns * (max_iter + 1), P->stream));
+    const int hs = max_iter + 1;
+    ESI_TRY(grow_t(&P->cg_hist, &P->cg_hist_cap, (int64_t)ns * hs, P->stream));
     c.hist = P->cg_hist;
     // the fused-residual iterations' data partials (sized here, outside any capture)
     ESI_TRY(grow_t(&P->part, &P->part_cap, (int64_t)ns * DATA_BLOCKS, P->stream));
-
-    // b = S^T d (adjoint modelling, Sec. 3); r_0 = b, p_0 = r_0, x_0 = 0
-    ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
-    {
-        StepArgs a = base_args(P, c.L, shot0, ns);
-        a.inj_data = d_obs;
-        a.dout = c.r;
-        int cs = 0;
-        ESI_TRY(adjoint_loop(P, a, F_INJ | F_OUT, P->ring, &cs, 0, P->nt));
-    }
-    ESI_TRY(launch_copy(P, c.p, c.r, ns * c.len));
-    ESI_TRY(launch_fill(P, x, ns * c.len, 0.f));
-    ESI_TRY(launch_dot(P, c.r, c.r, ns, c.len, c.rr));
-    ESI_HIP_TRY(hipMemcpyAsync(c.rr0, c.rr, ns * sizeof(double), hipMemcpyDeviceToDevice, P->stream));
-    ESI_TRY(launch_cg_init(P, c.rr0, c.active, c.finish, c.iters, c.status, c.hist, max_iter + 1,
-                           c.ctl, ns));
-    ESI_HIP_TRY(hipMemcpyAsync(P->h_ctl, c.ctl, 2 * sizeof(int), hipMemcpyDeviceToHost, P->stream));
-    ESI_HIP_TRY(hipStreamSynchronize(P->stream));
 
     std::vector<int> h_status(ns, 0);
     auto read_status = [&]() -> esi_status_t {
@@ -564,15 +586,60 @@ extern "C" esi_status_t esi_cg_solve(esi_plan_t plan, int32_t shot0, int32_t ns,
             if (h_status[s] == ESI_ERR_BREAKDOWN) return fail(ESI_ERR_BREAKDOWN, "CG breakdown: p.Np <= 0");
         return ESI_OK;
     };
-    esi_status_t status = read_status();
-    if (status == ESI_ERR_NONFINITE) return fail(ESI_ERR_NONFINITE, "non-finite right-hand side");
+    int k0 = 0;
+    if (!resume) {
+        // b = S^T d (adjoint modelling, Sec. 3); r_0 = b, p_0 = r_0, x_0 = 0
+        ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
+        {
+            StepArgs a = base_args(P, c.L, shot0, ns);
+            a.inj_data = d_obs;
+            a.dout = c.r;
+            int cs = 0;
+            ESI_TRY(adjoint_loop(P, a, F_INJ | F_OUT, P->ring, &cs, 0, P->nt));
+        }
+        ESI_TRY(launch_copy(P, c.p, c.r, ns * c.len));
+        ESI_TRY(launch_fill(P, x, ns * c.len, 0.f));
+        ESI_TRY(launch_dot(P, c.r, c.r, ns, c.len, c.rr));
+        ESI_HIP_TRY(hipMemcpyAsync(c.rr0, c.rr, ns * sizeof(double), hipMemcpyDeviceToDevice, P->stream));
+        ESI_TRY(launch_cg_init(P, c.rr0, c.active, c.finish, c.iters, c.status, c.hist, hs, c.ctl, ns));
+        ESI_HIP_TRY(hipMemcpyAsync(P->h_ctl, c.ctl, 2 * sizeof(int), hipMemcpyDeviceToHost, P->stream));
+        ESI_HIP_TRY(hipStreamSynchronize(P->stream));
+        if (read_status() == ESI_ERR_NONFINITE) return fail(ESI_ERR_NONFINITE, "non-finite right-hand side");
+    } else {
+        // x = x_k, work[0] = r_k, work[1] = p_{k-1} come from the caller; the
+        // next iteration forms p_k = r_k + beta p_{k-1} and, with alpha = 0,
+        // leaves x as it is (x_k already holds the last step)
+        k0 = resume->k;
+        std::vector<int> act(ns), fin(ns, 0);
+        std::vector<double> hist((size_t)ns * hs, -1.0), zero(ns, 0.0);
+        int cnt = 0;
+        for (int s = 0; s < ns; ++s) {
+            act[s] = resume->iterating[s] ? 1 : 0;
+            cnt += act[s];
+            for (int j = 0; j <= k0; ++j) hist[(size_t)s * hs + j] = resume->res_hist[(size_t)s * resume->hist_cap + j];
+        }
+        const int ctl[2] = {k0, cnt};
+        ESI_HIP_TRY(hipMemcpy(c.rr0, resume->rr0, ns * sizeof(double), hipMemcpyHostToDevice));
+        ESI_HIP_TRY(hipMemcpy(c.rr, resume->rr, ns * sizeof(double), hipMemcpyHostToDevice));
+        ESI_HIP_TRY(hipMemcpy(c.beta, resume->beta, ns * sizeof(double), hipMemcpyHostToDevice));
+        ESI_HIP_TRY(hipMemcpy(c.alpha, zero.data(), ns * sizeof(double), hipMemcpyHostToDevice));
+        ESI_HIP_TRY(hipMemcpy(c.active, act.data(), ns * sizeof(int), hipMemcpyHostToDevice));
+        ESI_HIP_TRY(hipMemcpy(c.finish, fin.data(), ns * sizeof(int), hipMemcpyHostToDevice));
+        ESI_HIP_TRY(hipMemcpy(c.iters, resume->iters, ns * sizeof(int), hipMemcpyHostToDevice));
+        ESI_HIP_TRY(hipMemcpy(c.status, resume->status, ns * sizeof(int), hipMemcpyHostToDevice));
+        ESI_HIP_TRY(hipMemcpy(c.hist, hist.data(), hist.size() * sizeof(double), hipMemcpyHostToDevice));
+        ESI_HIP_TRY(hipMemcpy(c.ctl, ctl, 2 * sizeof(int), hipMemcpyHostToDevice));
+        P->h_ctl[0] = ctl[0];
+        P->h_ctl[1] = ctl[1];
+    }
 
-    const bool graph = P->cg_graph && P->cap_stream;
+    // graph replay assumes the direction buffers of a fresh solve
+    const bool graph = P->cg_graph && P->cap_stream && !resume;
     if (graph && P->cg_key != cg_graph_key(P, c)) cg_graph_drop(P);
     float* p = c.p;
     float* Ap = c.Ap;
-    int done_iters = 0;
-    for (int k = 0; k < max_iter && P->h_ctl[1] > 0; ++k) {
+    int done_iters = k0;
+    for (int k = k0; k < max_iter && P->h_ctl[1] > 0; ++k) {
         if (graph && k >= 1) {
             const int i = k & 1;
             if (!P->cg_exec[i]) {
@@ -588,18 +655,59 @@ extern "C" esi_status_t esi_cg_solve(esi_plan_t plan, int32_t shot0, int32_t ns,
         ESI_HIP_TRY(hipStreamSynchronize(P->stream));
         done_iters = k + 1;
     }
-    status = read_status();
+    esi_status_t status = read_status();
+    if (save) {
+        // p_{k-1} into work[1] (the direction buffers alternate)
+        if (p != c.p) ESI_TRY(launch_copy(P, c.p, p, ns * c.len));
+        std::vector<double> hist((size_t)ns * hs);
+        ESI_HIP_TRY(hipMemcpyAsync(save->rr0, c.rr0, ns * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+        ESI_HIP_TRY(hipMemcpyAsync(save->rr, c.rr, ns * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+        ESI_HIP_TRY(hipMemcpyAsync(save->beta, c.beta, ns * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+        ESI_HIP_TRY(hipMemcpyAsync(save->iters, c.iters, ns * sizeof(int), hipMemcpyDeviceToHost, P->stream));
+        ESI_HIP_TRY(hipMemcpyAsync(save->status, c.status, ns * sizeof(int), hipMemcpyDeviceToHost, P->stream));
+        ESI_HIP_TRY(hipMemcpyAsync(hist.data(), c.hist, hist.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                   P->stream));
+        ESI_HIP_TRY(hipStreamSynchronize(P->stream));
+        save->k = done_iters;
+        for (int s = 0; s < ns; ++s) {
+            for (int j = 0; j < hs; ++j) save->res_hist[(size_t)s * save->hist_cap + j] = hist[(size_t)s * hs + j];
+            // still iterating: stopped by the iteration limit alone
+            const double rel = hist[(size_t)s * hs + done_iters];
+            save->iterating[s] = save->status[s] == ESI_OK && save->rr0[s] > 0.0 && save->iters[s] == done_iters &&
+                                 !(rel < rtol);
+        }
+    }
     if (rep) {
         rep->iters = done_iters;
         if (rep->shot_iters)
             ESI_HIP_TRY(hipMemcpyAsync(rep->shot_iters, c.iters, ns * sizeof(int),
                                        hipMemcpyDeviceToHost, P->stream));
         if (rep->res_hist)
-            ESI_HIP_TRY(hipMemcpyAsync(rep->res_hist, c.hist, (size_t)ns * (max_iter + 1) * sizeof(double),
+            ESI_HIP_TRY(hipMemcpyAsync(rep->res_hist, c.hist, (size_t)ns * hs * sizeof(double),
                                        hipMemcpyDeviceToHost, P->stream));
         ESI_HIP_TRY(hipStreamSynchronize(P->stream));
     }
     return status;
+}
+
+}  // namespace
+}  // namespace esi
+
+extern "C" esi_status_t esi_cg_solve(esi_plan_t plan, int32_t shot0, int32_t ns,
+                                     const float* d_obs, float* x, float* work, int32_t max_iter,
+                                     double rtol, esi_cg_report_t* rep) {
+    set_error("");
+    if (!plan) return fail(ESI_ERR_ARG, "null plan");
+    return cg_solve_impl((Plan*)plan, shot0, ns, d_obs, x, work, max_iter, rtol, nullptr, nullptr, rep);
+}
+
+extern "C" esi_status_t esi_cg_solve_state(esi_plan_t plan, int32_t shot0, int32_t ns, const float* d_obs,
+                                           float* x, float* work, int32_t max_iter, double rtol,
+                                           const esi_cg_state_t* resume, esi_cg_state_t* save,
+                                           esi_cg_report_t* rep) {
+    set_error("");
+    if (!plan) return fail(ESI_ERR_ARG, "null plan");
+    return cg_solve_impl((Plan*)plan, shot0, ns, d_obs, x, work, max_iter, rtol, resume, save, rep);
 }
 
 extern "C" esi_status_t esi_fpcg_solve(esi_plan_t plan, int32_t shot0, int32_t ns,
@@ -902,10 +1010,11 @@ esi_status_t gradient_impl(Plan* P, int32_t shot0, int32_t ns, int32_t mode, int
 // beta W q^2 to pen (device, FP64 [ns]).
 esi_status_t penalty_eval(Plan* P, int shot0, int ns, const float* q, const float* bg, float* gshot,
                           float* dsyn, double* pen) {
-    TileLists *L, *L2f;
+    TileLists* L;
     ESI_TRY(lists_for(P, &L));
-    ESI_TRY(t2_lists(P, &L2f, false));
-    P->part_stride = std::max(L->tiles, L2f ? L2f->tiles : 0);
+    const unsigned pfl = F_SRC_DENSE | F_PENALTY | F_GATHER | (bg ? F_SRC_POINT : 0u);
+    ESI_TRY(loop_lists(P, pfl, F_INJ));
+    P->part_stride = max_tiles(P);
     ESI_TRY(grow_t(&P->part, &P->part_cap, (int64_t)ns * P->part_stride, P->stream));
     ESI_TRY(launch_fill_d(P, P->part, (int64_t)ns * P->part_stride));
     ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
@@ -917,8 +1026,7 @@ esi_status_t penalty_eval(Plan* P, int shot0, int ns, const float* q, const floa
     a.part = P->part;
     a.part_stride = P->part_stride;
     int cs = 0;
-    ESI_TRY(forward_loop(P, a, F_SRC_DENSE | F_PENALTY | F_GATHER | (bg ? F_SRC_POINT : 0u), P->ring, &cs, 0,
-                         P->nt));
+    ESI_TRY(forward_loop(P, a, pfl, P->ring, &cs, 0, P->nt));
     ESI_TRY(launch_final_gather(P, P->ring + (int64_t)cs * P->fsize, RING * P->fsize, dsyn, shot0, ns));
     return launch_reduce_parts(P, P->part, P->part_stride, ns, pen);
 }
@@ -938,7 +1046,7 @@ extern "C" esi_status_t esi_gradient(esi_plan_t plan, int32_t shot0, int32_t ns,
 extern "C" esi_status_t esi_plan_set_beta(esi_plan_t plan, double beta) {
     set_error("");
     if (!plan) return fail(ESI_ERR_ARG, "null plan");
-    if (!(beta >= 0) || !std::isfinite(beta)) return fail(ESI_ERR_ARG, "beta must be finite and >= 0");
+    if (!std::isfinite(beta)) return fail(ESI_ERR_ARG, "beta must be finite");
     ((Plan*)plan)->beta = beta;
     return ESI_OK;
 }
@@ -1020,7 +1128,7 @@ extern "C" esi_status_t esi_plan_set_time_block(esi_plan_t plan, int32_t steps) 
     set_error("");
     if (!plan) return fail(ESI_ERR_ARG, "null plan");
     if (steps != 1 && steps != 2) return fail(ESI_ERR_ARG, "time block must be 1 or 2");
-    ((Plan*)plan)->tb_fwd = ((Plan*)plan)->tb_adj = steps;
+    ((Plan*)plan)->tb_fwd = ((Plan*)plan)->tb_adj = steps == 1 ? LS_ONE : LS_T2_32;
     return ESI_OK;
 }
 
@@ -1043,9 +1151,40 @@ esi_status_t fold_profile(Plan* P) {
     return ESI_OK;
 }
 
-// Process-wide cache of tuned choices: (ndim, nzp, nyp, nxp, nshots) -> (fwd, adj).
-struct TuneEntry { int key[5]; int fwd, adj; };
+// Process-wide cache of tuned choices, keyed by the grid, the shots (count,
+// apertures), nt and the kind of timing run.
+struct TuneEntry { std::vector<int64_t> key; int fwd, adj; std::vector<Plan::TuneRow> rows; };
 std::vector<TuneEntry> g_tune_cache;
+
+// FNV-1a over the apertures of shots [shot0, shot0 + ns) (0 without apertures)
+int64_t window_hash(Plan* P, int shot0, int ns) {
+    if (P->h_win.empty()) return 0;
+    uint64_t h = 1469598103934665603ull;
+    for (int i = 2 * shot0; i < 2 * (shot0 + ns); ++i) {
+        h ^= (uint64_t)(uint32_t)P->h_win[i];
+        h *= 1099511628211ull;
+    }
+    return (int64_t)(h >> 1);
+}
+
+// One timing run of the forward-type and adjoint-type loops of candidate
+// `shape`: the normal operator on p (probe = false), or a point-source forward
+// pass of nprobe steps and an adjoint pass injecting its data (probe = true).
+esi_status_t tune_run(Plan* P, int shot0, int ns, const float* p, float* Ap, bool probe, int nprobe,
+                      const TileLists* L) {
+    if (!probe) return do_normal(P, shot0, ns, p, Ap, L, nullptr, false, nullptr, nullptr, nullptr, nullptr, nullptr);
+    ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
+    StepArgs a = base_args(P, L, shot0, ns);
+    a.wavelet = P->dscr2;                  // zeros
+    a.gat_data = P->dscr;
+    int cs = 0;
+    ESI_TRY(forward_loop(P, a, F_SRC_POINT | F_GATHER, P->ring, &cs, 0, nprobe));
+    ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
+    StepArgs b = base_args(P, L, shot0, ns);
+    b.inj_data = P->dscr;
+    cs = 0;
+    return adjoint_loop(P, b, F_INJ, P->ring, &cs, P->nt - nprobe, P->nt);
+}
 
 }  // namespace
 
@@ -1055,63 +1194,105 @@ extern "C" esi_status_t esi_plan_autotune(esi_plan_t plan, int32_t shot0, int32_
     if (!plan) return fail(ESI_ERR_ARG, "null plan");
     Plan* P = (Plan*)plan;
     ESI_TRY(check_shots(P, shot0, ns));
-    if (!p || !Ap) return fail(ESI_ERR_ARG, "null pointer");
-    const int64_t n = (int64_t)ns * P->nt * P->nphys;
-    if ((Ap < p + n) && (p < Ap + n)) return fail(ESI_ERR_ARG, "p and Ap overlap");
-    if (P->ndim != 2) {
-        // one configuration only: the 3D kernel has no two-step variant
-        if (choice) { choice[0] = 1; choice[1] = 1; }
-        return ESI_OK;
+    if (!p != !Ap) return fail(ESI_ERR_ARG, "p and Ap: both device vectors, or both NULL");
+    const bool probe = !p;
+    if (!probe) {
+        const int64_t n = (int64_t)ns * P->nt * P->nphys;
+        if ((Ap < p + n) && (p < Ap + n)) return fail(ESI_ERR_ARG, "p and Ap overlap");
     }
-    const int key[5] = {P->ndim, P->nzp, P->nyp, P->nxp, ns};
+    P->tune_rows.clear();
+    const int nprobe = std::min(P->nt, 64);
+    const std::vector<int64_t> key = {P->ndim, P->nzp, P->nyp, P->nxp, ns, P->nt, probe ? 1 : 0,
+                                      window_hash(P, shot0, ns)};
     if (!force)
         for (const TuneEntry& e : g_tune_cache)
-            if (std::equal(key, key + 5, e.key)) {
+            if (e.key == key) {
                 P->tb_fwd = e.fwd;
                 P->tb_adj = e.adj;
+                P->tune_rows = e.rows;
                 if (choice) { choice[0] = e.fwd; choice[1] = e.adj; }
                 return ESI_OK;
             }
     TileLists* L;
     ESI_TRY(lists_for(P, &L));
+    if (probe) {
+        ESI_TRY(grow_t(&P->dscr, &P->dscr_cap, std::max<int64_t>(data_len(P, shot0, ns), 1), P->stream));
+        ESI_TRY(grow_t(&P->dscr2, &P->dscr2_cap, (int64_t)ns * P->nt, P->stream));
+        ESI_TRY(launch_fill(P, P->dscr2, (int64_t)ns * P->nt, 0.f));
+        ESI_TRY(launch_fill(P, P->dscr, std::max<int64_t>(data_len(P, shot0, ns), 1), 0.f));
+    }
     // keep the caller's profile aside and time each candidate on its own
     const bool prof = P->prof_on;
     std::vector<Plan::ProfRec> pend;
     std::vector<Plan::ProfTot> tot;
     pend.swap(P->prof_pending);
     tot.swap(P->prof_tot);
+    const int tf0 = P->tb_fwd, ta0 = P->tb_adj;
     double best_f = 1e300, best_a = 1e300;
-    int tb_f = 2, tb_a = 2;
+    int sf = LS_T2_32, sa = LS_T2_32;
     esi_status_t st = ESI_OK;
-    for (int tb = 1; tb <= 2 && st == ESI_OK; ++tb) {
-        P->tb_fwd = P->tb_adj = tb;
-        P->prof_on = false;   // first run builds the tile lists of this choice
-        st = do_normal(P, shot0, ns, p, Ap, L, nullptr, false, nullptr, nullptr, nullptr, nullptr, nullptr);
+    std::vector<Plan::TuneRow> rows;
+    const std::vector<int> cands = P->ndim == 2 ? std::vector<int>{LS_ONE, LS_T2_24, LS_T2_32, LS_T2_40}
+                                                : std::vector<int>{LS_ONE, LS_T2_32};
+    for (int shape : cands) {
+        P->tb_fwd = P->tb_adj = shape;
+        P->prof_on = false;   // first run builds the tile lists of this shape and warms up
+        st = tune_run(P, shot0, ns, p, Ap, probe, nprobe, L);
         if (st != ESI_OK) break;
         P->prof_on = true;
-        st = do_normal(P, shot0, ns, p, Ap, L, nullptr, false, nullptr, nullptr, nullptr, nullptr, nullptr);
+        st = tune_run(P, shot0, ns, p, Ap, probe, nprobe, L);
         if (st != ESI_OK) break;
         P->prof_on = false;
         st = fold_profile(P);
         if (st != ESI_OK) break;
         double f = 0.0, a = 0.0;
-        for (const auto& q : P->prof_tot) (q.flags & F_NORMAL ? a : f) += q.ms;
+        for (const auto& q : P->prof_tot) (q.flags & F_INJ ? a : f) += q.ms;
         P->prof_tot.clear();
-        if (f < best_f) { best_f = f; tb_f = tb; }
-        if (a < best_a) { best_a = a; tb_a = tb; }
+        rows.push_back({shape, f, a});
+        if (f < best_f) { best_f = f; sf = shape; }
+        if (a < best_a) { best_a = a; sa = shape; }
     }
     P->prof_on = prof;
     P->prof_pending.swap(pend);
     P->prof_tot.swap(tot);
-    if (st != ESI_OK) return st;
-    P->tb_fwd = tb_f;
-    P->tb_adj = tb_a;
-    TuneEntry e;
-    std::copy(key, key + 5, e.key);
-    e.fwd = tb_f;
-    e.adj = tb_a;
-    g_tune_cache.push_back(e);
-    if (choice) { choice[0] = tb_f; choice[1] = tb_a; }
+    if (st != ESI_OK) {
+        P->tb_fwd = tf0;
+        P->tb_adj = ta0;
+        return st;
+    }
+    P->tb_fwd = sf;
+    P->tb_adj = sa;
+    P->tune_rows = rows;
+    g_tune_cache.push_back({key, sf, sa, rows});
+    if (choice) { choice[0] = sf; choice[1] = sa; }
+    return ESI_OK;
+}
+
+extern "C" esi_status_t esi_plan_tune_table(esi_plan_t plan, int32_t cap, int32_t* count, int32_t* shape,
+                                            double* fwd_ms, double* adj_ms) {
+    set_error("");
+    if (!plan || !count) return fail(ESI_ERR_ARG, "null argument");
+    if (cap > 0 && (!shape || !fwd_ms || !adj_ms)) return fail(ESI_ERR_ARG, "null output array");
+    Plan* P = (Plan*)plan;
+    *count = (int32_t)P->tune_rows.size();
+    for (int i = 0; i < cap && i < (int)P->tune_rows.size(); ++i) {
+        shape[i] = P->tune_rows[i].shape;
+        fwd_ms[i] = P->tune_rows[i].fwd_ms;
+        adj_ms[i] = P->tune_rows[i].adj_ms;
+    }
+    return ESI_OK;
+}
+
+extern "C" esi_status_t esi_plan_set_launch_shape(esi_plan_t plan, int32_t forward, int32_t adjoint) {
+    set_error("");
+    if (!plan) return fail(ESI_ERR_ARG, "null plan");
+    Plan* P = (Plan*)plan;
+    if (forward < LS_ONE || forward > LS_COUNT || adjoint < LS_ONE || adjoint > LS_COUNT)
+        return fail(ESI_ERR_ARG, "launch shapes are 1 .. 4");
+    if (P->ndim != 2 && (forward > LS_T2_32 || adjoint > LS_T2_32))
+        return fail(ESI_ERR_ARG, "3D plans run shape 1 (one step per launch) or 2 (two steps)");
+    P->tb_fwd = forward;
+    P->tb_adj = adjoint;
     return ESI_OK;
 }
 

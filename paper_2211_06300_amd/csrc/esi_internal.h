@@ -17,6 +17,13 @@ constexpr int GH = 8;            // zero ghost cells around the padded grid in s
                                  // (two stencil radii: enough for two-step blocking)
 constexpr int XCDS = 8;          // MI355X: 8 accelerator complex dies, 32 CUs each
 
+// Launch shapes of 2D time loops (the autotuner's candidates): one step per
+// launch on 64 x 32 tiles, or two steps per launch on 56-column tiles of 32,
+// 24 or 40 rows.  3D loops use LS_ONE.
+enum : int { LS_ONE = 1, LS_T2_32 = 2, LS_T2_24 = 3, LS_T2_40 = 4 };
+constexpr int LS_COUNT = 4;
+
+
 // Thread-local error text.
 void set_error(const std::string& s);
 
@@ -163,7 +170,10 @@ struct Plan {
     int* fcg_i = nullptr; int64_t fcg_i_cap = 0;      // mode, restart, fallback, kbest, cg_at [5][nshots]
 
     std::vector<TileLists*> lists;       // one per tile shape used
-    int tb_fwd = 2, tb_adj = 2;          // 2D steps per launch (1 or 2) of forward / adjoint loops
+    int tb_fwd = LS_T2_32, tb_adj = LS_T2_32;   // launch shape of forward / adjoint loops (2D)
+    // the autotuner's last candidate table: shape, forward ms, adjoint ms
+    struct TuneRow { int shape; double fwd_ms, adj_ms; };
+    std::vector<TuneRow> tune_rows;
     // checkpoints retained by esi_forward_ckpt for a SEED_REUSE gradient
     bool ck_valid = false;
     int ck_shot0 = 0, ck_nshots = 0, ck_kind = 0, ck_K = 0;
@@ -351,7 +361,13 @@ constexpr int RING = 4;
 // time-loop plumbing of the entry points (api.hip)
 esi_status_t check_shots(Plan* P, int shot0, int nshots);
 esi_status_t lists_for(Plan* P, TileLists** L);
-esi_status_t t2_lists(Plan* P, TileLists** L2, bool adjoint);
+// launch shape a loop of `flags` runs with (the plan's choice, or 32-row
+// two-step tiles for variants without other heights), and its tiling
+int loop_shape(Plan* P, unsigned flags, bool adjoint);
+esi_status_t shape_lists(Plan* P, int shape, TileLists** L);
+void shape_tile(Plan* P, int shape, int* tx, int* ty, int* tz);
+// the largest tile count of the plan's tilings (stride of per-tile partials)
+int max_tiles(Plan* P);
 StepArgs base_args(Plan* P, const TileLists* L, int shot0, int nshots);
 esi_status_t ring_for(Plan* P, float** ring, int* cap, int nshots);
 int64_t data_len(Plan* P, int shot0, int nshots);

@@ -436,3 +436,20 @@ extern "C" esi_status_t esi_invert(esi_plan_t plan, int32_t shot0, int32_t ns, c
     }
     return ESI_OK;
 }
+
+extern "C" esi_status_t esi_precond_scale(esi_plan_t plan, int32_t shot0, int32_t nshots, double gamma,
+                                          float* out) {
+    set_error("");
+    if (!plan) return fail(ESI_ERR_ARG, "null plan");
+    Plan* P = (Plan*)plan;
+    ESI_TRY(check_shots(P, shot0, nshots));
+    if (P->ndim != 2) return fail(ESI_ERR_ARG, "the cell scale is for 2D plans");
+    if (P->w_identity) return fail(ESI_ERR_ARG, "the cell scale models the annihilator weight, not B = I");
+    if (!out) return fail(ESI_ERR_ARG, "null out");
+    if (!(gamma > 0) || !std::isfinite(gamma)) return fail(ESI_ERR_ARG, "gamma must be finite and > 0");
+    const int64_t n = (int64_t)nshots * P->nphys;
+    hipLaunchKernelGGL(k_cell_scale, dim3(grid_for(n)), dim3(NT), 0, P->stream, P->d_src, shot0, nshots, P->nz,
+                       P->nx, P->beta, P->b_eps, gamma, out);
+    ESI_HIP_TRY(hipGetLastError());
+    return ESI_OK;
+}

@@ -210,10 +210,11 @@ esi_status_t get_lists(Plan* P, int tx, int tz, int ty, TileLists** out) {
     std::vector<int32_t> inj_ptr((size_t)S * (T + 1)), gat_ptr((size_t)S * (T + 1));
     std::vector<int32_t> inj_cell, inj_rptr{0}, inj_rid, gat_cell, gat_rid;
     std::vector<int32_t> src_tile(S), src_cell(S);
-    // grown-tile injection lists (2D): a receiver belongs to every tile whose
-    // region [x0-4, x0+tx+4) x [z0-4, z0+tz+4) holds it
+    // grown-tile injection lists: a receiver belongs to every tile whose region
+    // grown by one stencil radius, [x0-4, x0+tx+4) x [z0-4, z0+tz+4)
+    // (x [y0-4, y0+ty+4) in 3D), holds it; cells are indexed on the grown tile
     std::vector<int32_t> inj2_ptr((size_t)S * (T + 1)), inj2_cell, inj2_rptr{0}, inj2_rid;
-    const int gw = tx + 2 * HALO, gh = tz + 2 * HALO;
+    const int gw = tx + 2 * HALO, gh = tz + 2 * HALO, gy3 = ty + 2 * HALO;
     for (int s = 0; s < S; ++s) {
         int64_t r0 = P->h_rec_ptr[s], r1 = P->h_rec_ptr[s + 1];
         // (tile, cell, rid) for every receiver of this shot, sorted
@@ -247,19 +248,25 @@ esi_status_t get_lists(Plan* P, int tx, int tz, int ty, TileLists** out) {
         }
         ip[T] = (int32_t)inj_cell.size();
         gp[T] = (int32_t)gat_cell.size();
-        if (nd == 2) {
+        {
             // (tile, grown cell, rid) for every tile region holding each receiver
             std::vector<std::array<int32_t, 3>> g2;
             for (int64_t r = r0; r < r1; ++r) {
                 const int32_t* pr = &P->h_rec[r * nd];
-                const int x = pr[0] + P->nb, z = pr[1] + P->nb;
+                const int x = pr[0] + P->nb, z = pr[1] + P->nb, y = nd == 3 ? pr[2] + P->nb : 0;
                 for (int tzi = 0; tzi < L->tiles_z; ++tzi) {
                     const int gz = z - (tzi * tz - HALO);
                     if (gz < 0 || gz >= gh) continue;
-                    for (int txi = 0; txi < L->tiles_x; ++txi) {
-                        const int gx = x - (txi * tx - HALO);
-                        if (gx < 0 || gx >= gw) continue;
-                        g2.push_back({tzi * L->tiles_x + txi, gz * gw + gx, (int32_t)(r - r0)});
+                    for (int tyi = 0; tyi < L->tiles_y; ++tyi) {
+                        const int gy = nd == 3 ? y - (tyi * ty - HALO) : 0;
+                        if (nd == 3 && (gy < 0 || gy >= gy3)) continue;
+                        for (int txi = 0; txi < L->tiles_x; ++txi) {
+                            const int gx = x - (txi * tx - HALO);
+                            if (gx < 0 || gx >= gw) continue;
+                            const int tile = (tzi * L->tiles_y + tyi) * L->tiles_x + txi;
+                            const int cell = nd == 3 ? (gz * gy3 + gy) * gw + gx : gz * gw + gx;
+                            g2.push_back({tile, cell, (int32_t)(r - r0)});
+                        }
                     }
                 }
             }
@@ -412,7 +419,9 @@ extern "C" esi_status_t esi_plan_create(esi_plan_t* plan, const esi_grid_t* g, c
         // round_up(nxp, 256) plus the ghost frame, and 56-wide two-step tiles
         // whose staged region reaches 72 columns past the last tile origin
         P->XS = round_up(std::max(round_up(P->nxp, 256) + 2 * GH, P->nxp + 80), 32);
-        P->ZS = round_up(P->nzp, 64) + 2 * GH;
+        // rows: whole tiles of every height in use (64-row one-step tiles,
+        // two-step tiles of 24, 32 or 40 rows) plus the ghost frame
+        P->ZS = std::max({round_up(P->nzp, 64), round_up(P->nzp, 24), round_up(P->nzp, 40)}) + 2 * GH;
         P->YS = 1;
     } else {
         // the 3D step kernel's column blocks (tx x ty) and z chunks (tz
@@ -424,6 +433,7 @@ extern "C" esi_status_t esi_plan_create(esi_plan_t* plan, const esi_grid_t* g, c
         P->ZS = round_up(P->nzp, tz) + 2 * GH;
     }
     P->fsize = (int64_t)P->ZS * P->YS * P->XS;
+    if (nd == 3) P->tb_fwd = P->tb_adj = LS_ONE;   // two steps per launch on request
     P->nphys = (int64_t)g->nz * g->ny * g->nx;
     double w[5];
     lap_weights(w);

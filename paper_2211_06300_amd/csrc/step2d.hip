@@ -480,21 +480,26 @@ __global__ __launch_bounds__(256, ESI_MINW) void k_step2d(const StepArgs a) {
 // one lane per column (a wave spans it exactly), 10 rows per wave, z
 // neighbours from a register window.  The second step runs on the tile, one
 // lane per column (lanes 56..63 idle), 8 rows per wave.
-constexpr int T2W = 56, T2Z = 32;                 // output tile
+// The tile height TH (24, 32 or 40 rows) is a template parameter: the
+// autotuner's candidates.  Every height computes the same bits per cell.
+constexpr int T2W = 56;                           // output tile width
 constexpr int A_W = T2W + 2 * HALO;               // 64: first-step region width
-constexpr int A_H = T2Z + 2 * HALO;               // 40
-constexpr int A_RZ = A_H / 4;                     // first-step rows per wave
-constexpr int B_RZ = T2Z / 4;                     // second-step rows per wave
-constexpr int U0W = T2W + 4 * HALO, U0H = T2Z + 4 * HALO;   // 72 x 48
-static_assert(A_W == 64 && A_H % 4 == 0 && U0H % 4 == 0, "two-step tile geometry");
+constexpr int U0W = T2W + 4 * HALO;               // 72
+static_assert(A_W == 64, "two-step tile geometry");
 
 // Occupancy targets: five waves per SIMD for the injecting (adjoint)
 // variants, whose registers and LDS allow it without spilling, and at least
 // four for the others (the flexible-CG direction update would otherwise take
 // 129 VGPRs and drop to three).
-template <unsigned FL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((FL & F_INJ) != 0) ? 5 : 4)))
+template <unsigned FL, int TH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((FL & F_INJ) != 0 && TH <= 32) ? 5 : 4)))
 void k_step2d_t2(const StepArgs a) {
+    constexpr int T2Z = TH;                       // output tile rows
+    constexpr int A_H = T2Z + 2 * HALO;           // first-step region rows
+    constexpr int A_RZ = A_H / 4;                 // first-step rows per wave
+    constexpr int B_RZ = T2Z / 4;                 // second-step rows per wave
+    constexpr int U0H = T2Z + 4 * HALO;
+    static_assert(T2Z % 4 == 0 && A_H % 4 == 0 && U0H % 4 == 0, "two-step tile geometry");
     // LDS (31 KB, five workgroups per CU): u^{tA} on the tile + 8 (dead after
     // the first step, then holding the second step's injection), u after the
     // first step on the tile + 4, d after the first step on the tile.  The
@@ -505,6 +510,16 @@ void k_step2d_t2(const StepArgs a) {
     __shared__ double sred[4];
     float* const sinjB = U0;
     static_assert(U0H * U0W >= A_H * A_W, "the second step's injection fits the u^{tA} buffer");
+    // Gradient accumulators are read and written once per launch: both steps'
+    // products are chained per cell in the second step, g = fmaf(B, fmaf(A, g))
+    // as two one-step launches would add them.  CORR takes the first step's
+    // field from U1 and reloads its stored (dA/dm)u there; PENALTY recomputes
+    // the first step's (dA/dm)u from u^{tA}, which U0 still holds (no
+    // injection reuses it in forward variants).  The DTFT source is not
+    // recomputed: that variant keeps one update per step.
+    constexpr bool CHAIN_CORR = (FL & F_CORR) != 0;
+    constexpr bool CHAIN_PEN = (FL & F_PENALTY) != 0 && (FL & (F_DTFT_SRC | F_INJ)) == 0;
+    constexpr unsigned FL_A = FL & ~((CHAIN_CORR ? F_CORR : 0u) | (CHAIN_PEN ? F_PENALTY : 0u));
 
     int s, t;
     work_item(a, xcd_remap(blockIdx.x, gridDim.x), &s, &t);
@@ -615,10 +630,6 @@ void k_step2d_t2(const StepArgs a) {
             for (int i = 0; i < A_RZ; ++i) rA[i] = tlA[i] ? at(oA.r, piA[i]) : 0.f;
         }
     }
-    if constexpr ((FL & F_CORR) != 0) {
-#pragma unroll
-        for (int i = 0; i < A_RZ; ++i) stA[i] = tlA[i] ? at(oA.stin, piA[i]) : 0.f;
-    }
 
 #pragma unroll
     for (int k = 0; k < RPW0; ++k) {
@@ -724,7 +735,8 @@ void k_step2d_t2(const StepArgs a) {
                 float wb = 0.f;
                 if constexpr ((FL & (F_NORMAL | F_PENALTY | F_RUPD)) != 0)
                     wb = annih_w(a, ixa, z0 - HALO + zr - a.nb, sx, sz);
-                cell_outputs<FL>(a, oA, piA[i], un, qd, lq, cA[i], pvA[i], stA[i], rA[i], wb, acc);
+                cell_outputs<FL_A>(a, oA, piA[i], un, qd, lq, cA[i], pvA[i], stA[i], rA[i], wb, acc);
+                if constexpr (CHAIN_PEN) acc += (double)(wb * qd) * (double)qd;   // penalty term
             }
         }
     }
@@ -812,6 +824,17 @@ void k_step2d_t2(const StepArgs a) {
 #pragma unroll
         for (int i = 0; i < B_RZ; ++i) stB[i] = at(oB.stin, pi[i]);
     }
+    // the first step's stored (dA/dm)u (CORR) or dense source (PENALTY) on the tile
+    float chA[(CHAIN_CORR || CHAIN_PEN) ? B_RZ : 1];
+    if constexpr (CHAIN_CORR) {
+#pragma unroll
+        for (int i = 0; i < B_RZ; ++i) chA[i] = at(oA.stin, pi[i]);
+    }
+    if constexpr (CHAIN_PEN) {
+        const float* __restrict__ q = a.dsrc + blk_off(a, s, tA, vA);
+#pragma unroll
+        for (int i = 0; i < B_RZ; ++i) chA[i] = ph[i] ? at(q, pi[i]) : 0.f;
+    }
 
     float colB[B_RZ + 2 * HALO];
 #pragma unroll
@@ -854,7 +877,24 @@ void k_step2d_t2(const StepArgs a) {
         }
         float wb = 0.f;
         if constexpr ((FL & (F_NORMAL | F_PENALTY | F_RUPD)) != 0) wb = annih_w(a, ix, z - a.nb, sx, sz);
-        cell_outputs<FL>(a, oB, pi[i], un, qd, lq, c2v[i], pvB[i], stB[i], rB[i], wb, acc);
+        cell_outputs<FL_A>(a, oB, pi[i], un, qd, lq, c2v[i], pvB[i], stB[i], rB[i], wb, acc);
+        if constexpr (CHAIN_CORR) {
+            const float uA = U1[(zl + HALO) * A_W + lc + HALO];
+            const float gA = fmaf(uA, chA[i], at(oB.gacc, pi[i]));
+            at(oB.gacc, pi[i]) = fmaf(un, stB[i], gA);
+        }
+        if constexpr (CHAIN_PEN) {
+            // the first step's lap + dx^2 q at this cell, as that step formed it
+            float qa = chA[i];
+            if constexpr ((FL & F_SRC_POINT) != 0) {
+                if ((zl + HALO) * A_W + lc + HALO == srcA) qa += a.wavelet[(int64_t)s * a.nt + tA];
+            }
+            const float lapA = lap_lds(a, U0 + (zl + 2 * HALO) * U0W + lc + 2 * HALO, U0W);
+            const float lqA = fmaf(a.dx2, qa, lapA);
+            const float gA = fmaf(wb * chA[i], c2v[i] * a.inv_dt2 * lqA, at(oB.gacc, pi[i]));
+            at(oB.gacc, pi[i]) = fmaf(wb * qd, c2v[i] * a.inv_dt2 * lq, gA);
+            acc += (double)(wb * qd) * (double)qd;   // penalty term (kept when a.part is set)
+        }
     }
 
     if constexpr ((FL & (F_NORMAL | F_SCALE | F_PENALTY | F_RUPD)) != 0) {
@@ -892,22 +932,60 @@ __global__ void k_final_gather(const float* __restrict__ field, int64_t fstride,
     }
 }
 
-template <unsigned FL, bool T2>
+// TH = 0: the one-step kernel; else the two-step kernel with TH-row tiles
+template <unsigned FL, int TH>
 esi_status_t launch2d(Plan* P, const StepArgs& a) {
     const int blocks = a.work ? a.nwork : a.tiles * a.nshots;
     if (blocks == 0) return ESI_OK;
-    if constexpr (T2)
-        hipLaunchKernelGGL(k_step2d_t2<FL>, dim3(blocks), dim3(256), 0, P->stream, a);
+    if constexpr (TH > 0)
+        hipLaunchKernelGGL((k_step2d_t2<FL, TH>), dim3(blocks), dim3(256), 0, P->stream, a);
     else
         hipLaunchKernelGGL(k_step2d<FL>, dim3(blocks), dim3(256), 0, P->stream, a);
     ESI_HIP_TRY(hipGetLastError());
     return ESI_OK;
 }
 
-template <bool T2>
+// The variants the autotuner may give other tile heights: those of the CG,
+// modelling and gradient loops.  Other variants run on 32-row tiles.
+template <int TH>
+esi_status_t dispatch2d_tuned(Plan* P, unsigned flags, const StepArgs& a) {
+    switch (flags) {
+#define ESI_CASE(F) case (F): return launch2d<(F), TH>(P, a);
+        ESI_CASE(F_SRC_POINT | F_GATHER)
+        ESI_CASE(F_SRC_POINT | F_STORE)
+        ESI_CASE(F_SRC_DENSE | F_GATHER)
+        ESI_CASE(F_SRC_DENSE | F_PENALTY)
+        ESI_CASE(F_CG_FUSE | F_GATHER | F_RUPD)
+        ESI_CASE(F_SRC_DENSE | F_GATHER | F_RUPD)
+        ESI_CASE(F_CG_FUSE | F_GATHER | F_SCALE)
+        ESI_CASE(F_SRC_DENSE | F_SCALE | F_GATHER)
+        ESI_CASE(F_INJ)
+        ESI_CASE(F_INJ | F_OUT)
+        ESI_CASE(F_INJ | F_NORMAL)
+        ESI_CASE(F_INJ | F_NORMAL | F_RUPD)
+        ESI_CASE(F_INJ | F_CORR)
+#undef ESI_CASE
+        default: return fail(ESI_ERR_ARG, "internal: 2D step flags " + std::to_string(flags) +
+                                              " have no " + std::to_string(TH) + "-row tiles");
+    }
+}
+
+bool tuned_variant(unsigned flags) {
+    switch (flags) {
+        case F_SRC_POINT | F_GATHER: case F_SRC_POINT | F_STORE: case F_SRC_DENSE | F_GATHER:
+        case F_SRC_DENSE | F_PENALTY: case F_CG_FUSE | F_GATHER | F_RUPD: case F_SRC_DENSE | F_GATHER | F_RUPD:
+        case F_CG_FUSE | F_GATHER | F_SCALE: case F_SRC_DENSE | F_SCALE | F_GATHER: case F_INJ:
+        case F_INJ | F_OUT: case F_INJ | F_NORMAL: case F_INJ | F_NORMAL | F_RUPD: case F_INJ | F_CORR:
+            return true;
+        default:
+            return false;
+    }
+}
+
+template <int TH>
 esi_status_t dispatch2d(Plan* P, unsigned flags, const StepArgs& a) {
     switch (flags) {
-#define ESI_CASE(F) case (F): return launch2d<(F), T2>(P, a);
+#define ESI_CASE(F) case (F): return launch2d<(F), TH>(P, a);
         ESI_CASE(F_SRC_POINT | F_GATHER)
         ESI_CASE(F_SRC_POINT | F_GATHER | F_STORE)
         ESI_CASE(F_SRC_POINT | F_STORE)
@@ -945,12 +1023,25 @@ esi_status_t dispatch2d(Plan* P, unsigned flags, const StepArgs& a) {
 
 }  // namespace
 
-esi_status_t launch_step2d(Plan* P, unsigned flags, const StepArgs& a, bool two_steps) {
-    return two_steps ? dispatch2d<true>(P, flags, a) : dispatch2d<false>(P, flags, a);
+esi_status_t launch_step2d(Plan* P, unsigned flags, const StepArgs& a, int shape) {
+    switch (shape) {
+        case LS_ONE: return dispatch2d<0>(P, flags, a);
+        case LS_T2_32: return dispatch2d<32>(P, flags, a);
+        case LS_T2_24: return dispatch2d_tuned<24>(P, flags, a);
+        case LS_T2_40: return dispatch2d_tuned<40>(P, flags, a);
+        default: return fail(ESI_ERR_ARG, "internal: launch shape " + std::to_string(shape));
+    }
+}
+
+int step2d_loop_shape(unsigned flags, int shape) {
+    return (shape == LS_T2_24 || shape == LS_T2_40) && !tuned_variant(flags) ? LS_T2_32 : shape;
 }
 
 void step2d_tile_shape(int* tx, int* tz) { *tx = TX; *tz = TZ; }
-void step2d_t2_tile_shape(int* tx, int* tz) { *tx = T2W; *tz = T2Z; }
+void step2d_shape_tile(int shape, int* tx, int* tz) {
+    *tx = shape == LS_ONE ? TX : T2W;
+    *tz = shape == LS_ONE ? TZ : shape == LS_T2_24 ? 24 : shape == LS_T2_40 ? 40 : 32;
+}
 
 esi_status_t launch_final_gather(Plan* P, const float* field, int64_t fstride, float* data,
                                  int shot0, int nshots) {

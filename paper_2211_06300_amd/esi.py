@@ -19,6 +19,9 @@ SRC_POINT, SRC_DENSE = 0, 1
 GRAD_PENALTY, GRAD_ADJOINT, GRAD_SEED, GRAD_SEED_REUSE = 0, 1, 2, 3
 WEIGHT_ANNIHILATOR, WEIGHT_IDENTITY = 0, 1
 BETA_FIXED, BETA_DISCREPANCY = 0, 1
+LAUNCH_ONE_STEP, LAUNCH_TWO_STEP_32, LAUNCH_TWO_STEP_24, LAUNCH_TWO_STEP_40 = 1, 2, 3, 4
+LAUNCH_NAMES = {1: "1 step, 64x32 tiles", 2: "2 steps, 56x32 tiles", 3: "2 steps, 56x24 tiles",
+                4: "2 steps, 56x40 tiles"}
 INNER_CG, INNER_FCG_SCALE, INNER_DATASPACE = 0, 1, 2
 _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_SHAPE", 3: "ERR_CFL", 4: "ERR_OOM", 5: "ERR_HIP",
            6: "ERR_BREAKDOWN", 7: "ERR_NONFINITE"}
@@ -51,6 +54,31 @@ class _CgReport(ctypes.Structure):
                 ("stat_xref", ctypes.c_void_p), ("stat_out", ctypes.c_void_p)]
 
 
+class _CgState(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("rr0", ctypes.c_void_p), ("rr", ctypes.c_void_p), ("beta", ctypes.c_void_p),
+                ("iterating", ctypes.c_void_p), ("iters", ctypes.c_void_p), ("status", ctypes.c_void_p),
+                ("res_hist", ctypes.c_void_p), ("hist_cap", ctypes.c_int32)]
+
+
+class CgState:
+    """Host arrays of a saved CG solve (esi_cg_state_t)."""
+
+    def __init__(self, nshots: int, hist_cap: int):
+        self.k = 0
+        self.rr0 = np.zeros(nshots)
+        self.rr = np.zeros(nshots)
+        self.beta = np.zeros(nshots)
+        self.iterating = np.zeros(nshots, dtype=np.int32)
+        self.iters = np.zeros(nshots, dtype=np.int32)
+        self.status = np.zeros(nshots, dtype=np.int32)
+        self.res_hist = np.full((nshots, hist_cap), -1.0)
+
+    def _struct(self):
+        return _CgState(self.k, self.rr0.ctypes.data, self.rr.ctypes.data, self.beta.ctypes.data,
+                        self.iterating.ctypes.data, self.iters.ctypes.data, self.status.ctypes.data,
+                        self.res_hist.ctypes.data, self.res_hist.shape[1])
+
+
 class _InvertOpts(ctypes.Structure):
     _fields_ = [("outer_iters", ctypes.c_int32), ("cg_iters", ctypes.c_int32), ("cg_rtol", ctypes.c_double),
                 ("shot_group", ctypes.c_int32), ("lbfgs_mem", ctypes.c_int32), ("ls_max", ctypes.c_int32),
@@ -78,7 +106,8 @@ EXPORTS = ["esi_plan_create", "esi_plan_set_model", "esi_plan_destroy", "esi_las
            "esi_plan_set_weight", "esi_data_residual", "esi_wri_gradient", "esi_plan_set_beta",
            "esi_invert", "esi_dtft_set_freqs", "esi_dtft_normal_apply", "esi_dtft_rhs", "esi_dtft_cg_solve",
            "esi_dtft_to_time", "esi_dtft_gradient", "esi_ds_cg_solve", "esi_plan_set_dtft_block",
-           "esi_plan_set_ds_ckpt"]
+           "esi_plan_set_ds_ckpt", "esi_precond_scale", "esi_plan_tune_table",
+           "esi_plan_set_launch_shape", "esi_cg_solve_state"]
 # time-step kernel variants (bit set of fused work), as in include/esi.h
 K_FLAGS = {1: "SRC_POINT", 2: "SRC_DENSE", 4: "CG_FUSE", 8: "INJ", 16: "GATHER", 32: "OUT",
            64: "NORMAL", 128: "PENALTY", 256: "STORE", 512: "CORR", 1024: "SRC_REC",
@@ -104,6 +133,8 @@ def load_library(path: str = LIB_PATH):
     L.esi_adjoint.argtypes = [vp, i32, i32, vp, vp]
     L.esi_normal_apply.argtypes = [vp, i32, i32, vp, vp, vp]
     L.esi_cg_solve.argtypes = [vp, i32, i32, vp, vp, vp, i32, dbl, ctypes.POINTER(_CgReport)]
+    L.esi_cg_solve_state.argtypes = [vp, i32, i32, vp, vp, vp, i32, dbl, ctypes.POINTER(_CgState),
+                                     ctypes.POINTER(_CgState), ctypes.POINTER(_CgReport)]
     L.esi_gradient.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp, vp, i32]
     L.esi_plan_set_weight.argtypes = [vp, i32]
     L.esi_plan_set_beta.argtypes = [vp, dbl]
@@ -126,6 +157,9 @@ def load_library(path: str = LIB_PATH):
     L.esi_plan_set_ds_ckpt.argtypes = [vp, i32]
     L.esi_plan_autotune.argtypes = [vp, i32, i32, vp, vp, i32, vp]
     L.esi_forward_ckpt.argtypes = [vp, i32, i32, i32, vp, vp, i32]
+    L.esi_precond_scale.argtypes = [vp, i32, i32, dbl, vp]
+    L.esi_plan_tune_table.argtypes = [vp, i32, vp, vp, vp, vp]
+    L.esi_plan_set_launch_shape.argtypes = [vp, i32, i32]
     L.esi_grad_velocity.argtypes = [vp, vp, vp, vp]
     L.esi_plan_profile_read.argtypes = [vp, i32, vp, vp, vp, vp, vp]
     L.esi_fpcg_solve.argtypes = [vp, i32, i32, vp, vp, vp, i32, dbl, vp, i32, vp, ctypes.POINTER(_CgReport)]
@@ -248,16 +282,36 @@ class Plan:
     def set_time_block(self, steps: int):
         _check(self._lib.esi_plan_set_time_block(self._h, int(steps)))
 
-    def autotune(self, shot0=0, nshots=None, force=False, p=None, Ap=None):
-        """esi_plan_autotune; returns (forward, adjoint) steps per launch."""
+    def autotune(self, shot0=0, nshots=None, force=False, p=None, Ap=None, probe=False):
+        """esi_plan_autotune; returns the (forward, adjoint) launch shapes.
+        probe=True times a propagation-only pass (no wavefield-sized vectors)."""
         shot0, nshots = self._range(shot0, nshots)
-        p = self.new_vec(nshots) if p is None else p
-        Ap = self.new_vec(nshots) if Ap is None else Ap
+        if probe:
+            pp = ap = None
+        else:
+            p = self.new_vec(nshots) if p is None else p
+            Ap = self.new_vec(nshots) if Ap is None else Ap
+            pp = _f32(p, self.vec_shape(nshots), "p")
+            ap = _f32(Ap, self.vec_shape(nshots), "Ap")
         ch = np.zeros(2, dtype=np.int32)
-        _check(self._lib.esi_plan_autotune(self._h, shot0, nshots, _f32(p, self.vec_shape(nshots), "p"),
-                                           _f32(Ap, self.vec_shape(nshots), "Ap"), int(bool(force)),
+        _check(self._lib.esi_plan_autotune(self._h, shot0, nshots, pp, ap, int(bool(force)),
                                            ch.ctypes.data_as(ctypes.c_void_p)))
         return int(ch[0]), int(ch[1])
+
+    def tune_table(self):
+        """esi_plan_tune_table: [(shape, forward ms, adjoint ms)] of the last autotune."""
+        cap = 8
+        cnt = np.zeros(1, dtype=np.int32)
+        sh = np.zeros(cap, dtype=np.int32)
+        f = np.zeros(cap)
+        a = np.zeros(cap)
+        _check(self._lib.esi_plan_tune_table(self._h, cap, cnt.ctypes.data, sh.ctypes.data, f.ctypes.data,
+                                             a.ctypes.data))
+        return [(int(sh[i]), float(f[i]), float(a[i])) for i in range(min(int(cnt[0]), cap))]
+
+    def set_launch_shape(self, forward: int, adjoint: int):
+        """esi_plan_set_launch_shape (LAUNCH_* shapes)."""
+        _check(self._lib.esi_plan_set_launch_shape(self._h, int(forward), int(adjoint)))
 
     def set_weight(self, kind: int):
         """esi_plan_set_weight: WEIGHT_ANNIHILATOR (ESI) or WEIGHT_IDENTITY (WRI, B = I)."""
@@ -421,6 +475,16 @@ class Plan:
                                      _f32(out, self.data_shape(shot0, nshots), "data")))
         return out
 
+    def precond_scale(self, gamma, shot0=0, nshots=None, out=None):
+        """esi_precond_scale: the analytic cell scale 1 / (beta B^2 + gamma) per
+        shot, float32 [nshots, *phys] on the device."""
+        shot0, nshots = self._range(shot0, nshots)
+        out = torch.empty((nshots, *self.phys_shape), dtype=torch.float32, device=self.device) \
+            if out is None else out
+        _check(self._lib.esi_precond_scale(self._h, shot0, nshots, float(gamma),
+                                           _f32(out, (nshots, *self.phys_shape), "out")))
+        return out
+
     def forward_ckpt(self, src, ckpt_every, kind=SRC_POINT, shot0=0, nshots=None, out=None):
         """Forward modelling that keeps wavefield checkpoints every `ckpt_every`
         steps for a following gradient(GRAD_SEED_REUSE, ...)."""
@@ -471,6 +535,31 @@ class Plan:
                                       _f32(work, (3, *self.vec_shape(nshots)), "work"),
                                       int(max_iter), float(rtol), ctypes.byref(rep)))
         return x, {"iters": int(rep.iters), "shot_iters": iters, "res_hist": hist}
+
+    def cg_solve_state(self, d_obs, max_iter, rtol=0.0, shot0=0, nshots=None, x=None, work=None,
+                       resume: "CgState | None" = None, save: bool = False):
+        """esi_cg_solve_state: CG from x_0 = 0 or from `resume`; with save=True
+        returns the state after the last iteration as a CgState."""
+        shot0, nshots = self._range(shot0, nshots)
+        x = self.new_vec(nshots) if x is None else x
+        if work is None:
+            work = torch.empty((3, *self.vec_shape(nshots)), dtype=torch.float32, device=self.device)
+        hist = np.zeros((nshots, max_iter + 1))
+        iters = np.zeros(nshots, dtype=np.int32)
+        rep = _CgReport(0, iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                        hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        st = CgState(nshots, max_iter + 1) if save else None
+        rs = resume._struct() if resume is not None else None
+        ss = st._struct() if st is not None else None
+        dptr = None if d_obs is None else _f32(d_obs, self.data_shape(shot0, nshots), "d_obs")
+        code = self._lib.esi_cg_solve_state(self._h, shot0, nshots, dptr, _f32(x, self.vec_shape(nshots), "x"),
+                                            _f32(work, (3, *self.vec_shape(nshots)), "work"), int(max_iter),
+                                            float(rtol), None if rs is None else ctypes.byref(rs),
+                                            None if ss is None else ctypes.byref(ss), ctypes.byref(rep))
+        if st is not None:
+            st.k = int(ss.k)
+        _check(code)
+        return x, {"iters": int(rep.iters), "shot_iters": iters, "res_hist": hist}, st
 
     def fpcg_solve(self, d_obs, max_iter, rtol=0.0, net=None, scale=None, shot0=0, nshots=None,
                    x=None, work=None, stat_xref=None, stat_out=None, net_every=0):

@@ -32,13 +32,10 @@ def pad8(n: int) -> int:
     return (n + 7) // 8 * 8
 
 
-def analytic_scale(cfg, gamma: float, device="cuda") -> torch.Tensor:
-    """Cell scale 1 / (beta B^2 + gamma) per shot, B = |x - x_s| / dx + eps in
-    cells; float32 [nshots, nz, nx] on the device."""
-    zz, xx = np.meshgrid(np.arange(cfg.nz), np.arange(cfg.nx), indexing="ij")
-    S = np.stack([1.0 / (cfg.beta * (np.hypot(xx - sx, zz - sz) + cfg.b_eps) ** 2 + gamma)
-                  for sx, sz in cfg.src[:, :2]])
-    return torch.from_numpy(S.astype(np.float32)).to(device)
+def analytic_scale(plan, gamma: float) -> torch.Tensor:
+    """The library's analytic cell scale of every shot of `plan`
+    (esi_precond_scale); float32 [nshots, nz, nx] on the device."""
+    return plan.precond_scale(gamma)
 
 
 def observed_data(cfg, device="cuda") -> torch.Tensor:
@@ -88,7 +85,7 @@ def model_pairs(cfg, k_plain=25, k_fcg=130, fcg_every=5, gamma=GAMMA0, ref_rtol=
     """Samples (x_in [n, 3, Hp, Wp], a [n, Hp, Wp], c [n, Hp, Wp]) of one model."""
     d = observed_data(cfg, device)
     plan = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_start).to(device))
-    S = analytic_scale(cfg, gamma, device)
+    S = analytic_scale(plan, gamma)
     ns = cfg.nshots
     work = torch.empty((3, *plan.vec_shape(ns)), dtype=torch.float32, device=device)
     xref, rep = plan.fpcg_solve(d, ref_iters, rtol=ref_rtol, scale=S, work=work)
@@ -226,7 +223,7 @@ def compare_solvers(cfg, theta=None, rtol=1e-3, max_iter=600, gamma=GAMMA0, devi
     ns = cfg.nshots
     work = torch.empty((3, *plan.vec_shape(ns)), dtype=torch.float32, device=device)
     x = plan.new_vec(ns)
-    S0 = analytic_scale(cfg, gamma, device)
+    S0 = analytic_scale(plan, gamma)
     net = None
     if theta is not None and any(m.startswith("learned") for m in methods):
         net = esi.Unet(pad8(cfg.nz), pad8(cfg.nx), ns, device=device)

@@ -44,7 +44,10 @@ def test_measured_traffic_lookup(tmp_path):
     assert bench.measured_traffic(20 | T, 16.0, str(p)) == (2 * 100 + 50) * 1024
     assert bench.measured_traffic(72 | T, 16.0, str(p)) == (2 * 10 + 5) * 1024
     assert bench.measured_traffic(20 | T, 8.0, str(p)) is None        # other launch shape
-    assert bench.measured_traffic(20, 16.0, str(p)) is None            # one-step variant
+    assert bench.measured_traffic(20, 16.0, str(p)) is None            # one-step variant (no row)
+    p.write_text(text + "\n| 20 (one step) | CG_FUSE+GATHER | 10 | 30.0 | 20.0 |")
+    assert bench.measured_traffic(20, 16.0, str(p)) == (2 * 30 + 20) * 1024
+    p.write_text(text)
     assert bench.measured_traffic(130 | T, 16.0, str(p)) is None       # not measured
     p.write_text(text.replace(h, "0" * 16))
     assert bench.measured_traffic(20 | T, 16.0, str(p)) is None        # kernels changed
@@ -58,13 +61,23 @@ def test_committed_summary_parses():
 
 
 def test_dense_bytes_per_cell_of_batching_variants():
-    """Dense-stream bytes per physical cell and step of the batching run's
-    variants, whatever the steps-per-launch bit: CORR|INJ (the adjoint with the
-    correlation) 12, SRC_POINT|STORE (the checkpointing forward) 4, and the
-    fused-residual adjoint 12."""
+    """Dense-stream bytes per physical cell and step, whatever the
+    steps-per-launch bit: CORR|INJ (the adjoint with the correlation) reads the
+    stored segment, 4; SRC_POINT|STORE (the recompute) writes it, 4; the
+    fused-residual adjoint 12.  The gradient image a correlation adds into is
+    an accumulator, not a stream of the method: PENALTY adds nothing to its
+    dense source's 4."""
     T = bench.TWO_STEP
-    assert bench.bench_dense_bytes(520 | T) == bench.bench_dense_bytes(520) == 12
+    assert bench.bench_dense_bytes(520 | T) == bench.bench_dense_bytes(520) == 4
     assert bench.bench_dense_bytes(257) == 4
     assert bench.bench_dense_bytes(72 | bench.RUPD) == 12
+    assert bench.bench_dense_bytes(2 | 128) == 4
     # a launch's algorithmic bytes split into the padded and the dense parts
-    assert bench.bytes_per_shot_launch(520 | T, 1000, 800) == 2 * (16 * 1000 + 12 * 800)
+    assert bench.bytes_per_shot_launch(520 | T, 1000, 800) == 2 * (16 * 1000 + 4 * 800)
+
+
+def test_roofline_object():
+    r = bench.roofline("k", 8e9, 1000.0, 6e9, 5000.0)
+    assert r["achieved"] == 8000.0 and r["frac"] == 1.0 and r["hbm_frac_counted"] == 0.75
+    assert r["peak_measured"] == 5000.0 and r["frac_of_measured"] == 1.6
+    assert bench.roofline("k", 8e9, 1000.0, None, None)["hbm_frac_counted"] is None

@@ -61,6 +61,25 @@ def test_fpcg_identity_matches_oracle(esi):
         assert _rel(x.cpu().numpy()[s], xc.cpu().numpy()[s]) < 1e-5
 
 
+def test_precond_scale_matches_oracle(esi):
+    """The library's analytic cell scale 1 / (beta B^2 + 0.03) against the
+    oracle's annihilator, rounded once to float32; identity-weight plans are
+    refused."""
+    cfg, g, m0, d, plan, flat = _setup(esi)
+    S = plan.precond_scale(0.03).cpu().numpy()
+    for s in range(cfg.nshots):
+        ref = 1.0 / (cfg.beta * core.annihilator_sq(g, cfg.src[s]) + 0.03)
+        np.testing.assert_allclose(S[s], ref, rtol=1.2e-7, atol=0)
+    S1 = plan.precond_scale(0.5, shot0=1, nshots=1).cpu().numpy()
+    np.testing.assert_allclose(S1[0], 1.0 / (cfg.beta * core.annihilator_sq(g, cfg.src[1]) + 0.5), rtol=1.2e-7)
+    with pytest.raises(esi.EsiError):
+        plan.precond_scale(0.0)
+    plan.set_weight(esi.WEIGHT_IDENTITY)
+    with pytest.raises(esi.EsiError):
+        plan.precond_scale(0.03)
+    plan.close()
+
+
 def test_fpcg_fixed_scale_matches_oracle(esi):
     """z = s r with s = 1 / (beta B^2 + gamma): the GPU iterates follow the
     oracle's FCG(1) with the same float32 scale, and the scaling reaches a
@@ -141,8 +160,7 @@ def test_fpcg_with_network(esi):
     theta = inputs.he_init(ounet.fan_segments(), 3)
     theta[:] *= 0.3
     net.set_params(torch.from_numpy(theta).to(DEV))
-    S0 = torch.from_numpy(np.stack([(1.0 / (cfg.beta * core.annihilator_sq(g, cfg.src[s]) + 0.03))
-                                    .astype(np.float32) for s in range(2)])).to(DEV)
+    S0 = plan.precond_scale(0.03)
     x, rep = plan.fpcg_solve(flat, max_iter=40, rtol=0.05, net=net, scale=S0)
     print("network FCG iterations", rep["shot_iters"], "fallback", rep["fallback"])
     assert np.all(np.isfinite(x.cpu().numpy()))

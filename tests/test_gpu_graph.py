@@ -104,18 +104,29 @@ def test_cg_graph_small_config_timing(esi):
 
 
 def test_autotune_choice_and_results(esi):
-    """The autotuner picks one or two steps per launch for each direction on
-    the plan's shapes and caches it; CG results agree with the untuned ones
-    to rounding (only the p.Np partials are summed over another tiling), and
-    propagations are bitwise the same."""
+    """The autotuner times the four launch shapes for each direction on the
+    plan's shapes, reports the table and caches the choice; CG results agree
+    with the untuned ones to rounding (only the p.Np partials are summed over
+    another tiling), and propagations are bitwise the same."""
     cfg = _ragged_cfg(nt=40)
     d = _d_obs(cfg)
     plan = _plan(esi, cfg)
     x0, _ = plan.cg_solve(d, max_iter=4)
     x0 = x0.clone()
     ch = plan.autotune()
-    assert ch[0] in (1, 2) and ch[1] in (1, 2)
+    assert ch[0] in (1, 2, 3, 4) and ch[1] in (1, 2, 3, 4)
+    table = plan.tune_table()
+    assert [r[0] for r in table] == [1, 2, 3, 4] or [r[0] for r in table] == [1, 3, 2, 4]
+    assert all(r[1] > 0 and r[2] > 0 for r in table)
+    best_f = min(table, key=lambda r: r[1])[0]
+    best_a = min(table, key=lambda r: r[2])[0]
+    assert ch == (best_f, best_a)
     assert plan.autotune() == ch                     # cached
+    assert plan.tune_table() == table
+    # the propagation-only timing run: its own cache entry
+    chp = plan.autotune(probe=True)
+    assert chp[0] in (1, 2, 3, 4) and chp[1] in (1, 2, 3, 4) and len(plan.tune_table()) == 4
+    plan.set_launch_shape(*ch)
     x1, _ = plan.cg_solve(d, max_iter=4)
     assert float(torch.linalg.norm(x1 - x0) / torch.linalg.norm(x0)) < 1e-6
     w = torch.from_numpy(np.tile(cfg.wavelet, (cfg.nshots, 1))).to(DEV)

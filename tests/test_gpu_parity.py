@@ -293,24 +293,28 @@ def test_single_step_and_errors(esi):
 
 
 def test_time_block_bitwise(esi):
-    """Two steps per launch give the same bits as one step per launch for
-    modelling, adjoint modelling, N p and the gradients (odd nt: the last step
-    of each pass runs alone)."""
+    """Every launch shape (one step per launch; two steps per launch on tiles
+    of 32, 24 and 40 rows) gives the same bits for modelling, adjoint
+    modelling, N p and the gradients (odd nt: the last step of each pass runs
+    alone)."""
     cfg = _ragged_cfg(nt=41)
     q = torch.from_numpy(inputs.random_field((cfg.nshots, cfg.nt, cfg.nz, cfg.nx), 11)).to(DEV)
     w = torch.from_numpy(np.stack([cfg.wavelet] * cfg.nshots).astype(np.float32)).to(DEV)
     outs = []
-    for tb in (1, 2):
+    for shape in (1, 2, 3, 4):
         plan = _plan(esi, cfg)
-        plan.set_time_block(tb)
+        plan.set_launch_shape(shape, shape)
         dd = torch.from_numpy(inputs.random_field(plan.data_shape(), 12)).to(DEV)
         r = [plan.forward(w, esi.SRC_POINT), plan.forward(q, esi.SRC_DENSE), plan.adjoint(dd),
              plan.normal_apply(q)[0], plan.gradient(esi.GRAD_PENALTY, q),
              plan.gradient(esi.GRAD_ADJOINT, q, dd), plan.gradient(esi.GRAD_ADJOINT, q, dd, ckpt_every=5)]
+        r.append(plan.forward_ckpt(w, 7))
+        r.append(plan.gradient(esi.GRAD_SEED_REUSE, w, dd, kind=esi.SRC_POINT, ckpt_every=7))
         outs.append([t.cpu().numpy() for t in r])
         plan.close()
-    for a, b in zip(*outs):
-        assert np.array_equal(a, b)
+    for other in outs[1:]:
+        for i, (a, b) in enumerate(zip(outs[0], other)):
+            assert np.array_equal(a, b), i
 
 
 def test_time_block_cg(esi):
