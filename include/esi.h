@@ -39,7 +39,8 @@
  * plan's device, owned by the caller, float32 and contiguous unless stated.
  * The plan owns only what it derives (coefficients, wavefield rings, data
  * and reduction scratch, per-tile injection lists); it grows that scratch on
- * demand with hipMalloc and frees it in esi_plan_destroy.  All work is
+ * demand with hipMalloc and frees it in esi_plan_destroy (esi_forward_noalloc
+ * is the one call that never allocates).  All work is
  * queued on the stream given at plan creation; calls return once the work is
  * queued, except esi_cg_solve, which waits for each iteration's residual norms
  * to decide convergence.
@@ -258,6 +259,25 @@ esi_status_t esi_gradient(esi_plan_t plan, int32_t shot0, int32_t nshots, int32_
  */
 esi_status_t esi_forward_ckpt(esi_plan_t plan, int32_t shot0, int32_t nshots, int32_t src_kind,
                               const float* src, float* data, int32_t ckpt_every);
+
+/*
+ * Forward modelling as esi_forward that allocates no device memory, for
+ * callers that cannot call hipMalloc: work under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation.  Same arguments, results
+ * (bit for bit) and errors as esi_forward.
+ *   The wavefield ring of the call (4 padded fields per shot) lives in a
+ *   fixed device array of the library, 64 MiB per GPU, held until the
+ *   process ends; nshots * 4 * (padded storage field) * 4 bytes beyond that
+ *   -> ESI_ERR_SHAPE (call with fewer shots).  The array is cleared by each
+ *   call before use.
+ *   Every call on one GPU uses that GPU's one array: calls that overlap in
+ *   time on the same GPU (two streams, two threads, two plans) race and give
+ *   wrong results; serialise them.
+ *   The plan must come from esi_plan_create (which builds the tile lists this
+ *   call needs and looks up the array's address on the device).
+ */
+esi_status_t esi_forward_noalloc(esi_plan_t plan, int32_t shot0, int32_t nshots, int32_t src_kind,
+                                 const float* src, float* data);
 
 /*
  * Penalty weight of the plan (Sec. 2.2-2.3, Table compare):

@@ -201,6 +201,10 @@ esi_status_t grow_t(T** p, int64_t* cap_elems, int64_t need_elems, hipStream_t s
 // Lists for a tile shape (built on first use).
 esi_status_t get_lists(Plan* P, int tx, int tz, int ty, TileLists** out);
 
+// Look up the no-allocation scratch array of `device` (current) once per
+// process; called when a plan is created (noalloc.hip).
+void noalloc_init_device(int device);
+
 // ---- launch-side descriptions -----------------------------------------------
 // Everything a time step needs; passed by value to the kernels.
 struct StepArgs {

@@ -473,6 +473,15 @@ extern "C" esi_status_t esi_plan_create(esi_plan_t* plan, const esi_grid_t* g, c
     }
     esi_status_t st = set_model(P, vel, true, g->eta_max);
     if (st != ESI_OK) return cleanup(st);
+    // the tilings of the default time loops are built now, so that calls that
+    // must not allocate (esi_forward_noalloc) find them
+    {
+        TileLists* L = nullptr;
+        st = lists_for(P, &L);
+        if (st == ESI_OK) st = shape_lists(P, loop_shape(P, F_SRC_POINT | F_GATHER, false), &L);
+        if (st != ESI_OK) return cleanup(st);
+    }
+    noalloc_init_device(P->device);
     hipError_t e = hipStreamSynchronize(P->stream);
     if (e != hipSuccess) return cleanup(fail(ESI_ERR_HIP, hipGetErrorString(e)));
     *plan = (esi_plan_t)P;

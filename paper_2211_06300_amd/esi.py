@@ -106,7 +106,7 @@ EXPORTS = ["esi_plan_create", "esi_plan_set_model", "esi_plan_destroy", "esi_las
            "esi_plan_set_weight", "esi_data_residual", "esi_wri_gradient", "esi_plan_set_beta",
            "esi_invert", "esi_dtft_set_freqs", "esi_dtft_normal_apply", "esi_dtft_rhs", "esi_dtft_cg_solve",
            "esi_dtft_to_time", "esi_dtft_gradient", "esi_ds_cg_solve", "esi_plan_set_dtft_block",
-           "esi_plan_set_ds_ckpt", "esi_precond_scale", "esi_plan_tune_table",
+           "esi_plan_set_ds_ckpt", "esi_forward_noalloc", "esi_precond_scale", "esi_plan_tune_table",
            "esi_plan_set_launch_shape", "esi_cg_solve_state"]
 # time-step kernel variants (bit set of fused work), as in include/esi.h
 K_FLAGS = {1: "SRC_POINT", 2: "SRC_DENSE", 4: "CG_FUSE", 8: "INJ", 16: "GATHER", 32: "OUT",
@@ -157,6 +157,7 @@ def load_library(path: str = LIB_PATH):
     L.esi_plan_set_ds_ckpt.argtypes = [vp, i32]
     L.esi_plan_autotune.argtypes = [vp, i32, i32, vp, vp, i32, vp]
     L.esi_forward_ckpt.argtypes = [vp, i32, i32, i32, vp, vp, i32]
+    L.esi_forward_noalloc.argtypes = [vp, i32, i32, i32, vp, vp]
     L.esi_precond_scale.argtypes = [vp, i32, i32, dbl, vp]
     L.esi_plan_tune_table.argtypes = [vp, i32, vp, vp, vp, vp]
     L.esi_plan_set_launch_shape.argtypes = [vp, i32, i32]
@@ -483,6 +484,16 @@ class Plan:
             if out is None else out
         _check(self._lib.esi_precond_scale(self._h, shot0, nshots, float(gamma),
                                            _f32(out, (nshots, *self.phys_shape), "out")))
+        return out
+
+    def forward_noalloc(self, src, kind=SRC_POINT, shot0=0, nshots=None, out=None):
+        """esi_forward_noalloc: forward modelling whose wavefield ring lives in
+        the library's fixed device array (no device allocation by the call)."""
+        shot0, nshots = self._range(shot0, nshots)
+        shape = (nshots, self.nt) if kind == SRC_POINT else self.vec_shape(nshots)
+        out = self.new_data(shot0, nshots) if out is None else out
+        _check(self._lib.esi_forward_noalloc(self._h, shot0, nshots, kind, _f32(src, shape, "src"),
+                                             _f32(out, self.data_shape(shot0, nshots), "data")))
         return out
 
     def forward_ckpt(self, src, ckpt_every, kind=SRC_POINT, shot0=0, nshots=None, out=None):
