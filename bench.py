@@ -115,12 +115,13 @@ def copy_bandwidth(torch, dev, mib: int = 2048, reps: int = 10) -> float:
     return 2 * mib * 1048576 / (ms * 1e-3) / 1e9
 
 
-def tune_report(esi, tuned, table):
+def tune_report(esi, tuned, table, names=None):
     """The autotuner's choice and candidate table (milliseconds of the timed
     forward-type and adjoint-type loops per launch shape)."""
-    return {"forward": esi.LAUNCH_NAMES.get(tuned[0], str(tuned[0])),
-            "adjoint": esi.LAUNCH_NAMES.get(tuned[1], str(tuned[1])), "chosen_by": "autotuner",
-            "candidates_ms": {esi.LAUNCH_NAMES.get(sh, str(sh)): {"forward": round(f, 3), "adjoint": round(a, 3)}
+    names = esi.LAUNCH_NAMES if names is None else names
+    return {"forward": names.get(tuned[0], str(tuned[0])), "adjoint": names.get(tuned[1], str(tuned[1])),
+            "chosen_by": "autotuner",
+            "candidates_ms": {names.get(sh, str(sh)): {"forward": round(f, 3), "adjoint": round(a, 3)}
                               for sh, f, a in table}}
 
 
@@ -530,6 +531,10 @@ def diff3d_run(args, torch, dev, peak_measured=None):
     seed = plan.forward(w, esi.SRC_POINT)                           # adjoint seed of the data's shape
     grad = torch.zeros(plan.phys_shape, dtype=torch.float32, device=dev)
     K = 50
+    # launch shape (one or two steps per launch): propagation-only timing run
+    tuned = plan.autotune(probe=True)
+    table = plan.tune_table()
+    log(f"3D autotuner: forward {esi.LAUNCH_NAMES_3D[tuned[0]]}, adjoint {esi.LAUNCH_NAMES_3D[tuned[1]]}")
 
     def one():
         grad.zero_()
@@ -557,6 +562,7 @@ def diff3d_run(args, torch, dev, peak_measured=None):
     kern = ("k_step3d_t2" if two else "k_step3d") + f"<{name}>"
     return {"workload": f"diff3d-{cfg.nx}x{cfg.ny}x{cfg.nz}-{cfg.nshots}shots", "nt": cfg.nt,
             "checkpoint_every": K, "propagations": 3, "seconds": round(wall, 3),
+            "launch_shape": tune_report(esi, tuned, table, esi.LAUNCH_NAMES_3D),
             "gpts_per_s": round(3 * cfg.nshots * npad * cfg.nt / wall / 1e9, 1),
             "dominant_loop": {"variant": name, "launches": rec["launches"], "ms": round(rec["ms"], 1)},
             "roofline": roofline(kern, alg, per_us, traffic, peak_measured),

@@ -340,10 +340,11 @@ class CGResult:
     alphas: list
     betas: list
     residuals: list | None = None   # r_0, r_1, ... when asked for
+    iterates: list | None = None    # x_1, x_2, ... when asked for
 
 
 def cg(apply_N, b: np.ndarray, max_iter: int, rtol: float = 0.0,
-       keep_residuals: bool = False) -> CGResult:
+       keep_residuals: bool = False, keep_iterates: bool = False) -> CGResult:
     """Algorithm 1 (conjugate gradient for N x = b, N symmetric), step by step.
 
     x_0 = 0, r_0 = b, p_0 = r_0; for k = 0..K-1: alpha = r.r / p.Np,
@@ -357,6 +358,7 @@ def cg(apply_N, b: np.ndarray, max_iter: int, rtol: float = 0.0,
     r0 = np.sqrt(rr)
     hist, alphas, betas = [1.0], [], []
     res = [r.copy()] if keep_residuals else None
+    its = [] if keep_iterates else None
     k = 0
     for k in range(max_iter):
         Ap = apply_N(p)
@@ -367,6 +369,8 @@ def cg(apply_N, b: np.ndarray, max_iter: int, rtol: float = 0.0,
         alphas.append(alpha)
         if keep_residuals:
             res.append(r.copy())
+        if keep_iterates:
+            its.append(x.copy())
         hist.append(np.sqrt(rr_new) / r0 if r0 > 0 else 0.0)
         if np.sqrt(rr_new) < rtol * r0 or k == max_iter - 1:
             break
@@ -374,7 +378,7 @@ def cg(apply_N, b: np.ndarray, max_iter: int, rtol: float = 0.0,
         betas.append(beta)
         p = r + beta * p
         rr = rr_new
-    return CGResult(x, k + 1, hist, alphas, betas, res)
+    return CGResult(x, k + 1, hist, alphas, betas, res, its)
 
 
 @dataclass
@@ -458,11 +462,11 @@ def fpcg(apply_N, b: np.ndarray, precond, max_iter: int, rtol: float = 0.0,
 
 
 def esi_cg(m: Model, src_pos, rec, d_obs, beta: float, max_iter: int, rtol: float = 0.0,
-           eps: float = 1.0) -> CGResult:
+           eps: float = 1.0, keep_iterates: bool = False) -> CGResult:
     """Solve (S^T S + beta B^T B) q = S^T d (eq. (normalewi)) for one shot by CG."""
     w2 = annihilator_sq(m.g, src_pos, eps)
     b = adjoint(m, rec, d_obs)
-    return cg(lambda p: normal_apply(m, rec, w2, beta, p), b, max_iter, rtol)
+    return cg(lambda p: normal_apply(m, rec, w2, beta, p), b, max_iter, rtol, keep_iterates=keep_iterates)
 
 
 # ---------------------------------------------------------------------------

@@ -24,7 +24,14 @@
 namespace esi {
 namespace {
 
-constexpr int BX = 56, BY = 24, BZ = 64;                 // output block and z chunk
+#ifndef ESI3_BZ
+#define ESI3_BZ 64
+#endif
+#ifndef ESI3_PF
+#define ESI3_PF 1
+#endif
+constexpr int BX = 56, BY = 24, BZ = ESI3_BZ;            // output block and z chunk
+constexpr int PF = ESI3_PF;                              // planes of state loads in flight ahead
 constexpr int RX = BX + 2 * HALO, RY = BY + 2 * HALO;    // first-step region: 64 x 32
 constexpr int NW = 16, NTH = 64 * NW;                    // 16 waves of 64 lanes
 constexpr int RPT = RY / NW;                             // region rows per thread: 2
@@ -256,20 +263,22 @@ __global__ __launch_bounds__(NTH) void k_step3d_t2(const StepArgs a) {
         wn[r][2 * HALO] = 0.f;
     }
     const int nit = min(BZ, a.nzp - zc0) + 2 * HALO;
-    // the next iteration's loads: u^n at z1 + 4, c and d^n at z1, halo u^n at z1
-    float nw[RPT], nc[RPT], nd[RPT], nh;
-    {
-        const int z1 = zc0 - HALO;
+    // state loads of the next PF iterations' planes z1: u^n at z1 + 4, c and
+    // d^n at z1, the halo cell's u^n at z1 (set 0 is the next to be used)
+    float nw[PF][RPT], nc[PF][RPT], nd[PF][RPT], nh[PF];
+    auto load_plane = [&](int z1, float* w4, float* cc, float* dd, float& hh) {
         const bool zin = z1 >= 0 && z1 < a.nzp;
         const bool zin4 = z1 + HALO >= 0 && z1 + HALO < a.nzp;
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            nw[r] = (cin[r] && zin4) ? at(cur, (uint32_t)(z1 + HALO + GH) * PS + col[r]) : 0.f;
-            nc[r] = (cin[r] && zin) ? at(a.c2, (uint32_t)(z1 + GH) * PS + col[r]) : 0.f;
-            nd[r] = (cin[r] && zin) ? at(din, (uint32_t)(z1 + GH) * PS + col[r]) : 0.f;
+            w4[r] = (cin[r] && zin4) ? at(cur, (uint32_t)(z1 + HALO + GH) * PS + col[r]) : 0.f;
+            cc[r] = (cin[r] && zin) ? at(a.c2, (uint32_t)(z1 + GH) * PS + col[r]) : 0.f;
+            dd[r] = (cin[r] && zin) ? at(din, (uint32_t)(z1 + GH) * PS + col[r]) : 0.f;
         }
-        nh = (zin && ho != ~0u) ? at(cur, (uint32_t)(z1 + GH) * PS + ho) : 0.f;
-    }
+        hh = (zin && ho != ~0u) ? at(cur, (uint32_t)(z1 + GH) * PS + ho) : 0.f;
+    };
+#pragma unroll
+    for (int k = 0; k < PF; ++k) load_plane(zc0 - HALO + k, nw[k], nc[k], nd[k], nh[k]);
 
     double acc = 0.0;
     for (int i = 0; i < nit; ++i) {
@@ -283,13 +292,13 @@ __global__ __launch_bounds__(NTH) void k_step3d_t2(const StepArgs a) {
         float c1[RPT], d1v[RPT];
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            wn[r][2 * HALO] = nw[r];
+            wn[r][2 * HALO] = nw[0][r];
             Ab[(ry[r] + HALO) * AW + lane + HALO] = wn[r][HALO];
             Bb[ry[r] * RX + lane] = w1[r][HALO + 1];          // u^{n+1} at z2
-            c1[r] = nc[r];
-            d1v[r] = nd[r];
+            c1[r] = nc[0][r];
+            d1v[r] = nd[0][r];
         }
-        if (hl >= 0) Ab[hl] = nh;
+        if (hl >= 0) Ab[hl] = nh[0];
         // ---- this iteration's dense loads and the next iteration's state loads
         const int iz1 = z1 - a.nb, iz2 = z2 - a.nb;
         const bool z1ph = iz1 >= 0 && iz1 < a.nz, z2ph = iz2 >= 0 && iz2 < a.nz;
@@ -343,18 +352,18 @@ __global__ __launch_bounds__(NTH) void k_step3d_t2(const StepArgs a) {
                 }
             }
         }
-        if (i + 1 < nit) {   // uniform over the workgroup
-            const int zn = z1 + 1;
-            const bool zin = zn >= 0 && zn < a.nzp;
-            const bool zin4 = zn + HALO >= 0 && zn + HALO < a.nzp;
+#pragma unroll
+        for (int k = 0; k + 1 < PF; ++k) {
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
-                nw[r] = (cin[r] && zin4) ? at(cur, (uint32_t)(zn + HALO + GH) * PS + col[r]) : 0.f;
-                nc[r] = (cin[r] && zin) ? at(a.c2, (uint32_t)(zn + GH) * PS + col[r]) : 0.f;
-                nd[r] = (cin[r] && zin) ? at(din, (uint32_t)(zn + GH) * PS + col[r]) : 0.f;
+                nw[k][r] = nw[k + 1][r];
+                nc[k][r] = nc[k + 1][r];
+                nd[k][r] = nd[k + 1][r];
             }
-            nh = (zin && ho != ~0u) ? at(cur, (uint32_t)(zn + GH) * PS + ho) : 0.f;
+            nh[k] = nh[k + 1];
         }
+        if (i + PF < nit)   // uniform over the workgroup
+            load_plane(z1 + PF, nw[PF - 1], nc[PF - 1], nd[PF - 1], nh[PF - 1]);
         // ---- injection planes of this iteration (entries sorted by cell, i.e. by plane)
         bool injA = false, injB = false;
         if constexpr ((FL & F_INJ) != 0) {

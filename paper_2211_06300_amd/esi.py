@@ -22,6 +22,7 @@ BETA_FIXED, BETA_DISCREPANCY = 0, 1
 LAUNCH_ONE_STEP, LAUNCH_TWO_STEP_32, LAUNCH_TWO_STEP_24, LAUNCH_TWO_STEP_40 = 1, 2, 3, 4
 LAUNCH_NAMES = {1: "1 step, 64x32 tiles", 2: "2 steps, 56x32 tiles", 3: "2 steps, 56x24 tiles",
                 4: "2 steps, 56x40 tiles"}
+LAUNCH_NAMES_3D = {1: "1 step, 64x16 columns, 32-plane chunks", 2: "2 steps, 56x24 columns, 64-plane chunks"}
 INNER_CG, INNER_FCG_SCALE, INNER_DATASPACE = 0, 1, 2
 _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_SHAPE", 3: "ERR_CFL", 4: "ERR_OOM", 5: "ERR_HIP",
            6: "ERR_BREAKDOWN", 7: "ERR_NONFINITE"}

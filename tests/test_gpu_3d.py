@@ -299,3 +299,75 @@ def test_autograd_fd_3d(esi):
     fd = (L_gpu(v0 + dv) - L_gpu(v0 - dv)) / 2.0
     an = float((vel.grad.double() * dv.double()).sum())
     assert abs(fd - an) / abs(fd) < 1e-2, (fd, an)
+
+
+def _cfg3_deep(nt=33, seed=37):
+    """70 x 27 in x and y, 75 planes deep with a 6-cell layer: 87 padded planes,
+    two z chunks of the two-step kernel (64 + 23 planes) and ragged 56 x 24
+    column blocks; receivers on several planes, one on the chunk boundary
+    (physical plane 58 = padded 64), shared cells and grid corners."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = 75, 27, 70
+    v = (1900.0 + 800.0 * rng.random((nz, ny, nx))).astype(np.float32)
+    src = np.array([[5, 3, 4], [60, 57, 20]], dtype=np.int32)             # (ix, iz, iy)
+    recs = [np.array([[0, 0, 0], [69, 74, 26], [30, 2, 13], [30, 2, 13], [31, 58, 13],
+                      [10, 58, 25], [65, 63, 1], [40, 57, 12]]),
+            np.stack([rng.integers(0, nx, 40), rng.integers(0, nz, 40), rng.integers(0, ny, 40)], axis=1)]
+    ptr = np.zeros(3, dtype=np.int64)
+    ptr[1:] = np.cumsum([len(r) for r in recs])
+    w = inputs.ricker_samples(nt, 1e-3, 25.0)
+    return inputs.Config("test3d-deep", 3, nz, nx, ny, 10.0, 1e-3, nt, 6, 25.0, 0.05, 0, v, v, src,
+                         ptr, np.concatenate(recs).astype(np.int32), w)
+
+
+def test_3d_two_step_bitwise(esi):
+    """Two time steps per launch (56 x 24 column blocks, 64-plane chunks, the
+    first step on the block grown by one stencil radius) give the same bits as
+    one step per launch for modelling, adjoint modelling, N p, the source
+    gradient records and the checkpointed gradients (odd nt: the last step of
+    each pass runs alone); CG agrees to rounding (p.Np partials are summed over
+    another tiling)."""
+    for cfg in (_cfg3_deep(), _cfg3(nt=41)):
+        q = torch.from_numpy(inputs.random_field((cfg.nshots, cfg.nt, *cfg.phys_shape), 51)).to(DEV)
+        w = torch.from_numpy(np.stack([cfg.wavelet, -0.6 * cfg.wavelet]).astype(np.float32)).to(DEV)
+        outs, xs = [], []
+        for shape in (1, 2):
+            plan = _plan(esi, cfg)
+            plan.set_launch_shape(shape, shape)
+            dd = torch.from_numpy(inputs.random_field(plan.data_shape(), 52)).to(DEV)
+            gsrc = torch.zeros((cfg.nshots, cfg.nt), device=DEV)
+            gq = torch.zeros_like(q)
+            r = [plan.forward(w, esi.SRC_POINT), plan.forward(q, esi.SRC_DENSE), plan.adjoint(dd),
+                 *plan.normal_apply(q),
+                 plan.gradient(esi.GRAD_ADJOINT, q, dd, ckpt_every=5),
+                 plan.gradient(esi.GRAD_ADJOINT, q, dd, ckpt_every=0),
+                 plan.gradient(esi.GRAD_SEED, w, dd, kind=esi.SRC_POINT, grad_src=gsrc, ckpt_every=6), gsrc,
+                 plan.gradient(esi.GRAD_SEED, q, dd, kind=esi.SRC_DENSE, grad_src=gq, ckpt_every=7), gq,
+                 plan.forward_ckpt(w, 8),
+                 plan.gradient(esi.GRAD_SEED_REUSE, w, dd, kind=esi.SRC_POINT, ckpt_every=8)]
+            outs.append([t.cpu().numpy() for t in r])
+            xs.append(plan.cg_solve(dd, max_iter=3)[0].cpu().numpy())
+            plan.close()
+        for i, (a, b) in enumerate(zip(*outs)):
+            if i == 4:   # p.Np (float64 partials over another tiling)
+                np.testing.assert_allclose(a, b, rtol=1e-12)
+            else:
+                assert np.array_equal(a, b), (cfg.name, i)
+        for s in range(cfg.nshots):
+            assert _rel(xs[1][s], xs[0][s]) < 1e-6
+
+
+def test_3d_deep_forward_matches_oracle(esi):
+    """The two-step 3D kernel across z chunks against the FP64 oracle."""
+    cfg = _cfg3_deep(nt=30)
+    plan = _plan(esi, cfg)
+    g, m = _model(cfg)
+    w = np.stack([cfg.wavelet, 0.8 * cfg.wavelet]).astype(np.float32)
+    d = plan.forward(torch.from_numpy(w).to(DEV), esi.SRC_POINT).cpu().numpy()
+    for s, ds in enumerate(_split(cfg, d)):
+        ref = core.forward(m, w[s].astype(np.float64), cfg.shot_rec(s), src_pos=cfg.src[s])
+        assert _rel(ds, ref) < 1e-5, s
+    dd = inputs.random_field(plan.data_shape(), 53)
+    out = plan.adjoint(torch.from_numpy(dd).to(DEV)).cpu().numpy()
+    for s, ds in enumerate(_split(cfg, dd)):
+        assert _rel(out[s], core.adjoint(m, cfg.shot_rec(s), ds.astype(np.float64))) < 1e-5, s
