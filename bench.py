@@ -47,6 +47,16 @@ DENSE_BYTES = {2: 4, 4: 20, 32: 4, 64: 8, 128: 0, 256: 4, 512: 4}
 
 TWO_STEP = 1 << 15
 RUPD = 1 << 14
+VARIANT_MASK = (1 << 15) - 1
+TILE_2D = {2: "56x32", 3: "56x24", 4: "56x40"}
+
+
+def launch_label(flags: int, ndim: int = 2) -> str:
+    """Counter-summary label of a profiled loop's launches: '1step', the 2D
+    two-step tile ('56x32', '56x24', '56x40') or '2step' (3D)."""
+    if not flags & TWO_STEP:
+        return "1step"
+    return TILE_2D.get((flags >> 16) & 7, "56x32") if ndim == 2 else "2step"
 
 # HBM counter summaries of the time-step kernels (two rocprofv3 --pmc passes,
 # FETCH_SIZE and WRITE_SIZE, calibrated on a copy of known size), one per
@@ -55,7 +65,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step2d_t2_single-solve-801x401_
 TRAFFIC_FILE_BATCHING = os.path.join(ROOT, "profiles", "k_step2d_t2_batching-1601x601-128shots_traffic.md")
 TRAFFIC_FILE_3D = os.path.join(ROOT, "profiles", "k_step3d_diff3d-256x256x256-8shots_traffic.md")
 KERNEL_SOURCES = ["paper_2211_06300_amd/csrc/step2d.hip", "paper_2211_06300_amd/csrc/esi_internal.h"]
-KERNEL_SOURCES_3D = ["paper_2211_06300_amd/csrc/step3d.hip", "paper_2211_06300_amd/csrc/esi_internal.h"]
+KERNEL_SOURCES_3D = ["paper_2211_06300_amd/csrc/step3d.hip", "paper_2211_06300_amd/csrc/step3d_t2.hip",
+                     "paper_2211_06300_amd/csrc/esi_internal.h"]
 
 
 def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
@@ -68,11 +79,11 @@ def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
 
 
 def measured_traffic(flags: int, shots_per_launch: float, path: str = TRAFFIC_FILE,
-                     sources=KERNEL_SOURCES, two_step: bool | None = None):
-    """HBM bytes per launch of the step variant `flags` from a committed counter
-    summary, or None when the kernel sources changed since the counters were
-    taken or the launch shape differs.  Rows name the variant's flag number
-    (without the two-step bit); a row "N (one step)" is the one-step launch."""
+                     sources=KERNEL_SOURCES, ndim: int = 2):
+    """HBM bytes per launch of the profiled loop `flags` from a committed
+    counter summary, or None when the kernel sources changed since the counters
+    were taken or the launch shape differs.  Rows name the variant's flag
+    number and its launch label ("16404 56x32", "520 1step", "520 2step")."""
     try:
         with open(path) as fh:
             text = fh.read()
@@ -87,8 +98,7 @@ def measured_traffic(flags: int, shots_per_launch: float, path: str = TRAFFIC_FI
         return None
     if float(meta["shots-per-launch:"][0]) != shots_per_launch:
         return None
-    two = bool(flags & TWO_STEP) if two_step is None else two_step
-    key = str(flags & ~TWO_STEP) + ("" if two else " (one step)")
+    key = f"{flags & VARIANT_MASK} {launch_label(flags, ndim)}"
     cf, cw = float(meta["calibration:"][1]), float(meta["calibration:"][3])
     for line in text.splitlines():
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
@@ -156,7 +166,7 @@ def bytes_per_shot_launch(flags: int, npad: int, nphys: int) -> int:
 
 def bench_dense_bytes(flags: int) -> int:
     """Algorithmic dense-stream bytes per physical cell of one step of a variant."""
-    return bytes_per_shot_launch(flags & ~TWO_STEP, 0, 1)
+    return bytes_per_shot_launch(flags & VARIANT_MASK & ~TWO_STEP, 0, 1)
 
 
 def cpu_baseline(cfg, nt_sample: int, iters: int = 3):
@@ -209,19 +219,46 @@ def unet_flops(H: int, W: int) -> int:
 
 def solver_comparison(args, torch, dev):
     """Plain CG vs flexible CG (analytic scale, learned correction) to a
-    relative residual of 1e-3 on a held-out model, and the network's forward
+    relative residual of 1e-3 on held-out models, and the network's forward
     throughput on the MFMA units."""
     from paper_2211_06300_amd import esi, inputs, precond
     wpath = os.path.join(ROOT, "paper_2211_06300_amd", "weights", "precond_unet.npy")
     theta = torch.from_numpy(np.load(wpath)).to(dev)
-    cfg = inputs.cfg_precond(args.solve_seed, nx=801, nz=401, nshots=args.solve_shots, nt=args.nt)
-    log(f"solver comparison on {cfg.name}: {cfg.nshots} shots, nt {cfg.nt}, to 1e-3")
-    res = precond.compare_solvers(cfg, theta, rtol=1e-3, max_iter=args.solve_iters, log=log)
-    # network forward throughput (batch = shots, 408 x 808 images)
-    H, W = precond.pad8(cfg.nz), precond.pad8(cfg.nx)
-    net = esi.Unet(H, W, cfg.nshots, device=dev)
+    seeds = [int(x) for x in args.solve_seeds.split(",")]
+    out = {"models": {}, "shots_per_model": args.solve_shots, "nt": args.nt, "rtol": 1e-3,
+           "max_iter": args.solve_iters, "plain_max_iter": args.plain_iters, "net_every": precond.NET_EVERY}
+    ratios = []
+    for i, sd in enumerate(seeds):
+        cfg = inputs.cfg_precond(sd, nx=801, nz=401, nshots=args.solve_shots, nt=args.nt)
+        # plain CG (capped: in float32 it stalls far above 1e-3) on the first model only
+        methods = ("plain", "analytic", "learned") if i == 0 else ("analytic", "learned")
+        log(f"solver comparison on {cfg.name}: {cfg.nshots} shots, nt {cfg.nt}, to 1e-3 ({', '.join(methods)})")
+        res = precond.compare_solvers(cfg, theta, rtol=1e-3, max_iter=args.solve_iters, log=log, methods=methods,
+                                      plain_max_iter=args.plain_iters)
+        m = {}
+        for k, v in res.items():
+            m[k] = {"iterations": v["iters"], "seconds": round(v["seconds"], 3), "reached_rtol": v["converged"],
+                    "true_residual_max": round(max(v["true_residual"]), 6), "fallback": v["fallback"]}
+        an, lr = res.get("analytic"), res.get("learned")
+        if an and lr and an["converged"] and lr["converged"]:
+            m["learned_speedup_vs_analytic_wall"] = round(an["seconds"] / lr["seconds"], 3)
+            m["learned_iteration_ratio_vs_analytic"] = round(sum(lr["iters"]) / sum(an["iters"]), 3)
+            ratios.append(an["seconds"] / lr["seconds"])
+        if "plain" in res:
+            pl = res["plain"]
+            m["plain_time_to_rtol"] = (round(pl["seconds"], 3) if pl["converged"] else
+                                       f"> {pl['seconds']:.1f} s (not reached in {args.plain_iters} iterations, "
+                                       f"true residual {max(pl['true_residual']):.3g})")
+        out["models"][cfg.name] = m
+        torch.cuda.empty_cache()
+    if ratios:
+        out["learned_speedup_vs_analytic_wall"] = {"min": round(min(ratios), 3), "median": round(float(np.median(ratios)), 3),
+                                                   "max": round(max(ratios), 3), "models": len(ratios)}
+    # network forward throughput (batch = 8 images of 408 x 808)
+    H, W, nb = precond.pad8(401), precond.pad8(801), 8
+    net = esi.Unet(H, W, nb, device=dev)
     net.set_params(theta)
-    x = torch.rand((cfg.nshots, 3, H, W), dtype=torch.float32, device=dev)
+    x = torch.rand((nb, 3, H, W), dtype=torch.float32, device=dev)
     for _ in range(3):
         net.forward(x)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -233,26 +270,9 @@ def solver_comparison(args, torch, dev):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     net.close()
-    flops = unet_flops(H, W) * cfg.nshots
+    flops = unet_flops(H, W) * nb
     tfs = flops / (ms * 1e-3) / 1e12
-    out = {"workload": cfg.name, "shots": cfg.nshots, "nt": cfg.nt, "rtol": 1e-3,
-           "max_iter": args.solve_iters}
-    for k, v in res.items():
-        out[k] = {"iterations": v["iters"], "seconds": round(v["seconds"], 3),
-                  "reached_rtol": v["converged"],
-                  "true_residual_max": round(max(v["true_residual"]), 6),
-                  "fallback": v["fallback"]}
-    if "learned" in res and "plain" in res:
-        lr, pl = res["learned"], res["plain"]
-        if pl["converged"]:
-            out["learned_speedup_vs_plain_wall"] = round(pl["seconds"] / lr["seconds"], 3)
-        else:
-            # plain CG did not reach the tolerance: its time to 1e-3 is above the cap
-            out["plain_time_to_rtol"] = f"> {pl['seconds']:.1f} s (not reached in {args.solve_iters} iterations)"
-            out["learned_speedup_vs_plain_wall"] = f"> {pl['seconds'] / lr['seconds']:.2f}" if lr["converged"] else None
-        if "analytic" in res and res["analytic"]["converged"] and lr["converged"]:
-            out["learned_speedup_vs_analytic_wall"] = round(res["analytic"]["seconds"] / lr["seconds"], 3)
-    out["network_forward"] = {"images": cfg.nshots, "image": f"{W}x{H}", "ms": round(ms, 3),
+    out["network_forward"] = {"images": nb, "image": f"{W}x{H}", "ms": round(ms, 3),
                               "tflops": round(tfs, 2), "bound": "mfma", "peak_tflops": 2500.0,
                               "frac": round(tfs / 2500.0, 4), "dtype": "bf16 (fp32 accumulate)"}
     return out
@@ -274,7 +294,7 @@ def batching_run(args, torch, dev, peak_measured=None):
     # launch shapes: propagation-only timing run of every candidate over all
     # 128 shots' windows (the wavefield-sized vectors of a normal-operator run
     # would not fit)
-    tuned = plan.autotune(probe=True)
+    tuned = plan.autotune(probe=True) if not args.all_shapes else (2, 2)
     table = plan.tune_table()
     log(f"batching autotuner: forward {esi.LAUNCH_NAMES[tuned[0]]}, adjoint {esi.LAUNCH_NAMES[tuned[1]]}")
 
@@ -283,6 +303,11 @@ def batching_run(args, torch, dev, peak_measured=None):
         plan.forward_ckpt(w, 50, kind=esi.SRC_POINT)
         plan.gradient(esi.GRAD_SEED_REUSE, w, seed, kind=esi.SRC_POINT, grad_m=grad, ckpt_every=50)
 
+    if args.all_shapes:   # counter runs: one pass with every launch shape
+        for sh in (1, 3, 2, 4):
+            plan.set_launch_shape(sh, sh)
+            one()
+        plan.set_launch_shape(*tuned)
     one()
     torch.cuda.synchronize()
     plan.profile(True)
@@ -532,9 +557,16 @@ def diff3d_run(args, torch, dev, peak_measured=None):
     grad = torch.zeros(plan.phys_shape, dtype=torch.float32, device=dev)
     K = 50
     # launch shape (one or two steps per launch): propagation-only timing run
-    tuned = plan.autotune(probe=True)
+    tuned = plan.autotune(probe=True) if not args.all_shapes else (1, 1)
     table = plan.tune_table()
     log(f"3D autotuner: forward {esi.LAUNCH_NAMES_3D[tuned[0]]}, adjoint {esi.LAUNCH_NAMES_3D[tuned[1]]}")
+    if args.all_shapes:   # counter runs: one pass with every launch shape
+        for sh in (1, 2):
+            plan.set_launch_shape(sh, sh)
+            grad.zero_()
+            plan.forward_ckpt(w, K, kind=esi.SRC_POINT)
+            plan.gradient(esi.GRAD_SEED_REUSE, w, seed, kind=esi.SRC_POINT, grad_m=grad, ckpt_every=K)
+        plan.set_launch_shape(*tuned)
 
     def one():
         grad.zero_()
@@ -558,7 +590,7 @@ def diff3d_run(args, torch, dev, peak_measured=None):
     spl = rec["shot_launches"] / rec["launches"]
     alg = bytes_per_shot_launch(rec["flags"], npad, nphys) * spl
     two = bool(rec["flags"] & TWO_STEP)
-    traffic = measured_traffic(rec["flags"], spl, TRAFFIC_FILE_3D, KERNEL_SOURCES_3D)
+    traffic = measured_traffic(rec["flags"], spl, TRAFFIC_FILE_3D, KERNEL_SOURCES_3D, ndim=3)
     kern = ("k_step3d_t2" if two else "k_step3d") + f"<{name}>"
     return {"workload": f"diff3d-{cfg.nx}x{cfg.ny}x{cfg.nz}-{cfg.nshots}shots", "nt": cfg.nt,
             "checkpoint_every": K, "propagations": 3, "seconds": round(wall, 3),
@@ -613,9 +645,11 @@ def main():
     ap.add_argument("--no-rfuse", action="store_true",
                     help="CG with the residual update as a separate pass (default: fused into the adjoint)")
     ap.add_argument("--no-solve", action="store_true", help="skip the plain vs learned CG comparison")
-    ap.add_argument("--solve-seed", type=int, default=6000)
-    ap.add_argument("--solve-shots", type=int, default=8)
+    ap.add_argument("--solve-seeds", default="6000,6001,6002,6003,6004",
+                    help="held-out 801 x 401 models of the solver comparison")
+    ap.add_argument("--solve-shots", type=int, default=4)
     ap.add_argument("--solve-iters", type=int, default=500)
+    ap.add_argument("--plain-iters", type=int, default=200, help="iteration cap of plain CG in the comparison")
     ap.add_argument("--no-batching", action="store_true", help="skip the uneven-aperture batching run")
     ap.add_argument("--batch-shots", type=int, default=128)
     ap.add_argument("--batch-nt", type=int, default=4000)
@@ -634,6 +668,9 @@ def main():
     ap.add_argument("--invert-inner", choices=["fcg", "ds", "cg"], default="fcg")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="also run one elementwise copy of this many MiB (counter calibration)")
+    ap.add_argument("--all-shapes", action="store_true",
+                    help="counter runs: run the legs with every launch shape (main leg: step i with shape i % 4) "
+                         "instead of the autotuner's choice")
     ap.add_argument("--nt3d", type=int, default=1500, help="steps of the 3D differentiation leg")
     ap.add_argument("--no-diff3d", action="store_true", help="skip the 3D differentiation run")
     ap.add_argument("--only-3d", action="store_true",
@@ -660,8 +697,10 @@ def main():
     if args.only_3d:
         print(json.dumps({"forward3d": forward3d_run(args, torch, dev)}), flush=True)
         return
-    peak_measured = copy_bandwidth(torch, dev)
-    log(f"measured copy bandwidth: {peak_measured:.0f} GB/s")
+    # (a counter-calibration run keeps its copy kernel the only one of its kind)
+    peak_measured = None if args.copy_calib else copy_bandwidth(torch, dev)
+    if peak_measured:
+        log(f"measured copy bandwidth: {peak_measured:.0f} GB/s")
     legs = {"batching": lambda: batching_run(args, torch, dev, peak_measured),
             "diff3d": lambda: diff3d_run(args, torch, dev, peak_measured),
             "solve": lambda: solver_comparison(args, torch, dev),
@@ -670,7 +709,7 @@ def main():
             "dtft": lambda: dtft_run(args, torch, dev),
             "dataspace": lambda: dataspace_run(args, torch, dev)}
     if args.only:
-        res = {"peak_measured_gbs": round(peak_measured, 1)}
+        res = {"peak_measured_gbs": peak_measured and round(peak_measured, 1)}
         for leg in args.only.split(","):
             res[leg] = legs[leg]()
             torch.cuda.empty_cache()
@@ -697,7 +736,7 @@ def main():
     work = torch.empty((3, *plan.vec_shape(G)), dtype=torch.float32, device=dev)
     grad = torch.zeros(plan.phys_shape, dtype=torch.float32, device=dev)
     offs = [int(cfg.nt * cfg.rec_ptr[s]) for s in range(cfg.nshots + 1)]
-    tuned = plan.autotune(nshots=G, p=work[0], Ap=work[1])
+    tuned = plan.autotune(nshots=G, p=work[0], Ap=work[1]) if not args.all_shapes else (2, 2)
     tune_table = plan.tune_table()
     log(f"autotuned launch shapes: forward {esi.LAUNCH_NAMES[tuned[0]]}, adjoint {esi.LAUNCH_NAMES[tuned[1]]}")
     log("setup done")
@@ -728,6 +767,8 @@ def main():
     t0 = time.perf_counter()
     ev0.record(stream)
     for i in range(args.steps):
+        if args.all_shapes:   # counter runs: step i with launch shape i % 4
+            plan.set_launch_shape((1, 3, 2, 4)[i % 4], (1, 3, 2, 4)[i % 4])
         step()
         log(f"step {i} queued/done")
     ev1.record(stream)

@@ -588,8 +588,10 @@ esi_status_t esi_plan_set_cg_rfuse(esi_plan_t plan, int32_t enable);
  * loops that ran it (kernel time plus the gaps between its launches).  The
  * variant is a bit set of fused work (source kind, recording, injection,
  * outputs, CG fusion, correlation) whose meaning is given by the ESI_K_*
- * values below; ESI_K_TWO_STEP marks launches that advance two steps.
- * Turning profiling on (enable != 0) clears the counters.
+ * values below; ESI_K_TWO_STEP marks launches that advance two steps, and
+ * bits 16-18 of such a variant hold its launch shape (ESI_LAUNCH_*; 2D tile
+ * height, or the 3D two-step kernel).  Turning profiling on (enable != 0)
+ * clears the counters.
  */
 enum {
     ESI_K_SRC_POINT = 1, ESI_K_SRC_DENSE = 2, ESI_K_CG_FUSE = 4, ESI_K_INJ = 8,

@@ -160,11 +160,12 @@ struct ProfScope {
 // Forward time loop over [n0, n1) on `ring` whose state is in slot *cs.
 // Two-step launches are used where allowed; a checkpoint of (u^n, d^n) is
 // saved at every n = k*K into ckpt[s][k][2][fsize] (two-step launches never
-// straddle a checkpoint).  Profiling records two-step launches with bit 1<<15.
+// straddle a checkpoint).  Profiling records two-step launches with bit 1<<15
+// and their launch shape in bits 16-18.
 esi_status_t forward_loop(Plan* P, StepArgs a, unsigned flags, float* ring, int* cs, int n0,
                           int n1, float* ckpt, int K, int nseg) {
-    ProfScope p1(P, flags, a.nshots), p2(P, flags | (1u << 15), a.nshots);
     const int shape = loop_shape(P, flags, false);
+    ProfScope p1(P, flags, a.nshots), p2(P, flags | (1u << 15) | ((unsigned)shape << 16), a.nshots);
     TileLists* L2 = nullptr;
     if (shape != LS_ONE) ESI_TRY(shape_lists(P, shape, &L2));
     const bool t2 = L2 != nullptr;
@@ -201,8 +202,8 @@ esi_status_t forward_loop(Plan* P, StepArgs a, unsigned flags, float* ring, int*
 // Adjoint time loop over j = j1-1 .. j0 on `ring` whose state is in slot *cs.
 esi_status_t adjoint_loop(Plan* P, StepArgs a, unsigned flags, float* ring, int* cs, int j0,
                           int j1, int K) {
-    ProfScope p1(P, flags, a.nshots), p2(P, flags | (1u << 15), a.nshots);
     const int shape = loop_shape(P, flags, true);
+    ProfScope p1(P, flags, a.nshots), p2(P, flags | (1u << 15) | ((unsigned)shape << 16), a.nshots);
     TileLists* L2 = nullptr;
     if (shape != LS_ONE) ESI_TRY(shape_lists(P, shape, &L2));
     const bool t2 = L2 != nullptr;

@@ -22,6 +22,7 @@ BETA_FIXED, BETA_DISCREPANCY = 0, 1
 LAUNCH_ONE_STEP, LAUNCH_TWO_STEP_32, LAUNCH_TWO_STEP_24, LAUNCH_TWO_STEP_40 = 1, 2, 3, 4
 LAUNCH_NAMES = {1: "1 step, 64x32 tiles", 2: "2 steps, 56x32 tiles", 3: "2 steps, 56x24 tiles",
                 4: "2 steps, 56x40 tiles"}
+LAUNCH_TILES = {1: "64x32", 2: "56x32", 3: "56x24", 4: "56x40"}
 LAUNCH_NAMES_3D = {1: "1 step, 64x16 columns, 32-plane chunks", 2: "2 steps, 56x24 columns, 64-plane chunks"}
 INNER_CG, INNER_FCG_SCALE, INNER_DATASPACE = 0, 1, 2
 _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_SHAPE", 3: "ERR_CFL", 4: "ERR_OOM", 5: "ERR_HIP",
@@ -646,9 +647,12 @@ class Plan:
                                                la.ctypes.data, sl.ctypes.data, ms.ctypes.data))
         out = {}
         for i in range(min(int(cnt[0]), cap)):
-            name = "|".join(v for k, v in K_FLAGS.items() if int(fl[i]) & k)
-            out[name] = {"flags": int(fl[i]), "launches": int(la[i]), "shot_launches": int(sl[i]),
-                         "ms": float(ms[i])}
+            f = int(fl[i])
+            name = "|".join(v for k, v in K_FLAGS.items() if f & k)
+            shape = (f >> 16) & 7
+            if shape and self.ndim == 2:
+                name += "@" + LAUNCH_TILES[shape]
+            out[name] = {"flags": f, "launches": int(la[i]), "shot_launches": int(sl[i]), "ms": float(ms[i])}
         return out
 
 

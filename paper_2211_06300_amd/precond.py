@@ -212,12 +212,16 @@ def true_residual(plan, b, x):
             for s in range(b.shape[0])]
 
 
+NET_EVERY = 10
+
+
 def compare_solvers(cfg, theta=None, rtol=1e-3, max_iter=600, gamma=GAMMA0, device="cuda", log=None,
-                    methods=("plain", "analytic", "learned")):
+                    methods=("plain", "analytic", "learned"), net_every=NET_EVERY, plain_max_iter=None):
     """Plain CG, flexible CG with the analytic scale s0, and flexible CG with
-    the learned correction s0 exp(Net) ("learned": the network on every
-    iteration's residual; "learned_fixed": once, on r_0) on one model, each to
-    a relative residual `rtol`: iterations per shot, wall time, true residual."""
+    the learned correction s0 exp(Net) ("learned": the network on r_0 and then
+    on every net_every-th iteration's residual; "learned_fixed": once, on r_0)
+    on one model, each to a relative residual `rtol`: iterations per shot, wall
+    time, true residual.  plain_max_iter caps plain CG (default max_iter)."""
     d = observed_data(cfg, device)
     plan = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_start).to(device))
     ns = cfg.nshots
@@ -236,11 +240,11 @@ def compare_solvers(cfg, theta=None, rtol=1e-3, max_iter=600, gamma=GAMMA0, devi
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if m == "plain":
-            _, rep = plan.cg_solve(d, max_iter, rtol, x=x, work=work)
+            _, rep = plan.cg_solve(d, plain_max_iter or max_iter, rtol, x=x, work=work)
             rep["fallback"] = np.full(ns, -1)
         else:
             _, rep = plan.fpcg_solve(d, max_iter, rtol, net=net if m.startswith("learned") else None, scale=S0,
-                                     x=x, work=work, net_every=0 if m == "learned_fixed" else 1)
+                                     x=x, work=work, net_every=0 if m == "learned_fixed" else net_every)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         its = rep["shot_iters"]

@@ -23,7 +23,7 @@ def test_committed_summary_has_the_dominant_kernel():
     """The committed counter summary lists the fused forward and adjoint
     variants of the main leg."""
     text = open(bench.TRAFFIC_FILE).read()
-    rows = {line.split("|")[1].strip() for line in text.splitlines() if line.startswith("| ")}
+    rows = {line.split("|")[1].strip().split()[0] for line in text.splitlines() if line.startswith("| ")}
     assert {str(20 | bench.RUPD), str(72 | bench.RUPD)} <= rows
 
 
@@ -33,29 +33,37 @@ def test_measured_traffic_lookup(tmp_path):
         f"kernel-sources-sha256-16: {h}  (note)",
         "calibration: fetch 2.0 write 1.0",
         "shots-per-launch: 16",
-        "| flags | variant | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB |",
-        "|---:|---|---:|---:|---:|",
-        "| 20 | CG_FUSE+GATHER | 10 | 100.0 | 50.0 |",
-        "| 72 | INJ+NORMAL | 10 | 10.0 | 5.0 |",
+        "| launch | variant | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB |",
+        "|---|---|---:|---:|---:|",
+        "| 20 56x32 | CG_FUSE+GATHER | 10 | 100.0 | 50.0 |",
+        "| 20 56x24 | CG_FUSE+GATHER | 10 | 90.0 | 50.0 |",
+        "| 72 56x32 | INJ+NORMAL | 10 | 10.0 | 5.0 |",
+        "| 20 1step | CG_FUSE+GATHER | 10 | 30.0 | 20.0 |",
     ])
     p = tmp_path / "t.md"
     p.write_text(text)
     T = bench.TWO_STEP
-    assert bench.measured_traffic(20 | T, 16.0, str(p)) == (2 * 100 + 50) * 1024
-    assert bench.measured_traffic(72 | T, 16.0, str(p)) == (2 * 10 + 5) * 1024
-    assert bench.measured_traffic(20 | T, 8.0, str(p)) is None        # other launch shape
-    assert bench.measured_traffic(20, 16.0, str(p)) is None            # one-step variant (no row)
-    p.write_text(text + "\n| 20 (one step) | CG_FUSE+GATHER | 10 | 30.0 | 20.0 |")
-    assert bench.measured_traffic(20, 16.0, str(p)) == (2 * 30 + 20) * 1024
-    p.write_text(text)
-    assert bench.measured_traffic(130 | T, 16.0, str(p)) is None       # not measured
+    assert bench.measured_traffic(20 | T | (2 << 16), 16.0, str(p)) == (2 * 100 + 50) * 1024
+    assert bench.measured_traffic(20 | T | (3 << 16), 16.0, str(p)) == (2 * 90 + 50) * 1024
+    assert bench.measured_traffic(72 | T | (2 << 16), 16.0, str(p)) == (2 * 10 + 5) * 1024
+    assert bench.measured_traffic(20, 16.0, str(p)) == (2 * 30 + 20) * 1024              # one step
+    assert bench.measured_traffic(20 | T | (4 << 16), 16.0, str(p)) is None             # 40-row tiles not measured
+    assert bench.measured_traffic(20 | T | (2 << 16), 8.0, str(p)) is None               # other shots per launch
+    assert bench.measured_traffic(130 | T | (2 << 16), 16.0, str(p)) is None             # not measured
     p.write_text(text.replace(h, "0" * 16))
-    assert bench.measured_traffic(20 | T, 16.0, str(p)) is None        # kernels changed
+    assert bench.measured_traffic(20 | T | (2 << 16), 16.0, str(p)) is None              # kernels changed
     assert bench.measured_traffic(20 | T, 16.0, str(tmp_path / "missing.md")) is None
 
 
+def test_launch_label():
+    T = bench.TWO_STEP
+    assert bench.launch_label(520) == "1step"
+    assert bench.launch_label(520 | T | (3 << 16)) == "56x24"
+    assert bench.launch_label(520 | T | (2 << 16), ndim=3) == "2step"
+
+
 def test_committed_summary_parses():
-    v = bench.measured_traffic(20 | bench.RUPD | bench.TWO_STEP, 16.0)
+    v = bench.measured_traffic(20 | bench.RUPD | bench.TWO_STEP | (2 << 16), 16.0)
     assert v is None or v > 0
     assert os.path.exists(bench.TRAFFIC_FILE)
 

@@ -1,9 +1,13 @@
-"""What the trained preconditioner gains over the method without it: on a
-held-out model (seed 6001, 401 x 201, 2 shots, 1500 steps) flexible CG with
-the learned correction reaches a relative residual of 1e-3 (true residual
-included) within 400 iterations, and plain CG (Algorithm 1) does not reach
-it in the same budget or wall time.  The analytic scale alone is run and
-printed beside them."""
+"""What the trained preconditioner gains over the method without it, on a
+held-out model (seed 6003, 801 x 401, 2 shots, 2000 steps, not in training):
+
+* flexible CG with the learned correction (the network re-evaluated every
+  10 iterations) reaches a relative residual of 1e-3, true residual included;
+* it needs fewer iterations and less wall time than flexible CG with the
+  analytic scale alone (the method without the network), and no shot gives
+  up the network on the way;
+* plain CG (Algorithm 1) does not reach the tolerance in 400 iterations (in
+  float32 it stalls near a relative residual of 1e-2 on these systems)."""
 import json
 import os
 
@@ -31,11 +35,12 @@ def esi():
 def test_learned_preconditioner_gain(esi):
     from paper_2211_06300_amd import precond
     theta = torch.from_numpy(np.load(WEIGHTS)).to(DEV)
-    cfg = inputs.cfg_precond(6001, nshots=2)
-    out = precond.compare_solvers(cfg, theta, rtol=1e-3, max_iter=400, log=print)
+    cfg = inputs.cfg_precond(6003, nx=801, nz=401, nshots=2, nt=2000)
+    out = precond.compare_solvers(cfg, theta, rtol=1e-3, max_iter=500, plain_max_iter=400, log=print)
     print(json.dumps(out))
-    plain, lrn = out["plain"], out["learned"]
-    assert lrn["converged"] and not plain["converged"]
-    assert sum(lrn["iters"]) < sum(plain["iters"])
-    assert lrn["seconds"] < plain["seconds"]
+    plain, an, lrn = out["plain"], out["analytic"], out["learned"]
+    assert lrn["converged"] and an["converged"] and not plain["converged"]
     assert max(lrn["true_residual"]) < 1.5e-3 < min(plain["true_residual"])
+    assert sum(lrn["iters"]) < sum(an["iters"])
+    assert lrn["seconds"] < an["seconds"]
+    assert all(f == -1 for f in lrn["fallback"]), lrn["fallback"]
