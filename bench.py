@@ -100,10 +100,13 @@ def measured_traffic(flags: int, shots_per_launch: float, path: str = TRAFFIC_FI
         return None
     key = f"{flags & VARIANT_MASK} {launch_label(flags, ndim)}"
     cf, cw = float(meta["calibration:"][1]), float(meta["calibration:"][3])
+    fi = wi = None
     for line in text.splitlines():
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
-        if len(cells) >= 5 and cells[0] == key:
-            return int((cf * float(cells[3]) + cw * float(cells[4])) * 1024)
+        if "FETCH_SIZE KiB" in cells and "WRITE_SIZE KiB" in cells:   # the table's header
+            fi, wi = cells.index("FETCH_SIZE KiB"), cells.index("WRITE_SIZE KiB")
+        elif fi is not None and len(cells) > max(fi, wi) and cells[0] == key:
+            return int((cf * float(cells[fi]) + cw * float(cells[wi])) * 1024)
     return None
 
 
