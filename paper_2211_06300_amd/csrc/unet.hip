@@ -11,13 +11,15 @@
 // no copy.
 //
 // 3x3 convolutions (forward and data gradient) are implicit GEMMs on
-// v_mfma_f32_16x16x16_bf16: D[cout][pixel] = sum_{tap, ci} W[tap][cout][ci]
-// X[pixel + tap][ci].  With the operand layout of that instruction a lane
-// holds four consecutive input channels of one pixel (one 8-byte load) and
-// four consecutive output channels of one pixel (one 8-byte store).  The data
-// gradient is the same kernel with taps reversed and weights transposed.  The
-// weight gradient is a GEMM over pixels (split into fixed chunks, partials
-// summed in a fixed order).
+// v_mfma_f32_16x16x32_bf16: D[cout][pixel] = sum_{tap, ci} W[tap][cout][ci]
+// X[pixel + tap][ci], with each input tile staged in LDS once and read by all
+// nine taps, and the weights packed in the instruction's operand order.  A
+// lane stores four consecutive output channels of one pixel (8 bytes).  The
+// data gradient is the same kernel with taps reversed and weights transposed.
+// Transposed convolutions use v_mfma_f32_16x16x16_bf16 with operands loaded
+// straight from memory (each input pixel is read once).  The weight gradient
+// is a GEMM over pixels (split into fixed chunks, partials summed in a fixed
+// order).
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -30,13 +32,13 @@ namespace {
 typedef uint16_t bf16_t;
 typedef short s4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+union bf8u {   // eight bf16 values as one 16-byte load or store
+    uint4 u;
+    uint16_t h[8];
+};
 
 constexpr int NT = 256;
-#ifndef ESI_CONV_TAPG
-#define ESI_CONV_TAPG 3
-#endif
-constexpr int TG = ESI_CONV_TAPG;   // 3x3 taps whose operands are loaded together (1, 3 or 9)
-static_assert(9 % TG == 0, "tap groups must split the 9 taps");
 
 __device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float((uint32_t)h << 16); }
 // round to nearest even (finite inputs)
@@ -53,77 +55,170 @@ static uint16_t f2bf_host(float f) {
 }
 
 // ---------------------------------------------------------------------------
-// 3x3 convolution, same size, zero padding; X and Y are NHWC views with pixel
-// strides sx, sy (elements) and Cin, Cout channels (multiples of 16).
-// Workgroup: 4 waves, one output row each, 64 pixels (4 groups of 16) x
-// 16*CB output channels.  Wp is [9][Cout][Cin] bf16.
-template <int CB>
-__global__ __launch_bounds__(NT) void k_conv3(const bf16_t* __restrict__ X, int sx, int Cin,
-                                              const bf16_t* __restrict__ Wp,
-                                              const float* __restrict__ bias, bf16_t* __restrict__ Y,
-                                              int sy, int Cout, int H, int W, int relu) {
+// 3x3 convolution, same size, zero padding, as an implicit GEMM on
+// v_mfma_f32_16x16x32_bf16: D[m][pixel] = sum over (tap, k) of
+// A[tap][m][k] X[pixel + tap][k].  X and Y are NHWC views with pixel strides
+// sx, sy (elements); K input and M output channels, multiples of 16.  A view
+// may hold its channels as two planar halves: channels from xsplit on
+// (ysplit for Y) live xhs (yhs) elements further on, at channel c - xsplit.
+//
+// The contraction runs in blocks of 32: (tap, 32 channels) when K is a
+// multiple of 32 (CK = 32, nine blocks per chunk of 32 channels), else (two
+// taps, 16 channels) (CK = 16, five blocks, the tenth tap with zero weights).
+// Lane l of a block holds the 8 consecutive contraction indices of k-group
+// l / 16, for row (A) or pixel (B) l % 16; A is packed in that order by
+// k_pack_frag, so a lane's weights are one coalesced 16-byte load.
+//
+// Workgroup: 4 waves, RPW output rows each, 64 pixels (4 groups of 16) x
+// 16 CB output channels.  Per chunk of CK input channels the (4 RPW + 2) x 66
+// input tile and the chunk's weight operands are staged in LDS once; every
+// tap then reads its shifted operands from there.  (Padding the pixel stride
+// by 8 or 16 elements measured 1.5-4 % slower: the smaller tile keeps more
+// workgroups resident.)
+//
+// The grid is persistent: workgroup b takes the (tile, chunk) steps of tiles
+// b, b + gridDim.x, ...  The global loads of the next step are issued
+// before the current step's MFMAs and land in registers, so memory latency
+// overlaps the arithmetic; a tile's outputs are stored after its last chunk.
+constexpr int frag_ck(int K) { return K % 32 == 0 ? 32 : 16; }
+constexpr int frag_nkb(int ck) { return ck == 32 ? 9 : 5; }
+
+template <int CB, int RPW, int CK>
+struct Conv3Tile {
+    static constexpr int NKB = frag_nkb(CK);
+    static constexpr int TR = 4 * RPW + 2, TC = 66, PS = CK, SUB = CK / 8;
+    static constexpr int NQ = TR * TC * SUB, NL = (NQ + NT - 1) / NT;   // 16-byte pieces of a tile, per thread
+    static constexpr int NWQ = NKB * CB * 64, NWL = (NWQ + NT - 1) / NT;  // and of a chunk's weights
+};
+
+template <int CB, int RPW, int CK>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_conv3(
+    const bf16_t* __restrict__ X, int sx, int64_t xhs, int xsplit, int K, const bf16_t* __restrict__ Af, int ncb,
+    const float* __restrict__ bias, bf16_t* __restrict__ Y, int sy, int64_t yhs, int ysplit, int M, int H, int W,
+    int N, int relu) {
+    using T = Conv3Tile<CB, RPW, CK>;
+    __shared__ __align__(16) bf16_t xs[T::TR * T::TC * T::PS];
+    __shared__ __align__(16) bf16_t ws[T::NWQ * 8];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int ncog = Cout / (16 * CB);
-    const int n = blockIdx.z / ncog;
-    const int co0 = (blockIdx.z % ncog) * 16 * CB;
-    const int y = blockIdx.y * 4 + wave;
-    if (y >= H) return;
-    const int x0 = blockIdx.x * 64;
-    const int jl = lane & 15, kq = (lane >> 4) * 4;
-    f4 acc[4][CB];
+    const int jl = lane & 15, g = lane >> 4;
+    const int ncog = M / (16 * CB), nchunk = K / CK;
+    const int ntx = (W + 63) / 64, nty = (H + 4 * RPW - 1) / (4 * RPW);
+    const int ntiles = ntx * nty * N * ncog;
+    // a contiguous run of tiles per workgroup, rows fastest: the halo rows of
+    // a tile were read by the same workgroup (same XCD, same L2) one tile ago
+    const int nmine = blockIdx.x < ntiles ? (ntiles - 1 - (int)blockIdx.x) / (int)gridDim.x + 1 : 0;
+    const int nsteps = nmine * nchunk;
+
+    // step -> tile origin, image, output-channel group, chunk
+    auto decode = [&](int step, int& x0, int& y0, int& n, int& cbg, int& chunk) {
+        const int t = (int)blockIdx.x + (step / nchunk) * (int)gridDim.x;
+        chunk = step % nchunk;
+        x0 = (t % ntx) * 64;
+        y0 = ((t / ntx) % nty) * 4 * RPW;
+        const int z = t / (ntx * nty);
+        n = z / ncog;
+        cbg = z % ncog;
+    };
+    uint4 st[T::NL], sw[T::NWL];
+    auto fetch = [&](int step) {
+        int x0, y0, n, cbg, chunk;
+        decode(step, x0, y0, n, cbg, chunk);
+        const bf16_t* Xn = X + (int64_t)n * H * W * sx;
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+        for (int l = 0; l < T::NL; ++l) {
+            const int q = threadIdx.x + l * NT;
+            const int sub = q % T::SUB, px = (q / T::SUB) % T::TC, row = q / (T::SUB * T::TC);
+            const int yy = y0 - 1 + row, xx = x0 - 1 + px;
+            const int ch = chunk * CK + sub * 8;             // channels at or past xsplit: second half
+            const int64_t hoff = ch >= xsplit ? xhs - xsplit : 0;
+            st[l] = uint4{0u, 0u, 0u, 0u};
+            if (q < T::NQ && yy >= 0 && yy < H && xx >= 0 && xx < W)
+                st[l] = *reinterpret_cast<const uint4*>(Xn + ((int64_t)yy * W + xx) * sx + hoff + ch);
+        }
+        // the workgroup's weight operands of the chunk: [kb][c][lane][8]
 #pragma unroll
-        for (int c = 0; c < CB; ++c) acc[p][c] = f4{0.f, 0.f, 0.f, 0.f};
-    const bf16_t* Xn = X + (int64_t)n * H * W * sx;
-    for (int ci = 0; ci < Cin; ci += 16) {
-        // the operands of TG taps first (TG x 4 pixel groups, TG x CB weight
-        // blocks), so their loads overlap; then the MFMAs
+        for (int l = 0; l < T::NWL; ++l) {
+            const int q = threadIdx.x + l * NT;
+            const int kbc = q / 64, kb = kbc / CB, c = kbc % CB;
+            sw[l] = uint4{0u, 0u, 0u, 0u};
+            if (q < T::NWQ)
+                sw[l] = *reinterpret_cast<const uint4*>(
+                    Af + (((int64_t)chunk * T::NKB + kb) * ncb + cbg * CB + c) * 512 + (q % 64) * 8);
+        }
+    };
+
+    f4 acc[RPW][4][CB];
 #pragma unroll
-        for (int t0 = 0; t0 < 9; t0 += TG) {
-            s4 b[TG][4], a[TG][CB];
+    for (int r = 0; r < RPW; ++r)
 #pragma unroll
-            for (int g = 0; g < TG; ++g) {
-                const int tap = t0 + g;
-                const int yy = y + tap / 3 - 1;
-                const bool rowok = yy >= 0 && yy < H;
-                const int dx = tap % 3 - 1;
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int c = 0; c < CB; ++c) acc[r][p][c] = f4{0.f, 0.f, 0.f, 0.f};
+
+    if (nsteps > 0) fetch(0);
+    for (int step = 0; step < nsteps; ++step) {
+        if (step) __syncthreads();   // every wave is done reading the previous step's LDS
+#pragma unroll
+        for (int l = 0; l < T::NL; ++l) {
+            const int q = threadIdx.x + l * NT;
+            const int sub = q % T::SUB, px = (q / T::SUB) % T::TC, row = q / (T::SUB * T::TC);
+            if (q < T::NQ) *reinterpret_cast<uint4*>(xs + (row * T::TC + px) * T::PS + sub * 8) = st[l];
+        }
+#pragma unroll
+        for (int l = 0; l < T::NWL; ++l) {
+            const int q = threadIdx.x + l * NT;
+            if (q < T::NWQ) *reinterpret_cast<uint4*>(ws + q * 8) = sw[l];
+        }
+        __syncthreads();
+        if (step + 1 < nsteps) fetch(step + 1);   // lands while this step computes
+#pragma unroll
+        for (int kb = 0; kb < T::NKB; ++kb) {
+            const int tap = CK == 32 ? kb : min(2 * kb + (g >> 1), 8);
+            const int koff = CK == 32 ? 8 * g : 8 * (g & 1);
+            const int dy = tap / 3, dx = tap % 3;
+            bf16x8 a[CB];
+#pragma unroll
+            for (int c = 0; c < CB; ++c)
+                a[c] = *reinterpret_cast<const bf16x8*>(ws + ((kb * CB + c) * 64 + lane) * 8);
+#pragma unroll
+            for (int r = 0; r < RPW; ++r)
 #pragma unroll
                 for (int p = 0; p < 4; ++p) {
-                    const int xx = x0 + p * 16 + jl + dx;
-                    b[g][p] = (rowok && xx >= 0 && xx < W)
-                                  ? *reinterpret_cast<const s4*>(Xn + ((int64_t)yy * W + xx) * sx + ci + kq)
-                                  : s4{0, 0, 0, 0};
-                }
-#pragma unroll
-                for (int c = 0; c < CB; ++c)
-                    a[g][c] = *reinterpret_cast<const s4*>(Wp + ((int64_t)tap * Cout + co0 + c * 16 + jl) * Cin + ci + kq);
-            }
-#pragma unroll
-            for (int g = 0; g < TG; ++g)
-#pragma unroll
-                for (int p = 0; p < 4; ++p)
+                    const bf16x8 b = *reinterpret_cast<const bf16x8*>(
+                        xs + ((wave * RPW + r + dy) * T::TC + p * 16 + jl + dx) * T::PS + koff);
 #pragma unroll
                     for (int c = 0; c < CB; ++c)
-                        acc[p][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[g][c], b[g][p], acc[p][c], 0, 0, 0);
+                        acc[r][p][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[c], b, acc[r][p][c], 0, 0, 0);
+                }
         }
-    }
-    bf16_t* Yn = Y + (int64_t)n * H * W * sy;
+        if (step % nchunk != nchunk - 1) continue;
+        // the tile's last chunk: bias, ReLU, bf16, store; clear the sums
+        int x0, y0, n, cbg, chunk;
+        decode(step, x0, y0, n, cbg, chunk);
+        bf16_t* Yn = Y + (int64_t)n * H * W * sy;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        const int xo = x0 + p * 16 + jl;
-        if (xo >= W) continue;
+        for (int r = 0; r < RPW; ++r) {
+            const int yo = y0 + wave * RPW + r;
 #pragma unroll
-        for (int c = 0; c < CB; ++c) {
-            const int co = co0 + c * 16 + kq;
-            s4 o;
+            for (int p = 0; p < 4; ++p) {
+                const int xo = x0 + p * 16 + jl;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                float v = acc[p][c][e] + (bias ? bias[co + e] : 0.f);
-                if (relu) v = fmaxf(v, 0.f);
-                o[e] = (short)f2bf(v);
+                for (int c = 0; c < CB; ++c) {
+                    const int co = (cbg * CB + c) * 16 + 4 * g;
+                    if (yo < H && xo < W) {
+                        s4 o;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            float v = acc[r][p][c][e] + (bias ? bias[co + e] : 0.f);
+                            if (relu) v = fmaxf(v, 0.f);
+                            o[e] = (short)f2bf(v);
+                        }
+                        const int64_t hoff = co >= ysplit ? yhs - ysplit : 0;
+                        *reinterpret_cast<s4*>(Yn + ((int64_t)yo * W + xo) * sy + hoff + co) = o;
+                    }
+                    acc[r][p][c] = f4{0.f, 0.f, 0.f, 0.f};
+                }
             }
-            *reinterpret_cast<s4*>(Yn + ((int64_t)y * W + xo) * sy + co) = o;
         }
     }
 }
@@ -133,7 +228,8 @@ __global__ __launch_bounds__(NT) void k_conv3(const bf16_t* __restrict__ X, int 
 // bpart[chunk][co] = sum gy[p][co] (written by the ci-block 0 waves).
 // One wave per (chunk, co block, ci block); rows of all images are chunked.
 __global__ __launch_bounds__(64) void k_conv3_wgrad(const bf16_t* __restrict__ GY, int sg, int Cout,
-                                                    const bf16_t* __restrict__ X, int sx, int Cin,
+                                                    const bf16_t* __restrict__ X, int sx, int64_t xhs, int xsplit,
+                                                    int Cin,
                                                     int H, int W, int nrows, int rows_per_chunk,
                                                     float* __restrict__ part, float* __restrict__ bpart) {
     const int lane = threadIdx.x;
@@ -150,7 +246,7 @@ __global__ __launch_bounds__(64) void k_conv3_wgrad(const bf16_t* __restrict__ G
     for (int r = r0; r < r1; ++r) {
         const int n = r / H, y = r % H;
         const bf16_t* Gr = GY + (int64_t)r * W * sg;
-        const bf16_t* Xn = X + (int64_t)n * H * W * sx;
+        const bf16_t* Xn = X + (int64_t)n * H * W * sx + (ci0 >= xsplit ? xhs - xsplit : 0);
         for (int x0 = 0; x0 < W; x0 += 16) {
             s4 a;
 #pragma unroll
@@ -213,15 +309,26 @@ __global__ void k_conv3_wgrad_reduce(const float* __restrict__ part, const float
 // 2x2 average pool: out[n][i][j][c] = bf16(mean of the 2x2 block).
 __global__ void k_pool(const bf16_t* __restrict__ X, int sx, bf16_t* __restrict__ Y, int sy, int C,
                        int N, int H2, int W2) {
-    const int64_t total = (int64_t)N * H2 * W2 * C;
+    // one thread per 8 channels of an output pixel (16-byte loads and store)
+    const int C8 = C / 8;
+    const int64_t total = (int64_t)N * H2 * W2 * C8;
     for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < total; i += (int64_t)gridDim.x * NT) {
-        const int c = (int)(i % C);
-        const int64_t pix = i / C;
+        const int c = (int)(i % C8) * 8;
+        const int64_t pix = i / C8;
         const int j = (int)(pix % W2), ii = (int)((pix / W2) % H2), n = (int)(pix / ((int64_t)W2 * H2));
         const int64_t base = ((int64_t)n * 2 * H2 + 2 * ii) * (2 * W2) + 2 * j;
-        const float s = bf2f(X[base * sx + c]) + bf2f(X[(base + 1) * sx + c]) +
-                        bf2f(X[(base + 2 * W2) * sx + c]) + bf2f(X[(base + 2 * W2 + 1) * sx + c]);
-        Y[pix * sy + c] = f2bf(0.25f * s);
+        bf8u v[4];
+        v[0].u = *reinterpret_cast<const uint4*>(X + base * sx + c);
+        v[1].u = *reinterpret_cast<const uint4*>(X + (base + 1) * sx + c);
+        v[2].u = *reinterpret_cast<const uint4*>(X + (base + 2 * W2) * sx + c);
+        v[3].u = *reinterpret_cast<const uint4*>(X + (base + 2 * W2 + 1) * sx + c);
+        bf8u o;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float s = bf2f(v[0].h[e]) + bf2f(v[1].h[e]) + bf2f(v[2].h[e]) + bf2f(v[3].h[e]);
+            o.h[e] = f2bf(0.25f * s);
+        }
+        *reinterpret_cast<uint4*>(Y + pix * sy + c) = o.u;
     }
 }
 
@@ -253,44 +360,49 @@ __global__ void k_relu_mask(bf16_t* __restrict__ G, int sg, const bf16_t* __rest
 }
 
 // Transposed 2x2 convolution, stride 2, as a GEMM per input pixel on
-// v_mfma_f32_16x16x16_bf16: D[(a d) Cout + co][pixel] = sum_ci W4[(a d) Cout +
-// co][ci] X[pixel][ci], stored with its bias at output pixel (2i + a, 2j + d).
-// W4 is [4 Cout][Cin] bf16.  Workgroup: 4 waves, one input row each, 64 input
-// pixels x 16 CB rows of D.
-template <int CB>
-__global__ __launch_bounds__(NT) void k_convT_mfma(const bf16_t* __restrict__ X, int sx, int Cin,
-                                                   const bf16_t* __restrict__ W4, const float* __restrict__ bias,
+// v_mfma_f32_16x16x32_bf16: D[(a d) Cout + co][pixel] = sum_ci W[ci][co][a][d]
+// X[pixel][ci], stored with its bias at output pixel (2i + a, 2j + d).  A is
+// packed by k_pack_frag_t in the instruction's operand order ([ci / 32][row
+// block][lane][8]).  Workgroup: 4 waves, one input row each, 64 input pixels
+// x 16 CB rows of D; every operand load of the launch (NKC = Cin / 32 blocks)
+// is issued before the first MFMA.
+template <int CB, int NKC>
+__global__ __launch_bounds__(NT) void k_convT_mfma(const bf16_t* __restrict__ X, int sx,
+                                                   const bf16_t* __restrict__ Af, const float* __restrict__ bias,
                                                    bf16_t* __restrict__ Y, int sy, int Cout, int Hi, int Wi) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int M = 4 * Cout;
+    const int jl = lane & 15, g = lane >> 4;
+    const int M = 4 * Cout, nmb = M / 16;
     const int ncog = M / (16 * CB);
     const int n = blockIdx.z / ncog;
-    const int m0 = (blockIdx.z % ncog) * 16 * CB;
+    const int mb0 = (blockIdx.z % ncog) * CB;
     const int y = blockIdx.y * 4 + wave;
     if (y >= Hi) return;
     const int x0 = blockIdx.x * 64;
-    const int jl = lane & 15, kq = (lane >> 4) * 4;
+    const bf16_t* Xr = X + ((int64_t)n * Hi + y) * Wi * sx;
+    bf16x8 b[NKC][4], a[NKC][CB];
+#pragma unroll
+    for (int kc = 0; kc < NKC; ++kc) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int xx = x0 + p * 16 + jl;
+            b[kc][p] = bf16x8{};
+            if (xx < Wi) b[kc][p] = *reinterpret_cast<const bf16x8*>(Xr + (int64_t)xx * sx + kc * 32 + 8 * g);
+        }
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+            a[kc][c] = *reinterpret_cast<const bf16x8*>(Af + (((int64_t)kc * nmb + mb0 + c) * 64 + lane) * 8);
+    }
     f4 acc[4][CB];
 #pragma unroll
     for (int p = 0; p < 4; ++p)
 #pragma unroll
-        for (int c = 0; c < CB; ++c) acc[p][c] = f4{0.f, 0.f, 0.f, 0.f};
-    const bf16_t* Xr = X + ((int64_t)n * Hi + y) * Wi * sx;
-    for (int ci = 0; ci < Cin; ci += 16) {
-        s4 b[4];
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const int xx = x0 + p * 16 + jl;
-            b[p] = xx < Wi ? *reinterpret_cast<const s4*>(Xr + (int64_t)xx * sx + ci + kq) : s4{0, 0, 0, 0};
-        }
-#pragma unroll
         for (int c = 0; c < CB; ++c) {
-            const s4 av = *reinterpret_cast<const s4*>(W4 + (int64_t)(m0 + c * 16 + jl) * Cin + ci + kq);
+            acc[p][c] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int p = 0; p < 4; ++p)
-                acc[p][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, b[p], acc[p][c], 0, 0, 0);
+            for (int kc = 0; kc < NKC; ++kc)
+                acc[p][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[kc][c], b[kc][p], acc[p][c], 0, 0, 0);
         }
-    }
     const int Wo = 2 * Wi;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
@@ -298,7 +410,7 @@ __global__ __launch_bounds__(NT) void k_convT_mfma(const bf16_t* __restrict__ X,
         if (xx >= Wi) continue;
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
-            const int mrow = m0 + c * 16 + kq;            // four consecutive rows: same (a, d)
+            const int mrow = (mb0 + c) * 16 + 4 * g;     // four consecutive rows: same (a, d)
             const int ad = mrow / Cout, co = mrow - ad * Cout;
             const int yo = 2 * y + (ad >> 1), xo = 2 * xx + (ad & 1);
             s4 o;
@@ -451,9 +563,12 @@ __global__ void k_sum_chunks(const float* __restrict__ part, int nchunks, int64_
 __global__ void k_out(const bf16_t* __restrict__ X, int sx, const bf16_t* __restrict__ w, const float* bias,
                       float* __restrict__ o, int64_t npix) {
     for (int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x; p < npix; p += (int64_t)gridDim.x * NT) {
+        bf8u x[2];
+        x[0].u = *reinterpret_cast<const uint4*>(X + p * sx);
+        x[1].u = *reinterpret_cast<const uint4*>(X + p * sx + 8);
         float s = bias[0];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) s += bf2f(w[c]) * bf2f(X[p * sx + c]);
+        for (int c = 0; c < 16; ++c) s += bf2f(w[c]) * bf2f(x[c >> 3].h[c & 7]);
         o[p] = s;
     }
 }
@@ -610,30 +725,60 @@ __global__ void k_adam(float* __restrict__ th, float* __restrict__ m, float* __r
     }
 }
 
-// bf16 copies of the master weights: conv3x3 forward [9][Cout][cin_pad] and
-// data-gradient [9][Cin][Cout] (taps reversed) from [co][ci][3][3].
-__global__ void k_pack_conv3(const float* __restrict__ w, int Cout, int cin_real, int cin_pad,
-                             bf16_t* __restrict__ wf, bf16_t* __restrict__ wb) {
-    const int64_t n = (int64_t)9 * Cout * cin_pad;
+// bf16 weights of a 3x3 layer in the operand order of k_conv3, from the
+// master weights w[co][ci][3][3] (cin real input channels): forward (bwd = 0)
+// A[tap][m = co][k = ci], the data gradient (bwd = 1) A[tap][m = ci][k = co]
+// with the taps reversed.  Element (chunk, kb, cb, lane, e) is A at
+// m = 16 cb + lane % 16 and the lane's tap and channel k of block kb
+// (k_conv3's contraction order); zero beyond M, K, cin or the ninth tap.
+__global__ void k_pack_frag(const float* __restrict__ w, int cout, int cin, int M, int K, int bwd,
+                            bf16_t* __restrict__ af, int64_t n) {
+    const int ck = frag_ck(K), nkb = frag_nkb(ck), ncb = (M + 15) / 16;
     for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
-        const int ci = (int)(i % cin_pad), co = (int)((i / cin_pad) % Cout), tap = (int)(i / ((int64_t)cin_pad * Cout));
-        const float v = ci < cin_real ? w[((int64_t)co * cin_real + ci) * 9 + tap] : 0.f;
-        const bf16_t h = f2bf(v);
-        wf[i] = h;
-        if (wb && ci < cin_real) wb[((int64_t)(8 - tap) * cin_real + ci) * Cout + co] = h;
+        const int e = (int)(i & 7), lane = (int)((i >> 3) & 63);
+        const int64_t rest = i >> 9;
+        const int cb = (int)(rest % ncb), kb = (int)((rest / ncb) % nkb), chunk = (int)(rest / ((int64_t)ncb * nkb));
+        const int g = lane >> 4, m = cb * 16 + (lane & 15);
+        const int tap = ck == 32 ? kb : 2 * kb + (g >> 1);
+        const int k = chunk * ck + (ck == 32 ? 8 * g : 8 * (g & 1)) + e;
+        float v = 0.f;
+        if (tap < 9 && m < M && k < K) {
+            const int co = bwd ? k : m, ci = bwd ? m : k;
+            if (ci < cin) v = w[((int64_t)co * cin + ci) * 9 + (bwd ? 8 - tap : tap)];
+        }
+        af[i] = f2bf(v);
     }
 }
 
-// bf16 copies of transposed-convolution weights from [ci][co][a][d]: forward
-// W4[(a d) Cout + co][ci] and data-gradient WT[ci][(a d) Cout + co].
-__global__ void k_pack_convT(const float* __restrict__ w, int Cin, int Cout, bf16_t* __restrict__ w4,
-                             bf16_t* __restrict__ wt) {
+int64_t convT_frag_elems(int Cin, int Cout) { return (int64_t)((Cin + 31) / 32) * (4 * Cout / 16) * 512; }
+
+int64_t frag_elems(int M, int K) {
+    const int ck = frag_ck(K);
+    return (int64_t)(K / ck) * frag_nkb(ck) * ((M + 15) / 16) * 512;
+}
+
+// bf16 data-gradient copy of transposed-convolution weights from
+// [ci][co][a][d]: WT[ci][(a d) Cout + co].
+__global__ void k_pack_convT(const float* __restrict__ w, int Cin, int Cout, bf16_t* __restrict__ wt) {
     const int64_t n = (int64_t)4 * Cin * Cout;
     for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
         const int ad = (int)(i % 4), co = (int)((i / 4) % Cout), ci = (int)(i / (4 * Cout));
-        const bf16_t h = f2bf(w[i]);
-        w4[((int64_t)ad * Cout + co) * Cin + ci] = h;
-        wt[(int64_t)ci * 4 * Cout + ad * Cout + co] = h;
+        wt[(int64_t)ci * 4 * Cout + ad * Cout + co] = f2bf(w[i]);
+    }
+}
+
+// Transposed-convolution weights w[ci][co][a][d] in k_convT_mfma's operand
+// order: element (kc, mb, lane, e) is W at row m = 16 mb + lane % 16 =
+// (a d) Cout + co and ci = 32 kc + 8 (lane / 16) + e.
+__global__ void k_pack_frag_t(const float* __restrict__ w, int Cin, int Cout, bf16_t* __restrict__ af, int64_t n) {
+    const int nmb = 4 * Cout / 16;
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+        const int e = (int)(i & 7), lane = (int)((i >> 3) & 63);
+        const int64_t rest = i >> 9;
+        const int mb = (int)(rest % nmb), kc = (int)(rest / nmb);
+        const int m = mb * 16 + (lane & 15), ci = kc * 32 + 8 * (lane >> 4) + e;
+        const int ad = m / Cout, co = m % Cout;
+        af[i] = f2bf(ci < Cin ? w[((int64_t)ci * Cout + co) * 4 + ad] : 0.f);
     }
 }
 
@@ -642,14 +787,17 @@ __global__ void k_to_bf16(const float* __restrict__ w, bf16_t* __restrict__ o, i
 }
 
 // Network input: NCHW float32 [n][3][H][W] to NHWC bf16 with 16 channels
-// (channels 3..15 zero).
+// (channels 3..15 zero), one thread per pixel.
 __global__ void k_input(const float* __restrict__ x, bf16_t* __restrict__ X, int N, int64_t HW) {
-    const int64_t total = (int64_t)N * HW * 16;
-    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < total; i += (int64_t)gridDim.x * NT) {
-        const int c = (int)(i % 16);
-        const int64_t pix = i / 16;
+    const int64_t total = (int64_t)N * HW;
+    for (int64_t pix = blockIdx.x * (int64_t)NT + threadIdx.x; pix < total; pix += (int64_t)gridDim.x * NT) {
         const int64_t n = pix / HW, p = pix % HW;
-        X[i] = c < 3 ? f2bf(x[(n * 3 + c) * HW + p]) : (bf16_t)0;
+        bf8u lo;
+        lo.u = uint4{0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) lo.h[c] = f2bf(x[(n * 3 + c) * HW + p]);
+        *reinterpret_cast<uint4*>(X + pix * 16) = lo.u;
+        *reinterpret_cast<uint4*>(X + pix * 16 + 8) = uint4{0u, 0u, 0u, 0u};
     }
 }
 
@@ -680,7 +828,9 @@ struct Unet {
     int64_t part_cap = 0;
     double* dloss = nullptr;     // per-sample loss
     // activation views (element offsets into act / grad, per-image strides)
-    struct View { int64_t off; int stride; int C; int lvl; };
+    // C channels per pixel at pixel stride `stride`; a concatenation buffer
+    // holds its two halves of C / 2 channels as planar tensors hs apart
+    struct View { int64_t off; int stride; int C; int lvl; int64_t hs; };
     std::vector<View> av;        // named below
 };
 
@@ -707,32 +857,90 @@ const int kLayerDef[NLAYERS][3] = {
 
 int64_t layer_weights(int kind, int ci, int co) { return kind == 0 ? (int64_t)9 * ci * co : kind == 1 ? (int64_t)4 * ci * co : ci * co; }
 
+// A tensor view handed to the convolution launchers: pointer, pixel stride and,
+// for a concatenation buffer, the distance to the second half and the first
+// channel that lives there (no split: hs = 0, split beyond every channel).
+struct Tv {
+    bf16_t* p;
+    int s;
+    int64_t hs = 0;
+    int split = 1 << 30;
+};
+
 struct Ctx {
     Unet* U;
     int N;
     int64_t pix(int lvl) const { return (int64_t)N * (U->H >> lvl) * (U->W >> lvl); }
-    bf16_t* a(int id, int choff = 0) const { return U->act + U->av[id].off * 1 + choff; }
-    bf16_t* g(int id, int choff = 0) const { return U->grad + U->av[id].off + choff; }
-    int s(int id) const { return U->av[id].stride; }
+    bf16_t* a(int id) const { return U->act + U->av[id].off; }
+    bf16_t* g(int id) const { return U->grad + U->av[id].off; }
+    // half h (0: upsampled decoder input, 1: encoder skip) of a concatenation buffer
+    bf16_t* ah(int id, int h) const { return U->act + U->av[id].off + h * U->av[id].hs; }
+    bf16_t* gh(int id, int h) const { return U->grad + U->av[id].off + h * U->av[id].hs; }
+    Tv at(int id) const { return view(U->act, id); }
+    Tv gt(int id) const { return view(U->grad, id); }
+    Tv view(bf16_t* base, int id) const {
+        const Unet::View& v = U->av[id];
+        Tv t{base + v.off, v.stride};
+        if (v.hs) { t.hs = v.hs; t.split = v.C / 2; }
+        return t;
+    }
     int h(int lvl) const { return U->H >> lvl; }
     int w(int lvl) const { return U->W >> lvl; }
 };
 
-esi_status_t conv3(const Ctx& c, const bf16_t* X, int sx, int Cin, int layer, bool bwd, bf16_t* Y, int sy,
-                   int Cout, int lvl, bool relu) {
+template <int CB, int RPW, int CK>
+void launch_conv3(const Ctx& c, const Tv& X, int K, const bf16_t* Af, const float* bias, const Tv& Y, int M, int H,
+                  int W, bool relu) {
+    // persistent grid: as many workgroups as the device holds at once
+    static int resident = 0;
+    if (!resident) {
+        int per_cu = 0, cus = 0, dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv3<CB, RPW, CK>, NT, 0) != hipSuccess)
+            per_cu = 1, cus = 256;
+        resident = std::max(1, per_cu) * std::max(1, cus);
+    }
+    const int64_t ntiles = (int64_t)((W + 63) / 64) * ((H + 4 * RPW - 1) / (4 * RPW)) * c.N * (M / (16 * CB));
+    const int grid = (int)std::min<int64_t>(ntiles, resident);
+    hipLaunchKernelGGL((k_conv3<CB, RPW, CK>), dim3(grid), dim3(NT), 0, c.U->stream, X.p, X.s, X.hs, X.split, K, Af,
+                       (M + 15) / 16, bias, Y.p, Y.s, Y.hs, Y.split, M, H, W, c.N, relu ? 1 : 0);
+}
+
+template <int CB, int CK>
+void launch_conv3_rows(const Ctx& c, const Tv& X, int K, const bf16_t* Af, const float* bias, const Tv& Y, int M,
+                       int H, int W, bool relu) {
+    // two output rows per wave (each weight operand feeds twice the MFMAs)
+    // where there are tiles enough; not with 64 output channels, whose
+    // accumulators leave no registers for the loads in flight
+    const int64_t tiles2 = (int64_t)((W + 63) / 64) * ((H + 7) / 8) * c.N * (M / (16 * CB));
+    if constexpr (CB <= 2) {
+        if (tiles2 >= 1024) {
+            launch_conv3<CB, 2, CK>(c, X, K, Af, bias, Y, M, H, W, relu);
+            return;
+        }
+    }
+    launch_conv3<CB, 1, CK>(c, X, K, Af, bias, Y, M, H, W, relu);
+}
+
+// K input channels (Cin, or Cout for the data gradient) to M outputs
+esi_status_t conv3(const Ctx& c, const Tv& X, int K, int layer, bool bwd, const Tv& Y, int M, int lvl, bool relu) {
     Unet* U = c.U;
     const Layer& Ly = U->L[layer];
-    const bf16_t* Wp = bwd ? Ly.wb : Ly.wf;
+    const bf16_t* Af = bwd ? Ly.wb : Ly.wf;
     const float* bias = bwd ? nullptr : U->theta + Ly.off + Ly.nw;
     const int H = c.h(lvl), W = c.w(lvl);
-    const int cb = Cout >= 64 ? 4 : Cout / 16;
-    dim3 grid((W + 63) / 64, (H + 3) / 4, c.N * (Cout / (16 * cb)));
-    if (cb == 4)
-        hipLaunchKernelGGL(k_conv3<4>, grid, dim3(NT), 0, U->stream, X, sx, Cin, Wp, bias, Y, sy, Cout, H, W, relu ? 1 : 0);
-    else if (cb == 2)
-        hipLaunchKernelGGL(k_conv3<2>, grid, dim3(NT), 0, U->stream, X, sx, Cin, Wp, bias, Y, sy, Cout, H, W, relu ? 1 : 0);
-    else
-        hipLaunchKernelGGL(k_conv3<1>, grid, dim3(NT), 0, U->stream, X, sx, Cin, Wp, bias, Y, sy, Cout, H, W, relu ? 1 : 0);
+    if (K % 16 || M % 16) return fail(ESI_ERR_SHAPE, "3x3 convolution channels must be multiples of 16");
+    const int cb = M >= 64 ? 4 : M / 16;
+    if (frag_ck(K) == 32) {
+        if (cb == 4) launch_conv3_rows<4, 32>(c, X, K, Af, bias, Y, M, H, W, relu);
+        else if (cb == 2) launch_conv3_rows<2, 32>(c, X, K, Af, bias, Y, M, H, W, relu);
+        else launch_conv3_rows<1, 32>(c, X, K, Af, bias, Y, M, H, W, relu);
+    } else {
+        if (cb == 4) launch_conv3_rows<4, 16>(c, X, K, Af, bias, Y, M, H, W, relu);
+        else if (cb == 2) launch_conv3_rows<2, 16>(c, X, K, Af, bias, Y, M, H, W, relu);
+        else launch_conv3_rows<1, 16>(c, X, K, Af, bias, Y, M, H, W, relu);
+    }
     ESI_HIP_TRY(hipGetLastError());
     return ESI_OK;
 }
@@ -742,8 +950,8 @@ esi_status_t need_part(Unet* U, int64_t n) {
 }
 
 // weight + bias gradient of a 3x3 layer into gflat
-esi_status_t conv3_wgrad(const Ctx& c, const bf16_t* GY, int sg, int Cout, const bf16_t* X, int sx, int Cin,
-                         int cin_real, int lvl, float* gflat) {
+esi_status_t conv3_wgrad(const Ctx& c, const Tv& GY, int Cout, const Tv& X, int Cin, int cin_real, int lvl,
+                         float* gflat) {
     Unet* U = c.U;
     const int H = c.h(lvl), W = c.w(lvl);
     const int nrows = c.N * H;
@@ -755,8 +963,8 @@ esi_status_t conv3_wgrad(const Ctx& c, const bf16_t* GY, int sg, int Cout, const
     ESI_TRY(need_part(U, np + (int64_t)nchunks * Cout));
     float* part = U->part;
     float* bpart = U->part + np;
-    hipLaunchKernelGGL(k_conv3_wgrad, dim3(nchunks, nblocks), dim3(64), 0, U->stream, GY, sg, Cout, X, sx,
-                       Cin, H, W, nrows, rpc, part, bpart);
+    hipLaunchKernelGGL(k_conv3_wgrad, dim3(nchunks, nblocks), dim3(64), 0, U->stream, GY.p, GY.s, Cout, X.p, X.s,
+                       X.hs, X.split, Cin, H, W, nrows, rpc, part, bpart);
     const int64_t nout = (int64_t)9 * Cout * Cin + Cout;
     hipLaunchKernelGGL(k_conv3_wgrad_reduce, dim3(grid_for(nout)), dim3(NT), 0, U->stream, part, bpart, nchunks,
                        Cout, Cin, cin_real, gflat);
@@ -764,20 +972,25 @@ esi_status_t conv3_wgrad(const Ctx& c, const bf16_t* GY, int sg, int Cout, const
     return ESI_OK;
 }
 
+template <int CB, int NKC>
+void launch_convT(const Ctx& c, const Layer& Ly, const bf16_t* X, int sx, const float* bias, bf16_t* Y, int sy,
+                  int Hi, int Wi) {
+    dim3 grid((Wi + 63) / 64, (Hi + 3) / 4, c.N * (4 * Ly.cout / (16 * CB)));
+    hipLaunchKernelGGL((k_convT_mfma<CB, NKC>), grid, dim3(NT), 0, c.U->stream, X, sx, Ly.wf, bias, Y, sy, Ly.cout,
+                       Hi, Wi);
+}
+
 esi_status_t convT_fwd(const Ctx& c, int layer, const bf16_t* X, int sx, bf16_t* Y, int sy, int lvl_in) {
     Unet* U = c.U;
     const Layer& Ly = U->L[layer];
     const int Hi = c.h(lvl_in), Wi = c.w(lvl_in);
-    const int M = 4 * Ly.cout;
-    const int cb = M >= 64 ? 4 : M / 16;
-    dim3 grid((Wi + 63) / 64, (Hi + 3) / 4, c.N * (M / (16 * cb)));
     const float* bias = U->theta + Ly.off + Ly.nw;
-    if (cb == 4)
-        hipLaunchKernelGGL(k_convT_mfma<4>, grid, dim3(NT), 0, U->stream, X, sx, Ly.cin, Ly.wf, bias, Y, sy,
-                           Ly.cout, Hi, Wi);
-    else
-        hipLaunchKernelGGL(k_convT_mfma<1>, grid, dim3(NT), 0, U->stream, X, sx, Ly.cin, Ly.wf, bias, Y, sy,
-                           Ly.cout, Hi, Wi);
+    // 4 Cout rows of D in blocks of 64; Cin in blocks of 32 (32, 64 or 128)
+    if (Ly.cout % 16 || (Ly.cin != 32 && Ly.cin != 64 && Ly.cin != 128))
+        return fail(ESI_ERR_SHAPE, "transposed convolution channels outside the supported set");
+    if (Ly.cin == 32) launch_convT<4, 1>(c, Ly, X, sx, bias, Y, sy, Hi, Wi);
+    else if (Ly.cin == 64) launch_convT<4, 2>(c, Ly, X, sx, bias, Y, sy, Hi, Wi);
+    else launch_convT<4, 4>(c, Ly, X, sx, bias, Y, sy, Hi, Wi);
     ESI_HIP_TRY(hipGetLastError());
     return ESI_OK;
 }
@@ -815,7 +1028,7 @@ esi_status_t convT_back(const Ctx& c, int layer, const bf16_t* X, int sx, const 
 }
 
 esi_status_t pool(const Ctx& c, const bf16_t* X, int sx, bf16_t* Y, int sy, int C, int lvl_in) {
-    const int64_t n = c.pix(lvl_in + 1) * C;
+    const int64_t n = c.pix(lvl_in + 1) * (C / 8);
     hipLaunchKernelGGL(k_pool, dim3(grid_for(n)), dim3(NT), 0, c.U->stream, X, sx, Y, sy, C, c.N,
                        c.h(lvl_in + 1), c.w(lvl_in + 1));
     ESI_HIP_TRY(hipGetLastError());
@@ -832,29 +1045,31 @@ esi_status_t mask(const Ctx& c, bf16_t* G, int sg, const bf16_t* Y, int sa, int 
 esi_status_t forward(const Ctx& c, const float* x, float* o) {
     Unet* U = c.U;
     const int64_t HW = (int64_t)U->H * U->W;
-    hipLaunchKernelGGL(k_input, dim3(grid_for(c.N * HW * 16)), dim3(NT), 0, U->stream, x, c.a(A_X), c.N, HW);
-    // encoder
-    ESI_TRY(conv3(c, c.a(A_X), 16, 16, C1A, false, c.a(A_A1), 16, 16, 0, true));
-    ESI_TRY(conv3(c, c.a(A_A1), 16, 16, C1B, false, c.a(A_CAT1, 16), 32, 16, 0, true));
-    ESI_TRY(pool(c, c.a(A_CAT1, 16), 32, c.a(A_P1), 16, 16, 0));
-    ESI_TRY(conv3(c, c.a(A_P1), 16, 16, C2A, false, c.a(A_A2), 32, 32, 1, true));
-    ESI_TRY(conv3(c, c.a(A_A2), 32, 32, C2B, false, c.a(A_CAT2, 32), 64, 32, 1, true));
-    ESI_TRY(pool(c, c.a(A_CAT2, 32), 64, c.a(A_P2), 32, 32, 1));
-    ESI_TRY(conv3(c, c.a(A_P2), 32, 32, C3A, false, c.a(A_A3), 64, 64, 2, true));
-    ESI_TRY(conv3(c, c.a(A_A3), 64, 64, C3B, false, c.a(A_CAT3, 64), 128, 64, 2, true));
-    ESI_TRY(pool(c, c.a(A_CAT3, 64), 128, c.a(A_P3), 64, 64, 2));
-    ESI_TRY(conv3(c, c.a(A_P3), 64, 64, C4A, false, c.a(A_A4), 128, 128, 3, true));
-    ESI_TRY(conv3(c, c.a(A_A4), 128, 128, C4B, false, c.a(A_B4), 128, 128, 3, true));
-    // decoder
-    ESI_TRY(convT_fwd(c, U3, c.a(A_B4), 128, c.a(A_CAT3), 128, 3));
-    ESI_TRY(conv3(c, c.a(A_CAT3), 128, 128, D3A, false, c.a(A_D3A), 64, 64, 2, true));
-    ESI_TRY(conv3(c, c.a(A_D3A), 64, 64, D3B, false, c.a(A_D3B), 64, 64, 2, true));
-    ESI_TRY(convT_fwd(c, U2, c.a(A_D3B), 64, c.a(A_CAT2), 64, 2));
-    ESI_TRY(conv3(c, c.a(A_CAT2), 64, 64, D2A, false, c.a(A_D2A), 32, 32, 1, true));
-    ESI_TRY(conv3(c, c.a(A_D2A), 32, 32, D2B, false, c.a(A_D2B), 32, 32, 1, true));
-    ESI_TRY(convT_fwd(c, U1, c.a(A_D2B), 32, c.a(A_CAT1), 32, 1));
-    ESI_TRY(conv3(c, c.a(A_CAT1), 32, 32, D1A, false, c.a(A_D1A), 16, 16, 0, true));
-    ESI_TRY(conv3(c, c.a(A_D1A), 16, 16, D1B, false, c.a(A_D1B), 16, 16, 0, true));
+    auto T = [](bf16_t* p, int s) { return Tv{p, s}; };
+    hipLaunchKernelGGL(k_input, dim3(grid_for(c.N * HW)), dim3(NT), 0, U->stream, x, c.a(A_X), c.N, HW);
+    // encoder: each level's second convolution writes the skip half of the
+    // decoder's concatenation buffer, which the pooling reads
+    ESI_TRY(conv3(c, c.at(A_X), 16, C1A, false, c.at(A_A1), 16, 0, true));
+    ESI_TRY(conv3(c, c.at(A_A1), 16, C1B, false, T(c.ah(A_CAT1, 1), 16), 16, 0, true));
+    ESI_TRY(pool(c, c.ah(A_CAT1, 1), 16, c.a(A_P1), 16, 16, 0));
+    ESI_TRY(conv3(c, c.at(A_P1), 16, C2A, false, c.at(A_A2), 32, 1, true));
+    ESI_TRY(conv3(c, c.at(A_A2), 32, C2B, false, T(c.ah(A_CAT2, 1), 32), 32, 1, true));
+    ESI_TRY(pool(c, c.ah(A_CAT2, 1), 32, c.a(A_P2), 32, 32, 1));
+    ESI_TRY(conv3(c, c.at(A_P2), 32, C3A, false, c.at(A_A3), 64, 2, true));
+    ESI_TRY(conv3(c, c.at(A_A3), 64, C3B, false, T(c.ah(A_CAT3, 1), 64), 64, 2, true));
+    ESI_TRY(pool(c, c.ah(A_CAT3, 1), 64, c.a(A_P3), 64, 64, 2));
+    ESI_TRY(conv3(c, c.at(A_P3), 64, C4A, false, c.at(A_A4), 128, 3, true));
+    ESI_TRY(conv3(c, c.at(A_A4), 128, C4B, false, c.at(A_B4), 128, 3, true));
+    // decoder: the transposed convolution writes the first half
+    ESI_TRY(convT_fwd(c, U3, c.a(A_B4), 128, c.ah(A_CAT3, 0), 64, 3));
+    ESI_TRY(conv3(c, c.at(A_CAT3), 128, D3A, false, c.at(A_D3A), 64, 2, true));
+    ESI_TRY(conv3(c, c.at(A_D3A), 64, D3B, false, c.at(A_D3B), 64, 2, true));
+    ESI_TRY(convT_fwd(c, U2, c.a(A_D3B), 64, c.ah(A_CAT2, 0), 32, 2));
+    ESI_TRY(conv3(c, c.at(A_CAT2), 64, D2A, false, c.at(A_D2A), 32, 1, true));
+    ESI_TRY(conv3(c, c.at(A_D2A), 32, D2B, false, c.at(A_D2B), 32, 1, true));
+    ESI_TRY(convT_fwd(c, U1, c.a(A_D2B), 32, c.ah(A_CAT1, 0), 16, 1));
+    ESI_TRY(conv3(c, c.at(A_CAT1), 32, D1A, false, c.at(A_D1A), 16, 0, true));
+    ESI_TRY(conv3(c, c.at(A_D1A), 16, D1B, false, c.at(A_D1B), 16, 0, true));
     const Layer& Lo = U->L[OUT];
     hipLaunchKernelGGL(k_out, dim3(grid_for(c.pix(0))), dim3(NT), 0, U->stream, c.a(A_D1B), 16, Lo.wf,
                        U->theta + Lo.off + Lo.nw, o, c.pix(0));
@@ -865,6 +1080,7 @@ esi_status_t forward(const Ctx& c, const float* x, float* o) {
 // Backward pass from U->go into the flat gradient gflat (after forward()).
 esi_status_t backward(const Ctx& c, float* gflat) {
     Unet* U = c.U;
+    auto T = [](bf16_t* p, int s) { return Tv{p, s}; };
     // output layer: g_d1b = bf16(w go) masked by d1b > 0; weight / bias sums
     {
         const int64_t npx = c.pix(0);
@@ -878,35 +1094,37 @@ esi_status_t backward(const Ctx& c, float* gflat) {
                            gflat + Lo.off);
         ESI_HIP_TRY(hipGetLastError());
     }
-    auto conv_back = [&](int layer, int gid, int gchoff, int gstride, int Cout, const bf16_t* X, int sx,
-                         int Cin, int lvl, bf16_t* GX, int sgx) -> esi_status_t {
+    // weight gradient of a 3x3 layer from its output gradient GY and input X,
+    // then (GX.p non-null) the gradient of its input
+    auto conv_back = [&](int layer, const Tv& GY, int Cout, const Tv& X, int Cin, int lvl,
+                         const Tv& GX) -> esi_status_t {
         const Layer& Ly = U->L[layer];
-        ESI_TRY(conv3_wgrad(c, c.g(gid, gchoff), gstride, Cout, X, sx, Cin, Ly.cin, lvl, gflat + Ly.off));
-        if (GX) ESI_TRY(conv3(c, c.g(gid, gchoff), gstride, Cout, layer, true, GX, sgx, Cin, lvl, false));
+        ESI_TRY(conv3_wgrad(c, GY, Cout, X, Cin, Ly.cin, lvl, gflat + Ly.off));
+        if (GX.p) ESI_TRY(conv3(c, GY, Cout, layer, true, GX, Cin, lvl, false));
         return ESI_OK;
     };
     // level 1 decoder: d1b, d1a (d1b's gradient is already masked)
-    ESI_TRY(conv_back(D1B, A_D1B, 0, 16, 16, c.a(A_D1A), 16, 16, 0, c.g(A_D1A), 16));
+    ESI_TRY(conv_back(D1B, c.gt(A_D1B), 16, c.at(A_D1A), 16, 0, c.gt(A_D1A)));
     ESI_TRY(mask(c, c.g(A_D1A), 16, c.a(A_D1A), 16, 16, 0));
-    ESI_TRY(conv_back(D1A, A_D1A, 0, 16, 16, c.a(A_CAT1), 32, 32, 0, c.g(A_CAT1), 32));
-    ESI_TRY(convT_back(c, U1, c.a(A_D2B), 32, c.g(A_CAT1), 32, c.g(A_D2B), 32, 1, gflat));
+    ESI_TRY(conv_back(D1A, c.gt(A_D1A), 16, c.at(A_CAT1), 32, 0, c.gt(A_CAT1)));
+    ESI_TRY(convT_back(c, U1, c.a(A_D2B), 32, c.gh(A_CAT1, 0), 16, c.g(A_D2B), 32, 1, gflat));
     // level 2 decoder
     ESI_TRY(mask(c, c.g(A_D2B), 32, c.a(A_D2B), 32, 32, 1));
-    ESI_TRY(conv_back(D2B, A_D2B, 0, 32, 32, c.a(A_D2A), 32, 32, 1, c.g(A_D2A), 32));
+    ESI_TRY(conv_back(D2B, c.gt(A_D2B), 32, c.at(A_D2A), 32, 1, c.gt(A_D2A)));
     ESI_TRY(mask(c, c.g(A_D2A), 32, c.a(A_D2A), 32, 32, 1));
-    ESI_TRY(conv_back(D2A, A_D2A, 0, 32, 32, c.a(A_CAT2), 64, 64, 1, c.g(A_CAT2), 64));
-    ESI_TRY(convT_back(c, U2, c.a(A_D3B), 64, c.g(A_CAT2), 64, c.g(A_D3B), 64, 2, gflat));
+    ESI_TRY(conv_back(D2A, c.gt(A_D2A), 32, c.at(A_CAT2), 64, 1, c.gt(A_CAT2)));
+    ESI_TRY(convT_back(c, U2, c.a(A_D3B), 64, c.gh(A_CAT2, 0), 32, c.g(A_D3B), 64, 2, gflat));
     // level 3 decoder
     ESI_TRY(mask(c, c.g(A_D3B), 64, c.a(A_D3B), 64, 64, 2));
-    ESI_TRY(conv_back(D3B, A_D3B, 0, 64, 64, c.a(A_D3A), 64, 64, 2, c.g(A_D3A), 64));
+    ESI_TRY(conv_back(D3B, c.gt(A_D3B), 64, c.at(A_D3A), 64, 2, c.gt(A_D3A)));
     ESI_TRY(mask(c, c.g(A_D3A), 64, c.a(A_D3A), 64, 64, 2));
-    ESI_TRY(conv_back(D3A, A_D3A, 0, 64, 64, c.a(A_CAT3), 128, 128, 2, c.g(A_CAT3), 128));
-    ESI_TRY(convT_back(c, U3, c.a(A_B4), 128, c.g(A_CAT3), 128, c.g(A_B4), 128, 3, gflat));
+    ESI_TRY(conv_back(D3A, c.gt(A_D3A), 64, c.at(A_CAT3), 128, 2, c.gt(A_CAT3)));
+    ESI_TRY(convT_back(c, U3, c.a(A_B4), 128, c.gh(A_CAT3, 0), 64, c.g(A_B4), 128, 3, gflat));
     // bottleneck
     ESI_TRY(mask(c, c.g(A_B4), 128, c.a(A_B4), 128, 128, 3));
-    ESI_TRY(conv_back(C4B, A_B4, 0, 128, 128, c.a(A_A4), 128, 128, 3, c.g(A_A4), 128));
+    ESI_TRY(conv_back(C4B, c.gt(A_B4), 128, c.at(A_A4), 128, 3, c.gt(A_A4)));
     ESI_TRY(mask(c, c.g(A_A4), 128, c.a(A_A4), 128, 128, 3));
-    ESI_TRY(conv_back(C4A, A_A4, 0, 128, 128, c.a(A_P3), 64, 64, 3, c.g(A_P3), 64));
+    ESI_TRY(conv_back(C4A, c.gt(A_A4), 128, c.at(A_P3), 64, 3, c.gt(A_P3)));
     // encoder levels: gradient into e_l = pool path + skip, masked by e_l > 0;
     // the e_l gradient goes into the skip half of the concat gradient buffer
     struct Enc { int lvl, ch, cat, p, a, cb, ca, pin; };
@@ -916,14 +1134,14 @@ esi_status_t backward(const Ctx& c, float* gflat) {
     for (const Enc& e : enc) {
         const int64_t n = c.pix(e.lvl) * e.ch;
         hipLaunchKernelGGL(k_pool_back, dim3(grid_for(n)), dim3(NT), 0, U->stream, c.g(e.p), e.ch,
-                           c.g(e.cat, e.ch), 2 * e.ch, c.a(e.cat, e.ch), 2 * e.ch, c.g(e.cat, e.ch), 2 * e.ch,
+                           c.gh(e.cat, 1), e.ch, c.ah(e.cat, 1), e.ch, c.gh(e.cat, 1), e.ch,
                            e.ch, c.N, c.h(e.lvl), c.w(e.lvl));
         ESI_HIP_TRY(hipGetLastError());
         const int cin_a = e.lvl == 0 ? 16 : e.ch / 2;
-        ESI_TRY(conv_back(e.cb, e.cat, e.ch, 2 * e.ch, e.ch, c.a(e.a), e.ch, e.ch, e.lvl, c.g(e.a), e.ch));
+        ESI_TRY(conv_back(e.cb, T(c.gh(e.cat, 1), e.ch), e.ch, c.at(e.a), e.ch, e.lvl, c.gt(e.a)));
         ESI_TRY(mask(c, c.g(e.a), e.ch, c.a(e.a), e.ch, e.ch, e.lvl));
-        ESI_TRY(conv_back(e.ca, e.a, 0, e.ch, e.ch, c.a(e.pin), cin_a, cin_a, e.lvl,
-                          e.lvl == 0 ? nullptr : c.g(e.pin), cin_a));
+        ESI_TRY(conv_back(e.ca, c.gt(e.a), e.ch, c.at(e.pin), cin_a, e.lvl,
+                          e.lvl == 0 ? Tv{nullptr, 0} : c.gt(e.pin)));
     }
     return ESI_OK;
 }
@@ -933,12 +1151,17 @@ esi_status_t pack(Unet* U) {
         const float* w = U->theta + Ly.off;
         if (Ly.kind == 0) {
             const int cpad = Ly.cin < 16 ? 16 : Ly.cin;
-            const int64_t n = (int64_t)9 * Ly.cout * cpad;
-            hipLaunchKernelGGL(k_pack_conv3, dim3(grid_for(n)), dim3(NT), 0, U->stream, w, Ly.cout, Ly.cin, cpad,
-                               Ly.wf, Ly.wb);
+            const int64_t nf = frag_elems(Ly.cout, cpad), nb = frag_elems(cpad, Ly.cout);
+            hipLaunchKernelGGL(k_pack_frag, dim3(grid_for(nf)), dim3(NT), 0, U->stream, w, Ly.cout, Ly.cin, Ly.cout,
+                               cpad, 0, Ly.wf, nf);
+            hipLaunchKernelGGL(k_pack_frag, dim3(grid_for(nb)), dim3(NT), 0, U->stream, w, Ly.cout, Ly.cin, Ly.cin,
+                               Ly.cout, 1, Ly.wb, nb);
         } else if (Ly.kind == 1) {
+            const int64_t nf = convT_frag_elems(Ly.cin, Ly.cout);
+            hipLaunchKernelGGL(k_pack_frag_t, dim3(grid_for(nf)), dim3(NT), 0, U->stream, w, Ly.cin, Ly.cout,
+                               Ly.wf, nf);
             hipLaunchKernelGGL(k_pack_convT, dim3(grid_for(Ly.nw)), dim3(NT), 0, U->stream, w, Ly.cin, Ly.cout,
-                               Ly.wf, Ly.wb);
+                               Ly.wb);
         } else {
             hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(Ly.nw)), dim3(NT), 0, U->stream, w, Ly.wf, Ly.nw);
         }
@@ -999,7 +1222,10 @@ extern "C" esi_status_t esi_unet_create(esi_unet_t* out, int32_t H, int32_t W, i
     int64_t aoff = 0;
     for (int i = 0; i < A_COUNT; ++i) {
         Unet::View vw;
-        vw.off = aoff; vw.stride = defs[i][0]; vw.C = defs[i][0]; vw.lvl = defs[i][1];
+        const bool cat = i == A_CAT1 || i == A_CAT2 || i == A_CAT3;
+        vw.off = aoff; vw.C = defs[i][0]; vw.lvl = defs[i][1];
+        vw.stride = cat ? vw.C / 2 : vw.C;
+        vw.hs = cat ? (int64_t)max_batch * (H >> vw.lvl) * (W >> vw.lvl) * (vw.C / 2) : 0;
         aoff += (int64_t)max_batch * (H >> vw.lvl) * (W >> vw.lvl) * vw.C;
         aoff = (aoff + 63) / 64 * 64;
         U->av.push_back(vw);
@@ -1013,9 +1239,10 @@ extern "C" esi_status_t esi_unet_create(esi_unet_t* out, int32_t H, int32_t W, i
         return fail_oom();
     for (Layer& Ly : U->L) {
         const int cpad = Ly.cin < 16 ? 16 : Ly.cin;
-        const int64_t nf = Ly.kind == 0 ? (int64_t)9 * Ly.cout * cpad : Ly.nw;
+        const int64_t nf = Ly.kind == 0 ? frag_elems(Ly.cout, cpad) : Ly.kind == 1 ? convT_frag_elems(Ly.cin, Ly.cout)
+                                                                            : Ly.nw;
         if (hipMalloc(&Ly.wf, nf * 2) != hipSuccess) return fail_oom();
-        if (Ly.kind == 0 && hipMalloc(&Ly.wb, (int64_t)9 * Ly.cin * Ly.cout * 2) != hipSuccess) return fail_oom();
+        if (Ly.kind == 0 && hipMalloc(&Ly.wb, frag_elems(cpad, Ly.cout) * 2) != hipSuccess) return fail_oom();
         if (Ly.kind == 1 && hipMalloc(&Ly.wb, Ly.nw * 2) != hipSuccess) return fail_oom();
     }
     // zero everything so unused padding channels never hold garbage

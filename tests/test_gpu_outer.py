@@ -191,6 +191,9 @@ def test_invert_argument_errors(esi):
                 dict(armijo_c1=1.5), dict(beta_rule=5)]:
         with pytest.raises(esi.EsiError):
             plan.invert(flat, vel, outer_iters=1, **bad)
-    with pytest.raises(esi.EsiError):
-        plan.set_beta(-1.0)
+    # any finite beta is accepted (a negative one makes the normal operator
+    # indefinite, which CG reports as a breakdown); a non-finite one is not
+    for beta in (float("nan"), float("inf")):
+        with pytest.raises(esi.EsiError):
+            plan.set_beta(beta)
     plan.close()
