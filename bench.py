@@ -220,6 +220,33 @@ def unet_flops(H: int, W: int) -> int:
     return 2 * macs
 
 
+def unet_roofline_us(H: int, W: int, nb: int, peak_tflops: float = 2500.0, peak_gbs: float = 8000.0) -> float:
+    """The network's own ceiling for one forward pass on nb H x W images, in
+    microseconds: the sum over its kernels of the larger of the FLOPs at the
+    bf16 MFMA peak and the minimum HBM bytes at the HBM peak.  Minimum bytes:
+    each input read once and each output written once, bf16 activations (the
+    first layer's 3 channels stored as 16), float32 network input and output;
+    the input conversion and the three poolings included."""
+    from paper_2211_06300_amd import unet_layout
+    lvl = {"c1a": 0, "c1b": 0, "c2a": 1, "c2b": 1, "c3a": 2, "c3b": 2, "c4a": 3, "c4b": 3, "u3": 3,
+           "d3a": 2, "d3b": 2, "u2": 2, "d2a": 1, "d2b": 1, "u1": 1, "d1a": 0, "d1b": 0, "out": 0}
+
+    def px(level):
+        return nb * (H >> level) * (W >> level)
+
+    items = [(0.0, (3 * 4 + 16 * 2) * px(0))]                       # input conversion
+    items += [(0.0, c * 2 * px(l) + c * 2 * px(l + 1)) for l, c in ((0, 16), (1, 32), (2, 64))]   # pooling
+    for name, kind, ci, co in unet_layout.LAYERS:
+        l = lvl[name]
+        if kind == "c3":
+            items.append((2.0 * 9 * ci * co * px(l), ((16 if ci < 16 else ci) + co) * 2 * px(l)))
+        elif kind == "t2":
+            items.append((2.0 * 4 * ci * co * px(l), ci * 2 * px(l) + co * 2 * px(l - 1)))
+        else:
+            items.append((2.0 * ci * co * px(l), (ci * 2 + 4) * px(l)))
+    return sum(max(f / (peak_tflops * 1e6), b / (peak_gbs * 1e3)) for f, b in items)
+
+
 def solver_comparison(args, torch, dev):
     """Plain CG vs flexible CG (analytic scale, learned correction) to a
     relative residual of 1e-3 on held-out models, and the network's forward
@@ -275,9 +302,12 @@ def solver_comparison(args, torch, dev):
     net.close()
     flops = unet_flops(H, W) * nb
     tfs = flops / (ms * 1e-3) / 1e12
+    own = unet_roofline_us(H, W, nb)
     out["network_forward"] = {"images": nb, "image": f"{W}x{H}", "ms": round(ms, 3),
                               "tflops": round(tfs, 2), "bound": "mfma", "peak_tflops": 2500.0,
-                              "frac": round(tfs / 2500.0, 4), "dtype": "bf16 (fp32 accumulate)"}
+                              "frac": round(tfs / 2500.0, 4), "dtype": "bf16 (fp32 accumulate)",
+                              "own_roofline_ms": round(own / 1e3, 4),
+                              "frac_of_own_roofline": round(own / 1e3 / ms, 4)}
     return out
 
 

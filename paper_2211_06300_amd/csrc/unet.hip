@@ -4,11 +4,13 @@
 // its CG open (Sec. 4.2 and Sec. 6: fewer inner iterations need an efficient
 // preconditioner); the network, its loss and its use are this library's.
 //
-// Activations are NHWC bfloat16 (channels contiguous, 8-byte aligned groups of
-// four).  A decoder level's concatenation [upsampled, skip] is one buffer: the
-// transposed convolution writes channels [0, ch) and the encoder's second
-// convolution writes its output straight into [ch, 2ch), so the skip costs
-// no copy.
+// Activations are NHWC bfloat16 (channels contiguous, 16-byte aligned groups
+// of eight).  A decoder level's concatenation [upsampled, skip] is one buffer
+// of two planar halves, each a dense NHWC tensor of ch channels: the
+// transposed convolution writes the first, the encoder's second convolution
+// writes its output straight into the second, and the decoder's first
+// convolution reads the pair as 2 ch channels.  The skip costs no copy, and
+// no kernel writes part of another's cache lines.
 //
 // 3x3 convolutions (forward and data gradient) are implicit GEMMs on
 // v_mfma_f32_16x16x32_bf16: D[cout][pixel] = sum_{tap, ci} W[tap][cout][ci]
@@ -16,8 +18,9 @@
 // nine taps, and the weights packed in the instruction's operand order.  A
 // lane stores four consecutive output channels of one pixel (8 bytes).  The
 // data gradient is the same kernel with taps reversed and weights transposed.
-// Transposed convolutions use v_mfma_f32_16x16x16_bf16 with operands loaded
-// straight from memory (each input pixel is read once).  The weight gradient
+// Transposed convolutions use the same instruction with operands loaded
+// straight from memory (each input pixel is read once); their data gradient
+// and the weight gradients use v_mfma_f32_16x16x16_bf16.  The weight gradient
 // is a GEMM over pixels (split into fixed chunks, partials summed in a fixed
 // order).
 #include <cmath>

@@ -89,3 +89,14 @@ def test_roofline_object():
     assert r["achieved"] == 8000.0 and r["frac"] == 1.0 and r["hbm_frac_counted"] == 0.75
     assert r["peak_measured"] == 5000.0 and r["frac_of_measured"] == 1.6
     assert bench.roofline("k", 8e9, 1000.0, None, None)["hbm_frac_counted"] is None
+
+
+def test_unet_roofline():
+    """The network's own ceiling: at least the FLOPs at the bf16 peak and the
+    bytes of the full-resolution layers at the HBM peak; linear in the batch."""
+    import bench
+    one = bench.unet_roofline_us(408, 808, 1)
+    assert abs(bench.unet_roofline_us(408, 808, 8) - 8 * one) < 1e-6 * one
+    assert one * 1e-6 >= bench.unet_flops(408, 808) / 2.5e15
+    # c1b alone: 16 channels in and out at 2 bytes, 808 x 408 pixels, at 8 TB/s
+    assert one >= (16 + 16) * 2 * 808 * 408 / 8e12 * 1e6
