@@ -99,3 +99,24 @@ def test_unet_loss_weights(esi):
     assert abs(L1 - L2) <= 1e-6 * abs(L1)
     assert _rel(g2.cpu().numpy(), g1.cpu().numpy()) < 1e-6
     net.close()
+
+
+def test_unet_batch_equals_single_images(esi):
+    """At the solver's image size (408 x 808) a batch of 8 runs each workgroup
+    of the persistent convolution kernels over several tiles (5304 full-
+    resolution tiles against at most 1024 resident workgroups); one image alone
+    fits in one pass.  A tile's arithmetic does not depend on which workgroup
+    takes it, so every image of the batch matches its own single-image forward
+    bit for bit."""
+    H, W, B = 408, 808, 8
+    rng = np.random.default_rng(21)
+    theta = inputs.he_init(ounet.fan_segments(), 21)
+    x = torch.from_numpy(rng.standard_normal((B, 3, H, W)).astype(np.float32)).to(DEV)
+    net = esi.Unet(H, W, B)
+    net.set_params(torch.from_numpy(theta).to(DEV))
+    ob = net.forward(x).clone()
+    assert torch.isfinite(ob).all()
+    for i in range(B):
+        oi = net.forward(x[i:i + 1].contiguous())
+        assert torch.equal(ob[i], oi[0]), i
+    net.close()
