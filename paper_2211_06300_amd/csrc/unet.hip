@@ -72,8 +72,8 @@ static uint16_t f2bf_host(float f) {
 // l / 16, for row (A) or pixel (B) l % 16; A is packed in that order by
 // k_pack_frag, so a lane's weights are one coalesced 16-byte load.
 //
-// Workgroup: 4 waves, RPW output rows each, 64 pixels (4 groups of 16) x
-// 16 CB output channels.  Per chunk of CK input channels the (4 RPW + 2) x 66
+// Workgroup: NWV waves, RPW output rows each, 64 pixels (4 groups of 16) x
+// 16 CB output channels.  Per chunk of CK input channels the (NWV RPW + 2) x 66
 // input tile and the chunk's weight operands are staged in LDS once; every
 // tap then reads its shifted operands from there.  (Padding the pixel stride
 // by 8 or 16 elements measured 1.5-4 % slower: the smaller tile keeps more
@@ -86,29 +86,30 @@ static uint16_t f2bf_host(float f) {
 constexpr int frag_ck(int K) { return K % 32 == 0 ? 32 : 16; }
 constexpr int frag_nkb(int ck) { return ck == 32 ? 9 : 5; }
 
-template <int CB, int RPW, int CK>
+template <int CB, int RPW, int CK, int NWV>
 struct Conv3Tile {
+    static constexpr int NTW = 64 * NWV;                  // threads of a workgroup
+    static constexpr int ROWS = NWV * RPW;                // output rows of a tile
     static constexpr int NKB = frag_nkb(CK);
-    static constexpr int TR = 4 * RPW + 2, TC = 66, PS = CK, SUB = CK / 8;
-    static constexpr int NQ = TR * TC * SUB, NL = (NQ + NT - 1) / NT;   // 16-byte pieces of a tile, per thread
-    static constexpr int NWQ = NKB * CB * 64, NWL = (NWQ + NT - 1) / NT;  // and of a chunk's weights
+    static constexpr int TR = ROWS + 2, TC = 66, PS = CK, SUB = CK / 8;
+    static constexpr int NQ = TR * TC * SUB, NL = (NQ + NTW - 1) / NTW;   // 16-byte pieces of a tile, per thread
+    static constexpr int NWQ = NKB * CB * 64, NWL = (NWQ + NTW - 1) / NTW;  // and of a chunk's weights
 };
 
-template <int CB, int RPW, int CK>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_conv3(
+template <int CB, int RPW, int CK, int NWV>
+__global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2))) void k_conv3(
     const bf16_t* __restrict__ X, int sx, int64_t xhs, int xsplit, int K, const bf16_t* __restrict__ Af, int ncb,
     const float* __restrict__ bias, bf16_t* __restrict__ Y, int sy, int64_t yhs, int ysplit, int M, int H, int W,
     int N, int relu) {
-    using T = Conv3Tile<CB, RPW, CK>;
+    using T = Conv3Tile<CB, RPW, CK, NWV>;
     __shared__ __align__(16) bf16_t xs[T::TR * T::TC * T::PS];
     __shared__ __align__(16) bf16_t ws[T::NWQ * 8];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int jl = lane & 15, g = lane >> 4;
     const int ncog = M / (16 * CB), nchunk = K / CK;
-    const int ntx = (W + 63) / 64, nty = (H + 4 * RPW - 1) / (4 * RPW);
+    const int ntx = (W + 63) / 64, nty = (H + T::ROWS - 1) / T::ROWS;
     const int ntiles = ntx * nty * N * ncog;
-    // a contiguous run of tiles per workgroup, rows fastest: the halo rows of
-    // a tile were read by the same workgroup (same XCD, same L2) one tile ago
+    // tiles b, b + gridDim.x, ... of this workgroup b
     const int nmine = blockIdx.x < ntiles ? (ntiles - 1 - (int)blockIdx.x) / (int)gridDim.x + 1 : 0;
     const int nsteps = nmine * nchunk;
 
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
         const int t = (int)blockIdx.x + (step / nchunk) * (int)gridDim.x;
         chunk = step % nchunk;
         x0 = (t % ntx) * 64;
-        y0 = ((t / ntx) % nty) * 4 * RPW;
+        y0 = ((t / ntx) % nty) * T::ROWS;
         const int z = t / (ntx * nty);
         n = z / ncog;
         cbg = z % ncog;
@@ -129,7 +130,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
         const bf16_t* Xn = X + (int64_t)n * H * W * sx;
 #pragma unroll
         for (int l = 0; l < T::NL; ++l) {
-            const int q = threadIdx.x + l * NT;
+            const int q = threadIdx.x + l * T::NTW;
             const int sub = q % T::SUB, px = (q / T::SUB) % T::TC, row = q / (T::SUB * T::TC);
             const int yy = y0 - 1 + row, xx = x0 - 1 + px;
             const int ch = chunk * CK + sub * 8;             // channels at or past xsplit: second half
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
         // the workgroup's weight operands of the chunk: [kb][c][lane][8]
 #pragma unroll
         for (int l = 0; l < T::NWL; ++l) {
-            const int q = threadIdx.x + l * NT;
+            const int q = threadIdx.x + l * T::NTW;
             const int kbc = q / 64, kb = kbc / CB, c = kbc % CB;
             sw[l] = uint4{0u, 0u, 0u, 0u};
             if (q < T::NWQ)
@@ -163,13 +164,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
         if (step) __syncthreads();   // every wave is done reading the previous step's LDS
 #pragma unroll
         for (int l = 0; l < T::NL; ++l) {
-            const int q = threadIdx.x + l * NT;
+            const int q = threadIdx.x + l * T::NTW;
             const int sub = q % T::SUB, px = (q / T::SUB) % T::TC, row = q / (T::SUB * T::TC);
             if (q < T::NQ) *reinterpret_cast<uint4*>(xs + (row * T::TC + px) * T::PS + sub * 8) = st[l];
         }
 #pragma unroll
         for (int l = 0; l < T::NWL; ++l) {
-            const int q = threadIdx.x + l * NT;
+            const int q = threadIdx.x + l * T::NTW;
             if (q < T::NWQ) *reinterpret_cast<uint4*>(ws + q * 8) = sw[l];
         }
         __syncthreads();
@@ -891,7 +892,11 @@ struct Ctx {
     int w(int lvl) const { return U->W >> lvl; }
 };
 
-template <int CB, int RPW, int CK>
+// Eight waves of one output row each: a chunk's weight operands, staged once
+// per workgroup, feed twice the MFMAs of a four-wave workgroup (0.68 against
+// 0.70 ms for the network forward on 8 images of 408 x 808; two rows per wave
+// or sixteen waves were slower, the latter spilling).
+template <int CB, int RPW, int CK, int NWV = 8>
 void launch_conv3(const Ctx& c, const Tv& X, int K, const bf16_t* Af, const float* bias, const Tv& Y, int M, int H,
                   int W, bool relu) {
     // persistent grid: as many workgroups as the device holds at once
@@ -900,30 +905,15 @@ void launch_conv3(const Ctx& c, const Tv& X, int K, const bf16_t* Af, const floa
         int per_cu = 0, cus = 0, dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv3<CB, RPW, CK>, NT, 0) != hipSuccess)
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv3<CB, RPW, CK, NWV>, 64 * NWV, 0) != hipSuccess)
             per_cu = 1, cus = 256;
         resident = std::max(1, per_cu) * std::max(1, cus);
     }
-    const int64_t ntiles = (int64_t)((W + 63) / 64) * ((H + 4 * RPW - 1) / (4 * RPW)) * c.N * (M / (16 * CB));
+    const int rows = NWV * RPW;
+    const int64_t ntiles = (int64_t)((W + 63) / 64) * ((H + rows - 1) / rows) * c.N * (M / (16 * CB));
     const int grid = (int)std::min<int64_t>(ntiles, resident);
-    hipLaunchKernelGGL((k_conv3<CB, RPW, CK>), dim3(grid), dim3(NT), 0, c.U->stream, X.p, X.s, X.hs, X.split, K, Af,
+    hipLaunchKernelGGL((k_conv3<CB, RPW, CK, NWV>), dim3(grid), dim3(64 * NWV), 0, c.U->stream, X.p, X.s, X.hs, X.split, K, Af,
                        (M + 15) / 16, bias, Y.p, Y.s, Y.hs, Y.split, M, H, W, c.N, relu ? 1 : 0);
-}
-
-template <int CB, int CK>
-void launch_conv3_rows(const Ctx& c, const Tv& X, int K, const bf16_t* Af, const float* bias, const Tv& Y, int M,
-                       int H, int W, bool relu) {
-    // two output rows per wave (each weight operand feeds twice the MFMAs)
-    // where there are tiles enough; not with 64 output channels, whose
-    // accumulators leave no registers for the loads in flight
-    const int64_t tiles2 = (int64_t)((W + 63) / 64) * ((H + 7) / 8) * c.N * (M / (16 * CB));
-    if constexpr (CB <= 2) {
-        if (tiles2 >= 1024) {
-            launch_conv3<CB, 2, CK>(c, X, K, Af, bias, Y, M, H, W, relu);
-            return;
-        }
-    }
-    launch_conv3<CB, 1, CK>(c, X, K, Af, bias, Y, M, H, W, relu);
 }
 
 // K input channels (Cin, or Cout for the data gradient) to M outputs
@@ -936,13 +926,13 @@ esi_status_t conv3(const Ctx& c, const Tv& X, int K, int layer, bool bwd, const 
     if (K % 16 || M % 16) return fail(ESI_ERR_SHAPE, "3x3 convolution channels must be multiples of 16");
     const int cb = M >= 64 ? 4 : M / 16;
     if (frag_ck(K) == 32) {
-        if (cb == 4) launch_conv3_rows<4, 32>(c, X, K, Af, bias, Y, M, H, W, relu);
-        else if (cb == 2) launch_conv3_rows<2, 32>(c, X, K, Af, bias, Y, M, H, W, relu);
-        else launch_conv3_rows<1, 32>(c, X, K, Af, bias, Y, M, H, W, relu);
+        if (cb == 4) launch_conv3<4, 1, 32>(c, X, K, Af, bias, Y, M, H, W, relu);
+        else if (cb == 2) launch_conv3<2, 1, 32>(c, X, K, Af, bias, Y, M, H, W, relu);
+        else launch_conv3<1, 1, 32>(c, X, K, Af, bias, Y, M, H, W, relu);
     } else {
-        if (cb == 4) launch_conv3_rows<4, 16>(c, X, K, Af, bias, Y, M, H, W, relu);
-        else if (cb == 2) launch_conv3_rows<2, 16>(c, X, K, Af, bias, Y, M, H, W, relu);
-        else launch_conv3_rows<1, 16>(c, X, K, Af, bias, Y, M, H, W, relu);
+        if (cb == 4) launch_conv3<4, 1, 16>(c, X, K, Af, bias, Y, M, H, W, relu);
+        else if (cb == 2) launch_conv3<2, 1, 16>(c, X, K, Af, bias, Y, M, H, W, relu);
+        else launch_conv3<1, 1, 16>(c, X, K, Af, bias, Y, M, H, W, relu);
     }
     ESI_HIP_TRY(hipGetLastError());
     return ESI_OK;

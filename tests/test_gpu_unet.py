@@ -104,7 +104,7 @@ def test_unet_loss_weights(esi):
 def test_unet_batch_equals_single_images(esi):
     """At the solver's image size (408 x 808) a batch of 8 runs each workgroup
     of the persistent convolution kernels over several tiles (5304 full-
-    resolution tiles against at most 1024 resident workgroups); one image alone
+    resolution tiles, several per resident workgroup); one image alone nearly
     fits in one pass.  A tile's arithmetic does not depend on which workgroup
     takes it, so every image of the batch matches its own single-image forward
     bit for bit."""
