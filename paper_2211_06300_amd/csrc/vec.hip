@@ -352,7 +352,11 @@ esi_status_t launch_dot(Plan* P, const float* x, const float* y, int nshots, int
 
 esi_status_t launch_axpy_flag(Plan* P, float* x, const float* p, const double* alpha,
                               const int* flag, int which, int nshots, int64_t len) {
-    const int g = (int)std::min<int64_t>(std::max<int64_t>(1, (len + NT - 1) / NT), 2048);
+    // about 8192 workgroups over all shots: enough to stream the shots that
+    // do update, few enough that the launch costs little when none does
+    // (most iterations: the blocks of the other shots return at once)
+    const int per = std::max(64, 8192 / std::max(1, nshots));
+    const int g = (int)std::min<int64_t>(std::max<int64_t>(1, (len + NT - 1) / NT), per);
     hipLaunchKernelGGL(k_axpy_flag, dim3(g, nshots), dim3(NT), 0, P->stream, x, p, alpha, flag, which,
                        len);
     ESI_HIP_TRY(hipGetLastError());
