@@ -47,6 +47,7 @@ DENSE_BYTES = {2: 4, 4: 20, 32: 4, 64: 8, 128: 0, 256: 4, 512: 4}
 
 TWO_STEP = 1 << 15
 RUPD = 1 << 14
+CORR = 1 << 9
 VARIANT_MASK = (1 << 15) - 1
 TILE_2D = {2: "56x32", 3: "56x24", 4: "56x40"}
 
@@ -625,6 +626,8 @@ def diff3d_run(args, torch, dev, peak_measured=None):
     two = bool(rec["flags"] & TWO_STEP)
     traffic = measured_traffic(rec["flags"], spl, TRAFFIC_FILE_3D, KERNEL_SOURCES_3D, ndim=3)
     kern = ("k_step3d_t2" if two else "k_step3d") + f"<{name}>"
+    if not two and rec["flags"] & CORR:   # one-step correlating launches run in pairs
+        kern += " paired with k_step3d<INJ>"
     return {"workload": f"diff3d-{cfg.nx}x{cfg.ny}x{cfg.nz}-{cfg.nshots}shots", "nt": cfg.nt,
             "checkpoint_every": K, "propagations": 3, "seconds": round(wall, 3),
             "launch_shape": tune_report(esi, tuned, table, esi.LAUNCH_NAMES_3D),

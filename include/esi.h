@@ -510,35 +510,39 @@ esi_status_t esi_grad_velocity(esi_plan_t plan, const float* vel, const float* g
 esi_status_t esi_plan_set_time_block(esi_plan_t plan, int32_t steps);
 
 /*
- * Launch shapes of the 2D time loops, the autotuner's candidates:
- *   ESI_LAUNCH_ONE_STEP (1): one time step per launch on 64 x 32 tiles;
+ * Launch shapes of the time loops, the autotuner's candidates:
+ *   ESI_LAUNCH_ONE_STEP (1): one time step per launch (2D: 64 x 32 tiles;
+ *   3D: 64 x 16 columns, 32-plane chunks);
  *   ESI_LAUNCH_TWO_STEP_32 (2, default), _24 (3), _40 (4): two time steps per
- *   launch on 56-column tiles of 32, 24 or 40 rows (the wavefield state
- *   crosses HBM once per two steps; the first step runs on the tile grown by
- *   one stencil radius).
+ *   launch on 56-column tiles of 32, 24 or 40 rows (2D), or on 56 x 24 columns
+ *   and 64-plane chunks (3D, shape 2 only); the wavefield state crosses HBM
+ *   once per two steps and the first step runs on the tile grown by one
+ *   stencil radius.
  * Every shape gives the same wavefield, data, dense outputs and gradients bit
  * for bit; float64 dot products sum their per-tile partials over a different
  * tiling, so CG results agree to rounding.  Time-loop variants the shapes of
- * 24 and 40 rows do not cover run on 32-row tiles.  3D plans run shape 1.
+ * 24 and 40 rows do not cover run on 32-row tiles.
  */
 enum { ESI_LAUNCH_ONE_STEP = 1, ESI_LAUNCH_TWO_STEP_32 = 2, ESI_LAUNCH_TWO_STEP_24 = 3,
        ESI_LAUNCH_TWO_STEP_40 = 4 };
 
-/* Set the launch shapes of forward-type and adjoint-type loops (1 .. 4; 3D: 1).
- * ESI_ERR_ARG otherwise. */
+/* Set the launch shapes of forward-type and adjoint-type loops (1 .. 4; 3D:
+ * 1 or 2).  ESI_ERR_ARG otherwise. */
 esi_status_t esi_plan_set_launch_shape(esi_plan_t plan, int32_t forward, int32_t adjoint);
 
 /*
  * Autotuner of the launch shape.  For the plan's grid and a batch of nshots
- * shots it times every candidate shape (2D: the four above; 3D: one), after a
+ * shots it times every candidate shape (2D: the four above; 3D: 1 and 2), after a
  * warm-up run of each, with the plan's hipEvent profiling, and keeps the
  * fastest for forward-type and for adjoint-type loops separately.
  *   p, Ap device [nshots][nt][phys] (contents irrelevant; Ap is overwritten):
  *     the candidates are timed on one application of the normal operator;
  *   p = Ap = NULL: on a point-source forward pass over the first min(nt, 64)
- *     steps and an adjoint pass injecting receiver data over the last ones
- *     (propagation alone, for batches whose wavefield-sized vectors are too
- *     large to allocate, e.g. many shots of long records).
+ *     steps and a gradient's adjoint pass over the last ones, injecting
+ *     receiver data and correlating with a two-slot (dA/dm)u store (for
+ *     batches whose wavefield-sized vectors are too large to allocate, e.g.
+ *     the gradients of many shots of long records; the store and the per-shot
+ *     images are plan scratch, 3 x nshots x physical cells floats).
  * Choices and timings are cached per process for (ndim, padded shape,
  * nshots, nt, the shots' apertures, timing kind); force != 0 measures again.
  * choice: host int[2] out (forward, adjoint launch shape) or NULL.
@@ -549,7 +553,7 @@ esi_status_t esi_plan_autotune(esi_plan_t plan, int32_t shot0, int32_t nshots, c
 /* The candidate table of the plan's last esi_plan_autotune call (also when it
  * came from the cache): count rows (host out); for i < min(cap, count) the
  * shape and the milliseconds of its forward-type and adjoint-type loops (host
- * arrays [cap] out).  count = 0 for 3D plans. */
+ * arrays [cap] out). */
 esi_status_t esi_plan_tune_table(esi_plan_t plan, int32_t cap, int32_t* count, int32_t* shape,
                                  double* fwd_ms, double* adj_ms);
 

@@ -210,7 +210,30 @@ esi_status_t adjoint_loop(Plan* P, StepArgs a, unsigned flags, float* ring, int*
     StepArgs b = a;
     if (t2) apply_lists(b, L2);
     a.dir = b.dir = -1;
+    // One-step correlating launches in 3D go in pairs: the first without the
+    // correlation, the second adding both steps' products in the order a
+    // two-step launch chains them, so the accumulator crosses HBM once per
+    // pair and the bits are those of unpaired launches.
+    const bool pair = !t2 && (flags & F_CORR) && P->ndim == 3;
     for (int j = j1 - 1; j >= j0;) {
+        if (pair && j - 1 >= j0) {
+            a.step = j;
+            set_fields(P, a, ring, *cs);
+            ESI_TRY(launch_step(P, flags & ~F_CORR, a, LS_ONE));
+            *cs ^= 1;
+            a.step = j - 1;
+            set_fields(P, a, ring, *cs);
+            a.store_slot = K > 0 ? (j - 1) % K : j - 1;
+            a.store_slot2 = K > 0 ? j % K : j;
+            a.corr_pair = 1;
+            const esi_status_t st = launch_step(P, flags, a, LS_ONE);
+            a.corr_pair = 0;
+            ESI_TRY(st);
+            p1.launches += 2;
+            *cs ^= 1;
+            j -= 2;
+            continue;
+        }
         const bool two = t2 && j - 1 >= j0;
         StepArgs& c = two ? b : a;
         c.step = j;
@@ -1170,7 +1193,8 @@ int64_t window_hash(Plan* P, int shot0, int ns) {
 
 // One timing run of the forward-type and adjoint-type loops of candidate
 // `shape`: the normal operator on p (probe = false), or a point-source forward
-// pass of nprobe steps and an adjoint pass injecting its data (probe = true).
+// pass of nprobe steps and a gradient's adjoint pass, injecting its data and
+// correlating with a two-slot store (probe = true).
 esi_status_t tune_run(Plan* P, int shot0, int ns, const float* p, float* Ap, bool probe, int nprobe,
                       const TileLists* L) {
     if (!probe) return do_normal(P, shot0, ns, p, Ap, L, nullptr, false, nullptr, nullptr, nullptr, nullptr, nullptr);
@@ -1183,8 +1207,11 @@ esi_status_t tune_run(Plan* P, int shot0, int ns, const float* p, float* Ap, boo
     ESI_TRY(ring_for(P, &P->ring, &P->ring_cap, ns));
     StepArgs b = base_args(P, L, shot0, ns);
     b.inj_data = P->dscr;
+    b.store = P->store;
+    b.store_stride = 2 * P->nphys;
+    b.gacc = P->gshot;
     cs = 0;
-    return adjoint_loop(P, b, F_INJ, P->ring, &cs, P->nt - nprobe, P->nt);
+    return adjoint_loop(P, b, F_INJ | F_CORR, P->ring, &cs, P->nt - nprobe, P->nt, 2);
 }
 
 }  // namespace
@@ -1221,6 +1248,11 @@ extern "C" esi_status_t esi_plan_autotune(esi_plan_t plan, int32_t shot0, int32_
         ESI_TRY(grow_t(&P->dscr2, &P->dscr2_cap, (int64_t)ns * P->nt, P->stream));
         ESI_TRY(launch_fill(P, P->dscr2, (int64_t)ns * P->nt, 0.f));
         ESI_TRY(launch_fill(P, P->dscr, std::max<int64_t>(data_len(P, shot0, ns), 1), 0.f));
+        // the correlation's two-slot store and per-shot images (gradient scratch)
+        ESI_TRY(grow_t(&P->store, &P->store_cap, (int64_t)ns * 2 * P->nphys, P->stream));
+        ESI_TRY(grow_t(&P->gshot, &P->gshot_cap, (int64_t)ns * P->nphys, P->stream));
+        ESI_TRY(launch_fill(P, P->store, (int64_t)ns * 2 * P->nphys, 0.f));
+        ESI_TRY(launch_fill(P, P->gshot, (int64_t)ns * P->nphys, 0.f));
     }
     // keep the caller's profile aside and time each candidate on its own
     const bool prof = P->prof_on;

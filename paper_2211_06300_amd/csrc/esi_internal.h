@@ -273,7 +273,11 @@ struct StepArgs {
     float* store;            // (dA/dm)u store [nshots][slots][phys]
     int64_t store_stride;    // floats per shot in store
     int store_slot;          // slot of this step
-    int store_slot2;         // slot of the second step of a two-step launch
+    int store_slot2;         // slot of the second step of a two-step launch; with
+                             // corr_pair, slot of the previous step
+    int corr_pair;           // one-step CORR launch (3D): also add the previous
+                             // step's product, its input field times slot
+                             // store_slot2, before this step's
     float* src_rec;          // [nshots][nt] adjoint field at the source cell
     // DTFT at dft_nf frequencies; frequency vectors [nshots][dft_nf][phys] of
     // (re, im) pairs; dft_tw[n][m] = (cos w_m t_n, sin w_m t_n)

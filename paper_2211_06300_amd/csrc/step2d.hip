@@ -825,7 +825,10 @@ void k_step2d_t2(const StepArgs a) {
         for (int i = 0; i < B_RZ; ++i) stB[i] = at(oB.stin, pi[i]);
     }
     // the first step's stored (dA/dm)u (CORR) or dense source (PENALTY) on the tile
-    float chA[(CHAIN_CORR || CHAIN_PEN) ? B_RZ : 1];
+    // and the accumulator, read here so that its latency overlaps the stencil
+    // (in the variants with a dense output too it would spill: read in place)
+    constexpr bool G_EARLY = (CHAIN_CORR || CHAIN_PEN) && (FL & F_OUT) == 0;
+    float chA[(CHAIN_CORR || CHAIN_PEN) ? B_RZ : 1], gv[G_EARLY ? B_RZ : 1];
     if constexpr (CHAIN_CORR) {
 #pragma unroll
         for (int i = 0; i < B_RZ; ++i) chA[i] = at(oA.stin, pi[i]);
@@ -834,6 +837,10 @@ void k_step2d_t2(const StepArgs a) {
         const float* __restrict__ q = a.dsrc + blk_off(a, s, tA, vA);
 #pragma unroll
         for (int i = 0; i < B_RZ; ++i) chA[i] = ph[i] ? at(q, pi[i]) : 0.f;
+    }
+    if constexpr (G_EARLY) {
+#pragma unroll
+        for (int i = 0; i < B_RZ; ++i) gv[i] = at(oB.gacc, pi[i]);
     }
 
     float colB[B_RZ + 2 * HALO];
@@ -880,7 +887,7 @@ void k_step2d_t2(const StepArgs a) {
         cell_outputs<FL_A>(a, oB, pi[i], un, qd, lq, c2v[i], pvB[i], stB[i], rB[i], wb, acc);
         if constexpr (CHAIN_CORR) {
             const float uA = U1[(zl + HALO) * A_W + lc + HALO];
-            const float gA = fmaf(uA, chA[i], at(oB.gacc, pi[i]));
+            const float gA = fmaf(uA, chA[i], G_EARLY ? gv[G_EARLY ? i : 0] : at(oB.gacc, pi[i]));
             at(oB.gacc, pi[i]) = fmaf(un, stB[i], gA);
         }
         if constexpr (CHAIN_PEN) {
@@ -891,7 +898,7 @@ void k_step2d_t2(const StepArgs a) {
             }
             const float lapA = lap_lds(a, U0 + (zl + 2 * HALO) * U0W + lc + 2 * HALO, U0W);
             const float lqA = fmaf(a.dx2, qa, lapA);
-            const float gA = fmaf(wb * chA[i], c2v[i] * a.inv_dt2 * lqA, at(oB.gacc, pi[i]));
+            const float gA = fmaf(wb * chA[i], c2v[i] * a.inv_dt2 * lqA, G_EARLY ? gv[G_EARLY ? i : 0] : at(oB.gacc, pi[i]));
             at(oB.gacc, pi[i]) = fmaf(wb * qd, c2v[i] * a.inv_dt2 * lq, gA);
             acc += (double)(wb * qd) * (double)qd;   // penalty term (kept when a.part is set)
         }

@@ -118,6 +118,10 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
     const float ral = ((FL & F_NORMAL) && (FL & F_RUPD)) ? (float)a.cg_alpha[s] : 0.f;
     float* gacc = (FL & (F_PENALTY | F_CORR)) ? a.gacc + (int64_t)s * a.nphys : nullptr;
     float* store = (FL & (F_STORE | F_CORR)) ? a.store + s * a.store_stride + (int64_t)a.store_slot * a.nphys : nullptr;
+    // paired correlation: this launch also adds the previous step's product,
+    // its input field times store slot store_slot2, first (uniform)
+    const bool pair = (FL & F_CORR) != 0 && a.corr_pair;
+    const float* store_prev = pair ? a.store + s * a.store_stride + (int64_t)a.store_slot2 * a.nphys : nullptr;
     float alp = 0.f, bet = 0.f;
     const float* cgp = nullptr; const float* cgr = nullptr; float* cgpn = nullptr; float* cgx = nullptr;
     if constexpr ((FL & F_CG_FUSE) != 0) {
@@ -210,12 +214,12 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
         const int iz = z - a.nb;
         bool ph[RY];
         uint32_t pi[RY];
-        float q[RY], po[RY], xo[RY], pv[RY], stv[RY], rv[RY];
+        float q[RY], po[RY], xo[RY], pv[RY], stv[RY], rv[RY], gv[RY], stp[RY];
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             ph[r] = xyphys[r] && iz >= 0 && iz < a.nz;
             pi[r] = ph[r] ? (uint32_t)((iz * a.ny + iy[r]) * a.nx + ix) : 0u;
-            q[r] = 0.f; po[r] = 0.f; xo[r] = 0.f; pv[r] = 0.f; stv[r] = 0.f; rv[r] = 0.f;
+            q[r] = 0.f; po[r] = 0.f; xo[r] = 0.f; pv[r] = 0.f; stv[r] = 0.f; rv[r] = 0.f; gv[r] = 0.f; stp[r] = 0.f;
             if constexpr ((FL & F_SRC_DENSE) != 0) {
                 q[r] = ph[r] ? at(dsrc, pi[r]) : 0.f;
                 if constexpr ((FL & F_SCALE) != 0) q[r] = q[r] * at(csc, pi[r]);   // cell-scaled dense source
@@ -227,7 +231,13 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
             }
             if constexpr ((FL & F_NORMAL) != 0) pv[r] = at(dp, pi[r]);
             if constexpr ((FL & F_NORMAL) != 0 && (FL & F_RUPD) != 0) rv[r] = at(rw, pi[r]);
-            if constexpr ((FL & F_CORR) != 0) stv[r] = at(store, pi[r]);
+            // the accumulator is read here, with the other dense loads, so that
+            // its latency overlaps the plane's stencil work
+            if constexpr ((FL & (F_PENALTY | F_CORR)) != 0) gv[r] = at(gacc, pi[r]);
+            if constexpr ((FL & F_CORR) != 0) {
+                stv[r] = at(store, pi[r]);
+                if (pair) stp[r] = at(store_prev, pi[r]);
+            }
         }
         bool inj_here = false;
         if constexpr ((FL & F_INJ) != 0) {
@@ -334,11 +344,15 @@ __global__ __launch_bounds__(NTH) void k_step3d(const StepArgs a) {
                     }
                 }
                 if constexpr ((FL & F_PENALTY) != 0) {
-                    at(gacc, pr) = fmaf(wb * qd, c2v[r] * a.inv_dt2 * lq, at(gacc, pr));
+                    at(gacc, pr) = fmaf(wb * qd, c2v[r] * a.inv_dt2 * lq, gv[r]);
                     acc += (double)(wb * qd) * (double)qd;   // penalty term (kept when a.part is set)
                 }
                 if constexpr ((FL & F_STORE) != 0) at(store, pr) = c2v[r] * a.inv_dt2 * lq;
-                if constexpr ((FL & F_CORR) != 0) at(gacc, pr) = fmaf(un, stv[r], at(gacc, pr));
+                if constexpr ((FL & F_CORR) != 0) {
+                    // the previous step's product first, as a two-step launch chains them
+                    const float g = pair ? fmaf(cv, stp[r], gv[r]) : gv[r];
+                    at(gacc, pr) = fmaf(un, stv[r], g);
+                }
             }
 #pragma unroll
             for (int k = 0; k < 2 * HALO; ++k) w[r][k] = w[r][k + 1];
@@ -394,6 +408,7 @@ esi_status_t launch_step3d(Plan* P, unsigned flags, const StepArgs& a) {
         ESI_CASE(F_SRC_DENSE | F_SCALE | F_GATHER)
         ESI_CASE(F_INJ)
         ESI_CASE(F_INJ | F_OUT)
+        ESI_CASE(F_INJ | F_SRC_REC)
         ESI_CASE(F_INJ | F_NORMAL)
         ESI_CASE(F_INJ | F_NORMAL | F_RUPD)
         ESI_CASE(F_INJ | F_CORR)

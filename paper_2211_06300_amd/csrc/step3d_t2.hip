@@ -279,6 +279,18 @@ __global__ __launch_bounds__(NTH) void k_step3d_t2(const StepArgs a) {
     };
 #pragma unroll
     for (int k = 0; k < PF; ++k) load_plane(zc0 - HALO + k, nw[k], nc[k], nd[k], nh[k]);
+    // c on the block for the second step of iteration ii (plane z2 = zc0 - 8
+    // + ii), issued one iteration ahead (the correlation's loads gain nothing
+    // from that: they stay in their own iteration)
+    float nc2[RPT];
+    auto load_c2 = [&](int ii) {
+        const int zz = zc0 - 2 * HALO + ii;
+        const bool on = ii >= 2 * HALO && ii < nit;   // uniform
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+            nc2[r] = (on && cout[r] && zz < a.nzp) ? at(a.c2, (uint32_t)(zz + GH) * PS + col[r]) : 0.f;
+    };
+    load_c2(0);
 
     double acc = 0.0;
     for (int i = 0; i < nit; ++i) {
@@ -303,7 +315,7 @@ __global__ __launch_bounds__(NTH) void k_step3d_t2(const StepArgs a) {
         const int iz1 = z1 - a.nb, iz2 = z2 - a.nb;
         const bool z1ph = iz1 >= 0 && iz1 < a.nz, z2ph = iz2 >= 0 && iz2 < a.nz;
         float qA[RPT], poA[RPT], xoA[RPT], pvA[RPT], rvA[RPT];
-        float c2B[RPT], qB[RPT], poB[RPT], xoB[RPT], pvB[RPT], rvB[RPT], stA[RPT], stB[RPT];
+        float c2B[RPT], qB[RPT], poB[RPT], xoB[RPT], pvB[RPT], rvB[RPT], stA[RPT], stB[RPT], gB[RPT];
         uint32_t piA[RPT], piB[RPT];
         bool phA[RPT], phB[RPT], oA[RPT];
 #pragma unroll
@@ -315,7 +327,8 @@ __global__ __launch_bounds__(NTH) void k_step3d_t2(const StepArgs a) {
             piB[r] = phB[r] ? (uint32_t)((iz2 * a.ny + iy[r]) * a.nx + ix) : 0u;
             qA[r] = 0.f; poA[r] = 0.f; xoA[r] = 0.f; pvA[r] = 0.f; rvA[r] = 0.f;
             qB[r] = 0.f; poB[r] = 0.f; xoB[r] = 0.f; pvB[r] = 0.f; rvB[r] = 0.f; stA[r] = 0.f; stB[r] = 0.f;
-            c2B[r] = (l2 && cout[r] && z2 < a.nzp) ? at(a.c2, (uint32_t)(z2 + GH) * PS + col[r]) : 0.f;
+            gB[r] = 0.f;
+            c2B[r] = nc2[r];
             if constexpr ((FL & F_SRC_DENSE) != 0) {
                 qA[r] = phA[r] ? at(a.dsrc + voff(a, s, tA), piA[r]) : 0.f;
                 qB[r] = phB[r] ? at(a.dsrc + voff(a, s, tB), piB[r]) : 0.f;
@@ -349,6 +362,9 @@ __global__ __launch_bounds__(NTH) void k_step3d_t2(const StepArgs a) {
                     const float* st = a.store + s * a.store_stride;
                     stA[r] = at(st + (int64_t)a.store_slot * a.nphys, piB[r]);
                     stB[r] = at(st + (int64_t)a.store_slot2 * a.nphys, piB[r]);
+                    // the accumulator with the other dense loads: its latency
+                    // overlaps the first step
+                    gB[r] = at(a.gacc + (int64_t)s * a.nphys, piB[r]);
                 }
             }
         }
@@ -364,6 +380,7 @@ __global__ __launch_bounds__(NTH) void k_step3d_t2(const StepArgs a) {
         }
         if (i + PF < nit)   // uniform over the workgroup
             load_plane(z1 + PF, nw[PF - 1], nc[PF - 1], nd[PF - 1], nh[PF - 1]);
+        load_c2(i + 1);
         // ---- injection planes of this iteration (entries sorted by cell, i.e. by plane)
         bool injA = false, injB = false;
         if constexpr ((FL & F_INJ) != 0) {
@@ -469,7 +486,7 @@ __global__ __launch_bounds__(NTH) void k_step3d_t2(const StepArgs a) {
                 if constexpr ((FL & F_CORR) != 0) {
                     // both steps' products chained, as two one-step launches add them
                     float* g = a.gacc + (int64_t)s * a.nphys;
-                    const float gA = fmaf(w1[r][HALO], stA[r], at(g, piB[r]));
+                    const float gA = fmaf(w1[r][HALO], stA[r], gB[r]);
                     at(g, piB[r]) = fmaf(un, stB[r], gA);
                 }
             }

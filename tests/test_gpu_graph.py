@@ -123,7 +123,7 @@ def test_autotune_choice_and_results(esi):
     assert ch == (best_f, best_a)
     assert plan.autotune() == ch                     # cached
     assert plan.tune_table() == table
-    # the propagation-only timing run: its own cache entry
+    # the propagation-only timing run (forward, and a gradient's adjoint): its own cache entry
     chp = plan.autotune(probe=True)
     assert chp[0] in (1, 2, 3, 4) and chp[1] in (1, 2, 3, 4) and len(plan.tune_table()) == 4
     plan.set_launch_shape(*ch)
@@ -133,4 +133,12 @@ def test_autotune_choice_and_results(esi):
     y0 = plan.forward(w, esi.SRC_POINT).clone()
     plan.set_time_block(1)
     assert torch.equal(plan.forward(w, esi.SRC_POINT), y0)
+    # the probe's correlating adjoint pass uses gradient scratch only: the
+    # checkpoints a forward pass keeps survive it
+    G = torch.from_numpy(inputs.random_field(plan.data_shape(), 47)).to(DEV)
+    plan.forward_ckpt(w, 6)
+    plan.autotune(probe=True, force=True)
+    g1 = plan.gradient(esi.GRAD_SEED_REUSE, w, G, kind=esi.SRC_POINT, ckpt_every=6).clone()
+    g0 = plan.gradient(esi.GRAD_SEED, w, G, kind=esi.SRC_POINT, ckpt_every=6)
+    assert torch.equal(g1, g0)
     plan.close()
