@@ -176,12 +176,12 @@ esi_status_t forward_loop(Plan* P, StepArgs a, unsigned flags, float* ring, int*
         if (ckpt && n % K == 0) {
             const int k = n / K;
             const int64_t cstr = (int64_t)nseg * 2 * P->fsize;   // per-shot checkpoint stride
-            ESI_TRY(launch_copy_shots(P, ckpt + (int64_t)k * 2 * P->fsize, cstr,
-                                      ring + (int64_t)(*cs) * P->fsize, RING * P->fsize, P->fsize,
-                                      a.nshots));
-            ESI_TRY(launch_copy_shots(P, ckpt + (int64_t)k * 2 * P->fsize + P->fsize, cstr,
-                                      ring + (int64_t)(2 + *cs) * P->fsize, RING * P->fsize,
-                                      P->fsize, a.nshots));
+            ESI_TRY(launch_copy_fields(P, ckpt + (int64_t)k * 2 * P->fsize, cstr,
+                                       ring + (int64_t)(*cs) * P->fsize, RING * P->fsize, a.shot0,
+                                       a.nshots));
+            ESI_TRY(launch_copy_fields(P, ckpt + (int64_t)k * 2 * P->fsize + P->fsize, cstr,
+                                       ring + (int64_t)(2 + *cs) * P->fsize, RING * P->fsize, a.shot0,
+                                       a.nshots));
         }
         const bool two = t2 && n + 1 < n1 && !(ckpt && (n + 1) % K == 0);
         StepArgs& c = two ? b : a;
@@ -1013,10 +1013,10 @@ esi_status_t gradient_impl(Plan* P, int32_t shot0, int32_t ns, int32_t mode, int
             const int n0 = k * K, n1 = std::min(nt, n0 + K);
             // restore (u^{n0}, d^{n0}) into slot 0 of the recompute ring
             const int64_t cstr = (int64_t)nseg * 2 * P->fsize;
-            ESI_TRY(launch_copy_shots(P, P->ring2, RING * P->fsize,
-                                      P->ckpt + (int64_t)k * 2 * P->fsize, cstr, P->fsize, ns));
-            ESI_TRY(launch_copy_shots(P, P->ring2 + 2 * P->fsize, RING * P->fsize,
-                                      P->ckpt + (int64_t)k * 2 * P->fsize + P->fsize, cstr, P->fsize, ns));
+            ESI_TRY(launch_copy_fields(P, P->ring2, RING * P->fsize,
+                                       P->ckpt + (int64_t)k * 2 * P->fsize, cstr, shot0, ns));
+            ESI_TRY(launch_copy_fields(P, P->ring2 + 2 * P->fsize, RING * P->fsize,
+                                       P->ckpt + (int64_t)k * 2 * P->fsize + P->fsize, cstr, shot0, ns));
             int rcs = 0;
             ESI_TRY(forward_loop(P, a, srcfl | F_STORE, P->ring2, &rcs, n0, n1, nullptr, K, nseg));
             ESI_TRY(adjoint_loop(P, b, bfl, adj_ring, &acs, n0, n1, K));

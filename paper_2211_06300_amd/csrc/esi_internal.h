@@ -326,6 +326,11 @@ esi_status_t launch_copy(Plan* P, float* dst, const float* src, int64_t n);
 // per shot s < nshots: dst[s * dst_stride + i] = src[s * src_stride + i], i < n
 esi_status_t launch_copy_shots(Plan* P, float* dst, int64_t dst_stride, const float* src,
                                int64_t src_stride, int64_t n, int nshots);
+// One stored field per shot s < nshots (global shot shot0 + s), dst[s * dst_stride
+// + i] = src[s * src_stride + i]: with 2D apertures only the window's cells
+// (with its absorbing layer), the only ones a step ever makes non-zero.
+esi_status_t launch_copy_fields(Plan* P, float* dst, int64_t dst_stride, const float* src, int64_t src_stride,
+                                int shot0, int nshots);
 // r -= alpha_s Np (float32), partial r.r (float64) per block into part;
 // then reduce into out[s].  Vectors are [nshots][len].
 esi_status_t launch_r_update(Plan* P, float* r, const float* Ap, const double* alpha,

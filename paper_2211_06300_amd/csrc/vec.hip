@@ -273,6 +273,23 @@ __global__ void k_copy_shots(float* __restrict__ d, int64_t ds, const float* __r
         d[s * ds + i] = src[s * ss + i];
 }
 
+// grid: (blocks, nshots): the part of shot s's field that a shot with an
+// aperture ever makes non-zero, rows [row0, row0 + nrows) of storage columns
+// [win[2 gs] + clo, win[2 gs + 1] + chi), gs = shot0 + s; the rest of its
+// fields stays zero (no velocity outside the window and its absorbing layer)
+__global__ void k_copy_shots_win(float* __restrict__ d, int64_t ds, const float* __restrict__ src, int64_t ss,
+                                 int XS, int row0, int nrows, const int32_t* __restrict__ win, int shot0,
+                                 int clo, int chi) {
+    const int s = blockIdx.y;
+    const int c0 = win[2 * (shot0 + s)] + clo, w = win[2 * (shot0 + s) + 1] + chi - c0;
+    const int n = nrows * w;
+    for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
+        const int r = i / w;
+        const int64_t o = (int64_t)(row0 + r) * XS + c0 + (i - r * w);
+        d[s * ds + o] = src[s * ss + o];
+    }
+}
+
 __global__ void k_grad_velocity(const float* __restrict__ v, const float* gm, float* gv, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
         const float vi = v[i];
@@ -314,6 +331,19 @@ esi_status_t launch_copy_shots(Plan* P, float* dst, int64_t dst_stride, const fl
     const int g = (int)std::min<int64_t>(std::max<int64_t>(1, (n + NT - 1) / NT), 2048);
     hipLaunchKernelGGL(k_copy_shots, dim3(g, nshots), dim3(NT), 0, P->stream, dst, dst_stride, src,
                        src_stride, n);
+    ESI_HIP_TRY(hipGetLastError());
+    return ESI_OK;
+}
+
+esi_status_t launch_copy_fields(Plan* P, float* dst, int64_t dst_stride, const float* src, int64_t src_stride,
+                                int shot0, int nshots) {
+    if (!P->d_win || P->ndim != 2)
+        return launch_copy_shots(P, dst, dst_stride, src, src_stride, P->fsize, nshots);
+    // padded columns [lo, hi + 2 nb) of the window, storage column = padded + GH
+    const int64_t n = (int64_t)P->nzp * P->nxp;   // bound of a window's cells
+    const int g = (int)std::min<int64_t>(std::max<int64_t>(1, (n + NT - 1) / NT), 2048);
+    hipLaunchKernelGGL(k_copy_shots_win, dim3(g, nshots), dim3(NT), 0, P->stream, dst, dst_stride, src,
+                       src_stride, P->XS, GH, P->nzp, (const int32_t*)P->d_win, shot0, GH, 2 * P->nb + GH);
     ESI_HIP_TRY(hipGetLastError());
     return ESI_OK;
 }
