@@ -371,3 +371,24 @@ def test_3d_deep_forward_matches_oracle(esi):
     out = plan.adjoint(torch.from_numpy(dd).to(DEV)).cpu().numpy()
     for s, ds in enumerate(_split(cfg, dd)):
         assert _rel(out[s], core.adjoint(m, cfg.shot_rec(s), ds.astype(np.float64))) < 1e-5, s
+
+
+def test_3d_autotune_probe(esi):
+    """The autotuner on a 3D plan times one and two steps per launch on its
+    propagation probe (a forward pass, and a gradient's adjoint pass with the
+    correlation over a two-slot store, in paired one-step launches or two-step
+    ones); whatever it picks, the checkpointed gradient keeps its bits."""
+    cfg = _cfg3(nt=41)
+    plan = _plan(esi, cfg)
+    w = torch.from_numpy(np.stack([cfg.wavelet, -0.6 * cfg.wavelet]).astype(np.float32)).to(DEV)
+    dd = torch.from_numpy(inputs.random_field(plan.data_shape(), 53)).to(DEV)
+    g0 = plan.gradient(esi.GRAD_SEED, w, dd, kind=esi.SRC_POINT, ckpt_every=7).clone()
+    ch = plan.autotune(probe=True)
+    table = plan.tune_table()
+    assert ch[0] in (1, 2) and ch[1] in (1, 2)
+    assert [r[0] for r in table] == [1, 2] and all(r[1] > 0 and r[2] > 0 for r in table)
+    assert ch == (min(table, key=lambda r: r[1])[0], min(table, key=lambda r: r[2])[0])
+    plan.forward_ckpt(w, 7)
+    g1 = plan.gradient(esi.GRAD_SEED_REUSE, w, dd, kind=esi.SRC_POINT, ckpt_every=7)
+    assert torch.equal(g1, g0)
+    plan.close()

@@ -130,6 +130,26 @@ def test_windowed_gradient_ckpt(esi):
     plan.close()
 
 
+def test_windowed_checkpoints_shot_range(esi):
+    """Checkpoints of shots with apertures hold each shot's window only: a
+    checkpointed gradient (forward_ckpt then SEED_REUSE, and SEED) of shots
+    [1, 3) equals the same shots' gradient with full storage bit for bit, in
+    both launch shapes."""
+    cfg = _cfg(nt=54)
+    plan = esi.Plan.from_config(cfg, vel=torch.from_numpy(cfg.v_true).to(DEV))
+    w = torch.from_numpy(np.stack([cfg.wavelet, -0.5 * cfg.wavelet]).astype(np.float32)).to(DEV)
+    G = torch.from_numpy(inputs.random_field(plan.data_shape(1, 2), 65)).to(DEV)
+    for tb in (1, 2):
+        plan.set_time_block(tb)
+        full = plan.gradient(esi.GRAD_SEED, w, G, kind=esi.SRC_POINT, shot0=1, nshots=2, ckpt_every=0).clone()
+        ck = plan.gradient(esi.GRAD_SEED, w, G, kind=esi.SRC_POINT, shot0=1, nshots=2, ckpt_every=9).clone()
+        plan.forward_ckpt(w, 9, shot0=1, nshots=2)
+        re = plan.gradient(esi.GRAD_SEED_REUSE, w, G, kind=esi.SRC_POINT, shot0=1, nshots=2, ckpt_every=9)
+        assert torch.equal(ck, full), tb
+        assert torch.equal(re, full), tb
+    plan.close()
+
+
 def test_full_windows_equal_no_windows(esi):
     """Windows that cover the grid give the same bits as a plan without them."""
     cfg = _cfg()
