@@ -285,7 +285,18 @@ def solver_comparison(args, torch, dev):
     if ratios:
         out["learned_speedup_vs_analytic_wall"] = {"min": round(min(ratios), 3), "median": round(float(np.median(ratios)), 3),
                                                    "max": round(max(ratios), 3), "models": len(ratios)}
-    # network forward throughput (batch = 8 images of 408 x 808)
+    out["network_forward"] = network_forward_run(args, torch, dev, theta)
+    return out
+
+
+def network_forward_run(args, torch, dev, theta=None):
+    """The preconditioner network's forward throughput on the MFMA units:
+    8 images of 408 x 808 (the padded 801 x 401 grid), 3 warm-up and 20 timed
+    passes with the trained parameters."""
+    from paper_2211_06300_amd import esi, precond
+    if theta is None:
+        wpath = os.path.join(ROOT, "paper_2211_06300_amd", "weights", "precond_unet.npy")
+        theta = torch.from_numpy(np.load(wpath)).to(dev)
     H, W, nb = precond.pad8(401), precond.pad8(801), 8
     net = esi.Unet(H, W, nb, device=dev)
     net.set_params(theta)
@@ -304,12 +315,11 @@ def solver_comparison(args, torch, dev):
     flops = unet_flops(H, W) * nb
     tfs = flops / (ms * 1e-3) / 1e12
     own = unet_roofline_us(H, W, nb)
-    out["network_forward"] = {"images": nb, "image": f"{W}x{H}", "ms": round(ms, 3),
-                              "tflops": round(tfs, 2), "bound": "mfma", "peak_tflops": 2500.0,
-                              "frac": round(tfs / 2500.0, 4), "dtype": "bf16 (fp32 accumulate)",
-                              "own_roofline_ms": round(own / 1e3, 4),
-                              "frac_of_own_roofline": round(own / 1e3 / ms, 4)}
-    return out
+    return {"images": nb, "image": f"{W}x{H}", "ms": round(ms, 3),
+            "tflops": round(tfs, 2), "bound": "mfma", "peak_tflops": 2500.0,
+            "frac": round(tfs / 2500.0, 4), "dtype": "bf16 (fp32 accumulate)",
+            "own_roofline_ms": round(own / 1e3, 4),
+            "frac_of_own_roofline": round(own / 1e3 / ms, 4)}
 
 
 def batching_run(args, torch, dev, peak_measured=None):
@@ -712,8 +722,8 @@ def main():
     ap.add_argument("--only-3d", action="store_true",
                     help="run the 3D forward modelling alone (--nt3d steps) and print its JSON object")
     ap.add_argument("--only", default="", metavar="LEGS",
-                    help="comma list of legs to run alone (batching, diff3d, solve, wri, invert, dtft, "
-                         "dataspace); prints one JSON object of them, not the contract line")
+                    help="comma list of legs to run alone (batching, diff3d, solve, network, wri, invert, "
+                         "dtft, dataspace); prints one JSON object of them, not the contract line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "bench.py runs on one GPU; --gpus must be 1 "
@@ -740,6 +750,7 @@ def main():
     legs = {"batching": lambda: batching_run(args, torch, dev, peak_measured),
             "diff3d": lambda: diff3d_run(args, torch, dev, peak_measured),
             "solve": lambda: solver_comparison(args, torch, dev),
+            "network": lambda: network_forward_run(args, torch, dev),
             "wri": lambda: wri_run(args, torch, dev),
             "invert": lambda: invert_run(args, torch, dev),
             "dtft": lambda: dtft_run(args, torch, dev),
